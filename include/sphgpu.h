@@ -1,0 +1,186 @@
+/* sphgpu -- the SPH neighbour loops of the SWIFT method (Borrow et al.,
+ * arXiv:1807.01341) on one AMD MI355X (gfx950).
+ *
+ * The calls follow the paper's statement of one time-step: build the adaptive
+ * cells (Sec. III-A), sort cell contents for neighbour finding (Fig. 5, the
+ * "sort" task), mark the particles and cells active in the current time-bin
+ * (Sec. II-A Eq. 2, Sec. III-D), run the density loop with the ghost's
+ * smoothing-length correction and then the force loop over the active cell
+ * pairs (Sec. III-A, Fig. 5), and kick/drift with individual time-steps
+ * (Sec. II-A, Eq. 1).
+ *
+ * Conventions that hold for every call:
+ *  - All particle arrays are DEVICE pointers owned by the caller, structure of
+ *    arrays, contiguous, length n.  They must stay valid until the work the
+ *    call enqueued has finished.
+ *  - Every call enqueues work on the stream given to sph_create and returns
+ *    without waiting, except where a host output is requested (stated below).
+ *  - Everything the library derives (cells, sorts, active lists, cell-pair
+ *    lists, scratch) belongs to the context and is allocated with hipMalloc;
+ *    it is freed by sph_destroy.
+ *  - No exception crosses this boundary.  Calls return sph_status; on an
+ *    error the context keeps a message readable with sph_last_error.  A
+ *    device fault surfaces as SPH_EDEVICE at the next call that synchronises.
+ *  - Call order per step: build_cells -> sort_cells -> mark_active ->
+ *    density_pass -> force_pass -> kick_drift; a call out of this order
+ *    returns SPH_ESTATE.  kick_drift moves particles, so the next step starts
+ *    with build_cells again.
+ */
+#ifndef SPHGPU_H
+#define SPHGPU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sph_ctx sph_ctx;
+
+typedef enum {
+  SPH_OK = 0,
+  SPH_EINVAL = -1,   /* bad argument (null pointer, n <= 0, bin out of range, box too small) */
+  SPH_ENOMEM = -2,   /* device allocation failed */
+  SPH_EDEVICE = -3,  /* HIP runtime or kernel error */
+  SPH_ENOCONV = -4,  /* smoothing-length solve not converged for some particles;
+                        outputs are written with the last iterate */
+  SPH_EREBUILD = -5, /* a smoothing length outgrew what the cells allow; rebuild */
+  SPH_ESTATE = -6    /* call out of order */
+} sph_status;
+
+/* Method parameters.  sph_default_params fills the values used throughout. */
+typedef struct {
+  double box;          /* periodic cube side L (1.0) */
+  double gamma;        /* adiabatic index (5/3) */
+  double cfl;          /* Courant factor C of Eq. 1 (0.2) */
+  float eta;           /* h = eta (m/rho)^(1/3) (1.2348, about 48 neighbours) */
+  float alpha;         /* Monaghan viscosity strength (0.8) */
+  float balsara_eps;   /* Balsara switch softening, times c/h (1e-4) */
+  float h_tol;         /* relative Newton step that ends the h solve (1e-6) */
+  int n_bins;          /* time-bins 0..n_bins-1 of Eq. 2 (14) */
+  int split_count;     /* a cell with at least this many particles is split (400, Sec. III-A) */
+  int morton_depth;    /* bits per axis of the Morton keys, D <= 21 (21) */
+  int top_cap;         /* top-level grid has at most 2^top_cap cells per side (7) */
+  int h_max_iter;      /* Newton iterations of the h solve (30) */
+  int compensated;     /* 1: compensated FP32 sums in the loops (1) */
+  int cand_cap;        /* loop tiling: candidate slots per wave (512) */
+  int list_cap;        /* loop tiling: neighbour-list slots per lane (96) */
+} sph_params;
+
+/* The particle state.  Arrays marked (opt) may be NULL.  build_cells reorders
+ * every non-NULL array of this struct in place into cell order. */
+typedef struct {
+  double *x, *y, *z;        /* positions; wrapped into [0, L) by build_cells */
+  double *vx, *vy, *vz;     /* velocity at the current time, read by the loops */
+  double *vfx, *vfy, *vfz;  /* kicked velocity, advanced by kicks only (kick_drift) */
+  float *m;                 /* mass */
+  float *u;                 /* specific internal energy: input when density_pass is
+                               called with entropy_from_u=1, else output */
+  float *A;                 /* entropic function at the current time (P = A rho^gamma) */
+  float *Af;                /* kicked entropic function (kick_drift) */
+  float *h;                 /* smoothing length: initial guess in, solution out */
+  int8_t *time_bin;         /* Eq. 2 time-bin */
+  /* density-loop outputs (for active particles; kept for inactive ones) */
+  float *rho, *drho_dh, *f_gradh, *divv, *curlx, *curly, *curlz, *P, *c, *balsara;
+  /* force-loop outputs (for active particles) */
+  float *ax, *ay, *az, *dA_dt, *du_dt, *vsig;
+  int32_t *nngb_density;    /* (opt) neighbours j != i with r < H_i at the final h */
+  int32_t *nngb_force;      /* (opt) neighbours j != i with r < max(H_i, H_j) */
+} sph_particles;
+
+/* Fills p with the defaults listed in sph_params. */
+void sph_default_params(sph_params *p);
+
+/* Creates a context that enqueues on `hip_stream` (a hipStream_t, NULL for the
+ * default stream) of the current device.  Returns SPH_EINVAL for invalid
+ * parameters (morton_depth outside 2..21, split_count < 2, ...). */
+sph_status sph_create(const sph_params *p, void *hip_stream, sph_ctx **out);
+void sph_destroy(sph_ctx *ctx);
+
+/* Adaptive cells (Sec. III-A: a fixed top-level grid refined while a cell has
+ * at least split_count particles).  Wraps positions into [0, L), computes
+ * Morton keys on D-bit integer coordinates, sorts particles stably by
+ * (key, index), reorders every particle array into that order, builds the
+ * octree leaves and their max H = 1.825742*h, and the FP32 offsets of every
+ * particle from its leaf centre.  perm_out (opt, device, n) receives the
+ * original index of each sorted position.  Synchronises once (the top-level
+ * size depends on the largest H).  SPH_EINVAL if max H > L/4. */
+sph_status sph_build_cells(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *perm_out);
+
+/* Per-cell particle sorts for neighbour pruning (Fig. 5 "sort" task): for
+ * each leaf and each of the 13 directions of the half neighbour stencil, the
+ * in-leaf order by projection of the FP32 offset (ties by in-leaf index). */
+sph_status sph_sort_cells(sph_ctx *ctx);
+
+/* Active set for the current time-bin (Eq. 2, Sec. III-D): particle i is
+ * active iff time_bin[i] <= max_active_bin; a leaf is active if it holds an
+ * active particle; every active leaf A is paired with each leaf B (A
+ * included) whose periodic box distance is below max H over A's active
+ * particles.  If n_active_host is non-NULL the call synchronises and writes
+ * the number of active particles there.  SPH_EINVAL if max_active_bin is
+ * outside [0, n_bins-1]. */
+sph_status sph_mark_active(sph_ctx *ctx, const sph_particles *p, int max_active_bin, int64_t *n_active_host);
+
+/* Density loop over the active cell pairs with the ghost's smoothing-length
+ * correction (Sec. III-A, Fig. 5): for every active i, Newton iterations on
+ * h^3 sum_j W(r_ij, h) = eta^3 (cubic spline, H = 1.825742 h), each pass
+ * re-running the loop for particles not yet converged; then rho, drho/dh,
+ * div v, curl v, the grad-h factor, pressure, sound speed, Balsara switch and
+ * the entropic function.  entropy_from_u=1 takes u as the thermal input
+ * (A = (gamma-1) u rho^(1-gamma)); 0 takes A (and writes u).  Synchronises
+ * once per Newton pass.  SPH_ENOCONV / SPH_EREBUILD as described above. */
+sph_status sph_density_pass(sph_ctx *ctx, sph_particles *p, int entropy_from_u);
+
+/* Force loop over the active cell pairs (Fig. 5): for active i and j != i
+ * with r_ij < max(H_i, H_j): pressure acceleration with grad-h terms,
+ * Monaghan viscosity with signal speed c_i + c_j - 3 min(0, v_ij.r_ij/r_ij)
+ * (Eq. 1) and the Balsara switch, dA/dt, du/dt and the max signal speed. */
+sph_status sph_force_pass(sph_ctx *ctx, sph_particles *p);
+
+/* Kick-drift-kick with individual time-steps (Sec. II-A): at integer time ti
+ * (units of t_min), for active particles the closing half-kick (skipped if
+ * first_step), the new time-step from Eq. 1 (C h / vsig) and bin from Eq. 2
+ * (limited to bins whose period divides ti), and the opening half-kick; then
+ * every particle drifts by drift_int * t_min (x += vf dt, v += a dt,
+ * A += dA/dt dt) and is wrapped into the box.  FP64 for x, v. */
+sph_status sph_kick_drift(sph_ctx *ctx, sph_particles *p, int64_t ti, double t_min, int64_t drift_int,
+                          int first_step);
+
+/* Waits for the context's stream and reports a pending device error. */
+sph_status sph_sync(sph_ctx *ctx);
+const char *sph_last_error(const sph_ctx *ctx);
+
+/* ---- Introspection, for checking the derived structures (all copies are
+ * enqueued on the context's stream into caller DEVICE buffers of the sizes
+ * given by sph_info). ---- */
+typedef struct {
+  int64_t n;                 /* particles */
+  int64_t n_leaves;
+  int32_t top_level;         /* top-level grid has 2^top_level cells per side */
+  int64_t n_active;          /* after mark_active */
+  int64_t n_active_leaves;
+  int64_t n_density_pairs;   /* current density cell-pair list */
+  int64_t n_force_pairs;     /* force cell-pair list of the last force pass */
+  int32_t density_iterations;/* Newton passes of the last density pass */
+  int64_t n_unconverged;     /* particles left unconverged by the last density pass */
+} sph_info_t;
+sph_status sph_info(sph_ctx *ctx, sph_info_t *out); /* synchronises */
+
+/* Leaf table in Morton order: level, integer coordinates at that level,
+ * first sorted index, particle count, max H. */
+sph_status sph_copy_leaves(sph_ctx *ctx, int32_t *level, int32_t *ix, int32_t *iy, int32_t *iz, int32_t *begin,
+                           int32_t *count, float *hmax);
+/* Sorted Morton keys and FP32 leaf-centre offsets (length n). */
+sph_status sph_copy_particles(sph_ctx *ctx, uint64_t *keys, float *ox, float *oy, float *oz);
+/* 13 x n in-leaf order (axis-major). */
+sph_status sph_copy_axis_order(sph_ctx *ctx, uint16_t *order);
+/* Active flags (n), active leaves and their max active H (n_active_leaves). */
+sph_status sph_copy_active(sph_ctx *ctx, uint8_t *active, int32_t *active_leaves, float *hmax_act);
+/* Cell-pair list (which = 0 density, 1 force): leaf A, leaf B, FP32 shift. */
+sph_status sph_copy_pairs(sph_ctx *ctx, int which, int32_t *a, int32_t *b, float *sx, float *sy, float *sz);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

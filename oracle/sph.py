@@ -339,7 +339,9 @@ def force(x, v, m, h, rho, f, P, c, B, L, centres=None, p: Params = Params(),
     du = f[centres_t] * P[centres_t] / rc ** 2 * adiab + 0.5 * visc
     vmax = torch.zeros(nc, dtype=F64).scatter_reduce(0, ci, vsig.detach(), "amax", include_self=True)
     count = torch.zeros(nc, dtype=torch.int64).index_add(0, ci, torch.ones_like(ci))
-    return dict(a=a, dA_dt=dA, du_dt=du, vsig=vmax, count=count)
+    # scale of a_i for error reporting: sum_j |pair term| (not part of a_i)
+    scale = torch.zeros(nc, dtype=F64).index_add(0, ci, (coef.abs() * r).detach())
+    return dict(a=a, dA_dt=dA, du_dt=du, vsig=vmax, count=count, scale=scale)
 
 
 # --------------------------------------------------------------------------

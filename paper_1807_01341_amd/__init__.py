@@ -1,0 +1,284 @@
+"""Python binding of libsphgpu (the C-ABI in include/sphgpu.h).
+
+Argument marshalling only: every step of the SPH path runs in the HIP kernels
+of the shared library.  PyTorch supplies device memory and the stream.  The
+binding raises if the library has not been built or no GPU is present; there
+is no CPU fallback.
+
+Names follow the C functions without their `sph_` prefix.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsphgpu.so")
+
+STATUS = {0: "SPH_OK", -1: "SPH_EINVAL", -2: "SPH_ENOMEM", -3: "SPH_EDEVICE", -4: "SPH_ENOCONV",
+          -5: "SPH_EREBUILD", -6: "SPH_ESTATE"}
+
+
+class SPHError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("box", C.c_double), ("gamma", C.c_double), ("cfl", C.c_double),
+                ("eta", C.c_float), ("alpha", C.c_float), ("balsara_eps", C.c_float), ("h_tol", C.c_float),
+                ("n_bins", C.c_int), ("split_count", C.c_int), ("morton_depth", C.c_int), ("top_cap", C.c_int),
+                ("h_max_iter", C.c_int), ("compensated", C.c_int), ("cand_cap", C.c_int), ("list_cap", C.c_int)]
+
+
+# field name, dtype, role
+PARTICLE_FIELDS = [
+    ("x", torch.float64), ("y", torch.float64), ("z", torch.float64),
+    ("vx", torch.float64), ("vy", torch.float64), ("vz", torch.float64),
+    ("vfx", torch.float64), ("vfy", torch.float64), ("vfz", torch.float64),
+    ("m", torch.float32), ("u", torch.float32), ("A", torch.float32), ("Af", torch.float32),
+    ("h", torch.float32), ("time_bin", torch.int8),
+    ("rho", torch.float32), ("drho_dh", torch.float32), ("f_gradh", torch.float32), ("divv", torch.float32),
+    ("curlx", torch.float32), ("curly", torch.float32), ("curlz", torch.float32), ("P", torch.float32),
+    ("c", torch.float32), ("balsara", torch.float32),
+    ("ax", torch.float32), ("ay", torch.float32), ("az", torch.float32), ("dA_dt", torch.float32),
+    ("du_dt", torch.float32), ("vsig", torch.float32),
+    ("nngb_density", torch.int32), ("nngb_force", torch.int32),
+]
+
+
+class ParticlesC(C.Structure):
+    _fields_ = [(name, C.c_void_p) for name, _ in PARTICLE_FIELDS]
+
+
+class Info(C.Structure):
+    _fields_ = [("n", C.c_int64), ("n_leaves", C.c_int64), ("top_level", C.c_int32),
+                ("n_active", C.c_int64), ("n_active_leaves", C.c_int64), ("n_density_pairs", C.c_int64),
+                ("n_force_pairs", C.c_int64), ("density_iterations", C.c_int32), ("n_unconverged", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded shared library; raises if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libsphgpu.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int
+        sigs = {
+            "sph_default_params": (None, [vp]),
+            "sph_create": (i32, [vp, vp, vp]),
+            "sph_destroy": (None, [vp]),
+            "sph_build_cells": (i32, [vp, vp, i64, vp]),
+            "sph_sort_cells": (i32, [vp]),
+            "sph_mark_active": (i32, [vp, vp, i32, vp]),
+            "sph_density_pass": (i32, [vp, vp, i32]),
+            "sph_force_pass": (i32, [vp, vp]),
+            "sph_kick_drift": (i32, [vp, vp, i64, C.c_double, i64, i32]),
+            "sph_sync": (i32, [vp]),
+            "sph_last_error": (C.c_char_p, [vp]),
+            "sph_info": (i32, [vp, vp]),
+            "sph_copy_leaves": (i32, [vp] * 8),
+            "sph_copy_particles": (i32, [vp] * 5),
+            "sph_copy_axis_order": (i32, [vp, vp]),
+            "sph_copy_active": (i32, [vp] * 4),
+            "sph_copy_pairs": (i32, [vp, i32] + [vp] * 5),
+        }
+        for name, (res, args) in sigs.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return ["sph_default_params", "sph_create", "sph_destroy", "sph_build_cells", "sph_sort_cells",
+            "sph_mark_active", "sph_density_pass", "sph_force_pass", "sph_kick_drift", "sph_sync",
+            "sph_last_error", "sph_info", "sph_copy_leaves", "sph_copy_particles", "sph_copy_axis_order",
+            "sph_copy_active", "sph_copy_pairs"]
+
+
+def require_device():
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: the SPH path runs only on the HIP device")
+    lib()
+
+
+def default_params(**overrides) -> Params:
+    p = Params()
+    lib().sph_default_params(C.byref(p))
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+@dataclass
+class Particles:
+    """Device arrays of the particle state (structure of arrays, cell order
+    after build_cells)."""
+    arrays: dict = field(default_factory=dict)
+
+    @property
+    def n(self):
+        return self.arrays["x"].shape[0]
+
+    def __getitem__(self, k):
+        return self.arrays[k]
+
+    def __setitem__(self, k, v):
+        self.arrays[k] = v
+
+    @classmethod
+    def from_initial(cls, ic: dict, device="cuda", counts=True):
+        """From a generator dict (x (N,3), v (N,3), m, u, h, bin); outputs
+        zero-filled; A and Af are filled by the first density pass."""
+        N = ic["x"].shape[0]
+        a = {}
+        dev = torch.device(device)
+        for d, k in enumerate("xyz"):
+            a[k] = torch.tensor(np.ascontiguousarray(ic["x"][:, d]), dtype=torch.float64, device=dev)
+        v = ic.get("v", np.zeros((N, 3)))
+        for d, k in enumerate(("vx", "vy", "vz")):
+            a[k] = torch.tensor(np.ascontiguousarray(v[:, d]), dtype=torch.float64, device=dev)
+            a["vf" + k[1]] = a[k].clone()
+        a["m"] = torch.tensor(ic["m"], dtype=torch.float32, device=dev)
+        a["u"] = torch.tensor(ic["u"], dtype=torch.float32, device=dev)
+        a["h"] = torch.tensor(ic["h"], dtype=torch.float32, device=dev)
+        a["time_bin"] = torch.tensor(ic.get("bin", np.zeros(N, np.int8)), dtype=torch.int8, device=dev)
+        for name, dt in PARTICLE_FIELDS:
+            if name in a:
+                continue
+            if name.startswith("nngb") and not counts:
+                continue
+            a[name] = torch.zeros(N, dtype=dt, device=dev)
+        return cls(a)
+
+    def to_c(self) -> ParticlesC:
+        s = ParticlesC()
+        for name, dt in PARTICLE_FIELDS:
+            t = self.arrays.get(name)
+            if t is not None:
+                if t.dtype != dt or not t.is_contiguous() or t.device.type != "cuda":
+                    raise TypeError(f"particle array {name}: need contiguous {dt} on the GPU")
+                setattr(s, name, t.data_ptr())
+        return s
+
+
+class Context:
+    """One sph_ctx bound to a torch stream (the current one by default)."""
+
+    def __init__(self, params: Params | None = None, stream=None, **overrides):
+        require_device()
+        self.params = params if params is not None else default_params(**overrides)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        self._check(lib().sph_create(C.byref(self.params), C.c_void_p(self.stream.cuda_stream), C.byref(h)),
+                    ctx=None)
+        self.h = h
+        self._pc = None
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().sph_destroy(self.h)
+            self.h = None
+
+    def _check(self, code, ctx="self"):
+        if code != 0:
+            msg = lib().sph_last_error(self.h).decode() if ctx == "self" and getattr(self, "h", None) else ""
+            raise SPHError(code, msg)
+        return code
+
+    def _pcs(self, p: Particles):
+        self._pc = p.to_c()   # keep alive while queued work reads the pointers
+        return C.byref(self._pc)
+
+    # ---- the path
+    def build_cells(self, p: Particles, perm_out: torch.Tensor | None = None):
+        return self._check(lib().sph_build_cells(self.h, self._pcs(p), p.n, _ptr(perm_out)))
+
+    def sort_cells(self):
+        return self._check(lib().sph_sort_cells(self.h))
+
+    def mark_active(self, p: Particles, max_active_bin: int, want_count=True):
+        n = C.c_int64(-1)
+        self._check(lib().sph_mark_active(self.h, self._pcs(p), int(max_active_bin),
+                                          C.byref(n) if want_count else None))
+        return n.value
+
+    def density_pass(self, p: Particles, entropy_from_u: bool):
+        return self._check(lib().sph_density_pass(self.h, self._pcs(p), int(bool(entropy_from_u))))
+
+    def force_pass(self, p: Particles):
+        return self._check(lib().sph_force_pass(self.h, self._pcs(p)))
+
+    def kick_drift(self, p: Particles, ti: int, t_min: float, drift_int: int, first_step: bool):
+        return self._check(lib().sph_kick_drift(self.h, self._pcs(p), int(ti), float(t_min), int(drift_int),
+                                                int(bool(first_step))))
+
+    def sync(self):
+        return self._check(lib().sph_sync(self.h))
+
+    def info(self) -> dict:
+        inf = Info()
+        self._check(lib().sph_info(self.h, C.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in Info._fields_}
+
+    # ---- introspection
+    def copy_leaves(self):
+        nl = self.info()["n_leaves"]
+        dev = torch.device("cuda")
+        out = {k: torch.empty(nl, dtype=torch.int32, device=dev)
+               for k in ("level", "ix", "iy", "iz", "begin", "count")}
+        out["hmax"] = torch.empty(nl, dtype=torch.float32, device=dev)
+        self._check(lib().sph_copy_leaves(self.h, *[_ptr(out[k]) for k in
+                                                    ("level", "ix", "iy", "iz", "begin", "count", "hmax")]))
+        return out
+
+    def copy_particles(self):
+        n = self.info()["n"]
+        dev = torch.device("cuda")
+        keys = torch.empty(n, dtype=torch.int64, device=dev)
+        o = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(3)]
+        self._check(lib().sph_copy_particles(self.h, _ptr(keys), *[_ptr(t) for t in o]))
+        return keys, o
+
+    def copy_axis_order(self):
+        n = self.info()["n"]
+        order = torch.empty(13 * n, dtype=torch.int16, device="cuda")
+        self._check(lib().sph_copy_axis_order(self.h, _ptr(order)))
+        return order.view(13, n)
+
+    def copy_active(self):
+        inf = self.info()
+        dev = torch.device("cuda")
+        act = torch.empty(inf["n"], dtype=torch.uint8, device=dev)
+        al = torch.empty(max(1, inf["n_active_leaves"]), dtype=torch.int32, device=dev)
+        hm = torch.empty(max(1, inf["n_active_leaves"]), dtype=torch.float32, device=dev)
+        self._check(lib().sph_copy_active(self.h, _ptr(act), _ptr(al), _ptr(hm)))
+        k = inf["n_active_leaves"]
+        return act, al[:k], hm[:k]
+
+    def copy_pairs(self, which: int):
+        inf = self.info()
+        np_ = inf["n_density_pairs"] if which == 0 else inf["n_force_pairs"]
+        dev = torch.device("cuda")
+        a = torch.empty(max(1, np_), dtype=torch.int32, device=dev)
+        b = torch.empty(max(1, np_), dtype=torch.int32, device=dev)
+        s = [torch.empty(max(1, np_), dtype=torch.float32, device=dev) for _ in range(3)]
+        self._check(lib().sph_copy_pairs(self.h, int(which), _ptr(a), _ptr(b), *[_ptr(t) for t in s]))
+        return a[:np_], b[:np_], torch.stack([t[:np_] for t in s], 1)

@@ -1,0 +1,223 @@
+// Public C-ABI entry points: argument and call-order checks around the stages.
+#include <string.h>
+
+#include <new>
+
+#include "sph_internal.h"
+
+extern "C" {
+
+void sph_default_params(sph_params *p) {
+  if (!p) return;
+  memset(p, 0, sizeof *p);
+  p->box = 1.0;
+  p->gamma = 5.0 / 3.0;
+  p->cfl = 0.2;
+  p->eta = 1.2348f;
+  p->alpha = 0.8f;
+  p->balsara_eps = 1e-4f;
+  p->h_tol = 1e-6f;
+  p->n_bins = 14;
+  p->split_count = 400;
+  p->morton_depth = 21;
+  p->top_cap = 7;
+  p->h_max_iter = 30;
+  p->compensated = 1;
+  p->cand_cap = 512;
+  p->list_cap = 96;
+}
+
+sph_status sph_create(const sph_params *p, void *hip_stream, sph_ctx **out) {
+  if (!p || !out) return SPH_EINVAL;
+  *out = nullptr;
+  if (!(p->box > 0) || p->morton_depth < 2 || p->morton_depth > 21 || p->split_count < 2 || p->top_cap < 2 ||
+      p->top_cap > 8 || p->n_bins < 1 || p->n_bins > 63 || p->h_max_iter < 1 || !(p->eta > 0) ||
+      !(p->gamma > 1.0) || p->cand_cap < 64 || p->list_cap < 64)
+    return SPH_EINVAL;
+  sph_ctx *ctx = new (std::nothrow) sph_ctx();
+  if (!ctx) return SPH_ENOMEM;
+  ctx->prm = *p;
+  ctx->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&ctx->device) != hipSuccess) {
+    delete ctx;
+    return SPH_EDEVICE;
+  }
+  if (sph_ensure(ctx, ctx->scalars, sizeof(int32_t) * SC_COUNT) != SPH_OK) {
+    delete ctx;
+    return SPH_ENOMEM;
+  }
+  if (hipMemsetAsync(ctx->scalars.p, 0, sizeof(int32_t) * SC_COUNT, ctx->stream) != hipSuccess) {
+    delete ctx;
+    return SPH_EDEVICE;
+  }
+  *out = ctx;
+  return SPH_OK;
+}
+
+void sph_destroy(sph_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  DevBuf *bufs[] = {&ctx->keys_a, &ctx->keys_b, &ctx->vals_a, &ctx->vals_b, &ctx->radix_counts, &ctx->scan_tmp,
+                    &ctx->gather_tmp, &ctx->scalars, &ctx->flags, &ctx->scan_out, &ctx->nodes_a, &ctx->nodes_b,
+                    &ctx->leaf_lvl_at, &ctx->leaf_level, &ctx->leaf_ix, &ctx->leaf_iy, &ctx->leaf_iz,
+                    &ctx->leaf_begin, &ctx->leaf_count, &ctx->leaf_hmax, &ctx->leaf_of, &ctx->top_first,
+                    &ctx->top_last, &ctx->pos4, &ctx->axis_order, &ctx->active, &ctx->leaf_nact,
+                    &ctx->leaf_act_off, &ctx->leaf_actleaf, &ctx->act_leaves, &ctx->act_hmax,
+                    &ctx->act_leaf_chunk_off, &ctx->active_idx, &ctx->chunk_of, &ctx->chunks, &ctx->chunk_todo,
+                    &ctx->dpair_off, &ctx->dpairs, &ctx->fpair_off, &ctx->fpairs, &ctx->pair_cnt, &ctx->jvm,
+                    &ctx->jth, &ctx->sums, &ctx->hlo, &ctx->hhi, &ctx->conv};
+  for (DevBuf *b : bufs)
+    if (b->p) (void)hipFree(b->p);
+  delete ctx;
+}
+
+static sph_status need_state(sph_ctx *ctx, int at_least, const char *call) {
+  if (!ctx) return SPH_EINVAL;
+  if (ctx->state < at_least) return sph_fail(ctx, SPH_ESTATE, "%s called out of order (state %d)", call, ctx->state);
+  return SPH_OK;
+}
+
+sph_status sph_build_cells(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *perm_out) {
+  if (!ctx) return SPH_EINVAL;
+  return build_cells_impl(ctx, p, n, perm_out);
+}
+
+sph_status sph_sort_cells(sph_ctx *ctx) {
+  SPH_TRY(need_state(ctx, 1, "sort_cells"));
+  return sort_cells_impl(ctx);
+}
+
+sph_status sph_mark_active(sph_ctx *ctx, const sph_particles *p, int max_active_bin, int64_t *n_active_host) {
+  SPH_TRY(need_state(ctx, 2, "mark_active"));
+  return mark_active_impl(ctx, p, max_active_bin, n_active_host);
+}
+
+sph_status sph_density_pass(sph_ctx *ctx, sph_particles *p, int entropy_from_u) {
+  SPH_TRY(need_state(ctx, 3, "density_pass"));
+  if (!p) return sph_fail(ctx, SPH_EINVAL, "density_pass: null particles");
+  return density_pass_impl(ctx, p, entropy_from_u);
+}
+
+sph_status sph_force_pass(sph_ctx *ctx, sph_particles *p) {
+  SPH_TRY(need_state(ctx, 4, "force_pass"));
+  if (!p) return sph_fail(ctx, SPH_EINVAL, "force_pass: null particles");
+  return force_pass_impl(ctx, p);
+}
+
+sph_status sph_kick_drift(sph_ctx *ctx, sph_particles *p, int64_t ti, double t_min, int64_t drift_int,
+                          int first_step) {
+  SPH_TRY(need_state(ctx, 5, "kick_drift"));
+  if (!p) return sph_fail(ctx, SPH_EINVAL, "kick_drift: null particles");
+  return kick_drift_impl(ctx, p, ti, t_min, drift_int, first_step);
+}
+
+sph_status sph_sync(sph_ctx *ctx) {
+  if (!ctx) return SPH_EINVAL;
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  HIP_TRY(ctx, hipGetLastError());
+  return SPH_OK;
+}
+
+const char *sph_last_error(const sph_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+sph_status sph_info(sph_ctx *ctx, sph_info_t *out) {
+  if (!ctx || !out) return SPH_EINVAL;
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  out->n = ctx->n;
+  out->n_leaves = ctx->n_leaves;
+  out->top_level = ctx->top_level;
+  out->n_active = ctx->n_active;
+  out->n_active_leaves = ctx->n_active_leaves;
+  out->n_density_pairs = ctx->n_dpairs;
+  out->n_force_pairs = ctx->n_fpairs;
+  out->density_iterations = ctx->density_iterations;
+  out->n_unconverged = ctx->n_unconverged;
+  return SPH_OK;
+}
+
+static sph_status copy_dev(sph_ctx *ctx, void *dst, const DevBuf &src, size_t bytes) {
+  if (!dst || bytes == 0) return SPH_OK;
+  if (!src.p || src.cap < bytes) return sph_fail(ctx, SPH_ESTATE, "copy: structure not built");
+  HIP_TRY(ctx, hipMemcpyAsync(dst, src.p, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+  return SPH_OK;
+}
+
+sph_status sph_copy_leaves(sph_ctx *ctx, int32_t *level, int32_t *ix, int32_t *iy, int32_t *iz, int32_t *begin,
+                           int32_t *count, float *hmax) {
+  SPH_TRY(need_state(ctx, 1, "copy_leaves"));
+  const size_t nl = (size_t)ctx->n_leaves;
+  SPH_TRY(copy_dev(ctx, level, ctx->leaf_level, 4 * nl));
+  SPH_TRY(copy_dev(ctx, ix, ctx->leaf_ix, 4 * nl));
+  SPH_TRY(copy_dev(ctx, iy, ctx->leaf_iy, 4 * nl));
+  SPH_TRY(copy_dev(ctx, iz, ctx->leaf_iz, 4 * nl));
+  SPH_TRY(copy_dev(ctx, begin, ctx->leaf_begin, 4 * nl));
+  SPH_TRY(copy_dev(ctx, count, ctx->leaf_count, 4 * nl));
+  SPH_TRY(copy_dev(ctx, hmax, ctx->leaf_hmax, 4 * nl));
+  return SPH_OK;
+}
+
+__global__ void split_pos4_kernel(const float4 *__restrict__ pos4, int64_t n, float *ox, float *oy, float *oz) {
+  for (int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x; s < n; s += (int64_t)gridDim.x * 256) {
+    const float4 q = pos4[s];
+    if (ox) ox[s] = q.x;
+    if (oy) oy[s] = q.y;
+    if (oz) oz[s] = q.z;
+  }
+}
+
+sph_status sph_copy_particles(sph_ctx *ctx, uint64_t *keys, float *ox, float *oy, float *oz) {
+  SPH_TRY(need_state(ctx, 1, "copy_particles"));
+  SPH_TRY(copy_dev(ctx, keys, ctx->keys_a, 8 * (size_t)ctx->n));
+  if (ox || oy || oz) {
+    int64_t g = ceil_div(ctx->n, 256);
+    if (g > 8192) g = 8192;
+    split_pos4_kernel<<<(unsigned)g, 256, 0, ctx->stream>>>((const float4 *)ctx->pos4.p, ctx->n, ox, oy, oz);
+    HIP_TRY(ctx, hipGetLastError());
+  }
+  return SPH_OK;
+}
+
+sph_status sph_copy_axis_order(sph_ctx *ctx, uint16_t *order) {
+  SPH_TRY(need_state(ctx, 2, "copy_axis_order"));
+  return copy_dev(ctx, order, ctx->axis_order, 2 * 13 * (size_t)ctx->n);
+}
+
+sph_status sph_copy_active(sph_ctx *ctx, uint8_t *active, int32_t *active_leaves, float *hmax_act) {
+  SPH_TRY(need_state(ctx, 3, "copy_active"));
+  SPH_TRY(copy_dev(ctx, active, ctx->active, (size_t)ctx->n));
+  SPH_TRY(copy_dev(ctx, active_leaves, ctx->act_leaves, 4 * (size_t)ctx->n_active_leaves));
+  SPH_TRY(copy_dev(ctx, hmax_act, ctx->act_hmax, 4 * (size_t)ctx->n_active_leaves));
+  return SPH_OK;
+}
+
+__global__ void split_pairs_kernel(const PairEntry *__restrict__ pe, const int32_t *__restrict__ off,
+                                   const int32_t *__restrict__ act_leaves, int64_t nal, int32_t *a, int32_t *b,
+                                   float *sx, float *sy, float *sz) {
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < nal; q += (int64_t)gridDim.x * 256) {
+    const int A = act_leaves[q];
+    for (int p = off[q]; p < off[q + 1]; ++p) {
+      const PairEntry e = pe[p];
+      if (a) a[p] = A;
+      if (b) b[p] = e.b;
+      if (sx) sx[p] = e.sx;
+      if (sy) sy[p] = e.sy;
+      if (sz) sz[p] = e.sz;
+    }
+  }
+}
+
+sph_status sph_copy_pairs(sph_ctx *ctx, int which, int32_t *a, int32_t *b, float *sx, float *sy, float *sz) {
+  SPH_TRY(need_state(ctx, which == 0 ? 3 : 5, "copy_pairs"));
+  const int64_t nal = ctx->n_active_leaves;
+  if (nal == 0) return SPH_OK;
+  const DevBuf &off = which == 0 ? ctx->dpair_off : ctx->fpair_off;
+  const DevBuf &lst = which == 0 ? ctx->dpairs : ctx->fpairs;
+  int64_t g = ceil_div(nal, 256);
+  if (g > 8192) g = 8192;
+  split_pairs_kernel<<<(unsigned)g, 256, 0, ctx->stream>>>((const PairEntry *)lst.p, (const int32_t *)off.p,
+                                                         (const int32_t *)ctx->act_leaves.p, nal, a, b, sx, sy, sz);
+  HIP_TRY(ctx, hipGetLastError());
+  return SPH_OK;
+}
+
+}  // extern "C"

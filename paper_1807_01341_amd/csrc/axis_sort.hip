@@ -1,0 +1,114 @@
+// Per-cell particle sorts for neighbour pruning (the "sort" task of Fig. 5):
+// for every leaf and each of the 13 directions of the half neighbour stencil,
+// the in-leaf order of the projections d = e . o of the FP32 offsets
+// (ascending, ties by in-leaf index).  One workgroup per leaf, all 13 axes,
+// bitonic sorts of (key, index) in LDS.
+#include <math.h>
+
+#include "sph_internal.h"
+
+#define AS_THREADS 256
+
+struct AxisSet {
+  float e[13][3];
+};
+
+// Directions (dx, dy, dz) in {-1,0,1}^3 with the first non-zero component
+// positive, in lexicographic order, normalised in double and rounded to float.
+static AxisSet make_axes() {
+  AxisSet a;
+  int k = 0;
+  for (int dx = -1; dx <= 1; ++dx)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dz = -1; dz <= 1; ++dz) {
+        const int first = dx != 0 ? dx : (dy != 0 ? dy : dz);
+        if (first <= 0) continue;
+        const double nrm = sqrt((double)(dx * dx + dy * dy + dz * dz));
+        a.e[k][0] = (float)(dx / nrm);
+        a.e[k][1] = (float)(dy / nrm);
+        a.e[k][2] = (float)(dz / nrm);
+        ++k;
+      }
+  return a;
+}
+
+template <int P>
+__global__ __launch_bounds__(AS_THREADS) void axis_sort_kernel(const float4 *__restrict__ pos4,
+                                                               const int32_t *__restrict__ leaf_begin,
+                                                               const int32_t *__restrict__ leaf_count, int64_t nl,
+                                                               int64_t n, AxisSet ax, int min_count,
+                                                               uint16_t *__restrict__ order) {
+  __shared__ float ox[P], oy[P], oz[P];
+  __shared__ float key[P];
+  __shared__ uint16_t idx[P];
+  const int l = blockIdx.x;
+  if (l >= nl) return;
+  const int cnt = leaf_count[l];
+  if (cnt < min_count || cnt > P) return;
+  const int b = leaf_begin[l];
+  int size = 2;
+  while (size < cnt) size <<= 1;
+  for (int k = threadIdx.x; k < cnt; k += AS_THREADS) {
+    const float4 q = pos4[b + k];
+    ox[k] = q.x;
+    oy[k] = q.y;
+    oz[k] = q.z;
+  }
+  __syncthreads();
+  for (int a = 0; a < 13; ++a) {
+    const float ex = ax.e[a][0], ey = ax.e[a][1], ez = ax.e[a][2];
+    for (int k = threadIdx.x; k < size; k += AS_THREADS) {
+      if (k < cnt) {
+        key[k] = fmaf(oz[k], ez, fmaf(oy[k], ey, ox[k] * ex));
+        idx[k] = (uint16_t)k;
+      } else {
+        key[k] = INFINITY;
+        idx[k] = 0xffff;
+      }
+    }
+    __syncthreads();
+    for (int kk = 2; kk <= size; kk <<= 1) {
+      for (int j = kk >> 1; j > 0; j >>= 1) {
+        for (int t = threadIdx.x; t < (size >> 1); t += AS_THREADS) {
+          const int i0 = 2 * t - (t & (j - 1));
+          const int i1 = i0 + j;
+          const bool up = (i0 & kk) == 0;
+          const float k0 = key[i0], k1 = key[i1];
+          const uint16_t d0 = idx[i0], d1 = idx[i1];
+          const bool gt = (k0 > k1) || (k0 == k1 && d0 > d1);
+          if (gt == up) {
+            key[i0] = k1;
+            key[i1] = k0;
+            idx[i0] = d1;
+            idx[i1] = d0;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int k = threadIdx.x; k < cnt; k += AS_THREADS) order[(int64_t)a * n + b + k] = idx[k];
+    __syncthreads();
+  }
+}
+
+sph_status sort_cells_impl(sph_ctx *ctx) {
+  const int64_t n = ctx->n, nl = ctx->n_leaves;
+  SPH_TRY(sph_ensure(ctx, ctx->axis_order, sizeof(uint16_t) * 13 * (size_t)n));
+  int32_t maxc = 0;
+  SPH_TRY(read_scalars(ctx, SC_MAXLEAF, 1, &maxc));
+  if (maxc > 4096)
+    return sph_fail(ctx, SPH_EINVAL, "sort_cells: a leaf holds %d particles (max 4096 for the axis sorts)", maxc);
+  const AxisSet ax = make_axes();
+  axis_sort_kernel<512><<<(unsigned)nl, AS_THREADS, 0, ctx->stream>>>(
+      (const float4 *)ctx->pos4.p, (const int32_t *)ctx->leaf_begin.p, (const int32_t *)ctx->leaf_count.p, nl, n, ax,
+      0, (uint16_t *)ctx->axis_order.p);
+  HIP_TRY(ctx, hipGetLastError());
+  if (maxc > 512) {
+    axis_sort_kernel<4096><<<(unsigned)nl, AS_THREADS, 0, ctx->stream>>>(
+        (const float4 *)ctx->pos4.p, (const int32_t *)ctx->leaf_begin.p, (const int32_t *)ctx->leaf_count.p, nl, n,
+        ax, 513, (uint16_t *)ctx->axis_order.p);
+    HIP_TRY(ctx, hipGetLastError());
+  }
+  ctx->state = 2;
+  return SPH_OK;
+}

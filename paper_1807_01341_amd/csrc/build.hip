@@ -1,0 +1,332 @@
+// Adaptive cell build (Sec. III-A): a fixed top-level grid refined by octree
+// splits while a cell holds at least split_count particles.  Particles are
+// ordered by Morton key of their D-bit integer coordinates (ties by original
+// index), so every cell of the octree is a contiguous range of that order.
+#include <math.h>
+#include <string.h>
+
+#include "sph_internal.h"
+
+#define BT 256
+
+// x - L floor(x/L), folded into [0, L).  Compiled without contraction, so the
+// product and the difference round separately.
+__device__ __forceinline__ double wrap_box(double x, double L) {
+  const double q = floor(x / L);
+  double xw = x - q * L;
+  if (xw < 0.0) xw += L;
+  if (xw >= L) xw -= L;
+  return xw;
+}
+
+__device__ __forceinline__ uint64_t coord_of(double xw, double scale, int64_t kmax) {
+  int64_t k = (int64_t)(xw * scale);
+  if (k > kmax) k = kmax;
+  if (k < 0) k = 0;
+  return (uint64_t)k;
+}
+
+// Wraps positions in place, writes Morton keys and the identity permutation,
+// and the largest H = GK32 * h (as int bits of a positive float).
+__global__ __launch_bounds__(BT) void morton_kernel(double *__restrict__ x, double *__restrict__ y,
+                                                    double *__restrict__ z, const float *__restrict__ h, int64_t n,
+                                                    double L, double scale, int64_t kmax, uint64_t *__restrict__ keys,
+                                                    int32_t *__restrict__ vals, int *__restrict__ hmax_bits) {
+  float hm = 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x; i < n; i += (int64_t)gridDim.x * BT) {
+    const double xw = wrap_box(x[i], L), yw = wrap_box(y[i], L), zw = wrap_box(z[i], L);
+    x[i] = xw;
+    y[i] = yw;
+    z[i] = zw;
+    keys[i] = (spread3_21(coord_of(xw, scale, kmax)) << 2) | (spread3_21(coord_of(yw, scale, kmax)) << 1) |
+              spread3_21(coord_of(zw, scale, kmax));
+    vals[i] = (int32_t)i;
+    hm = fmaxf(hm, GK32 * h[i]);
+  }
+  hm = wave_max_f(hm);
+  if ((threadIdx.x & 63) == 0) atomicMax(hmax_bits, __float_as_int(hm));
+}
+
+template <typename T>
+__global__ __launch_bounds__(BT) void gather_kernel(const T *__restrict__ src, T *__restrict__ dst,
+                                                    const int32_t *__restrict__ perm, int64_t n) {
+  for (int64_t s = (int64_t)blockIdx.x * BT + threadIdx.x; s < n; s += (int64_t)gridDim.x * BT) dst[s] = src[perm[s]];
+}
+
+__global__ __launch_bounds__(BT) void perm_out_kernel(const int32_t *__restrict__ perm, int64_t *__restrict__ out,
+                                                      int64_t n) {
+  for (int64_t s = (int64_t)blockIdx.x * BT + threadIdx.x; s < n; s += (int64_t)gridDim.x * BT) out[s] = perm[s];
+}
+
+// flags[s] = 1 where the top-level prefix changes.
+__global__ __launch_bounds__(BT) void prefix_start_kernel(const uint64_t *__restrict__ keys, int64_t n, int shift,
+                                                          int32_t *__restrict__ flags) {
+  for (int64_t s = (int64_t)blockIdx.x * BT + threadIdx.x; s < n; s += (int64_t)gridDim.x * BT)
+    flags[s] = (s == 0) || ((keys[s] >> shift) != (keys[s - 1] >> shift));
+}
+
+__global__ __launch_bounds__(BT) void top_nodes_kernel(const int32_t *__restrict__ flags,
+                                                       const int32_t *__restrict__ idx, int64_t n,
+                                                       int2 *__restrict__ nodes) {
+  for (int64_t s = (int64_t)blockIdx.x * BT + threadIdx.x; s < n; s += (int64_t)gridDim.x * BT)
+    if (flags[s]) nodes[idx[s]].x = (int)s;
+}
+
+__global__ __launch_bounds__(BT) void node_ends_kernel(int2 *__restrict__ nodes, const int32_t *__restrict__ count,
+                                                       int64_t n) {
+  const int m = *count;
+  for (int k = blockIdx.x * BT + threadIdx.x; k < m; k += gridDim.x * BT)
+    nodes[k].y = (k + 1 < m) ? nodes[k + 1].x : (int)n;
+}
+
+// One octree level: each node either becomes a leaf (marked at its first
+// particle) or is split into its non-empty children (appended to `out`).
+__global__ __launch_bounds__(BT) void split_level_kernel(const uint64_t *__restrict__ keys,
+                                                         const int2 *__restrict__ in, const int32_t *__restrict__ n_in,
+                                                         int2 *__restrict__ out, int32_t *__restrict__ n_out,
+                                                         int level, int D, int split, int32_t *__restrict__ leaf_flag,
+                                                         int8_t *__restrict__ leaf_lvl) {
+  const int m = *n_in;
+  for (int k = blockIdx.x * BT + threadIdx.x; k < m; k += gridDim.x * BT) {
+    const int2 nd = in[k];
+    const int cnt = nd.y - nd.x;
+    if (cnt < split || level >= D) {
+      leaf_flag[nd.x] = 1;
+      leaf_lvl[nd.x] = (int8_t)level;
+      continue;
+    }
+    const int shift = 3 * (D - level - 1);
+    int lo = nd.x;
+    for (int c = 0; c < 8; ++c) {
+      // first position in [lo, end) whose child digit exceeds c
+      int a = lo, b = nd.y;
+      while (a < b) {
+        const int mid = (a + b) >> 1;
+        if ((int)((keys[mid] >> shift) & 7ull) <= c)
+          a = mid + 1;
+        else
+          b = mid;
+      }
+      if (a > lo) {
+        const int slot = atomicAdd(n_out, 1);
+        out[slot] = make_int2(lo, a);
+      }
+      lo = a;
+    }
+  }
+}
+
+__global__ __launch_bounds__(BT) void leaf_table_kernel(const int32_t *__restrict__ leaf_flag,
+                                                        const int32_t *__restrict__ leaf_idx,
+                                                        const int8_t *__restrict__ leaf_lvl,
+                                                        const uint64_t *__restrict__ keys, int64_t n, int D,
+                                                        int32_t *__restrict__ level, int32_t *__restrict__ ix,
+                                                        int32_t *__restrict__ iy, int32_t *__restrict__ iz,
+                                                        int32_t *__restrict__ begin, int32_t *__restrict__ leaf_of) {
+  for (int64_t s = (int64_t)blockIdx.x * BT + threadIdx.x; s < n; s += (int64_t)gridDim.x * BT) {
+    const int f = leaf_flag[s];
+    const int l = leaf_idx[s] + f - 1;
+    leaf_of[s] = l;
+    if (f) {
+      const int lv = leaf_lvl[s];
+      const uint64_t pre = keys[s] >> (3 * (D - lv));
+      level[l] = lv;
+      ix[l] = (int32_t)compact3_21(pre >> 2);
+      iy[l] = (int32_t)compact3_21(pre >> 1);
+      iz[l] = (int32_t)compact3_21(pre);
+      begin[l] = (int32_t)s;
+    }
+  }
+}
+
+__global__ __launch_bounds__(BT) void leaf_count_kernel(const int32_t *__restrict__ begin, int32_t *__restrict__ count,
+                                                        int64_t nl, int64_t n, int32_t *__restrict__ max_count) {
+  int mc = 0;
+  for (int64_t l = (int64_t)blockIdx.x * BT + threadIdx.x; l < nl; l += (int64_t)gridDim.x * BT) {
+    const int c = (int32_t)(((l + 1 < nl) ? begin[l + 1] : n) - begin[l]);
+    count[l] = c;
+    mc = max(mc, c);
+  }
+  mc = wave_max_i(mc);
+  if ((threadIdx.x & 63) == 0) atomicMax(max_count, mc);
+}
+
+// FP32 offsets from the leaf centre, H, and the leaf's max H.
+__global__ __launch_bounds__(BT) void offsets_kernel(const double *__restrict__ x, const double *__restrict__ y,
+                                                     const double *__restrict__ z, const float *__restrict__ h,
+                                                     const int32_t *__restrict__ leaf_of,
+                                                     const int32_t *__restrict__ level, const int32_t *__restrict__ ix,
+                                                     const int32_t *__restrict__ iy, const int32_t *__restrict__ iz,
+                                                     int64_t n, int D, double unit, float4 *__restrict__ pos4,
+                                                     float *__restrict__ leaf_hmax) {
+  for (int64_t s = (int64_t)blockIdx.x * BT + threadIdx.x; s < n; s += (int64_t)gridDim.x * BT) {
+    const int l = leaf_of[s];
+    const int sh = D - level[l];
+    const double cx = (double)((2 * (int64_t)ix[l] + 1) << sh) * unit;
+    const double cy = (double)((2 * (int64_t)iy[l] + 1) << sh) * unit;
+    const double cz = (double)((2 * (int64_t)iz[l] + 1) << sh) * unit;
+    const float H = GK32 * h[s];
+    pos4[s] = make_float4((float)(x[s] - cx), (float)(y[s] - cy), (float)(z[s] - cz), H);
+    atomic_max_pos_f(&leaf_hmax[l], H);
+  }
+}
+
+// Leaf range of every top-level cell (leaves of one top cell are contiguous).
+__global__ __launch_bounds__(BT) void top_map_kernel(const int32_t *__restrict__ level, const int32_t *__restrict__ ix,
+                                                     const int32_t *__restrict__ iy, const int32_t *__restrict__ iz,
+                                                     int64_t nl, int k0, int32_t *__restrict__ first,
+                                                     int32_t *__restrict__ last) {
+  const int ntop = 1 << k0;
+  for (int64_t l = (int64_t)blockIdx.x * BT + threadIdx.x; l < nl; l += (int64_t)gridDim.x * BT) {
+    auto tc = [&](int64_t q) {
+      const int s = level[q] - k0;
+      return ((int64_t)(ix[q] >> s) * ntop + (iy[q] >> s)) * ntop + (iz[q] >> s);
+    };
+    const int64_t t = tc(l);
+    if (l == 0 || tc(l - 1) != t) first[t] = (int32_t)l;
+    if (l == nl - 1 || tc(l + 1) != t) last[t] = (int32_t)(l + 1);
+  }
+}
+
+static unsigned grid_for(int64_t n) {
+  int64_t g = ceil_div(n, BT);
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+template <typename T>
+static sph_status permute_array(sph_ctx *ctx, T *arr, int64_t n) {
+  if (!arr) return SPH_OK;
+  const int32_t *perm = (const int32_t *)ctx->vals_a.p;
+  gather_kernel<T><<<grid_for(n), BT, 0, ctx->stream>>>(arr, (T *)ctx->gather_tmp.p, perm, n);
+  HIP_TRY(ctx, hipGetLastError());
+  HIP_TRY(ctx, hipMemcpyAsync(arr, ctx->gather_tmp.p, sizeof(T) * n, hipMemcpyDeviceToDevice, ctx->stream));
+  return SPH_OK;
+}
+
+sph_status build_cells_impl(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *perm_out) {
+  if (!p || n <= 0 || n > INT32_MAX / 2) return sph_fail(ctx, SPH_EINVAL, "build_cells: bad particle count %lld", (long long)n);
+  if (!p->x || !p->y || !p->z || !p->h) return sph_fail(ctx, SPH_EINVAL, "build_cells: x, y, z and h are required");
+  const int D = ctx->prm.morton_depth;
+  const double L = ctx->prm.box;
+  ctx->n = n;
+  ctx->state = 0;
+  SPH_TRY(sph_ensure(ctx, ctx->keys_a, 8 * n));
+  SPH_TRY(sph_ensure(ctx, ctx->keys_b, 8 * n));
+  SPH_TRY(sph_ensure(ctx, ctx->vals_a, 4 * n));
+  SPH_TRY(sph_ensure(ctx, ctx->vals_b, 4 * n));
+  SPH_TRY(sph_ensure(ctx, ctx->gather_tmp, 8 * n));
+  int32_t *sc = (int32_t *)ctx->scalars.p;
+  HIP_TRY(ctx, hipMemsetAsync(sc, 0, sizeof(int32_t) * SC_COUNT, ctx->stream));
+
+  const double scale = ldexp(1.0, D) / L;
+  const int64_t kmax = ((int64_t)1 << D) - 1;
+  morton_kernel<<<grid_for(n), BT, 0, ctx->stream>>>(p->x, p->y, p->z, p->h, n, L, scale, kmax,
+                                                    (uint64_t *)ctx->keys_a.p, (int32_t *)ctx->vals_a.p,
+                                                    sc + SC_HMAX_BITS);
+  HIP_TRY(ctx, hipGetLastError());
+  SPH_TRY(radix_sort_pairs(ctx, n, 3 * D));
+
+  // reorder every particle array into key order
+  SPH_TRY(permute_array(ctx, p->x, n));
+  SPH_TRY(permute_array(ctx, p->y, n));
+  SPH_TRY(permute_array(ctx, p->z, n));
+  SPH_TRY(permute_array(ctx, p->vx, n));
+  SPH_TRY(permute_array(ctx, p->vy, n));
+  SPH_TRY(permute_array(ctx, p->vz, n));
+  SPH_TRY(permute_array(ctx, p->vfx, n));
+  SPH_TRY(permute_array(ctx, p->vfy, n));
+  SPH_TRY(permute_array(ctx, p->vfz, n));
+  SPH_TRY(permute_array(ctx, p->m, n));
+  SPH_TRY(permute_array(ctx, p->u, n));
+  SPH_TRY(permute_array(ctx, p->A, n));
+  SPH_TRY(permute_array(ctx, p->Af, n));
+  SPH_TRY(permute_array(ctx, p->h, n));
+  SPH_TRY(permute_array(ctx, p->time_bin, n));
+  float *fo[] = {p->rho, p->drho_dh, p->f_gradh, p->divv, p->curlx, p->curly, p->curlz, p->P, p->c, p->balsara,
+                 p->ax, p->ay, p->az, p->dA_dt, p->du_dt, p->vsig};
+  for (float *a : fo) SPH_TRY(permute_array(ctx, a, n));
+  SPH_TRY(permute_array(ctx, p->nngb_density, n));
+  SPH_TRY(permute_array(ctx, p->nngb_force, n));
+  if (perm_out) {
+    perm_out_kernel<<<grid_for(n), BT, 0, ctx->stream>>>((const int32_t *)ctx->vals_a.p, perm_out, n);
+    HIP_TRY(ctx, hipGetLastError());
+  }
+
+  // top level from the largest smoothing length
+  int32_t hb;
+  SPH_TRY(read_scalars(ctx, SC_HMAX_BITS, 1, &hb));
+  float hmax;
+  memcpy(&hmax, &hb, 4);
+  if (L * 0.25 < (double)hmax)
+    return sph_fail(ctx, SPH_EINVAL, "build_cells: max H = %g exceeds a quarter of the box %g", hmax, L);
+  int k0 = 2;
+  while (k0 < ctx->prm.top_cap && k0 < D && ldexp(L, -(k0 + 1)) >= (double)hmax) ++k0;
+  ctx->top_level = k0;
+  ctx->hmax_global = hmax;
+
+  const uint64_t *keys = (const uint64_t *)ctx->keys_a.p;
+  SPH_TRY(sph_ensure(ctx, ctx->flags, 4 * n));
+  SPH_TRY(sph_ensure(ctx, ctx->scan_out, 4 * n));
+  SPH_TRY(sph_ensure(ctx, ctx->nodes_a, 8 * n));
+  SPH_TRY(sph_ensure(ctx, ctx->nodes_b, 8 * n));
+  SPH_TRY(sph_ensure(ctx, ctx->leaf_lvl_at, n));
+  int32_t *flags = (int32_t *)ctx->flags.p, *sidx = (int32_t *)ctx->scan_out.p;
+  prefix_start_kernel<<<grid_for(n), BT, 0, ctx->stream>>>(keys, n, 3 * (D - k0), flags);
+  HIP_TRY(ctx, hipGetLastError());
+  SPH_TRY(scan_exclusive_i32(ctx, flags, sidx, n, sc + SC_NODES_A));
+  int2 *na = (int2 *)ctx->nodes_a.p, *nb = (int2 *)ctx->nodes_b.p;
+  top_nodes_kernel<<<grid_for(n), BT, 0, ctx->stream>>>(flags, sidx, n, na);
+  node_ends_kernel<<<grid_for(n), BT, 0, ctx->stream>>>(na, sc + SC_NODES_A, n);
+  HIP_TRY(ctx, hipGetLastError());
+
+  // refine level by level; leaves are flagged at their first particle
+  HIP_TRY(ctx, hipMemsetAsync(flags, 0, 4 * n, ctx->stream));
+  int cin = SC_NODES_A, cout = SC_NODES_B;
+  for (int lv = k0; lv <= D; ++lv) {
+    HIP_TRY(ctx, hipMemsetAsync(sc + cout, 0, 4, ctx->stream));
+    split_level_kernel<<<grid_for(n), BT, 0, ctx->stream>>>(keys, na, sc + cin, nb, sc + cout, lv, D,
+                                                           ctx->prm.split_count, flags,
+                                                           (int8_t *)ctx->leaf_lvl_at.p);
+    HIP_TRY(ctx, hipGetLastError());
+    int2 *t = na; na = nb; nb = t;
+    int tc = cin; cin = cout; cout = tc;
+  }
+  SPH_TRY(scan_exclusive_i32(ctx, flags, sidx, n, sc + SC_TOTAL0));
+  int32_t nl;
+  SPH_TRY(read_scalars(ctx, SC_TOTAL0, 1, &nl));
+  ctx->n_leaves = nl;
+  SPH_TRY(sph_ensure(ctx, ctx->leaf_level, 4 * (size_t)nl));
+  SPH_TRY(sph_ensure(ctx, ctx->leaf_ix, 4 * (size_t)nl));
+  SPH_TRY(sph_ensure(ctx, ctx->leaf_iy, 4 * (size_t)nl));
+  SPH_TRY(sph_ensure(ctx, ctx->leaf_iz, 4 * (size_t)nl));
+  SPH_TRY(sph_ensure(ctx, ctx->leaf_begin, 4 * (size_t)nl));
+  SPH_TRY(sph_ensure(ctx, ctx->leaf_count, 4 * (size_t)nl));
+  SPH_TRY(sph_ensure(ctx, ctx->leaf_hmax, 4 * (size_t)nl));
+  SPH_TRY(sph_ensure(ctx, ctx->leaf_of, 4 * n));
+  SPH_TRY(sph_ensure(ctx, ctx->pos4, 16 * n));
+  int32_t *lvl = (int32_t *)ctx->leaf_level.p, *lix = (int32_t *)ctx->leaf_ix.p, *liy = (int32_t *)ctx->leaf_iy.p,
+          *liz = (int32_t *)ctx->leaf_iz.p, *lb = (int32_t *)ctx->leaf_begin.p, *lc = (int32_t *)ctx->leaf_count.p,
+          *lof = (int32_t *)ctx->leaf_of.p;
+  leaf_table_kernel<<<grid_for(n), BT, 0, ctx->stream>>>(flags, sidx, (const int8_t *)ctx->leaf_lvl_at.p, keys, n, D,
+                                                        lvl, lix, liy, liz, lb, lof);
+  leaf_count_kernel<<<grid_for(nl), BT, 0, ctx->stream>>>(lb, lc, nl, n, sc + SC_MAXLEAF);
+  HIP_TRY(ctx, hipGetLastError());
+  HIP_TRY(ctx, hipMemsetAsync(ctx->leaf_hmax.p, 0, 4 * (size_t)nl, ctx->stream));
+  offsets_kernel<<<grid_for(n), BT, 0, ctx->stream>>>(p->x, p->y, p->z, p->h, lof, lvl, lix, liy, liz, n, D,
+                                                     ldexp(L, -(D + 1)), (float4 *)ctx->pos4.p,
+                                                     (float *)ctx->leaf_hmax.p);
+  HIP_TRY(ctx, hipGetLastError());
+  const int64_t ntop3 = (int64_t)1 << (3 * k0);
+  SPH_TRY(sph_ensure(ctx, ctx->top_first, 4 * (size_t)ntop3));
+  SPH_TRY(sph_ensure(ctx, ctx->top_last, 4 * (size_t)ntop3));
+  HIP_TRY(ctx, hipMemsetAsync(ctx->top_first.p, 0, 4 * (size_t)ntop3, ctx->stream));
+  HIP_TRY(ctx, hipMemsetAsync(ctx->top_last.p, 0, 4 * (size_t)ntop3, ctx->stream));
+  top_map_kernel<<<grid_for(nl), BT, 0, ctx->stream>>>(lvl, lix, liy, liz, nl, k0, (int32_t *)ctx->top_first.p,
+                                                      (int32_t *)ctx->top_last.p);
+  HIP_TRY(ctx, hipGetLastError());
+  SPH_TRY(pack_neighbour_data(ctx, p));
+  ctx->state = 1;
+  return SPH_OK;
+}

@@ -1,0 +1,339 @@
+// Active set for the current time-bin (Eq. 2, Sec. III-D) and the cell-pair
+// lists of the active cells (Sec. III-A: every pair of cells with at least one
+// member on the active list, paired where the geometry allows an interaction).
+#include <math.h>
+#include <string.h>
+
+#include "sph_internal.h"
+
+#define MT 256
+#define CHUNK 64
+
+// One wave per leaf: active flags, the number of active particles, their
+// max H, and the number of 64-particle chunks.
+__global__ __launch_bounds__(MT) void mark_count_kernel(const int8_t *__restrict__ bin, int m,
+                                                        const float4 *__restrict__ pos4,
+                                                        const int32_t *__restrict__ leaf_begin,
+                                                        const int32_t *__restrict__ leaf_count, int64_t nl,
+                                                        uint8_t *__restrict__ active, int32_t *__restrict__ nact,
+                                                        int32_t *__restrict__ isact, int32_t *__restrict__ nchunk,
+                                                        float *__restrict__ hmax_act_leaf) {
+  const int64_t l = (int64_t)blockIdx.x * (MT / 64) + (threadIdx.x >> 6);
+  if (l >= nl) return;
+  const int lane = threadIdx.x & 63;
+  const int b = leaf_begin[l], c = leaf_count[l];
+  int na = 0;
+  float hm = 0.f;
+  for (int t = 0; t < c; t += 64) {
+    const int k = t + lane;
+    const bool a = k < c && bin[b + k] <= m;
+    if (k < c) active[b + k] = a;
+    if (a) hm = fmaxf(hm, pos4[b + k].w);
+    na += __popcll(__ballot(a));
+  }
+  hm = wave_max_f(hm);
+  if (lane == 0) {
+    nact[l] = na;
+    isact[l] = na > 0;
+    nchunk[l] = (na + CHUNK - 1) / CHUNK;
+    hmax_act_leaf[l] = hm;
+  }
+}
+
+// One wave per active leaf: the ordered list of its active particles, the
+// chunk of each, the active-leaf table and the chunk table.
+__global__ __launch_bounds__(MT) void mark_fill_kernel(const uint8_t *__restrict__ active,
+                                                       const int32_t *__restrict__ leaf_begin,
+                                                       const int32_t *__restrict__ leaf_count, int64_t nl,
+                                                       const int32_t *__restrict__ nact,
+                                                       const int32_t *__restrict__ act_off,
+                                                       const int32_t *__restrict__ actleaf_idx,
+                                                       const int32_t *__restrict__ chunk_off,
+                                                       const float *__restrict__ hmax_act_leaf,
+                                                       int32_t *__restrict__ active_idx, int32_t *__restrict__ chunk_of,
+                                                       int32_t *__restrict__ act_leaves, float *__restrict__ act_hmax,
+                                                       int32_t *__restrict__ leaf_actleaf, Chunk *__restrict__ chunks) {
+  const int64_t l = (int64_t)blockIdx.x * (MT / 64) + (threadIdx.x >> 6);
+  if (l >= nl) return;
+  const int lane = threadIdx.x & 63;
+  const int na = nact[l];
+  if (na == 0) {
+    if (lane == 0) leaf_actleaf[l] = -1;
+    return;
+  }
+  const int b = leaf_begin[l], c = leaf_count[l];
+  const int ao = act_off[l], co = chunk_off[l], al = actleaf_idx[l];
+  int run = 0;
+  for (int t = 0; t < c; t += 64) {
+    const int k = t + lane;
+    const bool a = k < c && active[b + k];
+    const uint64_t mask = __ballot(a);
+    if (a) {
+      const int r = run + rank_below(mask);
+      active_idx[ao + r] = b + k;
+      chunk_of[ao + r] = co + r / CHUNK;
+    }
+    run += __popcll(mask);
+  }
+  if (lane == 0) {
+    act_leaves[al] = (int32_t)l;
+    act_hmax[al] = hmax_act_leaf[l];
+    leaf_actleaf[l] = al;
+  }
+  for (int q = lane; q * CHUNK < na; q += 64) {
+    Chunk ch;
+    ch.act_leaf = al;
+    ch.begin = ao + q * CHUNK;
+    ch.count = min(CHUNK, na - q * CHUNK);
+    ch.leaf = (int32_t)l;
+    chunks[co + q] = ch;
+  }
+}
+
+struct PairGeom {
+  int D, k0;
+  int64_t nu;    // half-units per box side, 2^(D+1)
+  double unit;   // L / 2^(D+1)
+  double wtop;   // top-level cell side
+};
+
+__device__ __forceinline__ void leaf_centre_units(int D, int lvl, int ix, int iy, int iz, int64_t *c) {
+  const int sh = D - lvl;
+  c[0] = (2 * (int64_t)ix + 1) << sh;
+  c[1] = (2 * (int64_t)iy + 1) << sh;
+  c[2] = (2 * (int64_t)iz + 1) << sh;
+}
+
+// One wave per active leaf A: walk the top-level cells within reach, test
+// every leaf B there by periodic box distance (exact integer gaps, compared in
+// double) and count (FILL=false) or write (FILL=true) the pairs in a fixed
+// order.  mode 0: R = max active H of A; mode 1: R = max(that, max H of B).
+template <bool FILL>
+__global__ __launch_bounds__(MT) void pairs_kernel(int mode, PairGeom g, int64_t n_act_leaves,
+                                                   const int32_t *__restrict__ act_leaves,
+                                                   const float *__restrict__ act_hmax,
+                                                   const int32_t *__restrict__ level, const int32_t *__restrict__ ix,
+                                                   const int32_t *__restrict__ iy, const int32_t *__restrict__ iz,
+                                                   const float *__restrict__ leaf_hmax,
+                                                   const int32_t *__restrict__ top_first,
+                                                   const int32_t *__restrict__ top_last, float hmax_global,
+                                                   int32_t *__restrict__ counts, const int32_t *__restrict__ offs,
+                                                   PairEntry *__restrict__ out) {
+  const int64_t a = (int64_t)blockIdx.x * (MT / 64) + (threadIdx.x >> 6);
+  if (a >= n_act_leaves) return;
+  const int lane = threadIdx.x & 63;
+  const int A = act_leaves[a];
+  const float RA = act_hmax[a];
+  const int lvA = level[A];
+  int64_t ca[3];
+  leaf_centre_units(g.D, lvA, ix[A], iy[A], iz[A], ca);
+  const int64_t hwa = (int64_t)1 << (g.D - lvA);
+  const float Rreach = mode == 0 ? RA : fmaxf(RA, hmax_global);
+  const int ntop = 1 << g.k0;
+  const double rr = ceil((double)Rreach / g.wtop);
+  const int ring = (rr >= 0.0 && rr < (double)ntop) ? (int)rr : ntop;  // non-finite reach: every top cell
+  const int sA = lvA - g.k0;
+  const int t[3] = {ix[A] >> sA, iy[A] >> sA, iz[A] >> sA};
+  int lo[3], cnt3[3];
+  for (int d = 0; d < 3; ++d) {
+    if (2 * ring + 1 >= ntop) {
+      lo[d] = 0;
+      cnt3[d] = ntop;
+    } else {
+      lo[d] = t[d] - ring;
+      cnt3[d] = 2 * ring + 1;
+    }
+  }
+  int written = 0;
+  const int base = FILL ? offs[a] : 0;
+  for (int u = 0; u < cnt3[0]; ++u) {
+    const int tx = ((lo[0] + u) % ntop + ntop) % ntop;
+    for (int v = 0; v < cnt3[1]; ++v) {
+      const int ty = ((lo[1] + v) % ntop + ntop) % ntop;
+      for (int w = 0; w < cnt3[2]; ++w) {
+        const int tz = ((lo[2] + w) % ntop + ntop) % ntop;
+        const int64_t tc = ((int64_t)tx * ntop + ty) * ntop + tz;
+        const int f = top_first[tc], e = top_last[tc];
+        for (int B0 = f; B0 < e; B0 += 64) {
+          const int B = B0 + lane;
+          bool ok = false;
+          int64_t dl[3] = {0, 0, 0};
+          if (B < e) {
+            int64_t cb[3];
+            const int lvB = level[B];
+            leaf_centre_units(g.D, lvB, ix[B], iy[B], iz[B], cb);
+            const int64_t hwb = (int64_t)1 << (g.D - lvB);
+            double d2 = 0.0;
+            for (int d = 0; d < 3; ++d) {
+              int64_t dd = cb[d] - ca[d];
+              if (dd > g.nu / 2) dd -= g.nu;
+              if (dd < -g.nu / 2) dd += g.nu;
+              dl[d] = dd;
+              int64_t gap = (dd < 0 ? -dd : dd) - hwa - hwb;
+              if (gap < 0) gap = 0;
+              const double gd = (double)gap * g.unit;
+              d2 = d2 + gd * gd;
+            }
+            float R = RA;
+            if (mode == 1) R = fmaxf(R, leaf_hmax[B]);
+            const double Rd = (double)R;
+            ok = d2 < Rd * Rd;
+          }
+          const uint64_t mask = __ballot(ok);
+          if (FILL && ok) {
+            PairEntry pe;
+            pe.b = B;
+            pe.sx = (float)((double)dl[0] * g.unit);
+            pe.sy = (float)((double)dl[1] * g.unit);
+            pe.sz = (float)((double)dl[2] * g.unit);
+            out[base + written + rank_below(mask)] = pe;
+          }
+          written += __popcll(mask);
+        }
+      }
+    }
+  }
+  if (!FILL && lane == 0) counts[a] = written;
+}
+
+// Max H over each active leaf's particles (all of them) and the running
+// global max, after the density loop changed active smoothing lengths.
+__global__ __launch_bounds__(MT) void leaf_hmax_refresh_kernel(const float4 *__restrict__ pos4,
+                                                               const uint8_t *__restrict__ active,
+                                                               const int32_t *__restrict__ leaf_begin,
+                                                               const int32_t *__restrict__ leaf_count,
+                                                               const int32_t *__restrict__ act_leaves,
+                                                               int64_t n_act_leaves, float *__restrict__ leaf_hmax,
+                                                               float *__restrict__ act_hmax,
+                                                               int *__restrict__ hmax_bits) {
+  const int64_t a = (int64_t)blockIdx.x * (MT / 64) + (threadIdx.x >> 6);
+  if (a >= n_act_leaves) return;
+  const int lane = threadIdx.x & 63;
+  const int A = act_leaves[a];
+  const int b = leaf_begin[A], c = leaf_count[A];
+  float hm = 0.f, ha = 0.f;
+  for (int k = lane; k < c; k += 64) {
+    const float H = pos4[b + k].w;
+    hm = fmaxf(hm, H);
+    if (active[b + k]) ha = fmaxf(ha, H);
+  }
+  hm = wave_max_f(hm);
+  ha = wave_max_f(ha);
+  if (lane == 0) {
+    leaf_hmax[A] = hm;
+    act_hmax[a] = ha;
+    atomicMax(hmax_bits, __float_as_int(hm));
+  }
+}
+
+static unsigned waves_grid(int64_t n_items) { return (unsigned)(ceil_div(n_items, MT / 64) > 0 ? ceil_div(n_items, MT / 64) : 1); }
+
+sph_status build_pairs(sph_ctx *ctx, int which) {
+  const int64_t na = ctx->n_active_leaves;
+  DevBuf &off = which == 0 ? ctx->dpair_off : ctx->fpair_off;
+  DevBuf &lst = which == 0 ? ctx->dpairs : ctx->fpairs;
+  SPH_TRY(sph_ensure(ctx, ctx->pair_cnt, 4 * (size_t)(na + 1)));
+  SPH_TRY(sph_ensure(ctx, off, 4 * (size_t)(na + 1)));
+  PairGeom g;
+  g.D = ctx->prm.morton_depth;
+  g.k0 = ctx->top_level;
+  g.nu = (int64_t)1 << (g.D + 1);
+  g.unit = ldexp(ctx->prm.box, -(g.D + 1));
+  g.wtop = ldexp(ctx->prm.box, -g.k0);
+  int32_t *sc = (int32_t *)ctx->scalars.p;
+  if (na == 0) {
+    if (which == 0) ctx->n_dpairs = 0; else ctx->n_fpairs = 0;
+    HIP_TRY(ctx, hipMemsetAsync(off.p, 0, 4, ctx->stream));
+    return SPH_OK;
+  }
+  pairs_kernel<false><<<waves_grid(na), MT, 0, ctx->stream>>>(
+      which, g, na, (const int32_t *)ctx->act_leaves.p, (const float *)ctx->act_hmax.p,
+      (const int32_t *)ctx->leaf_level.p, (const int32_t *)ctx->leaf_ix.p, (const int32_t *)ctx->leaf_iy.p,
+      (const int32_t *)ctx->leaf_iz.p, (const float *)ctx->leaf_hmax.p, (const int32_t *)ctx->top_first.p,
+      (const int32_t *)ctx->top_last.p, ctx->hmax_global, (int32_t *)ctx->pair_cnt.p, nullptr, nullptr);
+  HIP_TRY(ctx, hipGetLastError());
+  int32_t *o = (int32_t *)off.p;
+  SPH_TRY(scan_exclusive_i32(ctx, (const int32_t *)ctx->pair_cnt.p, o, na, o + na));
+  int32_t np;
+  HIP_TRY(ctx, hipMemcpyAsync(&np, o + na, 4, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  (void)sc;
+  SPH_TRY(sph_ensure(ctx, lst, sizeof(PairEntry) * (size_t)(np > 0 ? np : 1)));
+  pairs_kernel<true><<<waves_grid(na), MT, 0, ctx->stream>>>(
+      which, g, na, (const int32_t *)ctx->act_leaves.p, (const float *)ctx->act_hmax.p,
+      (const int32_t *)ctx->leaf_level.p, (const int32_t *)ctx->leaf_ix.p, (const int32_t *)ctx->leaf_iy.p,
+      (const int32_t *)ctx->leaf_iz.p, (const float *)ctx->leaf_hmax.p, (const int32_t *)ctx->top_first.p,
+      (const int32_t *)ctx->top_last.p, ctx->hmax_global, nullptr, o, (PairEntry *)lst.p);
+  HIP_TRY(ctx, hipGetLastError());
+  if (which == 0) ctx->n_dpairs = np; else ctx->n_fpairs = np;
+  return SPH_OK;
+}
+
+sph_status refresh_leaf_hmax(sph_ctx *ctx) {
+  const int64_t na = ctx->n_active_leaves;
+  if (na == 0) return SPH_OK;
+  int32_t *sc = (int32_t *)ctx->scalars.p;
+  int32_t hb;
+  {
+    float hg = ctx->hmax_global;
+    memcpy(&hb, &hg, 4);
+  }
+  HIP_TRY(ctx, hipMemcpyAsync(sc + SC_HMAX_BITS, &hb, 4, hipMemcpyHostToDevice, ctx->stream));
+  leaf_hmax_refresh_kernel<<<waves_grid(na), MT, 0, ctx->stream>>>(
+      (const float4 *)ctx->pos4.p, (const uint8_t *)ctx->active.p, (const int32_t *)ctx->leaf_begin.p,
+      (const int32_t *)ctx->leaf_count.p, (const int32_t *)ctx->act_leaves.p, na, (float *)ctx->leaf_hmax.p,
+      (float *)ctx->act_hmax.p, sc + SC_HMAX_BITS);
+  HIP_TRY(ctx, hipGetLastError());
+  SPH_TRY(read_scalars(ctx, SC_HMAX_BITS, 1, &hb));
+  float hg;
+  memcpy(&hg, &hb, 4);
+  ctx->hmax_global = hg;
+  return SPH_OK;
+}
+
+sph_status mark_active_impl(sph_ctx *ctx, const sph_particles *p, int m, int64_t *n_active_host) {
+  if (!p || !p->time_bin) return sph_fail(ctx, SPH_EINVAL, "mark_active: time_bin is required");
+  if (m < 0 || m >= ctx->prm.n_bins) return sph_fail(ctx, SPH_EINVAL, "mark_active: bin %d outside [0, %d)", m, ctx->prm.n_bins);
+  const int64_t n = ctx->n, nl = ctx->n_leaves;
+  ctx->max_active_bin = m;
+  SPH_TRY(sph_ensure(ctx, ctx->active, (size_t)n));
+  SPH_TRY(sph_ensure(ctx, ctx->leaf_nact, 4 * (size_t)(3 * nl + 3)));
+  SPH_TRY(sph_ensure(ctx, ctx->leaf_act_off, 4 * (size_t)(3 * nl + 3)));
+  SPH_TRY(sph_ensure(ctx, ctx->leaf_actleaf, 4 * (size_t)nl));
+  SPH_TRY(sph_ensure(ctx, ctx->act_leaf_chunk_off, 4 * (size_t)nl));
+  int32_t *nact = (int32_t *)ctx->leaf_nact.p, *isact = nact + nl, *nchunk = nact + 2 * nl;
+  int32_t *aoff = (int32_t *)ctx->leaf_act_off.p, *aidx = aoff + nl, *coff = aoff + 2 * nl;
+  float *hmax_act_leaf = (float *)ctx->act_leaf_chunk_off.p;
+  int32_t *sc = (int32_t *)ctx->scalars.p;
+  mark_count_kernel<<<waves_grid(nl), MT, 0, ctx->stream>>>(p->time_bin, m, (const float4 *)ctx->pos4.p,
+                                                            (const int32_t *)ctx->leaf_begin.p,
+                                                            (const int32_t *)ctx->leaf_count.p, nl,
+                                                            (uint8_t *)ctx->active.p, nact, isact, nchunk,
+                                                            hmax_act_leaf);
+  HIP_TRY(ctx, hipGetLastError());
+  SPH_TRY(scan_exclusive_i32(ctx, nact, aoff, nl, sc + SC_TOTAL0));
+  SPH_TRY(scan_exclusive_i32(ctx, isact, aidx, nl, sc + SC_TOTAL1));
+  SPH_TRY(scan_exclusive_i32(ctx, nchunk, coff, nl, sc + SC_TOTAL2));
+  int32_t tot[3];
+  SPH_TRY(read_scalars(ctx, SC_TOTAL0, 3, tot));
+  ctx->n_active = tot[0];
+  ctx->n_active_leaves = tot[1];
+  ctx->n_chunks = tot[2];
+  const int64_t nact_tot = tot[0] > 0 ? tot[0] : 1, nal = tot[1] > 0 ? tot[1] : 1, nch = tot[2] > 0 ? tot[2] : 1;
+  SPH_TRY(sph_ensure(ctx, ctx->active_idx, 4 * (size_t)nact_tot));
+  SPH_TRY(sph_ensure(ctx, ctx->chunk_of, 4 * (size_t)nact_tot));
+  SPH_TRY(sph_ensure(ctx, ctx->act_leaves, 4 * (size_t)nal));
+  SPH_TRY(sph_ensure(ctx, ctx->act_hmax, 4 * (size_t)nal));
+  SPH_TRY(sph_ensure(ctx, ctx->chunks, sizeof(Chunk) * (size_t)nch));
+  SPH_TRY(sph_ensure(ctx, ctx->chunk_todo, 4 * (size_t)nch));
+  mark_fill_kernel<<<waves_grid(nl), MT, 0, ctx->stream>>>(
+      (const uint8_t *)ctx->active.p, (const int32_t *)ctx->leaf_begin.p, (const int32_t *)ctx->leaf_count.p, nl,
+      nact, aoff, aidx, coff, hmax_act_leaf, (int32_t *)ctx->active_idx.p, (int32_t *)ctx->chunk_of.p,
+      (int32_t *)ctx->act_leaves.p, (float *)ctx->act_hmax.p, (int32_t *)ctx->leaf_actleaf.p,
+      (Chunk *)ctx->chunks.p);
+  HIP_TRY(ctx, hipGetLastError());
+  SPH_TRY(build_pairs(ctx, 0));
+  if (n_active_host) *n_active_host = ctx->n_active;
+  ctx->state = 3;
+  return SPH_OK;
+}

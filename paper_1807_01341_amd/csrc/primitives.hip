@@ -1,0 +1,220 @@
+// Device-wide primitives: exclusive prefix sum (int32) and a stable LSD radix
+// sort of (uint64 key, int32 value) pairs with 8-bit digits.
+#include <stdarg.h>
+#include <stdio.h>
+
+#include "sph_internal.h"
+
+// ---------------------------------------------------------------- host helpers
+
+sph_status sph_fail(sph_ctx *ctx, sph_status code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (ctx) ctx->err = buf;
+  return code;
+}
+
+sph_status sph_hip_check(sph_ctx *ctx, hipError_t e, const char *what) {
+  if (e == hipSuccess) return SPH_OK;
+  if (e == hipErrorOutOfMemory) return sph_fail(ctx, SPH_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+  return sph_fail(ctx, SPH_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+sph_status sph_ensure(sph_ctx *ctx, DevBuf &b, size_t bytes) {
+  if (bytes <= b.cap && b.p) return SPH_OK;
+  if (b.p) {
+    // the old buffer may still be read by queued work
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    HIP_TRY(ctx, hipFree(b.p));
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  size_t cap = bytes < 256 ? 256 : bytes + bytes / 8;
+  hipError_t e = hipMalloc(&b.p, cap);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    return sph_fail(ctx, SPH_ENOMEM, "hipMalloc(%zu bytes) failed: %s", cap, hipGetErrorString(e));
+  }
+  b.cap = cap;
+  return SPH_OK;
+}
+
+sph_status read_scalars(sph_ctx *ctx, int first, int count, int32_t *host) {
+  HIP_TRY(ctx, hipMemcpyAsync(host, (int32_t *)ctx->scalars.p + first, sizeof(int32_t) * count,
+                              hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return SPH_OK;
+}
+
+// ---------------------------------------------------------------- scan
+
+#define SCAN_THREADS 256
+#define SCAN_ROUNDS 16
+#define SCAN_TILE (SCAN_THREADS * SCAN_ROUNDS)
+
+__device__ __forceinline__ int wave_inclusive_scan(int v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// WRITE=false: per-block totals.  WRITE=true: exclusive scan of the tile plus
+// the block offset (or 0), and the grand total from the last block.
+template <bool WRITE>
+__global__ __launch_bounds__(SCAN_THREADS) void scan_kernel(const int32_t *__restrict__ in, int32_t *__restrict__ out,
+                                                            int64_t n, int32_t *__restrict__ block_sums,
+                                                            const int32_t *__restrict__ block_offsets,
+                                                            int32_t *__restrict__ total) {
+  __shared__ int wsum[SCAN_THREADS / 64];
+  const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+  int carry = (WRITE && block_offsets) ? block_offsets[blockIdx.x] : 0;
+  for (int r = 0; r < SCAN_ROUNDS; ++r) {
+    const int64_t i = base + (int64_t)r * SCAN_THREADS + tid;
+    const int v = i < n ? in[i] : 0;
+    const int inc = wave_inclusive_scan(v);
+    if (lane == 63) wsum[wid] = inc;
+    __syncthreads();
+    int wpre = 0, rtot = 0;
+#pragma unroll
+    for (int w = 0; w < SCAN_THREADS / 64; ++w) {
+      const int s = wsum[w];
+      if (w < wid) wpre += s;
+      rtot += s;
+    }
+    if (WRITE && i < n) out[i] = carry + wpre + inc - v;
+    carry += rtot;
+    __syncthreads();
+  }
+  if (!WRITE && tid == 0) block_sums[blockIdx.x] = carry;
+  if (WRITE && total && blockIdx.x == gridDim.x - 1 && tid == 0) *total = carry;
+}
+
+static sph_status scan_rec(sph_ctx *ctx, const int32_t *in, int32_t *out, int64_t n, int32_t *total,
+                           int32_t *tmp) {
+  const int64_t nb = ceil_div(n, SCAN_TILE);
+  if (nb <= 1) {
+    scan_kernel<true><<<1, SCAN_THREADS, 0, ctx->stream>>>(in, out, n, nullptr, nullptr, total);
+    return sph_hip_check(ctx, hipGetLastError(), "scan_kernel");
+  }
+  int32_t *bsum = tmp, *boff = tmp + nb;
+  scan_kernel<false><<<(unsigned)nb, SCAN_THREADS, 0, ctx->stream>>>(in, nullptr, n, bsum, nullptr, nullptr);
+  HIP_TRY(ctx, hipGetLastError());
+  SPH_TRY(scan_rec(ctx, bsum, boff, nb, nullptr, tmp + 2 * nb));
+  scan_kernel<true><<<(unsigned)nb, SCAN_THREADS, 0, ctx->stream>>>(in, out, n, nullptr, boff, total);
+  return sph_hip_check(ctx, hipGetLastError(), "scan_kernel");
+}
+
+sph_status scan_exclusive_i32(sph_ctx *ctx, const int32_t *in, int32_t *out, int64_t n, int32_t *total_dev) {
+  if (n <= 0) {
+    if (total_dev) HIP_TRY(ctx, hipMemsetAsync(total_dev, 0, sizeof(int32_t), ctx->stream));
+    return SPH_OK;
+  }
+  // temp: 2 * (n/T + n/T^2 + ...) ints
+  int64_t need = 0, m = n;
+  while (m > SCAN_TILE) {
+    m = ceil_div(m, SCAN_TILE);
+    need += 2 * m;
+  }
+  SPH_TRY(sph_ensure(ctx, ctx->scan_tmp, sizeof(int32_t) * (size_t)(need + 16)));
+  return scan_rec(ctx, in, out, n, total_dev, (int32_t *)ctx->scan_tmp.p);
+}
+
+// ---------------------------------------------------------------- radix sort
+
+#define RS_THREADS 256
+#define RS_ROUNDS 16
+#define RS_TILE (RS_THREADS * RS_ROUNDS)
+
+__global__ __launch_bounds__(RS_THREADS) void radix_hist_kernel(const uint64_t *__restrict__ keys, int64_t n, int shift,
+                                                                int32_t *__restrict__ counts, int nblocks) {
+  __shared__ int h[256];
+  const int tid = threadIdx.x;
+  h[tid] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+  for (int r = 0; r < RS_ROUNDS; ++r) {
+    const int64_t i = base + (int64_t)r * RS_THREADS + tid;
+    if (i < n) atomicAdd(&h[(int)((keys[i] >> shift) & 255ull)], 1);
+  }
+  __syncthreads();
+  counts[(int64_t)tid * nblocks + blockIdx.x] = h[tid];
+}
+
+// Stable scatter: elements of a tile keep their order among equal digits.
+// Each round ranks 256 consecutive elements: within a wave by matching digits
+// with 8 ballots, across the block's waves through per-wave digit counts.
+__global__ __launch_bounds__(RS_THREADS) void radix_scatter_kernel(const uint64_t *__restrict__ kin,
+                                                                   const int32_t *__restrict__ vin,
+                                                                   uint64_t *__restrict__ kout,
+                                                                   int32_t *__restrict__ vout, int64_t n, int shift,
+                                                                   const int32_t *__restrict__ offsets, int nblocks) {
+  __shared__ int run[256];
+  __shared__ int wcnt[RS_THREADS / 64][256];
+  const int tid = threadIdx.x, wid = tid >> 6;
+  run[tid] = offsets[(int64_t)tid * nblocks + blockIdx.x];
+  const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+  for (int r = 0; r < RS_ROUNDS; ++r) {
+#pragma unroll
+    for (int w = 0; w < RS_THREADS / 64; ++w) wcnt[w][tid] = 0;
+    __syncthreads();
+    const int64_t i = base + (int64_t)r * RS_THREADS + tid;
+    const bool valid = i < n;
+    const uint64_t key = valid ? kin[i] : 0ull;
+    const int d = (int)((key >> shift) & 255ull);
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1;
+      const uint64_t bal = __ballot(bit);
+      peers &= bit ? bal : ~bal;
+    }
+    const int rank = rank_below(peers);
+    if (valid && rank == 0) wcnt[wid][d] = __popcll(peers);
+    __syncthreads();
+    if (valid) {
+      int pos = run[d] + rank;
+      for (int w = 0; w < wid; ++w) pos += wcnt[w][d];
+      kout[pos] = key;
+      vout[pos] = vin[i];
+    }
+    __syncthreads();
+    int add = 0;
+#pragma unroll
+    for (int w = 0; w < RS_THREADS / 64; ++w) add += wcnt[w][tid];
+    run[tid] += add;
+    __syncthreads();
+  }
+}
+
+sph_status radix_sort_pairs(sph_ctx *ctx, int64_t n, int bits) {
+  if (n <= 1) return SPH_OK;
+  const int nblocks = (int)ceil_div(n, RS_TILE);
+  SPH_TRY(sph_ensure(ctx, ctx->radix_counts, sizeof(int32_t) * 256 * (size_t)nblocks * 2));
+  int32_t *counts = (int32_t *)ctx->radix_counts.p;
+  int32_t *offs = counts + 256 * (size_t)nblocks;
+  uint64_t *ka = (uint64_t *)ctx->keys_a.p, *kb = (uint64_t *)ctx->keys_b.p;
+  int32_t *va = (int32_t *)ctx->vals_a.p, *vb = (int32_t *)ctx->vals_b.p;
+  int passes = 0;
+  for (int shift = 0; shift < bits; shift += 8, ++passes) {
+    radix_hist_kernel<<<nblocks, RS_THREADS, 0, ctx->stream>>>(ka, n, shift, counts, nblocks);
+    HIP_TRY(ctx, hipGetLastError());
+    SPH_TRY(scan_exclusive_i32(ctx, counts, offs, 256 * (int64_t)nblocks, nullptr));
+    radix_scatter_kernel<<<nblocks, RS_THREADS, 0, ctx->stream>>>(ka, va, kb, vb, n, shift, offs, nblocks);
+    HIP_TRY(ctx, hipGetLastError());
+    uint64_t *tk = ka; ka = kb; kb = tk;
+    int32_t *tv = va; va = vb; vb = tv;
+  }
+  if (passes & 1) {
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->keys_a.p, ka, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->vals_a.p, va, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, ctx->stream));
+  }
+  return SPH_OK;
+}

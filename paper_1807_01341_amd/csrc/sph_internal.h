@@ -1,0 +1,170 @@
+// Internal declarations of the sphgpu library: the context, device buffers,
+// shared device helpers and the host launchers of every kernel file.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "sphgpu.h"
+
+// Kernel support over smoothing length (H = GK32 * h), rounded to float.
+#define GK32 1.825742f
+// 3-D normalisation of the M4 cubic spline on q = r/H: 8/pi.
+#define KNORM32 2.5464790894703255f
+
+#define WAVE 64
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t cap = 0;
+};
+
+// Pair-list entry: partner leaf index (as int bits) and the FP32 shift of the
+// partner's offsets into the owner leaf's frame.
+struct PairEntry {
+  int32_t b;
+  float sx, sy, sz;
+};
+
+struct Chunk {
+  int32_t act_leaf;  // index into the active-leaf list
+  int32_t begin;     // first active index (into active_idx)
+  int32_t count;     // <= 64 active particles
+  int32_t leaf;      // leaf index
+};
+
+struct sph_ctx {
+  sph_params prm;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::string err;
+  int state = 0;  // 0 none, 1 built, 2 sorted, 3 marked, 4 density done, 5 force done
+  int64_t n = 0;
+  int top_level = 0;
+  int64_t n_leaves = 0;
+  int64_t n_active = 0, n_active_leaves = 0, n_chunks = 0;
+  int64_t n_dpairs = 0, n_fpairs = 0;
+  int max_active_bin = 0;
+  int density_iterations = 0;
+  int64_t n_unconverged = 0;
+  float hmax_global = 0.f;  // max H over all particles (monotone between builds)
+
+  // build
+  DevBuf keys_a, keys_b, vals_a, vals_b, radix_counts, scan_tmp, gather_tmp;
+  DevBuf scalars;                         // small device counters
+  DevBuf flags, scan_out, nodes_a, nodes_b, leaf_lvl_at;
+  DevBuf leaf_level, leaf_ix, leaf_iy, leaf_iz, leaf_begin, leaf_count, leaf_hmax, leaf_of;
+  DevBuf top_first, top_last;
+  DevBuf pos4;                            // float4 (ox, oy, oz, H) per particle
+  // sort
+  DevBuf axis_order;                      // uint16 13 x n
+  // mark
+  DevBuf active, leaf_nact, leaf_act_off, leaf_actleaf, act_leaves, act_hmax, act_leaf_chunk_off;
+  DevBuf active_idx, chunk_of, chunks, chunk_todo;
+  DevBuf dpair_off, dpairs, fpair_off, fpairs, pair_cnt;
+  // loops
+  DevBuf jvm;                             // float4 (vx, vy, vz, m)
+  DevBuf jth;                             // float4 (rho, f P / rho^2, c, B)
+  DevBuf sums, hlo, hhi, conv;
+  DevBuf host_counters;                   // pinned host mirror of scalars
+};
+
+// ---------------------------------------------------------------- host helpers
+sph_status sph_fail(sph_ctx *ctx, sph_status code, const char *fmt, ...);
+sph_status sph_hip_check(sph_ctx *ctx, hipError_t e, const char *what);
+sph_status sph_ensure(sph_ctx *ctx, DevBuf &b, size_t bytes);
+
+#define SPH_TRY(expr)                    \
+  do {                                   \
+    sph_status _s = (expr);              \
+    if (_s != SPH_OK) return _s;         \
+  } while (0)
+#define HIP_TRY(ctx, expr) SPH_TRY(sph_hip_check((ctx), (expr), #expr))
+
+// Scratch counters in ctx->scalars (int32 slots).
+enum ScalarSlot {
+  SC_TOTAL0 = 0,      // scan totals
+  SC_TOTAL1 = 1,
+  SC_TOTAL2 = 2,
+  SC_NODES_A = 4,
+  SC_NODES_B = 5,
+  SC_HMAX_BITS = 6,
+  SC_UNCONV = 8,
+  SC_REBUILD = 9,
+  SC_PAIRTOT = 10,
+  SC_MAXLEAF = 11,
+  SC_COUNT = 32
+};
+
+// ---------------------------------------------------------------- primitives (primitives.hip)
+// Exclusive prefix sum of n int32 values; the total lands in *total_dev.
+sph_status scan_exclusive_i32(sph_ctx *ctx, const int32_t *in, int32_t *out, int64_t n, int32_t *total_dev);
+// Stable LSD radix sort of (key, value) pairs on the low `bits` key bits.
+// The sorted result is left in ctx->keys_a / ctx->vals_a.
+sph_status radix_sort_pairs(sph_ctx *ctx, int64_t n, int bits);
+sph_status read_scalars(sph_ctx *ctx, int first, int count, int32_t *host);
+
+// ---------------------------------------------------------------- stages
+sph_status build_cells_impl(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *perm_out);
+sph_status sort_cells_impl(sph_ctx *ctx);
+sph_status mark_active_impl(sph_ctx *ctx, const sph_particles *p, int m, int64_t *n_active_host);
+sph_status build_pairs(sph_ctx *ctx, int which);
+sph_status refresh_leaf_hmax(sph_ctx *ctx);
+sph_status pack_neighbour_data(sph_ctx *ctx, const sph_particles *p);
+sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u);
+sph_status force_pass_impl(sph_ctx *ctx, sph_particles *p);
+sph_status kick_drift_impl(sph_ctx *ctx, sph_particles *p, int64_t ti, double t_min, int64_t drift_int,
+                           int first_step);
+
+// ---------------------------------------------------------------- device helpers
+__device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+// Number of set bits of `mask` below this lane.
+__device__ __forceinline__ int rank_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ float wave_max_f(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ float wave_min_f(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_sum_i(int v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// max of non-negative floats through their int bit patterns
+__device__ __forceinline__ void atomic_max_pos_f(float *addr, float v) {
+  atomicMax(reinterpret_cast<int *>(addr), __float_as_int(v));
+}
+
+// Morton helpers (21 bits per axis)
+__host__ __device__ __forceinline__ uint64_t spread3_21(uint64_t v) {
+  v &= 0x1fffffull;
+  v = (v | (v << 32)) & 0x1f00000000ffffull;
+  v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+  v = (v | (v << 8)) & 0x100f00f00f00f00full;
+  v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+  v = (v | (v << 2)) & 0x1249249249249249ull;
+  return v;
+}
+__host__ __device__ __forceinline__ uint32_t compact3_21(uint64_t v) {
+  v &= 0x1249249249249249ull;
+  v = (v ^ (v >> 2)) & 0x10c30c30c30c30c3ull;
+  v = (v ^ (v >> 4)) & 0x100f00f00f00f00full;
+  v = (v ^ (v >> 8)) & 0x1f0000ff0000ffull;
+  v = (v ^ (v >> 16)) & 0x1f00000000ffffull;
+  v = (v ^ (v >> 32)) & 0x1fffffull;
+  return (uint32_t)v;
+}
+
+__host__ __device__ __forceinline__ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

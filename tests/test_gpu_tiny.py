@@ -1,0 +1,135 @@
+"""GPU parity on the tiny workload (16^3 jittered lattice, all active) and
+its variants, through the C-ABI."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import ics
+from oracle import sph
+from tests.gpu_cases import (A_TOL, RHO_TOL, check_counts, check_structures, float_errors, host, oracle_all,
+                             run_gpu_step)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("sigma", [0.0, 0.1])
+def test_tiny_lattice_step(gpu_lib, sigma):
+    ic = ics.tiny_lattice(16, velocity_sigma=sigma)
+    print(f"case tiny16 sigma={sigma}", flush=True)
+    ctx, p, perm, snap = run_gpu_step(gpu_lib, ic, 0)
+    cl, act = check_structures(ic, perm, snap)
+    check_counts(cl, p, snap, perm, ic, 0)
+    out, fo = oracle_all(ic)
+    e = float_errors(p, perm, out, fo)
+    print({k: f"{v:.2e}" for k, v in e.items()})
+    assert e["rho"] < RHO_TOL
+    assert e["h"] < 1e-5
+    assert e["a"] < A_TOL
+    assert e["f"] < 1e-5 and e["P"] < 1e-5 and e["c"] < 1e-5
+    assert e["vsig"] < 1e-5
+    if sigma > 0:
+        assert e["divv"] < 1e-3 and e["curlv"] < 1e-3 and e["B"] < 1e-3 and e["dA_dt"] < 1e-3
+    assert snap["info"]["n_unconverged"] == 0
+
+
+def test_perfect_lattice_counts_and_density(gpu_lib):
+    ic = ics.perfect_lattice(16)
+    ctx, p, perm, snap = run_gpu_step(gpu_lib, ic, 0)
+    # 56 neighbours besides itself for every particle, the lattice root density
+    assert np.all(host(p, "nngb_density") == 56)
+    rho = host(p, "rho").astype(np.float64)
+    assert np.max(np.abs(rho / 1.004021830777798 - 1)) < RHO_TOL
+    assert np.max(np.abs(host(p, "h") * 16 / 1.2331490390680415 - 1)) < 1e-5
+    a = np.stack([host(p, k) for k in ("ax", "ay", "az")], 1)
+    out, fo = oracle_all(ic)
+    S = fo["scale"].numpy()[perm]
+    assert np.max(np.linalg.norm(a, axis=1) / S) < 1e-6
+
+
+def test_deterministic(gpu_lib):
+    ic = ics.tiny_lattice(16, velocity_sigma=0.1)
+    r = []
+    for _ in range(2):
+        _, p, perm, _ = run_gpu_step(gpu_lib, ic, 0)
+        r.append({k: host(p, k).copy() for k in ("h", "rho", "ax", "ay", "az", "dA_dt", "vsig", "nngb_force")})
+    for k in r[0]:
+        assert np.array_equal(r[0][k].view(np.uint8), r[1][k].view(np.uint8)), k
+
+
+def test_kick_drift_matches_oracle(gpu_lib):
+    """kick_drift alone, on synthetic accelerations, smoothing lengths and
+    signal speeds (seeded), bit for bit against the FP64 definition."""
+    ic = ics.tiny_lattice(16, velocity_sigma=0.2)
+    rng = np.random.default_rng(11)
+    N = ic["x"].shape[0]
+    ic["bin"] = rng.integers(0, 6, size=N).astype(np.int8)
+    m_bin = 3
+    ctx, p, perm, snap = run_gpu_step(gpu_lib, ic, m_bin)
+    a = rng.normal(size=(N, 3)).astype(np.float32)
+    dA = rng.normal(size=N).astype(np.float32)
+    h = rng.uniform(0.05, 0.1, size=N).astype(np.float32)
+    vs = rng.uniform(0.5, 5.0, size=N).astype(np.float32)
+    vs[::17] = 0.0
+    Af = rng.uniform(0.5, 1.5, size=N).astype(np.float32)
+    for d, k in enumerate(("ax", "ay", "az")):
+        p[k].copy_(torch.from_numpy(a[:, d]))
+    p["dA_dt"].copy_(torch.from_numpy(dA))
+    p["h"].copy_(torch.from_numpy(h))
+    p["vsig"].copy_(torch.from_numpy(vs))
+    p["Af"].copy_(torch.from_numpy(Af))
+    p["A"].copy_(torch.from_numpy(Af))
+    x0 = np.stack([host(p, k) for k in "xyz"], 1)
+    vf0 = np.stack([host(p, k) for k in ("vfx", "vfy", "vfz")], 1)
+    vp0 = np.stack([host(p, k) for k in ("vx", "vy", "vz")], 1)
+    bins0 = host(p, "time_bin").astype(np.int64)
+    act = snap["active"]
+    t_min, ti, drift = 1e-4, 24, 8
+    ctx.kick_drift(p, ti, t_min, drift, False)
+    ctx.sync()
+    ref = sph.kick_drift(x0, vf0, vp0, Af.astype(np.float64), Af.astype(np.float64), a, dA, h, vs, bins0, act, ti,
+                         t_min, drift, 1.0)
+    assert np.array_equal(host(p, "time_bin").astype(np.int64), ref["bins"])
+    assert np.array_equal(np.stack([host(p, k) for k in "xyz"], 1), ref["x"])
+    assert np.array_equal(np.stack([host(p, k) for k in ("vfx", "vfy", "vfz")], 1), ref["vf"])
+    assert np.array_equal(np.stack([host(p, k) for k in ("vx", "vy", "vz")], 1), ref["vp"])
+    assert np.array_equal(host(p, "Af"), ref["Af"].astype(np.float32))
+    assert np.array_equal(host(p, "A"), ref["Ap"].astype(np.float32))
+
+
+def test_call_order_and_argument_errors(gpu_lib):
+    sg = gpu_lib
+    ic = ics.tiny_lattice(16)
+    p = sg.Particles.from_initial(ic)
+    ctx = sg.Context()
+    with pytest.raises(sg.SPHError) as e:
+        ctx.density_pass(p, True)
+    assert e.value.code == -6
+    ctx.build_cells(p)
+    ctx.sort_cells()
+    with pytest.raises(sg.SPHError) as e:
+        ctx.mark_active(p, 14)
+    assert e.value.code == -1
+    with pytest.raises(sg.SPHError) as e:
+        ctx.force_pass(p)
+    assert e.value.code == -6
+    # a box too small for the smoothing lengths
+    big = dict(ic)
+    big["h"] = np.full_like(ic["h"], 0.2)
+    pb = sg.Particles.from_initial(big)
+    with pytest.raises(sg.SPHError) as e:
+        ctx.build_cells(pb)
+    assert e.value.code == -1
+    # non-convergence reported with a tiny iteration budget
+    ctx2 = sg.Context(h_max_iter=1)
+    ic2 = dict(ic)
+    ic2["h"] = (ic["h"] * 1.3).astype(np.float32)
+    p2 = sg.Particles.from_initial(ic2)
+    ctx2.build_cells(p2)
+    ctx2.sort_cells()
+    ctx2.mark_active(p2, 0)
+    with pytest.raises(sg.SPHError) as e:
+        ctx2.density_pass(p2, True)
+    assert e.value.code == -4
+    assert ctx2.info()["n_unconverged"] > 0
