@@ -151,6 +151,15 @@ sph_status sph_kick_drift(sph_ctx *ctx, sph_particles *p, int64_t ti, double t_m
 sph_status sph_sync(sph_ctx *ctx);
 const char *sph_last_error(const sph_ctx *ctx);
 
+/* Per-kernel timing with HIP events recorded on the context's stream around
+ * each launch (or group of launches) of the library.  sph_profile(ctx, 1)
+ * clears the table and starts recording, 0 stops.  sph_profile_read
+ * synchronises, folds the recorded events into the table and writes it as
+ * text lines "name launches total_ms" into buf (NUL-terminated, truncated to
+ * cap); it returns the full length. */
+sph_status sph_profile(sph_ctx *ctx, int enable);
+int64_t sph_profile_read(sph_ctx *ctx, char *buf, int64_t cap);
+
 /* ---- Introspection, for checking the derived structures (all copies are
  * enqueued on the context's stream into caller DEVICE buffers of the sizes
  * given by sph_info). ---- */
@@ -164,6 +173,9 @@ typedef struct {
   int64_t n_force_pairs;     /* force cell-pair list of the last force pass */
   int32_t density_iterations;/* Newton passes of the last density pass */
   int64_t n_unconverged;     /* particles left unconverged by the last density pass */
+  int64_t interactions_density; /* cumulative over the context's life: in-support
+                                   pairs j != i of each finished density solve */
+  int64_t interactions_force;   /* cumulative: pairs j != i of every force loop */
 } sph_info_t;
 sph_status sph_info(sph_ctx *ctx, sph_info_t *out); /* synchronises */
 

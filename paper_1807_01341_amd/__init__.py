@@ -59,7 +59,8 @@ class ParticlesC(C.Structure):
 class Info(C.Structure):
     _fields_ = [("n", C.c_int64), ("n_leaves", C.c_int64), ("top_level", C.c_int32),
                 ("n_active", C.c_int64), ("n_active_leaves", C.c_int64), ("n_density_pairs", C.c_int64),
-                ("n_force_pairs", C.c_int64), ("density_iterations", C.c_int32), ("n_unconverged", C.c_int64)]
+                ("n_force_pairs", C.c_int64), ("density_iterations", C.c_int32), ("n_unconverged", C.c_int64),
+                ("interactions_density", C.c_int64), ("interactions_force", C.c_int64)]
 
 
 _lib = None
@@ -91,6 +92,8 @@ def lib():
             "sph_copy_axis_order": (i32, [vp, vp]),
             "sph_copy_active": (i32, [vp] * 4),
             "sph_copy_pairs": (i32, [vp, i32] + [vp] * 5),
+            "sph_profile": (i32, [vp, i32]),
+            "sph_profile_read": (i64, [vp, vp, i64]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(L, name)
@@ -104,7 +107,7 @@ def exported_symbols():
     return ["sph_default_params", "sph_create", "sph_destroy", "sph_build_cells", "sph_sort_cells",
             "sph_mark_active", "sph_density_pass", "sph_force_pass", "sph_kick_drift", "sph_sync",
             "sph_last_error", "sph_info", "sph_copy_leaves", "sph_copy_particles", "sph_copy_axis_order",
-            "sph_copy_active", "sph_copy_pairs"]
+            "sph_copy_active", "sph_copy_pairs", "sph_profile", "sph_profile_read"]
 
 
 def require_device():
@@ -237,6 +240,19 @@ class Context:
         inf = Info()
         self._check(lib().sph_info(self.h, C.byref(inf)))
         return {k: getattr(inf, k) for k, _ in Info._fields_}
+
+    def profile(self, enable: bool):
+        return self._check(lib().sph_profile(self.h, int(bool(enable))))
+
+    def profile_read(self) -> dict:
+        n = lib().sph_profile_read(self.h, None, 0)
+        buf = C.create_string_buffer(int(n) + 1)
+        lib().sph_profile_read(self.h, buf, int(n) + 1)
+        out = {}
+        for line in buf.value.decode().splitlines():
+            name, cnt, ms = line.split()
+            out[name] = (int(cnt), float(ms))
+        return out
 
     # ---- introspection
     def copy_leaves(self):

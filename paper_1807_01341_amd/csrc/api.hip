@@ -1,11 +1,87 @@
 // Public C-ABI entry points: argument and call-order checks around the stages.
+#include <stdio.h>
 #include <string.h>
 
 #include <new>
 
 #include "sph_internal.h"
 
+static hipEvent_t take_event(sph_ctx *ctx) {
+  if (!ctx->event_pool.empty()) {
+    hipEvent_t e = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+ProfScope::ProfScope(sph_ctx *c, const char *name) : ctx(c), on(c && c->prof) {
+  if (!on) return;
+  ev.name = name;
+  ev.a = take_event(ctx);
+  ev.b = take_event(ctx);
+  if (!ev.a || !ev.b) {
+    on = false;
+    return;
+  }
+  (void)hipEventRecord(ev.a, ctx->stream);
+}
+
+ProfScope::~ProfScope() {
+  if (!on) return;
+  (void)hipEventRecord(ev.b, ctx->stream);
+  ctx->pending.push_back(ev);
+}
+
+static void resolve_profile(sph_ctx *ctx) {
+  if (ctx->pending.empty()) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto &p : ctx->pending) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, p.a, p.b);
+    bool found = false;
+    for (auto &a : ctx->acc)
+      if (a.name == p.name) {
+        a.count += 1;
+        a.ms += ms;
+        found = true;
+        break;
+      }
+    if (!found) ctx->acc.push_back({p.name, 1, (double)ms});
+    ctx->event_pool.push_back(p.a);
+    ctx->event_pool.push_back(p.b);
+  }
+  ctx->pending.clear();
+}
+
 extern "C" {
+
+sph_status sph_profile(sph_ctx *ctx, int enable) {
+  if (!ctx) return SPH_EINVAL;
+  resolve_profile(ctx);
+  ctx->acc.clear();
+  ctx->prof = enable;
+  return SPH_OK;
+}
+
+int64_t sph_profile_read(sph_ctx *ctx, char *buf, int64_t cap) {
+  if (!ctx) return -1;
+  resolve_profile(ctx);
+  std::string s;
+  char line[256];
+  for (auto &a : ctx->acc) {
+    snprintf(line, sizeof line, "%s %ld %.6f\n", a.name.c_str(), a.count, a.ms);
+    s += line;
+  }
+  if (buf && cap > 0) {
+    const int64_t m = (int64_t)s.size() < cap - 1 ? (int64_t)s.size() : cap - 1;
+    memcpy(buf, s.data(), (size_t)m);
+    buf[m] = 0;
+  }
+  return (int64_t)s.size();
+}
 
 void sph_default_params(sph_params *p) {
   if (!p) return;
@@ -46,6 +122,14 @@ sph_status sph_create(const sph_params *p, void *hip_stream, sph_ctx **out) {
     delete ctx;
     return SPH_ENOMEM;
   }
+  if (sph_ensure(ctx, ctx->counters64, 2 * sizeof(uint64_t)) != SPH_OK) {
+    delete ctx;
+    return SPH_ENOMEM;
+  }
+  if (hipMemsetAsync(ctx->counters64.p, 0, 2 * sizeof(uint64_t), ctx->stream) != hipSuccess) {
+    delete ctx;
+    return SPH_EDEVICE;
+  }
   if (hipMemsetAsync(ctx->scalars.p, 0, sizeof(int32_t) * SC_COUNT, ctx->stream) != hipSuccess) {
     delete ctx;
     return SPH_EDEVICE;
@@ -57,7 +141,9 @@ sph_status sph_create(const sph_params *p, void *hip_stream, sph_ctx **out) {
 void sph_destroy(sph_ctx *ctx) {
   if (!ctx) return;
   (void)hipStreamSynchronize(ctx->stream);
-  DevBuf *bufs[] = {&ctx->keys_a, &ctx->keys_b, &ctx->vals_a, &ctx->vals_b, &ctx->radix_counts, &ctx->scan_tmp,
+  resolve_profile(ctx);
+  for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+  DevBuf *bufs[] = {&ctx->counters64, &ctx->keys_a, &ctx->keys_b, &ctx->vals_a, &ctx->vals_b, &ctx->radix_counts, &ctx->scan_tmp,
                     &ctx->gather_tmp, &ctx->scalars, &ctx->flags, &ctx->scan_out, &ctx->nodes_a, &ctx->nodes_b,
                     &ctx->leaf_lvl_at, &ctx->leaf_level, &ctx->leaf_ix, &ctx->leaf_iy, &ctx->leaf_iz,
                     &ctx->leaf_begin, &ctx->leaf_count, &ctx->leaf_hmax, &ctx->leaf_of, &ctx->top_first,
@@ -132,6 +218,10 @@ sph_status sph_info(sph_ctx *ctx, sph_info_t *out) {
   out->n_force_pairs = ctx->n_fpairs;
   out->density_iterations = ctx->density_iterations;
   out->n_unconverged = ctx->n_unconverged;
+  uint64_t c[2] = {0, 0};
+  HIP_TRY(ctx, hipMemcpy(c, ctx->counters64.p, sizeof c, hipMemcpyDeviceToHost));
+  out->interactions_density = (int64_t)c[0];
+  out->interactions_force = (int64_t)c[1];
   return SPH_OK;
 }
 

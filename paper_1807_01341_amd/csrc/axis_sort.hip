@@ -99,14 +99,20 @@ sph_status sort_cells_impl(sph_ctx *ctx) {
   if (maxc > 4096)
     return sph_fail(ctx, SPH_EINVAL, "sort_cells: a leaf holds %d particles (max 4096 for the axis sorts)", maxc);
   const AxisSet ax = make_axes();
-  axis_sort_kernel<512><<<(unsigned)nl, AS_THREADS, 0, ctx->stream>>>(
-      (const float4 *)ctx->pos4.p, (const int32_t *)ctx->leaf_begin.p, (const int32_t *)ctx->leaf_count.p, nl, n, ax,
-      0, (uint16_t *)ctx->axis_order.p);
+  {
+    PROF(ctx, "axis_sort");
+    axis_sort_kernel<512><<<(unsigned)nl, AS_THREADS, 0, ctx->stream>>>(
+        (const float4 *)ctx->pos4.p, (const int32_t *)ctx->leaf_begin.p, (const int32_t *)ctx->leaf_count.p, nl, n, ax,
+        0, (uint16_t *)ctx->axis_order.p);
+  }
   HIP_TRY(ctx, hipGetLastError());
   if (maxc > 512) {
-    axis_sort_kernel<4096><<<(unsigned)nl, AS_THREADS, 0, ctx->stream>>>(
-        (const float4 *)ctx->pos4.p, (const int32_t *)ctx->leaf_begin.p, (const int32_t *)ctx->leaf_count.p, nl, n,
-        ax, 513, (uint16_t *)ctx->axis_order.p);
+    {
+      PROF(ctx, "axis_sort");
+      axis_sort_kernel<4096><<<(unsigned)nl, AS_THREADS, 0, ctx->stream>>>(
+          (const float4 *)ctx->pos4.p, (const int32_t *)ctx->leaf_begin.p, (const int32_t *)ctx->leaf_count.p, nl, n,
+          ax, 513, (uint16_t *)ctx->axis_order.p);
+    }
     HIP_TRY(ctx, hipGetLastError());
   }
   ctx->state = 2;

@@ -199,7 +199,10 @@ template <typename T>
 static sph_status permute_array(sph_ctx *ctx, T *arr, int64_t n) {
   if (!arr) return SPH_OK;
   const int32_t *perm = (const int32_t *)ctx->vals_a.p;
-  gather_kernel<T><<<grid_for(n), BT, 0, ctx->stream>>>(arr, (T *)ctx->gather_tmp.p, perm, n);
+  {
+    PROF(ctx, "permute");
+    gather_kernel<T><<<grid_for(n), BT, 0, ctx->stream>>>(arr, (T *)ctx->gather_tmp.p, perm, n);
+  }
   HIP_TRY(ctx, hipGetLastError());
   HIP_TRY(ctx, hipMemcpyAsync(arr, ctx->gather_tmp.p, sizeof(T) * n, hipMemcpyDeviceToDevice, ctx->stream));
   return SPH_OK;
@@ -222,9 +225,12 @@ sph_status build_cells_impl(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *
 
   const double scale = ldexp(1.0, D) / L;
   const int64_t kmax = ((int64_t)1 << D) - 1;
-  morton_kernel<<<grid_for(n), BT, 0, ctx->stream>>>(p->x, p->y, p->z, p->h, n, L, scale, kmax,
-                                                    (uint64_t *)ctx->keys_a.p, (int32_t *)ctx->vals_a.p,
-                                                    sc + SC_HMAX_BITS);
+  {
+    PROF(ctx, "morton_keys");
+    morton_kernel<<<grid_for(n), BT, 0, ctx->stream>>>(p->x, p->y, p->z, p->h, n, L, scale, kmax,
+                                                      (uint64_t *)ctx->keys_a.p, (int32_t *)ctx->vals_a.p,
+                                                      sc + SC_HMAX_BITS);
+  }
   HIP_TRY(ctx, hipGetLastError());
   SPH_TRY(radix_sort_pairs(ctx, n, 3 * D));
 
@@ -273,12 +279,21 @@ sph_status build_cells_impl(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *
   SPH_TRY(sph_ensure(ctx, ctx->nodes_b, 8 * n));
   SPH_TRY(sph_ensure(ctx, ctx->leaf_lvl_at, n));
   int32_t *flags = (int32_t *)ctx->flags.p, *sidx = (int32_t *)ctx->scan_out.p;
-  prefix_start_kernel<<<grid_for(n), BT, 0, ctx->stream>>>(keys, n, 3 * (D - k0), flags);
+  {
+    PROF(ctx, "leaf_build");
+    prefix_start_kernel<<<grid_for(n), BT, 0, ctx->stream>>>(keys, n, 3 * (D - k0), flags);
+  }
   HIP_TRY(ctx, hipGetLastError());
   SPH_TRY(scan_exclusive_i32(ctx, flags, sidx, n, sc + SC_NODES_A));
   int2 *na = (int2 *)ctx->nodes_a.p, *nb = (int2 *)ctx->nodes_b.p;
-  top_nodes_kernel<<<grid_for(n), BT, 0, ctx->stream>>>(flags, sidx, n, na);
-  node_ends_kernel<<<grid_for(n), BT, 0, ctx->stream>>>(na, sc + SC_NODES_A, n);
+  {
+    PROF(ctx, "leaf_build");
+    top_nodes_kernel<<<grid_for(n), BT, 0, ctx->stream>>>(flags, sidx, n, na);
+  }
+  {
+    PROF(ctx, "leaf_build");
+    node_ends_kernel<<<grid_for(n), BT, 0, ctx->stream>>>(na, sc + SC_NODES_A, n);
+  }
   HIP_TRY(ctx, hipGetLastError());
 
   // refine level by level; leaves are flagged at their first particle
@@ -286,9 +301,12 @@ sph_status build_cells_impl(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *
   int cin = SC_NODES_A, cout = SC_NODES_B;
   for (int lv = k0; lv <= D; ++lv) {
     HIP_TRY(ctx, hipMemsetAsync(sc + cout, 0, 4, ctx->stream));
-    split_level_kernel<<<grid_for(n), BT, 0, ctx->stream>>>(keys, na, sc + cin, nb, sc + cout, lv, D,
-                                                           ctx->prm.split_count, flags,
-                                                           (int8_t *)ctx->leaf_lvl_at.p);
+    {
+      PROF(ctx, "leaf_build");
+      split_level_kernel<<<grid_for(n), BT, 0, ctx->stream>>>(keys, na, sc + cin, nb, sc + cout, lv, D,
+                                                             ctx->prm.split_count, flags,
+                                                             (int8_t *)ctx->leaf_lvl_at.p);
+    }
     HIP_TRY(ctx, hipGetLastError());
     int2 *t = na; na = nb; nb = t;
     int tc = cin; cin = cout; cout = tc;
@@ -309,22 +327,34 @@ sph_status build_cells_impl(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *
   int32_t *lvl = (int32_t *)ctx->leaf_level.p, *lix = (int32_t *)ctx->leaf_ix.p, *liy = (int32_t *)ctx->leaf_iy.p,
           *liz = (int32_t *)ctx->leaf_iz.p, *lb = (int32_t *)ctx->leaf_begin.p, *lc = (int32_t *)ctx->leaf_count.p,
           *lof = (int32_t *)ctx->leaf_of.p;
-  leaf_table_kernel<<<grid_for(n), BT, 0, ctx->stream>>>(flags, sidx, (const int8_t *)ctx->leaf_lvl_at.p, keys, n, D,
-                                                        lvl, lix, liy, liz, lb, lof);
-  leaf_count_kernel<<<grid_for(nl), BT, 0, ctx->stream>>>(lb, lc, nl, n, sc + SC_MAXLEAF);
+  {
+    PROF(ctx, "leaf_build");
+    leaf_table_kernel<<<grid_for(n), BT, 0, ctx->stream>>>(flags, sidx, (const int8_t *)ctx->leaf_lvl_at.p, keys, n, D,
+                                                          lvl, lix, liy, liz, lb, lof);
+  }
+  {
+    PROF(ctx, "leaf_build");
+    leaf_count_kernel<<<grid_for(nl), BT, 0, ctx->stream>>>(lb, lc, nl, n, sc + SC_MAXLEAF);
+  }
   HIP_TRY(ctx, hipGetLastError());
   HIP_TRY(ctx, hipMemsetAsync(ctx->leaf_hmax.p, 0, 4 * (size_t)nl, ctx->stream));
-  offsets_kernel<<<grid_for(n), BT, 0, ctx->stream>>>(p->x, p->y, p->z, p->h, lof, lvl, lix, liy, liz, n, D,
-                                                     ldexp(L, -(D + 1)), (float4 *)ctx->pos4.p,
-                                                     (float *)ctx->leaf_hmax.p);
+  {
+    PROF(ctx, "offsets");
+    offsets_kernel<<<grid_for(n), BT, 0, ctx->stream>>>(p->x, p->y, p->z, p->h, lof, lvl, lix, liy, liz, n, D,
+                                                       ldexp(L, -(D + 1)), (float4 *)ctx->pos4.p,
+                                                       (float *)ctx->leaf_hmax.p);
+  }
   HIP_TRY(ctx, hipGetLastError());
   const int64_t ntop3 = (int64_t)1 << (3 * k0);
   SPH_TRY(sph_ensure(ctx, ctx->top_first, 4 * (size_t)ntop3));
   SPH_TRY(sph_ensure(ctx, ctx->top_last, 4 * (size_t)ntop3));
   HIP_TRY(ctx, hipMemsetAsync(ctx->top_first.p, 0, 4 * (size_t)ntop3, ctx->stream));
   HIP_TRY(ctx, hipMemsetAsync(ctx->top_last.p, 0, 4 * (size_t)ntop3, ctx->stream));
-  top_map_kernel<<<grid_for(nl), BT, 0, ctx->stream>>>(lvl, lix, liy, liz, nl, k0, (int32_t *)ctx->top_first.p,
-                                                      (int32_t *)ctx->top_last.p);
+  {
+    PROF(ctx, "leaf_build");
+    top_map_kernel<<<grid_for(nl), BT, 0, ctx->stream>>>(lvl, lix, liy, liz, nl, k0, (int32_t *)ctx->top_first.p,
+                                                        (int32_t *)ctx->top_last.p);
+  }
   HIP_TRY(ctx, hipGetLastError());
   SPH_TRY(pack_neighbour_data(ctx, p));
   ctx->state = 1;

@@ -98,7 +98,10 @@ sph_status kick_drift_impl(sph_ctx *ctx, sph_particles *p, int64_t ti, double t_
   g.ctz_ti = ti != 0 ? __builtin_ctzll((unsigned long long)ti) : 0;
   int64_t grid = ceil_div(g.n, 256);
   if (grid > 8192) grid = 8192;
-  kick_drift_kernel<<<(unsigned)grid, 256, 0, ctx->stream>>>(g);
+  {
+    PROF(ctx, "kick_drift");
+    kick_drift_kernel<<<(unsigned)grid, 256, 0, ctx->stream>>>(g);
+  }
   HIP_TRY(ctx, hipGetLastError());
   ctx->state = 0;
   return SPH_OK;

@@ -68,6 +68,7 @@ struct LoopArgs {
   float *ax_out, *ay_out, *az_out, *dA_out, *du_out, *vsig_out;
   int32_t *nngb_out;
   float half_alpha, gm1;
+  unsigned long long *ctr;  // cumulative force interactions
 };
 
 __device__ __forceinline__ void kernel_w_dw(float q, float &w, float &wp) {
@@ -352,6 +353,10 @@ __global__ __launch_bounds__(64) void loop_kernel(LoopArgs g) {
       if (g.nngb_out) g.nngb_out[i] = cnt;
     }
   }
+  if (MODE == 1) {
+    const int tot_cnt = wave_sum_i(live ? cnt : 0);
+    if (lane == 0) atomicAdd(g.ctr, (unsigned long long)tot_cnt);
+  }
 }
 
 struct GhostArgs {
@@ -374,12 +379,14 @@ struct GhostArgs {
   float *rho, *drho_dh, *f, *divv, *curlx, *curly, *curlz, *P, *c, *B, *A, *u;
   int32_t *nngb;
   int32_t *n_unconv, *rebuild;
+  unsigned long long *ctr;  // cumulative density interactions of finished solves
 };
 
 // Newton step on F(h) = h^3 sum_j W(r_ij, h) - eta^3 for each active particle
 // not yet converged; converged (or last-pass) particles get their ghost
 // quantities written.
 __global__ __launch_bounds__(256) void ghost_kernel(GhostArgs g) {
+  int finished = 0;
   for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < g.n_active; k += (int64_t)gridDim.x * 256) {
     if (g.conv[k]) continue;
     const int i = g.active_idx[k];
@@ -438,6 +445,7 @@ __global__ __launch_bounds__(256) void ghost_kernel(GhostArgs g) {
       g.B[i] = Bs;
       if (g.nngb) g.nngb[i] = g.act_cnt[k];
       g.jth[i] = make_float4(rho, fg * P / (rho * rho), cs, Bs);
+      finished += g.act_cnt[k];
       g.conv[k] = 1;
       if (!done) atomicAdd(g.n_unconv, 1);
     } else {
@@ -453,6 +461,8 @@ __global__ __launch_bounds__(256) void ghost_kernel(GhostArgs g) {
       if (Hn > g.box_quarter) atomicOr(g.rebuild, 2);
     }
   }
+  finished = wave_sum_i(finished);
+  if ((threadIdx.x & 63) == 0 && finished) atomicAdd(g.ctr, (unsigned long long)finished);
 }
 
 __global__ __launch_bounds__(256) void pack_jvm_kernel(const double *__restrict__ vx, const double *__restrict__ vy,
@@ -503,6 +513,7 @@ sph_status launch_loop(sph_ctx *ctx, const LoopArgs &a) {
   LoopArgs g = a;
   g.per_xcd = per;
   const int cap = ctx->prm.cand_cap, lcap = ctx->prm.list_cap;
+  PROF(ctx, MODE == 0 ? "density_loop" : "force_loop");
   if (cap <= 256 && lcap <= 64)
     loop_kernel<MODE, 256, 64, COMP><<<grid, 64, 0, ctx->stream>>>(g);
   else if (cap <= 512 && lcap <= 96)
@@ -547,14 +558,20 @@ sph_status pack_neighbour_data(sph_ctx *ctx, const sph_particles *p) {
   SPH_TRY(sph_ensure(ctx, ctx->jvm, 16 * (size_t)n));
   SPH_TRY(sph_ensure(ctx, ctx->jth, 16 * (size_t)n));
   if (p->vx && p->vy && p->vz && p->m) {
-    pack_jvm_kernel<<<grid256(n), 256, 0, ctx->stream>>>(p->vx, p->vy, p->vz, p->m, n, (float4 *)ctx->jvm.p);
+    {
+      PROF(ctx, "pack");
+      pack_jvm_kernel<<<grid256(n), 256, 0, ctx->stream>>>(p->vx, p->vy, p->vz, p->m, n, (float4 *)ctx->jvm.p);
+    }
     HIP_TRY(ctx, hipGetLastError());
   } else {
     HIP_TRY(ctx, hipMemsetAsync(ctx->jvm.p, 0, 16 * (size_t)n, ctx->stream));
   }
   if (p->rho && p->f_gradh && p->P && p->c && p->balsara) {
-    pack_jth_kernel<<<grid256(n), 256, 0, ctx->stream>>>(p->rho, p->f_gradh, p->P, p->c, p->balsara, n,
-                                                        (float4 *)ctx->jth.p);
+    {
+      PROF(ctx, "pack");
+      pack_jth_kernel<<<grid256(n), 256, 0, ctx->stream>>>(p->rho, p->f_gradh, p->P, p->c, p->balsara, n,
+                                                          (float4 *)ctx->jth.p);
+    }
     HIP_TRY(ctx, hipGetLastError());
   } else {
     HIP_TRY(ctx, hipMemsetAsync(ctx->jth.p, 0, 16 * (size_t)n, ctx->stream));
@@ -581,9 +598,12 @@ sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u)
   SPH_TRY(sph_ensure(ctx, ctx->hlo, 4 * (size_t)na));
   SPH_TRY(sph_ensure(ctx, ctx->hhi, 4 * (size_t)na));
   SPH_TRY(sph_ensure(ctx, ctx->conv, (size_t)na));
-  density_init_kernel<<<grid256(na > ctx->n_chunks ? na : ctx->n_chunks), 256, 0, ctx->stream>>>(
-      ctx->n_chunks, (int32_t *)ctx->chunk_todo.p, na, (float *)ctx->hlo.p, (float *)ctx->hhi.p,
-      (uint8_t *)ctx->conv.p);
+  {
+    PROF(ctx, "ghost");
+    density_init_kernel<<<grid256(na > ctx->n_chunks ? na : ctx->n_chunks), 256, 0, ctx->stream>>>(
+        ctx->n_chunks, (int32_t *)ctx->chunk_todo.p, na, (float *)ctx->hlo.p, (float *)ctx->hhi.p,
+        (uint8_t *)ctx->conv.p);
+  }
   HIP_TRY(ctx, hipGetLastError());
 
   int32_t *sc = (int32_t *)ctx->scalars.p;
@@ -639,7 +659,11 @@ sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u)
     gh.nngb = p->nngb_density;
     gh.n_unconv = sc + SC_UNCONV;
     gh.rebuild = sc + SC_REBUILD;
-    ghost_kernel<<<grid256(na), 256, 0, ctx->stream>>>(gh);
+    gh.ctr = (unsigned long long *)ctx->counters64.p;
+    {
+      PROF(ctx, "ghost");
+      ghost_kernel<<<grid256(na), 256, 0, ctx->stream>>>(gh);
+    }
     HIP_TRY(ctx, hipGetLastError());
     int32_t st[2];
     SPH_TRY(read_scalars(ctx, SC_UNCONV, 2, st));
@@ -687,6 +711,7 @@ sph_status force_pass_impl(sph_ctx *ctx, sph_particles *p) {
   a.du_out = p->du_dt;
   a.vsig_out = p->vsig;
   a.nngb_out = p->nngb_force;
+  a.ctr = (unsigned long long *)ctx->counters64.p + 1;
   if (ctx->prm.compensated)
     SPH_TRY((launch_loop<1, true>(ctx, a)));
   else

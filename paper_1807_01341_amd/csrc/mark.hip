@@ -246,11 +246,14 @@ sph_status build_pairs(sph_ctx *ctx, int which) {
     HIP_TRY(ctx, hipMemsetAsync(off.p, 0, 4, ctx->stream));
     return SPH_OK;
   }
-  pairs_kernel<false><<<waves_grid(na), MT, 0, ctx->stream>>>(
-      which, g, na, (const int32_t *)ctx->act_leaves.p, (const float *)ctx->act_hmax.p,
-      (const int32_t *)ctx->leaf_level.p, (const int32_t *)ctx->leaf_ix.p, (const int32_t *)ctx->leaf_iy.p,
-      (const int32_t *)ctx->leaf_iz.p, (const float *)ctx->leaf_hmax.p, (const int32_t *)ctx->top_first.p,
-      (const int32_t *)ctx->top_last.p, ctx->hmax_global, (int32_t *)ctx->pair_cnt.p, nullptr, nullptr);
+  {
+    PROF(ctx, "cell_pairs");
+    pairs_kernel<false><<<waves_grid(na), MT, 0, ctx->stream>>>(
+        which, g, na, (const int32_t *)ctx->act_leaves.p, (const float *)ctx->act_hmax.p,
+        (const int32_t *)ctx->leaf_level.p, (const int32_t *)ctx->leaf_ix.p, (const int32_t *)ctx->leaf_iy.p,
+        (const int32_t *)ctx->leaf_iz.p, (const float *)ctx->leaf_hmax.p, (const int32_t *)ctx->top_first.p,
+        (const int32_t *)ctx->top_last.p, ctx->hmax_global, (int32_t *)ctx->pair_cnt.p, nullptr, nullptr);
+  }
   HIP_TRY(ctx, hipGetLastError());
   int32_t *o = (int32_t *)off.p;
   SPH_TRY(scan_exclusive_i32(ctx, (const int32_t *)ctx->pair_cnt.p, o, na, o + na));
@@ -259,11 +262,14 @@ sph_status build_pairs(sph_ctx *ctx, int which) {
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   (void)sc;
   SPH_TRY(sph_ensure(ctx, lst, sizeof(PairEntry) * (size_t)(np > 0 ? np : 1)));
-  pairs_kernel<true><<<waves_grid(na), MT, 0, ctx->stream>>>(
-      which, g, na, (const int32_t *)ctx->act_leaves.p, (const float *)ctx->act_hmax.p,
-      (const int32_t *)ctx->leaf_level.p, (const int32_t *)ctx->leaf_ix.p, (const int32_t *)ctx->leaf_iy.p,
-      (const int32_t *)ctx->leaf_iz.p, (const float *)ctx->leaf_hmax.p, (const int32_t *)ctx->top_first.p,
-      (const int32_t *)ctx->top_last.p, ctx->hmax_global, nullptr, o, (PairEntry *)lst.p);
+  {
+    PROF(ctx, "cell_pairs");
+    pairs_kernel<true><<<waves_grid(na), MT, 0, ctx->stream>>>(
+        which, g, na, (const int32_t *)ctx->act_leaves.p, (const float *)ctx->act_hmax.p,
+        (const int32_t *)ctx->leaf_level.p, (const int32_t *)ctx->leaf_ix.p, (const int32_t *)ctx->leaf_iy.p,
+        (const int32_t *)ctx->leaf_iz.p, (const float *)ctx->leaf_hmax.p, (const int32_t *)ctx->top_first.p,
+        (const int32_t *)ctx->top_last.p, ctx->hmax_global, nullptr, o, (PairEntry *)lst.p);
+  }
   HIP_TRY(ctx, hipGetLastError());
   if (which == 0) ctx->n_dpairs = np; else ctx->n_fpairs = np;
   return SPH_OK;
@@ -279,10 +285,13 @@ sph_status refresh_leaf_hmax(sph_ctx *ctx) {
     memcpy(&hb, &hg, 4);
   }
   HIP_TRY(ctx, hipMemcpyAsync(sc + SC_HMAX_BITS, &hb, 4, hipMemcpyHostToDevice, ctx->stream));
-  leaf_hmax_refresh_kernel<<<waves_grid(na), MT, 0, ctx->stream>>>(
-      (const float4 *)ctx->pos4.p, (const uint8_t *)ctx->active.p, (const int32_t *)ctx->leaf_begin.p,
-      (const int32_t *)ctx->leaf_count.p, (const int32_t *)ctx->act_leaves.p, na, (float *)ctx->leaf_hmax.p,
-      (float *)ctx->act_hmax.p, sc + SC_HMAX_BITS);
+  {
+    PROF(ctx, "cell_pairs");
+    leaf_hmax_refresh_kernel<<<waves_grid(na), MT, 0, ctx->stream>>>(
+        (const float4 *)ctx->pos4.p, (const uint8_t *)ctx->active.p, (const int32_t *)ctx->leaf_begin.p,
+        (const int32_t *)ctx->leaf_count.p, (const int32_t *)ctx->act_leaves.p, na, (float *)ctx->leaf_hmax.p,
+        (float *)ctx->act_hmax.p, sc + SC_HMAX_BITS);
+  }
   HIP_TRY(ctx, hipGetLastError());
   SPH_TRY(read_scalars(ctx, SC_HMAX_BITS, 1, &hb));
   float hg;
@@ -305,11 +314,14 @@ sph_status mark_active_impl(sph_ctx *ctx, const sph_particles *p, int m, int64_t
   int32_t *aoff = (int32_t *)ctx->leaf_act_off.p, *aidx = aoff + nl, *coff = aoff + 2 * nl;
   float *hmax_act_leaf = (float *)ctx->act_leaf_chunk_off.p;
   int32_t *sc = (int32_t *)ctx->scalars.p;
-  mark_count_kernel<<<waves_grid(nl), MT, 0, ctx->stream>>>(p->time_bin, m, (const float4 *)ctx->pos4.p,
-                                                            (const int32_t *)ctx->leaf_begin.p,
-                                                            (const int32_t *)ctx->leaf_count.p, nl,
-                                                            (uint8_t *)ctx->active.p, nact, isact, nchunk,
-                                                            hmax_act_leaf);
+  {
+    PROF(ctx, "mark");
+    mark_count_kernel<<<waves_grid(nl), MT, 0, ctx->stream>>>(p->time_bin, m, (const float4 *)ctx->pos4.p,
+                                                              (const int32_t *)ctx->leaf_begin.p,
+                                                              (const int32_t *)ctx->leaf_count.p, nl,
+                                                              (uint8_t *)ctx->active.p, nact, isact, nchunk,
+                                                              hmax_act_leaf);
+  }
   HIP_TRY(ctx, hipGetLastError());
   SPH_TRY(scan_exclusive_i32(ctx, nact, aoff, nl, sc + SC_TOTAL0));
   SPH_TRY(scan_exclusive_i32(ctx, isact, aidx, nl, sc + SC_TOTAL1));
@@ -326,11 +338,14 @@ sph_status mark_active_impl(sph_ctx *ctx, const sph_particles *p, int m, int64_t
   SPH_TRY(sph_ensure(ctx, ctx->act_hmax, 4 * (size_t)nal));
   SPH_TRY(sph_ensure(ctx, ctx->chunks, sizeof(Chunk) * (size_t)nch));
   SPH_TRY(sph_ensure(ctx, ctx->chunk_todo, 4 * (size_t)nch));
-  mark_fill_kernel<<<waves_grid(nl), MT, 0, ctx->stream>>>(
-      (const uint8_t *)ctx->active.p, (const int32_t *)ctx->leaf_begin.p, (const int32_t *)ctx->leaf_count.p, nl,
-      nact, aoff, aidx, coff, hmax_act_leaf, (int32_t *)ctx->active_idx.p, (int32_t *)ctx->chunk_of.p,
-      (int32_t *)ctx->act_leaves.p, (float *)ctx->act_hmax.p, (int32_t *)ctx->leaf_actleaf.p,
-      (Chunk *)ctx->chunks.p);
+  {
+    PROF(ctx, "mark");
+    mark_fill_kernel<<<waves_grid(nl), MT, 0, ctx->stream>>>(
+        (const uint8_t *)ctx->active.p, (const int32_t *)ctx->leaf_begin.p, (const int32_t *)ctx->leaf_count.p, nl,
+        nact, aoff, aidx, coff, hmax_act_leaf, (int32_t *)ctx->active_idx.p, (int32_t *)ctx->chunk_of.p,
+        (int32_t *)ctx->act_leaves.p, (float *)ctx->act_hmax.p, (int32_t *)ctx->leaf_actleaf.p,
+        (Chunk *)ctx->chunks.p);
+  }
   HIP_TRY(ctx, hipGetLastError());
   SPH_TRY(build_pairs(ctx, 0));
   if (n_active_host) *n_active_host = ctx->n_active;

@@ -101,14 +101,23 @@ static sph_status scan_rec(sph_ctx *ctx, const int32_t *in, int32_t *out, int64_
                            int32_t *tmp) {
   const int64_t nb = ceil_div(n, SCAN_TILE);
   if (nb <= 1) {
-    scan_kernel<true><<<1, SCAN_THREADS, 0, ctx->stream>>>(in, out, n, nullptr, nullptr, total);
+    {
+      PROF(ctx, "scan");
+      scan_kernel<true><<<1, SCAN_THREADS, 0, ctx->stream>>>(in, out, n, nullptr, nullptr, total);
+    }
     return sph_hip_check(ctx, hipGetLastError(), "scan_kernel");
   }
   int32_t *bsum = tmp, *boff = tmp + nb;
-  scan_kernel<false><<<(unsigned)nb, SCAN_THREADS, 0, ctx->stream>>>(in, nullptr, n, bsum, nullptr, nullptr);
+  {
+    PROF(ctx, "scan");
+    scan_kernel<false><<<(unsigned)nb, SCAN_THREADS, 0, ctx->stream>>>(in, nullptr, n, bsum, nullptr, nullptr);
+  }
   HIP_TRY(ctx, hipGetLastError());
   SPH_TRY(scan_rec(ctx, bsum, boff, nb, nullptr, tmp + 2 * nb));
-  scan_kernel<true><<<(unsigned)nb, SCAN_THREADS, 0, ctx->stream>>>(in, out, n, nullptr, boff, total);
+  {
+    PROF(ctx, "scan");
+    scan_kernel<true><<<(unsigned)nb, SCAN_THREADS, 0, ctx->stream>>>(in, out, n, nullptr, boff, total);
+  }
   return sph_hip_check(ctx, hipGetLastError(), "scan_kernel");
 }
 
@@ -204,10 +213,16 @@ sph_status radix_sort_pairs(sph_ctx *ctx, int64_t n, int bits) {
   int32_t *va = (int32_t *)ctx->vals_a.p, *vb = (int32_t *)ctx->vals_b.p;
   int passes = 0;
   for (int shift = 0; shift < bits; shift += 8, ++passes) {
-    radix_hist_kernel<<<nblocks, RS_THREADS, 0, ctx->stream>>>(ka, n, shift, counts, nblocks);
+    {
+      PROF(ctx, "radix_hist");
+      radix_hist_kernel<<<nblocks, RS_THREADS, 0, ctx->stream>>>(ka, n, shift, counts, nblocks);
+    }
     HIP_TRY(ctx, hipGetLastError());
     SPH_TRY(scan_exclusive_i32(ctx, counts, offs, 256 * (int64_t)nblocks, nullptr));
-    radix_scatter_kernel<<<nblocks, RS_THREADS, 0, ctx->stream>>>(ka, va, kb, vb, n, shift, offs, nblocks);
+    {
+      PROF(ctx, "radix_scatter");
+      radix_scatter_kernel<<<nblocks, RS_THREADS, 0, ctx->stream>>>(ka, va, kb, vb, n, shift, offs, nblocks);
+    }
     HIP_TRY(ctx, hipGetLastError());
     uint64_t *tk = ka; ka = kb; kb = tk;
     int32_t *tv = va; va = vb; vb = tv;

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "sphgpu.h"
 
@@ -68,8 +69,35 @@ struct sph_ctx {
   DevBuf jvm;                             // float4 (vx, vy, vz, m)
   DevBuf jth;                             // float4 (rho, f P / rho^2, c, B)
   DevBuf sums, hlo, hhi, conv;
-  DevBuf host_counters;                   // pinned host mirror of scalars
+  DevBuf counters64;                      // cumulative interaction counts (2 x uint64)
+
+  // optional per-kernel timing with HIP events on ctx->stream
+  int prof = 0;
+  struct Pending {
+    const char *name;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> event_pool;
+  struct Acc {
+    std::string name;
+    long count;
+    double ms;
+  };
+  std::vector<Acc> acc;
 };
+
+// Records events around the enclosed launches when profiling is on.
+struct ProfScope {
+  sph_ctx *ctx;
+  sph_ctx::Pending ev;
+  bool on;
+  ProfScope(sph_ctx *c, const char *name);
+  ~ProfScope();
+};
+#define SPH_CAT2(a, b) a##b
+#define SPH_CAT(a, b) SPH_CAT2(a, b)
+#define PROF(ctx, name) ProfScope SPH_CAT(_prof_scope_, __LINE__)((ctx), (name))
 
 // ---------------------------------------------------------------- host helpers
 sph_status sph_fail(sph_ctx *ctx, sph_status code, const char *fmt, ...);
