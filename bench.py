@@ -5,7 +5,8 @@ force_pass -> kick_drift on the clustered workload (2,097,152 particles: 90 %
 uniform background, 10 % in 20 Plummer spheres, u log-uniform, 14 model
 time-bins), at the deep bin m whose active set {bin <= m} is closest to 1 %
 of the particles.  Steps run at integer times t with ctz(t) = m, so the active
-set keeps its size from step to step.
+set keeps its size from step to step; each step advances time by the step of
+bin m, 2^m t_min.
 
 Prints one JSON line: interactions/s (density + force, in-support pairs only,
 counted by the kernels) over the whole step, the fraction of FP32 vector peak,
@@ -103,6 +104,8 @@ def main():
     ap.add_argument("--cand-cap", type=int, default=None)
     ap.add_argument("--list-cap", type=int, default=None)
     ap.add_argument("--profile-steps", type=int, default=None)
+    ap.add_argument("--h-tol", type=float, default=None)
+    ap.add_argument("--nw", type=int, default=None)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the multi-GPU decomposition "
@@ -126,6 +129,10 @@ def main():
         kw["cand_cap"] = args.cand_cap
     if args.list_cap:
         kw["list_cap"] = args.list_cap
+    if args.h_tol:
+        kw["h_tol"] = args.h_tol
+    if args.nw:
+        kw["waves_per_chunk"] = args.nw
     ctx = sg.Context(**kw)
     p = sg.Particles.from_initial(ic)
 
@@ -144,7 +151,7 @@ def main():
         ctx.mark_active(p, m, want_count=False)
         ctx.density_pass(p, entropy_from_u=False)
         ctx.force_pass(p)
-        ctx.kick_drift(p, ti, t_min, 1 << (m + 1), False)
+        ctx.kick_drift(p, ti, t_min, 1 << m, False)
 
     for s in range(args.warmup):
         step(s)
@@ -171,6 +178,7 @@ def main():
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     prof = ctx.profile_read()
+    last = ctx.info()
     ctx.profile(False)
     inf2 = ctx.info()
     I_d2 = inf2["interactions_density"] - inf1["interactions_density"]
@@ -215,6 +223,8 @@ def main():
         "fp32_peak_frac_loops": (flops_step / (loop_ms / 1e3) / FP32_PEAK) if loop_ms > 0 else None,
         "loops_rate_interactions_per_s": ((I_d2 + I_f2) / ksteps) / (loop_ms / 1e3) if loop_ms > 0 else None,
         "profiled_ms_per_step": (t3 - t2) / ksteps * 1e3,
+        "last_step_newton": {"unconverged_after_pass": last["unconverged_after_pass"],
+                             "pair_rebuilds": last["pair_rebuilds"]},
         "kernels": kernels,
         "roofline": roof,
     }

@@ -66,6 +66,8 @@ typedef struct {
   int compensated;     /* 1: compensated FP32 sums in the loops (1) */
   int cand_cap;        /* loop tiling: candidate slots per wave (512) */
   int list_cap;        /* loop tiling: neighbour-list slots per lane (96) */
+  int waves_per_chunk; /* loop tiling: waves sharing one chunk's cell pairs, 1/2/4/8,
+                          0 = chosen from the number of active chunks (0) */
 } sph_params;
 
 /* The particle state.  Arrays marked (opt) may be NULL.  build_cells reorders
@@ -176,6 +178,9 @@ typedef struct {
   int64_t interactions_density; /* cumulative over the context's life: in-support
                                    pairs j != i of each finished density solve */
   int64_t interactions_force;   /* cumulative: pairs j != i of every force loop */
+  int32_t unconverged_after_pass[32]; /* last density pass: particles still unconverged
+                                         after each Newton pass (first 32 passes) */
+  int32_t pair_rebuilds;     /* last density pass: cell-pair lists widened mid-solve */
 } sph_info_t;
 sph_status sph_info(sph_ctx *ctx, sph_info_t *out); /* synchronises */
 

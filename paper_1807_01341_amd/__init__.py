@@ -33,7 +33,8 @@ class Params(C.Structure):
     _fields_ = [("box", C.c_double), ("gamma", C.c_double), ("cfl", C.c_double),
                 ("eta", C.c_float), ("alpha", C.c_float), ("balsara_eps", C.c_float), ("h_tol", C.c_float),
                 ("n_bins", C.c_int), ("split_count", C.c_int), ("morton_depth", C.c_int), ("top_cap", C.c_int),
-                ("h_max_iter", C.c_int), ("compensated", C.c_int), ("cand_cap", C.c_int), ("list_cap", C.c_int)]
+                ("h_max_iter", C.c_int), ("compensated", C.c_int), ("cand_cap", C.c_int), ("list_cap", C.c_int),
+                ("waves_per_chunk", C.c_int)]
 
 
 # field name, dtype, role
@@ -60,7 +61,8 @@ class Info(C.Structure):
     _fields_ = [("n", C.c_int64), ("n_leaves", C.c_int64), ("top_level", C.c_int32),
                 ("n_active", C.c_int64), ("n_active_leaves", C.c_int64), ("n_density_pairs", C.c_int64),
                 ("n_force_pairs", C.c_int64), ("density_iterations", C.c_int32), ("n_unconverged", C.c_int64),
-                ("interactions_density", C.c_int64), ("interactions_force", C.c_int64)]
+                ("interactions_density", C.c_int64), ("interactions_force", C.c_int64),
+                ("unconverged_after_pass", C.c_int32 * 32), ("pair_rebuilds", C.c_int32)]
 
 
 _lib = None
@@ -239,7 +241,9 @@ class Context:
     def info(self) -> dict:
         inf = Info()
         self._check(lib().sph_info(self.h, C.byref(inf)))
-        return {k: getattr(inf, k) for k, _ in Info._fields_}
+        out = {k: getattr(inf, k) for k, _ in Info._fields_}
+        out["unconverged_after_pass"] = list(out["unconverged_after_pass"])[:max(0, out["density_iterations"])]
+        return out
 
     def profile(self, enable: bool):
         return self._check(lib().sph_profile(self.h, int(bool(enable))))

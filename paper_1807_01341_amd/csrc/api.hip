@@ -222,6 +222,8 @@ sph_status sph_info(sph_ctx *ctx, sph_info_t *out) {
   HIP_TRY(ctx, hipMemcpy(c, ctx->counters64.p, sizeof c, hipMemcpyDeviceToHost));
   out->interactions_density = (int64_t)c[0];
   out->interactions_force = (int64_t)c[1];
+  for (int q = 0; q < 32; ++q) out->unconverged_after_pass[q] = ctx->unconv_hist[q];
+  out->pair_rebuilds = ctx->pair_rebuilds;
   return SPH_OK;
 }
 

@@ -32,6 +32,8 @@ static AxisSet make_axes() {
   return a;
 }
 
+// Workgroup LDS bitonic sort for leaves of 513..4096 particles (only at the
+// maximum depth, where coincident particles cannot be split further).
 template <int P>
 __global__ __launch_bounds__(AS_THREADS) void axis_sort_kernel(const float4 *__restrict__ pos4,
                                                                const int32_t *__restrict__ leaf_begin,
@@ -91,6 +93,112 @@ __global__ __launch_bounds__(AS_THREADS) void axis_sort_kernel(const float4 *__r
   }
 }
 
+// (key, index) as one orderable 64-bit word: ascending float order (-0 taken
+// as +0, so that equal keys tie) then ascending in-leaf index.
+__device__ __forceinline__ uint64_t sort_word(float key, int idx) {
+  uint32_t u = __float_as_uint(key + 0.0f);
+  u ^= (u >> 31) ? 0xffffffffu : 0x80000000u;
+  return ((uint64_t)u << 32) | (uint32_t)idx;
+}
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+  const uint32_t lo = __shfl_xor((unsigned)(v & 0xffffffffu), m, 64);
+  const uint32_t hi = __shfl_xor((unsigned)(v >> 32), m, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Bitonic sort of 64*E words held E per lane (element e = lane*E + r),
+// entirely in registers: partners within a lane are swapped in place, across
+// lanes exchanged with shuffles.
+template <int E>
+__device__ __forceinline__ void wave_bitonic(uint64_t (&w)[E], int lane) {
+  constexpr int P = 64 * E;
+#pragma unroll
+  for (int k = 2; k <= P; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      if (j < E) {
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+          if ((r & j) == 0) {
+            const int i = lane * E + r;
+            const bool up = (i & k) == 0;
+            const uint64_t a = w[r], b = w[r | j];
+            const bool sw = (a > b) == up;
+            w[r] = sw ? b : a;
+            w[r | j] = sw ? a : b;
+          }
+        }
+      } else {
+        const int lm = j / E;
+        const bool lower = (lane & lm) == 0;
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+          const int i = lane * E + r;
+          const bool up = (i & k) == 0;
+          const uint64_t o = shfl_xor_u64(w[r], lm);
+          const bool keep_min = (lower == up);
+          const uint64_t mn = w[r] < o ? w[r] : o;
+          const uint64_t mx = w[r] < o ? o : w[r];
+          w[r] = keep_min ? mn : mx;
+        }
+      }
+    }
+  }
+}
+
+template <int E>
+__device__ __forceinline__ void sort_leaf_axes(const float4 *__restrict__ pos4, int b, int cnt, int64_t n,
+                                               const AxisSet &ax, uint16_t *__restrict__ order, int lane) {
+  float ox[E], oy[E], oz[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int e = lane * E + r;
+    if (e < cnt) {
+      const float4 q = pos4[b + e];
+      ox[r] = q.x;
+      oy[r] = q.y;
+      oz[r] = q.z;
+    } else {
+      ox[r] = oy[r] = oz[r] = 0.f;
+    }
+  }
+  for (int a = 0; a < 13; ++a) {
+    const float ex = ax.e[a][0], ey = ax.e[a][1], ez = ax.e[a][2];
+    uint64_t w[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int e = lane * E + r;
+      w[r] = e < cnt ? sort_word(fmaf(oz[r], ez, fmaf(oy[r], ey, ox[r] * ex)), e) : ~0ull;
+    }
+    wave_bitonic<E>(w, lane);
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int e = lane * E + r;
+      if (e < cnt) order[(int64_t)a * n + b + e] = (uint16_t)(w[r] & 0xffffu);
+    }
+  }
+}
+
+// One wave per leaf of at most 512 particles.
+__global__ __launch_bounds__(256) void axis_sort_wave_kernel(const float4 *__restrict__ pos4,
+                                                             const int32_t *__restrict__ leaf_begin,
+                                                             const int32_t *__restrict__ leaf_count, int64_t nl,
+                                                             int64_t n, AxisSet ax, uint16_t *__restrict__ order) {
+  const int64_t l = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (l >= nl) return;
+  const int lane = threadIdx.x & 63;
+  const int cnt = leaf_count[l], b = leaf_begin[l];
+  if (cnt <= 64)
+    sort_leaf_axes<1>(pos4, b, cnt, n, ax, order, lane);
+  else if (cnt <= 128)
+    sort_leaf_axes<2>(pos4, b, cnt, n, ax, order, lane);
+  else if (cnt <= 256)
+    sort_leaf_axes<4>(pos4, b, cnt, n, ax, order, lane);
+  else if (cnt <= 512)
+    sort_leaf_axes<8>(pos4, b, cnt, n, ax, order, lane);
+}
+
 sph_status sort_cells_impl(sph_ctx *ctx) {
   const int64_t n = ctx->n, nl = ctx->n_leaves;
   SPH_TRY(sph_ensure(ctx, ctx->axis_order, sizeof(uint16_t) * 13 * (size_t)n));
@@ -101,18 +209,16 @@ sph_status sort_cells_impl(sph_ctx *ctx) {
   const AxisSet ax = make_axes();
   {
     PROF(ctx, "axis_sort");
-    axis_sort_kernel<512><<<(unsigned)nl, AS_THREADS, 0, ctx->stream>>>(
-        (const float4 *)ctx->pos4.p, (const int32_t *)ctx->leaf_begin.p, (const int32_t *)ctx->leaf_count.p, nl, n, ax,
-        0, (uint16_t *)ctx->axis_order.p);
+    axis_sort_wave_kernel<<<(unsigned)ceil_div(nl, 4), 256, 0, ctx->stream>>>(
+        (const float4 *)ctx->pos4.p, (const int32_t *)ctx->leaf_begin.p, (const int32_t *)ctx->leaf_count.p, nl, n,
+        ax, (uint16_t *)ctx->axis_order.p);
   }
   HIP_TRY(ctx, hipGetLastError());
   if (maxc > 512) {
-    {
-      PROF(ctx, "axis_sort");
-      axis_sort_kernel<4096><<<(unsigned)nl, AS_THREADS, 0, ctx->stream>>>(
-          (const float4 *)ctx->pos4.p, (const int32_t *)ctx->leaf_begin.p, (const int32_t *)ctx->leaf_count.p, nl, n,
-          ax, 513, (uint16_t *)ctx->axis_order.p);
-    }
+    PROF(ctx, "axis_sort");
+    axis_sort_kernel<4096><<<(unsigned)nl, AS_THREADS, 0, ctx->stream>>>(
+        (const float4 *)ctx->pos4.p, (const int32_t *)ctx->leaf_begin.p, (const int32_t *)ctx->leaf_count.p, nl, n,
+        ax, 513, (uint16_t *)ctx->axis_order.p);
     HIP_TRY(ctx, hipGetLastError());
   }
   ctx->state = 2;

@@ -31,7 +31,7 @@ __device__ __forceinline__ uint64_t coord_of(double xw, double scale, int64_t km
 __global__ __launch_bounds__(BT) void morton_kernel(double *__restrict__ x, double *__restrict__ y,
                                                     double *__restrict__ z, const float *__restrict__ h, int64_t n,
                                                     double L, double scale, int64_t kmax, uint64_t *__restrict__ keys,
-                                                    int32_t *__restrict__ vals, int *__restrict__ hmax_bits) {
+                                                    int32_t *__restrict__ vals, float *__restrict__ hmax_part) {
   float hm = 0.f;
   for (int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x; i < n; i += (int64_t)gridDim.x * BT) {
     const double xw = wrap_box(x[i], L), yw = wrap_box(y[i], L), zw = wrap_box(z[i], L);
@@ -43,14 +43,75 @@ __global__ __launch_bounds__(BT) void morton_kernel(double *__restrict__ x, doub
     vals[i] = (int32_t)i;
     hm = fmaxf(hm, GK32 * h[i]);
   }
+  // block maximum to a per-block slot (no contended atomics)
+  __shared__ float wmax[BT / 64];
   hm = wave_max_f(hm);
-  if ((threadIdx.x & 63) == 0) atomicMax(hmax_bits, __float_as_int(hm));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = hm;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float b = wmax[0];
+    for (int w = 1; w < BT / 64; ++w) b = fmaxf(b, wmax[w]);
+    hmax_part[blockIdx.x] = b;
+  }
 }
 
-template <typename T>
-__global__ __launch_bounds__(BT) void gather_kernel(const T *__restrict__ src, T *__restrict__ dst,
-                                                    const int32_t *__restrict__ perm, int64_t n) {
-  for (int64_t s = (int64_t)blockIdx.x * BT + threadIdx.x; s < n; s += (int64_t)gridDim.x * BT) dst[s] = src[perm[s]];
+__global__ __launch_bounds__(BT) void max_reduce_kernel(const float *__restrict__ part, int n, int *__restrict__ out_bits) {
+  float m = 0.f;
+  for (int k = threadIdx.x; k < n; k += BT) m = fmaxf(m, part[k]);
+  __shared__ float wmax[BT / 64];
+  m = wave_max_f(m);
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float b = wmax[0];
+    for (int w = 1; w < BT / 64; ++w) b = fmaxf(b, wmax[w]);
+    *out_bits = __float_as_int(b);
+  }
+}
+
+// All particle arrays are reordered by two launches: gather into one staging
+// buffer, then copy back into the caller's arrays.
+struct PermArray {
+  void *ptr;
+  int64_t size;  // bytes per element: 8, 4 or 1
+};
+struct PermSet {
+  PermArray a[40];
+  int count;
+};
+
+__global__ __launch_bounds__(BT) void multi_gather_kernel(PermSet set, const int32_t *__restrict__ perm, int64_t n,
+                                                          char *__restrict__ tmp) {
+  for (int64_t s = (int64_t)blockIdx.x * BT + threadIdx.x; s < n; s += (int64_t)gridDim.x * BT) {
+    const int64_t p = perm[s];
+    int64_t off = 0;
+    for (int k = 0; k < set.count; ++k) {
+      const int64_t sz = set.a[k].size;
+      if (sz == 8)
+        reinterpret_cast<uint64_t *>(tmp + off)[s] = reinterpret_cast<const uint64_t *>(set.a[k].ptr)[p];
+      else if (sz == 4)
+        reinterpret_cast<uint32_t *>(tmp + off)[s] = reinterpret_cast<const uint32_t *>(set.a[k].ptr)[p];
+      else
+        reinterpret_cast<uint8_t *>(tmp + off)[s] = reinterpret_cast<const uint8_t *>(set.a[k].ptr)[p];
+      off += sz * n;
+    }
+  }
+}
+
+__global__ __launch_bounds__(BT) void multi_copyback_kernel(PermSet set, int64_t n, const char *__restrict__ tmp) {
+  for (int64_t s = (int64_t)blockIdx.x * BT + threadIdx.x; s < n; s += (int64_t)gridDim.x * BT) {
+    int64_t off = 0;
+    for (int k = 0; k < set.count; ++k) {
+      const int64_t sz = set.a[k].size;
+      if (sz == 8)
+        reinterpret_cast<uint64_t *>(set.a[k].ptr)[s] = reinterpret_cast<const uint64_t *>(tmp + off)[s];
+      else if (sz == 4)
+        reinterpret_cast<uint32_t *>(set.a[k].ptr)[s] = reinterpret_cast<const uint32_t *>(tmp + off)[s];
+      else
+        reinterpret_cast<uint8_t *>(set.a[k].ptr)[s] = reinterpret_cast<const uint8_t *>(tmp + off)[s];
+      off += sz * n;
+    }
+  }
 }
 
 __global__ __launch_bounds__(BT) void perm_out_kernel(const int32_t *__restrict__ perm, int64_t *__restrict__ out,
@@ -151,24 +212,32 @@ __global__ __launch_bounds__(BT) void leaf_count_kernel(const int32_t *__restric
   if ((threadIdx.x & 63) == 0) atomicMax(max_count, mc);
 }
 
-// FP32 offsets from the leaf centre, H, and the leaf's max H.
+// FP32 offsets from the leaf centre, H, and the leaf's max H: one wave per
+// leaf.
 __global__ __launch_bounds__(BT) void offsets_kernel(const double *__restrict__ x, const double *__restrict__ y,
                                                      const double *__restrict__ z, const float *__restrict__ h,
-                                                     const int32_t *__restrict__ leaf_of,
+                                                     const int32_t *__restrict__ begin, const int32_t *__restrict__ count,
                                                      const int32_t *__restrict__ level, const int32_t *__restrict__ ix,
                                                      const int32_t *__restrict__ iy, const int32_t *__restrict__ iz,
-                                                     int64_t n, int D, double unit, float4 *__restrict__ pos4,
+                                                     int64_t nl, int D, double unit, float4 *__restrict__ pos4,
                                                      float *__restrict__ leaf_hmax) {
-  for (int64_t s = (int64_t)blockIdx.x * BT + threadIdx.x; s < n; s += (int64_t)gridDim.x * BT) {
-    const int l = leaf_of[s];
-    const int sh = D - level[l];
-    const double cx = (double)((2 * (int64_t)ix[l] + 1) << sh) * unit;
-    const double cy = (double)((2 * (int64_t)iy[l] + 1) << sh) * unit;
-    const double cz = (double)((2 * (int64_t)iz[l] + 1) << sh) * unit;
+  const int64_t l = (int64_t)blockIdx.x * (BT / 64) + (threadIdx.x >> 6);
+  if (l >= nl) return;
+  const int lane = threadIdx.x & 63;
+  const int sh = D - level[l];
+  const double cx = (double)((2 * (int64_t)ix[l] + 1) << sh) * unit;
+  const double cy = (double)((2 * (int64_t)iy[l] + 1) << sh) * unit;
+  const double cz = (double)((2 * (int64_t)iz[l] + 1) << sh) * unit;
+  const int b = begin[l], c = count[l];
+  float hm = 0.f;
+  for (int k = lane; k < c; k += 64) {
+    const int s = b + k;
     const float H = GK32 * h[s];
     pos4[s] = make_float4((float)(x[s] - cx), (float)(y[s] - cy), (float)(z[s] - cz), H);
-    atomic_max_pos_f(&leaf_hmax[l], H);
+    hm = fmaxf(hm, H);
   }
+  hm = wave_max_f(hm);
+  if (lane == 0) leaf_hmax[l] = hm;
 }
 
 // Leaf range of every top-level cell (leaves of one top cell are contiguous).
@@ -195,17 +264,11 @@ static unsigned grid_for(int64_t n) {
   return (unsigned)g;
 }
 
-template <typename T>
-static sph_status permute_array(sph_ctx *ctx, T *arr, int64_t n) {
-  if (!arr) return SPH_OK;
-  const int32_t *perm = (const int32_t *)ctx->vals_a.p;
-  {
-    PROF(ctx, "permute");
-    gather_kernel<T><<<grid_for(n), BT, 0, ctx->stream>>>(arr, (T *)ctx->gather_tmp.p, perm, n);
-  }
-  HIP_TRY(ctx, hipGetLastError());
-  HIP_TRY(ctx, hipMemcpyAsync(arr, ctx->gather_tmp.p, sizeof(T) * n, hipMemcpyDeviceToDevice, ctx->stream));
-  return SPH_OK;
+static void add_perm(PermSet &set, void *p, int64_t size) {
+  if (!p) return;
+  set.a[set.count].ptr = p;
+  set.a[set.count].size = size;
+  ++set.count;
 }
 
 sph_status build_cells_impl(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *perm_out) {
@@ -219,42 +282,44 @@ sph_status build_cells_impl(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *
   SPH_TRY(sph_ensure(ctx, ctx->keys_b, 8 * n));
   SPH_TRY(sph_ensure(ctx, ctx->vals_a, 4 * n));
   SPH_TRY(sph_ensure(ctx, ctx->vals_b, 4 * n));
-  SPH_TRY(sph_ensure(ctx, ctx->gather_tmp, 8 * n));
   int32_t *sc = (int32_t *)ctx->scalars.p;
   HIP_TRY(ctx, hipMemsetAsync(sc, 0, sizeof(int32_t) * SC_COUNT, ctx->stream));
 
   const double scale = ldexp(1.0, D) / L;
   const int64_t kmax = ((int64_t)1 << D) - 1;
+  const unsigned mgrid = grid_for(n);
+  SPH_TRY(sph_ensure(ctx, ctx->scan_out, 4 * n));
   {
     PROF(ctx, "morton_keys");
-    morton_kernel<<<grid_for(n), BT, 0, ctx->stream>>>(p->x, p->y, p->z, p->h, n, L, scale, kmax,
-                                                      (uint64_t *)ctx->keys_a.p, (int32_t *)ctx->vals_a.p,
-                                                      sc + SC_HMAX_BITS);
+    morton_kernel<<<mgrid, BT, 0, ctx->stream>>>(p->x, p->y, p->z, p->h, n, L, scale, kmax,
+                                                (uint64_t *)ctx->keys_a.p, (int32_t *)ctx->vals_a.p,
+                                                (float *)ctx->scan_out.p);
+    max_reduce_kernel<<<1, BT, 0, ctx->stream>>>((const float *)ctx->scan_out.p, (int)mgrid, sc + SC_HMAX_BITS);
   }
   HIP_TRY(ctx, hipGetLastError());
   SPH_TRY(radix_sort_pairs(ctx, n, 3 * D));
 
   // reorder every particle array into key order
-  SPH_TRY(permute_array(ctx, p->x, n));
-  SPH_TRY(permute_array(ctx, p->y, n));
-  SPH_TRY(permute_array(ctx, p->z, n));
-  SPH_TRY(permute_array(ctx, p->vx, n));
-  SPH_TRY(permute_array(ctx, p->vy, n));
-  SPH_TRY(permute_array(ctx, p->vz, n));
-  SPH_TRY(permute_array(ctx, p->vfx, n));
-  SPH_TRY(permute_array(ctx, p->vfy, n));
-  SPH_TRY(permute_array(ctx, p->vfz, n));
-  SPH_TRY(permute_array(ctx, p->m, n));
-  SPH_TRY(permute_array(ctx, p->u, n));
-  SPH_TRY(permute_array(ctx, p->A, n));
-  SPH_TRY(permute_array(ctx, p->Af, n));
-  SPH_TRY(permute_array(ctx, p->h, n));
-  SPH_TRY(permute_array(ctx, p->time_bin, n));
-  float *fo[] = {p->rho, p->drho_dh, p->f_gradh, p->divv, p->curlx, p->curly, p->curlz, p->P, p->c, p->balsara,
-                 p->ax, p->ay, p->az, p->dA_dt, p->du_dt, p->vsig};
-  for (float *a : fo) SPH_TRY(permute_array(ctx, a, n));
-  SPH_TRY(permute_array(ctx, p->nngb_density, n));
-  SPH_TRY(permute_array(ctx, p->nngb_force, n));
+  {
+    PermSet set;
+    set.count = 0;
+    double *d8[] = {p->x, p->y, p->z, p->vx, p->vy, p->vz, p->vfx, p->vfy, p->vfz};
+    for (double *a : d8) add_perm(set, a, 8);
+    float *f4[] = {p->m, p->u, p->A, p->Af, p->h, p->rho, p->drho_dh, p->f_gradh, p->divv, p->curlx, p->curly,
+                   p->curlz, p->P, p->c, p->balsara, p->ax, p->ay, p->az, p->dA_dt, p->du_dt, p->vsig};
+    for (float *a : f4) add_perm(set, a, 4);
+    add_perm(set, p->nngb_density, 4);
+    add_perm(set, p->nngb_force, 4);
+    add_perm(set, p->time_bin, 1);
+    int64_t bytes = 0;
+    for (int k = 0; k < set.count; ++k) bytes += set.a[k].size * n;
+    SPH_TRY(sph_ensure(ctx, ctx->gather_tmp, (size_t)bytes));
+    PROF(ctx, "permute");
+    multi_gather_kernel<<<grid_for(n), BT, 0, ctx->stream>>>(set, (const int32_t *)ctx->vals_a.p, n,
+                                                           (char *)ctx->gather_tmp.p);
+    multi_copyback_kernel<<<grid_for(n), BT, 0, ctx->stream>>>(set, n, (const char *)ctx->gather_tmp.p);
+    HIP_TRY(ctx, hipGetLastError());
+  }
   if (perm_out) {
     perm_out_kernel<<<grid_for(n), BT, 0, ctx->stream>>>((const int32_t *)ctx->vals_a.p, perm_out, n);
     HIP_TRY(ctx, hipGetLastError());
@@ -303,7 +368,7 @@ sph_status build_cells_impl(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *
     HIP_TRY(ctx, hipMemsetAsync(sc + cout, 0, 4, ctx->stream));
     {
       PROF(ctx, "leaf_build");
-      split_level_kernel<<<grid_for(n), BT, 0, ctx->stream>>>(keys, na, sc + cin, nb, sc + cout, lv, D,
+      split_level_kernel<<<grid_for(n / 16 + 1), BT, 0, ctx->stream>>>(keys, na, sc + cin, nb, sc + cout, lv, D,
                                                              ctx->prm.split_count, flags,
                                                              (int8_t *)ctx->leaf_lvl_at.p);
     }
@@ -337,12 +402,11 @@ sph_status build_cells_impl(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *
     leaf_count_kernel<<<grid_for(nl), BT, 0, ctx->stream>>>(lb, lc, nl, n, sc + SC_MAXLEAF);
   }
   HIP_TRY(ctx, hipGetLastError());
-  HIP_TRY(ctx, hipMemsetAsync(ctx->leaf_hmax.p, 0, 4 * (size_t)nl, ctx->stream));
   {
     PROF(ctx, "offsets");
-    offsets_kernel<<<grid_for(n), BT, 0, ctx->stream>>>(p->x, p->y, p->z, p->h, lof, lvl, lix, liy, liz, n, D,
-                                                       ldexp(L, -(D + 1)), (float4 *)ctx->pos4.p,
-                                                       (float *)ctx->leaf_hmax.p);
+    offsets_kernel<<<(unsigned)ceil_div(nl, BT / 64), BT, 0, ctx->stream>>>(
+        p->x, p->y, p->z, p->h, lb, lc, lvl, lix, liy, liz, nl, D, ldexp(L, -(D + 1)), (float4 *)ctx->pos4.p,
+        (float *)ctx->leaf_hmax.p);
   }
   HIP_TRY(ctx, hipGetLastError());
   const int64_t ntop3 = (int64_t)1 << (3 * k0);

@@ -7,8 +7,8 @@
 struct KickArgs {
   int64_t n;
   double *x, *y, *z, *vx, *vy, *vz, *vfx, *vfy, *vfz;
-  float *A, *Af;
-  const float *ax, *ay, *az, *dA, *h, *vsig;
+  float *A, *Af, *h;
+  const float *ax, *ay, *az, *dA, *vsig, *divv;
   int8_t *bin;
   const uint8_t *active;
   int64_t ti, drift_int;
@@ -70,6 +70,13 @@ __global__ __launch_bounds__(256) void kick_drift_kernel(KickArgs g) {
     g.vy[s] = v1 + a1 * dt;
     g.vz[s] = v2 + a2 * dt;
     g.A[s] = (float)(A + da * dt);
+    // smoothing length predicted along the flow, dh/dt = -(h/3) div v (a
+    // starting point for the next solve), at most a factor e^0.2 per drift
+    if (g.divv) {
+      double x = -(double)g.divv[s] * dt / 3.0;
+      x = fmin(fmax(x, -0.2), 0.2);
+      g.h[s] = (float)((double)g.h[s] * exp(x));
+    }
   }
 }
 
@@ -86,6 +93,7 @@ sph_status kick_drift_impl(sph_ctx *ctx, sph_particles *p, int64_t ti, double t_
   g.vfx = p->vfx; g.vfy = p->vfy; g.vfz = p->vfz;
   g.A = p->A; g.Af = p->Af;
   g.ax = p->ax; g.ay = p->ay; g.az = p->az; g.dA = p->dA_dt; g.h = p->h; g.vsig = p->vsig;
+  g.divv = p->divv;
   g.bin = p->time_bin;
   g.active = (const uint8_t *)ctx->active.p;
   g.ti = ti;

@@ -122,18 +122,31 @@ __device__ __forceinline__ int chunk_id(int64_t per_xcd, int64_t n_chunks) {
   return cid < n_chunks ? (int)cid : -1;
 }
 
-// MODE 0: density loop; MODE 1: force loop.
-template <int MODE, int CAP, int LCAP, bool COMP>
-__global__ __launch_bounds__(64) void loop_kernel(LoopArgs g) {
-  __shared__ float4 cand[CAP];
-  __shared__ float candH[MODE == 1 ? CAP : 1];
-  __shared__ uint16_t lists[LCAP * 64];
+// Orders this wave's LDS accesses across its lanes (each wave owns its own
+// LDS region, so no workgroup barrier is needed between its phases).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// MODE 0: density loop; MODE 1: force loop.  NW waves share one chunk: wave w
+// takes the partner cells w, w+NW, ... of the chunk's pair list, and the
+// per-lane partial sums are combined across waves in wave order at the end.
+template <int MODE, int CAP, int LCAP, bool COMP, int NW>
+__global__ __launch_bounds__(64 * NW) void loop_kernel(LoopArgs g) {
+  __shared__ float4 cand_all[NW][CAP];
+  __shared__ float candH_all[NW][MODE == 1 ? CAP : 1];
+  __shared__ uint16_t lists_all[NW][LCAP * 64];
 
   const int cid = chunk_id(g.per_xcd, g.n_chunks);
   if (cid < 0) return;
   if (!g.chunk_todo[cid]) return;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  float4 *cand = cand_all[wave];
+  float *candH = candH_all[wave];
+  uint16_t *lists = lists_all[wave];
   const Chunk ch = g.chunks[cid];
-  const int lane = threadIdx.x;
   const bool live = lane < ch.count;
   const int k = ch.begin + lane;
   const int i = live ? g.active_idx[k] : -1;
@@ -151,7 +164,6 @@ __global__ __launch_bounds__(64) void loop_kernel(LoopArgs g) {
   const float bminz = wave_min_f(live ? pi.z : INFINITY), bmaxz = wave_max_f(live ? pi.z : -INFINITY);
   const float Rc = wave_max_f(live ? Hi : 0.f);
   const float R2c = Rc * Rc;
-  if (lane == 0) g.chunk_todo[cid] = 0;
 
   // accumulators: density (w, m w, 3w+qw', m(3w+qw'), div, curl x3); force (a x3, visc, adiab)
   float acc[9];
@@ -237,7 +249,7 @@ __global__ __launch_bounds__(64) void loop_kernel(LoopArgs g) {
   };
 
   auto flush = [&]() {
-    __syncthreads();
+    wave_sync();
     for (int b0 = 0; b0 < ncand; b0 += 64) {
       if (wave_max_i(len) > LCAP - 64) interact();
       const int bend = min(ncand, b0 + 64);
@@ -260,11 +272,11 @@ __global__ __launch_bounds__(64) void loop_kernel(LoopArgs g) {
     }
     interact();
     ncand = 0;
-    __syncthreads();
+    wave_sync();
   };
 
   const int pbeg = g.pair_off[ch.act_leaf], pend = g.pair_off[ch.act_leaf + 1];
-  for (int pp = pbeg; pp < pend; ++pp) {
+  for (int pp = pbeg + wave; pp < pend; pp += NW) {
     const PairEntry e = g.pairs[pp];
     const int B = e.b;
     const int bb = g.leaf_begin[B], bc = g.leaf_count[B];
@@ -325,31 +337,76 @@ __global__ __launch_bounds__(64) void loop_kernel(LoopArgs g) {
   }
   flush();
 
+  // per-lane results of this wave
+  float res[9];
+  if (MODE == 0) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) res[q] = tot[q].value();
+    res[8] = 0.f;
+  } else {
+    if (COMP) {
+      res[0] = ka[0].s - ka[0].c + tot[0].value();
+      res[1] = ka[1].s - ka[1].c + tot[1].value();
+      res[2] = ka[2].s - ka[2].c + tot[2].value();
+    } else {
+      res[0] = tot[0].value();
+      res[1] = tot[1].value();
+      res[2] = tot[2].value();
+    }
+    res[3] = tot[3].value();
+    res[4] = tot[4].value();
+    res[5] = vmax;
+    res[6] = res[7] = res[8] = 0.f;
+  }
+  if (NW > 1) {
+    // combine the waves' partial sums in wave order through LDS
+    constexpr int NQ = 10;
+    static_assert(CAP * 4 >= NQ * 64, "reduction buffer");
+    __syncthreads();
+    float *red = reinterpret_cast<float *>(cand_all[wave]);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) red[q * 64 + lane] = res[q];
+    red[9 * 64 + lane] = __int_as_float(cnt);
+    __syncthreads();
+    if (wave != 0) return;
+    Neu sum[9];
+    int csum = 0;
+    float vm = 0.f;
+    for (int w = 0; w < NW; ++w) {
+      const float *rw = reinterpret_cast<const float *>(cand_all[w]);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        if (MODE == 1 && q == 5)
+          vm = fmaxf(vm, rw[q * 64 + lane]);
+        else if (COMP)
+          sum[q].add(rw[q * 64 + lane]);
+        else
+          sum[q].s += rw[q * 64 + lane];
+      }
+      csum += __float_as_int(rw[9 * 64 + lane]);
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) res[q] = sum[q].value();
+    res[5] = MODE == 1 ? vm : res[5];
+    cnt = csum;
+  }
+  if (lane == 0) g.chunk_todo[cid] = 0;
+
   if (live) {
     if (MODE == 0) {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) g.sums[(int64_t)q * g.n_active + k] = tot[q].value();
+      for (int q = 0; q < 8; ++q) g.sums[(int64_t)q * g.n_active + k] = res[q];
       g.act_cnt[k] = cnt;
     } else {
-      float a0, a1, a2;
-      if (COMP) {
-        a0 = ka[0].s - ka[0].c + tot[0].value();
-        a1 = ka[1].s - ka[1].c + tot[1].value();
-        a2 = ka[2].s - ka[2].c + tot[2].value();
-      } else {
-        a0 = tot[0].value();
-        a1 = tot[1].value();
-        a2 = tot[2].value();
-      }
-      g.ax_out[i] = a0;
-      g.ay_out[i] = a1;
-      g.az_out[i] = a2;
-      const float visc = tot[3].value();
-      const float adiab = tot[4].value();
+      g.ax_out[i] = res[0];
+      g.ay_out[i] = res[1];
+      g.az_out[i] = res[2];
+      const float visc = res[3];
+      const float adiab = res[4];
       const float rho = thi.x;
       g.dA_out[i] = 0.5f * g.gm1 * __powf(rho, -g.gm1) * visc;
       g.du_out[i] = fmaf(thi.y, adiab, 0.5f * visc);
-      g.vsig_out[i] = vmax;
+      g.vsig_out[i] = res[5];
       if (g.nngb_out) g.nngb_out[i] = cnt;
     }
   }
@@ -374,7 +431,7 @@ struct GhostArgs {
   float *h;
   int last;
   int from_u;
-  float eta3, kc, tol, gamma, eps, box_quarter;
+  float eta3, kc, tol, gamma, eps, box_quarter, reach;
   // outputs
   float *rho, *drho_dh, *f, *divv, *curlx, *curly, *curlz, *P, *c, *B, *A, *u;
   int32_t *nngb;
@@ -387,22 +444,25 @@ struct GhostArgs {
 // quantities written.
 __global__ __launch_bounds__(256) void ghost_kernel(GhostArgs g) {
   int finished = 0;
+  int unconv = 0;
   for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < g.n_active; k += (int64_t)gridDim.x * 256) {
     if (g.conv[k]) continue;
     const int i = g.active_idx[k];
     const float S_w = g.sums[k], S_mw = g.sums[g.n_active + k], S_d = g.sums[2 * g.n_active + k],
                 S_md = g.sums[3 * g.n_active + k];
     const float h = g.h[i];
-    // h^3 n = (8/pi)/GK^3 sum w;  dF/dh = (8/pi)/GK^3 (3 sum w - sum (3w + q w')) / h
-    const float F = fmaf(g.kc, S_w, -g.eta3);
-    const float Fp = g.kc * (3.f * S_w - S_d) / h;
+    // Newton in ln h on G = ln(h^3 n / eta^3), with h^3 n = (8/pi)/GK^3 sum w
+    // and dG/dln h = (3 sum w - sum (3w + q w')) / sum w: the same root as
+    // h^3 n = eta^3, reached in one step where the density is locally uniform.
+    const float hn3 = g.kc * S_w;
+    const float G = __logf(hn3 / g.eta3);
+    const float Gp = (3.f * S_w - S_d) / S_w;
     float lo = g.hlo[k], hi = g.hhi[k];
-    if (F < 0.f) lo = fmaxf(lo, h);
-    if (F > 0.f) hi = fminf(hi, h);
-    float hn = h - F / Fp;
-    if (!(hn >= lo && hn <= hi) || !(Fp > 0.f)) hn = (hi < INFINITY) ? 0.5f * (lo + hi) : 2.f * h;
-    hn = fminf(fmaxf(hn, 0.5f * h), 2.f * h);
-    if (F == 0.f) hn = h;
+    if (G < 0.f) lo = fmaxf(lo, h);
+    if (G > 0.f) hi = fminf(hi, h);
+    float hn = h * __expf(fminf(fmaxf(-G / Gp, -0.6931472f), 0.6931472f));
+    if (!(hn >= lo && hn <= hi) || !(Gp > 0.f)) hn = (hi < INFINITY) ? 0.5f * (lo + hi) : 2.f * h;
+    if (G == 0.f) hn = h;
     const bool done = fabsf(hn - h) < g.tol * h;
     if (done || g.last) {
       const float H = GK32 * h;
@@ -447,7 +507,7 @@ __global__ __launch_bounds__(256) void ghost_kernel(GhostArgs g) {
       g.jth[i] = make_float4(rho, fg * P / (rho * rho), cs, Bs);
       finished += g.act_cnt[k];
       g.conv[k] = 1;
-      if (!done) atomicAdd(g.n_unconv, 1);
+      if (!done) ++unconv;
     } else {
       g.hlo[k] = lo;
       g.hhi[k] = hi;
@@ -455,14 +515,18 @@ __global__ __launch_bounds__(256) void ghost_kernel(GhostArgs g) {
       const float Hn = GK32 * hn;
       g.pos4[i].w = Hn;
       g.chunk_todo[g.chunk_of[k]] = 1;
-      atomicAdd(g.n_unconv, 1);
+      ++unconv;
       const Chunk ch = g.chunks[g.chunk_of[k]];
-      if (Hn > g.act_hmax[ch.act_leaf]) atomicOr(g.rebuild, 1);
+      if (Hn > g.act_hmax[ch.act_leaf] * g.reach) atomicOr(g.rebuild, 1);
       if (Hn > g.box_quarter) atomicOr(g.rebuild, 2);
     }
   }
   finished = wave_sum_i(finished);
-  if ((threadIdx.x & 63) == 0 && finished) atomicAdd(g.ctr, (unsigned long long)finished);
+  unconv = wave_sum_i(unconv);
+  if ((threadIdx.x & 63) == 0) {
+    if (finished) atomicAdd(g.ctr, (unsigned long long)finished);
+    if (unconv) atomicAdd(g.n_unconv, unconv);
+  }
 }
 
 __global__ __launch_bounds__(256) void pack_jvm_kernel(const double *__restrict__ vx, const double *__restrict__ vy,
@@ -513,15 +577,27 @@ sph_status launch_loop(sph_ctx *ctx, const LoopArgs &a) {
   LoopArgs g = a;
   g.per_xcd = per;
   const int cap = ctx->prm.cand_cap, lcap = ctx->prm.list_cap;
+  // waves per chunk: enough waves in flight when few chunks are active
+  int nw = ctx->prm.waves_per_chunk;
+  if (nw <= 0) {
+    nw = 1;
+    while (nw < 8 && a.n_chunks * nw < 16384) nw <<= 1;
+  }
   PROF(ctx, MODE == 0 ? "density_loop" : "force_loop");
-  if (cap <= 256 && lcap <= 64)
-    loop_kernel<MODE, 256, 64, COMP><<<grid, 64, 0, ctx->stream>>>(g);
+  if (nw >= 8)
+    loop_kernel<MODE, 256, 64, COMP, 8><<<grid, 512, 0, ctx->stream>>>(g);
+  else if (nw >= 4)
+    loop_kernel<MODE, 256, 64, COMP, 4><<<grid, 256, 0, ctx->stream>>>(g);
+  else if (nw >= 2)
+    loop_kernel<MODE, 512, 96, COMP, 2><<<grid, 128, 0, ctx->stream>>>(g);
+  else if (cap <= 256 && lcap <= 64)
+    loop_kernel<MODE, 256, 64, COMP, 1><<<grid, 64, 0, ctx->stream>>>(g);
   else if (cap <= 512 && lcap <= 96)
-    loop_kernel<MODE, 512, 96, COMP><<<grid, 64, 0, ctx->stream>>>(g);
+    loop_kernel<MODE, 512, 96, COMP, 1><<<grid, 64, 0, ctx->stream>>>(g);
   else if (cap <= 1024 && lcap <= 128)
-    loop_kernel<MODE, 1024, 128, COMP><<<grid, 64, 0, ctx->stream>>>(g);
+    loop_kernel<MODE, 1024, 128, COMP, 1><<<grid, 64, 0, ctx->stream>>>(g);
   else
-    loop_kernel<MODE, 2048, 192, COMP><<<grid, 64, 0, ctx->stream>>>(g);
+    loop_kernel<MODE, 2048, 192, COMP, 1><<<grid, 64, 0, ctx->stream>>>(g);
   return sph_hip_check(ctx, hipGetLastError(), MODE == 0 ? "density loop" : "force loop");
 }
 
@@ -589,6 +665,8 @@ sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u)
   const int64_t n = ctx->n, na = ctx->n_active;
   ctx->density_iterations = 0;
   ctx->n_unconverged = 0;
+  ctx->pair_rebuilds = 0;
+  for (int q = 0; q < 32; ++q) ctx->unconv_hist[q] = 0;
   (void)n;
   if (na == 0) {
     ctx->state = 4;
@@ -644,6 +722,7 @@ sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u)
     gh.gamma = G;
     gh.eps = ctx->prm.balsara_eps;
     gh.box_quarter = (float)(0.25 * ctx->prm.box);
+    gh.reach = ctx->dpair_slack;
     gh.rho = p->rho;
     gh.drho_dh = p->drho_dh;
     gh.f = p->f_gradh;
@@ -668,6 +747,7 @@ sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u)
     int32_t st[2];
     SPH_TRY(read_scalars(ctx, SC_UNCONV, 2, st));
     ctx->density_iterations = it;
+    if (it <= 32) ctx->unconv_hist[it - 1] = st[0];
     if (st[1] & 2) return sph_fail(ctx, SPH_EREBUILD, "density_pass: a smoothing length exceeds a quarter of the box");
     if (gh.last) {
       ctx->n_unconverged = st[0];
@@ -676,8 +756,9 @@ sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u)
     if (st[0] == 0) break;
     if (st[1] & 1) {
       // a smoothing length outgrew its cell's pair reach: widen the pair lists
+      ctx->pair_rebuilds++;
       SPH_TRY(refresh_leaf_hmax(ctx));
-      SPH_TRY(build_pairs(ctx, 0));
+      SPH_TRY(build_pairs(ctx, 0, 1.5f));
     }
   }
   ctx->state = 4;
@@ -698,7 +779,7 @@ sph_status force_pass_impl(sph_ctx *ctx, sph_particles *p) {
   }
   (void)n;
   SPH_TRY(refresh_leaf_hmax(ctx));
-  SPH_TRY(build_pairs(ctx, 1));
+  SPH_TRY(build_pairs(ctx, 1, 1.0f));
   fill_i32_kernel<<<grid256(ctx->n_chunks), 256, 0, ctx->stream>>>((int32_t *)ctx->chunk_todo.p, ctx->n_chunks, 1);
   HIP_TRY(ctx, hipGetLastError());
   LoopArgs a = base_args(ctx);

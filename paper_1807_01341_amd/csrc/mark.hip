@@ -109,7 +109,7 @@ __device__ __forceinline__ void leaf_centre_units(int D, int lvl, int ix, int iy
 // double) and count (FILL=false) or write (FILL=true) the pairs in a fixed
 // order.  mode 0: R = max active H of A; mode 1: R = max(that, max H of B).
 template <bool FILL>
-__global__ __launch_bounds__(MT) void pairs_kernel(int mode, PairGeom g, int64_t n_act_leaves,
+__global__ __launch_bounds__(MT) void pairs_kernel(int mode, float slack, PairGeom g, int64_t n_act_leaves,
                                                    const int32_t *__restrict__ act_leaves,
                                                    const float *__restrict__ act_hmax,
                                                    const int32_t *__restrict__ level, const int32_t *__restrict__ ix,
@@ -123,7 +123,7 @@ __global__ __launch_bounds__(MT) void pairs_kernel(int mode, PairGeom g, int64_t
   if (a >= n_act_leaves) return;
   const int lane = threadIdx.x & 63;
   const int A = act_leaves[a];
-  const float RA = act_hmax[a];
+  const float RA = act_hmax[a] * slack;
   const int lvA = level[A];
   int64_t ca[3];
   leaf_centre_units(g.D, lvA, ix[A], iy[A], iz[A], ca);
@@ -228,8 +228,11 @@ __global__ __launch_bounds__(MT) void leaf_hmax_refresh_kernel(const float4 *__r
 
 static unsigned waves_grid(int64_t n_items) { return (unsigned)(ceil_div(n_items, MT / 64) > 0 ? ceil_div(n_items, MT / 64) : 1); }
 
-sph_status build_pairs(sph_ctx *ctx, int which) {
+// which = 0: density lists, 1: force lists.  slack > 1 widens the reach of
+// every active leaf (used when smoothing lengths grow during the h solve).
+sph_status build_pairs(sph_ctx *ctx, int which, float slack) {
   const int64_t na = ctx->n_active_leaves;
+  if (which == 0) ctx->dpair_slack = slack;
   DevBuf &off = which == 0 ? ctx->dpair_off : ctx->fpair_off;
   DevBuf &lst = which == 0 ? ctx->dpairs : ctx->fpairs;
   SPH_TRY(sph_ensure(ctx, ctx->pair_cnt, 4 * (size_t)(na + 1)));
@@ -249,7 +252,7 @@ sph_status build_pairs(sph_ctx *ctx, int which) {
   {
     PROF(ctx, "cell_pairs");
     pairs_kernel<false><<<waves_grid(na), MT, 0, ctx->stream>>>(
-        which, g, na, (const int32_t *)ctx->act_leaves.p, (const float *)ctx->act_hmax.p,
+        which, slack, g, na, (const int32_t *)ctx->act_leaves.p, (const float *)ctx->act_hmax.p,
         (const int32_t *)ctx->leaf_level.p, (const int32_t *)ctx->leaf_ix.p, (const int32_t *)ctx->leaf_iy.p,
         (const int32_t *)ctx->leaf_iz.p, (const float *)ctx->leaf_hmax.p, (const int32_t *)ctx->top_first.p,
         (const int32_t *)ctx->top_last.p, ctx->hmax_global, (int32_t *)ctx->pair_cnt.p, nullptr, nullptr);
@@ -265,7 +268,7 @@ sph_status build_pairs(sph_ctx *ctx, int which) {
   {
     PROF(ctx, "cell_pairs");
     pairs_kernel<true><<<waves_grid(na), MT, 0, ctx->stream>>>(
-        which, g, na, (const int32_t *)ctx->act_leaves.p, (const float *)ctx->act_hmax.p,
+        which, slack, g, na, (const int32_t *)ctx->act_leaves.p, (const float *)ctx->act_hmax.p,
         (const int32_t *)ctx->leaf_level.p, (const int32_t *)ctx->leaf_ix.p, (const int32_t *)ctx->leaf_iy.p,
         (const int32_t *)ctx->leaf_iz.p, (const float *)ctx->leaf_hmax.p, (const int32_t *)ctx->top_first.p,
         (const int32_t *)ctx->top_last.p, ctx->hmax_global, nullptr, o, (PairEntry *)lst.p);
@@ -347,7 +350,7 @@ sph_status mark_active_impl(sph_ctx *ctx, const sph_particles *p, int m, int64_t
         (Chunk *)ctx->chunks.p);
   }
   HIP_TRY(ctx, hipGetLastError());
-  SPH_TRY(build_pairs(ctx, 0));
+  SPH_TRY(build_pairs(ctx, 0, 1.0f));
   if (n_active_host) *n_active_host = ctx->n_active;
   ctx->state = 3;
   return SPH_OK;

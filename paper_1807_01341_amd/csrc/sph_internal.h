@@ -50,6 +50,9 @@ struct sph_ctx {
   int max_active_bin = 0;
   int density_iterations = 0;
   int64_t n_unconverged = 0;
+  int32_t unconv_hist[32] = {0};
+  int32_t pair_rebuilds = 0;
+  float dpair_slack = 1.f;  // reach factor of the current density pair lists
   float hmax_global = 0.f;  // max H over all particles (monotone between builds)
 
   // build
@@ -138,7 +141,7 @@ sph_status read_scalars(sph_ctx *ctx, int first, int count, int32_t *host);
 sph_status build_cells_impl(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *perm_out);
 sph_status sort_cells_impl(sph_ctx *ctx);
 sph_status mark_active_impl(sph_ctx *ctx, const sph_particles *p, int m, int64_t *n_active_host);
-sph_status build_pairs(sph_ctx *ctx, int which);
+sph_status build_pairs(sph_ctx *ctx, int which, float slack);
 sph_status refresh_leaf_hmax(sph_ctx *ctx);
 sph_status pack_neighbour_data(sph_ctx *ctx, const sph_particles *p);
 sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u);

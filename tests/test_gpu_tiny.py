@@ -73,6 +73,8 @@ def test_kick_drift_matches_oracle(gpu_lib):
     vs = rng.uniform(0.5, 5.0, size=N).astype(np.float32)
     vs[::17] = 0.0
     Af = rng.uniform(0.5, 1.5, size=N).astype(np.float32)
+    dv = rng.normal(scale=300.0, size=N).astype(np.float32)
+    p["divv"].copy_(torch.from_numpy(dv))
     for d, k in enumerate(("ax", "ay", "az")):
         p[k].copy_(torch.from_numpy(a[:, d]))
     p["dA_dt"].copy_(torch.from_numpy(dA))
@@ -89,13 +91,17 @@ def test_kick_drift_matches_oracle(gpu_lib):
     ctx.kick_drift(p, ti, t_min, drift, False)
     ctx.sync()
     ref = sph.kick_drift(x0, vf0, vp0, Af.astype(np.float64), Af.astype(np.float64), a, dA, h, vs, bins0, act, ti,
-                         t_min, drift, 1.0)
+                         t_min, drift, 1.0, divv=dv)
     assert np.array_equal(host(p, "time_bin").astype(np.int64), ref["bins"])
     assert np.array_equal(np.stack([host(p, k) for k in "xyz"], 1), ref["x"])
     assert np.array_equal(np.stack([host(p, k) for k in ("vfx", "vfy", "vfz")], 1), ref["vf"])
     assert np.array_equal(np.stack([host(p, k) for k in ("vx", "vy", "vz")], 1), ref["vp"])
     assert np.array_equal(host(p, "Af"), ref["Af"].astype(np.float32))
     assert np.array_equal(host(p, "A"), ref["Ap"].astype(np.float32))
+    # h after the predicted drift: exp in double on both sides, rounded to float
+    hg = host(p, "h").view(np.int32).astype(np.int64)
+    hr = ref["h"].astype(np.float32).view(np.int32).astype(np.int64)
+    assert np.max(np.abs(hg - hr)) <= 1
 
 
 def test_call_order_and_argument_errors(gpu_lib):
@@ -133,3 +139,20 @@ def test_call_order_and_argument_errors(gpu_lib):
         ctx2.density_pass(p2, True)
     assert e.value.code == -4
     assert ctx2.info()["n_unconverged"] > 0
+
+
+@pytest.mark.parametrize("nw", [1, 2, 4, 8])
+def test_waves_per_chunk_variants_agree(gpu_lib, nw):
+    """Every loop tiling (waves per chunk, candidate/list capacities) gives
+    the same neighbour counts and the same sums to rounding."""
+    ic = ics.tiny_lattice(16, velocity_sigma=0.1)
+    _, p0, perm0, _ = run_gpu_step(gpu_lib, ic, 0, ctx_kw=dict(waves_per_chunk=1, cand_cap=2048, list_cap=192))
+    _, p1, perm1, _ = run_gpu_step(gpu_lib, ic, 0, ctx_kw=dict(waves_per_chunk=nw, cand_cap=256, list_cap=64))
+    assert np.array_equal(perm0, perm1)
+    for k in ("nngb_density", "nngb_force"):
+        assert np.array_equal(host(p0, k), host(p1, k)), k
+    for k in ("h", "rho", "vsig"):
+        assert np.max(np.abs(host(p0, k) / host(p1, k) - 1)) < 2e-6, k
+    a0 = np.stack([host(p0, k) for k in ("ax", "ay", "az")], 1)
+    a1 = np.stack([host(p1, k) for k in ("ax", "ay", "az")], 1)
+    assert np.max(np.linalg.norm(a0 - a1, axis=1)) < 1e-5 * np.max(np.linalg.norm(a0, axis=1))
