@@ -106,6 +106,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=None)
     ap.add_argument("--h-tol", type=float, default=None)
     ap.add_argument("--nw", type=int, default=None)
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--tune-file", default=os.path.join(ROOT, "gpurun_out", "tuning_clustered.txt"))
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the multi-GPU decomposition "
@@ -151,6 +153,22 @@ def main():
         ctx.mark_active(p, m, want_count=False)
         ctx.density_pass(p, entropy_from_u=False)
         ctx.force_pass(p)
+        ctx.kick_drift(p, ti, t_min, 1 << m, False)
+
+    tuned = None
+    if not args.no_tune:
+        # one step whose loops are tuned on the step's own active chunks
+        ti = 1 << m
+        ctx.build_cells(p)
+        ctx.sort_cells()
+        ctx.mark_active(p, m, want_count=False)
+        ctx.density_pass(p, entropy_from_u=False)
+        ctx.force_pass(p)
+        os.makedirs(os.path.dirname(args.tune_file), exist_ok=True)
+        if os.path.exists(args.tune_file):
+            os.remove(args.tune_file)
+        ctx.autotune(p, args.tune_file)
+        tuned = [l.split() for l in open(args.tune_file) if l.startswith("best")]
         ctx.kick_drift(p, ti, t_min, 1 << m, False)
 
     for s in range(args.warmup):
@@ -226,6 +244,9 @@ def main():
         "last_step_newton": {"unconverged_after_pass": last["unconverged_after_pass"],
                              "pair_rebuilds": last["pair_rebuilds"]},
         "kernels": kernels,
+        "tuned_loops": [{"loop": ("density", "force")[int(t[1])], "chunk_class": int(t[2]), "waves_per_chunk": int(t[3]),
+                         "tile": int(t[4]), "cost_ordered": int(t[5]), "persistent": int(t[6]), "ms": float(t[7])}
+                        for t in (tuned or [])],
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

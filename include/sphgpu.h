@@ -60,7 +60,7 @@ typedef struct {
   float h_tol;         /* relative Newton step that ends the h solve (1e-6) */
   int n_bins;          /* time-bins 0..n_bins-1 of Eq. 2 (14) */
   int split_count;     /* a cell with at least this many particles is split (400, Sec. III-A) */
-  int morton_depth;    /* bits per axis of the Morton keys, D <= 21 (21) */
+  int morton_depth;    /* bits per axis of the Morton keys, D <= 21 (16) */
   int top_cap;         /* top-level grid has at most 2^top_cap cells per side (7) */
   int h_max_iter;      /* Newton iterations of the h solve (30) */
   int compensated;     /* 1: compensated FP32 sums in the loops (1) */
@@ -152,6 +152,18 @@ sph_status sph_kick_drift(sph_ctx *ctx, sph_particles *p, int64_t ti, double t_m
 /* Waits for the context's stream and reports a pending device error. */
 sph_status sph_sync(sph_ctx *ctx);
 const char *sph_last_error(const sph_ctx *ctx);
+
+/* Autotuner for the loop tiling (waves per chunk, candidate/list capacity,
+ * work order, grid or persistent launch): after a force pass, times every
+ * valid configuration of both loops on the current active chunks with HIP
+ * events (best of two launches after a warm-up), keeps the fastest per loop
+ * for this number of chunks (log2 class), and appends the measurements and
+ * the winners to the text file `path` (NULL: keep in the context only).
+ * Later passes of the context with a chunk count of the same class use the
+ * winner.  Synchronises. */
+sph_status sph_autotune(sph_ctx *ctx, sph_particles *p, const char *path);
+/* Loads the "best" lines of a file written by sph_autotune. */
+sph_status sph_load_tuning(sph_ctx *ctx, const char *path);
 
 /* Per-kernel timing with HIP events recorded on the context's stream around
  * each launch (or group of launches) of the library.  sph_profile(ctx, 1)

@@ -96,6 +96,8 @@ def lib():
             "sph_copy_pairs": (i32, [vp, i32] + [vp] * 5),
             "sph_profile": (i32, [vp, i32]),
             "sph_profile_read": (i64, [vp, vp, i64]),
+            "sph_autotune": (i32, [vp, vp, C.c_char_p]),
+            "sph_load_tuning": (i32, [vp, C.c_char_p]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(L, name)
@@ -109,7 +111,8 @@ def exported_symbols():
     return ["sph_default_params", "sph_create", "sph_destroy", "sph_build_cells", "sph_sort_cells",
             "sph_mark_active", "sph_density_pass", "sph_force_pass", "sph_kick_drift", "sph_sync",
             "sph_last_error", "sph_info", "sph_copy_leaves", "sph_copy_particles", "sph_copy_axis_order",
-            "sph_copy_active", "sph_copy_pairs", "sph_profile", "sph_profile_read"]
+            "sph_copy_active", "sph_copy_pairs", "sph_profile", "sph_profile_read", "sph_autotune",
+            "sph_load_tuning"]
 
 
 def require_device():
@@ -244,6 +247,12 @@ class Context:
         out = {k: getattr(inf, k) for k, _ in Info._fields_}
         out["unconverged_after_pass"] = list(out["unconverged_after_pass"])[:max(0, out["density_iterations"])]
         return out
+
+    def autotune(self, p: Particles, path: str | None = None):
+        return self._check(lib().sph_autotune(self.h, self._pcs(p), path.encode() if path else None))
+
+    def load_tuning(self, path: str):
+        return self._check(lib().sph_load_tuning(self.h, path.encode()))
 
     def profile(self, enable: bool):
         return self._check(lib().sph_profile(self.h, int(bool(enable))))

@@ -95,7 +95,7 @@ void sph_default_params(sph_params *p) {
   p->h_tol = 1e-6f;
   p->n_bins = 14;
   p->split_count = 400;
-  p->morton_depth = 21;
+  p->morton_depth = 16;
   p->top_cap = 7;
   p->h_max_iter = 30;
   p->compensated = 1;
@@ -118,6 +118,9 @@ sph_status sph_create(const sph_params *p, void *hip_stream, sph_ctx **out) {
     delete ctx;
     return SPH_EDEVICE;
   }
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device) == hipSuccess && ncu > 0)
+    ctx->n_cu = ncu;
   if (sph_ensure(ctx, ctx->scalars, sizeof(int32_t) * SC_COUNT) != SPH_OK) {
     delete ctx;
     return SPH_ENOMEM;
@@ -143,7 +146,7 @@ void sph_destroy(sph_ctx *ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   resolve_profile(ctx);
   for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
-  DevBuf *bufs[] = {&ctx->counters64, &ctx->keys_a, &ctx->keys_b, &ctx->vals_a, &ctx->vals_b, &ctx->radix_counts, &ctx->scan_tmp,
+  DevBuf *bufs[] = {&ctx->counters64, &ctx->act_cost, &ctx->work, &ctx->work_tmp, &ctx->box_args, &ctx->box_work, &ctx->keys_a, &ctx->keys_b, &ctx->vals_a, &ctx->vals_b, &ctx->radix_counts, &ctx->scan_tmp,
                     &ctx->gather_tmp, &ctx->scalars, &ctx->flags, &ctx->scan_out, &ctx->nodes_a, &ctx->nodes_b,
                     &ctx->leaf_lvl_at, &ctx->leaf_level, &ctx->leaf_ix, &ctx->leaf_iy, &ctx->leaf_iz,
                     &ctx->leaf_begin, &ctx->leaf_count, &ctx->leaf_hmax, &ctx->leaf_of, &ctx->top_first,

@@ -1,532 +1,15 @@
-// The neighbour loops over active cell pairs (Sec. III-A, Fig. 5): the density
-// loop with the ghost's smoothing-length correction, and the force loop.
-//
-// Work item: one wave per chunk of up to 64 active particles of one leaf
-// (gather formulation: each active particle's sums are produced by the single
-// wave that owns it, in a fixed order, so there are no atomics and results are
-// reproducible).  For every partner leaf of the chunk's cell-pair list:
-//   1. staging: the partner's particles are read 64 at a time (coalesced SoA
-//      loads, in the per-cell axis-sort order when the pair is not a self pair
-//      so that the sweep stops once the projections leave the chunk's reach),
-//      moved into the chunk leaf's frame with the FP32 pair shift, and kept if
-//      they are within reach of the chunk's bounding box (wave ballot + rank
-//      into an LDS candidate array);
-//   2. filter: every lane tests its own particle against each candidate with
-//      the FP32 predicate and appends hits to its own LDS neighbour list;
-//   3. interact: every lane walks its own list (lanes have near-equal neighbour
-//      counts because h adapts) and accumulates its sums in registers.
-// No MFMA: pair interactions are not a dense contraction.
-#include <math.h>
-#include <string.h>
+// Single-box passes: the density loop with the ghost's h solve, and the
+// force loop, over the active chunks of one context.
+#include <stdio.h>
 
-#include "sph_internal.h"
+#include "loops_common.h"
 
 namespace {
 
-struct AxisTab {
-  float e[13][3];
-};
-
-AxisTab host_axes() {
-  AxisTab a;
-  int k = 0;
-  for (int dx = -1; dx <= 1; ++dx)
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dz = -1; dz <= 1; ++dz) {
-        const int first = dx != 0 ? dx : (dy != 0 ? dy : dz);
-        if (first <= 0) continue;
-        const double nrm = sqrt((double)(dx * dx + dy * dy + dz * dz));
-        a.e[k][0] = (float)(dx / nrm);
-        a.e[k][1] = (float)(dy / nrm);
-        a.e[k][2] = (float)(dz / nrm);
-        ++k;
-      }
-  return a;
-}
-
-struct LoopArgs {
-  const Chunk *chunks;
-  int32_t *chunk_todo;
-  int64_t n_chunks;
-  int64_t per_xcd;
-  const int32_t *active_idx;
-  const float4 *pos4;  // (ox, oy, oz, H)
-  const float4 *jvm;   // (vx, vy, vz, m)
-  const float4 *jth;   // (rho, f P / rho^2, c, B)  force only
-  const int32_t *leaf_begin, *leaf_count;
-  const float *leaf_hmax;
-  const int32_t *pair_off;
-  const PairEntry *pairs;
-  const uint16_t *axis_order;
-  int64_t n;
-  AxisTab ax;
-  // density outputs: per active index
-  float *sums;
-  int32_t *act_cnt;
-  int64_t n_active;
-  // force outputs: per particle
-  float *ax_out, *ay_out, *az_out, *dA_out, *du_out, *vsig_out;
-  int32_t *nngb_out;
-  float half_alpha, gm1;
-  unsigned long long *ctr;  // cumulative force interactions
-};
-
-__device__ __forceinline__ void kernel_w_dw(float q, float &w, float &wp) {
-  // w = 1 - 6q^2 + 6q^3, w' = -12q + 18q^2 on [0, 1/2); 2(1-q)^3, -6(1-q)^2 on [1/2, 1)
-  const float wi = fmaf(q * q, fmaf(6.f, q, -6.f), 1.f);
-  const float wpi = q * fmaf(18.f, q, -12.f);
-  const float t = 1.f - q;
-  const float t2 = t * t;
-  const float wo = 2.f * t2 * t;
-  const float wpo = -6.f * t2;
-  const bool in = q < 0.5f;
-  w = in ? wi : wo;
-  wp = in ? wpi : wpo;
-}
-
-__device__ __forceinline__ float kernel_dw_only(float q) {
-  const float wpi = q * fmaf(18.f, q, -12.f);
-  const float t = 1.f - q;
-  const float wpo = -6.f * t * t;
-  return q < 0.5f ? wpi : (q < 1.f ? wpo : 0.f);
-}
-
-struct Neu {  // compensated running sum
-  float s = 0.f, c = 0.f;
-  __device__ __forceinline__ void add(float b) {
-    const float t = s + b;
-    if (fabsf(s) >= fabsf(b))
-      c += (s - t) + b;
-    else
-      c += (b - t) + s;
-    s = t;
-  }
-  __device__ __forceinline__ float value() const { return s + c; }
-};
-
-struct Kahan {  // per-term compensated accumulator
-  float s = 0.f, c = 0.f;
-  __device__ __forceinline__ void add(float b) {
-    const float y = b - c;
-    const float t = s + y;
-    c = (t - s) - y;
-    s = t;
-  }
-};
-
-__device__ __forceinline__ int chunk_id(int64_t per_xcd, int64_t n_chunks) {
-  // consecutive chunks (neighbours in Morton order) on the same XCD, so that
-  // their shared partner cells are re-read from that XCD's L2
-  const int64_t b = blockIdx.x;
-  const int64_t cid = (b & 7) * per_xcd + (b >> 3);
-  return cid < n_chunks ? (int)cid : -1;
-}
-
-// Orders this wave's LDS accesses across its lanes (each wave owns its own
-// LDS region, so no workgroup barrier is needed between its phases).
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
-
-// MODE 0: density loop; MODE 1: force loop.  NW waves share one chunk: wave w
-// takes the partner cells w, w+NW, ... of the chunk's pair list, and the
-// per-lane partial sums are combined across waves in wave order at the end.
-template <int MODE, int CAP, int LCAP, bool COMP, int NW>
-__global__ __launch_bounds__(64 * NW) void loop_kernel(LoopArgs g) {
-  __shared__ float4 cand_all[NW][CAP];
-  __shared__ float candH_all[NW][MODE == 1 ? CAP : 1];
-  __shared__ uint16_t lists_all[NW][LCAP * 64];
-
-  const int cid = chunk_id(g.per_xcd, g.n_chunks);
-  if (cid < 0) return;
-  if (!g.chunk_todo[cid]) return;
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  float4 *cand = cand_all[wave];
-  float *candH = candH_all[wave];
-  uint16_t *lists = lists_all[wave];
-  const Chunk ch = g.chunks[cid];
-  const bool live = lane < ch.count;
-  const int k = ch.begin + lane;
-  const int i = live ? g.active_idx[k] : -1;
-  const float4 pi = live ? g.pos4[i] : make_float4(0.f, 0.f, 0.f, 0.f);
-  const float Hi = pi.w;
-  const float H2i = live ? Hi * Hi : -1.f;
-  const float invHi = live ? 1.f / Hi : 0.f;
-  const float4 vi = live ? g.jvm[i] : make_float4(0.f, 0.f, 0.f, 0.f);
-  float4 thi = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (MODE == 1 && live) thi = g.jth[i];
-
-  // chunk bounding box and reach
-  const float bminx = wave_min_f(live ? pi.x : INFINITY), bmaxx = wave_max_f(live ? pi.x : -INFINITY);
-  const float bminy = wave_min_f(live ? pi.y : INFINITY), bmaxy = wave_max_f(live ? pi.y : -INFINITY);
-  const float bminz = wave_min_f(live ? pi.z : INFINITY), bmaxz = wave_max_f(live ? pi.z : -INFINITY);
-  const float Rc = wave_max_f(live ? Hi : 0.f);
-  const float R2c = Rc * Rc;
-
-  // accumulators: density (w, m w, 3w+qw', m(3w+qw'), div, curl x3); force (a x3, visc, adiab)
-  float acc[9];
-  Neu tot[9];
-#pragma unroll
-  for (int q = 0; q < 9; ++q) acc[q] = 0.f;
-  Kahan ka[3];
-  float vmax = 0.f;
-  int cnt = 0;
-  int len = 0;
-  int ncand = 0;
-
-  auto interact = [&]() {
-    const int maxlen = wave_max_i(len);
-    for (int t = 0; t < maxlen; ++t) {
-      if (t < len) {
-        const int c = lists[t * 64 + lane];
-        const float4 cj = cand[c];
-        const int j = __float_as_int(cj.w);
-        const float dx = pi.x - cj.x, dy = pi.y - cj.y, dz = pi.z - cj.z;
-        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        const float4 vj = g.jvm[j];
-        const float rinv = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
-        const float r = r2 * rinv;
-        const float vx = vi.x - vj.x, vy = vi.y - vj.y, vz = vi.z - vj.z;
-        const float vr = fmaf(vz, dz, fmaf(vy, dy, vx * dx));
-        const float mj = vj.w;
-        if (MODE == 0) {
-          float w, wp;
-          const float q = r * invHi;
-          kernel_w_dw(q, w, wp);
-          const float d3 = fmaf(q, wp, 3.f * w);
-          acc[0] += w;
-          acc[1] = fmaf(mj, w, acc[1]);
-          acc[2] += d3;
-          acc[3] = fmaf(mj, d3, acc[3]);
-          const float fac = mj * wp * rinv;
-          acc[4] = fmaf(fac, vr, acc[4]);
-          acc[5] = fmaf(fac, fmaf(vy, dz, -vz * dy), acc[5]);
-          acc[6] = fmaf(fac, fmaf(vz, dx, -vx * dz), acc[6]);
-          acc[7] = fmaf(fac, fmaf(vx, dy, -vy * dx), acc[7]);
-          cnt += (j != i);
-        } else {
-          const float Hj = candH[c];
-          const float invHj = __builtin_amdgcn_rcpf(Hj);
-          const float4 th = g.jth[j];
-          const float wpi = kernel_dw_only(r * invHi);
-          const float wpj = kernel_dw_only(r * invHj);
-          const float ih2 = invHj * invHj;
-          const float Fi = (KNORM32 * invHi * invHi * invHi * invHi) * wpi * rinv;
-          const float Fj = KNORM32 * (ih2 * ih2) * wpj * rinv;
-          const float mu = fminf(vr * rinv, 0.f);
-          const float vsig = thi.z + th.z - 3.f * mu;
-          vmax = fmaxf(vmax, vsig);
-          const float Pi = -g.half_alpha * vsig * mu * (thi.w + th.w) * __builtin_amdgcn_rcpf(thi.x + th.x);
-          const float gbar = 0.5f * (Fi + Fj);
-          const float coef = mj * fmaf(thi.y, Fi, fmaf(th.y, Fj, Pi * gbar));
-          if (COMP) {
-            ka[0].add(-coef * dx);
-            ka[1].add(-coef * dy);
-            ka[2].add(-coef * dz);
-          } else {
-            acc[0] = fmaf(-coef, dx, acc[0]);
-            acc[1] = fmaf(-coef, dy, acc[1]);
-            acc[2] = fmaf(-coef, dz, acc[2]);
-          }
-          acc[3] = fmaf(mj * Pi * vr, gbar, acc[3]);
-          acc[4] = fmaf(mj * vr, Fi, acc[4]);
-          ++cnt;
-        }
-      }
-    }
-    // fold the batch into the compensated totals
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      if (COMP)
-        tot[q].add(acc[q]);
-      else
-        tot[q].s += acc[q];
-      acc[q] = 0.f;
-    }
-    len = 0;
-  };
-
-  auto flush = [&]() {
-    wave_sync();
-    for (int b0 = 0; b0 < ncand; b0 += 64) {
-      if (wave_max_i(len) > LCAP - 64) interact();
-      const int bend = min(ncand, b0 + 64);
-      for (int c = b0; c < bend; ++c) {
-        const float4 cj = cand[c];
-        const float dx = pi.x - cj.x, dy = pi.y - cj.y, dz = pi.z - cj.z;
-        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        bool hit;
-        if (MODE == 0) {
-          hit = r2 < H2i;
-        } else {
-          const float Hj = candH[c];
-          hit = live && (r2 < H2i || r2 < Hj * Hj) && __float_as_int(cj.w) != i;
-        }
-        if (hit) {
-          lists[len * 64 + lane] = (uint16_t)c;
-          ++len;
-        }
-      }
-    }
-    interact();
-    ncand = 0;
-    wave_sync();
-  };
-
-  const int pbeg = g.pair_off[ch.act_leaf], pend = g.pair_off[ch.act_leaf + 1];
-  for (int pp = pbeg + wave; pp < pend; pp += NW) {
-    const PairEntry e = g.pairs[pp];
-    const int B = e.b;
-    const int bb = g.leaf_begin[B], bc = g.leaf_count[B];
-    const bool selfp = (B == ch.leaf);
-    const float Rb = MODE == 0 ? Rc : fmaxf(Rc, g.leaf_hmax[B]);
-    // sweep axis: the stencil direction closest to the pair offset
-    int axis = 0;
-    float best = -1.f, sgn = 1.f;
-    if (!selfp) {
-#pragma unroll
-      for (int a = 0; a < 13; ++a) {
-        const float d = fmaf(e.sz, g.ax.e[a][2], fmaf(e.sy, g.ax.e[a][1], e.sx * g.ax.e[a][0]));
-        if (fabsf(d) > best) {
-          best = fabsf(d);
-          axis = a;
-          sgn = d >= 0.f ? 1.f : -1.f;
-        }
-      }
-    }
-    const float ex = g.ax.e[axis][0], ey = g.ax.e[axis][1], ez = g.ax.e[axis][2];
-    // reach of the chunk box along the axis, in the partner leaf's frame
-    const float pmin = fminf(ex * bminx, ex * bmaxx) + fminf(ey * bminy, ey * bmaxy) + fminf(ez * bminz, ez * bmaxz);
-    const float pmax = fmaxf(ex * bminx, ex * bmaxx) + fmaxf(ey * bminy, ey * bmaxy) + fmaxf(ez * bminz, ez * bmaxz);
-    const float sproj = fmaf(e.sz, ez, fmaf(e.sy, ey, e.sx * ex));
-    const float margin = 1.0001f * Rb + 1e-6f * (fabsf(pmin) + fabsf(pmax) + fabsf(sproj));
-    const float lo_b = pmin - margin - sproj, hi_b = pmax + margin - sproj;
-    const uint16_t *ord = g.axis_order + (int64_t)axis * g.n + bb;
-    for (int t = 0; t < bc; t += 64) {
-      const int kk = t + lane;
-      const bool valid = kk < bc;
-      int j = bb;
-      if (valid) j = selfp ? bb + kk : bb + (int)ord[sgn > 0.f ? kk : bc - 1 - kk];
-      const float4 pj = valid ? g.pos4[j] : make_float4(0.f, 0.f, 0.f, 0.f);
-      if (!selfp) {
-        const float key = fmaf(pj.z, ez, fmaf(pj.y, ey, pj.x * ex));
-        const bool beyond = sgn > 0.f ? key > hi_b : key < lo_b;
-        if (__ballot(valid && !beyond) == 0ull) break;
-      }
-      const float xj = pj.x + e.sx, yj = pj.y + e.sy, zj = pj.z + e.sz;
-      const float gx = fmaxf(fmaxf(bminx - xj, xj - bmaxx), 0.f);
-      const float gy = fmaxf(fmaxf(bminy - yj, yj - bmaxy), 0.f);
-      const float gz = fmaxf(fmaxf(bminz - zj, zj - bmaxz), 0.f);
-      const float d2 = fmaf(gz, gz, fmaf(gy, gy, gx * gx));
-      bool keep;
-      if (MODE == 0)
-        keep = valid && d2 < R2c;
-      else
-        keep = valid && (d2 < R2c || d2 < pj.w * pj.w);
-      const uint64_t mask = __ballot(keep);
-      if (keep) {
-        const int slot = ncand + rank_below(mask);
-        cand[slot] = make_float4(xj, yj, zj, __int_as_float(j));
-        if (MODE == 1) candH[slot] = pj.w;
-      }
-      ncand += __popcll(mask);
-      if (ncand > CAP - 64) flush();
-    }
-  }
-  flush();
-
-  // per-lane results of this wave
-  float res[9];
-  if (MODE == 0) {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) res[q] = tot[q].value();
-    res[8] = 0.f;
-  } else {
-    if (COMP) {
-      res[0] = ka[0].s - ka[0].c + tot[0].value();
-      res[1] = ka[1].s - ka[1].c + tot[1].value();
-      res[2] = ka[2].s - ka[2].c + tot[2].value();
-    } else {
-      res[0] = tot[0].value();
-      res[1] = tot[1].value();
-      res[2] = tot[2].value();
-    }
-    res[3] = tot[3].value();
-    res[4] = tot[4].value();
-    res[5] = vmax;
-    res[6] = res[7] = res[8] = 0.f;
-  }
-  if (NW > 1) {
-    // combine the waves' partial sums in wave order through LDS
-    constexpr int NQ = 10;
-    static_assert(CAP * 4 >= NQ * 64, "reduction buffer");
-    __syncthreads();
-    float *red = reinterpret_cast<float *>(cand_all[wave]);
-#pragma unroll
-    for (int q = 0; q < 9; ++q) red[q * 64 + lane] = res[q];
-    red[9 * 64 + lane] = __int_as_float(cnt);
-    __syncthreads();
-    if (wave != 0) return;
-    Neu sum[9];
-    int csum = 0;
-    float vm = 0.f;
-    for (int w = 0; w < NW; ++w) {
-      const float *rw = reinterpret_cast<const float *>(cand_all[w]);
-#pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        if (MODE == 1 && q == 5)
-          vm = fmaxf(vm, rw[q * 64 + lane]);
-        else if (COMP)
-          sum[q].add(rw[q * 64 + lane]);
-        else
-          sum[q].s += rw[q * 64 + lane];
-      }
-      csum += __float_as_int(rw[9 * 64 + lane]);
-    }
-#pragma unroll
-    for (int q = 0; q < 9; ++q) res[q] = sum[q].value();
-    res[5] = MODE == 1 ? vm : res[5];
-    cnt = csum;
-  }
-  if (lane == 0) g.chunk_todo[cid] = 0;
-
-  if (live) {
-    if (MODE == 0) {
-#pragma unroll
-      for (int q = 0; q < 8; ++q) g.sums[(int64_t)q * g.n_active + k] = res[q];
-      g.act_cnt[k] = cnt;
-    } else {
-      g.ax_out[i] = res[0];
-      g.ay_out[i] = res[1];
-      g.az_out[i] = res[2];
-      const float visc = res[3];
-      const float adiab = res[4];
-      const float rho = thi.x;
-      g.dA_out[i] = 0.5f * g.gm1 * __powf(rho, -g.gm1) * visc;
-      g.du_out[i] = fmaf(thi.y, adiab, 0.5f * visc);
-      g.vsig_out[i] = res[5];
-      if (g.nngb_out) g.nngb_out[i] = cnt;
-    }
-  }
-  if (MODE == 1) {
-    const int tot_cnt = wave_sum_i(live ? cnt : 0);
-    if (lane == 0) atomicAdd(g.ctr, (unsigned long long)tot_cnt);
-  }
-}
-
-struct GhostArgs {
-  int64_t n_active;
-  const int32_t *active_idx, *chunk_of;
-  const Chunk *chunks;
-  int32_t *chunk_todo;
-  const float *sums;
-  const int32_t *act_cnt;
-  const float *act_hmax;
-  float *hlo, *hhi;
-  uint8_t *conv;
-  float4 *pos4;
-  float4 *jth;
-  float *h;
-  int last;
-  int from_u;
-  float eta3, kc, tol, gamma, eps, box_quarter, reach;
-  // outputs
-  float *rho, *drho_dh, *f, *divv, *curlx, *curly, *curlz, *P, *c, *B, *A, *u;
-  int32_t *nngb;
-  int32_t *n_unconv, *rebuild;
-  unsigned long long *ctr;  // cumulative density interactions of finished solves
-};
-
-// Newton step on F(h) = h^3 sum_j W(r_ij, h) - eta^3 for each active particle
-// not yet converged; converged (or last-pass) particles get their ghost
-// quantities written.
-__global__ __launch_bounds__(256) void ghost_kernel(GhostArgs g) {
-  int finished = 0;
-  int unconv = 0;
-  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < g.n_active; k += (int64_t)gridDim.x * 256) {
-    if (g.conv[k]) continue;
-    const int i = g.active_idx[k];
-    const float S_w = g.sums[k], S_mw = g.sums[g.n_active + k], S_d = g.sums[2 * g.n_active + k],
-                S_md = g.sums[3 * g.n_active + k];
-    const float h = g.h[i];
-    // Newton in ln h on G = ln(h^3 n / eta^3), with h^3 n = (8/pi)/GK^3 sum w
-    // and dG/dln h = (3 sum w - sum (3w + q w')) / sum w: the same root as
-    // h^3 n = eta^3, reached in one step where the density is locally uniform.
-    const float hn3 = g.kc * S_w;
-    const float G = __logf(hn3 / g.eta3);
-    const float Gp = (3.f * S_w - S_d) / S_w;
-    float lo = g.hlo[k], hi = g.hhi[k];
-    if (G < 0.f) lo = fmaxf(lo, h);
-    if (G > 0.f) hi = fminf(hi, h);
-    float hn = h * __expf(fminf(fmaxf(-G / Gp, -0.6931472f), 0.6931472f));
-    if (!(hn >= lo && hn <= hi) || !(Gp > 0.f)) hn = (hi < INFINITY) ? 0.5f * (lo + hi) : 2.f * h;
-    if (G == 0.f) hn = h;
-    const bool done = fabsf(hn - h) < g.tol * h;
-    if (done || g.last) {
-      const float H = GK32 * h;
-      const float iH = 1.f / H;
-      const float C3 = KNORM32 * iH * iH * iH;
-      const float rho = C3 * S_mw;
-      const float drho = -C3 / h * S_md;
-      const float fg = 1.f / (1.f + h / (3.f * rho) * drho);
-      float P, A, u;
-      const float rg = __powf(rho, g.gamma);
-      if (g.from_u) {
-        u = g.u[i];
-        P = (g.gamma - 1.f) * rho * u;
-        A = P / rg;
-        g.A[i] = A;
-      } else {
-        A = g.A[i];
-        P = A * rg;
-        u = P / ((g.gamma - 1.f) * rho);
-        if (g.u) g.u[i] = u;
-      }
-      const float cs = sqrtf(g.gamma * P / rho);
-      const float C4 = C3 * iH;
-      const float dv = -C4 * g.sums[4 * g.n_active + k] / rho;
-      const float cx = C4 * g.sums[5 * g.n_active + k] / rho;
-      const float cy = C4 * g.sums[6 * g.n_active + k] / rho;
-      const float cz = C4 * g.sums[7 * g.n_active + k] / rho;
-      const float adv = fabsf(dv);
-      const float acu = sqrtf(fmaf(cz, cz, fmaf(cy, cy, cx * cx)));
-      const float Bs = adv > 0.f ? adv / (adv + acu + g.eps * cs / h) : 0.f;
-      g.rho[i] = rho;
-      g.drho_dh[i] = drho;
-      g.f[i] = fg;
-      g.divv[i] = dv;
-      g.curlx[i] = cx;
-      g.curly[i] = cy;
-      g.curlz[i] = cz;
-      g.P[i] = P;
-      g.c[i] = cs;
-      g.B[i] = Bs;
-      if (g.nngb) g.nngb[i] = g.act_cnt[k];
-      g.jth[i] = make_float4(rho, fg * P / (rho * rho), cs, Bs);
-      finished += g.act_cnt[k];
-      g.conv[k] = 1;
-      if (!done) ++unconv;
-    } else {
-      g.hlo[k] = lo;
-      g.hhi[k] = hi;
-      g.h[i] = hn;
-      const float Hn = GK32 * hn;
-      g.pos4[i].w = Hn;
-      g.chunk_todo[g.chunk_of[k]] = 1;
-      ++unconv;
-      const Chunk ch = g.chunks[g.chunk_of[k]];
-      if (Hn > g.act_hmax[ch.act_leaf] * g.reach) atomicOr(g.rebuild, 1);
-      if (Hn > g.box_quarter) atomicOr(g.rebuild, 2);
-    }
-  }
-  finished = wave_sum_i(finished);
-  unconv = wave_sum_i(unconv);
-  if ((threadIdx.x & 63) == 0) {
-    if (finished) atomicAdd(g.ctr, (unsigned long long)finished);
-    if (unconv) atomicAdd(g.n_unconv, unconv);
-  }
+__global__ __launch_bounds__(256) void fill_work_kernel(const int32_t *__restrict__ order, int64_t n,
+                                                        int2 *__restrict__ work) {
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256)
+    work[q] = make_int2(0, order ? order[q] : (int)q);
 }
 
 __global__ __launch_bounds__(256) void pack_jvm_kernel(const double *__restrict__ vx, const double *__restrict__ vy,
@@ -570,35 +53,138 @@ unsigned grid256(int64_t n) {
   return (unsigned)(g < 1 ? 1 : g);
 }
 
+// Chunks in decreasing order of staged partner particles (longest first),
+// by log2 buckets: histogram, bucket offsets, scatter.
+__global__ __launch_bounds__(256) void cost_bucket_kernel(const Chunk *__restrict__ chunks, int64_t n_chunks,
+                                                          const int32_t *__restrict__ act_cost,
+                                                          int32_t *__restrict__ bucket_of,
+                                                          int32_t *__restrict__ hist) {
+  __shared__ int h[32];
+  if (threadIdx.x < 32) h[threadIdx.x] = 0;
+  __syncthreads();
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n_chunks; q += (int64_t)gridDim.x * 256) {
+    const int cost = max(1, act_cost[chunks[q].act_leaf]);
+    const int b = __clz(cost);  // larger cost, smaller bucket
+    bucket_of[q] = b;
+    atomicAdd(&h[b], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < 32 && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ void cost_bucket_scan_kernel(int32_t *hist) {
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int b = 0; b < 32; ++b) {
+      const int v = hist[b];
+      hist[b] = s;
+      s += v;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void cost_scatter_kernel(const int32_t *__restrict__ bucket_of, int64_t n_chunks,
+                                                           int32_t *__restrict__ cursor, int32_t *__restrict__ work) {
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n_chunks; q += (int64_t)gridDim.x * 256)
+    work[atomicAdd(&cursor[bucket_of[q]], 1)] = (int32_t)q;
+}
+
+// Workgroups of a persistent launch: every CU filled to the occupancy its
+// LDS allows (bytes per wave of the force variant, the larger of the two).
+int persistent_grid_for(int n_cu, const LoopConfig &c) {
+  static const int wave_bytes[5] = {6656, 13312, 23040, 36864, 65536};
+  int per_cu = 163840 / (c.nw * wave_bytes[c.tile]);
+  if (per_cu < 1) per_cu = 1;
+  if (per_cu * c.nw > 32) per_cu = 32 / c.nw;
+  return n_cu * per_cu;
+}
+
+unsigned grid_for_items(int64_t n) {
+  int64_t g = ceil_div(n, 256);
+  if (g > 4096) g = 4096;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+// The configuration for a pass: a tuned entry for this number of chunks if
+// one exists, else a rule that keeps enough waves in flight.
+LoopConfig choose_config(sph_ctx *ctx, int mode) {
+  const int cls = tune_class(ctx->n_chunks);
+  const auto &t = ctx->tune[mode][cls];
+  LoopConfig c;
+  if (t.valid) {
+    c.nw = t.nw;
+    c.tile = t.tile;
+    c.ordered = t.ordered;
+    c.persistent = t.persistent;
+    return c;
+  }
+  if (ctx->prm.waves_per_chunk > 0) {
+    c.nw = ctx->prm.waves_per_chunk;
+    c.tile = c.nw >= 4 ? 1 : 2;
+    const int cap = ctx->prm.cand_cap, lcap = ctx->prm.list_cap;
+    if (c.nw == 1) c.tile = cap <= 128 && lcap <= 32 ? 0 : cap <= 256 && lcap <= 64 ? 1 : cap <= 512 && lcap <= 96 ? 2 : cap <= 1024 && lcap <= 128 ? 3 : 4;
+    if (c.nw == 2) c.tile = cap <= 128 && lcap <= 32 ? 0 : cap <= 256 && lcap <= 64 ? 1 : 2;
+    if (c.nw >= 4) c.tile = cap <= 128 && lcap <= 32 ? 0 : 1;
+    return c;
+  }
+  const int64_t nc = ctx->n_chunks;
+  if (nc < 2048) {
+    c.nw = 8, c.tile = 0, c.ordered = 1;
+  } else if (nc < 8192) {
+    c.nw = 4, c.tile = 1, c.ordered = 1;
+  } else if (nc < 32768) {
+    c.nw = 2, c.tile = 2;
+  } else {
+    c.nw = 1, c.tile = 2;
+  }
+  return c;
+}
+
+sph_status order_chunks_by_cost(sph_ctx *ctx) {
+  const int64_t nc = ctx->n_chunks;
+  SPH_TRY(sph_ensure(ctx, ctx->work, 4 * (size_t)(nc > 0 ? nc : 1)));
+  SPH_TRY(sph_ensure(ctx, ctx->work_tmp, 4 * (size_t)(nc > 0 ? nc : 1) + 256));
+  int32_t *bucket_of = (int32_t *)ctx->work_tmp.p + 64;
+  int32_t *hist = (int32_t *)ctx->work_tmp.p;
+  HIP_TRY(ctx, hipMemsetAsync(hist, 0, 32 * sizeof(int32_t), ctx->stream));
+  PROF(ctx, "cost_order");
+  cost_bucket_kernel<<<grid_for_items(nc), 256, 0, ctx->stream>>>((const Chunk *)ctx->chunks.p, nc,
+                                                                 (const int32_t *)ctx->act_cost.p, bucket_of, hist);
+  cost_bucket_scan_kernel<<<1, 64, 0, ctx->stream>>>(hist);
+  cost_scatter_kernel<<<grid_for_items(nc), 256, 0, ctx->stream>>>(bucket_of, nc, hist, (int32_t *)ctx->work.p);
+  return sph_hip_check(ctx, hipGetLastError(), "cost order");
+}
+
 template <int MODE, bool COMP>
-sph_status launch_loop(sph_ctx *ctx, const LoopArgs &a) {
-  const int64_t per = ceil_div(a.n_chunks, 8);
-  const unsigned grid = (unsigned)(8 * (per > 0 ? per : 1));
-  LoopArgs g = a;
-  g.per_xcd = per;
-  const int cap = ctx->prm.cand_cap, lcap = ctx->prm.list_cap;
-  // waves per chunk: enough waves in flight when few chunks are active
-  int nw = ctx->prm.waves_per_chunk;
-  if (nw <= 0) {
-    nw = 1;
-    while (nw < 8 && a.n_chunks * nw < 16384) nw <<= 1;
+sph_status launch_loop(sph_ctx *ctx, const LoopArgs &a0) {
+  const LoopConfig cfg = choose_config(ctx, MODE);
+  LoopArgs a = a0;
+  if (cfg.ordered) {
+    if (!ctx->work_valid) {
+      SPH_TRY(order_chunks_by_cost(ctx));
+      ctx->work_valid = 1;
+    }
+    a.work = (const int32_t *)ctx->work.p;
+    a.n_items = ctx->n_chunks;
   }
   PROF(ctx, MODE == 0 ? "density_loop" : "force_loop");
-  if (nw >= 8)
-    loop_kernel<MODE, 256, 64, COMP, 8><<<grid, 512, 0, ctx->stream>>>(g);
-  else if (nw >= 4)
-    loop_kernel<MODE, 256, 64, COMP, 4><<<grid, 256, 0, ctx->stream>>>(g);
-  else if (nw >= 2)
-    loop_kernel<MODE, 512, 96, COMP, 2><<<grid, 128, 0, ctx->stream>>>(g);
-  else if (cap <= 256 && lcap <= 64)
-    loop_kernel<MODE, 256, 64, COMP, 1><<<grid, 64, 0, ctx->stream>>>(g);
-  else if (cap <= 512 && lcap <= 96)
-    loop_kernel<MODE, 512, 96, COMP, 1><<<grid, 64, 0, ctx->stream>>>(g);
-  else if (cap <= 1024 && lcap <= 128)
-    loop_kernel<MODE, 1024, 128, COMP, 1><<<grid, 64, 0, ctx->stream>>>(g);
-  else
-    loop_kernel<MODE, 2048, 192, COMP, 1><<<grid, 64, 0, ctx->stream>>>(g);
-  return sph_hip_check(ctx, hipGetLastError(), MODE == 0 ? "density loop" : "force loop");
+  if (cfg.persistent) {
+    // one box through the persistent kernel: a device copy of the arguments
+    // and a (0, chunk) work list
+    SPH_TRY(sph_ensure(ctx, ctx->box_args, sizeof(LoopArgs)));
+    SPH_TRY(sph_ensure(ctx, ctx->box_work, sizeof(int2) * (size_t)(ctx->n_chunks > 0 ? ctx->n_chunks : 1)));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->box_args.p, &a, sizeof(LoopArgs), hipMemcpyHostToDevice, ctx->stream));
+    fill_work_kernel<<<grid_for_items(ctx->n_chunks), 256, 0, ctx->stream>>>(
+        cfg.ordered ? (const int32_t *)ctx->work.p : nullptr, ctx->n_chunks, (int2 *)ctx->box_work.p);
+    HIP_TRY(ctx, hipGetLastError());
+    return sph_hip_check(ctx,
+                         launch_loop_any<MODE, COMP>(ctx->stream, a, cfg, (const LoopArgs *)ctx->box_args.p,
+                                                     (const int2 *)ctx->box_work.p, (int)ctx->n_chunks,
+                                                     (int *)ctx->scalars.p + SC_WORKCTR, persistent_grid_for(ctx->n_cu, cfg)),
+                         MODE == 0 ? "density loop" : "force loop");
+  }
+  return sph_hip_check(ctx, launch_loop_any<MODE, COMP>(ctx->stream, a, cfg, nullptr, nullptr, 0, nullptr, 0),
+                       MODE == 0 ? "density loop" : "force loop");
 }
 
 LoopArgs base_args(sph_ctx *ctx) {
@@ -757,10 +343,13 @@ sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u)
     if (st[1] & 1) {
       // a smoothing length outgrew its cell's pair reach: widen the pair lists
       ctx->pair_rebuilds++;
-      SPH_TRY(refresh_leaf_hmax(ctx));
+      SPH_TRY(refresh_leaf_hmax(ctx, false));
       SPH_TRY(build_pairs(ctx, 0, 1.5f));
     }
   }
+  // leaf max H follows the new smoothing lengths, so that any later cell-pair
+  // list (the force list, or a later active set without a rebuild) sees them
+  SPH_TRY(refresh_leaf_hmax(ctx, true));
   ctx->state = 4;
   if (ctx->n_unconverged > 0)
     return sph_fail(ctx, SPH_ENOCONV, "density_pass: %lld particles not converged after %d iterations",
@@ -778,7 +367,6 @@ sph_status force_pass_impl(sph_ctx *ctx, sph_particles *p) {
     return SPH_OK;
   }
   (void)n;
-  SPH_TRY(refresh_leaf_hmax(ctx));
   SPH_TRY(build_pairs(ctx, 1, 1.0f));
   fill_i32_kernel<<<grid256(ctx->n_chunks), 256, 0, ctx->stream>>>((int32_t *)ctx->chunk_todo.p, ctx->n_chunks, 1);
   HIP_TRY(ctx, hipGetLastError());
@@ -799,4 +387,155 @@ sph_status force_pass_impl(sph_ctx *ctx, sph_particles *p) {
     SPH_TRY((launch_loop<1, false>(ctx, a)));
   ctx->state = 5;
   return SPH_OK;
+}
+
+// ---------------------------------------------------------------- autotuner
+
+namespace {
+
+struct TimedLaunch {
+  LoopConfig cfg;
+  float ms;
+};
+
+template <int MODE>
+sph_status time_config(sph_ctx *ctx, const LoopArgs &a0, const LoopConfig &cfg, int reps, float *ms_out) {
+  hipEvent_t e0, e1;
+  HIP_TRY(ctx, hipEventCreate(&e0));
+  HIP_TRY(ctx, hipEventCreate(&e1));
+  float best = INFINITY;
+  for (int r = 0; r <= reps; ++r) {
+    fill_i32_kernel<<<grid256(ctx->n_chunks), 256, 0, ctx->stream>>>((int32_t *)ctx->chunk_todo.p, ctx->n_chunks, 1);
+    LoopArgs a = a0;
+    if (cfg.ordered) {
+      a.work = (const int32_t *)ctx->work.p;
+      a.n_items = ctx->n_chunks;
+    }
+    HIP_TRY(ctx, hipEventRecord(e0, ctx->stream));
+    hipError_t err;
+    if (cfg.persistent) {
+      HIP_TRY(ctx, hipMemcpyAsync(ctx->box_args.p, &a, sizeof(LoopArgs), hipMemcpyHostToDevice, ctx->stream));
+      fill_work_kernel<<<grid_for_items(ctx->n_chunks), 256, 0, ctx->stream>>>(
+          cfg.ordered ? (const int32_t *)ctx->work.p : nullptr, ctx->n_chunks, (int2 *)ctx->box_work.p);
+      err = launch_loop_any<MODE, true>(ctx->stream, a, cfg, (const LoopArgs *)ctx->box_args.p,
+                                        (const int2 *)ctx->box_work.p, (int)ctx->n_chunks,
+                                        (int *)ctx->scalars.p + SC_WORKCTR, persistent_grid_for(ctx->n_cu, cfg));
+    } else {
+      err = launch_loop_any<MODE, true>(ctx->stream, a, cfg, nullptr, nullptr, 0, nullptr, 0);
+    }
+    HIP_TRY(ctx, err);
+    HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
+    HIP_TRY(ctx, hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_TRY(ctx, hipEventElapsedTime(&ms, e0, e1));
+    if (r > 0 && ms < best) best = ms;  // the first launch warms caches
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms_out = best;
+  return SPH_OK;
+}
+
+}  // namespace
+
+extern "C" sph_status sph_autotune(sph_ctx *ctx, sph_particles *p, const char *path) {
+  if (!ctx || !p) return SPH_EINVAL;
+  if (ctx->state < 5) return sph_fail(ctx, SPH_ESTATE, "autotune: run a force pass first");
+  if (ctx->n_chunks == 0) return SPH_OK;
+  const int cls = tune_class(ctx->n_chunks);
+  SPH_TRY(order_chunks_by_cost(ctx));
+  ctx->work_valid = 1;
+  SPH_TRY(sph_ensure(ctx, ctx->box_args, sizeof(LoopArgs)));
+  SPH_TRY(sph_ensure(ctx, ctx->box_work, sizeof(int2) * (size_t)ctx->n_chunks));
+  const int prof = ctx->prof;
+  ctx->prof = 0;
+  FILE *f = path ? fopen(path, "a") : nullptr;
+  for (int mode = 0; mode < 2; ++mode) {
+    LoopArgs a = base_args(ctx);
+    if (mode == 0) {
+      a.pair_off = (const int32_t *)ctx->dpair_off.p;
+      a.pairs = (const PairEntry *)ctx->dpairs.p;
+      a.sums = (float *)ctx->sums.p;
+      a.act_cnt = (int32_t *)ctx->sums.p + 8 * ctx->n_active;
+    } else {
+      a.pair_off = (const int32_t *)ctx->fpair_off.p;
+      a.pairs = (const PairEntry *)ctx->fpairs.p;
+      a.ax_out = p->ax;
+      a.ay_out = p->ay;
+      a.az_out = p->az;
+      a.dA_out = p->dA_dt;
+      a.du_out = p->du_dt;
+      a.vsig_out = p->vsig;
+      a.nngb_out = p->nngb_force;
+      // counts of tuning launches are not interactions of a step
+      a.ctr = (unsigned long long *)ctx->work_tmp.p;
+    }
+    sph_ctx::TuneEntry best;
+    best.ms = INFINITY;
+    const int nws[4] = {1, 2, 4, 8};
+    for (int wi = 0; wi < 4; ++wi)
+      for (int tile = 0; tile <= 4; ++tile)
+        for (int ordered = 0; ordered <= 1; ++ordered)
+          for (int pers = 0; pers <= 1; ++pers) {
+            LoopConfig c;
+            c.nw = nws[wi];
+            c.tile = tile;
+            c.ordered = ordered;
+            c.persistent = pers;
+            if (!loop_config_valid(c)) continue;
+            float ms = 0.f;
+            if (mode == 0)
+              SPH_TRY(time_config<0>(ctx, a, c, 2, &ms));
+            else
+              SPH_TRY(time_config<1>(ctx, a, c, 2, &ms));
+            if (f)
+              fprintf(f, "candidate %d %d %d %d %d %d %.6f %lld\n", mode, cls, c.nw, c.tile, c.ordered, c.persistent,
+                      ms, (long long)ctx->n_chunks);
+            if (ms < best.ms) {
+              best.valid = 1;
+              best.nw = c.nw;
+              best.tile = c.tile;
+              best.ordered = c.ordered;
+              best.persistent = c.persistent;
+              best.ms = ms;
+            }
+          }
+    ctx->tune[mode][cls] = best;
+    if (f)
+      fprintf(f, "best %d %d %d %d %d %d %.6f %lld\n", mode, cls, best.nw, best.tile, best.ordered, best.persistent,
+              best.ms, (long long)ctx->n_chunks);
+  }
+  if (f) fclose(f);
+  ctx->prof = prof;
+  // leave every chunk marked done, as after a completed pass
+  HIP_TRY(ctx, hipMemsetAsync(ctx->chunk_todo.p, 0, 4 * (size_t)ctx->n_chunks, ctx->stream));
+  return sph_sync(ctx);
+}
+
+extern "C" sph_status sph_load_tuning(sph_ctx *ctx, const char *path) {
+  if (!ctx || !path) return SPH_EINVAL;
+  FILE *f = fopen(path, "r");
+  if (!f) return sph_fail(ctx, SPH_EINVAL, "load_tuning: cannot open %s", path);
+  char tag[32];
+  int mode, cls, nw, tile, ord, pers;
+  float ms;
+  long long nc;
+  int loaded = 0;
+  while (fscanf(f, "%31s %d %d %d %d %d %d %f %lld", tag, &mode, &cls, &nw, &tile, &ord, &pers, &ms, &nc) == 9) {
+    if (strcmp(tag, "best") != 0 || mode < 0 || mode > 1 || cls < 0 || cls > 31) continue;
+    LoopConfig c;
+    c.nw = nw;
+    c.tile = tile;
+    if (!loop_config_valid(c)) continue;
+    auto &t = ctx->tune[mode][cls];
+    t.valid = 1;
+    t.nw = nw;
+    t.tile = tile;
+    t.ordered = ord != 0;
+    t.persistent = pers != 0;
+    t.ms = ms;
+    ++loaded;
+  }
+  fclose(f);
+  return loaded > 0 ? SPH_OK : sph_fail(ctx, SPH_EINVAL, "load_tuning: no entries in %s", path);
 }

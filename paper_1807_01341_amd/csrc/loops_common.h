@@ -1,0 +1,663 @@
+// Shared pieces of the neighbour loops (Sec. III-A, Fig. 5): the per-chunk
+// body of the density and force loops, its grid and persistent launches, and
+// the ghost's Newton step.  Included by the single-box passes, the batched
+// multi-box passes and the autotuner.
+//
+// Work item: one chunk of up to 64 active particles of one leaf (gather
+// formulation: each active particle's sums are produced by the single
+// workgroup that owns it, in a fixed order, so there are no atomics and the
+// results are reproducible).  For every partner leaf of the chunk's cell-pair
+// list:
+//   1. staging: the partner's particles are read 64 at a time (coalesced
+//      loads, in the per-cell axis-sort order when the pair is not a self
+//      pair so that the sweep stops once the projections leave the chunk's
+//      reach), moved into the chunk leaf's frame with the FP32 pair shift, and
+//      kept if they are within reach of the chunk's bounding box (wave ballot
+//      + rank into an LDS candidate array);
+//   2. filter: every lane tests its own particle against each candidate with
+//      the FP32 predicate and appends hits to its own LDS neighbour list;
+//   3. interact: every lane walks its own list (lanes have near-equal
+//      neighbour counts because h adapts) and accumulates in registers.
+// No MFMA: pair interactions are not a dense contraction.
+#pragma once
+
+#include <math.h>
+#include <string.h>
+
+#include "sph_internal.h"
+
+
+struct AxisTab {
+  float e[13][3];
+};
+
+AxisTab host_axes() {
+  AxisTab a;
+  int k = 0;
+  for (int dx = -1; dx <= 1; ++dx)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dz = -1; dz <= 1; ++dz) {
+        const int first = dx != 0 ? dx : (dy != 0 ? dy : dz);
+        if (first <= 0) continue;
+        const double nrm = sqrt((double)(dx * dx + dy * dy + dz * dz));
+        a.e[k][0] = (float)(dx / nrm);
+        a.e[k][1] = (float)(dy / nrm);
+        a.e[k][2] = (float)(dz / nrm);
+        ++k;
+      }
+  return a;
+}
+
+struct LoopArgs {
+  const Chunk *chunks;
+  int32_t *chunk_todo;
+  int64_t n_chunks;
+  int64_t per_xcd;
+  const int32_t *work;  // optional cost-ordered chunk list (grid kernel)
+  int64_t n_items;      // grid items: chunks, or entries of `work`
+  const int32_t *active_idx;
+  const float4 *pos4;  // (ox, oy, oz, H)
+  const float4 *jvm;   // (vx, vy, vz, m)
+  const float4 *jth;   // (rho, f P / rho^2, c, B)  force only
+  const int32_t *leaf_begin, *leaf_count;
+  const float *leaf_hmax;
+  const int32_t *pair_off;
+  const PairEntry *pairs;
+  const uint16_t *axis_order;
+  int64_t n;
+  AxisTab ax;
+  // density outputs: per active index
+  float *sums;
+  int32_t *act_cnt;
+  int64_t n_active;
+  // force outputs: per particle
+  float *ax_out, *ay_out, *az_out, *dA_out, *du_out, *vsig_out;
+  int32_t *nngb_out;
+  float half_alpha, gm1;
+  unsigned long long *ctr;  // cumulative force interactions
+};
+
+__device__ __forceinline__ void kernel_w_dw(float q, float &w, float &wp) {
+  // w = 1 - 6q^2 + 6q^3, w' = -12q + 18q^2 on [0, 1/2); 2(1-q)^3, -6(1-q)^2 on [1/2, 1)
+  const float wi = fmaf(q * q, fmaf(6.f, q, -6.f), 1.f);
+  const float wpi = q * fmaf(18.f, q, -12.f);
+  const float t = 1.f - q;
+  const float t2 = t * t;
+  const float wo = 2.f * t2 * t;
+  const float wpo = -6.f * t2;
+  const bool in = q < 0.5f;
+  w = in ? wi : wo;
+  wp = in ? wpi : wpo;
+}
+
+__device__ __forceinline__ float kernel_dw_only(float q) {
+  const float wpi = q * fmaf(18.f, q, -12.f);
+  const float t = 1.f - q;
+  const float wpo = -6.f * t * t;
+  return q < 0.5f ? wpi : (q < 1.f ? wpo : 0.f);
+}
+
+struct Neu {  // compensated running sum
+  float s = 0.f, c = 0.f;
+  __device__ __forceinline__ void add(float b) {
+    const float t = s + b;
+    if (fabsf(s) >= fabsf(b))
+      c += (s - t) + b;
+    else
+      c += (b - t) + s;
+    s = t;
+  }
+  __device__ __forceinline__ float value() const { return s + c; }
+};
+
+struct Kahan {  // per-term compensated accumulator
+  float s = 0.f, c = 0.f;
+  __device__ __forceinline__ void add(float b) {
+    const float y = b - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+  }
+};
+
+// Orders this wave's LDS accesses across its lanes (each wave owns its own
+// LDS region, so no workgroup barrier is needed between its phases).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Bytes of LDS one wave of the loop kernel uses.
+template <int MODE, int CAP, int LCAP>
+struct WaveLds {
+  static constexpr int cand = CAP * 16;
+  static constexpr int candH = MODE == 1 ? CAP * 4 : 0;
+  static constexpr int lists = LCAP * 64 * 2;
+  static constexpr int bytes = cand + candH + lists;
+  static_assert(bytes >= 10 * 64 * 4, "room for the cross-wave reduction");
+};
+
+// One chunk of up to 64 active particles of one leaf.  MODE 0: density loop;
+// MODE 1: force loop.  NW waves share the chunk: wave w takes the partner
+// cells w, w+NW, ... of the chunk's pair list, and the per-lane partial sums
+// are combined across waves in wave order at the end.  `lds` holds NW wave
+// regions of WaveLds::bytes each.
+template <int MODE, int CAP, int LCAP, bool COMP, int NW>
+__device__ __forceinline__ void chunk_body(const LoopArgs &g, int cid, char *lds) {
+  using W = WaveLds<MODE, CAP, LCAP>;
+  constexpr int FB = LCAP / 2 < 64 ? LCAP / 2 : 64;  // candidates filtered between list checks
+  if (!g.chunk_todo[cid]) return;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  char *mine = lds + wave * W::bytes;
+  float4 *cand = reinterpret_cast<float4 *>(mine);
+  float *candH = reinterpret_cast<float *>(mine + W::cand);
+  uint16_t *lists = reinterpret_cast<uint16_t *>(mine + W::cand + W::candH);
+  const Chunk ch = g.chunks[cid];
+  const bool live = lane < ch.count;
+  const int k = ch.begin + lane;
+  const int i = live ? g.active_idx[k] : -1;
+  const float4 pi = live ? g.pos4[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+  const float Hi = pi.w;
+  const float H2i = live ? Hi * Hi : -1.f;
+  const float invHi = live ? 1.f / Hi : 0.f;
+  const float4 vi = live ? g.jvm[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+  float4 thi = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (MODE == 1 && live) thi = g.jth[i];
+
+  // chunk bounding box and reach
+  const float bminx = wave_min_f(live ? pi.x : INFINITY), bmaxx = wave_max_f(live ? pi.x : -INFINITY);
+  const float bminy = wave_min_f(live ? pi.y : INFINITY), bmaxy = wave_max_f(live ? pi.y : -INFINITY);
+  const float bminz = wave_min_f(live ? pi.z : INFINITY), bmaxz = wave_max_f(live ? pi.z : -INFINITY);
+  const float Rc = wave_max_f(live ? Hi : 0.f);
+  const float R2c = Rc * Rc;
+
+  // accumulators: density (w, m w, 3w+qw', m(3w+qw'), div, curl x3); force (a x3, visc, adiab)
+  float acc[9];
+  Neu tot[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) acc[q] = 0.f;
+  Kahan ka[3];
+  float vmax = 0.f;
+  int cnt = 0;
+  int len = 0;
+  int ncand = 0;
+
+  auto interact = [&]() {
+    const int maxlen = wave_max_i(len);
+    for (int t = 0; t < maxlen; ++t) {
+      if (t < len) {
+        const int c = lists[t * 64 + lane];
+        const float4 cj = cand[c];
+        const int j = __float_as_int(cj.w);
+        const float dx = pi.x - cj.x, dy = pi.y - cj.y, dz = pi.z - cj.z;
+        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        const float4 vj = g.jvm[j];
+        const float rinv = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
+        const float r = r2 * rinv;
+        const float vx = vi.x - vj.x, vy = vi.y - vj.y, vz = vi.z - vj.z;
+        const float vr = fmaf(vz, dz, fmaf(vy, dy, vx * dx));
+        const float mj = vj.w;
+        if (MODE == 0) {
+          float w, wp;
+          const float q = r * invHi;
+          kernel_w_dw(q, w, wp);
+          const float d3 = fmaf(q, wp, 3.f * w);
+          acc[0] += w;
+          acc[1] = fmaf(mj, w, acc[1]);
+          acc[2] += d3;
+          acc[3] = fmaf(mj, d3, acc[3]);
+          const float fac = mj * wp * rinv;
+          acc[4] = fmaf(fac, vr, acc[4]);
+          acc[5] = fmaf(fac, fmaf(vy, dz, -vz * dy), acc[5]);
+          acc[6] = fmaf(fac, fmaf(vz, dx, -vx * dz), acc[6]);
+          acc[7] = fmaf(fac, fmaf(vx, dy, -vy * dx), acc[7]);
+          cnt += (j != i);
+        } else {
+          const float Hj = candH[c];
+          const float invHj = __builtin_amdgcn_rcpf(Hj);
+          const float4 th = g.jth[j];
+          const float wpi = kernel_dw_only(r * invHi);
+          const float wpj = kernel_dw_only(r * invHj);
+          const float ih2 = invHj * invHj;
+          const float Fi = (KNORM32 * invHi * invHi * invHi * invHi) * wpi * rinv;
+          const float Fj = KNORM32 * (ih2 * ih2) * wpj * rinv;
+          const float mu = fminf(vr * rinv, 0.f);
+          const float vsig = thi.z + th.z - 3.f * mu;
+          vmax = fmaxf(vmax, vsig);
+          const float Pi = -g.half_alpha * vsig * mu * (thi.w + th.w) * __builtin_amdgcn_rcpf(thi.x + th.x);
+          const float gbar = 0.5f * (Fi + Fj);
+          const float coef = mj * fmaf(thi.y, Fi, fmaf(th.y, Fj, Pi * gbar));
+          if (COMP) {
+            ka[0].add(-coef * dx);
+            ka[1].add(-coef * dy);
+            ka[2].add(-coef * dz);
+          } else {
+            acc[0] = fmaf(-coef, dx, acc[0]);
+            acc[1] = fmaf(-coef, dy, acc[1]);
+            acc[2] = fmaf(-coef, dz, acc[2]);
+          }
+          acc[3] = fmaf(mj * Pi * vr, gbar, acc[3]);
+          acc[4] = fmaf(mj * vr, Fi, acc[4]);
+          ++cnt;
+        }
+      }
+    }
+    // fold the batch into the compensated totals
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      if (COMP)
+        tot[q].add(acc[q]);
+      else
+        tot[q].s += acc[q];
+      acc[q] = 0.f;
+    }
+    len = 0;
+  };
+
+  auto flush = [&]() {
+    wave_sync();
+    for (int b0 = 0; b0 < ncand; b0 += FB) {
+      if (wave_max_i(len) > LCAP - FB) interact();
+      const int bend = min(ncand, b0 + FB);
+      for (int c = b0; c < bend; ++c) {
+        const float4 cj = cand[c];
+        const float dx = pi.x - cj.x, dy = pi.y - cj.y, dz = pi.z - cj.z;
+        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        bool hit;
+        if (MODE == 0) {
+          hit = r2 < H2i;
+        } else {
+          const float Hj = candH[c];
+          hit = live && (r2 < H2i || r2 < Hj * Hj) && __float_as_int(cj.w) != i;
+        }
+        if (hit) {
+          lists[len * 64 + lane] = (uint16_t)c;
+          ++len;
+        }
+      }
+    }
+    interact();
+    ncand = 0;
+    wave_sync();
+  };
+
+  const int pbeg = g.pair_off[ch.act_leaf], pend = g.pair_off[ch.act_leaf + 1];
+  for (int pp = pbeg + wave; pp < pend; pp += NW) {
+    const PairEntry e = g.pairs[pp];
+    const int B = e.b;
+    const int bb = g.leaf_begin[B], bc = g.leaf_count[B];
+    const bool selfp = (B == ch.leaf);
+    const float Rb = MODE == 0 ? Rc : fmaxf(Rc, g.leaf_hmax[B]);
+    // sweep axis: the stencil direction closest to the pair offset
+    int axis = 0;
+    float best = -1.f, sgn = 1.f;
+    if (!selfp) {
+#pragma unroll
+      for (int a = 0; a < 13; ++a) {
+        const float d = fmaf(e.sz, g.ax.e[a][2], fmaf(e.sy, g.ax.e[a][1], e.sx * g.ax.e[a][0]));
+        if (fabsf(d) > best) {
+          best = fabsf(d);
+          axis = a;
+          sgn = d >= 0.f ? 1.f : -1.f;
+        }
+      }
+    }
+    const float ex = g.ax.e[axis][0], ey = g.ax.e[axis][1], ez = g.ax.e[axis][2];
+    // reach of the chunk box along the axis, in the partner leaf's frame
+    const float pmin = fminf(ex * bminx, ex * bmaxx) + fminf(ey * bminy, ey * bmaxy) + fminf(ez * bminz, ez * bmaxz);
+    const float pmax = fmaxf(ex * bminx, ex * bmaxx) + fmaxf(ey * bminy, ey * bmaxy) + fmaxf(ez * bminz, ez * bmaxz);
+    const float sproj = fmaf(e.sz, ez, fmaf(e.sy, ey, e.sx * ex));
+    const float margin = 1.0001f * Rb + 1e-6f * (fabsf(pmin) + fabsf(pmax) + fabsf(sproj));
+    const float lo_b = pmin - margin - sproj, hi_b = pmax + margin - sproj;
+    const uint16_t *ord = g.axis_order + (int64_t)axis * g.n + bb;
+    for (int t = 0; t < bc; t += 64) {
+      const int kk = t + lane;
+      const bool valid = kk < bc;
+      int j = bb;
+      if (valid) j = selfp ? bb + kk : bb + (int)ord[sgn > 0.f ? kk : bc - 1 - kk];
+      const float4 pj = valid ? g.pos4[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+      if (!selfp) {
+        const float key = fmaf(pj.z, ez, fmaf(pj.y, ey, pj.x * ex));
+        const bool beyond = sgn > 0.f ? key > hi_b : key < lo_b;
+        if (__ballot(valid && !beyond) == 0ull) break;
+      }
+      const float xj = pj.x + e.sx, yj = pj.y + e.sy, zj = pj.z + e.sz;
+      const float gx = fmaxf(fmaxf(bminx - xj, xj - bmaxx), 0.f);
+      const float gy = fmaxf(fmaxf(bminy - yj, yj - bmaxy), 0.f);
+      const float gz = fmaxf(fmaxf(bminz - zj, zj - bmaxz), 0.f);
+      const float d2 = fmaf(gz, gz, fmaf(gy, gy, gx * gx));
+      bool keep;
+      if (MODE == 0)
+        keep = valid && d2 < R2c;
+      else
+        keep = valid && (d2 < R2c || d2 < pj.w * pj.w);
+      const uint64_t mask = __ballot(keep);
+      if (keep) {
+        const int slot = ncand + rank_below(mask);
+        cand[slot] = make_float4(xj, yj, zj, __int_as_float(j));
+        if (MODE == 1) candH[slot] = pj.w;
+      }
+      ncand += __popcll(mask);
+      if (ncand > CAP - 64) flush();
+    }
+  }
+  flush();
+
+  // per-lane results of this wave
+  float res[9];
+  if (MODE == 0) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) res[q] = tot[q].value();
+    res[8] = 0.f;
+  } else {
+    if (COMP) {
+      res[0] = ka[0].s - ka[0].c + tot[0].value();
+      res[1] = ka[1].s - ka[1].c + tot[1].value();
+      res[2] = ka[2].s - ka[2].c + tot[2].value();
+    } else {
+      res[0] = tot[0].value();
+      res[1] = tot[1].value();
+      res[2] = tot[2].value();
+    }
+    res[3] = tot[3].value();
+    res[4] = tot[4].value();
+    res[5] = vmax;
+    res[6] = res[7] = res[8] = 0.f;
+  }
+  if (NW > 1) {
+    // combine the waves' partial sums in wave order through LDS
+    __syncthreads();
+    float *red = reinterpret_cast<float *>(mine);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) red[q * 64 + lane] = res[q];
+    red[9 * 64 + lane] = __int_as_float(cnt);
+    __syncthreads();
+    if (wave != 0) return;
+    Neu sum[9];
+    int csum = 0;
+    float vm = 0.f;
+    for (int w = 0; w < NW; ++w) {
+      const float *rw = reinterpret_cast<const float *>(lds + w * W::bytes);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        if (MODE == 1 && q == 5)
+          vm = fmaxf(vm, rw[q * 64 + lane]);
+        else if (COMP)
+          sum[q].add(rw[q * 64 + lane]);
+        else
+          sum[q].s += rw[q * 64 + lane];
+      }
+      csum += __float_as_int(rw[9 * 64 + lane]);
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) res[q] = sum[q].value();
+    res[5] = MODE == 1 ? vm : res[5];
+    cnt = csum;
+  }
+  if (lane == 0) g.chunk_todo[cid] = 0;
+
+  if (live) {
+    if (MODE == 0) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) g.sums[(int64_t)q * g.n_active + k] = res[q];
+      g.act_cnt[k] = cnt;
+    } else {
+      g.ax_out[i] = res[0];
+      g.ay_out[i] = res[1];
+      g.az_out[i] = res[2];
+      const float visc = res[3];
+      const float adiab = res[4];
+      const float rho = thi.x;
+      g.dA_out[i] = 0.5f * g.gm1 * __powf(rho, -g.gm1) * visc;
+      g.du_out[i] = fmaf(thi.y, adiab, 0.5f * visc);
+      g.vsig_out[i] = res[5];
+      if (g.nngb_out) g.nngb_out[i] = cnt;
+    }
+  }
+  if (MODE == 1) {
+    const int tot_cnt = wave_sum_i(live ? cnt : 0);
+    if (lane == 0) atomicAdd(g.ctr, (unsigned long long)tot_cnt);
+  }
+}
+
+
+// One workgroup per work item: items are chunk ids (or indices into a
+// cost-ordered work list).  Without a work list, consecutive chunks (Morton
+// neighbours) go to the same XCD so that their shared partner cells are
+// re-read from that XCD's L2.
+template <int MODE, int CAP, int LCAP, bool COMP, int NW>
+__global__ __launch_bounds__(64 * NW) void loop_grid_kernel(LoopArgs g) {
+  __shared__ __align__(16) char lds[NW * WaveLds<MODE, CAP, LCAP>::bytes];
+  int item;
+  if (g.work) {
+    item = blockIdx.x;
+  } else {
+    const int64_t b = blockIdx.x;
+    const int64_t c = (b & 7) * g.per_xcd + (b >> 3);
+    item = (int)c;
+  }
+  if (item >= g.n_items) return;
+  const int cid = g.work ? g.work[item] : item;
+  chunk_body<MODE, CAP, LCAP, COMP, NW>(g, cid, lds);
+}
+
+// Persistent variant: a grid sized to the machine pulls work items (box,
+// chunk) from one atomic counter until the list is exhausted; every
+// workgroup exits once the counter passes the end.
+template <int MODE, int CAP, int LCAP, bool COMP, int NW>
+__global__ __launch_bounds__(64 * NW) void loop_persistent_kernel(const LoopArgs *__restrict__ boxes,
+                                                                  const int2 *__restrict__ work, int n_items,
+                                                                  int *__restrict__ counter) {
+  __shared__ __align__(16) char lds[NW * WaveLds<MODE, CAP, LCAP>::bytes];
+  __shared__ int item_s;
+  for (;;) {
+    if (threadIdx.x == 0) item_s = atomicAdd(counter, 1);
+    __syncthreads();
+    const int item = item_s;
+    __syncthreads();
+    if (item >= n_items) break;
+    const int2 w = work[item];
+    chunk_body<MODE, CAP, LCAP, COMP, NW>(boxes[w.x], w.y, lds);
+    __syncthreads();
+  }
+}
+
+// Multi-box grid variant: one workgroup per (box, chunk) work item.
+template <int MODE, int CAP, int LCAP, bool COMP, int NW>
+__global__ __launch_bounds__(64 * NW) void loop_multi_kernel(const LoopArgs *__restrict__ boxes,
+                                                             const int2 *__restrict__ work, int n_items) {
+  __shared__ __align__(16) char lds[NW * WaveLds<MODE, CAP, LCAP>::bytes];
+  const int item = blockIdx.x;
+  if (item >= n_items) return;
+  const int2 w = work[item];
+  chunk_body<MODE, CAP, LCAP, COMP, NW>(boxes[w.x], w.y, lds);
+}
+
+// Loop tiling: waves per chunk, tile class (candidate slots / list slots per
+// lane), work order and launch style.  Tile classes: 0 = 128/32, 1 = 256/64,
+// 2 = 512/96, 3 = 1024/128, 4 = 2048/192.
+struct LoopConfig {
+  int nw = 1;
+  int tile = 2;
+  int ordered = 0;     // 1: chunks in decreasing cost order, 0: Morton order
+  int persistent = 0;  // 1: persistent grid with an atomic work counter
+};
+
+inline bool loop_config_valid(const LoopConfig &c) {
+  switch (c.nw) {
+    case 1: return c.tile >= 0 && c.tile <= 4;
+    case 2: return c.tile >= 0 && c.tile <= 2;
+    case 4: return c.tile >= 0 && c.tile <= 1;
+    case 8: return c.tile >= 0 && c.tile <= 1;
+    default: return false;
+  }
+}
+
+// Launches one pass of the loop over the given work.  Single box: `a` with
+// a.work (ordered) or without (Morton order, XCD-grouped).  Multi box or
+// persistent: dev_boxes/dev_work/n_items (counter zeroed here).
+template <int MODE, bool COMP, int CAP, int LCAP, int NW>
+hipError_t launch_loop_t(hipStream_t st, const LoopArgs &a, const LoopConfig &cfg, const LoopArgs *dev_boxes,
+                         const int2 *dev_work, int n_items, int *counter, int grid_persistent) {
+  if (dev_boxes) {
+    if (cfg.persistent) {
+      hipError_t e = hipMemsetAsync(counter, 0, sizeof(int), st);
+      if (e != hipSuccess) return e;
+      loop_persistent_kernel<MODE, CAP, LCAP, COMP, NW><<<grid_persistent, 64 * NW, 0, st>>>(dev_boxes, dev_work,
+                                                                                            n_items, counter);
+    } else {
+      loop_multi_kernel<MODE, CAP, LCAP, COMP, NW><<<n_items > 0 ? n_items : 1, 64 * NW, 0, st>>>(dev_boxes,
+                                                                                                dev_work, n_items);
+    }
+  } else {
+    LoopArgs g = a;
+    int64_t grid;
+    if (g.work) {
+      grid = g.n_items;
+    } else {
+      g.n_items = g.n_chunks;
+      g.per_xcd = ceil_div(g.n_chunks, 8);
+      grid = 8 * (g.per_xcd > 0 ? g.per_xcd : 1);
+    }
+    loop_grid_kernel<MODE, CAP, LCAP, COMP, NW><<<(unsigned)(grid > 0 ? grid : 1), 64 * NW, 0, st>>>(g);
+  }
+  return hipGetLastError();
+}
+
+template <int MODE, bool COMP>
+hipError_t launch_loop_any(hipStream_t st, const LoopArgs &a, const LoopConfig &c, const LoopArgs *dev_boxes,
+                           const int2 *dev_work, int n_items, int *counter, int grid_persistent) {
+#define SPH_LAUNCH(CAP_, LCAP_, NW_) \
+  return launch_loop_t<MODE, COMP, CAP_, LCAP_, NW_>(st, a, c, dev_boxes, dev_work, n_items, counter, grid_persistent)
+  switch (c.nw * 10 + c.tile) {
+    case 10: SPH_LAUNCH(128, 32, 1);
+    case 11: SPH_LAUNCH(256, 64, 1);
+    case 12: SPH_LAUNCH(512, 96, 1);
+    case 13: SPH_LAUNCH(1024, 128, 1);
+    case 14: SPH_LAUNCH(2048, 192, 1);
+    case 20: SPH_LAUNCH(128, 32, 2);
+    case 21: SPH_LAUNCH(256, 64, 2);
+    case 22: SPH_LAUNCH(512, 96, 2);
+    case 40: SPH_LAUNCH(128, 32, 4);
+    case 41: SPH_LAUNCH(256, 64, 4);
+    case 80: SPH_LAUNCH(128, 32, 8);
+    case 81: SPH_LAUNCH(256, 64, 8);
+    default: return hipErrorInvalidValue;
+  }
+#undef SPH_LAUNCH
+}
+
+struct GhostArgs {
+  int64_t n_active;
+  const int32_t *active_idx, *chunk_of;
+  const Chunk *chunks;
+  int32_t *chunk_todo;
+  const float *sums;
+  const int32_t *act_cnt;
+  const float *act_hmax;
+  float *hlo, *hhi;
+  uint8_t *conv;
+  float4 *pos4;
+  float4 *jth;
+  float *h;
+  int last;
+  int from_u;
+  float eta3, kc, tol, gamma, eps, box_quarter, reach;
+  // outputs
+  float *rho, *drho_dh, *f, *divv, *curlx, *curly, *curlz, *P, *c, *B, *A, *u;
+  int32_t *nngb;
+  int32_t *n_unconv, *rebuild;
+  unsigned long long *ctr;  // cumulative density interactions of finished solves
+};
+
+// Newton step on F(h) = h^3 sum_j W(r_ij, h) - eta^3 for each active particle
+// not yet converged; converged (or last-pass) particles get their ghost
+// quantities written.
+__global__ __launch_bounds__(256) void ghost_kernel(GhostArgs g) {
+  int finished = 0;
+  int unconv = 0;
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < g.n_active; k += (int64_t)gridDim.x * 256) {
+    if (g.conv[k]) continue;
+    const int i = g.active_idx[k];
+    const float S_w = g.sums[k], S_mw = g.sums[g.n_active + k], S_d = g.sums[2 * g.n_active + k],
+                S_md = g.sums[3 * g.n_active + k];
+    const float h = g.h[i];
+    // Newton in ln h on G = ln(h^3 n / eta^3), with h^3 n = (8/pi)/GK^3 sum w
+    // and dG/dln h = (3 sum w - sum (3w + q w')) / sum w: the same root as
+    // h^3 n = eta^3, reached in one step where the density is locally uniform.
+    const float hn3 = g.kc * S_w;
+    const float G = __logf(hn3 / g.eta3);
+    const float Gp = (3.f * S_w - S_d) / S_w;
+    float lo = g.hlo[k], hi = g.hhi[k];
+    if (G < 0.f) lo = fmaxf(lo, h);
+    if (G > 0.f) hi = fminf(hi, h);
+    float hn = h * __expf(fminf(fmaxf(-G / Gp, -0.6931472f), 0.6931472f));
+    if (!(hn >= lo && hn <= hi) || !(Gp > 0.f)) hn = (hi < INFINITY) ? 0.5f * (lo + hi) : 2.f * h;
+    if (G == 0.f) hn = h;
+    const bool done = fabsf(hn - h) < g.tol * h;
+    if (done || g.last) {
+      const float H = GK32 * h;
+      const float iH = 1.f / H;
+      const float C3 = KNORM32 * iH * iH * iH;
+      const float rho = C3 * S_mw;
+      const float drho = -C3 / h * S_md;
+      const float fg = 1.f / (1.f + h / (3.f * rho) * drho);
+      float P, A, u;
+      const float rg = __powf(rho, g.gamma);
+      if (g.from_u) {
+        u = g.u[i];
+        P = (g.gamma - 1.f) * rho * u;
+        A = P / rg;
+        g.A[i] = A;
+      } else {
+        A = g.A[i];
+        P = A * rg;
+        u = P / ((g.gamma - 1.f) * rho);
+        if (g.u) g.u[i] = u;
+      }
+      const float cs = sqrtf(g.gamma * P / rho);
+      const float C4 = C3 * iH;
+      const float dv = -C4 * g.sums[4 * g.n_active + k] / rho;
+      const float cx = C4 * g.sums[5 * g.n_active + k] / rho;
+      const float cy = C4 * g.sums[6 * g.n_active + k] / rho;
+      const float cz = C4 * g.sums[7 * g.n_active + k] / rho;
+      const float adv = fabsf(dv);
+      const float acu = sqrtf(fmaf(cz, cz, fmaf(cy, cy, cx * cx)));
+      const float Bs = adv > 0.f ? adv / (adv + acu + g.eps * cs / h) : 0.f;
+      g.rho[i] = rho;
+      g.drho_dh[i] = drho;
+      g.f[i] = fg;
+      g.divv[i] = dv;
+      g.curlx[i] = cx;
+      g.curly[i] = cy;
+      g.curlz[i] = cz;
+      g.P[i] = P;
+      g.c[i] = cs;
+      g.B[i] = Bs;
+      if (g.nngb) g.nngb[i] = g.act_cnt[k];
+      g.jth[i] = make_float4(rho, fg * P / (rho * rho), cs, Bs);
+      finished += g.act_cnt[k];
+      g.conv[k] = 1;
+      if (!done) ++unconv;
+    } else {
+      g.hlo[k] = lo;
+      g.hhi[k] = hi;
+      g.h[i] = hn;
+      const float Hn = GK32 * hn;
+      g.pos4[i].w = Hn;
+      g.chunk_todo[g.chunk_of[k]] = 1;
+      ++unconv;
+      const Chunk ch = g.chunks[g.chunk_of[k]];
+      if (Hn > g.act_hmax[ch.act_leaf] * g.reach) atomicOr(g.rebuild, 1);
+      if (Hn > g.box_quarter) atomicOr(g.rebuild, 2);
+    }
+  }
+  finished = wave_sum_i(finished);
+  unconv = wave_sum_i(unconv);
+  if ((threadIdx.x & 63) == 0) {
+    if (finished) atomicAdd(g.ctr, (unsigned long long)finished);
+    if (unconv) atomicAdd(g.n_unconv, unconv);
+  }
+}
+

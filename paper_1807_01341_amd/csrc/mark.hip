@@ -62,7 +62,9 @@ __global__ __launch_bounds__(MT) void mark_fill_kernel(const uint8_t *__restrict
     return;
   }
   const int b = leaf_begin[l], c = leaf_count[l];
-  const int ao = act_off[l], co = chunk_off[l], al = actleaf_idx[l];
+  const int ao = act_off[l];
+  const int al = actleaf_idx[l] - act_off[nl];
+  const int co = chunk_off[l] - actleaf_idx[nl];
   int run = 0;
   for (int t = 0; t < c; t += 64) {
     const int k = t + lane;
@@ -118,7 +120,8 @@ __global__ __launch_bounds__(MT) void pairs_kernel(int mode, float slack, PairGe
                                                    const int32_t *__restrict__ top_first,
                                                    const int32_t *__restrict__ top_last, float hmax_global,
                                                    int32_t *__restrict__ counts, const int32_t *__restrict__ offs,
-                                                   PairEntry *__restrict__ out) {
+                                                   PairEntry *__restrict__ out, const int32_t *__restrict__ leaf_count,
+                                                   int32_t *__restrict__ act_cost) {
   const int64_t a = (int64_t)blockIdx.x * (MT / 64) + (threadIdx.x >> 6);
   if (a >= n_act_leaves) return;
   const int lane = threadIdx.x & 63;
@@ -145,6 +148,7 @@ __global__ __launch_bounds__(MT) void pairs_kernel(int mode, float slack, PairGe
     }
   }
   int written = 0;
+  int staged = 0;
   const int base = FILL ? offs[a] : 0;
   for (int u = 0; u < cnt3[0]; ++u) {
     const int tx = ((lo[0] + u) % ntop + ntop) % ntop;
@@ -187,6 +191,7 @@ __global__ __launch_bounds__(MT) void pairs_kernel(int mode, float slack, PairGe
             pe.sy = (float)((double)dl[1] * g.unit);
             pe.sz = (float)((double)dl[2] * g.unit);
             out[base + written + rank_below(mask)] = pe;
+            if (act_cost) staged += leaf_count[B];
           }
           written += __popcll(mask);
         }
@@ -194,6 +199,10 @@ __global__ __launch_bounds__(MT) void pairs_kernel(int mode, float slack, PairGe
     }
   }
   if (!FILL && lane == 0) counts[a] = written;
+  if (FILL && act_cost) {
+    staged = wave_sum_i(staged);
+    if (lane == 0) act_cost[a] = staged;
+  }
 }
 
 // Max H over each active leaf's particles (all of them) and the running
@@ -236,6 +245,8 @@ sph_status build_pairs(sph_ctx *ctx, int which, float slack) {
   DevBuf &off = which == 0 ? ctx->dpair_off : ctx->fpair_off;
   DevBuf &lst = which == 0 ? ctx->dpairs : ctx->fpairs;
   SPH_TRY(sph_ensure(ctx, ctx->pair_cnt, 4 * (size_t)(na + 1)));
+  SPH_TRY(sph_ensure(ctx, ctx->act_cost, 4 * (size_t)(na + 1)));
+  if (which == 0) ctx->work_valid = 0;
   SPH_TRY(sph_ensure(ctx, off, 4 * (size_t)(na + 1)));
   PairGeom g;
   g.D = ctx->prm.morton_depth;
@@ -255,7 +266,8 @@ sph_status build_pairs(sph_ctx *ctx, int which, float slack) {
         which, slack, g, na, (const int32_t *)ctx->act_leaves.p, (const float *)ctx->act_hmax.p,
         (const int32_t *)ctx->leaf_level.p, (const int32_t *)ctx->leaf_ix.p, (const int32_t *)ctx->leaf_iy.p,
         (const int32_t *)ctx->leaf_iz.p, (const float *)ctx->leaf_hmax.p, (const int32_t *)ctx->top_first.p,
-        (const int32_t *)ctx->top_last.p, ctx->hmax_global, (int32_t *)ctx->pair_cnt.p, nullptr, nullptr);
+        (const int32_t *)ctx->top_last.p, ctx->hmax_global, (int32_t *)ctx->pair_cnt.p, nullptr, nullptr, nullptr,
+      nullptr);
   }
   HIP_TRY(ctx, hipGetLastError());
   int32_t *o = (int32_t *)off.p;
@@ -271,14 +283,18 @@ sph_status build_pairs(sph_ctx *ctx, int which, float slack) {
         which, slack, g, na, (const int32_t *)ctx->act_leaves.p, (const float *)ctx->act_hmax.p,
         (const int32_t *)ctx->leaf_level.p, (const int32_t *)ctx->leaf_ix.p, (const int32_t *)ctx->leaf_iy.p,
         (const int32_t *)ctx->leaf_iz.p, (const float *)ctx->leaf_hmax.p, (const int32_t *)ctx->top_first.p,
-        (const int32_t *)ctx->top_last.p, ctx->hmax_global, nullptr, o, (PairEntry *)lst.p);
+        (const int32_t *)ctx->top_last.p, ctx->hmax_global, nullptr, o, (PairEntry *)lst.p,
+      (const int32_t *)ctx->leaf_count.p, which == 0 ? (int32_t *)ctx->act_cost.p : nullptr);
   }
   HIP_TRY(ctx, hipGetLastError());
   if (which == 0) ctx->n_dpairs = np; else ctx->n_fpairs = np;
   return SPH_OK;
 }
 
-sph_status refresh_leaf_hmax(sph_ctx *ctx) {
+// Refreshes the max H of every active leaf (all particles, and active ones)
+// from the current smoothing lengths; with read_global the running global
+// max H is read back for the pair-search reach (synchronises).
+sph_status refresh_leaf_hmax(sph_ctx *ctx, bool read_global) {
   const int64_t na = ctx->n_active_leaves;
   if (na == 0) return SPH_OK;
   int32_t *sc = (int32_t *)ctx->scalars.p;
@@ -296,6 +312,7 @@ sph_status refresh_leaf_hmax(sph_ctx *ctx) {
         (float *)ctx->act_hmax.p, sc + SC_HMAX_BITS);
   }
   HIP_TRY(ctx, hipGetLastError());
+  if (!read_global) return SPH_OK;
   SPH_TRY(read_scalars(ctx, SC_HMAX_BITS, 1, &hb));
   float hg;
   memcpy(&hg, &hb, 4);
@@ -326,11 +343,15 @@ sph_status mark_active_impl(sph_ctx *ctx, const sph_particles *p, int m, int64_t
                                                               hmax_act_leaf);
   }
   HIP_TRY(ctx, hipGetLastError());
-  SPH_TRY(scan_exclusive_i32(ctx, nact, aoff, nl, sc + SC_TOTAL0));
-  SPH_TRY(scan_exclusive_i32(ctx, isact, aidx, nl, sc + SC_TOTAL1));
-  SPH_TRY(scan_exclusive_i32(ctx, nchunk, coff, nl, sc + SC_TOTAL2));
-  int32_t tot[3];
-  SPH_TRY(read_scalars(ctx, SC_TOTAL0, 3, tot));
+  // one scan over [nact | isact | nchunk]: the second and third segments come
+  // out shifted by the totals before them, read back by the fill kernel
+  SPH_TRY(scan_exclusive_i32(ctx, nact, aoff, 3 * nl, aoff + 3 * nl));
+  int32_t tot3[4];
+  HIP_TRY(ctx, hipMemcpyAsync(tot3, aoff + nl, 4, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(tot3 + 1, aoff + 2 * nl, 4, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(tot3 + 2, aoff + 3 * nl, 4, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  int32_t tot[3] = {tot3[0], tot3[1] - tot3[0], tot3[2] - tot3[1]};
   ctx->n_active = tot[0];
   ctx->n_active_leaves = tot[1];
   ctx->n_chunks = tot[2];

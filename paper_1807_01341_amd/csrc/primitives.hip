@@ -137,6 +137,12 @@ sph_status scan_exclusive_i32(sph_ctx *ctx, const int32_t *in, int32_t *out, int
 }
 
 // ---------------------------------------------------------------- radix sort
+//
+// LSD radix sort with 8-bit digits.  Each pass counts the digits of every
+// tile of the current arrangement (the per-tile counts of pass p depend on
+// where pass p-1 put the keys), scans the counts into offsets, then ranks
+// each tile stably, stages it in LDS in digit order and writes contiguous
+// runs.
 
 #define RS_THREADS 256
 #define RS_ROUNDS 16
@@ -157,19 +163,50 @@ __global__ __launch_bounds__(RS_THREADS) void radix_hist_kernel(const uint64_t *
   counts[(int64_t)tid * nblocks + blockIdx.x] = h[tid];
 }
 
-// Stable scatter: elements of a tile keep their order among equal digits.
-// Each round ranks 256 consecutive elements: within a wave by matching digits
-// with 8 ballots, across the block's waves through per-wave digit counts.
 __global__ __launch_bounds__(RS_THREADS) void radix_scatter_kernel(const uint64_t *__restrict__ kin,
                                                                    const int32_t *__restrict__ vin,
                                                                    uint64_t *__restrict__ kout,
                                                                    int32_t *__restrict__ vout, int64_t n, int shift,
                                                                    const int32_t *__restrict__ offsets, int nblocks) {
+  __shared__ uint64_t sk[RS_TILE];
+  __shared__ int32_t sv[RS_TILE];
+  __shared__ int tcount[256];  // digit counts of this tile
+  __shared__ int lbase[256];   // exclusive scan of tcount: start of each digit run in LDS
   __shared__ int run[256];
   __shared__ int wcnt[RS_THREADS / 64][256];
-  const int tid = threadIdx.x, wid = tid >> 6;
-  run[tid] = offsets[(int64_t)tid * nblocks + blockIdx.x];
+  const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
   const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+  tcount[tid] = 0;
+  run[tid] = 0;
+  __syncthreads();
+  for (int r = 0; r < RS_ROUNDS; ++r) {
+    const int64_t i = base + (int64_t)r * RS_THREADS + tid;
+    if (i < n) atomicAdd(&tcount[(int)((kin[i] >> shift) & 255ull)], 1);
+  }
+  __syncthreads();
+  // exclusive scan of the 256 tile counts by the first wave
+  if (wid == 0) {
+    int v[4], s = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      v[q] = tcount[lane * 4 + q];
+      s += v[q];
+    }
+    int inc = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += t;
+    }
+    int e = inc - s;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      lbase[lane * 4 + q] = e;
+      e += v[q];
+    }
+  }
+  __syncthreads();
+  // stable ranking, round by round, into the LDS tile in digit order
   for (int r = 0; r < RS_ROUNDS; ++r) {
 #pragma unroll
     for (int w = 0; w < RS_THREADS / 64; ++w) wcnt[w][tid] = 0;
@@ -189,10 +226,10 @@ __global__ __launch_bounds__(RS_THREADS) void radix_scatter_kernel(const uint64_
     if (valid && rank == 0) wcnt[wid][d] = __popcll(peers);
     __syncthreads();
     if (valid) {
-      int pos = run[d] + rank;
+      int pos = lbase[d] + run[d] + rank;
       for (int w = 0; w < wid; ++w) pos += wcnt[w][d];
-      kout[pos] = key;
-      vout[pos] = vin[i];
+      sk[pos] = key;
+      sv[pos] = vin[i];
     }
     __syncthreads();
     int add = 0;
@@ -201,27 +238,37 @@ __global__ __launch_bounds__(RS_THREADS) void radix_scatter_kernel(const uint64_
     run[tid] += add;
     __syncthreads();
   }
+  // contiguous runs out: element t of digit d goes to its global offset
+  const int tile_n = (int)((n - base) < RS_TILE ? (n - base) : RS_TILE);
+  for (int t = tid; t < tile_n; t += RS_THREADS) {
+    const uint64_t key = sk[t];
+    const int d = (int)((key >> shift) & 255ull);
+    const int64_t g = (int64_t)offsets[(int64_t)d * nblocks + blockIdx.x] + (t - lbase[d]);
+    kout[g] = key;
+    vout[g] = sv[t];
+  }
 }
 
 sph_status radix_sort_pairs(sph_ctx *ctx, int64_t n, int bits) {
   if (n <= 1) return SPH_OK;
   const int nblocks = (int)ceil_div(n, RS_TILE);
-  SPH_TRY(sph_ensure(ctx, ctx->radix_counts, sizeof(int32_t) * 256 * (size_t)nblocks * 2));
+  const int passes = (bits + 7) / 8;
+  const int64_t per = 256 * (int64_t)nblocks;
+  SPH_TRY(sph_ensure(ctx, ctx->radix_counts, sizeof(int32_t) * (size_t)per * 2));
   int32_t *counts = (int32_t *)ctx->radix_counts.p;
-  int32_t *offs = counts + 256 * (size_t)nblocks;
+  int32_t *offs = counts + per;
   uint64_t *ka = (uint64_t *)ctx->keys_a.p, *kb = (uint64_t *)ctx->keys_b.p;
   int32_t *va = (int32_t *)ctx->vals_a.p, *vb = (int32_t *)ctx->vals_b.p;
-  int passes = 0;
-  for (int shift = 0; shift < bits; shift += 8, ++passes) {
+  for (int p = 0; p < passes; ++p) {
     {
       PROF(ctx, "radix_hist");
-      radix_hist_kernel<<<nblocks, RS_THREADS, 0, ctx->stream>>>(ka, n, shift, counts, nblocks);
+      radix_hist_kernel<<<nblocks, RS_THREADS, 0, ctx->stream>>>(ka, n, 8 * p, counts, nblocks);
     }
     HIP_TRY(ctx, hipGetLastError());
-    SPH_TRY(scan_exclusive_i32(ctx, counts, offs, 256 * (int64_t)nblocks, nullptr));
+    SPH_TRY(scan_exclusive_i32(ctx, counts, offs, per, nullptr));
     {
       PROF(ctx, "radix_scatter");
-      radix_scatter_kernel<<<nblocks, RS_THREADS, 0, ctx->stream>>>(ka, va, kb, vb, n, shift, offs, nblocks);
+      radix_scatter_kernel<<<nblocks, RS_THREADS, 0, ctx->stream>>>(ka, va, kb, vb, n, 8 * p, offs, nblocks);
     }
     HIP_TRY(ctx, hipGetLastError());
     uint64_t *tk = ka; ka = kb; kb = tk;

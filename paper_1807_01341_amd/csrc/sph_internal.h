@@ -40,6 +40,7 @@ struct sph_ctx {
   sph_params prm;
   hipStream_t stream = nullptr;
   int device = 0;
+  int n_cu = 256;
   std::string err;
   int state = 0;  // 0 none, 1 built, 2 sorted, 3 marked, 4 density done, 5 force done
   int64_t n = 0;
@@ -73,6 +74,16 @@ struct sph_ctx {
   DevBuf jth;                             // float4 (rho, f P / rho^2, c, B)
   DevBuf sums, hlo, hhi, conv;
   DevBuf counters64;                      // cumulative interaction counts (2 x uint64)
+  DevBuf act_cost;                        // staged partner particles per active leaf
+  DevBuf work, work_tmp, box_args, box_work;
+  int work_valid = 0;                     // work (cost order) matches the current chunks
+
+  // tuned loop configurations per pass (0 density, 1 force) and chunk-count class
+  struct TuneEntry {
+    int valid = 0, nw = 1, tile = 2, ordered = 0, persistent = 0;
+    float ms = 0.f;
+  };
+  TuneEntry tune[2][32];
 
   // optional per-kernel timing with HIP events on ctx->stream
   int prof = 0;
@@ -126,6 +137,7 @@ enum ScalarSlot {
   SC_REBUILD = 9,
   SC_PAIRTOT = 10,
   SC_MAXLEAF = 11,
+  SC_WORKCTR = 12,
   SC_COUNT = 32
 };
 
@@ -142,7 +154,7 @@ sph_status build_cells_impl(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *
 sph_status sort_cells_impl(sph_ctx *ctx);
 sph_status mark_active_impl(sph_ctx *ctx, const sph_particles *p, int m, int64_t *n_active_host);
 sph_status build_pairs(sph_ctx *ctx, int which, float slack);
-sph_status refresh_leaf_hmax(sph_ctx *ctx);
+sph_status refresh_leaf_hmax(sph_ctx *ctx, bool read_global);
 sph_status pack_neighbour_data(sph_ctx *ctx, const sph_particles *p);
 sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u);
 sph_status force_pass_impl(sph_ctx *ctx, sph_particles *p);
@@ -199,3 +211,10 @@ __host__ __device__ __forceinline__ uint32_t compact3_21(uint64_t v) {
 }
 
 __host__ __device__ __forceinline__ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Chunk-count class of a pass for the tuning table: floor(log2(n_chunks)).
+inline int tune_class(int64_t n_chunks) {
+  int c = 0;
+  while (c < 31 && ((int64_t)1 << (c + 1)) <= n_chunks) ++c;
+  return c;
+}

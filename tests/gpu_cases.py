@@ -10,10 +10,12 @@ A_TOL = 1e-4      # accelerations, relative to max(|a_ref|, 1e-2 * S_i)
 RHO_TOL = 1e-5    # density, relative
 
 
-def run_gpu_step(sg, ic, m_bin, ctx_kw=None, entropy_from_u=True):
+def run_gpu_step(sg, ic, m_bin, ctx_kw=None, entropy_from_u=True, setup_all=False):
     """build -> sort -> mark -> density -> force on the GPU.  Returns the
     context, particles (cell order), perm and a snapshot of the derived
-    structures taken right after mark_active."""
+    structures taken right after mark_active.  setup_all first runs an
+    all-active density pass, which gives the inactive particles of a deep
+    bin their density-loop state (h, rho, f, P, c, B)."""
     p = sg.Particles.from_initial(ic)
     ctx = sg.Context(**(ctx_kw or {}))
     perm = torch.empty(p.n, dtype=torch.int64, device="cuda")
@@ -26,6 +28,12 @@ def run_gpu_step(sg, ic, m_bin, ctx_kw=None, entropy_from_u=True):
     snap["leaves"] = {k: v.cpu().numpy() for k, v in ctx.copy_leaves().items()}
     snap["order"] = ctx.copy_axis_order().cpu().numpy().view(np.uint16)
     snap["info_build"] = ctx.info()
+    snap["H_mark"] = None
+    if setup_all:
+        ctx.mark_active(p, ctx.params.n_bins - 1)
+        ctx.density_pass(p, entropy_from_u=entropy_from_u)
+        entropy_from_u = False
+        snap["H_mark"] = (np.float32(1.825742) * p["h"].cpu().numpy()).astype(np.float32)
     ctx.mark_active(p, m_bin)
     act, al, hm = ctx.copy_active()
     snap["active"] = act.cpu().numpy().astype(bool)
@@ -50,10 +58,10 @@ def pair_set(a, b, s):
     return sorted(zip(a.tolist(), b.tolist(), [tuple(x) for x in s.astype(np.float32).tolist()]))
 
 
-def check_structures(ic, perm, snap, split=400, m_bin=0):
+def check_structures(ic, perm, snap, split=400, m_bin=0, D=16):
     """Bit-exact: permutation, keys, offsets, leaves, axis orders, active
     set and density cell pairs against the C definitions."""
-    cl = emu.build_cells(ic["x"], ic["h"], split=split)
+    cl = emu.build_cells(ic["x"], ic["h"], split=split, D=D)
     assert np.array_equal(perm, cl["perm"])
     assert np.array_equal(snap["keys"], cl["key"])
     for d, k in enumerate(("ox", "oy", "oz")):
@@ -69,7 +77,7 @@ def check_structures(ic, perm, snap, split=400, m_bin=0):
     order, _ = emu.axis_sort(cl)
     assert np.array_equal(snap["order"], order)
     binsorted = ic["bin"][perm]
-    act = emu.mark_active(cl, binsorted, m_bin)
+    act = emu.mark_active(cl, binsorted, m_bin, H=snap.get("H_mark"))
     assert np.array_equal(snap["active"], act["active"])
     assert np.array_equal(snap["active_leaves"], act["active_leaves"])
     assert np.array_equal(snap["hmax_act"].view(np.uint32), act["hmax_act"].view(np.uint32))
@@ -103,9 +111,10 @@ def oracle_all(ic, entropy_from_u=True):
     return out, fo
 
 
-def float_errors(p, perm, out, fo, idx_sorted=None):
+def float_errors(p, perm, out, fo, idx_sorted=None, fo_aligned=False):
     """Per-quantity errors of the GPU (cell order) against the oracle
-    (original order), over the active particles `idx_sorted`."""
+    (original order), over the active particles `idx_sorted`.  The force
+    arrays are in original order, or aligned with idx_sorted (fo_aligned)."""
     if idx_sorted is None:
         idx_sorted = np.arange(p.n)
     orig = perm[idx_sorted]
@@ -130,13 +139,13 @@ def float_errors(p, perm, out, fo, idx_sorted=None):
     e["curlv"] = np.max(np.linalg.norm(curl_g - curl_r, axis=1) / cs)
     e["B"] = np.max(np.abs(host(p, "balsara")[idx_sorted] - out["B"].numpy()[orig]))
     a_g = np.stack([host(p, k)[idx_sorted] for k in ("ax", "ay", "az")], 1).astype(np.float64)
-    a_r = fo["a"].numpy()[orig] if fo["a"].shape[0] == perm.size else fo["a"].numpy()
-    S = fo["scale"].numpy()[orig] if fo["scale"].shape[0] == perm.size else fo["scale"].numpy()
+    a_r = fo["a"].numpy() if fo_aligned else fo["a"].numpy()[orig]
+    S = fo["scale"].numpy() if fo_aligned else fo["scale"].numpy()[orig]
     den = np.maximum(np.linalg.norm(a_r, axis=1), 1e-2 * S)
     e["a"] = np.max(np.linalg.norm(a_g - a_r, axis=1) / den)
     e["a_normwise"] = np.linalg.norm(a_g - a_r) / max(np.linalg.norm(a_r), 1e-300)
-    vs_r = fo["vsig"].numpy()[orig] if fo["vsig"].shape[0] == perm.size else fo["vsig"].numpy()
+    vs_r = fo["vsig"].numpy() if fo_aligned else fo["vsig"].numpy()[orig]
     e["vsig"] = rel(host(p, "vsig")[idx_sorted], vs_r)
-    dA_r = fo["dA_dt"].numpy()[orig] if fo["dA_dt"].shape[0] == perm.size else fo["dA_dt"].numpy()
+    dA_r = fo["dA_dt"].numpy() if fo_aligned else fo["dA_dt"].numpy()[orig]
     e["dA_dt"] = np.max(np.abs(host(p, "dA_dt")[idx_sorted] - dA_r)) / max(np.max(np.abs(dA_r)), 1e-300)
     return e

@@ -156,3 +156,30 @@ def test_waves_per_chunk_variants_agree(gpu_lib, nw):
     a0 = np.stack([host(p0, k) for k in ("ax", "ay", "az")], 1)
     a1 = np.stack([host(p1, k) for k in ("ax", "ay", "az")], 1)
     assert np.max(np.linalg.norm(a0 - a1, axis=1)) < 1e-5 * np.max(np.linalg.norm(a0, axis=1))
+
+
+def test_autotune_keeps_results(gpu_lib, tmp_path):
+    """Tuning picks a loop configuration per pass; passes run with it give
+    the same counts and the same sums to rounding."""
+    ic = ics.tiny_lattice(16, velocity_sigma=0.1)
+    ctx, p, perm, snap = run_gpu_step(gpu_lib, ic, 0)
+    ref = {k: host(p, k).copy() for k in ("rho", "ax", "nngb_density", "nngb_force")}
+    path = str(tmp_path / "tune.txt")
+    ctx.autotune(p, path)
+    lines = open(path).read().splitlines()
+    assert sum(l.startswith("best") for l in lines) == 2
+    assert sum(l.startswith("candidate") for l in lines) >= 2 * 24
+    # a fresh context with the loaded table reproduces the step
+    ctx2, p2, perm2, _ = run_gpu_step(gpu_lib, ic, 0)
+    ctx3 = gpu_lib.Context()
+    ctx3.load_tuning(path)
+    p3 = gpu_lib.Particles.from_initial(ic)
+    ctx3.build_cells(p3)
+    ctx3.sort_cells()
+    ctx3.mark_active(p3, 0)
+    ctx3.density_pass(p3, True)
+    ctx3.force_pass(p3)
+    ctx3.sync()
+    assert np.array_equal(host(p3, "nngb_density"), ref["nngb_density"])
+    assert np.array_equal(host(p3, "nngb_force"), ref["nngb_force"])
+    assert np.max(np.abs(host(p3, "rho") / ref["rho"] - 1)) < 2e-6

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 def test_default_params_and_struct_layout():
     import paper_1807_01341_amd as sg
     p = sg.default_params()
-    assert p.split_count == 400 and p.morton_depth == 21 and abs(p.cfl - 0.2) == 0.0
+    assert p.split_count == 400 and p.morton_depth == 16 and abs(p.cfl - 0.2) == 0.0
     assert abs(p.eta - 1.2348) < 1e-6 and p.n_bins == 14
     # the ctypes mirror has the C field order and sizes
     text = open(os.path.join(ROOT, "include", "sphgpu.h")).read()
