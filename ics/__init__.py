@@ -186,7 +186,7 @@ def differentiation(index: int = 4, velocity_sigma: float = 0.1):
 def batch_of_boxes(n_boxes: int = 64, n_range=(1_000, 200_000), index: int = 3,
                    frac_range=(0.005, 1.0)):
     """Workload 3: n_boxes independent unit boxes.  Box b draws N_b log-uniform
-    in n_range; it is a k_b^3 jittered lattice (k_b = round((0.9 N_b)^{1/3}))
+    in n_range; it is a k_b^3 jittered lattice (k_b = floor((0.9 N_b)^{1/3}))
     plus one Plummer clump of N_b - k_b^3 particles (a = 0.01), u log-uniform
     in [1e-2, 1e2], model time-bins, and a target active fraction f_b
     log-uniform in frac_range."""
@@ -198,7 +198,7 @@ def batch_of_boxes(n_boxes: int = 64, n_range=(1_000, 200_000), index: int = 3,
     for b in range(n_boxes):
         g = [np.random.Generator(np.random.PCG64(s))
              for s in np.random.SeedSequence(int(seeds[b])).spawn(3)]
-        k = int(round((0.9 * Ns[b]) ** (1.0 / 3.0)))
+        k = int(math.floor((0.9 * Ns[b]) ** (1.0 / 3.0)))
         x, m, rho_model = lattice_plus_clump(k, int(Ns[b]) - k ** 3, 0.01, g[0], g[1])
         N = x.shape[0]
         u = np.exp(g[2].uniform(math.log(1e-2), math.log(1e2), size=N)).astype(np.float32)
