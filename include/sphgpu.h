@@ -149,6 +149,48 @@ sph_status sph_force_pass(sph_ctx *ctx, sph_particles *p);
 sph_status sph_kick_drift(sph_ctx *ctx, sph_particles *p, int64_t ti, double t_min, int64_t drift_int,
                           int first_step);
 
+/* ---- Batched passes: several contexts (independent periodic boxes, or any
+ * set of particle systems), each built, sorted and marked by its own calls
+ * and all created on the SAME stream, run each loop pass of the density /
+ * force pass as ONE launch over the concatenation of their active chunks
+ * (work items (box, chunk) in decreasing order of staged partner particles,
+ * pulled from one atomic counter by a grid sized to the machine, or one
+ * workgroup per item, as the batch tuning table says).  ctxs[0] leads: it
+ * holds the work list, the batch tuning table and, on an error, the message
+ * (prefixed with the failing box).  ps is an array of n_boxes particle sets,
+ * ps[b] belonging to ctxs[b].  A box's results are those of its own
+ * sph_density_pass / sph_force_pass run with the same loop tiling (bitwise;
+ * the tiling is the batch's).  Each call synchronises (once per Newton pass
+ * for the density, once for the force pass's cell-pair sizes).  SPH_EINVAL
+ * for a null or repeated context or one on another stream, SPH_ESTATE if a
+ * box is not marked (density) or has no density pass (force); the single-box
+ * errors otherwise. */
+sph_status sph_batch_density_pass(sph_ctx **ctxs, sph_particles *ps, int n_boxes, int entropy_from_u);
+sph_status sph_batch_force_pass(sph_ctx **ctxs, sph_particles *ps, int n_boxes);
+/* Autotuner of the batched loops: after a batched force pass, times every
+ * valid tiling (waves per chunk, candidate/list capacity) with persistent and
+ * one-workgroup-per-item launches over the whole batch, keeps the fastest per
+ * loop in ctxs[0]'s batch table (keyed by the log2 class of the total chunk
+ * count) and appends "batch_candidate" / "batch_best" lines to `path` (NULL:
+ * table only).  sph_load_tuning reads "batch_best" lines too.  Synchronises. */
+sph_status sph_batch_autotune(sph_ctx **ctxs, sph_particles *ps, int n_boxes, const char *path);
+
+/* Reverse mode of the density and force loops (differentiable-simulation
+ * use of the Sec. III-A loops): after a force pass in which every particle
+ * was active and whose density pass took the pressure from u
+ * (entropy_from_u = 1), for the loss L = sum_i w_i . a_i with weights
+ * (wx, wy, wz) (device, float, length n, cell order as the particle arrays)
+ * writes dL/dx into gx, gy, gz (device, double, length n) and dL/du into gu
+ * (device, float, length n).  The smoothing lengths are the converged roots
+ * of h^3 n(h) = eta^3, differentiated implicitly; neighbours are recomputed
+ * from fresh cell-pair lists; FP32 pair arithmetic with compensated sums.
+ * Does not change the particle arrays or the step state.  SPH_EINVAL if a
+ * particle is inactive or an array is missing, SPH_ESTATE before a force
+ * pass or after a density pass that took A as the thermal input.
+ * Synchronises twice (cell-pair list sizes). */
+sph_status sph_adjoint(sph_ctx *ctx, sph_particles *p, const float *wx, const float *wy, const float *wz,
+                       double *gx, double *gy, double *gz, float *gu);
+
 /* Waits for the context's stream and reports a pending device error. */
 sph_status sph_sync(sph_ctx *ctx);
 const char *sph_last_error(const sph_ctx *ctx);

@@ -98,6 +98,10 @@ def lib():
             "sph_profile_read": (i64, [vp, vp, i64]),
             "sph_autotune": (i32, [vp, vp, C.c_char_p]),
             "sph_load_tuning": (i32, [vp, C.c_char_p]),
+            "sph_adjoint": (i32, [vp] * 9),
+            "sph_batch_density_pass": (i32, [vp, vp, i32, i32]),
+            "sph_batch_force_pass": (i32, [vp, vp, i32]),
+            "sph_batch_autotune": (i32, [vp, vp, i32, C.c_char_p]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(L, name)
@@ -112,7 +116,8 @@ def exported_symbols():
             "sph_mark_active", "sph_density_pass", "sph_force_pass", "sph_kick_drift", "sph_sync",
             "sph_last_error", "sph_info", "sph_copy_leaves", "sph_copy_particles", "sph_copy_axis_order",
             "sph_copy_active", "sph_copy_pairs", "sph_profile", "sph_profile_read", "sph_autotune",
-            "sph_load_tuning"]
+            "sph_load_tuning", "sph_adjoint", "sph_batch_density_pass", "sph_batch_force_pass",
+            "sph_batch_autotune"]
 
 
 def require_device():
@@ -168,6 +173,31 @@ class Particles:
         a["u"] = torch.tensor(ic["u"], dtype=torch.float32, device=dev)
         a["h"] = torch.tensor(ic["h"], dtype=torch.float32, device=dev)
         a["time_bin"] = torch.tensor(ic.get("bin", np.zeros(N, np.int8)), dtype=torch.int8, device=dev)
+        for name, dt in PARTICLE_FIELDS:
+            if name in a:
+                continue
+            if name.startswith("nngb") and not counts:
+                continue
+            a[name] = torch.zeros(N, dtype=dt, device=dev)
+        return cls(a)
+
+    @classmethod
+    def from_tensors(cls, x, v, m, u, h, counts=True):
+        """From device tensors: x, v (N,3), m, u, h (N,).  Copies them into
+        the library's layout (x, v as FP64 columns; m, u, h as FP32), so the
+        caller's tensors are not modified by the calls."""
+        N = x.shape[0]
+        dev = x.device
+        a = {}
+        for d, k in enumerate("xyz"):
+            a[k] = x[:, d].to(torch.float64).contiguous().clone()
+        for d, k in enumerate(("vx", "vy", "vz")):
+            a[k] = v[:, d].to(torch.float64).contiguous().clone()
+            a["vf" + k[1]] = a[k].clone()
+        a["m"] = m.to(torch.float32).contiguous().clone()
+        a["u"] = u.to(torch.float32).contiguous().clone()
+        a["h"] = h.to(torch.float32).contiguous().clone()
+        a["time_bin"] = torch.zeros(N, dtype=torch.int8, device=dev)
         for name, dt in PARTICLE_FIELDS:
             if name in a:
                 continue
@@ -237,6 +267,20 @@ class Context:
     def kick_drift(self, p: Particles, ti: int, t_min: float, drift_int: int, first_step: bool):
         return self._check(lib().sph_kick_drift(self.h, self._pcs(p), int(ti), float(t_min), int(drift_int),
                                                 int(bool(first_step))))
+
+    def adjoint(self, p: Particles, w: torch.Tensor):
+        """dL/dx (N,3) float64 and dL/du (N,) float32 of L = sum_i w_i . a_i
+        after an all-active force pass (cell order, as the particle arrays)."""
+        w = w.to(torch.float32)
+        wx, wy, wz = (w[:, d].contiguous() for d in range(3))
+        n = p.n
+        dev = w.device
+        gx, gy, gz = (torch.empty(n, dtype=torch.float64, device=dev) for _ in range(3))
+        gu = torch.empty(n, dtype=torch.float32, device=dev)
+        self._check(lib().sph_adjoint(self.h, self._pcs(p), _ptr(wx), _ptr(wy), _ptr(wz), _ptr(gx), _ptr(gy),
+                                      _ptr(gz), _ptr(gu)))
+        self._keep = (wx, wy, wz)
+        return torch.stack([gx, gy, gz], 1), gu
 
     def sync(self):
         return self._check(lib().sph_sync(self.h))
@@ -311,3 +355,68 @@ class Context:
         s = [torch.empty(max(1, np_), dtype=torch.float32, device=dev) for _ in range(3)]
         self._check(lib().sph_copy_pairs(self.h, int(which), _ptr(a), _ptr(b), *[_ptr(t) for t in s]))
         return a[:np_], b[:np_], torch.stack([t[:np_] for t in s], 1)
+
+
+class Batch:
+    """Batched passes over several contexts that share one stream: each loop
+    pass of the density / force pass is one launch over all boxes' active
+    chunks.  contexts[0] leads (work list, batch tuning table, errors)."""
+
+    def __init__(self, contexts, particles):
+        if len(contexts) != len(particles) or not contexts:
+            raise ValueError("one particle set per context")
+        self.contexts = list(contexts)
+        self.particles = list(particles)
+        self._h = (C.c_void_p * len(contexts))(*[c.h.value for c in contexts])
+
+    def _ps(self):
+        self._pc = (ParticlesC * len(self.particles))(*[p.to_c() for p in self.particles])
+        return self._pc
+
+    def density_pass(self, entropy_from_u: bool):
+        return self.contexts[0]._check(lib().sph_batch_density_pass(self._h, self._ps(), len(self.contexts),
+                                                                    int(bool(entropy_from_u))))
+
+    def force_pass(self):
+        return self.contexts[0]._check(lib().sph_batch_force_pass(self._h, self._ps(), len(self.contexts)))
+
+    def autotune(self, path: str | None = None):
+        return self.contexts[0]._check(lib().sph_batch_autotune(
+            self._h, self._ps(), len(self.contexts), path.encode() if path else None))
+
+
+class SPHForce(torch.autograd.Function):
+    """a = SPHForce.apply(x, u, v, m, h0[, context]): accelerations (N,3,
+    FP32) of one all-active density + force evaluation at positions x (N,3)
+    and internal energies u, with velocities v, masses m and initial
+    smoothing lengths h0 (solved for in the density pass).  The backward
+    runs the library's adjoint and returns dL/dx (FP64) and dL/du; v, m and
+    h0 get no gradient.  The forward keeps the context and the per-particle
+    state of the evaluation for the backward."""
+
+    @staticmethod
+    def forward(fctx, x, u, v, m, h0, context=None):
+        c = context if context is not None else Context()
+        p = Particles.from_tensors(x.detach(), v.detach(), m.detach(), u.detach(), h0.detach())
+        n = p.n
+        perm = torch.empty(n, dtype=torch.int64, device=x.device)
+        c.build_cells(p, perm)
+        c.sort_cells()
+        c.mark_active(p, c.params.n_bins - 1, want_count=False)
+        c.density_pass(p, entropy_from_u=True)
+        c.force_pass(p)
+        a = torch.empty(n, 3, dtype=torch.float32, device=x.device)
+        a[perm] = torch.stack([p["ax"], p["ay"], p["az"]], 1)
+        fctx.sph = (c, p, perm)
+        fctx.x_dtype, fctx.u_dtype = x.dtype, u.dtype
+        return a
+
+    @staticmethod
+    def backward(fctx, ga):
+        c, p, perm = fctx.sph
+        gx_s, gu_s = c.adjoint(p, ga[perm])
+        gx = torch.empty(p.n, 3, dtype=torch.float64, device=ga.device)
+        gu = torch.empty(p.n, dtype=torch.float32, device=ga.device)
+        gx[perm] = gx_s
+        gu[perm] = gu_s
+        return gx.to(fctx.x_dtype), gu.to(fctx.u_dtype), None, None, None, None

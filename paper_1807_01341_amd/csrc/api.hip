@@ -193,6 +193,28 @@ sph_status sph_force_pass(sph_ctx *ctx, sph_particles *p) {
   return force_pass_impl(ctx, p);
 }
 
+sph_status sph_batch_density_pass(sph_ctx **ctxs, sph_particles *ps, int n_boxes, int entropy_from_u) {
+  if (!ps) return ctxs && n_boxes > 0 && ctxs[0] ? sph_fail(ctxs[0], SPH_EINVAL, "batch: null particles") : SPH_EINVAL;
+  return batch_density_impl(ctxs, ps, n_boxes, entropy_from_u);
+}
+
+sph_status sph_batch_force_pass(sph_ctx **ctxs, sph_particles *ps, int n_boxes) {
+  if (!ps) return ctxs && n_boxes > 0 && ctxs[0] ? sph_fail(ctxs[0], SPH_EINVAL, "batch: null particles") : SPH_EINVAL;
+  return batch_force_impl(ctxs, ps, n_boxes);
+}
+
+sph_status sph_batch_autotune(sph_ctx **ctxs, sph_particles *ps, int n_boxes, const char *path) {
+  if (!ps) return ctxs && n_boxes > 0 && ctxs[0] ? sph_fail(ctxs[0], SPH_EINVAL, "batch: null particles") : SPH_EINVAL;
+  return batch_autotune_impl(ctxs, ps, n_boxes, path);
+}
+
+sph_status sph_adjoint(sph_ctx *ctx, sph_particles *p, const float *wx, const float *wy, const float *wz, double *gx,
+                       double *gy, double *gz, float *gu) {
+  SPH_TRY(need_state(ctx, 5, "adjoint"));
+  if (!p) return sph_fail(ctx, SPH_EINVAL, "adjoint: null particles");
+  return adjoint_impl(ctx, p, wx, wy, wz, gx, gy, gz, gu);
+}
+
 sph_status sph_kick_drift(sph_ctx *ctx, sph_particles *p, int64_t ti, double t_min, int64_t drift_int,
                           int first_step) {
   SPH_TRY(need_state(ctx, 5, "kick_drift"));

@@ -187,6 +187,9 @@ sph_status launch_loop(sph_ctx *ctx, const LoopArgs &a0) {
                        MODE == 0 ? "density loop" : "force loop");
 }
 
+
+}  // namespace
+
 LoopArgs base_args(sph_ctx *ctx) {
   LoopArgs a;
   memset(&a, 0, sizeof a);
@@ -208,8 +211,6 @@ LoopArgs base_args(sph_ctx *ctx) {
   a.gm1 = (float)(ctx->prm.gamma - 1.0);
   return a;
 }
-
-}  // namespace
 
 // Per-particle neighbour data in cell order, packed once per build: velocity
 // and mass, and the density-loop state (rho, f P/rho^2, c, B) that inactive
@@ -241,19 +242,150 @@ sph_status pack_neighbour_data(sph_ctx *ctx, const sph_particles *p) {
   return SPH_OK;
 }
 
-sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u) {
+struct GhostArgs {
+  int64_t n_active;
+  const int32_t *active_idx, *chunk_of;
+  const Chunk *chunks;
+  int32_t *chunk_todo;
+  const float *sums;
+  const int32_t *act_cnt;
+  const float *act_hmax;
+  float *hlo, *hhi;
+  uint8_t *conv;
+  float4 *pos4;
+  float4 *jth;
+  float *h;
+  int last;
+  int from_u;
+  float eta3, kc, tol, gamma, eps, box_quarter, reach;
+  // outputs
+  float *rho, *drho_dh, *f, *divv, *curlx, *curly, *curlz, *P, *c, *B, *A, *u;
+  int32_t *nngb;
+  int32_t *n_unconv, *rebuild;
+  unsigned long long *ctr;  // cumulative density interactions of finished solves
+};
+
+// Newton step on F(h) = h^3 sum_j W(r_ij, h) - eta^3 for each active particle
+// not yet converged; converged (or last-pass) particles get their ghost
+// quantities written.
+__device__ __forceinline__ void ghost_body(const GhostArgs &g) {
+  int finished = 0;
+  int unconv = 0;
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < g.n_active; k += (int64_t)gridDim.x * 256) {
+    if (g.conv[k]) continue;
+    const int i = g.active_idx[k];
+    const float S_w = g.sums[k], S_mw = g.sums[g.n_active + k], S_d = g.sums[2 * g.n_active + k],
+                S_md = g.sums[3 * g.n_active + k];
+    const float h = g.h[i];
+    // Newton in ln h on G = ln(h^3 n / eta^3), with h^3 n = (8/pi)/GK^3 sum w
+    // and dG/dln h = (3 sum w - sum (3w + q w')) / sum w: the same root as
+    // h^3 n = eta^3, reached in one step where the density is locally uniform.
+    const float hn3 = g.kc * S_w;
+    const float G = __logf(hn3 / g.eta3);
+    const float Gp = (3.f * S_w - S_d) / S_w;
+    float lo = g.hlo[k], hi = g.hhi[k];
+    if (G < 0.f) lo = fmaxf(lo, h);
+    if (G > 0.f) hi = fminf(hi, h);
+    float hn = h * __expf(fminf(fmaxf(-G / Gp, -0.6931472f), 0.6931472f));
+    // a step that lands on (or beyond) an end of the bracket falls back to
+    // bisection: a clamped step of exactly x2 / x0.5 between two earlier
+    // iterates would otherwise cycle
+    const bool small = Gp > 0.f && fabsf(hn - h) < g.tol * h;
+    if (!small && (!(hn > lo && hn < hi) || !(Gp > 0.f))) hn = (hi < INFINITY) ? 0.5f * (lo + hi) : 2.f * h;
+    if (G == 0.f) hn = h;
+    const bool done = fabsf(hn - h) < g.tol * h;
+    if (done || g.last) {
+      const float H = GK32 * h;
+      const float iH = 1.f / H;
+      const float C3 = KNORM32 * iH * iH * iH;
+      const float rho = C3 * S_mw;
+      const float drho = -C3 / h * S_md;
+      const float fg = 1.f / (1.f + h / (3.f * rho) * drho);
+      float P, A, u;
+      const float rg = __powf(rho, g.gamma);
+      if (g.from_u) {
+        u = g.u[i];
+        P = (g.gamma - 1.f) * rho * u;
+        A = P / rg;
+        g.A[i] = A;
+      } else {
+        A = g.A[i];
+        P = A * rg;
+        u = P / ((g.gamma - 1.f) * rho);
+        if (g.u) g.u[i] = u;
+      }
+      const float cs = sqrtf(g.gamma * P / rho);
+      const float C4 = C3 * iH;
+      const float dv = -C4 * g.sums[4 * g.n_active + k] / rho;
+      const float cx = C4 * g.sums[5 * g.n_active + k] / rho;
+      const float cy = C4 * g.sums[6 * g.n_active + k] / rho;
+      const float cz = C4 * g.sums[7 * g.n_active + k] / rho;
+      const float adv = fabsf(dv);
+      const float acu = sqrtf(fmaf(cz, cz, fmaf(cy, cy, cx * cx)));
+      const float Bs = adv > 0.f ? adv / (adv + acu + g.eps * cs / h) : 0.f;
+      g.rho[i] = rho;
+      g.drho_dh[i] = drho;
+      g.f[i] = fg;
+      g.divv[i] = dv;
+      g.curlx[i] = cx;
+      g.curly[i] = cy;
+      g.curlz[i] = cz;
+      g.P[i] = P;
+      g.c[i] = cs;
+      g.B[i] = Bs;
+      if (g.nngb) g.nngb[i] = g.act_cnt[k];
+      g.jth[i] = make_float4(rho, fg * P / (rho * rho), cs, Bs);
+      finished += g.act_cnt[k];
+      g.conv[k] = 1;
+      if (!done) ++unconv;
+    } else {
+      g.hlo[k] = lo;
+      g.hhi[k] = hi;
+      g.h[i] = hn;
+      const float Hn = GK32 * hn;
+      g.pos4[i].w = Hn;
+      g.chunk_todo[g.chunk_of[k]] = 1;
+      ++unconv;
+      const Chunk ch = g.chunks[g.chunk_of[k]];
+      if (Hn > g.act_hmax[ch.act_leaf] * g.reach) atomicOr(g.rebuild, 1);
+      if (Hn > g.box_quarter) atomicOr(g.rebuild, 2);
+    }
+  }
+  finished = wave_sum_i(finished);
+  unconv = wave_sum_i(unconv);
+  if ((threadIdx.x & 63) == 0) {
+    if (finished) atomicAdd(g.ctr, (unsigned long long)finished);
+    if (unconv) atomicAdd(g.n_unconv, unconv);
+  }
+}
+
+__global__ __launch_bounds__(256) void ghost_kernel(GhostArgs g) { ghost_body(g); }
+
+// Several boxes in one launch: box blockIdx.y.
+__global__ __launch_bounds__(256) void ghost_multi_kernel(const GhostArgs *__restrict__ boxes) {
+  const GhostArgs g = boxes[blockIdx.y];
+  ghost_body(g);
+}
+
+// ---------------------------------------------------------------- density pass phases
+
+// Checks the arrays, resets the pass counters and, with active particles,
+// sizes the solver state and marks every chunk to do.  Returns SPH_OK with
+// *any = 0 when nothing is active (the pass is then complete).
+sph_status density_begin(sph_ctx *ctx, const sph_particles *p, int entropy_from_u, int *any) {
+  *any = 0;
   if (!p->vx || !p->vy || !p->vz || !p->m || !p->h)
     return sph_fail(ctx, SPH_EINVAL, "density_pass: v, m and h are required");
   if (!p->rho || !p->drho_dh || !p->f_gradh || !p->divv || !p->curlx || !p->curly || !p->curlz || !p->P || !p->c ||
       !p->balsara || !p->A)
     return sph_fail(ctx, SPH_EINVAL, "density_pass: an output array is missing");
   if (entropy_from_u && !p->u) return sph_fail(ctx, SPH_EINVAL, "density_pass: u is required with entropy_from_u");
-  const int64_t n = ctx->n, na = ctx->n_active;
+  const int64_t na = ctx->n_active;
+  ctx->density_from_u = entropy_from_u ? 1 : 0;
   ctx->density_iterations = 0;
   ctx->n_unconverged = 0;
   ctx->pair_rebuilds = 0;
   for (int q = 0; q < 32; ++q) ctx->unconv_hist[q] = 0;
-  (void)n;
   if (na == 0) {
     ctx->state = 4;
     return SPH_OK;
@@ -269,92 +401,144 @@ sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u)
         (uint8_t *)ctx->conv.p);
   }
   HIP_TRY(ctx, hipGetLastError());
+  *any = 1;
+  return SPH_OK;
+}
 
+LoopArgs density_loop_args(sph_ctx *ctx) {
+  LoopArgs a = base_args(ctx);
+  a.pair_off = (const int32_t *)ctx->dpair_off.p;
+  a.pairs = (const PairEntry *)ctx->dpairs.p;
+  a.sums = (float *)ctx->sums.p;
+  a.act_cnt = (int32_t *)ctx->sums.p + 8 * ctx->n_active;
+  return a;
+}
+
+// Ghost arguments of Newton pass `it`; the pass counters go to status[0]
+// (unconverged) and status[1] (rebuild flags).
+GhostArgs density_ghost_args(sph_ctx *ctx, sph_particles *p, int it, int entropy_from_u, int32_t *status) {
+  const int64_t na = ctx->n_active;
+  GhostArgs gh;
+  gh.n_active = na;
+  gh.active_idx = (const int32_t *)ctx->active_idx.p;
+  gh.chunk_of = (const int32_t *)ctx->chunk_of.p;
+  gh.chunks = (const Chunk *)ctx->chunks.p;
+  gh.chunk_todo = (int32_t *)ctx->chunk_todo.p;
+  gh.sums = (const float *)ctx->sums.p;
+  gh.act_cnt = (const int32_t *)ctx->sums.p + 8 * na;
+  gh.act_hmax = (const float *)ctx->act_hmax.p;
+  gh.hlo = (float *)ctx->hlo.p;
+  gh.hhi = (float *)ctx->hhi.p;
+  gh.conv = (uint8_t *)ctx->conv.p;
+  gh.pos4 = (float4 *)ctx->pos4.p;
+  gh.jth = (float4 *)ctx->jth.p;
+  gh.h = p->h;
+  gh.last = it == ctx->prm.h_max_iter;
+  gh.from_u = entropy_from_u;
+  gh.eta3 = ctx->prm.eta * ctx->prm.eta * ctx->prm.eta;
+  gh.kc = (float)((8.0 / M_PI) / ((double)GK32 * GK32 * GK32));
+  gh.tol = ctx->prm.h_tol;
+  gh.gamma = (float)ctx->prm.gamma;
+  gh.eps = ctx->prm.balsara_eps;
+  gh.box_quarter = (float)(0.25 * ctx->prm.box);
+  gh.reach = ctx->dpair_slack;
+  gh.rho = p->rho;
+  gh.drho_dh = p->drho_dh;
+  gh.f = p->f_gradh;
+  gh.divv = p->divv;
+  gh.curlx = p->curlx;
+  gh.curly = p->curly;
+  gh.curlz = p->curlz;
+  gh.P = p->P;
+  gh.c = p->c;
+  gh.B = p->balsara;
+  gh.A = p->A;
+  gh.u = p->u;
+  gh.nngb = p->nngb_density;
+  gh.n_unconv = status;
+  gh.rebuild = status + 1;
+  gh.ctr = (unsigned long long *)ctx->counters64.p;
+  return gh;
+}
+
+// Book-keeping after Newton pass `it` with the ghost's counters st: returns
+// SPH_OK with *done = 1 when the solve is over; widens the pair lists when a
+// smoothing length outgrew them.
+sph_status density_after_pass(sph_ctx *ctx, int it, const int32_t st[2], int *done) {
+  *done = 0;
+  ctx->density_iterations = it;
+  if (it <= 32) ctx->unconv_hist[it - 1] = st[0];
+  if (st[1] & 2) return sph_fail(ctx, SPH_EREBUILD, "density_pass: a smoothing length exceeds a quarter of the box");
+  if (it == ctx->prm.h_max_iter) {
+    ctx->n_unconverged = st[0];
+    *done = 1;
+    return SPH_OK;
+  }
+  if (st[0] == 0) {
+    *done = 1;
+    return SPH_OK;
+  }
+  if (st[1] & 1) {
+    // a smoothing length outgrew its cell's pair reach: widen the pair lists
+    ctx->pair_rebuilds++;
+    SPH_TRY(refresh_leaf_hmax(ctx, false));
+    SPH_TRY(build_pairs(ctx, 0, 1.5f));
+  }
+  return SPH_OK;
+}
+
+// Leaf max H follows the new smoothing lengths, so that any later cell-pair
+// list (the force list, or a later active set without a rebuild) sees them.
+sph_status density_end(sph_ctx *ctx, bool read_global) {
+  SPH_TRY(refresh_leaf_hmax(ctx, read_global));
+  ctx->state = 4;
+  if (ctx->n_unconverged > 0)
+    return sph_fail(ctx, SPH_ENOCONV, "density_pass: %lld particles not converged after %d iterations",
+                    (long long)ctx->n_unconverged, ctx->prm.h_max_iter);
+  return SPH_OK;
+}
+
+sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u) {
+  int any;
+  SPH_TRY(density_begin(ctx, p, entropy_from_u, &any));
+  if (!any) return SPH_OK;
   int32_t *sc = (int32_t *)ctx->scalars.p;
-  const float G = (float)ctx->prm.gamma;
-  const double kc = (8.0 / M_PI) / ((double)GK32 * GK32 * GK32);
-  const int maxit = ctx->prm.h_max_iter;
-  for (int it = 1; it <= maxit; ++it) {
-    LoopArgs a = base_args(ctx);
-    a.pair_off = (const int32_t *)ctx->dpair_off.p;
-    a.pairs = (const PairEntry *)ctx->dpairs.p;
-    a.sums = (float *)ctx->sums.p;
-    a.act_cnt = (int32_t *)ctx->sums.p + 8 * na;
+  for (int it = 1; it <= ctx->prm.h_max_iter; ++it) {
+    LoopArgs a = density_loop_args(ctx);
     if (ctx->prm.compensated)
       SPH_TRY((launch_loop<0, true>(ctx, a)));
     else
       SPH_TRY((launch_loop<0, false>(ctx, a)));
     HIP_TRY(ctx, hipMemsetAsync(sc + SC_UNCONV, 0, 8, ctx->stream));
-    GhostArgs gh;
-    gh.n_active = na;
-    gh.active_idx = (const int32_t *)ctx->active_idx.p;
-    gh.chunk_of = (const int32_t *)ctx->chunk_of.p;
-    gh.chunks = (const Chunk *)ctx->chunks.p;
-    gh.chunk_todo = (int32_t *)ctx->chunk_todo.p;
-    gh.sums = (const float *)ctx->sums.p;
-    gh.act_cnt = (const int32_t *)ctx->sums.p + 8 * na;
-    gh.act_hmax = (const float *)ctx->act_hmax.p;
-    gh.hlo = (float *)ctx->hlo.p;
-    gh.hhi = (float *)ctx->hhi.p;
-    gh.conv = (uint8_t *)ctx->conv.p;
-    gh.pos4 = (float4 *)ctx->pos4.p;
-    gh.jth = (float4 *)ctx->jth.p;
-    gh.h = p->h;
-    gh.last = it == maxit;
-    gh.from_u = entropy_from_u;
-    gh.eta3 = ctx->prm.eta * ctx->prm.eta * ctx->prm.eta;
-    gh.kc = (float)kc;
-    gh.tol = ctx->prm.h_tol;
-    gh.gamma = G;
-    gh.eps = ctx->prm.balsara_eps;
-    gh.box_quarter = (float)(0.25 * ctx->prm.box);
-    gh.reach = ctx->dpair_slack;
-    gh.rho = p->rho;
-    gh.drho_dh = p->drho_dh;
-    gh.f = p->f_gradh;
-    gh.divv = p->divv;
-    gh.curlx = p->curlx;
-    gh.curly = p->curly;
-    gh.curlz = p->curlz;
-    gh.P = p->P;
-    gh.c = p->c;
-    gh.B = p->balsara;
-    gh.A = p->A;
-    gh.u = p->u;
-    gh.nngb = p->nngb_density;
-    gh.n_unconv = sc + SC_UNCONV;
-    gh.rebuild = sc + SC_REBUILD;
-    gh.ctr = (unsigned long long *)ctx->counters64.p;
+    GhostArgs gh = density_ghost_args(ctx, p, it, entropy_from_u, sc + SC_UNCONV);
     {
       PROF(ctx, "ghost");
-      ghost_kernel<<<grid256(na), 256, 0, ctx->stream>>>(gh);
+      ghost_kernel<<<grid256(ctx->n_active), 256, 0, ctx->stream>>>(gh);
     }
     HIP_TRY(ctx, hipGetLastError());
     int32_t st[2];
     SPH_TRY(read_scalars(ctx, SC_UNCONV, 2, st));
-    ctx->density_iterations = it;
-    if (it <= 32) ctx->unconv_hist[it - 1] = st[0];
-    if (st[1] & 2) return sph_fail(ctx, SPH_EREBUILD, "density_pass: a smoothing length exceeds a quarter of the box");
-    if (gh.last) {
-      ctx->n_unconverged = st[0];
-      break;
-    }
-    if (st[0] == 0) break;
-    if (st[1] & 1) {
-      // a smoothing length outgrew its cell's pair reach: widen the pair lists
-      ctx->pair_rebuilds++;
-      SPH_TRY(refresh_leaf_hmax(ctx, false));
-      SPH_TRY(build_pairs(ctx, 0, 1.5f));
-    }
+    int done;
+    SPH_TRY(density_after_pass(ctx, it, st, &done));
+    if (done) break;
   }
-  // leaf max H follows the new smoothing lengths, so that any later cell-pair
-  // list (the force list, or a later active set without a rebuild) sees them
-  SPH_TRY(refresh_leaf_hmax(ctx, true));
-  ctx->state = 4;
-  if (ctx->n_unconverged > 0)
-    return sph_fail(ctx, SPH_ENOCONV, "density_pass: %lld particles not converged after %d iterations",
-                    (long long)ctx->n_unconverged, maxit);
-  return SPH_OK;
+  return density_end(ctx, true);
+}
+
+// Force loop arguments with the outputs of p.
+LoopArgs force_loop_args(sph_ctx *ctx, sph_particles *p) {
+  LoopArgs a = base_args(ctx);
+  a.pair_off = (const int32_t *)ctx->fpair_off.p;
+  a.pairs = (const PairEntry *)ctx->fpairs.p;
+  a.ax_out = p->ax;
+  a.ay_out = p->ay;
+  a.az_out = p->az;
+  a.dA_out = p->dA_dt;
+  a.du_out = p->du_dt;
+  a.vsig_out = p->vsig;
+  a.nngb_out = p->nngb_force;
+  a.ctr = (unsigned long long *)ctx->counters64.p + 1;
+  return a;
 }
 
 sph_status force_pass_impl(sph_ctx *ctx, sph_particles *p) {
@@ -370,17 +554,7 @@ sph_status force_pass_impl(sph_ctx *ctx, sph_particles *p) {
   SPH_TRY(build_pairs(ctx, 1, 1.0f));
   fill_i32_kernel<<<grid256(ctx->n_chunks), 256, 0, ctx->stream>>>((int32_t *)ctx->chunk_todo.p, ctx->n_chunks, 1);
   HIP_TRY(ctx, hipGetLastError());
-  LoopArgs a = base_args(ctx);
-  a.pair_off = (const int32_t *)ctx->fpair_off.p;
-  a.pairs = (const PairEntry *)ctx->fpairs.p;
-  a.ax_out = p->ax;
-  a.ay_out = p->ay;
-  a.az_out = p->az;
-  a.dA_out = p->dA_dt;
-  a.du_out = p->du_dt;
-  a.vsig_out = p->vsig;
-  a.nngb_out = p->nngb_force;
-  a.ctr = (unsigned long long *)ctx->counters64.p + 1;
+  LoopArgs a = force_loop_args(ctx, p);
   if (ctx->prm.compensated)
     SPH_TRY((launch_loop<1, true>(ctx, a)));
   else
@@ -522,12 +696,13 @@ extern "C" sph_status sph_load_tuning(sph_ctx *ctx, const char *path) {
   long long nc;
   int loaded = 0;
   while (fscanf(f, "%31s %d %d %d %d %d %d %f %lld", tag, &mode, &cls, &nw, &tile, &ord, &pers, &ms, &nc) == 9) {
-    if (strcmp(tag, "best") != 0 || mode < 0 || mode > 1 || cls < 0 || cls > 31) continue;
+    const bool single = strcmp(tag, "best") == 0, batch = strcmp(tag, "batch_best") == 0;
+    if ((!single && !batch) || mode < 0 || mode > 1 || cls < 0 || cls > 31) continue;
     LoopConfig c;
     c.nw = nw;
     c.tile = tile;
     if (!loop_config_valid(c)) continue;
-    auto &t = ctx->tune[mode][cls];
+    auto &t = single ? ctx->tune[mode][cls] : ctx->btune[mode][cls];
     t.valid = 1;
     t.nw = nw;
     t.tile = tile;
@@ -538,4 +713,401 @@ extern "C" sph_status sph_load_tuning(sph_ctx *ctx, const char *path) {
   }
   fclose(f);
   return loaded > 0 ? SPH_OK : sph_fail(ctx, SPH_EINVAL, "load_tuning: no entries in %s", path);
+}
+
+// ---------------------------------------------------------------- batched passes
+//
+// Several contexts (independent periodic boxes, each built, sorted and marked
+// by its own calls, all on one stream) run each loop pass as ONE launch over
+// the concatenated work items (box, chunk), ordered by decreasing cost (staged
+// partner particles of the chunk's leaf), pulled from one atomic counter by a
+// machine-sized grid (persistent) or one workgroup per item.  The per-chunk
+// work is the single-box chunk body, so a box's results equal those of its
+// own pass run with the same loop tiling.
+
+namespace {
+
+struct BatchItems {
+  const Chunk *chunks;
+  const int32_t *act_cost;
+  int32_t *todo;
+  int64_t n_chunks;
+  int64_t off;  // first work item of this box
+  int32_t box;  // index into the launch's box descriptors
+};
+
+__global__ __launch_bounds__(256) void batch_bucket_kernel(const BatchItems *__restrict__ boxes,
+                                                           int32_t *__restrict__ bucket_of,
+                                                           int32_t *__restrict__ hist, int set_todo) {
+  __shared__ int h[32];
+  if (threadIdx.x < 32) h[threadIdx.x] = 0;
+  __syncthreads();
+  const BatchItems b = boxes[blockIdx.y];
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < b.n_chunks; q += (int64_t)gridDim.x * 256) {
+    const int cost = max(1, b.act_cost[b.chunks[q].act_leaf]);
+    const int k = __clz(cost);
+    bucket_of[b.off + q] = k;
+    atomicAdd(&h[k], 1);
+    if (set_todo) b.todo[q] = 1;
+  }
+  __syncthreads();
+  if (threadIdx.x < 32 && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ __launch_bounds__(256) void batch_scatter_kernel(const BatchItems *__restrict__ boxes,
+                                                            const int32_t *__restrict__ bucket_of,
+                                                            int32_t *__restrict__ cursor, int2 *__restrict__ work) {
+  const BatchItems b = boxes[blockIdx.y];
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < b.n_chunks; q += (int64_t)gridDim.x * 256)
+    work[atomicAdd(&cursor[bucket_of[b.off + q]], 1)] = make_int2(b.box, (int)q);
+}
+
+__global__ __launch_bounds__(256) void batch_todo_kernel(const BatchItems *__restrict__ boxes) {
+  const BatchItems b = boxes[blockIdx.y];
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < b.n_chunks; q += (int64_t)gridDim.x * 256)
+    b.todo[q] = 1;
+}
+
+unsigned grid_x_for(int64_t n) {
+  int64_t g = ceil_div(n, 256);
+  if (g > 1024) g = 1024;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+// Host staging: [LoopArgs x nb | GhostArgs x nb | BatchItems x nb], rewritten
+// only after the stream has drained past the previous upload.
+struct Staging {
+  LoopArgs *args;
+  GhostArgs *ghost;
+  BatchItems *items;
+};
+
+Staging staging(sph_ctx *lead, int nb) {
+  const size_t need = (sizeof(LoopArgs) + sizeof(GhostArgs) + sizeof(BatchItems)) * (size_t)nb;
+  if (lead->batch_host.size() < need) lead->batch_host.resize(need);
+  char *base = lead->batch_host.data();
+  Staging s;
+  s.args = reinterpret_cast<LoopArgs *>(base);
+  s.ghost = reinterpret_cast<GhostArgs *>(base + sizeof(LoopArgs) * nb);
+  s.items = reinterpret_cast<BatchItems *>(base + (sizeof(LoopArgs) + sizeof(GhostArgs)) * nb);
+  return s;
+}
+
+LoopConfig batch_config(sph_ctx *lead, int mode, int64_t total) {
+  const auto &t = lead->btune[mode][tune_class(total)];
+  LoopConfig c;
+  c.ordered = 1;
+  if (t.valid) {
+    c.nw = t.nw;
+    c.tile = t.tile;
+    c.persistent = t.persistent;
+    return c;
+  }
+  c.persistent = 1;
+  if (lead->prm.waves_per_chunk > 0) {
+    const LoopConfig s = choose_config(lead, mode);  // the parameter rule
+    c.nw = s.nw;
+    c.tile = s.tile;
+    return c;
+  }
+  if (total < 2048) {
+    c.nw = 8, c.tile = 0;
+  } else if (total < 8192) {
+    c.nw = 4, c.tile = 1;
+  } else if (total < 32768) {
+    c.nw = 2, c.tile = 2;
+  } else {
+    c.nw = 1, c.tile = 2;
+  }
+  return c;
+}
+
+sph_status batch_fail(sph_ctx *lead, int b, sph_ctx *box, sph_status st) {
+  if (box != lead) return sph_fail(lead, st, "box %d: %s", b, box->err.c_str());
+  return st;
+}
+
+#define BATCH_TRY(b, expr)                                   \
+  do {                                                       \
+    sph_status _s = (expr);                                  \
+    if (_s != SPH_OK) return batch_fail(lead, (b), cs[(b)], _s); \
+  } while (0)
+
+// Uploads the item descriptors of the boxes in `live` and writes the
+// cost-ordered work list; returns the number of items.
+sph_status batch_work_list(sph_ctx *lead, sph_ctx **cs, const std::vector<int> &live, Staging &s, int set_todo,
+                           int64_t *total_out) {
+  const int nl = (int)live.size();
+  int64_t total = 0, maxc = 0;
+  for (int q = 0; q < nl; ++q) {
+    sph_ctx *c = cs[live[q]];
+    s.items[q].chunks = (const Chunk *)c->chunks.p;
+    s.items[q].act_cost = (const int32_t *)c->act_cost.p;
+    s.items[q].todo = (int32_t *)c->chunk_todo.p;
+    s.items[q].n_chunks = c->n_chunks;
+    s.items[q].off = total;
+    s.items[q].box = q;
+    total += c->n_chunks;
+    if (c->n_chunks > maxc) maxc = c->n_chunks;
+  }
+  *total_out = total;
+  SPH_TRY(sph_ensure(lead, lead->batch_items, sizeof(BatchItems) * (size_t)nl));
+  SPH_TRY(sph_ensure(lead, lead->batch_work, sizeof(int2) * (size_t)(total > 0 ? total : 1)));
+  SPH_TRY(sph_ensure(lead, lead->batch_tmp, 4 * (size_t)(total + 64)));
+  HIP_TRY(lead, hipMemcpyAsync(lead->batch_items.p, s.items, sizeof(BatchItems) * nl, hipMemcpyHostToDevice,
+                               lead->stream));
+  int32_t *hist = (int32_t *)lead->batch_tmp.p;
+  int32_t *bucket_of = hist + 64;
+  HIP_TRY(lead, hipMemsetAsync(hist, 0, 32 * sizeof(int32_t), lead->stream));
+  PROF(lead, "cost_order");
+  const dim3 grid(grid_x_for(maxc), nl);
+  batch_bucket_kernel<<<grid, 256, 0, lead->stream>>>((const BatchItems *)lead->batch_items.p, bucket_of, hist,
+                                                      set_todo);
+  cost_bucket_scan_kernel<<<1, 64, 0, lead->stream>>>(hist);
+  batch_scatter_kernel<<<grid, 256, 0, lead->stream>>>((const BatchItems *)lead->batch_items.p, bucket_of, hist,
+                                                       (int2 *)lead->batch_work.p);
+  return sph_hip_check(lead, hipGetLastError(), "batch work list");
+}
+
+template <int MODE, bool COMP>
+sph_status batch_launch(sph_ctx *lead, const LoopConfig &cfg, int64_t total, const char *what) {
+  PROF(lead, what);
+  LoopArgs unused;
+  memset(&unused, 0, sizeof unused);
+  return sph_hip_check(lead,
+                       launch_loop_any<MODE, COMP>(lead->stream, unused, cfg, (const LoopArgs *)lead->batch_args.p,
+                                                   (const int2 *)lead->batch_work.p, (int)total,
+                                                   (int *)lead->scalars.p + SC_WORKCTR,
+                                                   persistent_grid_for(lead->n_cu, cfg)),
+                       what);
+}
+
+sph_status batch_check(sph_ctx **cs, int nb, int at_least, const char *call) {
+  if (!cs || nb < 1 || !cs[0]) return SPH_EINVAL;
+  sph_ctx *lead = cs[0];
+  for (int b = 0; b < nb; ++b) {
+    if (!cs[b]) return sph_fail(lead, SPH_EINVAL, "%s: context %d is null", call, b);
+    if (cs[b]->stream != lead->stream)
+      return sph_fail(lead, SPH_EINVAL, "%s: context %d is on another stream", call, b);
+    if (cs[b]->state < at_least)
+      return sph_fail(lead, SPH_ESTATE, "%s: box %d is not ready (state %d, need %d)", call, b, cs[b]->state,
+                      at_least);
+    for (int q = 0; q < b; ++q)
+      if (cs[q] == cs[b]) return sph_fail(lead, SPH_EINVAL, "%s: context %d appears twice", call, b);
+  }
+  return SPH_OK;
+}
+
+}  // namespace
+
+sph_status batch_density_impl(sph_ctx **cs, sph_particles *ps, int nb, int entropy_from_u) {
+  SPH_TRY(batch_check(cs, nb, 3, "batch_density_pass"));
+  sph_ctx *lead = cs[0];
+  HIP_TRY(lead, hipStreamSynchronize(lead->stream));
+  std::vector<int> live;
+  for (int b = 0; b < nb; ++b) {
+    int any;
+    BATCH_TRY(b, density_begin(cs[b], &ps[b], entropy_from_u, &any));
+    if (any) live.push_back(b);
+  }
+  if (live.empty()) return SPH_OK;
+  const int nl = (int)live.size();
+  Staging s = staging(lead, nl);
+  int64_t total;
+  SPH_TRY(batch_work_list(lead, cs, live, s, 0, &total));
+  SPH_TRY(sph_ensure(lead, lead->batch_args, sizeof(LoopArgs) * (size_t)nl));
+  SPH_TRY(sph_ensure(lead, lead->batch_ghost, sizeof(GhostArgs) * (size_t)nl));
+  SPH_TRY(sph_ensure(lead, lead->batch_status, 8 * (size_t)nl));
+  const LoopConfig cfg = batch_config(lead, 0, total);
+  std::vector<int> iterating(live);  // boxes (indices into cs) still solving
+  std::vector<int32_t> st(2 * (size_t)nl);
+  const int maxit = lead->prm.h_max_iter;
+  for (int b : live)
+    if (cs[b]->prm.h_max_iter != maxit)
+      return sph_fail(lead, SPH_EINVAL, "batch_density_pass: box %d has another h_max_iter", b);
+  for (int it = 1; it <= maxit && !iterating.empty(); ++it) {
+    // loop over every live box's chunks (finished boxes have no chunk to do)
+    for (int q = 0; q < nl; ++q) s.args[q] = density_loop_args(cs[live[q]]);
+    HIP_TRY(lead, hipMemcpyAsync(lead->batch_args.p, s.args, sizeof(LoopArgs) * nl, hipMemcpyHostToDevice,
+                                 lead->stream));
+    if (lead->prm.compensated)
+      SPH_TRY((batch_launch<0, true>(lead, cfg, total, "density_loop")));
+    else
+      SPH_TRY((batch_launch<0, false>(lead, cfg, total, "density_loop")));
+    // one ghost launch over the boxes still solving
+    int32_t *status = (int32_t *)lead->batch_status.p;
+    HIP_TRY(lead, hipMemsetAsync(status, 0, 8 * (size_t)nl, lead->stream));
+    int64_t max_na = 0;
+    const int ni = (int)iterating.size();
+    for (int q = 0; q < ni; ++q) {
+      sph_ctx *c = cs[iterating[q]];
+      s.ghost[q] = density_ghost_args(c, &ps[iterating[q]], it, entropy_from_u, status + 2 * q);
+      if (c->n_active > max_na) max_na = c->n_active;
+    }
+    HIP_TRY(lead, hipMemcpyAsync(lead->batch_ghost.p, s.ghost, sizeof(GhostArgs) * ni, hipMemcpyHostToDevice,
+                                 lead->stream));
+    {
+      PROF(lead, "ghost");
+      ghost_multi_kernel<<<dim3(grid_x_for(max_na), ni), 256, 0, lead->stream>>>(
+          (const GhostArgs *)lead->batch_ghost.p);
+    }
+    HIP_TRY(lead, hipGetLastError());
+    HIP_TRY(lead, hipMemcpyAsync(st.data(), status, 8 * (size_t)ni, hipMemcpyDeviceToHost, lead->stream));
+    HIP_TRY(lead, hipStreamSynchronize(lead->stream));
+    std::vector<int> next;
+    for (int q = 0; q < ni; ++q) {
+      const int b = iterating[q];
+      int done;
+      BATCH_TRY(b, density_after_pass(cs[b], it, &st[2 * q], &done));
+      if (!done) next.push_back(b);
+    }
+    iterating.swap(next);
+  }
+  // leaf max H per box, then one read-back of every box's running global max H
+  std::vector<int32_t> hb(nl);
+  for (int q = 0; q < nl; ++q) {
+    sph_ctx *c = cs[live[q]];
+    BATCH_TRY(live[q], refresh_leaf_hmax(c, false));
+    HIP_TRY(lead, hipMemcpyAsync(&hb[q], (int32_t *)c->scalars.p + SC_HMAX_BITS, 4, hipMemcpyDeviceToHost,
+                                 lead->stream));
+  }
+  HIP_TRY(lead, hipStreamSynchronize(lead->stream));
+  sph_status first = SPH_OK;
+  for (int q = 0; q < nl; ++q) {
+    sph_ctx *c = cs[live[q]];
+    float hg;
+    memcpy(&hg, &hb[q], 4);
+    c->hmax_global = hg;
+    const sph_status e = density_end(c, false);
+    if (e != SPH_OK && first == SPH_OK) first = batch_fail(lead, live[q], c, e);
+  }
+  return first;
+}
+
+sph_status batch_force_impl(sph_ctx **cs, sph_particles *ps, int nb) {
+  SPH_TRY(batch_check(cs, nb, 4, "batch_force_pass"));
+  sph_ctx *lead = cs[0];
+  for (int b = 0; b < nb; ++b)
+    if (!ps[b].ax || !ps[b].ay || !ps[b].az || !ps[b].dA_dt || !ps[b].du_dt || !ps[b].vsig)
+      return sph_fail(lead, SPH_EINVAL, "batch_force_pass: box %d: an output array is missing", b);
+  HIP_TRY(lead, hipStreamSynchronize(lead->stream));
+  std::vector<int> live;
+  for (int b = 0; b < nb; ++b) {
+    if (cs[b]->n_active == 0) {
+      cs[b]->n_fpairs = 0;
+      cs[b]->state = 5;
+    } else {
+      live.push_back(b);
+    }
+  }
+  if (live.empty()) return SPH_OK;
+  const int nl = (int)live.size();
+  // force cell pairs of every box with one synchronisation
+  std::vector<int32_t> np(nl);
+  for (int q = 0; q < nl; ++q) BATCH_TRY(live[q], build_pairs_count(cs[live[q]], 1, 1.0f, &np[q]));
+  HIP_TRY(lead, hipStreamSynchronize(lead->stream));
+  for (int q = 0; q < nl; ++q) BATCH_TRY(live[q], build_pairs_fill(cs[live[q]], 1, 1.0f, np[q]));
+  Staging s = staging(lead, nl);
+  int64_t total;
+  SPH_TRY(batch_work_list(lead, cs, live, s, 1, &total));
+  SPH_TRY(sph_ensure(lead, lead->batch_args, sizeof(LoopArgs) * (size_t)nl));
+  for (int q = 0; q < nl; ++q) s.args[q] = force_loop_args(cs[live[q]], &ps[live[q]]);
+  HIP_TRY(lead, hipMemcpyAsync(lead->batch_args.p, s.args, sizeof(LoopArgs) * nl, hipMemcpyHostToDevice,
+                               lead->stream));
+  const LoopConfig cfg = batch_config(lead, 1, total);
+  if (lead->prm.compensated)
+    SPH_TRY((batch_launch<1, true>(lead, cfg, total, "force_loop")));
+  else
+    SPH_TRY((batch_launch<1, false>(lead, cfg, total, "force_loop")));
+  for (int b : live) cs[b]->state = 5;
+  return SPH_OK;
+}
+
+sph_status batch_autotune_impl(sph_ctx **cs, sph_particles *ps, int nb, const char *path) {
+  SPH_TRY(batch_check(cs, nb, 5, "batch_autotune"));
+  sph_ctx *lead = cs[0];
+  HIP_TRY(lead, hipStreamSynchronize(lead->stream));
+  std::vector<int> live;
+  for (int b = 0; b < nb; ++b)
+    if (cs[b]->n_active > 0) live.push_back(b);
+  if (live.empty()) return SPH_OK;
+  const int nl = (int)live.size();
+  Staging s = staging(lead, nl);
+  int64_t total;
+  SPH_TRY(batch_work_list(lead, cs, live, s, 1, &total));
+  SPH_TRY(sph_ensure(lead, lead->batch_args, sizeof(LoopArgs) * (size_t)nl));
+  SPH_TRY(sph_ensure(lead, lead->batch_status, 8 * (size_t)nl + 64));
+  // counts of tuning launches are not interactions of a step
+  unsigned long long *scratch_ctr = (unsigned long long *)((char *)lead->batch_status.p + 8 * (size_t)nl);
+  const int cls = tune_class(total);
+  const int prof = lead->prof;
+  lead->prof = 0;
+  FILE *f = path ? fopen(path, "a") : nullptr;
+  hipEvent_t e0, e1;
+  HIP_TRY(lead, hipEventCreate(&e0));
+  HIP_TRY(lead, hipEventCreate(&e1));
+  sph_status st = SPH_OK;
+  for (int mode = 0; mode < 2 && st == SPH_OK; ++mode) {
+    HIP_TRY(lead, hipStreamSynchronize(lead->stream));
+    for (int q = 0; q < nl; ++q) {
+      s.args[q] = mode == 0 ? density_loop_args(cs[live[q]]) : force_loop_args(cs[live[q]], &ps[live[q]]);
+      if (mode == 1) s.args[q].ctr = scratch_ctr;
+    }
+    HIP_TRY(lead, hipMemcpyAsync(lead->batch_args.p, s.args, sizeof(LoopArgs) * nl, hipMemcpyHostToDevice,
+                                 lead->stream));
+    sph_ctx::TuneEntry best;
+    best.ms = INFINITY;
+    const int nws[4] = {1, 2, 4, 8};
+    for (int wi = 0; wi < 4 && st == SPH_OK; ++wi)
+      for (int tile = 0; tile <= 4 && st == SPH_OK; ++tile)
+        for (int pers = 0; pers <= 1 && st == SPH_OK; ++pers) {
+          LoopConfig c;
+          c.nw = nws[wi];
+          c.tile = tile;
+          c.ordered = 1;
+          c.persistent = pers;
+          if (!loop_config_valid(c)) continue;
+          float bestc = INFINITY;
+          for (int r = 0; r <= 2; ++r) {
+            batch_todo_kernel<<<dim3(grid_x_for(total), nl), 256, 0, lead->stream>>>(
+                (const BatchItems *)lead->batch_items.p);
+            HIP_TRY(lead, hipEventRecord(e0, lead->stream));
+            st = mode == 0 ? batch_launch<0, true>(lead, c, total, "tune") : batch_launch<1, true>(lead, c, total, "tune");
+            if (st != SPH_OK) break;
+            HIP_TRY(lead, hipEventRecord(e1, lead->stream));
+            HIP_TRY(lead, hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_TRY(lead, hipEventElapsedTime(&ms, e0, e1));
+            if (r > 0 && ms < bestc) bestc = ms;  // the first launch warms caches
+          }
+          if (st != SPH_OK) break;
+          if (f)
+            fprintf(f, "batch_candidate %d %d %d %d %d %d %.6f %lld\n", mode, cls, c.nw, c.tile, c.ordered,
+                    c.persistent, bestc, (long long)total);
+          if (bestc < best.ms) {
+            best.valid = 1;
+            best.nw = c.nw;
+            best.tile = c.tile;
+            best.ordered = 1;
+            best.persistent = c.persistent;
+            best.ms = bestc;
+          }
+        }
+    if (st == SPH_OK) {
+      lead->btune[mode][cls] = best;
+      if (f)
+        fprintf(f, "batch_best %d %d %d %d %d %d %.6f %lld\n", mode, cls, best.nw, best.tile, best.ordered,
+                best.persistent, best.ms, (long long)total);
+    }
+  }
+  if (f) fclose(f);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  lead->prof = prof;
+  if (st != SPH_OK) return st;
+  // leave every chunk marked done, as after a completed pass
+  for (int b : live)
+    HIP_TRY(lead, hipMemsetAsync(cs[b]->chunk_todo.p, 0, 4 * (size_t)cs[b]->n_chunks, lead->stream));
+  HIP_TRY(lead, hipStreamSynchronize(lead->stream));
+  return SPH_OK;
 }

@@ -31,7 +31,7 @@ struct AxisTab {
   float e[13][3];
 };
 
-AxisTab host_axes() {
+inline AxisTab host_axes() {
   AxisTab a;
   int k = 0;
   for (int dx = -1; dx <= 1; ++dx)
@@ -75,6 +75,20 @@ struct LoopArgs {
   int32_t *nngb_out;
   float half_alpha, gm1;
   unsigned long long *ctr;  // cumulative force interactions
+  // adjoint passes
+  const float4 *jw;     // loss weights (wx, wy, wz, 0) per particle
+  const float4 *jadj1;  // (rho_bar, drho_dh_bar, D_bar, lambda) per particle
+  const float4 *jadj2;  // (C_bar x, y, z, 0) per particle
+  float *outp;          // per-particle outputs, [q * n + i]
+};
+
+// Modes of the chunk body: 0 density loop, 1 force loop, 2 force adjoint,
+// 3 density adjoint (h derivatives and the implicit-h solve), 4 density
+// adjoint (position terms).  Symmetric modes run over r < max(H_i, H_j)
+// without the self pair; the others over r < H_i with the self pair.
+template <int MODE>
+struct ModeTraits {
+  static constexpr bool sym = MODE == 1 || MODE == 2 || MODE == 4;
 };
 
 __device__ __forceinline__ void kernel_w_dw(float q, float &w, float &wp) {
@@ -88,6 +102,14 @@ __device__ __forceinline__ void kernel_w_dw(float q, float &w, float &wp) {
   const bool in = q < 0.5f;
   w = in ? wi : wo;
   wp = in ? wpi : wpo;
+}
+
+// w' and w'' of the cubic spline (zero beyond q = 1).
+__device__ __forceinline__ void kernel_d1_d2(float q, float &wp, float &wpp) {
+  const float t = 1.f - q;
+  const bool in = q < 0.5f, sup = q < 1.f;
+  wp = in ? q * fmaf(18.f, q, -12.f) : (sup ? -6.f * t * t : 0.f);
+  wpp = in ? fmaf(36.f, q, -12.f) : (sup ? 12.f * t : 0.f);
 }
 
 __device__ __forceinline__ float kernel_dw_only(float q) {
@@ -131,7 +153,7 @@ __device__ __forceinline__ void wave_sync() {
 template <int MODE, int CAP, int LCAP>
 struct WaveLds {
   static constexpr int cand = CAP * 16;
-  static constexpr int candH = MODE == 1 ? CAP * 4 : 0;
+  static constexpr int candH = ModeTraits<MODE>::sym ? CAP * 4 : 0;
   static constexpr int lists = LCAP * 64 * 2;
   static constexpr int bytes = cand + candH + lists;
   static_assert(bytes >= 10 * 64 * 4, "room for the cross-wave reduction");
@@ -163,7 +185,14 @@ __device__ __forceinline__ void chunk_body(const LoopArgs &g, int cid, char *lds
   const float invHi = live ? 1.f / Hi : 0.f;
   const float4 vi = live ? g.jvm[i] : make_float4(0.f, 0.f, 0.f, 0.f);
   float4 thi = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (MODE == 1 && live) thi = g.jth[i];
+  if ((MODE == 1 || MODE == 2) && live) thi = g.jth[i];
+  float4 wi = make_float4(0.f, 0.f, 0.f, 0.f), adj1i = wi, adj2i = wi;
+  if (MODE == 2 && live) wi = g.jw[i];
+  if (MODE == 4 && live) {
+    adj1i = g.jadj1[i];
+    adj2i = g.jadj2[i];
+  }
+  const float hi_ = Hi * (1.f / GK32);
 
   // chunk bounding box and reach
   const float bminx = wave_min_f(live ? pi.x : INFINITY), bmaxx = wave_max_f(live ? pi.x : -INFINITY);
@@ -213,6 +242,104 @@ __device__ __forceinline__ void chunk_body(const LoopArgs &g, int cid, char *lds
           acc[6] = fmaf(fac, fmaf(vz, dx, -vx * dz), acc[6]);
           acc[7] = fmaf(fac, fmaf(vx, dy, -vy * dx), acc[7]);
           cnt += (j != i);
+        } else if (MODE == 2) {
+          // force adjoint: both orders (i,j) and (j,i) of the pair
+          const float Hj = candH[c];
+          const float invHj = __builtin_amdgcn_rcpf(Hj);
+          const float4 th = g.jth[j];
+          const float4 wj = g.jw[j];
+          const float qi = r * invHi, qj = r * invHj;
+          float wpi, wppi, wpj, wppj;
+          kernel_d1_d2(qi, wpi, wppi);
+          kernel_d1_d2(qj, wpj, wppj);
+          const float C4i = KNORM32 * (invHi * invHi) * (invHi * invHi);
+          const float C4j = KNORM32 * (invHj * invHj) * (invHj * invHj);
+          const float Fi = C4i * wpi * rinv, Fj = C4j * wpj * rinv;
+          const float Fri = C4i * rinv * fmaf(wppi, invHi, -wpi * rinv);
+          const float Frj = C4j * rinv * fmaf(wppj, invHj, -wpj * rinv);
+          const float Fhi = -C4i * fmaf(qi, wppi, 4.f * wpi) * rinv * (GK32 * invHi);
+          const float mi = vi.w;
+          const bool appr = vr < 0.f;
+          const float mu = appr ? vr * rinv : 0.f;
+          const float vsig = thi.z + th.z - 3.f * mu;
+          const float rs = __builtin_amdgcn_rcpf(thi.x + th.x);
+          const float Bs = thi.w + th.w;
+          const float Pi = -g.half_alpha * vsig * mu * Bs * rs;
+          const float Pc = -g.half_alpha * mu * Bs * rs;
+          const float PB = -g.half_alpha * vsig * mu * rs;
+          const float Pr = -Pi * rs;
+          const float Pm = appr ? -g.half_alpha * Bs * rs * (vsig - 3.f * mu) : 0.f;
+          const float Fb = 0.5f * (Fi + Fj);
+          const float S = fmaf(thi.y, Fi, fmaf(th.y, Fj, Pi * Fb));
+          const float wdi = fmaf(wi.z, dz, fmaf(wi.y, dy, wi.x * dx));
+          const float wdj = fmaf(wj.z, dz, fmaf(wj.y, dy, wj.x * dx));
+          const float sb = fmaf(mi, wdj, -mj * wdi);
+          const float dS = fmaf(thi.y + 0.5f * Pi, Fri, (th.y + 0.5f * Pi) * Frj);
+          const float cv = sb * Fb * Pm * rinv;
+          const float cd = sb * dS * rinv - cv * mu * rinv;
+          acc[0] = fmaf(S, fmaf(mi, wj.x, -mj * wi.x), fmaf(cd, dx, fmaf(cv, vx, acc[0])));
+          acc[1] = fmaf(S, fmaf(mi, wj.y, -mj * wi.y), fmaf(cd, dy, fmaf(cv, vy, acc[1])));
+          acc[2] = fmaf(S, fmaf(mi, wj.z, -mj * wi.z), fmaf(cd, dz, fmaf(cv, vz, acc[2])));
+          acc[3] = fmaf(sb, Fi, acc[3]);
+          acc[4] = fmaf(sb * (thi.y + 0.5f * Pi), Fhi, acc[4]);
+          acc[5] = fmaf(sb * Fb, Pc, acc[5]);
+          acc[6] = fmaf(sb * Fb, PB, acc[6]);
+          acc[7] = fmaf(sb * Fb, Pr, acc[7]);
+          ++cnt;
+        } else if (MODE == 3) {
+          // h derivatives of the density sums (self pair included)
+          const float q = r * invHi;
+          float w, wp, wpp;
+          kernel_w_dw(q, w, wp);
+          float wp2;
+          kernel_d1_d2(q, wp2, wpp);
+          acc[0] += w;
+          acc[1] += fmaf(q, wp, 3.f * w);
+          acc[2] = fmaf(mj, fmaf(q * q, wpp, fmaf(8.f * q, wp, 12.f * w)), acc[2]);
+          const float t = mj * fmaf(q, wpp, 4.f * wp) * rinv;
+          acc[3] = fmaf(t, vr, acc[3]);
+          acc[4] = fmaf(t, fmaf(vy, dz, -vz * dy), acc[4]);
+          acc[5] = fmaf(t, fmaf(vz, dx, -vx * dz), acc[5]);
+          acc[6] = fmaf(t, fmaf(vx, dy, -vy * dx), acc[6]);
+          cnt += (j != i);
+        } else if (MODE == 4) {
+          // position terms of the density sums and of the h constraint, both orders
+          const float Hj = candH[c];
+          const float invHj = __builtin_amdgcn_rcpf(Hj);
+          const float4 a1 = g.jadj1[j];
+          const float4 a2 = g.jadj2[j];
+          const float qi = r * invHi, qj = r * invHj;
+          float wpi, wppi, wpj, wppj;
+          kernel_d1_d2(qi, wpi, wppi);
+          kernel_d1_d2(qj, wpj, wppj);
+          const float C4i = KNORM32 * (invHi * invHi) * (invHi * invHi);
+          const float C4j = KNORM32 * (invHj * invHj) * (invHj * invHj);
+          const float Fi = C4i * wpi * rinv, Fj = C4j * wpj * rinv;
+          const float Fri = C4i * rinv * fmaf(wppi, invHi, -wpi * rinv);
+          const float Frj = C4j * rinv * fmaf(wppj, invHj, -wpj * rinv);
+          const float Fhi = -C4i * fmaf(qi, wppi, 4.f * wpi) * rinv * (GK32 * invHi);
+          const float Fhj = -C4j * fmaf(qj, wppj, 4.f * wpj) * rinv * (GK32 * invHj);
+          const float mi = vi.w;
+          const float hj_ = Hj * (1.f / GK32);
+          const float hi3 = hi_ * hi_ * hi_, hj3 = hj_ * hj_ * hj_;
+          // C_bar x v and C_bar . (v x d) for both owners
+          const float cxv = fmaf(vy, dz, -vz * dy), cyv = fmaf(vz, dx, -vx * dz), czv = fmaf(vx, dy, -vy * dx);
+          const float ti = fmaf(adj2i.z, czv, fmaf(adj2i.y, cyv, adj2i.x * cxv));
+          const float tj = fmaf(a2.z, czv, fmaf(a2.y, cyv, a2.x * cxv));
+          const float ai = fmaf(adj1i.x * mj, Fi, fmaf(adj1i.y * mj, Fhi, -adj1i.w * hi3 * Fi));
+          const float aj = fmaf(a1.x * mi, Fj, fmaf(a1.y * mi, Fhj, -a1.w * hj3 * Fj));
+          // G_ij - G_ji = (ai + aj) d + (Di mj Fi + Dj mi Fj) v + (Di mj vr Fri + mj ti Fri
+          //               + Dj mi vr Frj + mi tj Frj) d / r + mj Fi (Ci x v) + mi Fj (Cj x v)
+          const float sv = fmaf(adj1i.z * mj, Fi, a1.z * mi * Fj);
+          const float se = (ai + aj) + rinv * fmaf(mj * fmaf(adj1i.z, vr, ti), Fri, mi * fmaf(a1.z, vr, tj) * Frj);
+          const float ci = mj * Fi, cj = mi * Fj;
+          const float gxv = fmaf(ci, fmaf(adj2i.y, vz, -adj2i.z * vy), cj * fmaf(a2.y, vz, -a2.z * vy));
+          const float gyv = fmaf(ci, fmaf(adj2i.z, vx, -adj2i.x * vz), cj * fmaf(a2.z, vx, -a2.x * vz));
+          const float gzv = fmaf(ci, fmaf(adj2i.x, vy, -adj2i.y * vx), cj * fmaf(a2.x, vy, -a2.y * vx));
+          acc[0] = fmaf(se, dx, fmaf(sv, vx, gxv + acc[0]));
+          acc[1] = fmaf(se, dy, fmaf(sv, vy, gyv + acc[1]));
+          acc[2] = fmaf(se, dz, fmaf(sv, vz, gzv + acc[2]));
+          ++cnt;
         } else {
           const float Hj = candH[c];
           const float invHj = __builtin_amdgcn_rcpf(Hj);
@@ -265,7 +392,7 @@ __device__ __forceinline__ void chunk_body(const LoopArgs &g, int cid, char *lds
         const float dx = pi.x - cj.x, dy = pi.y - cj.y, dz = pi.z - cj.z;
         const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
         bool hit;
-        if (MODE == 0) {
+        if (!ModeTraits<MODE>::sym) {
           hit = r2 < H2i;
         } else {
           const float Hj = candH[c];
@@ -288,7 +415,7 @@ __device__ __forceinline__ void chunk_body(const LoopArgs &g, int cid, char *lds
     const int B = e.b;
     const int bb = g.leaf_begin[B], bc = g.leaf_count[B];
     const bool selfp = (B == ch.leaf);
-    const float Rb = MODE == 0 ? Rc : fmaxf(Rc, g.leaf_hmax[B]);
+    const float Rb = !ModeTraits<MODE>::sym ? Rc : fmaxf(Rc, g.leaf_hmax[B]);
     // sweep axis: the stencil direction closest to the pair offset
     int axis = 0;
     float best = -1.f, sgn = 1.f;
@@ -328,7 +455,7 @@ __device__ __forceinline__ void chunk_body(const LoopArgs &g, int cid, char *lds
       const float gz = fmaxf(fmaxf(bminz - zj, zj - bmaxz), 0.f);
       const float d2 = fmaf(gz, gz, fmaf(gy, gy, gx * gx));
       bool keep;
-      if (MODE == 0)
+      if (!ModeTraits<MODE>::sym)
         keep = valid && d2 < R2c;
       else
         keep = valid && (d2 < R2c || d2 < pj.w * pj.w);
@@ -336,7 +463,7 @@ __device__ __forceinline__ void chunk_body(const LoopArgs &g, int cid, char *lds
       if (keep) {
         const int slot = ncand + rank_below(mask);
         cand[slot] = make_float4(xj, yj, zj, __int_as_float(j));
-        if (MODE == 1) candH[slot] = pj.w;
+        if (ModeTraits<MODE>::sym) candH[slot] = pj.w;
       }
       ncand += __popcll(mask);
       if (ncand > CAP - 64) flush();
@@ -346,10 +473,9 @@ __device__ __forceinline__ void chunk_body(const LoopArgs &g, int cid, char *lds
 
   // per-lane results of this wave
   float res[9];
-  if (MODE == 0) {
+  if (MODE != 1) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) res[q] = tot[q].value();
-    res[8] = 0.f;
+    for (int q = 0; q < 9; ++q) res[q] = tot[q].value();
   } else {
     if (COMP) {
       res[0] = ka[0].s - ka[0].c + tot[0].value();
@@ -402,6 +528,10 @@ __device__ __forceinline__ void chunk_body(const LoopArgs &g, int cid, char *lds
 #pragma unroll
       for (int q = 0; q < 8; ++q) g.sums[(int64_t)q * g.n_active + k] = res[q];
       g.act_cnt[k] = cnt;
+    } else if (MODE >= 2) {
+      constexpr int NOUT = MODE == 2 ? 8 : (MODE == 3 ? 7 : 3);
+#pragma unroll
+      for (int q = 0; q < NOUT; ++q) g.outp[(int64_t)q * g.n + i] = res[q];
     } else {
       g.ax_out[i] = res[0];
       g.ay_out[i] = res[1];
@@ -548,116 +678,5 @@ hipError_t launch_loop_any(hipStream_t st, const LoopArgs &a, const LoopConfig &
 #undef SPH_LAUNCH
 }
 
-struct GhostArgs {
-  int64_t n_active;
-  const int32_t *active_idx, *chunk_of;
-  const Chunk *chunks;
-  int32_t *chunk_todo;
-  const float *sums;
-  const int32_t *act_cnt;
-  const float *act_hmax;
-  float *hlo, *hhi;
-  uint8_t *conv;
-  float4 *pos4;
-  float4 *jth;
-  float *h;
-  int last;
-  int from_u;
-  float eta3, kc, tol, gamma, eps, box_quarter, reach;
-  // outputs
-  float *rho, *drho_dh, *f, *divv, *curlx, *curly, *curlz, *P, *c, *B, *A, *u;
-  int32_t *nngb;
-  int32_t *n_unconv, *rebuild;
-  unsigned long long *ctr;  // cumulative density interactions of finished solves
-};
-
-// Newton step on F(h) = h^3 sum_j W(r_ij, h) - eta^3 for each active particle
-// not yet converged; converged (or last-pass) particles get their ghost
-// quantities written.
-__global__ __launch_bounds__(256) void ghost_kernel(GhostArgs g) {
-  int finished = 0;
-  int unconv = 0;
-  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < g.n_active; k += (int64_t)gridDim.x * 256) {
-    if (g.conv[k]) continue;
-    const int i = g.active_idx[k];
-    const float S_w = g.sums[k], S_mw = g.sums[g.n_active + k], S_d = g.sums[2 * g.n_active + k],
-                S_md = g.sums[3 * g.n_active + k];
-    const float h = g.h[i];
-    // Newton in ln h on G = ln(h^3 n / eta^3), with h^3 n = (8/pi)/GK^3 sum w
-    // and dG/dln h = (3 sum w - sum (3w + q w')) / sum w: the same root as
-    // h^3 n = eta^3, reached in one step where the density is locally uniform.
-    const float hn3 = g.kc * S_w;
-    const float G = __logf(hn3 / g.eta3);
-    const float Gp = (3.f * S_w - S_d) / S_w;
-    float lo = g.hlo[k], hi = g.hhi[k];
-    if (G < 0.f) lo = fmaxf(lo, h);
-    if (G > 0.f) hi = fminf(hi, h);
-    float hn = h * __expf(fminf(fmaxf(-G / Gp, -0.6931472f), 0.6931472f));
-    if (!(hn >= lo && hn <= hi) || !(Gp > 0.f)) hn = (hi < INFINITY) ? 0.5f * (lo + hi) : 2.f * h;
-    if (G == 0.f) hn = h;
-    const bool done = fabsf(hn - h) < g.tol * h;
-    if (done || g.last) {
-      const float H = GK32 * h;
-      const float iH = 1.f / H;
-      const float C3 = KNORM32 * iH * iH * iH;
-      const float rho = C3 * S_mw;
-      const float drho = -C3 / h * S_md;
-      const float fg = 1.f / (1.f + h / (3.f * rho) * drho);
-      float P, A, u;
-      const float rg = __powf(rho, g.gamma);
-      if (g.from_u) {
-        u = g.u[i];
-        P = (g.gamma - 1.f) * rho * u;
-        A = P / rg;
-        g.A[i] = A;
-      } else {
-        A = g.A[i];
-        P = A * rg;
-        u = P / ((g.gamma - 1.f) * rho);
-        if (g.u) g.u[i] = u;
-      }
-      const float cs = sqrtf(g.gamma * P / rho);
-      const float C4 = C3 * iH;
-      const float dv = -C4 * g.sums[4 * g.n_active + k] / rho;
-      const float cx = C4 * g.sums[5 * g.n_active + k] / rho;
-      const float cy = C4 * g.sums[6 * g.n_active + k] / rho;
-      const float cz = C4 * g.sums[7 * g.n_active + k] / rho;
-      const float adv = fabsf(dv);
-      const float acu = sqrtf(fmaf(cz, cz, fmaf(cy, cy, cx * cx)));
-      const float Bs = adv > 0.f ? adv / (adv + acu + g.eps * cs / h) : 0.f;
-      g.rho[i] = rho;
-      g.drho_dh[i] = drho;
-      g.f[i] = fg;
-      g.divv[i] = dv;
-      g.curlx[i] = cx;
-      g.curly[i] = cy;
-      g.curlz[i] = cz;
-      g.P[i] = P;
-      g.c[i] = cs;
-      g.B[i] = Bs;
-      if (g.nngb) g.nngb[i] = g.act_cnt[k];
-      g.jth[i] = make_float4(rho, fg * P / (rho * rho), cs, Bs);
-      finished += g.act_cnt[k];
-      g.conv[k] = 1;
-      if (!done) ++unconv;
-    } else {
-      g.hlo[k] = lo;
-      g.hhi[k] = hi;
-      g.h[i] = hn;
-      const float Hn = GK32 * hn;
-      g.pos4[i].w = Hn;
-      g.chunk_todo[g.chunk_of[k]] = 1;
-      ++unconv;
-      const Chunk ch = g.chunks[g.chunk_of[k]];
-      if (Hn > g.act_hmax[ch.act_leaf] * g.reach) atomicOr(g.rebuild, 1);
-      if (Hn > g.box_quarter) atomicOr(g.rebuild, 2);
-    }
-  }
-  finished = wave_sum_i(finished);
-  unconv = wave_sum_i(unconv);
-  if ((threadIdx.x & 63) == 0) {
-    if (finished) atomicAdd(g.ctr, (unsigned long long)finished);
-    if (unconv) atomicAdd(g.n_unconv, unconv);
-  }
-}
-
+// Loop arguments common to every pass of one context (defined with the passes).
+LoopArgs base_args(sph_ctx *ctx);

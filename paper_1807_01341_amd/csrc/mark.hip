@@ -237,29 +237,36 @@ __global__ __launch_bounds__(MT) void leaf_hmax_refresh_kernel(const float4 *__r
 
 static unsigned waves_grid(int64_t n_items) { return (unsigned)(ceil_div(n_items, MT / 64) > 0 ? ceil_div(n_items, MT / 64) : 1); }
 
-// which = 0: density lists, 1: force lists.  slack > 1 widens the reach of
-// every active leaf (used when smoothing lengths grow during the h solve).
-sph_status build_pairs(sph_ctx *ctx, int which, float slack) {
-  const int64_t na = ctx->n_active_leaves;
-  if (which == 0) ctx->dpair_slack = slack;
-  DevBuf &off = which == 0 ? ctx->dpair_off : ctx->fpair_off;
-  DevBuf &lst = which == 0 ? ctx->dpairs : ctx->fpairs;
-  SPH_TRY(sph_ensure(ctx, ctx->pair_cnt, 4 * (size_t)(na + 1)));
-  SPH_TRY(sph_ensure(ctx, ctx->act_cost, 4 * (size_t)(na + 1)));
-  if (which == 0) ctx->work_valid = 0;
-  SPH_TRY(sph_ensure(ctx, off, 4 * (size_t)(na + 1)));
+static PairGeom pair_geom(const sph_ctx *ctx) {
   PairGeom g;
   g.D = ctx->prm.morton_depth;
   g.k0 = ctx->top_level;
   g.nu = (int64_t)1 << (g.D + 1);
   g.unit = ldexp(ctx->prm.box, -(g.D + 1));
   g.wtop = ldexp(ctx->prm.box, -g.k0);
-  int32_t *sc = (int32_t *)ctx->scalars.p;
+  return g;
+}
+
+// which = 0: density lists, 1: force lists.  slack > 1 widens the reach of
+// every active leaf (used when smoothing lengths grow during the h solve).
+// Two phases so that several contexts can share one synchronisation: the
+// count phase enqueues the per-leaf counts, their scan and the copy of the
+// total into *host_total (valid once the stream has been synchronised); the
+// fill phase writes the lists.
+sph_status build_pairs_count(sph_ctx *ctx, int which, float slack, int32_t *host_total) {
+  const int64_t na = ctx->n_active_leaves;
+  if (which == 0) ctx->dpair_slack = slack;
+  DevBuf &off = which == 0 ? ctx->dpair_off : ctx->fpair_off;
+  SPH_TRY(sph_ensure(ctx, ctx->pair_cnt, 4 * (size_t)(na + 1)));
+  SPH_TRY(sph_ensure(ctx, ctx->act_cost, 4 * (size_t)(na + 1)));
+  if (which == 0) ctx->work_valid = 0;
+  SPH_TRY(sph_ensure(ctx, off, 4 * (size_t)(na + 1)));
+  *host_total = 0;
   if (na == 0) {
-    if (which == 0) ctx->n_dpairs = 0; else ctx->n_fpairs = 0;
     HIP_TRY(ctx, hipMemsetAsync(off.p, 0, 4, ctx->stream));
     return SPH_OK;
   }
+  const PairGeom g = pair_geom(ctx);
   {
     PROF(ctx, "cell_pairs");
     pairs_kernel<false><<<waves_grid(na), MT, 0, ctx->stream>>>(
@@ -267,28 +274,41 @@ sph_status build_pairs(sph_ctx *ctx, int which, float slack) {
         (const int32_t *)ctx->leaf_level.p, (const int32_t *)ctx->leaf_ix.p, (const int32_t *)ctx->leaf_iy.p,
         (const int32_t *)ctx->leaf_iz.p, (const float *)ctx->leaf_hmax.p, (const int32_t *)ctx->top_first.p,
         (const int32_t *)ctx->top_last.p, ctx->hmax_global, (int32_t *)ctx->pair_cnt.p, nullptr, nullptr, nullptr,
-      nullptr);
+        nullptr);
   }
   HIP_TRY(ctx, hipGetLastError());
   int32_t *o = (int32_t *)off.p;
   SPH_TRY(scan_exclusive_i32(ctx, (const int32_t *)ctx->pair_cnt.p, o, na, o + na));
-  int32_t np;
-  HIP_TRY(ctx, hipMemcpyAsync(&np, o + na, 4, hipMemcpyDeviceToHost, ctx->stream));
-  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-  (void)sc;
+  HIP_TRY(ctx, hipMemcpyAsync(host_total, o + na, 4, hipMemcpyDeviceToHost, ctx->stream));
+  return SPH_OK;
+}
+
+sph_status build_pairs_fill(sph_ctx *ctx, int which, float slack, int32_t np) {
+  const int64_t na = ctx->n_active_leaves;
+  DevBuf &off = which == 0 ? ctx->dpair_off : ctx->fpair_off;
+  DevBuf &lst = which == 0 ? ctx->dpairs : ctx->fpairs;
+  if (which == 0) ctx->n_dpairs = np; else ctx->n_fpairs = np;
+  if (na == 0) return SPH_OK;
   SPH_TRY(sph_ensure(ctx, lst, sizeof(PairEntry) * (size_t)(np > 0 ? np : 1)));
+  const PairGeom g = pair_geom(ctx);
   {
     PROF(ctx, "cell_pairs");
     pairs_kernel<true><<<waves_grid(na), MT, 0, ctx->stream>>>(
         which, slack, g, na, (const int32_t *)ctx->act_leaves.p, (const float *)ctx->act_hmax.p,
         (const int32_t *)ctx->leaf_level.p, (const int32_t *)ctx->leaf_ix.p, (const int32_t *)ctx->leaf_iy.p,
         (const int32_t *)ctx->leaf_iz.p, (const float *)ctx->leaf_hmax.p, (const int32_t *)ctx->top_first.p,
-        (const int32_t *)ctx->top_last.p, ctx->hmax_global, nullptr, o, (PairEntry *)lst.p,
-      (const int32_t *)ctx->leaf_count.p, which == 0 ? (int32_t *)ctx->act_cost.p : nullptr);
+        (const int32_t *)ctx->top_last.p, ctx->hmax_global, nullptr, (int32_t *)off.p, (PairEntry *)lst.p,
+        (const int32_t *)ctx->leaf_count.p, which == 0 ? (int32_t *)ctx->act_cost.p : nullptr);
   }
   HIP_TRY(ctx, hipGetLastError());
-  if (which == 0) ctx->n_dpairs = np; else ctx->n_fpairs = np;
   return SPH_OK;
+}
+
+sph_status build_pairs(sph_ctx *ctx, int which, float slack) {
+  int32_t np = 0;
+  SPH_TRY(build_pairs_count(ctx, which, slack, &np));
+  if (ctx->n_active_leaves > 0) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return build_pairs_fill(ctx, which, slack, np);
 }
 
 // Refreshes the max H of every active leaf (all particles, and active ones)

@@ -77,6 +77,9 @@ struct sph_ctx {
   DevBuf act_cost;                        // staged partner particles per active leaf
   DevBuf work, work_tmp, box_args, box_work;
   int work_valid = 0;                     // work (cost order) matches the current chunks
+  int density_from_u = 0;                 // the last density pass took P from u
+  // adjoint
+  DevBuf adj_w, adj1, adj2, adj_out;
 
   // tuned loop configurations per pass (0 density, 1 force) and chunk-count class
   struct TuneEntry {
@@ -84,6 +87,11 @@ struct sph_ctx {
     float ms = 0.f;
   };
   TuneEntry tune[2][32];
+  TuneEntry btune[2][32];                 // batched passes led by this context (total chunks)
+
+  // batched passes led by this context: per-box descriptors and the work list
+  DevBuf batch_args, batch_ghost, batch_items, batch_work, batch_tmp, batch_status;
+  std::vector<char> batch_host;           // host staging of the descriptors
 
   // optional per-kernel timing with HIP events on ctx->stream
   int prof = 0;
@@ -154,10 +162,17 @@ sph_status build_cells_impl(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *
 sph_status sort_cells_impl(sph_ctx *ctx);
 sph_status mark_active_impl(sph_ctx *ctx, const sph_particles *p, int m, int64_t *n_active_host);
 sph_status build_pairs(sph_ctx *ctx, int which, float slack);
+sph_status build_pairs_count(sph_ctx *ctx, int which, float slack, int32_t *host_total);
+sph_status build_pairs_fill(sph_ctx *ctx, int which, float slack, int32_t np);
 sph_status refresh_leaf_hmax(sph_ctx *ctx, bool read_global);
 sph_status pack_neighbour_data(sph_ctx *ctx, const sph_particles *p);
 sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u);
 sph_status force_pass_impl(sph_ctx *ctx, sph_particles *p);
+sph_status batch_density_impl(sph_ctx **cs, sph_particles *ps, int nb, int entropy_from_u);
+sph_status batch_force_impl(sph_ctx **cs, sph_particles *ps, int nb);
+sph_status batch_autotune_impl(sph_ctx **cs, sph_particles *ps, int nb, const char *path);
+sph_status adjoint_impl(sph_ctx *ctx, sph_particles *p, const float *wx, const float *wy, const float *wz,
+                        double *gx, double *gy, double *gz, float *gu);
 sph_status kick_drift_impl(sph_ctx *ctx, sph_particles *p, int64_t ti, double t_min, int64_t drift_int,
                            int first_step);
 
