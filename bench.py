@@ -375,7 +375,7 @@ def main():
     ap.add_argument("--tune-file", default=os.path.join(ROOT, "gpurun_out", "tuning_clustered.txt"))
     ap.add_argument("--workload", choices=("deepbin", "large"), default="deepbin")
     ap.add_argument("--substeps", type=int, default=8192, help="large workload: sub-steps of the sweep")
-    ap.add_argument("--grf-amplitude", type=float, default=1.6)
+    ap.add_argument("--grf-amplitude", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy 5 times (for scaling HBM counters)")
     ap.add_argument("--no-extras", action="store_true",

@@ -209,12 +209,14 @@ def batch_of_boxes(n_boxes: int = 64, n_range=(1_000, 200_000), index: int = 3,
     return boxes
 
 
-def grf_zeldovich(nside: int = 256, spectral_index: float = -2.5, amplitude: float = 1.6,
+def grf_zeldovich(nside: int = 256, spectral_index: float = -2.5, amplitude: float = 12.0,
                   index: int = 5, u_range=(1e-2, 1e2)):
     """Workload 5: nside^3 lattice displaced by the Zel'dovich field of a
     Gaussian random density field with P(k) ~ k^spectral_index.  The
     displacement is psi_k = i k delta_k / k^2 scaled so that its rms equals
-    `amplitude` lattice spacings; u is log-uniform.  The model density for the
+    `amplitude` lattice spacings (12 gives the largest density contrast of
+    this spectrum at 256^3, about 2e2 between the densest particles and the
+    median; larger amplitudes smear the caustics out); u is log-uniform.  The model density for the
     initial h guess and the model bins is a cloud-in-cell count of the
     displaced particles on the nside^3 grid."""
     r_field, r_u = _streams(index, 2)
