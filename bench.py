@@ -555,7 +555,8 @@ def main():
                              "pair_rebuilds": last["pair_rebuilds"]},
         "kernels": kernels,
         "tuned_loops": [{"loop": ("density", "force")[int(t[1])], "chunk_class": int(t[2]), "waves_per_chunk": int(t[3]),
-                         "tile": int(t[4]), "cost_ordered": int(t[5]), "persistent": int(t[6]), "ms": float(t[7])}
+                         "tile": int(t[4]), "cost_ordered": int(t[5]), "persistent": int(t[6]), "chunk_split": int(t[7]),
+                         "ms": float(t[8])}
                         for t in (tuned or [])],
         "roofline": roof,
     }

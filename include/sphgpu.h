@@ -68,6 +68,9 @@ typedef struct {
   int list_cap;        /* loop tiling: neighbour-list slots per lane (96) */
   int waves_per_chunk; /* loop tiling: waves sharing one chunk's cell pairs, 1/2/4/8,
                           0 = chosen from the number of active chunks (0) */
+  int chunk_split;     /* loop work items: 0 = one per chunk; 1 / 2 = a chunk's cell-pair
+                          list split into parts of about 1024 / 4096 staged partner
+                          particles (at most 16), when no tuned entry applies (0) */
 } sph_params;
 
 /* The particle state.  Arrays marked (opt) may be NULL.  build_cells reorders
@@ -112,7 +115,12 @@ sph_status sph_build_cells(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *p
 
 /* Per-cell particle sorts for neighbour pruning (Fig. 5 "sort" task): for
  * each leaf and each of the 13 directions of the half neighbour stencil, the
- * in-leaf order by projection of the FP32 offset (ties by in-leaf index). */
+ * in-leaf order by projection of the FP32 offset (ties by in-leaf index).
+ * The sorts are made lazily, like the paper's sort tasks that run only for
+ * active cells: this call prepares them (and synchronises once to check the
+ * largest leaf, SPH_EINVAL above 4096 particles); each loop pass then sorts
+ * the leaves its cell pairs reach that are not sorted yet in this step.
+ * sph_copy_axis_order sorts every leaf first. */
 sph_status sph_sort_cells(sph_ctx *ctx);
 
 /* Active set for the current time-bin (Eq. 2, Sec. III-D): particle i is

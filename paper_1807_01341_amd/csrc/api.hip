@@ -108,7 +108,9 @@ sph_status sph_create(const sph_params *p, void *hip_stream, sph_ctx **out) {
   *out = nullptr;
   if (!(p->box > 0) || p->morton_depth < 2 || p->morton_depth > 21 || p->split_count < 2 || p->top_cap < 2 ||
       p->top_cap > 8 || p->n_bins < 1 || p->n_bins > 63 || p->h_max_iter < 1 || !(p->eta > 0) ||
-      !(p->gamma > 1.0) || p->cand_cap < 64 || p->list_cap < 64)
+      !(p->gamma > 1.0) || p->cand_cap < 64 || p->list_cap < 64 || p->chunk_split < 0 || p->chunk_split > 2 ||
+      !(p->waves_per_chunk == 0 || p->waves_per_chunk == 1 || p->waves_per_chunk == 2 || p->waves_per_chunk == 4 ||
+        p->waves_per_chunk == 8))
     return SPH_EINVAL;
   sph_ctx *ctx = new (std::nothrow) sph_ctx();
   if (!ctx) return SPH_ENOMEM;
@@ -146,17 +148,7 @@ void sph_destroy(sph_ctx *ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   resolve_profile(ctx);
   for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
-  DevBuf *bufs[] = {&ctx->counters64, &ctx->act_cost, &ctx->work, &ctx->work_tmp, &ctx->box_args, &ctx->box_work, &ctx->keys_a, &ctx->keys_b, &ctx->vals_a, &ctx->vals_b, &ctx->radix_counts, &ctx->scan_tmp,
-                    &ctx->gather_tmp, &ctx->scalars, &ctx->flags, &ctx->scan_out, &ctx->nodes_a, &ctx->nodes_b,
-                    &ctx->leaf_lvl_at, &ctx->leaf_level, &ctx->leaf_ix, &ctx->leaf_iy, &ctx->leaf_iz,
-                    &ctx->leaf_begin, &ctx->leaf_count, &ctx->leaf_hmax, &ctx->leaf_of, &ctx->top_first,
-                    &ctx->top_last, &ctx->pos4, &ctx->axis_order, &ctx->active, &ctx->leaf_nact,
-                    &ctx->leaf_act_off, &ctx->leaf_actleaf, &ctx->act_leaves, &ctx->act_hmax,
-                    &ctx->act_leaf_chunk_off, &ctx->active_idx, &ctx->chunk_of, &ctx->chunks, &ctx->chunk_todo,
-                    &ctx->dpair_off, &ctx->dpairs, &ctx->fpair_off, &ctx->fpairs, &ctx->pair_cnt, &ctx->jvm,
-                    &ctx->jth, &ctx->sums, &ctx->hlo, &ctx->hhi, &ctx->conv};
-  for (DevBuf *b : bufs)
-    if (b->p) (void)hipFree(b->p);
+  // every DevBuf member frees its allocation
   delete ctx;
 }
 
@@ -296,6 +288,7 @@ sph_status sph_copy_particles(sph_ctx *ctx, uint64_t *keys, float *ox, float *oy
 
 sph_status sph_copy_axis_order(sph_ctx *ctx, uint16_t *order) {
   SPH_TRY(need_state(ctx, 2, "copy_axis_order"));
+  SPH_TRY(sort_all_leaves(ctx));
   return copy_dev(ctx, order, ctx->axis_order, 2 * 13 * (size_t)ctx->n);
 }
 

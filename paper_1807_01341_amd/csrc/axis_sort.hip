@@ -5,6 +5,8 @@
 // bitonic sorts of (key, index) in LDS.
 #include <math.h>
 
+#include <algorithm>
+
 #include "sph_internal.h"
 
 #define AS_THREADS 256
@@ -38,13 +40,20 @@ template <int P>
 __global__ __launch_bounds__(AS_THREADS) void axis_sort_kernel(const float4 *__restrict__ pos4,
                                                                const int32_t *__restrict__ leaf_begin,
                                                                const int32_t *__restrict__ leaf_count, int64_t nl,
-                                                               int64_t n, AxisSet ax, int min_count,
+                                                               const int32_t *__restrict__ list,
+                                                               const int32_t *__restrict__ list_len, int64_t n,
+                                                               AxisSet ax, int min_count,
                                                                uint16_t *__restrict__ order) {
   __shared__ float ox[P], oy[P], oz[P];
   __shared__ float key[P];
   __shared__ uint16_t idx[P];
-  const int l = blockIdx.x;
-  if (l >= nl) return;
+  int l = blockIdx.x;
+  if (list) {
+    if (l >= *list_len) return;
+    l = list[l];
+  } else if (l >= nl) {
+    return;
+  }
   const int cnt = leaf_count[l];
   if (cnt < min_count || cnt > P) return;
   const int b = leaf_begin[l];
@@ -180,13 +189,21 @@ __device__ __forceinline__ void sort_leaf_axes(const float4 *__restrict__ pos4, 
   }
 }
 
-// One wave per leaf of at most 512 particles.
+// One wave per leaf of at most 512 particles: every leaf, or the leaves of
+// `list` (its length on the device).
 __global__ __launch_bounds__(256) void axis_sort_wave_kernel(const float4 *__restrict__ pos4,
                                                              const int32_t *__restrict__ leaf_begin,
                                                              const int32_t *__restrict__ leaf_count, int64_t nl,
-                                                             int64_t n, AxisSet ax, uint16_t *__restrict__ order) {
-  const int64_t l = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (l >= nl) return;
+                                                             const int32_t *__restrict__ list,
+                                                             const int32_t *__restrict__ list_len, int64_t n,
+                                                             AxisSet ax, uint16_t *__restrict__ order) {
+  int64_t l = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (list) {
+    if (l >= *list_len) return;
+    l = list[l];
+  } else if (l >= nl) {
+    return;
+  }
   const int lane = threadIdx.x & 63;
   const int cnt = leaf_count[l], b = leaf_begin[l];
   if (cnt <= 64)
@@ -199,28 +216,84 @@ __global__ __launch_bounds__(256) void axis_sort_wave_kernel(const float4 *__res
     sort_leaf_axes<8>(pos4, b, cnt, n, ax, order, lane);
 }
 
+// Leaves of a cell-pair list not yet sorted: each is claimed once (its flag
+// set) and appended to the sort list.
+__global__ __launch_bounds__(256) void claim_partners_kernel(const PairEntry *__restrict__ pairs, int64_t np,
+                                                             int32_t *__restrict__ sorted, int32_t *__restrict__ list,
+                                                             int32_t *__restrict__ list_len) {
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < np; q += (int64_t)gridDim.x * 256) {
+    const int B = pairs[q].b;
+    if (sorted[B]) continue;
+    if (atomicExch(&sorted[B], 1) == 0) list[atomicAdd(list_len, 1)] = B;
+  }
+}
+
+// The sorts are made lazily: sph_sort_cells prepares them, and a loop pass
+// sorts the leaves its cell pairs reach that no earlier pass of the step has
+// sorted (the paper likewise runs sort tasks only for active cells).
 sph_status sort_cells_impl(sph_ctx *ctx) {
   const int64_t n = ctx->n, nl = ctx->n_leaves;
   SPH_TRY(sph_ensure(ctx, ctx->axis_order, sizeof(uint16_t) * 13 * (size_t)n));
+  SPH_TRY(sph_ensure(ctx, ctx->leaf_sorted, sizeof(int32_t) * (size_t)(nl + 1)));
+  SPH_TRY(sph_ensure(ctx, ctx->sort_list, sizeof(int32_t) * (size_t)(nl + 1)));
   int32_t maxc = 0;
   SPH_TRY(read_scalars(ctx, SC_MAXLEAF, 1, &maxc));
   if (maxc > 4096)
     return sph_fail(ctx, SPH_EINVAL, "sort_cells: a leaf holds %d particles (max 4096 for the axis sorts)", maxc);
+  ctx->max_leaf = maxc;
+  HIP_TRY(ctx, hipMemsetAsync(ctx->leaf_sorted.p, 0, sizeof(int32_t) * (size_t)nl, ctx->stream));
+  ctx->sorted_lists = 0;
+  ctx->state = 2;
+  return SPH_OK;
+}
+
+static sph_status sort_leaves(sph_ctx *ctx, const int32_t *list, const int32_t *list_len, int64_t grid_leaves) {
+  const int64_t n = ctx->n, nl = ctx->n_leaves;
   const AxisSet ax = make_axes();
+  if (grid_leaves <= 0) return SPH_OK;
   {
     PROF(ctx, "axis_sort");
-    axis_sort_wave_kernel<<<(unsigned)ceil_div(nl, 4), 256, 0, ctx->stream>>>(
-        (const float4 *)ctx->pos4.p, (const int32_t *)ctx->leaf_begin.p, (const int32_t *)ctx->leaf_count.p, nl, n,
-        ax, (uint16_t *)ctx->axis_order.p);
+    axis_sort_wave_kernel<<<(unsigned)ceil_div(grid_leaves, 4), 256, 0, ctx->stream>>>(
+        (const float4 *)ctx->pos4.p, (const int32_t *)ctx->leaf_begin.p, (const int32_t *)ctx->leaf_count.p, nl,
+        list, list_len, n, ax, (uint16_t *)ctx->axis_order.p);
   }
   HIP_TRY(ctx, hipGetLastError());
-  if (maxc > 512) {
+  if (ctx->max_leaf > 512) {
     PROF(ctx, "axis_sort");
-    axis_sort_kernel<4096><<<(unsigned)nl, AS_THREADS, 0, ctx->stream>>>(
-        (const float4 *)ctx->pos4.p, (const int32_t *)ctx->leaf_begin.p, (const int32_t *)ctx->leaf_count.p, nl, n,
-        ax, 513, (uint16_t *)ctx->axis_order.p);
+    axis_sort_kernel<4096><<<(unsigned)grid_leaves, AS_THREADS, 0, ctx->stream>>>(
+        (const float4 *)ctx->pos4.p, (const int32_t *)ctx->leaf_begin.p, (const int32_t *)ctx->leaf_count.p, nl,
+        list, list_len, n, ax, 513, (uint16_t *)ctx->axis_order.p);
     HIP_TRY(ctx, hipGetLastError());
   }
-  ctx->state = 2;
+  return SPH_OK;
+}
+
+// Sorts the partner leaves of cell-pair list `which` (0 density, 1 force)
+// not sorted yet in this step.  No synchronisation: the sort list's length
+// stays on the device.
+sph_status sort_partners(sph_ctx *ctx, int which) {
+  const int bit = 1 << which;
+  if (ctx->sorted_lists & bit) return SPH_OK;
+  const int64_t np = which == 0 ? ctx->n_dpairs : ctx->n_fpairs;
+  const PairEntry *pairs = (const PairEntry *)(which == 0 ? ctx->dpairs.p : ctx->fpairs.p);
+  ctx->sorted_lists |= bit;
+  if (np <= 0) return SPH_OK;
+  int32_t *len = (int32_t *)ctx->sort_list.p + ctx->n_leaves;
+  HIP_TRY(ctx, hipMemsetAsync(len, 0, sizeof(int32_t), ctx->stream));
+  {
+    PROF(ctx, "axis_sort");
+    claim_partners_kernel<<<(unsigned)std::min<int64_t>(ceil_div(np, 256), 4096), 256, 0, ctx->stream>>>(
+        pairs, np, (int32_t *)ctx->leaf_sorted.p, (int32_t *)ctx->sort_list.p, len);
+  }
+  HIP_TRY(ctx, hipGetLastError());
+  return sort_leaves(ctx, (const int32_t *)ctx->sort_list.p, len, std::min<int64_t>(np, ctx->n_leaves));
+}
+
+// Every leaf (for the introspection copy).
+sph_status sort_all_leaves(sph_ctx *ctx) {
+  SPH_TRY(sort_leaves(ctx, nullptr, nullptr, ctx->n_leaves));
+  if (ctx->n_leaves > 0)
+    HIP_TRY(ctx, hipMemsetAsync(ctx->leaf_sorted.p, 0x01, sizeof(int32_t) * (size_t)ctx->n_leaves, ctx->stream));
+  ctx->sorted_lists = 3;
   return SPH_OK;
 }

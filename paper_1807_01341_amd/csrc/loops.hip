@@ -9,7 +9,7 @@ namespace {
 __global__ __launch_bounds__(256) void fill_work_kernel(const int32_t *__restrict__ order, int64_t n,
                                                         int2 *__restrict__ work) {
   for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256)
-    work[q] = make_int2(0, order ? order[q] : (int)q);
+    work[q] = make_int2(0, order ? order[q] : (int)(q << 4));
 }
 
 __global__ __launch_bounds__(256) void pack_jvm_kernel(const double *__restrict__ vx, const double *__restrict__ vy,
@@ -53,20 +53,44 @@ unsigned grid256(int64_t n) {
   return (unsigned)(g < 1 ? 1 : g);
 }
 
-// Chunks in decreasing order of staged partner particles (longest first),
-// by log2 buckets: histogram, bucket offsets, scatter.
-__global__ __launch_bounds__(256) void cost_bucket_kernel(const Chunk *__restrict__ chunks, int64_t n_chunks,
+// Work items: every chunk's cell-pair list in parts of about `target` staged
+// partner particles (at most 16 parts and at most one per cell pair; one part
+// when target is 0), as codes chunk * 16 + part, in chunk order and in
+// decreasing order of part cost (log2 buckets: histogram, offsets, scatter).
+__global__ __launch_bounds__(256) void split_count_kernel(const Chunk *__restrict__ chunks, int64_t n_chunks,
                                                           const int32_t *__restrict__ act_cost,
-                                                          int32_t *__restrict__ bucket_of,
-                                                          int32_t *__restrict__ hist) {
+                                                          const int32_t *__restrict__ pair_off, int target,
+                                                          int32_t *__restrict__ parts) {
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n_chunks; q += (int64_t)gridDim.x * 256) {
+    const int al = chunks[q].act_leaf;
+    int P = 1;
+    if (target > 0) {
+      const int cost = max(1, act_cost[al]);
+      const int np = pair_off[al + 1] - pair_off[al];
+      P = min(16, min(np, (cost + target - 1) / target));
+      P = max(P, 1);
+    }
+    parts[q] = P;
+  }
+}
+
+__global__ __launch_bounds__(256) void split_fill_kernel(const Chunk *__restrict__ chunks, int64_t n_chunks,
+                                                         const int32_t *__restrict__ act_cost,
+                                                         const int32_t *__restrict__ item0,
+                                                         int32_t *__restrict__ items, int32_t *__restrict__ bucket_of,
+                                                         int32_t *__restrict__ hist) {
   __shared__ int h[32];
   if (threadIdx.x < 32) h[threadIdx.x] = 0;
   __syncthreads();
   for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n_chunks; q += (int64_t)gridDim.x * 256) {
-    const int cost = max(1, act_cost[chunks[q].act_leaf]);
+    const int i0 = item0[q], P = item0[q + 1] - i0;
+    const int cost = max(1, act_cost[chunks[q].act_leaf] / P);
     const int b = __clz(cost);  // larger cost, smaller bucket
-    bucket_of[q] = b;
-    atomicAdd(&h[b], 1);
+    for (int p = 0; p < P; ++p) {
+      items[i0 + p] = (int)(q << 4) | p;
+      bucket_of[i0 + p] = b;
+    }
+    atomicAdd(&h[b], P);
   }
   __syncthreads();
   if (threadIdx.x < 32 && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
@@ -83,10 +107,11 @@ __global__ void cost_bucket_scan_kernel(int32_t *hist) {
   }
 }
 
-__global__ __launch_bounds__(256) void cost_scatter_kernel(const int32_t *__restrict__ bucket_of, int64_t n_chunks,
-                                                           int32_t *__restrict__ cursor, int32_t *__restrict__ work) {
-  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n_chunks; q += (int64_t)gridDim.x * 256)
-    work[atomicAdd(&cursor[bucket_of[q]], 1)] = (int32_t)q;
+__global__ __launch_bounds__(256) void item_scatter_kernel(const int32_t *__restrict__ items,
+                                                           const int32_t *__restrict__ bucket_of, int64_t n,
+                                                           int32_t *__restrict__ cursor, int32_t *__restrict__ out) {
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256)
+    out[atomicAdd(&cursor[bucket_of[q]], 1)] = items[q];
 }
 
 // Workgroups of a persistent launch: every CU filled to the occupancy its
@@ -116,11 +141,12 @@ LoopConfig choose_config(sph_ctx *ctx, int mode) {
     c.tile = t.tile;
     c.ordered = t.ordered;
     c.persistent = t.persistent;
+    c.split = t.split;
     return c;
   }
+  c.split = ctx->prm.chunk_split;
   if (ctx->prm.waves_per_chunk > 0) {
     c.nw = ctx->prm.waves_per_chunk;
-    c.tile = c.nw >= 4 ? 1 : 2;
     const int cap = ctx->prm.cand_cap, lcap = ctx->prm.list_cap;
     if (c.nw == 1) c.tile = cap <= 128 && lcap <= 32 ? 0 : cap <= 256 && lcap <= 64 ? 1 : cap <= 512 && lcap <= 96 ? 2 : cap <= 1024 && lcap <= 128 ? 3 : 4;
     if (c.nw == 2) c.tile = cap <= 128 && lcap <= 32 ? 0 : cap <= 256 && lcap <= 64 ? 1 : 2;
@@ -140,53 +166,110 @@ LoopConfig choose_config(sph_ctx *ctx, int mode) {
   return c;
 }
 
-sph_status order_chunks_by_cost(sph_ctx *ctx) {
+}  // namespace
+
+// Work items for a split target, in two phases so that several contexts can
+// share one synchronisation: the count phase enqueues the parts per chunk,
+// their scan and the copy of the total into *host_total; the fill phase
+// writes the items in chunk order and in cost order and clears the arrival
+// counters.  The costs come from the density cell-pair lists.
+sph_status items_count(sph_ctx *ctx, int target, int32_t *host_total) {
   const int64_t nc = ctx->n_chunks;
-  SPH_TRY(sph_ensure(ctx, ctx->work, 4 * (size_t)(nc > 0 ? nc : 1)));
-  SPH_TRY(sph_ensure(ctx, ctx->work_tmp, 4 * (size_t)(nc > 0 ? nc : 1) + 256));
-  int32_t *bucket_of = (int32_t *)ctx->work_tmp.p + 64;
-  int32_t *hist = (int32_t *)ctx->work_tmp.p;
-  HIP_TRY(ctx, hipMemsetAsync(hist, 0, 32 * sizeof(int32_t), ctx->stream));
+  SPH_TRY(sph_ensure(ctx, ctx->chunk_item0, 4 * (size_t)(nc + 1)));
+  SPH_TRY(sph_ensure(ctx, ctx->work_tmp, 4 * (size_t)(nc + 1) + 256));
+  *host_total = 0;
+  if (nc == 0) return SPH_OK;
+  int32_t *parts = (int32_t *)ctx->work_tmp.p + 64;
   PROF(ctx, "cost_order");
-  cost_bucket_kernel<<<grid_for_items(nc), 256, 0, ctx->stream>>>((const Chunk *)ctx->chunks.p, nc,
-                                                                 (const int32_t *)ctx->act_cost.p, bucket_of, hist);
-  cost_bucket_scan_kernel<<<1, 64, 0, ctx->stream>>>(hist);
-  cost_scatter_kernel<<<grid_for_items(nc), 256, 0, ctx->stream>>>(bucket_of, nc, hist, (int32_t *)ctx->work.p);
-  return sph_hip_check(ctx, hipGetLastError(), "cost order");
+  split_count_kernel<<<grid_for_items(nc), 256, 0, ctx->stream>>>(
+      (const Chunk *)ctx->chunks.p, nc, (const int32_t *)ctx->act_cost.p, (const int32_t *)ctx->dpair_off.p, target,
+      parts);
+  HIP_TRY(ctx, hipGetLastError());
+  int32_t *i0 = (int32_t *)ctx->chunk_item0.p;
+  SPH_TRY(scan_exclusive_i32(ctx, parts, i0, nc, i0 + nc));
+  HIP_TRY(ctx, hipMemcpyAsync(host_total, i0 + nc, 4, hipMemcpyDeviceToHost, ctx->stream));
+  return SPH_OK;
 }
+
+sph_status items_fill(sph_ctx *ctx, int target, int32_t total) {
+  const int64_t nc = ctx->n_chunks;
+  ctx->n_items = total;
+  ctx->items_target = target;
+  ctx->work_valid = 1;
+  if (nc == 0) return SPH_OK;
+  SPH_TRY(sph_ensure(ctx, ctx->items_nat, 4 * (size_t)total));
+  SPH_TRY(sph_ensure(ctx, ctx->work, 4 * (size_t)total));
+  SPH_TRY(sph_ensure(ctx, ctx->work_tmp, 4 * (size_t)(total > nc + 1 ? total : nc + 1) + 256));
+  SPH_TRY(sph_ensure(ctx, ctx->chunk_ctr, 4 * (size_t)nc));
+  if (target > 0) SPH_TRY(sph_ensure(ctx, ctx->partials, sizeof(float) * 11 * 64 * (size_t)total));
+  int32_t *hist = (int32_t *)ctx->work_tmp.p;
+  int32_t *bucket_of = hist + 64;
+  HIP_TRY(ctx, hipMemsetAsync(hist, 0, 32 * sizeof(int32_t), ctx->stream));
+  HIP_TRY(ctx, hipMemsetAsync(ctx->chunk_ctr.p, 0, 4 * (size_t)nc, ctx->stream));
+  PROF(ctx, "cost_order");
+  split_fill_kernel<<<grid_for_items(nc), 256, 0, ctx->stream>>>(
+      (const Chunk *)ctx->chunks.p, nc, (const int32_t *)ctx->act_cost.p, (const int32_t *)ctx->chunk_item0.p,
+      (int32_t *)ctx->items_nat.p, bucket_of, hist);
+  cost_bucket_scan_kernel<<<1, 64, 0, ctx->stream>>>(hist);
+  item_scatter_kernel<<<grid_for_items(total), 256, 0, ctx->stream>>>(
+      (const int32_t *)ctx->items_nat.p, bucket_of, total, hist, (int32_t *)ctx->work.p);
+  return sph_hip_check(ctx, hipGetLastError(), "work items");
+}
+
+sph_status ensure_items(sph_ctx *ctx, int target) {
+  if (ctx->work_valid && ctx->items_target == target) return SPH_OK;
+  int32_t total = 0;
+  SPH_TRY(items_count(ctx, target, &total));
+  if (ctx->n_chunks > 0) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return items_fill(ctx, target, total);
+}
+
+// The loop arguments' work list for a configuration (items built if needed).
+sph_status apply_config(sph_ctx *ctx, const LoopConfig &cfg, LoopArgs &a) {
+  const int target = split_target(cfg.split);
+  a.work = nullptr;
+  a.chunk_item0 = nullptr;
+  a.chunk_ctr = nullptr;
+  a.partials = nullptr;
+  if (!cfg.ordered && target == 0) return SPH_OK;
+  SPH_TRY(ensure_items(ctx, target));
+  a.work = cfg.ordered ? (const int32_t *)ctx->work.p : (const int32_t *)ctx->items_nat.p;
+  a.n_items = ctx->n_items;
+  if (target > 0) {
+    a.chunk_item0 = (const int32_t *)ctx->chunk_item0.p;
+    a.chunk_ctr = (int32_t *)ctx->chunk_ctr.p;
+    a.partials = (float *)ctx->partials.p;
+  }
+  return SPH_OK;
+}
+
+namespace {
 
 template <int MODE, bool COMP>
 sph_status launch_loop(sph_ctx *ctx, const LoopArgs &a0) {
+  SPH_TRY(sort_partners(ctx, MODE == 0 ? 0 : 1));
   const LoopConfig cfg = choose_config(ctx, MODE);
   LoopArgs a = a0;
-  if (cfg.ordered) {
-    if (!ctx->work_valid) {
-      SPH_TRY(order_chunks_by_cost(ctx));
-      ctx->work_valid = 1;
-    }
-    a.work = (const int32_t *)ctx->work.p;
-    a.n_items = ctx->n_chunks;
-  }
+  SPH_TRY(apply_config(ctx, cfg, a));
   PROF(ctx, MODE == 0 ? "density_loop" : "force_loop");
   if (cfg.persistent) {
     // one box through the persistent kernel: a device copy of the arguments
-    // and a (0, chunk) work list
+    // and a (0, item) work list
+    const int64_t ni = a.work ? a.n_items : ctx->n_chunks;
     SPH_TRY(sph_ensure(ctx, ctx->box_args, sizeof(LoopArgs)));
-    SPH_TRY(sph_ensure(ctx, ctx->box_work, sizeof(int2) * (size_t)(ctx->n_chunks > 0 ? ctx->n_chunks : 1)));
+    SPH_TRY(sph_ensure(ctx, ctx->box_work, sizeof(int2) * (size_t)(ni > 0 ? ni : 1)));
     HIP_TRY(ctx, hipMemcpyAsync(ctx->box_args.p, &a, sizeof(LoopArgs), hipMemcpyHostToDevice, ctx->stream));
-    fill_work_kernel<<<grid_for_items(ctx->n_chunks), 256, 0, ctx->stream>>>(
-        cfg.ordered ? (const int32_t *)ctx->work.p : nullptr, ctx->n_chunks, (int2 *)ctx->box_work.p);
+    fill_work_kernel<<<grid_for_items(ni), 256, 0, ctx->stream>>>(a.work, ni, (int2 *)ctx->box_work.p);
     HIP_TRY(ctx, hipGetLastError());
     return sph_hip_check(ctx,
                          launch_loop_any<MODE, COMP>(ctx->stream, a, cfg, (const LoopArgs *)ctx->box_args.p,
-                                                     (const int2 *)ctx->box_work.p, (int)ctx->n_chunks,
+                                                     (const int2 *)ctx->box_work.p, (int)ni,
                                                      (int *)ctx->scalars.p + SC_WORKCTR, persistent_grid_for(ctx->n_cu, cfg)),
                          MODE == 0 ? "density loop" : "force loop");
   }
   return sph_hip_check(ctx, launch_loop_any<MODE, COMP>(ctx->stream, a, cfg, nullptr, nullptr, 0, nullptr, 0),
                        MODE == 0 ? "density loop" : "force loop");
 }
-
 
 }  // namespace
 
@@ -574,26 +657,25 @@ struct TimedLaunch {
 
 template <int MODE>
 sph_status time_config(sph_ctx *ctx, const LoopArgs &a0, const LoopConfig &cfg, int reps, float *ms_out) {
+  LoopArgs a = a0;
+  SPH_TRY(apply_config(ctx, cfg, a));
+  const int64_t ni = a.work ? a.n_items : ctx->n_chunks;
+  SPH_TRY(sph_ensure(ctx, ctx->box_args, sizeof(LoopArgs)));
+  SPH_TRY(sph_ensure(ctx, ctx->box_work, sizeof(int2) * (size_t)(ni > 0 ? ni : 1)));
   hipEvent_t e0, e1;
   HIP_TRY(ctx, hipEventCreate(&e0));
   HIP_TRY(ctx, hipEventCreate(&e1));
   float best = INFINITY;
   for (int r = 0; r <= reps; ++r) {
     fill_i32_kernel<<<grid256(ctx->n_chunks), 256, 0, ctx->stream>>>((int32_t *)ctx->chunk_todo.p, ctx->n_chunks, 1);
-    LoopArgs a = a0;
-    if (cfg.ordered) {
-      a.work = (const int32_t *)ctx->work.p;
-      a.n_items = ctx->n_chunks;
-    }
     HIP_TRY(ctx, hipEventRecord(e0, ctx->stream));
     hipError_t err;
     if (cfg.persistent) {
       HIP_TRY(ctx, hipMemcpyAsync(ctx->box_args.p, &a, sizeof(LoopArgs), hipMemcpyHostToDevice, ctx->stream));
-      fill_work_kernel<<<grid_for_items(ctx->n_chunks), 256, 0, ctx->stream>>>(
-          cfg.ordered ? (const int32_t *)ctx->work.p : nullptr, ctx->n_chunks, (int2 *)ctx->box_work.p);
+      fill_work_kernel<<<grid_for_items(ni), 256, 0, ctx->stream>>>(a.work, ni, (int2 *)ctx->box_work.p);
       err = launch_loop_any<MODE, true>(ctx->stream, a, cfg, (const LoopArgs *)ctx->box_args.p,
-                                        (const int2 *)ctx->box_work.p, (int)ctx->n_chunks,
-                                        (int *)ctx->scalars.p + SC_WORKCTR, persistent_grid_for(ctx->n_cu, cfg));
+                                        (const int2 *)ctx->box_work.p, (int)ni, (int *)ctx->scalars.p + SC_WORKCTR,
+                                        persistent_grid_for(ctx->n_cu, cfg));
     } else {
       err = launch_loop_any<MODE, true>(ctx->stream, a, cfg, nullptr, nullptr, 0, nullptr, 0);
     }
@@ -617,70 +699,60 @@ extern "C" sph_status sph_autotune(sph_ctx *ctx, sph_particles *p, const char *p
   if (ctx->state < 5) return sph_fail(ctx, SPH_ESTATE, "autotune: run a force pass first");
   if (ctx->n_chunks == 0) return SPH_OK;
   const int cls = tune_class(ctx->n_chunks);
-  SPH_TRY(order_chunks_by_cost(ctx));
-  ctx->work_valid = 1;
-  SPH_TRY(sph_ensure(ctx, ctx->box_args, sizeof(LoopArgs)));
-  SPH_TRY(sph_ensure(ctx, ctx->box_work, sizeof(int2) * (size_t)ctx->n_chunks));
   const int prof = ctx->prof;
   ctx->prof = 0;
   FILE *f = path ? fopen(path, "a") : nullptr;
-  for (int mode = 0; mode < 2; ++mode) {
-    LoopArgs a = base_args(ctx);
+  sph_status st = SPH_OK;
+  for (int mode = 0; mode < 2 && st == SPH_OK; ++mode) {
+    LoopArgs a;
     if (mode == 0) {
-      a.pair_off = (const int32_t *)ctx->dpair_off.p;
-      a.pairs = (const PairEntry *)ctx->dpairs.p;
-      a.sums = (float *)ctx->sums.p;
-      a.act_cnt = (int32_t *)ctx->sums.p + 8 * ctx->n_active;
+      a = density_loop_args(ctx);
     } else {
-      a.pair_off = (const int32_t *)ctx->fpair_off.p;
-      a.pairs = (const PairEntry *)ctx->fpairs.p;
-      a.ax_out = p->ax;
-      a.ay_out = p->ay;
-      a.az_out = p->az;
-      a.dA_out = p->dA_dt;
-      a.du_out = p->du_dt;
-      a.vsig_out = p->vsig;
-      a.nngb_out = p->nngb_force;
+      a = force_loop_args(ctx, p);
       // counts of tuning launches are not interactions of a step
-      a.ctr = (unsigned long long *)ctx->work_tmp.p;
+      SPH_TRY(sph_ensure(ctx, ctx->box_args, sizeof(LoopArgs) + 64));
+      a.ctr = (unsigned long long *)((char *)ctx->box_args.p + sizeof(LoopArgs) + 32);
     }
     sph_ctx::TuneEntry best;
     best.ms = INFINITY;
     const int nws[4] = {1, 2, 4, 8};
-    for (int wi = 0; wi < 4; ++wi)
-      for (int tile = 0; tile <= 4; ++tile)
-        for (int ordered = 0; ordered <= 1; ++ordered)
-          for (int pers = 0; pers <= 1; ++pers) {
-            LoopConfig c;
-            c.nw = nws[wi];
-            c.tile = tile;
-            c.ordered = ordered;
-            c.persistent = pers;
-            if (!loop_config_valid(c)) continue;
-            float ms = 0.f;
-            if (mode == 0)
-              SPH_TRY(time_config<0>(ctx, a, c, 2, &ms));
-            else
-              SPH_TRY(time_config<1>(ctx, a, c, 2, &ms));
-            if (f)
-              fprintf(f, "candidate %d %d %d %d %d %d %.6f %lld\n", mode, cls, c.nw, c.tile, c.ordered, c.persistent,
-                      ms, (long long)ctx->n_chunks);
-            if (ms < best.ms) {
-              best.valid = 1;
-              best.nw = c.nw;
-              best.tile = c.tile;
-              best.ordered = c.ordered;
-              best.persistent = c.persistent;
-              best.ms = ms;
+    for (int wi = 0; wi < 4 && st == SPH_OK; ++wi)
+      for (int tile = 0; tile <= 4 && st == SPH_OK; ++tile)
+        for (int split = 0; split <= 2 && st == SPH_OK; ++split)
+          for (int ordered = 0; ordered <= 1 && st == SPH_OK; ++ordered)
+            for (int pers = 0; pers <= 1 && st == SPH_OK; ++pers) {
+              LoopConfig c;
+              c.nw = nws[wi];
+              c.tile = tile;
+              c.ordered = ordered;
+              c.persistent = pers;
+              c.split = split;
+              if (!loop_config_valid(c)) continue;
+              float ms = 0.f;
+              st = mode == 0 ? time_config<0>(ctx, a, c, 2, &ms) : time_config<1>(ctx, a, c, 2, &ms);
+              if (st != SPH_OK) break;
+              if (f)
+                fprintf(f, "candidate %d %d %d %d %d %d %d %.6f %lld\n", mode, cls, c.nw, c.tile, c.ordered,
+                        c.persistent, c.split, ms, (long long)ctx->n_chunks);
+              if (ms < best.ms) {
+                best.valid = 1;
+                best.nw = c.nw;
+                best.tile = c.tile;
+                best.ordered = c.ordered;
+                best.persistent = c.persistent;
+                best.split = c.split;
+                best.ms = ms;
+              }
             }
-          }
+    if (st != SPH_OK) break;
     ctx->tune[mode][cls] = best;
     if (f)
-      fprintf(f, "best %d %d %d %d %d %d %.6f %lld\n", mode, cls, best.nw, best.tile, best.ordered, best.persistent,
-              best.ms, (long long)ctx->n_chunks);
+      fprintf(f, "best %d %d %d %d %d %d %d %.6f %lld\n", mode, cls, best.nw, best.tile, best.ordered,
+              best.persistent, best.split, best.ms, (long long)ctx->n_chunks);
   }
   if (f) fclose(f);
   ctx->prof = prof;
+  if (st != SPH_OK) return st;
   // leave every chunk marked done, as after a completed pass
   HIP_TRY(ctx, hipMemsetAsync(ctx->chunk_todo.p, 0, 4 * (size_t)ctx->n_chunks, ctx->stream));
   return sph_sync(ctx);
@@ -691,16 +763,18 @@ extern "C" sph_status sph_load_tuning(sph_ctx *ctx, const char *path) {
   FILE *f = fopen(path, "r");
   if (!f) return sph_fail(ctx, SPH_EINVAL, "load_tuning: cannot open %s", path);
   char tag[32];
-  int mode, cls, nw, tile, ord, pers;
+  int mode, cls, nw, tile, ord, pers, split;
   float ms;
   long long nc;
   int loaded = 0;
-  while (fscanf(f, "%31s %d %d %d %d %d %d %f %lld", tag, &mode, &cls, &nw, &tile, &ord, &pers, &ms, &nc) == 9) {
+  while (fscanf(f, "%31s %d %d %d %d %d %d %d %f %lld", tag, &mode, &cls, &nw, &tile, &ord, &pers, &split, &ms,
+                &nc) == 10) {
     const bool single = strcmp(tag, "best") == 0, batch = strcmp(tag, "batch_best") == 0;
     if ((!single && !batch) || mode < 0 || mode > 1 || cls < 0 || cls > 31) continue;
     LoopConfig c;
     c.nw = nw;
     c.tile = tile;
+    c.split = split;
     if (!loop_config_valid(c)) continue;
     auto &t = single ? ctx->tune[mode][cls] : ctx->btune[mode][cls];
     t.valid = 1;
@@ -708,6 +782,7 @@ extern "C" sph_status sph_load_tuning(sph_ctx *ctx, const char *path) {
     t.tile = tile;
     t.ordered = ord != 0;
     t.persistent = pers != 0;
+    t.split = split;
     t.ms = ms;
     ++loaded;
   }
@@ -728,10 +803,12 @@ extern "C" sph_status sph_load_tuning(sph_ctx *ctx, const char *path) {
 namespace {
 
 struct BatchItems {
+  const int32_t *items;     // the box's work items in chunk order (codes chunk * 16 + part)
+  const int32_t *item0;     // first item of each chunk (null: one part per chunk)
   const Chunk *chunks;
   const int32_t *act_cost;
   int32_t *todo;
-  int64_t n_chunks;
+  int64_t n_items, n_chunks;
   int64_t off;  // first work item of this box
   int32_t box;  // index into the launch's box descriptors
 };
@@ -743,13 +820,17 @@ __global__ __launch_bounds__(256) void batch_bucket_kernel(const BatchItems *__r
   if (threadIdx.x < 32) h[threadIdx.x] = 0;
   __syncthreads();
   const BatchItems b = boxes[blockIdx.y];
-  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < b.n_chunks; q += (int64_t)gridDim.x * 256) {
-    const int cost = max(1, b.act_cost[b.chunks[q].act_leaf]);
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < b.n_items; q += (int64_t)gridDim.x * 256) {
+    const int cid = b.items[q] >> 4;
+    const int P = b.item0 ? b.item0[cid + 1] - b.item0[cid] : 1;
+    const int cost = max(1, b.act_cost[b.chunks[cid].act_leaf] / P);
     const int k = __clz(cost);
     bucket_of[b.off + q] = k;
     atomicAdd(&h[k], 1);
-    if (set_todo) b.todo[q] = 1;
   }
+  if (set_todo)
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < b.n_chunks; q += (int64_t)gridDim.x * 256)
+      b.todo[q] = 1;
   __syncthreads();
   if (threadIdx.x < 32 && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
 }
@@ -758,8 +839,8 @@ __global__ __launch_bounds__(256) void batch_scatter_kernel(const BatchItems *__
                                                             const int32_t *__restrict__ bucket_of,
                                                             int32_t *__restrict__ cursor, int2 *__restrict__ work) {
   const BatchItems b = boxes[blockIdx.y];
-  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < b.n_chunks; q += (int64_t)gridDim.x * 256)
-    work[atomicAdd(&cursor[bucket_of[b.off + q]], 1)] = make_int2(b.box, (int)q);
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < b.n_items; q += (int64_t)gridDim.x * 256)
+    work[atomicAdd(&cursor[bucket_of[b.off + q]], 1)] = make_int2(b.box, b.items[q]);
 }
 
 __global__ __launch_bounds__(256) void batch_todo_kernel(const BatchItems *__restrict__ boxes) {
@@ -801,13 +882,16 @@ LoopConfig batch_config(sph_ctx *lead, int mode, int64_t total) {
     c.nw = t.nw;
     c.tile = t.tile;
     c.persistent = t.persistent;
+    c.split = t.split;
     return c;
   }
   c.persistent = 1;
+  c.split = lead->prm.chunk_split;
   if (lead->prm.waves_per_chunk > 0) {
     const LoopConfig s = choose_config(lead, mode);  // the parameter rule
     c.nw = s.nw;
     c.tile = s.tile;
+    c.split = s.split;
     return c;
   }
   if (total < 2048) {
@@ -833,22 +917,40 @@ sph_status batch_fail(sph_ctx *lead, int b, sph_ctx *box, sph_status st) {
     if (_s != SPH_OK) return batch_fail(lead, (b), cs[(b)], _s); \
   } while (0)
 
-// Uploads the item descriptors of the boxes in `live` and writes the
-// cost-ordered work list; returns the number of items.
+// Builds every live box's work items for the batch's split target (one
+// synchronisation for all boxes), uploads the item descriptors and writes the
+// cost-ordered (box, item) list; returns the number of items.
 sph_status batch_work_list(sph_ctx *lead, sph_ctx **cs, const std::vector<int> &live, Staging &s, int set_todo,
-                           int64_t *total_out) {
+                           int target, int64_t *total_out) {
   const int nl = (int)live.size();
+  std::vector<int32_t> totals(nl, 0);
+  bool any = false;
+  for (int q = 0; q < nl; ++q) {
+    sph_ctx *c = cs[live[q]];
+    if (c->work_valid && c->items_target == target) continue;
+    SPH_TRY(items_count(c, target, &totals[q]));
+    any = true;
+  }
+  if (any) HIP_TRY(lead, hipStreamSynchronize(lead->stream));
+  for (int q = 0; q < nl; ++q) {
+    sph_ctx *c = cs[live[q]];
+    if (c->work_valid && c->items_target == target) continue;
+    SPH_TRY(items_fill(c, target, totals[q]));
+  }
   int64_t total = 0, maxc = 0;
   for (int q = 0; q < nl; ++q) {
     sph_ctx *c = cs[live[q]];
+    s.items[q].items = (const int32_t *)c->items_nat.p;
+    s.items[q].item0 = target > 0 ? (const int32_t *)c->chunk_item0.p : nullptr;
     s.items[q].chunks = (const Chunk *)c->chunks.p;
     s.items[q].act_cost = (const int32_t *)c->act_cost.p;
     s.items[q].todo = (int32_t *)c->chunk_todo.p;
+    s.items[q].n_items = c->n_items;
     s.items[q].n_chunks = c->n_chunks;
     s.items[q].off = total;
     s.items[q].box = q;
-    total += c->n_chunks;
-    if (c->n_chunks > maxc) maxc = c->n_chunks;
+    total += c->n_items;
+    maxc = std::max<int64_t>(maxc, std::max<int64_t>(c->n_items, c->n_chunks));
   }
   *total_out = total;
   SPH_TRY(sph_ensure(lead, lead->batch_items, sizeof(BatchItems) * (size_t)nl));
@@ -867,6 +969,14 @@ sph_status batch_work_list(sph_ctx *lead, sph_ctx **cs, const std::vector<int> &
   batch_scatter_kernel<<<grid, 256, 0, lead->stream>>>((const BatchItems *)lead->batch_items.p, bucket_of, hist,
                                                        (int2 *)lead->batch_work.p);
   return sph_hip_check(lead, hipGetLastError(), "batch work list");
+}
+
+// Per-box loop arguments of a batched launch: the box's split-chunk state.
+void batch_split_args(sph_ctx *c, int target, LoopArgs &a) {
+  a.work = nullptr;
+  a.chunk_item0 = target > 0 ? (const int32_t *)c->chunk_item0.p : nullptr;
+  a.chunk_ctr = target > 0 ? (int32_t *)c->chunk_ctr.p : nullptr;
+  a.partials = target > 0 ? (float *)c->partials.p : nullptr;
 }
 
 template <int MODE, bool COMP>
@@ -913,12 +1023,15 @@ sph_status batch_density_impl(sph_ctx **cs, sph_particles *ps, int nb, int entro
   if (live.empty()) return SPH_OK;
   const int nl = (int)live.size();
   Staging s = staging(lead, nl);
+  int64_t nchunks = 0;
+  for (int b : live) nchunks += cs[b]->n_chunks;
+  const LoopConfig cfg = batch_config(lead, 0, nchunks);
+  const int target = split_target(cfg.split);
   int64_t total;
-  SPH_TRY(batch_work_list(lead, cs, live, s, 0, &total));
+  SPH_TRY(batch_work_list(lead, cs, live, s, 0, target, &total));
   SPH_TRY(sph_ensure(lead, lead->batch_args, sizeof(LoopArgs) * (size_t)nl));
   SPH_TRY(sph_ensure(lead, lead->batch_ghost, sizeof(GhostArgs) * (size_t)nl));
   SPH_TRY(sph_ensure(lead, lead->batch_status, 8 * (size_t)nl));
-  const LoopConfig cfg = batch_config(lead, 0, total);
   std::vector<int> iterating(live);  // boxes (indices into cs) still solving
   std::vector<int32_t> st(2 * (size_t)nl);
   const int maxit = lead->prm.h_max_iter;
@@ -927,7 +1040,11 @@ sph_status batch_density_impl(sph_ctx **cs, sph_particles *ps, int nb, int entro
       return sph_fail(lead, SPH_EINVAL, "batch_density_pass: box %d has another h_max_iter", b);
   for (int it = 1; it <= maxit && !iterating.empty(); ++it) {
     // loop over every live box's chunks (finished boxes have no chunk to do)
-    for (int q = 0; q < nl; ++q) s.args[q] = density_loop_args(cs[live[q]]);
+    for (int q = 0; q < nl; ++q) {
+      BATCH_TRY(live[q], sort_partners(cs[live[q]], 0));
+      s.args[q] = density_loop_args(cs[live[q]]);
+      batch_split_args(cs[live[q]], target, s.args[q]);
+    }
     HIP_TRY(lead, hipMemcpyAsync(lead->batch_args.p, s.args, sizeof(LoopArgs) * nl, hipMemcpyHostToDevice,
                                  lead->stream));
     if (lead->prm.compensated)
@@ -1008,13 +1125,20 @@ sph_status batch_force_impl(sph_ctx **cs, sph_particles *ps, int nb) {
   HIP_TRY(lead, hipStreamSynchronize(lead->stream));
   for (int q = 0; q < nl; ++q) BATCH_TRY(live[q], build_pairs_fill(cs[live[q]], 1, 1.0f, np[q]));
   Staging s = staging(lead, nl);
+  int64_t nchunks = 0;
+  for (int b : live) nchunks += cs[b]->n_chunks;
+  const LoopConfig cfg = batch_config(lead, 1, nchunks);
+  const int target = split_target(cfg.split);
   int64_t total;
-  SPH_TRY(batch_work_list(lead, cs, live, s, 1, &total));
+  SPH_TRY(batch_work_list(lead, cs, live, s, 1, target, &total));
   SPH_TRY(sph_ensure(lead, lead->batch_args, sizeof(LoopArgs) * (size_t)nl));
-  for (int q = 0; q < nl; ++q) s.args[q] = force_loop_args(cs[live[q]], &ps[live[q]]);
+  for (int q = 0; q < nl; ++q) {
+    BATCH_TRY(live[q], sort_partners(cs[live[q]], 1));
+    s.args[q] = force_loop_args(cs[live[q]], &ps[live[q]]);
+    batch_split_args(cs[live[q]], target, s.args[q]);
+  }
   HIP_TRY(lead, hipMemcpyAsync(lead->batch_args.p, s.args, sizeof(LoopArgs) * nl, hipMemcpyHostToDevice,
                                lead->stream));
-  const LoopConfig cfg = batch_config(lead, 1, total);
   if (lead->prm.compensated)
     SPH_TRY((batch_launch<1, true>(lead, cfg, total, "force_loop")));
   else
@@ -1033,13 +1157,13 @@ sph_status batch_autotune_impl(sph_ctx **cs, sph_particles *ps, int nb, const ch
   if (live.empty()) return SPH_OK;
   const int nl = (int)live.size();
   Staging s = staging(lead, nl);
-  int64_t total;
-  SPH_TRY(batch_work_list(lead, cs, live, s, 1, &total));
+  int64_t nchunks = 0;
+  for (int b : live) nchunks += cs[b]->n_chunks;
   SPH_TRY(sph_ensure(lead, lead->batch_args, sizeof(LoopArgs) * (size_t)nl));
   SPH_TRY(sph_ensure(lead, lead->batch_status, 8 * (size_t)nl + 64));
   // counts of tuning launches are not interactions of a step
   unsigned long long *scratch_ctr = (unsigned long long *)((char *)lead->batch_status.p + 8 * (size_t)nl);
-  const int cls = tune_class(total);
+  const int cls = tune_class(nchunks);
   const int prof = lead->prof;
   lead->prof = 0;
   FILE *f = path ? fopen(path, "a") : nullptr;
@@ -1048,56 +1172,66 @@ sph_status batch_autotune_impl(sph_ctx **cs, sph_particles *ps, int nb, const ch
   HIP_TRY(lead, hipEventCreate(&e1));
   sph_status st = SPH_OK;
   for (int mode = 0; mode < 2 && st == SPH_OK; ++mode) {
-    HIP_TRY(lead, hipStreamSynchronize(lead->stream));
-    for (int q = 0; q < nl; ++q) {
-      s.args[q] = mode == 0 ? density_loop_args(cs[live[q]]) : force_loop_args(cs[live[q]], &ps[live[q]]);
-      if (mode == 1) s.args[q].ctr = scratch_ctr;
-    }
-    HIP_TRY(lead, hipMemcpyAsync(lead->batch_args.p, s.args, sizeof(LoopArgs) * nl, hipMemcpyHostToDevice,
-                                 lead->stream));
     sph_ctx::TuneEntry best;
     best.ms = INFINITY;
-    const int nws[4] = {1, 2, 4, 8};
-    for (int wi = 0; wi < 4 && st == SPH_OK; ++wi)
-      for (int tile = 0; tile <= 4 && st == SPH_OK; ++tile)
-        for (int pers = 0; pers <= 1 && st == SPH_OK; ++pers) {
-          LoopConfig c;
-          c.nw = nws[wi];
-          c.tile = tile;
-          c.ordered = 1;
-          c.persistent = pers;
-          if (!loop_config_valid(c)) continue;
-          float bestc = INFINITY;
-          for (int r = 0; r <= 2; ++r) {
-            batch_todo_kernel<<<dim3(grid_x_for(total), nl), 256, 0, lead->stream>>>(
-                (const BatchItems *)lead->batch_items.p);
-            HIP_TRY(lead, hipEventRecord(e0, lead->stream));
-            st = mode == 0 ? batch_launch<0, true>(lead, c, total, "tune") : batch_launch<1, true>(lead, c, total, "tune");
+    for (int split = 0; split <= 2 && st == SPH_OK; ++split) {
+      const int target = split_target(split);
+      int64_t total;
+      st = batch_work_list(lead, cs, live, s, 1, target, &total);
+      if (st != SPH_OK) break;
+      HIP_TRY(lead, hipStreamSynchronize(lead->stream));
+      for (int q = 0; q < nl; ++q) {
+        s.args[q] = mode == 0 ? density_loop_args(cs[live[q]]) : force_loop_args(cs[live[q]], &ps[live[q]]);
+        batch_split_args(cs[live[q]], target, s.args[q]);
+        if (mode == 1) s.args[q].ctr = scratch_ctr;
+      }
+      HIP_TRY(lead, hipMemcpyAsync(lead->batch_args.p, s.args, sizeof(LoopArgs) * nl, hipMemcpyHostToDevice,
+                                   lead->stream));
+      const int nws[4] = {1, 2, 4, 8};
+      for (int wi = 0; wi < 4 && st == SPH_OK; ++wi)
+        for (int tile = 0; tile <= 4 && st == SPH_OK; ++tile)
+          for (int pers = 0; pers <= 1 && st == SPH_OK; ++pers) {
+            LoopConfig c;
+            c.nw = nws[wi];
+            c.tile = tile;
+            c.ordered = 1;
+            c.persistent = pers;
+            c.split = split;
+            if (!loop_config_valid(c)) continue;
+            float bestc = INFINITY;
+            for (int r = 0; r <= 2; ++r) {
+              batch_todo_kernel<<<dim3(grid_x_for(nchunks), nl), 256, 0, lead->stream>>>(
+                  (const BatchItems *)lead->batch_items.p);
+              HIP_TRY(lead, hipEventRecord(e0, lead->stream));
+              st = mode == 0 ? batch_launch<0, true>(lead, c, total, "tune")
+                             : batch_launch<1, true>(lead, c, total, "tune");
+              if (st != SPH_OK) break;
+              HIP_TRY(lead, hipEventRecord(e1, lead->stream));
+              HIP_TRY(lead, hipEventSynchronize(e1));
+              float ms = 0.f;
+              HIP_TRY(lead, hipEventElapsedTime(&ms, e0, e1));
+              if (r > 0 && ms < bestc) bestc = ms;  // the first launch warms caches
+            }
             if (st != SPH_OK) break;
-            HIP_TRY(lead, hipEventRecord(e1, lead->stream));
-            HIP_TRY(lead, hipEventSynchronize(e1));
-            float ms = 0.f;
-            HIP_TRY(lead, hipEventElapsedTime(&ms, e0, e1));
-            if (r > 0 && ms < bestc) bestc = ms;  // the first launch warms caches
+            if (f)
+              fprintf(f, "batch_candidate %d %d %d %d %d %d %d %.6f %lld\n", mode, cls, c.nw, c.tile, c.ordered,
+                      c.persistent, c.split, bestc, (long long)nchunks);
+            if (bestc < best.ms) {
+              best.valid = 1;
+              best.nw = c.nw;
+              best.tile = c.tile;
+              best.ordered = 1;
+              best.persistent = c.persistent;
+              best.split = c.split;
+              best.ms = bestc;
+            }
           }
-          if (st != SPH_OK) break;
-          if (f)
-            fprintf(f, "batch_candidate %d %d %d %d %d %d %.6f %lld\n", mode, cls, c.nw, c.tile, c.ordered,
-                    c.persistent, bestc, (long long)total);
-          if (bestc < best.ms) {
-            best.valid = 1;
-            best.nw = c.nw;
-            best.tile = c.tile;
-            best.ordered = 1;
-            best.persistent = c.persistent;
-            best.ms = bestc;
-          }
-        }
+    }
     if (st == SPH_OK) {
       lead->btune[mode][cls] = best;
       if (f)
-        fprintf(f, "batch_best %d %d %d %d %d %d %.6f %lld\n", mode, cls, best.nw, best.tile, best.ordered,
-                best.persistent, best.ms, (long long)total);
+        fprintf(f, "batch_best %d %d %d %d %d %d %d %.6f %lld\n", mode, cls, best.nw, best.tile, best.ordered,
+                best.persistent, best.split, best.ms, (long long)nchunks);
     }
   }
   if (f) fclose(f);

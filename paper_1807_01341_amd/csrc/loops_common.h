@@ -53,8 +53,14 @@ struct LoopArgs {
   int32_t *chunk_todo;
   int64_t n_chunks;
   int64_t per_xcd;
-  const int32_t *work;  // optional cost-ordered chunk list (grid kernel)
+  const int32_t *work;  // optional work-item list: codes chunk * 16 + part
   int64_t n_items;      // grid items: chunks, or entries of `work`
+  int xcd;              // grid kernel: consecutive items to the same XCD
+  // split chunks: a chunk's pair list in parts [chunk_item0[c], chunk_item0[c+1]);
+  // null when no chunk is split
+  const int32_t *chunk_item0;
+  int32_t *chunk_ctr;   // arrivals per chunk (counts up; the last of a round combines)
+  float *partials;      // per item: 11 x 64 per-lane partial results
   const int32_t *active_idx;
   const float4 *pos4;  // (ox, oy, oz, H)
   const float4 *jvm;   // (vx, vy, vz, m)
@@ -165,9 +171,13 @@ struct WaveLds {
 // are combined across waves in wave order at the end.  `lds` holds NW wave
 // regions of WaveLds::bytes each.
 template <int MODE, int CAP, int LCAP, bool COMP, int NW>
-__device__ __forceinline__ void chunk_body(const LoopArgs &g, int cid, char *lds) {
+__device__ __forceinline__ void chunk_body(const LoopArgs &g, int code, bool coded, char *lds) {
   using W = WaveLds<MODE, CAP, LCAP>;
   constexpr int FB = LCAP / 2 < 64 ? LCAP / 2 : 64;  // candidates filtered between list checks
+  // work item: a chunk, or one part of a chunk's cell-pair list
+  const int cid = coded ? code >> 4 : code;
+  const int part = coded ? code & 15 : 0;
+  const int nparts = g.chunk_item0 ? g.chunk_item0[cid + 1] - g.chunk_item0[cid] : 1;
   if (!g.chunk_todo[cid]) return;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -409,7 +419,9 @@ __device__ __forceinline__ void chunk_body(const LoopArgs &g, int cid, char *lds
     wave_sync();
   };
 
-  const int pbeg = g.pair_off[ch.act_leaf], pend = g.pair_off[ch.act_leaf + 1];
+  const int pbeg0 = g.pair_off[ch.act_leaf], npair = g.pair_off[ch.act_leaf + 1] - pbeg0;
+  const int pbeg = pbeg0 + (int)((int64_t)npair * part / nparts);
+  const int pend = pbeg0 + (int)((int64_t)npair * (part + 1) / nparts);
   for (int pp = pbeg + wave; pp < pend; pp += NW) {
     const PairEntry e = g.pairs[pp];
     const int B = e.b;
@@ -521,6 +533,42 @@ __device__ __forceinline__ void chunk_body(const LoopArgs &g, int cid, char *lds
     res[5] = MODE == 1 ? vm : res[5];
     cnt = csum;
   }
+  if (nparts > 1) {
+    // publish this part's per-lane results; the last part of the chunk to
+    // arrive combines all parts in part order (deterministic) and finishes
+    const int64_t item0 = g.chunk_item0[cid];
+    float *mine_p = g.partials + (item0 + part) * (11 * 64);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) mine_p[q * 64 + lane] = res[q];
+    mine_p[9 * 64 + lane] = __int_as_float(cnt);
+    __threadfence();
+    int old = 0;
+    if (lane == 0) old = atomicAdd(&g.chunk_ctr[cid], 1);
+    old = __shfl(old, 0, 64);
+    if ((old + 1) % nparts != 0) return;
+    __threadfence();
+    Neu sum[9];
+    int csum = 0;
+    float vm = 0.f;
+    for (int pp = 0; pp < nparts; ++pp) {
+      const float *rp = g.partials + (item0 + pp) * (11 * 64);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        const float v = rp[q * 64 + lane];
+        if (MODE == 1 && q == 5)
+          vm = fmaxf(vm, v);
+        else if (COMP)
+          sum[q].add(v);
+        else
+          sum[q].s += v;
+      }
+      csum += __float_as_int(rp[9 * 64 + lane]);
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) res[q] = sum[q].value();
+    res[5] = MODE == 1 ? vm : res[5];
+    cnt = csum;
+  }
   if (lane == 0) g.chunk_todo[cid] = 0;
 
   if (live) {
@@ -560,7 +608,7 @@ template <int MODE, int CAP, int LCAP, bool COMP, int NW>
 __global__ __launch_bounds__(64 * NW) void loop_grid_kernel(LoopArgs g) {
   __shared__ __align__(16) char lds[NW * WaveLds<MODE, CAP, LCAP>::bytes];
   int item;
-  if (g.work) {
+  if (!g.xcd) {
     item = blockIdx.x;
   } else {
     const int64_t b = blockIdx.x;
@@ -568,8 +616,10 @@ __global__ __launch_bounds__(64 * NW) void loop_grid_kernel(LoopArgs g) {
     item = (int)c;
   }
   if (item >= g.n_items) return;
-  const int cid = g.work ? g.work[item] : item;
-  chunk_body<MODE, CAP, LCAP, COMP, NW>(g, cid, lds);
+  if (g.work)
+    chunk_body<MODE, CAP, LCAP, COMP, NW>(g, g.work[item], true, lds);
+  else
+    chunk_body<MODE, CAP, LCAP, COMP, NW>(g, item, false, lds);
 }
 
 // Persistent variant: a grid sized to the machine pulls work items (box,
@@ -588,7 +638,7 @@ __global__ __launch_bounds__(64 * NW) void loop_persistent_kernel(const LoopArgs
     __syncthreads();
     if (item >= n_items) break;
     const int2 w = work[item];
-    chunk_body<MODE, CAP, LCAP, COMP, NW>(boxes[w.x], w.y, lds);
+    chunk_body<MODE, CAP, LCAP, COMP, NW>(boxes[w.x], w.y, true, lds);
     __syncthreads();
   }
 }
@@ -601,7 +651,7 @@ __global__ __launch_bounds__(64 * NW) void loop_multi_kernel(const LoopArgs *__r
   const int item = blockIdx.x;
   if (item >= n_items) return;
   const int2 w = work[item];
-  chunk_body<MODE, CAP, LCAP, COMP, NW>(boxes[w.x], w.y, lds);
+  chunk_body<MODE, CAP, LCAP, COMP, NW>(boxes[w.x], w.y, true, lds);
 }
 
 // Loop tiling: waves per chunk, tile class (candidate slots / list slots per
@@ -612,9 +662,14 @@ struct LoopConfig {
   int tile = 2;
   int ordered = 0;     // 1: chunks in decreasing cost order, 0: Morton order
   int persistent = 0;  // 1: persistent grid with an atomic work counter
+  int split = 0;       // chunk splitting class: 0 none, 1 / 2 parts of ~1024 / ~4096 staged particles
 };
 
+// Staged partner particles per work item of a split class (0: no splitting).
+inline int split_target(int split) { return split == 1 ? 1024 : split == 2 ? 4096 : 0; }
+
 inline bool loop_config_valid(const LoopConfig &c) {
+  if (c.split < 0 || c.split > 2) return false;
   switch (c.nw) {
     case 1: return c.tile >= 0 && c.tile <= 4;
     case 2: return c.tile >= 0 && c.tile <= 2;
@@ -643,11 +698,12 @@ hipError_t launch_loop_t(hipStream_t st, const LoopArgs &a, const LoopConfig &cf
   } else {
     LoopArgs g = a;
     int64_t grid;
-    if (g.work) {
+    if (!g.work) g.n_items = g.n_chunks;
+    g.xcd = !cfg.ordered;
+    if (!g.xcd) {
       grid = g.n_items;
     } else {
-      g.n_items = g.n_chunks;
-      g.per_xcd = ceil_div(g.n_chunks, 8);
+      g.per_xcd = ceil_div(g.n_items, 8);
       grid = 8 * (g.per_xcd > 0 ? g.per_xcd : 1);
     }
     loop_grid_kernel<MODE, CAP, LCAP, COMP, NW><<<(unsigned)(grid > 0 ? grid : 1), 64 * NW, 0, st>>>(g);

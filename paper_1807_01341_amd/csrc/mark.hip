@@ -259,7 +259,6 @@ sph_status build_pairs_count(sph_ctx *ctx, int which, float slack, int32_t *host
   DevBuf &off = which == 0 ? ctx->dpair_off : ctx->fpair_off;
   SPH_TRY(sph_ensure(ctx, ctx->pair_cnt, 4 * (size_t)(na + 1)));
   SPH_TRY(sph_ensure(ctx, ctx->act_cost, 4 * (size_t)(na + 1)));
-  if (which == 0) ctx->work_valid = 0;
   SPH_TRY(sph_ensure(ctx, off, 4 * (size_t)(na + 1)));
   *host_total = 0;
   if (na == 0) {
@@ -288,6 +287,7 @@ sph_status build_pairs_fill(sph_ctx *ctx, int which, float slack, int32_t np) {
   DevBuf &off = which == 0 ? ctx->dpair_off : ctx->fpair_off;
   DevBuf &lst = which == 0 ? ctx->dpairs : ctx->fpairs;
   if (which == 0) ctx->n_dpairs = np; else ctx->n_fpairs = np;
+  ctx->sorted_lists &= ~(1 << which);  // new partners may need their axis sorts
   if (na == 0) return SPH_OK;
   SPH_TRY(sph_ensure(ctx, lst, sizeof(PairEntry) * (size_t)(np > 0 ? np : 1)));
   const PairGeom g = pair_geom(ctx);
@@ -391,6 +391,9 @@ sph_status mark_active_impl(sph_ctx *ctx, const sph_particles *p, int m, int64_t
         (Chunk *)ctx->chunks.p);
   }
   HIP_TRY(ctx, hipGetLastError());
+  // new chunks: the loop work items are rebuilt at the next launch (they keep
+  // the costs of these lists through the pass, also if the lists are widened)
+  ctx->work_valid = 0;
   SPH_TRY(build_pairs(ctx, 0, 1.0f));
   if (n_active_host) *n_active_host = ctx->n_active;
   ctx->state = 3;

@@ -17,9 +17,17 @@
 
 #define WAVE 64
 
+// Device allocation owned by the context: grown by sph_ensure, freed with the
+// context.
 struct DevBuf {
   void *p = nullptr;
   size_t cap = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
 };
 
 // Pair-list entry: partner leaf index (as int bits) and the FP32 shift of the
@@ -65,6 +73,9 @@ struct sph_ctx {
   DevBuf pos4;                            // float4 (ox, oy, oz, H) per particle
   // sort
   DevBuf axis_order;                      // uint16 13 x n
+  DevBuf leaf_sorted, sort_list;          // per leaf: axis orders made this step; leaves to sort
+  int max_leaf = 0;                       // largest leaf of the build
+  int sorted_lists = 0;                   // bit w: partners of cell-pair list w are sorted
   // mark
   DevBuf active, leaf_nact, leaf_act_off, leaf_actleaf, act_leaves, act_hmax, act_leaf_chunk_off;
   DevBuf active_idx, chunk_of, chunks, chunk_todo;
@@ -76,14 +87,19 @@ struct sph_ctx {
   DevBuf counters64;                      // cumulative interaction counts (2 x uint64)
   DevBuf act_cost;                        // staged partner particles per active leaf
   DevBuf work, work_tmp, box_args, box_work;
-  int work_valid = 0;                     // work (cost order) matches the current chunks
+  int work_valid = 0;                     // the work items match the current chunks and costs
+  // loop work items (codes chunk * 16 + part): chunk order and cost order,
+  // first item of every chunk, arrival counters and partial results of split chunks
+  DevBuf items_nat, chunk_item0, chunk_ctr, partials;
+  int64_t n_items = 0;
+  int items_target = -1;                  // staged particles per part the items were built for
   int density_from_u = 0;                 // the last density pass took P from u
   // adjoint
   DevBuf adj_w, adj1, adj2, adj_out;
 
   // tuned loop configurations per pass (0 density, 1 force) and chunk-count class
   struct TuneEntry {
-    int valid = 0, nw = 1, tile = 2, ordered = 0, persistent = 0;
+    int valid = 0, nw = 1, tile = 2, ordered = 0, persistent = 0, split = 0;
     float ms = 0.f;
   };
   TuneEntry tune[2][32];
@@ -165,6 +181,8 @@ sph_status build_pairs(sph_ctx *ctx, int which, float slack);
 sph_status build_pairs_count(sph_ctx *ctx, int which, float slack, int32_t *host_total);
 sph_status build_pairs_fill(sph_ctx *ctx, int which, float slack, int32_t np);
 sph_status refresh_leaf_hmax(sph_ctx *ctx, bool read_global);
+sph_status sort_partners(sph_ctx *ctx, int which);
+sph_status sort_all_leaves(sph_ctx *ctx);
 sph_status pack_neighbour_data(sph_ctx *ctx, const sph_particles *p);
 sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u);
 sph_status force_pass_impl(sph_ctx *ctx, sph_particles *p);

@@ -38,12 +38,14 @@ def snapshot(ps):
     return [{k: host(p, k).copy() for k in OUTPUTS} for p in ps]
 
 
-def test_batch_equals_separate_passes_64_boxes(gpu_lib):
+@pytest.mark.parametrize("split", [0, 1])
+def test_batch_equals_separate_passes_64_boxes(gpu_lib, split):
     sg = gpu_lib
     boxes = ics.batch_of_boxes()
     ms = [ics.deep_bin_for_fraction(b["bin"], b["target_active_fraction"]) for b in boxes]
-    print(f"case batch64 N={sum(b['x'].shape[0] for b in boxes)}", flush=True)
-    cs, ps, _ = prepare(sg, boxes, ms, TILING)
+    print(f"case batch64 N={sum(b['x'].shape[0] for b in boxes)} split={split}", flush=True)
+    tiling = dict(TILING, chunk_split=split)
+    cs, ps, _ = prepare(sg, boxes, ms, tiling)
     for c, p in zip(cs, ps):
         c.density_pass(p, False)
         c.force_pass(p)
@@ -51,7 +53,7 @@ def test_batch_equals_separate_passes_64_boxes(gpu_lib):
     ref = snapshot(ps)
     ref_info = [c.info() for c in cs]
     del cs, ps
-    cs, ps, _ = prepare(sg, boxes, ms, TILING)
+    cs, ps, _ = prepare(sg, boxes, ms, tiling)
     batch = sg.Batch(cs, ps)
     batch.density_pass(False)
     batch.force_pass()
@@ -120,7 +122,7 @@ def test_batch_autotune_and_reload(gpu_lib, tmp_path):
     batch.autotune(path)
     lines = open(path).read().splitlines()
     assert sum(l.startswith("batch_best") for l in lines) == 2
-    assert sum(l.startswith("batch_candidate") for l in lines) == 2 * 2 * 12
+    assert sum(l.startswith("batch_candidate") for l in lines) == 2 * 3 * 2 * 12
     # the tuned tiling gives the same counts and the same sums to rounding
     cs2, ps2, _ = prepare(sg, boxes, ms, {})
     cs2[0].load_tuning(path)

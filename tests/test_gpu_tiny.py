@@ -141,13 +141,15 @@ def test_call_order_and_argument_errors(gpu_lib):
     assert ctx2.info()["n_unconverged"] > 0
 
 
-@pytest.mark.parametrize("nw", [1, 2, 4, 8])
-def test_waves_per_chunk_variants_agree(gpu_lib, nw):
-    """Every loop tiling (waves per chunk, candidate/list capacities) gives
-    the same neighbour counts and the same sums to rounding."""
+@pytest.mark.parametrize("nw,split", [(1, 0), (2, 0), (4, 0), (8, 0), (1, 1), (2, 2), (4, 1), (8, 1)])
+def test_waves_per_chunk_variants_agree(gpu_lib, nw, split):
+    """Every loop tiling (waves per chunk, candidate/list capacities, chunks
+    split into parts of their cell-pair lists) gives the same neighbour
+    counts and the same sums to rounding."""
     ic = ics.tiny_lattice(16, velocity_sigma=0.1)
     _, p0, perm0, _ = run_gpu_step(gpu_lib, ic, 0, ctx_kw=dict(waves_per_chunk=1, cand_cap=2048, list_cap=192))
-    _, p1, perm1, _ = run_gpu_step(gpu_lib, ic, 0, ctx_kw=dict(waves_per_chunk=nw, cand_cap=256, list_cap=64))
+    _, p1, perm1, _ = run_gpu_step(gpu_lib, ic, 0, ctx_kw=dict(waves_per_chunk=nw, cand_cap=256, list_cap=64,
+                                                               chunk_split=split))
     assert np.array_equal(perm0, perm1)
     for k in ("nngb_density", "nngb_force"):
         assert np.array_equal(host(p0, k), host(p1, k)), k
@@ -183,3 +185,31 @@ def test_autotune_keeps_results(gpu_lib, tmp_path):
     assert np.array_equal(host(p3, "nngb_density"), ref["nngb_density"])
     assert np.array_equal(host(p3, "nngb_force"), ref["nngb_force"])
     assert np.max(np.abs(host(p3, "rho") / ref["rho"] - 1)) < 2e-6
+
+
+def test_lazy_axis_sorts_match_full_sorts(gpu_lib):
+    """A deep-bin step whose loop passes sort only the partner leaves they
+    reach gives the same bits as the step after a sort of every leaf."""
+    sg = gpu_lib
+    ic = ics.tiny_lattice(16, velocity_sigma=0.1)
+    ic["bin"] = np.random.default_rng(7).integers(0, 6, size=ic["x"].shape[0]).astype(np.int8)
+    out = []
+    for full in (False, True):
+        p = sg.Particles.from_initial(ic)
+        ctx = sg.Context(split_count=64)
+        ctx.build_cells(p)
+        ctx.sort_cells()
+        ctx.mark_active(p, ctx.params.n_bins - 1)
+        ctx.density_pass(p, True)
+        ctx.force_pass(p)
+        ctx.build_cells(p)
+        ctx.sort_cells()
+        if full:
+            ctx.copy_axis_order()
+        ctx.mark_active(p, 0)
+        ctx.density_pass(p, False)
+        ctx.force_pass(p)
+        ctx.sync()
+        out.append({k: host(p, k).copy() for k in ("h", "rho", "ax", "ay", "az", "vsig", "nngb_density", "nngb_force")})
+    for k in out[0]:
+        assert np.array_equal(out[0][k].view(np.uint8), out[1][k].view(np.uint8)), k
