@@ -71,6 +71,9 @@ typedef struct {
   int chunk_split;     /* loop work items: 0 = one per chunk; 1 / 2 = a chunk's cell-pair
                           list split into parts of about 1024 / 4096 staged partner
                           particles (at most 16), when no tuned entry applies (0) */
+  float rebuild_frac;  /* sph_build_cells keeps the cells of its last full build while no
+                          leaf's particles moved more than this fraction of the leaf's
+                          width since that build (0 = rebuild every call) (0.125) */
 } sph_params;
 
 /* The particle state.  Arrays marked (opt) may be NULL.  build_cells reorders
@@ -110,7 +113,19 @@ void sph_destroy(sph_ctx *ctx);
  * octree leaves and their max H = 1.825742*h, and the FP32 offsets of every
  * particle from its leaf centre.  perm_out (opt, device, n) receives the
  * original index of each sorted position.  Synchronises once (the top-level
- * size depends on the largest H).  SPH_EINVAL if max H > L/4. */
+ * size depends on the largest H).  SPH_EINVAL if max H > L/4.
+ * Rebuild criterion (the paper rebuilds its cells only when particles have
+ * moved too far, Sec. V): when the context's last full build had the same n
+ * and rebuild_frac > 0, the call first tries to keep those cells.  It wraps
+ * the positions and recomputes the offsets from the same leaves (minimum
+ * image), H, each leaf's max H and each leaf's largest displacement since the
+ * full build; the particle order is unchanged (perm_out = identity).  The
+ * cell-pair searches then widen every leaf-pair distance test by both
+ * leaves' displacement bounds, so no pair is missed.  If some leaf's
+ * displacement exceeds rebuild_frac times its width (or max H > L/4), the
+ * full build runs.  The criterion compares positions index by index, so
+ * arrays changed or reordered by the caller are caught as large
+ * displacements.  Synchronises once either way. */
 sph_status sph_build_cells(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *perm_out);
 
 /* Per-cell particle sorts for neighbour pruning (Fig. 5 "sort" task): for
@@ -243,13 +258,17 @@ typedef struct {
   int32_t unconverged_after_pass[32]; /* last density pass: particles still unconverged
                                          after each Newton pass (first 32 passes) */
   int32_t pair_rebuilds;     /* last density pass: cell-pair lists widened mid-solve */
+  int64_t full_builds;       /* cumulative: sph_build_cells calls that rebuilt the cells */
+  int64_t cell_updates;      /* cumulative: calls that kept them (offsets, H_max, drift margins) */
+  float dx_max;              /* largest displacement since the last full build */
 } sph_info_t;
 sph_status sph_info(sph_ctx *ctx, sph_info_t *out); /* synchronises */
 
 /* Leaf table in Morton order: level, integer coordinates at that level,
- * first sorted index, particle count, max H. */
+ * first sorted index, particle count, max H, and (opt) the drift margin of
+ * each leaf (0 right after a full build). */
 sph_status sph_copy_leaves(sph_ctx *ctx, int32_t *level, int32_t *ix, int32_t *iy, int32_t *iz, int32_t *begin,
-                           int32_t *count, float *hmax);
+                           int32_t *count, float *hmax, float *drift);
 /* Sorted Morton keys and FP32 leaf-centre offsets (length n). */
 sph_status sph_copy_particles(sph_ctx *ctx, uint64_t *keys, float *ox, float *oy, float *oz);
 /* 13 x n in-leaf order (axis-major). */

@@ -266,13 +266,14 @@ int64_t emu_mark_active(int64_t n, const int8_t *bin, int m, int64_t n_leaves, c
 }
 
 /* All-pairs cell test.  mode 0: density (R = hmax_act[A]); mode 1: force
- * (R = max(hmax_act[A], leaf_hmax[B])).  Writes up to cap pairs
+ * (R = max(hmax_act[A], leaf_hmax[B])); with leaf_dx (non-NULL) the test
+ * radius is R + leaf_dx[A] + leaf_dx[B] in float, in that order.  Writes up to cap pairs
  * (A, B, sx, sy, sz) in (A, B) order; returns the number of pairs (which may
  * exceed cap, in which case only cap were written). */
 int64_t emu_pairs(int mode, double L, int D, int64_t n_active_leaves, const int64_t *active_leaves,
                   const float *hmax_act, int64_t n_leaves, const int32_t *leaf_level, const int64_t *leaf_ix,
-                  const int64_t *leaf_iy, const int64_t *leaf_iz, const float *leaf_hmax, int64_t cap,
-                  int64_t *pa, int64_t *pb, float *sx, float *sy, float *sz) {
+                  const int64_t *leaf_iy, const int64_t *leaf_iz, const float *leaf_hmax, const float *leaf_dx,
+                  int64_t cap, int64_t *pa, int64_t *pb, float *sx, float *sy, float *sz) {
   int64_t nu = (int64_t)1 << (D + 1);
   double unit = ldexp(L, -(D + 1));
   int64_t np = 0;
@@ -295,6 +296,8 @@ int64_t emu_pairs(int mode, double L, int D, int64_t n_active_leaves, const int6
       }
       float R = hmax_act[k];
       if (mode == 1 && leaf_hmax[B] > R) R = leaf_hmax[B];
+      /* drift margins of both leaves (cells kept from an earlier build) */
+      if (leaf_dx) R = (R + leaf_dx[A]) + leaf_dx[B];
       double Rd = (double)R;
       if (d2 < Rd * Rd) {
         if (np < cap) {
@@ -350,4 +353,53 @@ void emu_counts(int mode, double L, int D, int64_t n, const float *ox, const flo
     }
     counts[t] = c;
   }
+}
+
+/* ---------------- cells kept from an earlier build ---------------- */
+
+/* Offsets of the (wrapped) positions from the centres of the given leaves by
+ * the minimum image, H = fl32(1.825742 h), each leaf's max H and a bound on
+ * the displacement of its particles from the positions xb of the build:
+ * sqrt(3) times the largest displacement component (in double), rounded to
+ * float, then the next float up.  Returns 1 when some leaf's bound exceeds
+ * frac times its width. */
+int emu_update(int64_t n, double *x, double *y, double *z, const float *h, const double *xb, const double *yb,
+               const double *zb, double L, int D, int64_t n_leaves, const int64_t *leaf_begin,
+               const int32_t *leaf_count, const int32_t *leaf_level, const int64_t *leaf_ix, const int64_t *leaf_iy,
+               const int64_t *leaf_iz, float frac, float *ox, float *oy, float *oz, float *H, float *leaf_hmax,
+               float *leaf_dx) {
+  double unit = ldexp(L, -(D + 1));
+  double half = 0.5 * L;
+  int flag = 0;
+  (void)n;
+  for (int64_t l = 0; l < n_leaves; ++l) {
+    int64_t c[3];
+    leaf_centre_units(D, leaf_level[l], leaf_ix[l], leaf_iy[l], leaf_iz[l], c);
+    double cx = (double)c[0] * unit, cy = (double)c[1] * unit, cz = (double)c[2] * unit;
+    float hm = 0.0f;
+    double d2m = 0.0;
+    for (int64_t s = leaf_begin[l]; s < leaf_begin[l] + leaf_count[l]; ++s) {
+      double p[3] = {emu_wrap(x[s], L), emu_wrap(y[s], L), emu_wrap(z[s], L)};
+      x[s] = p[0];
+      y[s] = p[1];
+      z[s] = p[2];
+      double o[3] = {p[0] - cx, p[1] - cy, p[2] - cz};
+      double d[3] = {p[0] - xb[s], p[1] - yb[s], p[2] - zb[s]};
+      for (int a = 0; a < 3; ++a) {
+        if (o[a] > half) o[a] -= L; else if (o[a] < -half) o[a] += L;
+        if (d[a] > half) d[a] -= L; else if (d[a] < -half) d[a] += L;
+      }
+      for (int a = 0; a < 3; ++a)
+        if (fabs(d[a]) > d2m) d2m = fabs(d[a]);
+      ox[s] = (float)o[0];
+      oy[s] = (float)o[1];
+      oz[s] = (float)o[2];
+      H[s] = 1.825742f * h[s];
+      if (H[s] > hm) hm = H[s];
+    }
+    leaf_hmax[l] = hm;
+    leaf_dx[l] = d2m > 0.0 ? nextafterf((float)(d2m * 1.7320508075688772), INFINITY) : 0.0f;
+    if ((double)leaf_dx[l] > (double)frac * ldexp(L, -leaf_level[l])) flag = 1;
+  }
+  return flag;
 }

@@ -116,9 +116,10 @@ def leaf_hmax(cells, H):
     return out
 
 
-def pairs(cells, act, mode, leaf_hmax_arr=None):
-    """All-pairs cell test (mode 'density' or 'force').  Returns (A, B, s) with
-    s (P,3) float32 shifts, in (A, B) order."""
+def pairs(cells, act, mode, leaf_hmax_arr=None, leaf_dx=None):
+    """All-pairs cell test (mode 'density' or 'force'), widened by the leaves'
+    drift margins when leaf_dx is given.  Returns (A, B, s) with s (P,3)
+    float32 shifts, in (A, B) order."""
     md = {"density": 0, "force": 1}[mode]
     lh = cells["leaf_hmax"] if leaf_hmax_arr is None else np.ascontiguousarray(leaf_hmax_arr, np.float32)
     f = lib().emu_pairs
@@ -131,7 +132,8 @@ def pairs(cells, act, mode, leaf_hmax_arr=None):
         np_ = f(C.c_int(md), C.c_double(cells["L"]), C.c_int(cells["D"]),
                 C.c_int64(len(act["active_leaves"])), _p(act["active_leaves"]), _p(act["hmax_act"]),
                 C.c_int64(cells["n_leaves"]), _p(cells["leaf_level"]), _p(cells["leaf_ix"]),
-                _p(cells["leaf_iy"]), _p(cells["leaf_iz"]), _p(lh), C.c_int64(cap),
+                _p(cells["leaf_iy"]), _p(cells["leaf_iz"]), _p(lh),
+                None if leaf_dx is None else _p(np.ascontiguousarray(leaf_dx, np.float32)), C.c_int64(cap),
                 _p(pa), _p(pb), _p(s[0]), _p(s[1]), _p(s[2]))
         if np_ <= cap:
             return pa[:np_].copy(), pb[:np_].copy(), s[:, :np_].T.copy()
@@ -149,3 +151,29 @@ def counts(cells, mode, samples, H=None):
                      _p(cells["leaf_level"]), _p(cells["leaf_ix"]), _p(cells["leaf_iy"]), _p(cells["leaf_iz"]),
                      C.c_int64(samples.size), _p(samples), _p(out))
     return out
+
+
+def update(cells, x_sorted, h_sorted, x_build, frac=0.125):
+    """The cells of `cells` kept for new positions (sorted order): wrapped
+    positions, offsets by the minimum image, H, leaf max H, leaf drift
+    margins and the rebuild flag, as the C definitions compute them."""
+    x = np.ascontiguousarray(x_sorted, np.float64).copy()
+    xs, ys, zs = (np.ascontiguousarray(x[:, a]) for a in range(3))
+    xb = np.ascontiguousarray(x_build, np.float64)
+    xbs, ybs, zbs = (np.ascontiguousarray(xb[:, a]) for a in range(3))
+    h = np.ascontiguousarray(h_sorted, np.float32)
+    n = x.shape[0]
+    nl = cells["n_leaves"]
+    out = dict(ox=np.empty(n, np.float32), oy=np.empty(n, np.float32), oz=np.empty(n, np.float32),
+               H=np.empty(n, np.float32), leaf_hmax=np.empty(nl, np.float32), leaf_dx=np.empty(nl, np.float32))
+    f = lib().emu_update
+    f.restype = C.c_int
+    flag = f(C.c_int64(n), _p(xs), _p(ys), _p(zs), _p(h), _p(xbs), _p(ybs), _p(zbs), C.c_double(cells["L"]),
+             C.c_int(cells["D"]), C.c_int64(nl), _p(cells["leaf_begin"]), _p(cells["leaf_count"]),
+             _p(cells["leaf_level"]), _p(cells["leaf_ix"]), _p(cells["leaf_iy"]), _p(cells["leaf_iz"]),
+             C.c_float(frac), _p(out["ox"]), _p(out["oy"]), _p(out["oz"]), _p(out["H"]), _p(out["leaf_hmax"]),
+             _p(out["leaf_dx"]))
+    new = dict(cells)
+    new.update(out)
+    new["xw"], new["yw"], new["zw"] = xs, ys, zs
+    return new, bool(flag)

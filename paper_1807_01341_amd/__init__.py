@@ -34,7 +34,7 @@ class Params(C.Structure):
                 ("eta", C.c_float), ("alpha", C.c_float), ("balsara_eps", C.c_float), ("h_tol", C.c_float),
                 ("n_bins", C.c_int), ("split_count", C.c_int), ("morton_depth", C.c_int), ("top_cap", C.c_int),
                 ("h_max_iter", C.c_int), ("compensated", C.c_int), ("cand_cap", C.c_int), ("list_cap", C.c_int),
-                ("waves_per_chunk", C.c_int), ("chunk_split", C.c_int)]
+                ("waves_per_chunk", C.c_int), ("chunk_split", C.c_int), ("rebuild_frac", C.c_float)]
 
 
 # field name, dtype, role
@@ -62,7 +62,8 @@ class Info(C.Structure):
                 ("n_active", C.c_int64), ("n_active_leaves", C.c_int64), ("n_density_pairs", C.c_int64),
                 ("n_force_pairs", C.c_int64), ("density_iterations", C.c_int32), ("n_unconverged", C.c_int64),
                 ("interactions_density", C.c_int64), ("interactions_force", C.c_int64),
-                ("unconverged_after_pass", C.c_int32 * 32), ("pair_rebuilds", C.c_int32)]
+                ("unconverged_after_pass", C.c_int32 * 32), ("pair_rebuilds", C.c_int32),
+                ("full_builds", C.c_int64), ("cell_updates", C.c_int64), ("dx_max", C.c_float)]
 
 
 _lib = None
@@ -89,7 +90,7 @@ def lib():
             "sph_sync": (i32, [vp]),
             "sph_last_error": (C.c_char_p, [vp]),
             "sph_info": (i32, [vp, vp]),
-            "sph_copy_leaves": (i32, [vp] * 8),
+            "sph_copy_leaves": (i32, [vp] * 9),
             "sph_copy_particles": (i32, [vp] * 5),
             "sph_copy_axis_order": (i32, [vp, vp]),
             "sph_copy_active": (i32, [vp] * 4),
@@ -318,8 +319,9 @@ class Context:
         out = {k: torch.empty(nl, dtype=torch.int32, device=dev)
                for k in ("level", "ix", "iy", "iz", "begin", "count")}
         out["hmax"] = torch.empty(nl, dtype=torch.float32, device=dev)
+        out["drift"] = torch.empty(nl, dtype=torch.float32, device=dev)
         self._check(lib().sph_copy_leaves(self.h, *[_ptr(out[k]) for k in
-                                                    ("level", "ix", "iy", "iz", "begin", "count", "hmax")]))
+                                                    ("level", "ix", "iy", "iz", "begin", "count", "hmax", "drift")]))
         return out
 
     def copy_particles(self):

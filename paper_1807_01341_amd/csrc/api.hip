@@ -101,6 +101,7 @@ void sph_default_params(sph_params *p) {
   p->compensated = 1;
   p->cand_cap = 512;
   p->list_cap = 96;
+  p->rebuild_frac = 0.125f;
 }
 
 sph_status sph_create(const sph_params *p, void *hip_stream, sph_ctx **out) {
@@ -109,6 +110,7 @@ sph_status sph_create(const sph_params *p, void *hip_stream, sph_ctx **out) {
   if (!(p->box > 0) || p->morton_depth < 2 || p->morton_depth > 21 || p->split_count < 2 || p->top_cap < 2 ||
       p->top_cap > 8 || p->n_bins < 1 || p->n_bins > 63 || p->h_max_iter < 1 || !(p->eta > 0) ||
       !(p->gamma > 1.0) || p->cand_cap < 64 || p->list_cap < 64 || p->chunk_split < 0 || p->chunk_split > 2 ||
+      !(p->rebuild_frac >= 0.f && p->rebuild_frac <= 1.f) ||
       !(p->waves_per_chunk == 0 || p->waves_per_chunk == 1 || p->waves_per_chunk == 2 || p->waves_per_chunk == 4 ||
         p->waves_per_chunk == 8))
     return SPH_EINVAL;
@@ -241,6 +243,9 @@ sph_status sph_info(sph_ctx *ctx, sph_info_t *out) {
   out->interactions_force = (int64_t)c[1];
   for (int q = 0; q < 32; ++q) out->unconverged_after_pass[q] = ctx->unconv_hist[q];
   out->pair_rebuilds = ctx->pair_rebuilds;
+  out->full_builds = ctx->n_full_builds;
+  out->cell_updates = ctx->n_updates;
+  out->dx_max = ctx->dx_max;
   return SPH_OK;
 }
 
@@ -252,7 +257,7 @@ static sph_status copy_dev(sph_ctx *ctx, void *dst, const DevBuf &src, size_t by
 }
 
 sph_status sph_copy_leaves(sph_ctx *ctx, int32_t *level, int32_t *ix, int32_t *iy, int32_t *iz, int32_t *begin,
-                           int32_t *count, float *hmax) {
+                           int32_t *count, float *hmax, float *drift) {
   SPH_TRY(need_state(ctx, 1, "copy_leaves"));
   const size_t nl = (size_t)ctx->n_leaves;
   SPH_TRY(copy_dev(ctx, level, ctx->leaf_level, 4 * nl));
@@ -262,6 +267,7 @@ sph_status sph_copy_leaves(sph_ctx *ctx, int32_t *level, int32_t *ix, int32_t *i
   SPH_TRY(copy_dev(ctx, begin, ctx->leaf_begin, 4 * nl));
   SPH_TRY(copy_dev(ctx, count, ctx->leaf_count, 4 * nl));
   SPH_TRY(copy_dev(ctx, hmax, ctx->leaf_hmax, 4 * nl));
+  if (drift) SPH_TRY(copy_dev(ctx, drift, ctx->leaf_dx, 4 * nl));
   return SPH_OK;
 }
 

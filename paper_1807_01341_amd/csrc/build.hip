@@ -240,6 +240,84 @@ __global__ __launch_bounds__(BT) void offsets_kernel(const double *__restrict__ 
   if (lane == 0) leaf_hmax[l] = hm;
 }
 
+// Cell update without a rebuild (the leaves of the last build kept): wraps
+// the positions, the FP32 offsets from the leaf centre (minimum image), H,
+// the leaf's max H and a bound on its particles' displacement since the last
+// build (sqrt(3) times the largest component, rounded up to float),
+// and flags a rebuild when a leaf's particles moved more than frac of its
+// width.  One wave per leaf; block maxima of H and of the displacement.
+__global__ __launch_bounds__(BT) void update_kernel(double *__restrict__ x, double *__restrict__ y,
+                                                    double *__restrict__ z, const float *__restrict__ h,
+                                                    const double *__restrict__ xb, const double *__restrict__ yb,
+                                                    const double *__restrict__ zb, const int32_t *__restrict__ begin,
+                                                    const int32_t *__restrict__ count,
+                                                    const int32_t *__restrict__ level, const int32_t *__restrict__ ix,
+                                                    const int32_t *__restrict__ iy, const int32_t *__restrict__ iz,
+                                                    int64_t nl, int D, double L, double unit, float frac,
+                                                    float4 *__restrict__ pos4, float *__restrict__ leaf_hmax,
+                                                    float *__restrict__ leaf_dx, int32_t *__restrict__ sc_hmax,
+                                                    int32_t *__restrict__ sc_dx, int32_t *__restrict__ sc_flag) {
+  const int64_t l = (int64_t)blockIdx.x * (BT / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  float hm = 0.f, dm = 0.f;
+  if (l < nl) {
+    const int sh = D - level[l];
+    const double cx = (double)((2 * (int64_t)ix[l] + 1) << sh) * unit;
+    const double cy = (double)((2 * (int64_t)iy[l] + 1) << sh) * unit;
+    const double cz = (double)((2 * (int64_t)iz[l] + 1) << sh) * unit;
+    const double half = 0.5 * L;
+    const int b = begin[l], cnt = count[l];
+    double d2m = 0.0;  // largest displacement component
+    for (int k = lane; k < cnt; k += 64) {
+      const int s = b + k;
+      const double xw = wrap_box(x[s], L), yw = wrap_box(y[s], L), zw = wrap_box(z[s], L);
+      x[s] = xw;
+      y[s] = yw;
+      z[s] = zw;
+      double ox = xw - cx, oy = yw - cy, oz = zw - cz;
+      ox = ox > half ? ox - L : (ox < -half ? ox + L : ox);
+      oy = oy > half ? oy - L : (oy < -half ? oy + L : oy);
+      oz = oz > half ? oz - L : (oz < -half ? oz + L : oz);
+      double dx = xw - xb[s], dy = yw - yb[s], dz = zw - zb[s];
+      dx = dx > half ? dx - L : (dx < -half ? dx + L : dx);
+      dy = dy > half ? dy - L : (dy < -half ? dy + L : dy);
+      dz = dz > half ? dz - L : (dz < -half ? dz + L : dz);
+      d2m = fmax(d2m, fmax(fabs(dx), fmax(fabs(dy), fabs(dz))));
+      const float H = GK32 * h[s];
+      pos4[s] = make_float4((float)ox, (float)oy, (float)oz, H);
+      hm = fmaxf(hm, H);
+    }
+    for (int o = 32; o > 0; o >>= 1) d2m = fmax(d2m, __shfl_xor(d2m, o, 64));
+    hm = wave_max_f(hm);
+    // |displacement| <= sqrt(3) * (largest component), rounded up to float
+    dm = d2m > 0.0 ? __int_as_float(__float_as_int((float)(d2m * 1.7320508075688772)) + 1) : 0.f;
+    if (lane == 0) {
+      leaf_hmax[l] = hm;
+      leaf_dx[l] = dm;
+      if ((double)dm > (double)frac * ldexp(L, -level[l])) atomicOr(sc_flag, 1);
+    }
+  }
+  __shared__ float wh[BT / 64], wd[BT / 64];
+  if (lane == 0) {
+    wh[threadIdx.x >> 6] = hm;
+    wd[threadIdx.x >> 6] = dm;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float a = wh[0], d = wd[0];
+    for (int w = 1; w < BT / 64; ++w) {
+      a = fmaxf(a, wh[w]);
+      d = fmaxf(d, wd[w]);
+    }
+    if (a > 0.f) atomicMax(sc_hmax, __float_as_int(a));
+    if (d > 0.f) atomicMax(sc_dx, __float_as_int(d));
+  }
+}
+
+__global__ __launch_bounds__(BT) void iota_kernel(int64_t *__restrict__ out, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x; i < n; i += (int64_t)gridDim.x * BT) out[i] = i;
+}
+
 // Leaf range of every top-level cell (leaves of one top cell are contiguous).
 __global__ __launch_bounds__(BT) void top_map_kernel(const int32_t *__restrict__ level, const int32_t *__restrict__ ix,
                                                      const int32_t *__restrict__ iy, const int32_t *__restrict__ iz,
@@ -276,6 +354,13 @@ sph_status build_cells_impl(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *
   if (!p->x || !p->y || !p->z || !p->h) return sph_fail(ctx, SPH_EINVAL, "build_cells: x, y, z and h are required");
   const int D = ctx->prm.morton_depth;
   const double L = ctx->prm.box;
+  if (ctx->prm.rebuild_frac > 0.f && ctx->built_n == n && ctx->n_leaves > 0) {
+    // keep the cells of the last build while every leaf's particles stay
+    // within rebuild_frac of its width of where that build saw them
+    int rebuild = 0;
+    SPH_TRY(update_cells(ctx, p, perm_out, &rebuild));
+    if (!rebuild) return SPH_OK;
+  }
   ctx->n = n;
   ctx->state = 0;
   SPH_TRY(sph_ensure(ctx, ctx->keys_a, 8 * n));
@@ -420,6 +505,60 @@ sph_status build_cells_impl(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *
                                                         (int32_t *)ctx->top_last.p);
   }
   HIP_TRY(ctx, hipGetLastError());
+  // positions the cells were built from (for the update criterion); no drift margin yet
+  SPH_TRY(sph_ensure(ctx, ctx->x_build, 24 * (size_t)n));
+  SPH_TRY(sph_ensure(ctx, ctx->leaf_dx, 4 * (size_t)(nl > 0 ? nl : 1)));
+  {
+    double *xb = (double *)ctx->x_build.p;
+    HIP_TRY(ctx, hipMemcpyAsync(xb, p->x, 8 * n, hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(xb + n, p->y, 8 * n, hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(xb + 2 * n, p->z, 8 * n, hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemsetAsync(ctx->leaf_dx.p, 0, 4 * (size_t)nl, ctx->stream));
+  }
+  ctx->dx_max = 0.f;
+  ctx->built_n = n;
+  ctx->n_full_builds++;
+  SPH_TRY(pack_neighbour_data(ctx, p));
+  ctx->state = 1;
+  return SPH_OK;
+}
+
+// The update path of sph_build_cells (see there): one launch over the leaves
+// and one synchronisation; *rebuild = 1 when the full build must run.
+sph_status update_cells(sph_ctx *ctx, sph_particles *p, int64_t *perm_out, int *rebuild) {
+  const int64_t n = ctx->n, nl = ctx->n_leaves;
+  const int D = ctx->prm.morton_depth;
+  const double L = ctx->prm.box;
+  int32_t *sc = (int32_t *)ctx->scalars.p;
+  HIP_TRY(ctx, hipMemsetAsync(sc + SC_UPD_HMAX, 0, 3 * sizeof(int32_t), ctx->stream));
+  const double *xb = (const double *)ctx->x_build.p;
+  {
+    PROF(ctx, "cell_update");
+    update_kernel<<<(unsigned)ceil_div(nl, BT / 64), BT, 0, ctx->stream>>>(
+        p->x, p->y, p->z, p->h, xb, xb + n, xb + 2 * n, (const int32_t *)ctx->leaf_begin.p,
+        (const int32_t *)ctx->leaf_count.p, (const int32_t *)ctx->leaf_level.p, (const int32_t *)ctx->leaf_ix.p,
+        (const int32_t *)ctx->leaf_iy.p, (const int32_t *)ctx->leaf_iz.p, nl, D, L, ldexp(L, -(D + 1)),
+        ctx->prm.rebuild_frac, (float4 *)ctx->pos4.p, (float *)ctx->leaf_hmax.p, (float *)ctx->leaf_dx.p,
+        sc + SC_UPD_HMAX, sc + SC_UPD_DX, sc + SC_UPD_FLAG);
+  }
+  HIP_TRY(ctx, hipGetLastError());
+  int32_t st[3];
+  SPH_TRY(read_scalars(ctx, SC_UPD_HMAX, 3, st));
+  float hmax, dxm;
+  memcpy(&hmax, &st[0], 4);
+  memcpy(&dxm, &st[1], 4);
+  if (st[2] || L * 0.25 < (double)hmax) {
+    *rebuild = 1;
+    return SPH_OK;
+  }
+  *rebuild = 0;
+  ctx->hmax_global = hmax;
+  ctx->dx_max = dxm;
+  ctx->n_updates++;
+  if (perm_out) {
+    iota_kernel<<<grid_for(n), BT, 0, ctx->stream>>>(perm_out, n);
+    HIP_TRY(ctx, hipGetLastError());
+  }
   SPH_TRY(pack_neighbour_data(ctx, p));
   ctx->state = 1;
   return SPH_OK;

@@ -119,6 +119,7 @@ __global__ __launch_bounds__(MT) void pairs_kernel(int mode, float slack, PairGe
                                                    const float *__restrict__ leaf_hmax,
                                                    const int32_t *__restrict__ top_first,
                                                    const int32_t *__restrict__ top_last, float hmax_global,
+                                                   const float *__restrict__ leaf_dx, float dx_max,
                                                    int32_t *__restrict__ counts, const int32_t *__restrict__ offs,
                                                    PairEntry *__restrict__ out, const int32_t *__restrict__ leaf_count,
                                                    int32_t *__restrict__ act_cost) {
@@ -131,7 +132,10 @@ __global__ __launch_bounds__(MT) void pairs_kernel(int mode, float slack, PairGe
   int64_t ca[3];
   leaf_centre_units(g.D, lvA, ix[A], iy[A], iz[A], ca);
   const int64_t hwa = (int64_t)1 << (g.D - lvA);
-  const float Rreach = mode == 0 ? RA : fmaxf(RA, hmax_global);
+  // particles may have drifted out of their leaves since the cells were
+  // built: leaf_dx widens every test by both leaves' displacement bounds
+  const float dxA = leaf_dx[A];
+  const float Rreach = (mode == 0 ? RA : fmaxf(RA, hmax_global)) + dxA + dx_max;
   const int ntop = 1 << g.k0;
   const double rr = ceil((double)Rreach / g.wtop);
   const int ring = (rr >= 0.0 && rr < (double)ntop) ? (int)rr : ntop;  // non-finite reach: every top cell
@@ -180,6 +184,7 @@ __global__ __launch_bounds__(MT) void pairs_kernel(int mode, float slack, PairGe
             }
             float R = RA;
             if (mode == 1) R = fmaxf(R, leaf_hmax[B]);
+            R = (R + dxA) + leaf_dx[B];
             const double Rd = (double)R;
             ok = d2 < Rd * Rd;
           }
@@ -272,8 +277,8 @@ sph_status build_pairs_count(sph_ctx *ctx, int which, float slack, int32_t *host
         which, slack, g, na, (const int32_t *)ctx->act_leaves.p, (const float *)ctx->act_hmax.p,
         (const int32_t *)ctx->leaf_level.p, (const int32_t *)ctx->leaf_ix.p, (const int32_t *)ctx->leaf_iy.p,
         (const int32_t *)ctx->leaf_iz.p, (const float *)ctx->leaf_hmax.p, (const int32_t *)ctx->top_first.p,
-        (const int32_t *)ctx->top_last.p, ctx->hmax_global, (int32_t *)ctx->pair_cnt.p, nullptr, nullptr, nullptr,
-        nullptr);
+        (const int32_t *)ctx->top_last.p, ctx->hmax_global, (const float *)ctx->leaf_dx.p, ctx->dx_max,
+        (int32_t *)ctx->pair_cnt.p, nullptr, nullptr, nullptr, nullptr);
   }
   HIP_TRY(ctx, hipGetLastError());
   int32_t *o = (int32_t *)off.p;
@@ -297,8 +302,9 @@ sph_status build_pairs_fill(sph_ctx *ctx, int which, float slack, int32_t np) {
         which, slack, g, na, (const int32_t *)ctx->act_leaves.p, (const float *)ctx->act_hmax.p,
         (const int32_t *)ctx->leaf_level.p, (const int32_t *)ctx->leaf_ix.p, (const int32_t *)ctx->leaf_iy.p,
         (const int32_t *)ctx->leaf_iz.p, (const float *)ctx->leaf_hmax.p, (const int32_t *)ctx->top_first.p,
-        (const int32_t *)ctx->top_last.p, ctx->hmax_global, nullptr, (int32_t *)off.p, (PairEntry *)lst.p,
-        (const int32_t *)ctx->leaf_count.p, which == 0 ? (int32_t *)ctx->act_cost.p : nullptr);
+        (const int32_t *)ctx->top_last.p, ctx->hmax_global, (const float *)ctx->leaf_dx.p, ctx->dx_max, nullptr,
+        (int32_t *)off.p, (PairEntry *)lst.p, (const int32_t *)ctx->leaf_count.p,
+        which == 0 ? (int32_t *)ctx->act_cost.p : nullptr);
   }
   HIP_TRY(ctx, hipGetLastError());
   return SPH_OK;

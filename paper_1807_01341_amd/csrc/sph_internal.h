@@ -63,6 +63,12 @@ struct sph_ctx {
   int32_t pair_rebuilds = 0;
   float dpair_slack = 1.f;  // reach factor of the current density pair lists
   float hmax_global = 0.f;  // max H over all particles (monotone between builds)
+  // cells kept between builds: positions of the last full build, per-leaf and
+  // largest displacement since then (the cell-pair search margin)
+  DevBuf x_build, leaf_dx;
+  float dx_max = 0.f;
+  int64_t built_n = 0;
+  int64_t n_full_builds = 0, n_updates = 0;
 
   // build
   DevBuf keys_a, keys_b, vals_a, vals_b, radix_counts, scan_tmp, gather_tmp;
@@ -162,6 +168,9 @@ enum ScalarSlot {
   SC_PAIRTOT = 10,
   SC_MAXLEAF = 11,
   SC_WORKCTR = 12,
+  SC_UPD_HMAX = 13,   // cell update: max H bits, max displacement bits, rebuild flag
+  SC_UPD_DX = 14,
+  SC_UPD_FLAG = 15,
   SC_COUNT = 32
 };
 
@@ -175,6 +184,7 @@ sph_status read_scalars(sph_ctx *ctx, int first, int count, int32_t *host);
 
 // ---------------------------------------------------------------- stages
 sph_status build_cells_impl(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *perm_out);
+sph_status update_cells(sph_ctx *ctx, sph_particles *p, int64_t *perm_out, int *rebuild);
 sph_status sort_cells_impl(sph_ctx *ctx);
 sph_status mark_active_impl(sph_ctx *ctx, const sph_particles *p, int m, int64_t *n_active_host);
 sph_status build_pairs(sph_ctx *ctx, int which, float slack);

@@ -134,6 +134,63 @@ def test_active_mask_and_pairs_cover_all_neighbours(clustered_small):
             assert np.array_equal(sv.astype(np.float64), dd)
 
 
+def test_cell_update_without_motion_reproduces_the_build(clustered_small):
+    c, cl = clustered_small
+    xs = np.stack([cl["xw"], cl["yw"], cl["zw"]], 1)
+    hs = c["h"][cl["perm"]]
+    up, flag = cells.update(cl, xs, hs, xs)
+    assert not flag
+    for k in ("ox", "oy", "oz", "H", "leaf_hmax"):
+        assert np.array_equal(up[k].view(np.uint32), cl[k].view(np.uint32)), k
+    assert np.all(up["leaf_dx"] == 0)
+
+
+def test_cell_update_margins_cover_every_neighbour_pair(clustered_small):
+    """Particles moved after the build, cells kept: the drift margins make the
+    cell pairs cover every FP64 neighbour pair at the new positions, and a
+    large move asks for a rebuild."""
+    c, cl = clustered_small
+    xs = np.stack([cl["xw"], cl["yw"], cl["zw"]], 1)
+    hs = c["h"][cl["perm"]]
+    rng = np.random.default_rng(21)
+    width = 0.5 ** cl["leaf_level"][cl["leaf_of"]]
+    step = (0.1 * width)[:, None] * rng.uniform(-1, 1, size=xs.shape) / math.sqrt(3)
+    moved = xs + step
+    up, flag = cells.update(cl, moved, hs, xs)
+    assert not flag
+    assert np.all(up["leaf_dx"] > 0)
+    x = np.stack([up["xw"], up["yw"], up["zw"]], 1)
+    assert np.all((x >= 0) & (x < 1))
+    # offsets are the minimum-image differences to the (unchanged) leaf centres
+    lf = cl["leaf_of"]
+    cen = (np.stack([cl["leaf_ix"][lf], cl["leaf_iy"][lf], cl["leaf_iz"][lf]], 1) + 0.5) * \
+        (0.5 ** cl["leaf_level"][lf])[:, None]
+    d = x - cen
+    d -= np.round(d)
+    assert np.array_equal(up["ox"], d[:, 0].astype(np.float32))
+    binsorted = c["bin"][cl["perm"]]
+    act = cells.mark_active(up, binsorted, ics.deep_bin_for_fraction(c["bin"], 0.05), H=up["H"])
+    H = up["H"].astype(np.float64)
+    from scipy.spatial import cKDTree
+    tree = cKDTree(x, boxsize=1.0)
+    ia = np.nonzero(act["active"])[0]
+    for mode in ("density", "force"):
+        pa, pb, _ = cells.pairs(up, act, mode, leaf_dx=up["leaf_dx"])
+        got = set(zip(pa.tolist(), pb.tolist()))
+        p0, _, _ = cells.pairs(up, act, mode)
+        assert len(pa) >= len(p0)
+        rad = H[ia] if mode == "density" else np.full(ia.size, H.max())
+        for i, js in zip(ia, tree.query_ball_point(x[ia], rad)):
+            for j in js:
+                e = x[i] - x[j]
+                e -= np.round(e)
+                r = math.sqrt(float(e @ e))
+                if (r < H[i]) if mode == "density" else (r < H[i] or r < H[j]):
+                    assert (lf[i], lf[j]) in got
+    _, flag = cells.update(cl, xs + 3 * step, hs, xs)
+    assert flag
+
+
 def test_fp32_counts_agree_with_fp64_neighbour_sets():
     c = ics.tiny_lattice(16)
     out = sph.solve_density(c["x"], c["v"], c["m"], c["h"], 1.0)

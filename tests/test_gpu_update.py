@@ -1,0 +1,102 @@
+"""GPU parity of the cell update (cells kept between builds while particles
+stay near them): structures bit-exact against the C definitions of the
+update, and the physics against the FP64 oracle at the moved positions."""
+import numpy as np
+import pytest
+import torch
+
+import ics
+from oracle import cells as emu
+from oracle import sph
+from tests.gpu_cases import A_TOL, RHO_TOL, host, pair_set
+
+pytestmark = pytest.mark.gpu
+
+
+def test_cell_update_matches_definitions_and_oracle(gpu_lib):
+    sg = gpu_lib
+    ic = ics.tiny_lattice(16, velocity_sigma=0.3)
+    print("case update tiny16 sigma=0.3", flush=True)
+    p = sg.Particles.from_initial(ic)
+    ctx = sg.Context(split_count=64)
+    perm = torch.empty(p.n, dtype=torch.int64, device="cuda")
+    ctx.build_cells(p, perm)
+    perm = perm.cpu().numpy()
+    cl = emu.build_cells(ic["x"], ic["h"], split=64, D=16)
+    assert np.array_equal(perm, cl["perm"])
+    x_build = np.stack([host(p, k) for k in "xyz"], 1)
+    ctx.sort_cells()
+    ctx.mark_active(p, ctx.params.n_bins - 1)
+    ctx.density_pass(p, True)
+    ctx.force_pass(p)
+    # move every particle by a few per cent of a leaf (drift of the given step)
+    ctx.kick_drift(p, 0, 2e-3, 1, True)
+    ctx.sync()
+    x_moved = np.stack([host(p, k) for k in "xyz"], 1)
+    h_now = host(p, "h").copy()
+    assert np.max(np.abs(x_moved - x_build)) > 0
+    perm2 = torch.empty(p.n, dtype=torch.int64, device="cuda")
+    ctx.build_cells(p, perm2)
+    inf = ctx.info()
+    assert inf["full_builds"] == 1 and inf["cell_updates"] == 1 and inf["dx_max"] > 0
+    assert np.array_equal(perm2.cpu().numpy(), np.arange(p.n))
+    up, flag = emu.update(cl, x_moved, h_now, x_build)
+    assert not flag
+    # positions wrapped in place, offsets, leaf max H and drift margins bit for bit
+    assert np.array_equal(np.stack([host(p, k) for k in "xyz"], 1), np.stack([up["xw"], up["yw"], up["zw"]], 1))
+    keys, o = ctx.copy_particles()
+    for d, k in enumerate(("ox", "oy", "oz")):
+        assert np.array_equal(o[d].cpu().numpy().view(np.uint32), up[k].view(np.uint32)), k
+    lv = {k: v.cpu().numpy() for k, v in ctx.copy_leaves().items()}
+    assert np.array_equal(lv["begin"], cl["leaf_begin"]) and np.array_equal(lv["count"], cl["leaf_count"])
+    assert np.array_equal(lv["hmax"].view(np.uint32), up["leaf_hmax"].view(np.uint32))
+    assert np.array_equal(lv["drift"].view(np.uint32), up["leaf_dx"].view(np.uint32))
+    # the step on the kept cells: pair sets with the margins, counts, physics
+    ctx.sort_cells()
+    ctx.mark_active(p, ctx.params.n_bins - 1)
+    act = emu.mark_active(up, host(p, "time_bin"), ctx.params.n_bins - 1, H=up["H"])
+    a, b, s = ctx.copy_pairs(0)
+    ea, eb, es = emu.pairs(up, act, "density", leaf_dx=up["leaf_dx"])
+    assert pair_set(a.cpu().numpy(), b.cpu().numpy(), s.cpu().numpy()) == pair_set(ea, eb, es)
+    ctx.density_pass(p, True)
+    ctx.force_pass(p)
+    ctx.sync()
+    H = (np.float32(1.825742) * host(p, "h")).astype(np.float32)
+    idx = np.arange(0, p.n, 7)
+    assert np.array_equal(host(p, "nngb_density")[idx], emu.counts(up, "density", idx, H=H))
+    assert np.array_equal(host(p, "nngb_force")[idx], emu.counts(up, "force", idx, H=H))
+    lh = emu.leaf_hmax(up, H)
+    a, b, s = ctx.copy_pairs(1)
+    ea, eb, es = emu.pairs(up, act, "force", leaf_hmax_arr=lh, leaf_dx=up["leaf_dx"])
+    assert pair_set(a.cpu().numpy(), b.cpu().numpy(), s.cpu().numpy()) == pair_set(ea, eb, es)
+    # physics at the moved positions, in cell order
+    xs = np.stack([up["xw"], up["yw"], up["zw"]], 1)
+    v = np.stack([host(p, k) for k in ("vx", "vy", "vz")], 1)
+    u = host(p, "u").astype(np.float64)
+    out = sph.density_and_ghost(xs, v, host(p, "m"), h_now, 1.0, u=u)
+    fo = sph.force(xs, v, host(p, "m"), out["h"], out["rho"], out["f"], out["P"], out["c"], out["B"], 1.0)
+    rho_err = np.max(np.abs(host(p, "rho") / out["rho"].numpy() - 1))
+    a_g = np.stack([host(p, k) for k in ("ax", "ay", "az")], 1).astype(np.float64)
+    a_r = fo["a"].numpy()
+    den = np.maximum(np.linalg.norm(a_r, axis=1), 1e-2 * fo["scale"].numpy())
+    a_err = np.max(np.linalg.norm(a_g - a_r, axis=1) / den)
+    print(f"rho {rho_err:.2e} a {a_err:.2e}", flush=True)
+    assert rho_err < RHO_TOL and a_err < A_TOL
+
+
+def test_large_move_rebuilds(gpu_lib):
+    sg = gpu_lib
+    ic = ics.tiny_lattice(16, velocity_sigma=0.1)
+    p = sg.Particles.from_initial(ic)
+    ctx = sg.Context()
+    ctx.build_cells(p)
+    shift = torch.full_like(p["x"], 0.05)
+    p["x"].add_(shift)
+    ctx.build_cells(p)
+    inf = ctx.info()
+    assert inf["full_builds"] == 2 and inf["cell_updates"] == 0
+    ctx0 = sg.Context(rebuild_frac=0.0)
+    p0 = sg.Particles.from_initial(ic)
+    ctx0.build_cells(p0)
+    ctx0.build_cells(p0)
+    assert ctx0.info()["full_builds"] == 2
