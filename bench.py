@@ -6,8 +6,9 @@ uniform background, 10 % in 20 Plummer spheres, u log-uniform, 14 model
 time-bins), at the deep bin m whose active set {bin <= m} is closest to 1 %
 of the particles.  The step's input is the state one deep-bin drift after an
 all-active density + force pass (positions moved, h predicted); every timed
-step starts from that input (one fused device copy, inside the timed region)
-and runs the whole path on it, so all steps do the same work.
+step starts from that input (a fused device copy of the arrays a step
+changes, inside the timed region) and runs the whole path on it, so all
+steps do the same work.
 
 Prints one JSON line: interactions/s (density + force, in-support pairs only,
 counted by the kernels) over the whole step, the fraction of FP32 vector peak,
@@ -370,6 +371,7 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=None)
     ap.add_argument("--h-tol", type=float, default=None)
     ap.add_argument("--nw", type=int, default=None)
+    ap.add_argument("--sweep-below", type=int, default=None)
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--load-tune", default=None, help="load a tuning file instead of tuning")
     ap.add_argument("--tune-file", default=os.path.join(ROOT, "gpurun_out", "tuning_clustered.txt"))
@@ -420,6 +422,8 @@ def main():
         kw["h_tol"] = args.h_tol
     if args.nw:
         kw["waves_per_chunk"] = args.nw
+    if args.sweep_below is not None:
+        kw["sweep_below"] = args.sweep_below
     ctx = sg.Context(**kw)
     p = sg.Particles.from_initial(ic)
 
@@ -438,7 +442,11 @@ def main():
     ctx.force_pass(p)
     ctx.kick_drift(p, 1 << m, t_min, 1 << m, False)
     ctx.sync()
-    names = sorted(p.arrays)
+    # the arrays a step changes that a later step reads: positions,
+    # velocities, entropies, h and bins (every other per-particle input of an
+    # active particle is recomputed before it is read, and the step does not
+    # write those of inactive particles)
+    names = ["x", "y", "z", "vx", "vy", "vz", "vfx", "vfy", "vfz", "A", "Af", "h", "time_bin"]
     dst = [p[k] for k in names]
     src = [t.clone() for t in dst]
 

@@ -71,6 +71,9 @@ typedef struct {
   int chunk_split;     /* loop work items: 0 = one per chunk; 1 / 2 = a chunk's cell-pair
                           list split into parts of about 1024 / 4096 staged partner
                           particles (at most 16), when no tuned entry applies (0) */
+  int sweep_below;     /* density Newton passes with fewer particles to do than this run one
+                          wave per particle (sorted sweep of each partner leaf) instead of
+                          the chunk loop (2048) */
   float rebuild_frac;  /* sph_build_cells keeps the cells of its last full build while no
                           leaf's particles moved more than this fraction of the leaf's
                           width since that build (0 = rebuild every call) (0.125) */
@@ -134,7 +137,8 @@ sph_status sph_build_cells(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *p
  * The sorts are made lazily, like the paper's sort tasks that run only for
  * active cells: this call prepares them (and synchronises once to check the
  * largest leaf, SPH_EINVAL above 4096 particles); each loop pass then sorts
- * the leaves its cell pairs reach that are not sorted yet in this step.
+ * the leaves its cell pairs reach that are not sorted yet in this step, except
+ * leaves of at most 128 particles, which the loops read whole.
  * sph_copy_axis_order sorts every leaf first. */
 sph_status sph_sort_cells(sph_ctx *ctx);
 

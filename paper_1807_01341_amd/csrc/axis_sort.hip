@@ -37,26 +37,9 @@ static AxisSet make_axes() {
 // Workgroup LDS bitonic sort for leaves of 513..4096 particles (only at the
 // maximum depth, where coincident particles cannot be split further).
 template <int P>
-__global__ __launch_bounds__(AS_THREADS) void axis_sort_kernel(const float4 *__restrict__ pos4,
-                                                               const int32_t *__restrict__ leaf_begin,
-                                                               const int32_t *__restrict__ leaf_count, int64_t nl,
-                                                               const int32_t *__restrict__ list,
-                                                               const int32_t *__restrict__ list_len, int64_t n,
-                                                               AxisSet ax, int min_count,
-                                                               uint16_t *__restrict__ order) {
-  __shared__ float ox[P], oy[P], oz[P];
-  __shared__ float key[P];
-  __shared__ uint16_t idx[P];
-  int l = blockIdx.x;
-  if (list) {
-    if (l >= *list_len) return;
-    l = list[l];
-  } else if (l >= nl) {
-    return;
-  }
-  const int cnt = leaf_count[l];
-  if (cnt < min_count || cnt > P) return;
-  const int b = leaf_begin[l];
+__device__ void sort_leaf_lds(const float4 *__restrict__ pos4, int b, int cnt, int64_t n, const AxisSet &ax,
+                              uint16_t *__restrict__ order, float *ox, float *oy, float *oz, float *key,
+                              uint16_t *idx) {
   int size = 2;
   while (size < cnt) size <<= 1;
   for (int k = threadIdx.x; k < cnt; k += AS_THREADS) {
@@ -99,6 +82,26 @@ __global__ __launch_bounds__(AS_THREADS) void axis_sort_kernel(const float4 *__r
     }
     for (int k = threadIdx.x; k < cnt; k += AS_THREADS) order[(int64_t)a * n + b + k] = idx[k];
     __syncthreads();
+  }
+}
+
+template <int P>
+__global__ __launch_bounds__(AS_THREADS) void axis_sort_kernel(const float4 *__restrict__ pos4,
+                                                               const int32_t *__restrict__ leaf_begin,
+                                                               const int32_t *__restrict__ leaf_count, int64_t nl,
+                                                               const int32_t *__restrict__ list,
+                                                               const int32_t *__restrict__ list_len, int64_t n,
+                                                               AxisSet ax, int min_count,
+                                                               uint16_t *__restrict__ order) {
+  __shared__ float ox[P], oy[P], oz[P];
+  __shared__ float key[P];
+  __shared__ uint16_t idx[P];
+  const int64_t items = list ? (int64_t)*list_len : nl;
+  for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+    const int l = list ? list[it] : (int)it;
+    const int cnt = leaf_count[l];
+    if (cnt < min_count || cnt > P) continue;
+    sort_leaf_lds<P>(pos4, leaf_begin[l], cnt, n, ax, order, ox, oy, oz, key, idx);
   }
 }
 
@@ -189,42 +192,48 @@ __device__ __forceinline__ void sort_leaf_axes(const float4 *__restrict__ pos4, 
   }
 }
 
-// One wave per leaf of at most 512 particles: every leaf, or the leaves of
-// `list` (its length on the device).
+// One wave per leaf of at most 512 particles (grid-stride): every leaf, or
+// the leaves of `list` (its length on the device).
 __global__ __launch_bounds__(256) void axis_sort_wave_kernel(const float4 *__restrict__ pos4,
                                                              const int32_t *__restrict__ leaf_begin,
                                                              const int32_t *__restrict__ leaf_count, int64_t nl,
                                                              const int32_t *__restrict__ list,
                                                              const int32_t *__restrict__ list_len, int64_t n,
                                                              AxisSet ax, uint16_t *__restrict__ order) {
-  int64_t l = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (list) {
-    if (l >= *list_len) return;
-    l = list[l];
-  } else if (l >= nl) {
-    return;
-  }
   const int lane = threadIdx.x & 63;
-  const int cnt = leaf_count[l], b = leaf_begin[l];
-  if (cnt <= 64)
-    sort_leaf_axes<1>(pos4, b, cnt, n, ax, order, lane);
-  else if (cnt <= 128)
-    sort_leaf_axes<2>(pos4, b, cnt, n, ax, order, lane);
-  else if (cnt <= 256)
-    sort_leaf_axes<4>(pos4, b, cnt, n, ax, order, lane);
-  else if (cnt <= 512)
-    sort_leaf_axes<8>(pos4, b, cnt, n, ax, order, lane);
+  const int64_t items = list ? (int64_t)*list_len : nl;
+  for (int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); it < items; it += (int64_t)gridDim.x * 4) {
+    const int64_t l = list ? list[it] : it;
+    const int cnt = leaf_count[l], b = leaf_begin[l];
+    if (cnt <= 64)
+      sort_leaf_axes<1>(pos4, b, cnt, n, ax, order, lane);
+    else if (cnt <= 128)
+      sort_leaf_axes<2>(pos4, b, cnt, n, ax, order, lane);
+    else if (cnt <= 256)
+      sort_leaf_axes<4>(pos4, b, cnt, n, ax, order, lane);
+    else if (cnt <= 512)
+      sort_leaf_axes<8>(pos4, b, cnt, n, ax, order, lane);
+  }
 }
 
 // Leaves of a cell-pair list not yet sorted: each is claimed once (its flag
-// set) and appended to the sort list.
+// set) and appended to the sort list of its size class.  Leaves of at most
+// 128 particles need no order: the loops read them whole.
 __global__ __launch_bounds__(256) void claim_partners_kernel(const PairEntry *__restrict__ pairs, int64_t np,
+                                                             const int32_t *__restrict__ leaf_count,
                                                              int32_t *__restrict__ sorted, int32_t *__restrict__ list,
-                                                             int32_t *__restrict__ list_len) {
+                                                             int32_t *__restrict__ list_len,
+                                                             int32_t *__restrict__ big, int32_t *__restrict__ big_len) {
   for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < np; q += (int64_t)gridDim.x * 256) {
     const int B = pairs[q].b;
     if (sorted[B]) continue;
-    if (atomicExch(&sorted[B], 1) == 0) list[atomicAdd(list_len, 1)] = B;
+    if (atomicExch(&sorted[B], 1) == 0) {
+      const int cnt = leaf_count[B];
+      if (cnt > 512)
+        big[atomicAdd(big_len, 1)] = B;
+      else if (cnt > 128)  // leaves of up to two 64-particle tiles are read whole, unsorted
+        list[atomicAdd(list_len, 1)] = B;
+    }
   }
 }
 
@@ -235,42 +244,55 @@ sph_status sort_cells_impl(sph_ctx *ctx) {
   const int64_t n = ctx->n, nl = ctx->n_leaves;
   SPH_TRY(sph_ensure(ctx, ctx->axis_order, sizeof(uint16_t) * 13 * (size_t)n));
   SPH_TRY(sph_ensure(ctx, ctx->leaf_sorted, sizeof(int32_t) * (size_t)(nl + 1)));
-  SPH_TRY(sph_ensure(ctx, ctx->sort_list, sizeof(int32_t) * (size_t)(nl + 1)));
-  int32_t maxc = 0;
-  SPH_TRY(read_scalars(ctx, SC_MAXLEAF, 1, &maxc));
-  if (maxc > 4096)
-    return sph_fail(ctx, SPH_EINVAL, "sort_cells: a leaf holds %d particles (max 4096 for the axis sorts)", maxc);
-  ctx->max_leaf = maxc;
+  SPH_TRY(sph_ensure(ctx, ctx->sort_list, sizeof(int32_t) * (size_t)(nl + 2)));
+  if (!ctx->leaves_checked) {
+    // the leaf sizes of a new full build (kept by cell updates)
+    int32_t st[SC_NBIG - SC_MAXLEAF + 1];
+    SPH_TRY(read_scalars(ctx, SC_MAXLEAF, SC_NBIG - SC_MAXLEAF + 1, st));
+    const int32_t maxc = st[0];
+    if (maxc > 4096)
+      return sph_fail(ctx, SPH_EINVAL, "sort_cells: a leaf holds %d particles (max 4096 for the axis sorts)", maxc);
+    ctx->max_leaf = maxc;
+    ctx->n_big_leaves = st[SC_NBIG - SC_MAXLEAF];
+    ctx->leaves_checked = 1;
+  }
   HIP_TRY(ctx, hipMemsetAsync(ctx->leaf_sorted.p, 0, sizeof(int32_t) * (size_t)nl, ctx->stream));
   ctx->sorted_lists = 0;
   ctx->state = 2;
   return SPH_OK;
 }
 
-static sph_status sort_leaves(sph_ctx *ctx, const int32_t *list, const int32_t *list_len, int64_t grid_leaves) {
+// Leaves of at most 512 particles from `small` (length *small_len on the
+// device, at most small_cap), larger ones from `big` (*big_len, at most
+// n_big_leaves); grids sized to the machine, not to the lists.
+static sph_status sort_leaves(sph_ctx *ctx, const int32_t *small, const int32_t *small_len, int64_t small_cap,
+                              const int32_t *big, const int32_t *big_len) {
   const int64_t n = ctx->n, nl = ctx->n_leaves;
   const AxisSet ax = make_axes();
-  if (grid_leaves <= 0) return SPH_OK;
-  {
+  const int64_t cap_small = std::min<int64_t>(small ? small_cap : nl, nl);
+  if (cap_small > 0) {
     PROF(ctx, "axis_sort");
-    axis_sort_wave_kernel<<<(unsigned)ceil_div(grid_leaves, 4), 256, 0, ctx->stream>>>(
+    const int64_t blocks = std::min<int64_t>(ceil_div(cap_small, 4), (int64_t)ctx->n_cu * 8);
+    axis_sort_wave_kernel<<<(unsigned)blocks, 256, 0, ctx->stream>>>(
         (const float4 *)ctx->pos4.p, (const int32_t *)ctx->leaf_begin.p, (const int32_t *)ctx->leaf_count.p, nl,
-        list, list_len, n, ax, (uint16_t *)ctx->axis_order.p);
+        small, small_len, n, ax, (uint16_t *)ctx->axis_order.p);
   }
   HIP_TRY(ctx, hipGetLastError());
-  if (ctx->max_leaf > 512) {
+  const int64_t cap_big = small ? ctx->n_big_leaves : (ctx->max_leaf > 512 ? nl : 0);
+  if (cap_big > 0) {
     PROF(ctx, "axis_sort");
-    axis_sort_kernel<4096><<<(unsigned)grid_leaves, AS_THREADS, 0, ctx->stream>>>(
+    const int64_t blocks = std::min<int64_t>(cap_big, (int64_t)ctx->n_cu * 2);
+    axis_sort_kernel<4096><<<(unsigned)blocks, AS_THREADS, 0, ctx->stream>>>(
         (const float4 *)ctx->pos4.p, (const int32_t *)ctx->leaf_begin.p, (const int32_t *)ctx->leaf_count.p, nl,
-        list, list_len, n, ax, 513, (uint16_t *)ctx->axis_order.p);
+        small ? big : nullptr, big_len, n, ax, 513, (uint16_t *)ctx->axis_order.p);
     HIP_TRY(ctx, hipGetLastError());
   }
   return SPH_OK;
 }
 
 // Sorts the partner leaves of cell-pair list `which` (0 density, 1 force)
-// not sorted yet in this step.  No synchronisation: the sort list's length
-// stays on the device.
+// not sorted yet in this step.  No synchronisation: the lists' lengths stay
+// on the device.
 sph_status sort_partners(sph_ctx *ctx, int which) {
   const int bit = 1 << which;
   if (ctx->sorted_lists & bit) return SPH_OK;
@@ -278,20 +300,24 @@ sph_status sort_partners(sph_ctx *ctx, int which) {
   const PairEntry *pairs = (const PairEntry *)(which == 0 ? ctx->dpairs.p : ctx->fpairs.p);
   ctx->sorted_lists |= bit;
   if (np <= 0) return SPH_OK;
-  int32_t *len = (int32_t *)ctx->sort_list.p + ctx->n_leaves;
-  HIP_TRY(ctx, hipMemsetAsync(len, 0, sizeof(int32_t), ctx->stream));
+  const int64_t nl = ctx->n_leaves;
+  SPH_TRY(sph_ensure(ctx, ctx->sort_big, sizeof(int32_t) * (size_t)(ctx->n_big_leaves + 1)));
+  int32_t *len = (int32_t *)ctx->sort_list.p + nl;  // [small length, big length]
+  HIP_TRY(ctx, hipMemsetAsync(len, 0, 2 * sizeof(int32_t), ctx->stream));
   {
     PROF(ctx, "axis_sort");
     claim_partners_kernel<<<(unsigned)std::min<int64_t>(ceil_div(np, 256), 4096), 256, 0, ctx->stream>>>(
-        pairs, np, (int32_t *)ctx->leaf_sorted.p, (int32_t *)ctx->sort_list.p, len);
+        pairs, np, (const int32_t *)ctx->leaf_count.p, (int32_t *)ctx->leaf_sorted.p, (int32_t *)ctx->sort_list.p,
+        len, (int32_t *)ctx->sort_big.p, len + 1);
   }
   HIP_TRY(ctx, hipGetLastError());
-  return sort_leaves(ctx, (const int32_t *)ctx->sort_list.p, len, std::min<int64_t>(np, ctx->n_leaves));
+  return sort_leaves(ctx, (const int32_t *)ctx->sort_list.p, len, std::min<int64_t>(np, nl),
+                     (const int32_t *)ctx->sort_big.p, len + 1);
 }
 
 // Every leaf (for the introspection copy).
 sph_status sort_all_leaves(sph_ctx *ctx) {
-  SPH_TRY(sort_leaves(ctx, nullptr, nullptr, ctx->n_leaves));
+  SPH_TRY(sort_leaves(ctx, nullptr, nullptr, 0, nullptr, nullptr));
   if (ctx->n_leaves > 0)
     HIP_TRY(ctx, hipMemsetAsync(ctx->leaf_sorted.p, 0x01, sizeof(int32_t) * (size_t)ctx->n_leaves, ctx->stream));
   ctx->sorted_lists = 3;

@@ -12,6 +12,7 @@
 // x - L floor(x/L), folded into [0, L).  Compiled without contraction, so the
 // product and the difference round separately.
 __device__ __forceinline__ double wrap_box(double x, double L) {
+  if (x >= 0.0 && x < L) return x;  // inside already (floor(x / L) = 0)
   const double q = floor(x / L);
   double xw = x - q * L;
   if (xw < 0.0) xw += L;
@@ -201,15 +202,21 @@ __global__ __launch_bounds__(BT) void leaf_table_kernel(const int32_t *__restric
 }
 
 __global__ __launch_bounds__(BT) void leaf_count_kernel(const int32_t *__restrict__ begin, int32_t *__restrict__ count,
-                                                        int64_t nl, int64_t n, int32_t *__restrict__ max_count) {
-  int mc = 0;
+                                                        int64_t nl, int64_t n, int32_t *__restrict__ max_count,
+                                                        int32_t *__restrict__ n_big) {
+  int mc = 0, nb = 0;
   for (int64_t l = (int64_t)blockIdx.x * BT + threadIdx.x; l < nl; l += (int64_t)gridDim.x * BT) {
     const int c = (int32_t)(((l + 1 < nl) ? begin[l + 1] : n) - begin[l]);
     count[l] = c;
     mc = max(mc, c);
+    nb += c > 512;
   }
   mc = wave_max_i(mc);
-  if ((threadIdx.x & 63) == 0) atomicMax(max_count, mc);
+  nb = wave_sum_i(nb);
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(max_count, mc);
+    if (nb) atomicAdd(n_big, nb);
+  }
 }
 
 // FP32 offsets from the leaf centre, H, and the leaf's max H: one wave per
@@ -484,7 +491,7 @@ sph_status build_cells_impl(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *
   }
   {
     PROF(ctx, "leaf_build");
-    leaf_count_kernel<<<grid_for(nl), BT, 0, ctx->stream>>>(lb, lc, nl, n, sc + SC_MAXLEAF);
+    leaf_count_kernel<<<grid_for(nl), BT, 0, ctx->stream>>>(lb, lc, nl, n, sc + SC_MAXLEAF, sc + SC_NBIG);
   }
   HIP_TRY(ctx, hipGetLastError());
   {
@@ -518,6 +525,7 @@ sph_status build_cells_impl(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *
   ctx->dx_max = 0.f;
   ctx->built_n = n;
   ctx->n_full_builds++;
+  ctx->leaves_checked = 0;
   SPH_TRY(pack_neighbour_data(ctx, p));
   ctx->state = 1;
   return SPH_OK;

@@ -43,6 +43,32 @@ __global__ __launch_bounds__(256) void density_init_kernel(int64_t n_chunks, int
   }
 }
 
+// Particles that waited for wider cell-pair lists become ordinary
+// unconverged ones again, their chunks to do.
+__global__ __launch_bounds__(256) void release_waiting_kernel(uint8_t *__restrict__ conv,
+                                                              const int32_t *__restrict__ chunk_of, int64_t n_act,
+                                                              int32_t *__restrict__ chunk_todo) {
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n_act; k += (int64_t)gridDim.x * 256)
+    if (conv[k] == 2) {
+      conv[k] = 0;
+      chunk_todo[chunk_of[k]] = 1;
+    }
+}
+
+// Active indices whose smoothing length is not converged yet (waiting ones
+// excluded).
+__global__ __launch_bounds__(256) void unconverged_kernel(const uint8_t *__restrict__ conv, int64_t n_act,
+                                                          int32_t *__restrict__ list, int32_t *__restrict__ len) {
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n_act; k += (int64_t)gridDim.x * 256) {
+    const bool todo = conv[k] == 0;
+    const uint64_t m = __ballot(todo);
+    int base = 0;
+    if ((threadIdx.x & 63) == 0 && m) base = atomicAdd(len, __popcll(m));
+    base = __shfl(base, 0, 64);
+    if (todo) list[base + rank_below(m)] = (int32_t)k;
+  }
+}
+
 __global__ __launch_bounds__(256) void fill_i32_kernel(int32_t *p, int64_t n, int32_t v) {
   for (int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x; s < n; s += (int64_t)gridDim.x * 256) p[s] = v;
 }
@@ -83,7 +109,7 @@ __global__ __launch_bounds__(256) void split_fill_kernel(const Chunk *__restrict
   if (threadIdx.x < 32) h[threadIdx.x] = 0;
   __syncthreads();
   for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n_chunks; q += (int64_t)gridDim.x * 256) {
-    const int i0 = item0[q], P = item0[q + 1] - i0;
+    const int i0 = item0 ? item0[q] : (int)q, P = item0 ? item0[q + 1] - i0 : 1;
     const int cost = max(1, act_cost[chunks[q].act_leaf] / P);
     const int b = __clz(cost);  // larger cost, smaller bucket
     for (int p = 0; p < P; ++p) {
@@ -179,6 +205,10 @@ sph_status items_count(sph_ctx *ctx, int target, int32_t *host_total) {
   SPH_TRY(sph_ensure(ctx, ctx->work_tmp, 4 * (size_t)(nc + 1) + 256));
   *host_total = 0;
   if (nc == 0) return SPH_OK;
+  if (target == 0) {  // one item per chunk: nothing to count
+    *host_total = (int32_t)nc;
+    return SPH_OK;
+  }
   int32_t *parts = (int32_t *)ctx->work_tmp.p + 64;
   PROF(ctx, "cost_order");
   split_count_kernel<<<grid_for_items(nc), 256, 0, ctx->stream>>>(
@@ -208,8 +238,8 @@ sph_status items_fill(sph_ctx *ctx, int target, int32_t total) {
   HIP_TRY(ctx, hipMemsetAsync(ctx->chunk_ctr.p, 0, 4 * (size_t)nc, ctx->stream));
   PROF(ctx, "cost_order");
   split_fill_kernel<<<grid_for_items(nc), 256, 0, ctx->stream>>>(
-      (const Chunk *)ctx->chunks.p, nc, (const int32_t *)ctx->act_cost.p, (const int32_t *)ctx->chunk_item0.p,
-      (int32_t *)ctx->items_nat.p, bucket_of, hist);
+      (const Chunk *)ctx->chunks.p, nc, (const int32_t *)ctx->act_cost.p,
+      target > 0 ? (const int32_t *)ctx->chunk_item0.p : nullptr, (int32_t *)ctx->items_nat.p, bucket_of, hist);
   cost_bucket_scan_kernel<<<1, 64, 0, ctx->stream>>>(hist);
   item_scatter_kernel<<<grid_for_items(total), 256, 0, ctx->stream>>>(
       (const int32_t *)ctx->items_nat.p, bucket_of, total, hist, (int32_t *)ctx->work.p);
@@ -220,7 +250,7 @@ sph_status ensure_items(sph_ctx *ctx, int target) {
   if (ctx->work_valid && ctx->items_target == target) return SPH_OK;
   int32_t total = 0;
   SPH_TRY(items_count(ctx, target, &total));
-  if (ctx->n_chunks > 0) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  if (ctx->n_chunks > 0 && target > 0) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   return items_fill(ctx, target, total);
 }
 
@@ -355,7 +385,11 @@ __device__ __forceinline__ void ghost_body(const GhostArgs &g) {
   int finished = 0;
   int unconv = 0;
   for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < g.n_active; k += (int64_t)gridDim.x * 256) {
-    if (g.conv[k]) continue;
+    if (g.conv[k] == 1) continue;
+    if (g.conv[k] == 2) {  // waiting for wider cell-pair lists: not converged
+      ++unconv;
+      continue;
+    }
     const int i = g.active_idx[k];
     const float S_w = g.sums[k], S_mw = g.sums[g.n_active + k], S_d = g.sums[2 * g.n_active + k],
                 S_md = g.sums[3 * g.n_active + k];
@@ -422,16 +456,22 @@ __device__ __forceinline__ void ghost_body(const GhostArgs &g) {
       g.conv[k] = 1;
       if (!done) ++unconv;
     } else {
+      const Chunk ch = g.chunks[g.chunk_of[k]];
+      const float Hn = GK32 * hn;
+      if (Hn > g.act_hmax[ch.act_leaf] * g.reach) {
+        // beyond the reach of the cell-pair lists: the particle waits (no
+        // evaluation) until they are widened, so that every evaluation sees
+        // all its neighbours
+        atomicOr(g.rebuild, 1);
+        g.conv[k] = 2;
+      }
+      if (Hn > g.box_quarter) atomicOr(g.rebuild, 2);
       g.hlo[k] = lo;
       g.hhi[k] = hi;
       g.h[i] = hn;
-      const float Hn = GK32 * hn;
       g.pos4[i].w = Hn;
       g.chunk_todo[g.chunk_of[k]] = 1;
       ++unconv;
-      const Chunk ch = g.chunks[g.chunk_of[k]];
-      if (Hn > g.act_hmax[ch.act_leaf] * g.reach) atomicOr(g.rebuild, 1);
-      if (Hn > g.box_quarter) atomicOr(g.rebuild, 2);
     }
   }
   finished = wave_sum_i(finished);
@@ -450,6 +490,166 @@ __global__ __launch_bounds__(256) void ghost_multi_kernel(const GhostArgs *__res
   ghost_body(g);
 }
 
+// Density loop, one wave per particle: for Newton passes with few particles
+// left (and deep time-bins, whose chunks hold few active particles).  The
+// partner leaves of at most 128 particles (and the particle's own leaf) are
+// read as one flat candidate range, 64 candidates per step across leaves, so
+// that their loads are issued together; larger partner leaves are swept in
+// the order of their sort along the stencil axis nearest to the pair offset
+// (the paper's sorted sweep), from the side facing the particle to past its
+// reach.  Same predicate, per-pair terms and outputs as the chunk loop (sums
+// per active index, count); the lanes' sums are reduced in a fixed butterfly.
+struct SweepPair {
+  int off, bb;
+  float sx, sy, sz;
+};
+
+__device__ __forceinline__ void density_term(const float4 &pi, const float4 &vi, float invHi, float dx, float dy,
+                                             float dz, float r2, const float4 &vj, float (&acc)[8]) {
+  const float rinv = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
+  const float r = r2 * rinv;
+  const float vx = vi.x - vj.x, vy = vi.y - vj.y, vz = vi.z - vj.z;
+  const float vr = fmaf(vz, dz, fmaf(vy, dy, vx * dx));
+  const float mj = vj.w;
+  float wq, wp;
+  const float q = r * invHi;
+  kernel_w_dw(q, wq, wp);
+  const float d3 = fmaf(q, wp, 3.f * wq);
+  acc[0] += wq;
+  acc[1] = fmaf(mj, wq, acc[1]);
+  acc[2] += d3;
+  acc[3] = fmaf(mj, d3, acc[3]);
+  const float fac = mj * wp * rinv;
+  acc[4] = fmaf(fac, vr, acc[4]);
+  acc[5] = fmaf(fac, fmaf(vy, dz, -vz * dy), acc[5]);
+  acc[6] = fmaf(fac, fmaf(vz, dx, -vx * dz), acc[6]);
+  acc[7] = fmaf(fac, fmaf(vx, dy, -vy * dx), acc[7]);
+  (void)pi;
+}
+
+__global__ __launch_bounds__(256) void density_sweep_kernel(LoopArgs g, const int32_t *__restrict__ todo,
+                                                            const int32_t *__restrict__ n_todo_dev, int64_t n_todo,
+                                                            const int32_t *__restrict__ chunk_of) {
+  __shared__ SweepPair sp[4][64];
+  const int wave = threadIdx.x >> 6;
+  const int64_t w = (int64_t)blockIdx.x * 4 + wave;
+  if (n_todo_dev) n_todo = *n_todo_dev;
+  if (w >= n_todo) return;
+  const int lane = threadIdx.x & 63;
+  SweepPair *my = sp[wave];
+  const int k = todo ? todo[w] : (int)w;
+  const int i = g.active_idx[k];
+  const float4 pi = g.pos4[i];
+  const float Hi = pi.w, H2i = Hi * Hi, invHi = 1.f / Hi;
+  const float4 vi = g.jvm[i];
+  const Chunk ch = g.chunks[chunk_of[k]];
+  const int pbeg = g.pair_off[ch.act_leaf], pend = g.pair_off[ch.act_leaf + 1];
+  float acc[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc[q] = 0.f;
+  int cnt = 0;
+  for (int p0 = pbeg; p0 < pend; p0 += 64) {
+    const int p = p0 + lane;
+    PairEntry e;
+    e.b = 0;
+    e.sx = e.sy = e.sz = 0.f;
+    int bb = 0, bc = 0;
+    if (p < pend) {
+      e = g.pairs[p];
+      bb = g.leaf_begin[e.b];
+      bc = g.leaf_count[e.b];
+    }
+    const bool big = p < pend && e.b != ch.leaf && bc > 128;
+    // flat range of the small partners: exclusive scan of their counts
+    const int n_small = (p < pend && !big) ? bc : 0;
+    int incl = n_small;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += t;
+    }
+    const int total = __shfl(incl, 63, 64);
+    wave_sync();
+    my[lane].off = incl - n_small;
+    my[lane].bb = bb;
+    my[lane].sx = e.sx;
+    my[lane].sy = e.sy;
+    my[lane].sz = e.sz;
+    wave_sync();
+    for (int t = 0; t < total; t += 64) {
+      const int f = t + lane;
+      if (f < total) {
+        // last pair whose range starts at or before f
+        int lo = 0, hi = 63;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (my[mid].off <= f) lo = mid; else hi = mid - 1;
+        }
+        const SweepPair q = my[lo];
+        const int j = q.bb + (f - q.off);
+        const float4 pj = g.pos4[j];
+        const float dx = pi.x - (pj.x + q.sx), dy = pi.y - (pj.y + q.sy), dz = pi.z - (pj.z + q.sz);
+        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        if (r2 < H2i) {
+          density_term(pi, vi, invHi, dx, dy, dz, r2, g.jvm[j], acc);
+          cnt += (j != i);
+        }
+      }
+    }
+    // large partners, one after the other: sorted sweep
+    uint64_t bigm = __ballot(big);
+    while (bigm) {
+      const int src = __ffsll((unsigned long long)bigm) - 1;
+      bigm &= bigm - 1;
+      const int bbq = __shfl(bb, src, 64), bcq = __shfl(bc, src, 64);
+      const float sx = __shfl(e.sx, src, 64), sy = __shfl(e.sy, src, 64), sz = __shfl(e.sz, src, 64);
+      int axis = 0;
+      float best = -1.f, sgn = 1.f;
+#pragma unroll
+      for (int a = 0; a < 13; ++a) {
+        const float d = fmaf(sz, g.ax.e[a][2], fmaf(sy, g.ax.e[a][1], sx * g.ax.e[a][0]));
+        if (fabsf(d) > best) {
+          best = fabsf(d);
+          axis = a;
+          sgn = d >= 0.f ? 1.f : -1.f;
+        }
+      }
+      const float ex = g.ax.e[axis][0], ey = g.ax.e[axis][1], ez = g.ax.e[axis][2];
+      const float pp = fmaf(pi.z, ez, fmaf(pi.y, ey, pi.x * ex));
+      const float sproj = fmaf(sz, ez, fmaf(sy, ey, sx * ex));
+      const float margin = 1.0001f * Hi + 1e-6f * (2.f * fabsf(pp) + fabsf(sproj));
+      const float lo_b = pp - margin - sproj, hi_b = pp + margin - sproj;
+      const uint16_t *ord = g.axis_order + (int64_t)axis * g.n + bbq;
+      for (int t = 0; t < bcq; t += 64) {
+        const int kk = t + lane;
+        const bool valid = kk < bcq;
+        const int j = valid ? bbq + (int)ord[sgn > 0.f ? kk : bcq - 1 - kk] : bbq;
+        const float4 pj = valid ? g.pos4[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float key = fmaf(pj.z, ez, fmaf(pj.y, ey, pj.x * ex));
+        const bool beyond = sgn > 0.f ? key > hi_b : key < lo_b;
+        if (__ballot(valid && !beyond) == 0ull) break;
+        const float dx = pi.x - (pj.x + sx), dy = pi.y - (pj.y + sy), dz = pi.z - (pj.z + sz);
+        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        if (valid && r2 < H2i) {
+          density_term(pi, vi, invHi, dx, dy, dz, r2, g.jvm[j], acc);
+          cnt += (j != i);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    float v = acc[q];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    acc[q] = v;
+  }
+  for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) g.sums[(int64_t)q * g.n_active + k] = acc[q];
+    g.act_cnt[k] = cnt;
+  }
+}
+
 // ---------------------------------------------------------------- density pass phases
 
 // Checks the arrays, resets the pass counters and, with active particles,
@@ -465,6 +665,7 @@ sph_status density_begin(sph_ctx *ctx, const sph_particles *p, int entropy_from_
   if (entropy_from_u && !p->u) return sph_fail(ctx, SPH_EINVAL, "density_pass: u is required with entropy_from_u");
   const int64_t na = ctx->n_active;
   ctx->density_from_u = entropy_from_u ? 1 : 0;
+  ctx->widen_pending = 0;
   ctx->density_iterations = 0;
   ctx->n_unconverged = 0;
   ctx->pair_rebuilds = 0;
@@ -547,6 +748,10 @@ GhostArgs density_ghost_args(sph_ctx *ctx, sph_particles *p, int it, int entropy
 // Book-keeping after Newton pass `it` with the ghost's counters st: returns
 // SPH_OK with *done = 1 when the solve is over; widens the pair lists when a
 // smoothing length outgrew them.
+// Passes are grouped like the single-box path's batches (passes 1-2, 3-4,
+// ...): widening happens only at the end of a group.
+static inline bool group_end(int it) { return (it % 2) == 0; }
+
 sph_status density_after_pass(sph_ctx *ctx, int it, const int32_t st[2], int *done) {
   *done = 0;
   ctx->density_iterations = it;
@@ -561,11 +766,17 @@ sph_status density_after_pass(sph_ctx *ctx, int it, const int32_t st[2], int *do
     *done = 1;
     return SPH_OK;
   }
-  if (st[1] & 1) {
-    // a smoothing length outgrew its cell's pair reach: widen the pair lists
+  if (st[1] & 1) ctx->widen_pending = 1;
+  if (ctx->widen_pending && group_end(it)) {
+    // a smoothing length outgrew its cell's pair reach: widen the pair lists,
+    // then the waiting particles go on
+    ctx->widen_pending = 0;
     ctx->pair_rebuilds++;
     SPH_TRY(refresh_leaf_hmax(ctx, false));
     SPH_TRY(build_pairs(ctx, 0, 1.5f));
+    release_waiting_kernel<<<grid256(ctx->n_active), 256, 0, ctx->stream>>>(
+        (uint8_t *)ctx->conv.p, (const int32_t *)ctx->chunk_of.p, ctx->n_active, (int32_t *)ctx->chunk_todo.p);
+    HIP_TRY(ctx, hipGetLastError());
   }
   return SPH_OK;
 }
@@ -581,29 +792,68 @@ sph_status density_end(sph_ctx *ctx, bool read_global) {
   return SPH_OK;
 }
 
+// Newton passes are enqueued in pairs without waiting for the host: each
+// pass's loop runs over what the previous ghost left to do, read on the
+// device, and a pass past convergence does nothing.  One synchronisation per
+// pair of passes reads both passes' counters.
 sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u) {
   int any;
   SPH_TRY(density_begin(ctx, p, entropy_from_u, &any));
   if (!any) return SPH_OK;
-  int32_t *sc = (int32_t *)ctx->scalars.p;
-  for (int it = 1; it <= ctx->prm.h_max_iter; ++it) {
-    LoopArgs a = density_loop_args(ctx);
-    if (ctx->prm.compensated)
-      SPH_TRY((launch_loop<0, true>(ctx, a)));
-    else
-      SPH_TRY((launch_loop<0, false>(ctx, a)));
-    HIP_TRY(ctx, hipMemsetAsync(sc + SC_UNCONV, 0, 8, ctx->stream));
-    GhostArgs gh = density_ghost_args(ctx, p, it, entropy_from_u, sc + SC_UNCONV);
-    {
-      PROF(ctx, "ghost");
-      ghost_kernel<<<grid256(ctx->n_active), 256, 0, ctx->stream>>>(gh);
+  const int64_t na = ctx->n_active;
+  const int maxit = ctx->prm.h_max_iter;
+  SPH_TRY(sph_ensure(ctx, ctx->pass_stats, sizeof(int32_t) * 2 * (size_t)(maxit + 1)));
+  SPH_TRY(sph_ensure(ctx, ctx->todo_list, 4 * (size_t)(na + 1)));
+  int32_t *stats = (int32_t *)ctx->pass_stats.p;
+  int32_t *list = (int32_t *)ctx->todo_list.p;
+  int64_t n_todo = na;  // upper bound of the particles left to do
+  int it = 0, done = 0;
+  while (!done) {
+    const int first = it + 1, last = std::min(it + 2, maxit);
+    HIP_TRY(ctx, hipMemsetAsync(stats + 2 * first, 0, sizeof(int32_t) * 2 * (last - first + 1), ctx->stream));
+    for (int pass = first; pass <= last; ++pass) {
+      LoopArgs a = density_loop_args(ctx);
+      if (n_todo < ctx->prm.sweep_below) {
+        // few particles to do: one wave per particle
+        SPH_TRY(sort_partners(ctx, 0));
+        if (pass > 1) {
+          HIP_TRY(ctx, hipMemsetAsync(list + na, 0, 4, ctx->stream));
+          PROF(ctx, "density_loop");
+          unconverged_kernel<<<grid256(na), 256, 0, ctx->stream>>>((const uint8_t *)ctx->conv.p, na, list,
+                                                                    list + na);
+        }
+        {
+          PROF(ctx, "density_loop");
+          density_sweep_kernel<<<(unsigned)std::max<int64_t>(1, ceil_div(n_todo, 4)), 256, 0, ctx->stream>>>(
+              a, pass > 1 ? list : nullptr, pass > 1 ? list + na : nullptr, n_todo,
+              (const int32_t *)ctx->chunk_of.p);
+        }
+        HIP_TRY(ctx, hipGetLastError());
+        // no chunk is left to do for the chunk loop; the ghost marks them again
+        fill_i32_kernel<<<grid256(ctx->n_chunks), 256, 0, ctx->stream>>>((int32_t *)ctx->chunk_todo.p,
+                                                                          ctx->n_chunks, 0);
+        HIP_TRY(ctx, hipGetLastError());
+      } else if (ctx->prm.compensated) {
+        SPH_TRY((launch_loop<0, true>(ctx, a)));
+      } else {
+        SPH_TRY((launch_loop<0, false>(ctx, a)));
+      }
+      GhostArgs gh = density_ghost_args(ctx, p, pass, entropy_from_u, stats + 2 * pass);
+      {
+        PROF(ctx, "ghost");
+        ghost_kernel<<<grid256(na), 256, 0, ctx->stream>>>(gh);
+      }
+      HIP_TRY(ctx, hipGetLastError());
     }
-    HIP_TRY(ctx, hipGetLastError());
-    int32_t st[2];
-    SPH_TRY(read_scalars(ctx, SC_UNCONV, 2, st));
-    int done;
-    SPH_TRY(density_after_pass(ctx, it, st, &done));
-    if (done) break;
+    std::vector<int32_t> st(2 * (size_t)(last - first + 1));
+    HIP_TRY(ctx, hipMemcpyAsync(st.data(), stats + 2 * first, sizeof(int32_t) * st.size(), hipMemcpyDeviceToHost,
+                                ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    for (int pass = first; pass <= last && !done; ++pass) {
+      SPH_TRY(density_after_pass(ctx, pass, &st[2 * (pass - first)], &done));
+      n_todo = st[2 * (pass - first)];
+    }
+    it = last;
   }
   return density_end(ctx, true);
 }
@@ -931,7 +1181,7 @@ sph_status batch_work_list(sph_ctx *lead, sph_ctx **cs, const std::vector<int> &
     SPH_TRY(items_count(c, target, &totals[q]));
     any = true;
   }
-  if (any) HIP_TRY(lead, hipStreamSynchronize(lead->stream));
+  if (any && target > 0) HIP_TRY(lead, hipStreamSynchronize(lead->stream));
   for (int q = 0; q < nl; ++q) {
     sph_ctx *c = cs[live[q]];
     if (c->work_valid && c->items_target == target) continue;

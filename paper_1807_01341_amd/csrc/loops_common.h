@@ -392,8 +392,50 @@ __device__ __forceinline__ void chunk_body(const LoopArgs &g, int code, bool cod
     len = 0;
   };
 
+  // Filter of the staged candidates into per-lane neighbour lists, FB
+  // candidates at a time.  Two schedules give the same lists in the same
+  // order: with many live lanes every lane walks the candidates (the
+  // candidate broadcast from LDS); with few live lanes (sparse chunks of a
+  // deep time-bin) lane t holds candidate b0 + t and the wave walks the live
+  // particles instead (their data broadcast by readlane), so the work
+  // follows the live particles, not the 64 lanes.
+  const int nlive = ch.count;
+  const float H2b = H2i, pxb = pi.x, pyb = pi.y, pzb = pi.z;
   auto flush = [&]() {
     wave_sync();
+    if (nlive < FB) {
+      for (int b0 = 0; b0 < ncand; b0 += FB) {
+        if (wave_max_i(len) > LCAP - FB) interact();
+        const int c = b0 + lane;
+        const bool cv = lane < FB && c < ncand;
+        const float4 cj = cv ? cand[c] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float Hj = (ModeTraits<MODE>::sym && cv) ? candH[c] : 0.f;
+        const int jj = __float_as_int(cj.w);
+        for (int ii = 0; ii < nlive; ++ii) {
+          const float xi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pxb), ii));
+          const float yi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pyb), ii));
+          const float zi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pzb), ii));
+          const float H2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(H2b), ii));
+          const float dx = xi - cj.x, dy = yi - cj.y, dz = zi - cj.z;
+          const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+          bool hit;
+          if (!ModeTraits<MODE>::sym)
+            hit = cv && r2 < H2;
+          else
+            hit = cv && (r2 < H2 || r2 < Hj * Hj) && jj != __builtin_amdgcn_readlane(i, ii);
+          const uint64_t hm = __ballot(hit);
+          if (hm) {
+            const int base = __builtin_amdgcn_readlane(len, ii);
+            if (hit) lists[(base + rank_below(hm)) * 64 + ii] = (uint16_t)c;
+            if (lane == ii) len += __popcll(hm);
+          }
+        }
+      }
+      interact();
+      ncand = 0;
+      wave_sync();
+      return;
+    }
     for (int b0 = 0; b0 < ncand; b0 += FB) {
       if (wave_max_i(len) > LCAP - FB) interact();
       const int bend = min(ncand, b0 + FB);
@@ -454,9 +496,11 @@ __device__ __forceinline__ void chunk_body(const LoopArgs &g, int code, bool cod
       const int kk = t + lane;
       const bool valid = kk < bc;
       int j = bb;
-      if (valid) j = selfp ? bb + kk : bb + (int)ord[sgn > 0.f ? kk : bc - 1 - kk];
+      // a partner of at most two tiles is read in cell order (its axis order is not made)
+      if (valid) j = (selfp || bc <= 128) ? bb + kk : bb + (int)ord[sgn > 0.f ? kk : bc - 1 - kk];
       const float4 pj = valid ? g.pos4[j] : make_float4(0.f, 0.f, 0.f, 0.f);
-      if (!selfp) {
+      if (!selfp && bc > 128) {
+        // sorted partner: stop at the first tile wholly past the reach
         const float key = fmaf(pj.z, ez, fmaf(pj.y, ey, pj.x * ex));
         const bool beyond = sgn > 0.f ? key > hi_b : key < lo_b;
         if (__ballot(valid && !beyond) == 0ull) break;

@@ -79,8 +79,10 @@ struct sph_ctx {
   DevBuf pos4;                            // float4 (ox, oy, oz, H) per particle
   // sort
   DevBuf axis_order;                      // uint16 13 x n
-  DevBuf leaf_sorted, sort_list;          // per leaf: axis orders made this step; leaves to sort
+  DevBuf leaf_sorted, sort_list, sort_big;  // per leaf: axis orders made this step; leaves to sort
   int max_leaf = 0;                       // largest leaf of the build
+  int64_t n_big_leaves = 0;               // leaves of more than 512 particles
+  int leaves_checked = 0;                 // max_leaf / n_big_leaves read for the current build
   int sorted_lists = 0;                   // bit w: partners of cell-pair list w are sorted
   // mark
   DevBuf active, leaf_nact, leaf_act_off, leaf_actleaf, act_leaves, act_hmax, act_leaf_chunk_off;
@@ -89,7 +91,7 @@ struct sph_ctx {
   // loops
   DevBuf jvm;                             // float4 (vx, vy, vz, m)
   DevBuf jth;                             // float4 (rho, f P / rho^2, c, B)
-  DevBuf sums, hlo, hhi, conv;
+  DevBuf sums, hlo, hhi, conv, todo_list, pass_stats;
   DevBuf counters64;                      // cumulative interaction counts (2 x uint64)
   DevBuf act_cost;                        // staged partner particles per active leaf
   DevBuf work, work_tmp, box_args, box_work;
@@ -100,6 +102,7 @@ struct sph_ctx {
   int64_t n_items = 0;
   int items_target = -1;                  // staged particles per part the items were built for
   int density_from_u = 0;                 // the last density pass took P from u
+  int widen_pending = 0;                  // a smoothing length reached the density pair reach
   // adjoint
   DevBuf adj_w, adj1, adj2, adj_out;
 
@@ -171,6 +174,7 @@ enum ScalarSlot {
   SC_UPD_HMAX = 13,   // cell update: max H bits, max displacement bits, rebuild flag
   SC_UPD_DX = 14,
   SC_UPD_FLAG = 15,
+  SC_NBIG = 16,       // leaves of more than 512 particles (full build)
   SC_COUNT = 32
 };
 

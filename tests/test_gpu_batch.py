@@ -10,7 +10,7 @@ from tests.gpu_cases import A_TOL, RHO_TOL, float_errors, host, oracle_all
 
 pytestmark = pytest.mark.gpu
 
-TILING = dict(waves_per_chunk=4, cand_cap=256, list_cap=64)
+TILING = dict(waves_per_chunk=4, cand_cap=256, list_cap=64, sweep_below=0)
 OUTPUTS = ("h", "rho", "drho_dh", "f_gradh", "divv", "curlx", "curly", "curlz", "P", "c", "balsara", "A",
            "ax", "ay", "az", "dA_dt", "du_dt", "vsig", "nngb_density", "nngb_force")
 
@@ -123,7 +123,9 @@ def test_batch_autotune_and_reload(gpu_lib, tmp_path):
     lines = open(path).read().splitlines()
     assert sum(l.startswith("batch_best") for l in lines) == 2
     assert sum(l.startswith("batch_candidate") for l in lines) == 2 * 3 * 2 * 12
-    # the tuned tiling gives the same counts and the same sums to rounding
+    # the tuned tiling gives the same counts, and the same densities within
+    # the solve's tolerance (another summation order can end the Newton
+    # iteration one step apart)
     cs2, ps2, _ = prepare(sg, boxes, ms, {})
     cs2[0].load_tuning(path)
     b2 = sg.Batch(cs2, ps2)
@@ -133,7 +135,7 @@ def test_batch_autotune_and_reload(gpu_lib, tmp_path):
     for b in range(len(boxes)):
         assert np.array_equal(got[b]["nngb_density"], ref[b]["nngb_density"])
         assert np.array_equal(got[b]["nngb_force"], ref[b]["nngb_force"])
-        assert np.max(np.abs(got[b]["rho"] / ref[b]["rho"] - 1)) < 2e-6
+        assert np.max(np.abs(got[b]["rho"] / ref[b]["rho"] - 1)) < RHO_TOL
 
 
 def test_batch_argument_errors(gpu_lib):

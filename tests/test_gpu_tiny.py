@@ -141,15 +141,17 @@ def test_call_order_and_argument_errors(gpu_lib):
     assert ctx2.info()["n_unconverged"] > 0
 
 
-@pytest.mark.parametrize("nw,split", [(1, 0), (2, 0), (4, 0), (8, 0), (1, 1), (2, 2), (4, 1), (8, 1)])
-def test_waves_per_chunk_variants_agree(gpu_lib, nw, split):
+@pytest.mark.parametrize("nw,split,sweep", [(1, 0, 0), (2, 0, 0), (4, 0, 0), (8, 0, 0), (1, 1, 0), (2, 2, 0),
+                                             (4, 1, 0), (8, 1, 0), (4, 0, 1 << 30)])
+def test_waves_per_chunk_variants_agree(gpu_lib, nw, split, sweep):
     """Every loop tiling (waves per chunk, candidate/list capacities, chunks
-    split into parts of their cell-pair lists) gives the same neighbour
-    counts and the same sums to rounding."""
+    split into parts of their cell-pair lists, one wave per particle) gives
+    the same neighbour counts and the same sums to rounding."""
     ic = ics.tiny_lattice(16, velocity_sigma=0.1)
-    _, p0, perm0, _ = run_gpu_step(gpu_lib, ic, 0, ctx_kw=dict(waves_per_chunk=1, cand_cap=2048, list_cap=192))
+    _, p0, perm0, _ = run_gpu_step(gpu_lib, ic, 0, ctx_kw=dict(waves_per_chunk=1, cand_cap=2048, list_cap=192,
+                                                               sweep_below=0))
     _, p1, perm1, _ = run_gpu_step(gpu_lib, ic, 0, ctx_kw=dict(waves_per_chunk=nw, cand_cap=256, list_cap=64,
-                                                               chunk_split=split))
+                                                               chunk_split=split, sweep_below=sweep))
     assert np.array_equal(perm0, perm1)
     for k in ("nngb_density", "nngb_force"):
         assert np.array_equal(host(p0, k), host(p1, k)), k
