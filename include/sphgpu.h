@@ -73,7 +73,7 @@ typedef struct {
                           particles (at most 16), when no tuned entry applies (0) */
   int sweep_below;     /* density Newton passes with fewer particles to do than this run one
                           wave per particle (sorted sweep of each partner leaf) instead of
-                          the chunk loop (2048) */
+                          the chunk loop (2^30: always; batched passes use chunks) */
   float rebuild_frac;  /* sph_build_cells keeps the cells of its last full build while no
                           leaf's particles moved more than this fraction of the leaf's
                           width since that build (0 = rebuild every call) (0.125) */

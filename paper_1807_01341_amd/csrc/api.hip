@@ -102,7 +102,7 @@ void sph_default_params(sph_params *p) {
   p->cand_cap = 512;
   p->list_cap = 96;
   p->rebuild_frac = 0.125f;
-  p->sweep_below = 2048;
+  p->sweep_below = 1 << 30;
 }
 
 sph_status sph_create(const sph_params *p, void *hip_stream, sph_ctx **out) {

@@ -161,7 +161,8 @@ __device__ __forceinline__ void wave_bitonic(uint64_t (&w)[E], int lane) {
 
 template <int E>
 __device__ __forceinline__ void sort_leaf_axes(const float4 *__restrict__ pos4, int b, int cnt, int64_t n,
-                                               const AxisSet &ax, uint16_t *__restrict__ order, int lane) {
+                                               const AxisSet &ax, uint16_t *__restrict__ order, int lane,
+                                               int a_first, int a_end) {
   float ox[E], oy[E], oz[E];
 #pragma unroll
   for (int r = 0; r < E; ++r) {
@@ -175,7 +176,7 @@ __device__ __forceinline__ void sort_leaf_axes(const float4 *__restrict__ pos4, 
       ox[r] = oy[r] = oz[r] = 0.f;
     }
   }
-  for (int a = 0; a < 13; ++a) {
+  for (int a = a_first; a < a_end; ++a) {
     const float ex = ax.e[a][0], ey = ax.e[a][1], ez = ax.e[a][2];
     uint64_t w[E];
 #pragma unroll
@@ -192,8 +193,8 @@ __device__ __forceinline__ void sort_leaf_axes(const float4 *__restrict__ pos4, 
   }
 }
 
-// One wave per leaf of at most 512 particles (grid-stride): every leaf, or
-// the leaves of `list` (its length on the device).
+// One wave per (leaf of at most 512 particles, axis), grid-stride: every
+// leaf, or the leaves of `list` (its length on the device).
 __global__ __launch_bounds__(256) void axis_sort_wave_kernel(const float4 *__restrict__ pos4,
                                                              const int32_t *__restrict__ leaf_begin,
                                                              const int32_t *__restrict__ leaf_count, int64_t nl,
@@ -201,18 +202,21 @@ __global__ __launch_bounds__(256) void axis_sort_wave_kernel(const float4 *__res
                                                              const int32_t *__restrict__ list_len, int64_t n,
                                                              AxisSet ax, uint16_t *__restrict__ order) {
   const int lane = threadIdx.x & 63;
-  const int64_t items = list ? (int64_t)*list_len : nl;
+  // work item = (leaf, axis): the 13 sorts of a leaf run on 13 waves
+  const int64_t items = 13 * (list ? (int64_t)*list_len : nl);
   for (int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); it < items; it += (int64_t)gridDim.x * 4) {
-    const int64_t l = list ? list[it] : it;
+    const int64_t li = it / 13;
+    const int a = (int)(it - 13 * li);
+    const int64_t l = list ? list[li] : li;
     const int cnt = leaf_count[l], b = leaf_begin[l];
     if (cnt <= 64)
-      sort_leaf_axes<1>(pos4, b, cnt, n, ax, order, lane);
+      sort_leaf_axes<1>(pos4, b, cnt, n, ax, order, lane, a, a + 1);
     else if (cnt <= 128)
-      sort_leaf_axes<2>(pos4, b, cnt, n, ax, order, lane);
+      sort_leaf_axes<2>(pos4, b, cnt, n, ax, order, lane, a, a + 1);
     else if (cnt <= 256)
-      sort_leaf_axes<4>(pos4, b, cnt, n, ax, order, lane);
+      sort_leaf_axes<4>(pos4, b, cnt, n, ax, order, lane, a, a + 1);
     else if (cnt <= 512)
-      sort_leaf_axes<8>(pos4, b, cnt, n, ax, order, lane);
+      sort_leaf_axes<8>(pos4, b, cnt, n, ax, order, lane, a, a + 1);
   }
 }
 
@@ -272,7 +276,7 @@ static sph_status sort_leaves(sph_ctx *ctx, const int32_t *small, const int32_t 
   const int64_t cap_small = std::min<int64_t>(small ? small_cap : nl, nl);
   if (cap_small > 0) {
     PROF(ctx, "axis_sort");
-    const int64_t blocks = std::min<int64_t>(ceil_div(cap_small, 4), (int64_t)ctx->n_cu * 8);
+    const int64_t blocks = std::min<int64_t>(ceil_div(13 * cap_small, 4), (int64_t)ctx->n_cu * 8);
     axis_sort_wave_kernel<<<(unsigned)blocks, 256, 0, ctx->stream>>>(
         (const float4 *)ctx->pos4.p, (const int32_t *)ctx->leaf_begin.p, (const int32_t *)ctx->leaf_count.p, nl,
         small, small_len, n, ax, (uint16_t *)ctx->axis_order.p);

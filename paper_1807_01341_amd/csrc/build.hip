@@ -262,8 +262,8 @@ __global__ __launch_bounds__(BT) void update_kernel(double *__restrict__ x, doub
                                                     const int32_t *__restrict__ iy, const int32_t *__restrict__ iz,
                                                     int64_t nl, int D, double L, double unit, float frac,
                                                     float4 *__restrict__ pos4, float *__restrict__ leaf_hmax,
-                                                    float *__restrict__ leaf_dx, int32_t *__restrict__ sc_hmax,
-                                                    int32_t *__restrict__ sc_dx, int32_t *__restrict__ sc_flag) {
+                                                    float *__restrict__ leaf_dx, float2 *__restrict__ block_max,
+                                                    int32_t *__restrict__ sc_flag) {
   const int64_t l = (int64_t)blockIdx.x * (BT / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   float hm = 0.f, dm = 0.f;
@@ -316,8 +316,34 @@ __global__ __launch_bounds__(BT) void update_kernel(double *__restrict__ x, doub
       a = fmaxf(a, wh[w]);
       d = fmaxf(d, wd[w]);
     }
-    if (a > 0.f) atomicMax(sc_hmax, __float_as_int(a));
-    if (d > 0.f) atomicMax(sc_dx, __float_as_int(d));
+    block_max[blockIdx.x] = make_float2(a, d);  // reduced by a second kernel (no contended atomics)
+  }
+}
+
+__global__ __launch_bounds__(BT) void max2_reduce_kernel(const float2 *__restrict__ part, int n,
+                                                         int32_t *__restrict__ out_bits) {
+  float a = 0.f, d = 0.f;
+  for (int k = threadIdx.x; k < n; k += BT) {
+    a = fmaxf(a, part[k].x);
+    d = fmaxf(d, part[k].y);
+  }
+  __shared__ float wa[BT / 64], wd[BT / 64];
+  a = wave_max_f(a);
+  d = wave_max_f(d);
+  if ((threadIdx.x & 63) == 0) {
+    wa[threadIdx.x >> 6] = a;
+    wd[threadIdx.x >> 6] = d;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < BT / 64; ++w) {
+      a = fmaxf(a, wa[w]);
+      d = fmaxf(d, wd[w]);
+    }
+    a = fmaxf(a, wa[0]);
+    d = fmaxf(d, wd[0]);
+    out_bits[0] = __float_as_int(a);
+    out_bits[1] = __float_as_int(d);
   }
 }
 
@@ -540,14 +566,17 @@ sph_status update_cells(sph_ctx *ctx, sph_particles *p, int64_t *perm_out, int *
   int32_t *sc = (int32_t *)ctx->scalars.p;
   HIP_TRY(ctx, hipMemsetAsync(sc + SC_UPD_HMAX, 0, 3 * sizeof(int32_t), ctx->stream));
   const double *xb = (const double *)ctx->x_build.p;
+  const int64_t blocks = ceil_div(nl, BT / 64);
+  SPH_TRY(sph_ensure(ctx, ctx->scan_out, sizeof(float2) * (size_t)blocks));
   {
     PROF(ctx, "cell_update");
-    update_kernel<<<(unsigned)ceil_div(nl, BT / 64), BT, 0, ctx->stream>>>(
+    update_kernel<<<(unsigned)blocks, BT, 0, ctx->stream>>>(
         p->x, p->y, p->z, p->h, xb, xb + n, xb + 2 * n, (const int32_t *)ctx->leaf_begin.p,
         (const int32_t *)ctx->leaf_count.p, (const int32_t *)ctx->leaf_level.p, (const int32_t *)ctx->leaf_ix.p,
         (const int32_t *)ctx->leaf_iy.p, (const int32_t *)ctx->leaf_iz.p, nl, D, L, ldexp(L, -(D + 1)),
         ctx->prm.rebuild_frac, (float4 *)ctx->pos4.p, (float *)ctx->leaf_hmax.p, (float *)ctx->leaf_dx.p,
-        sc + SC_UPD_HMAX, sc + SC_UPD_DX, sc + SC_UPD_FLAG);
+        (float2 *)ctx->scan_out.p, sc + SC_UPD_FLAG);
+    max2_reduce_kernel<<<1, BT, 0, ctx->stream>>>((const float2 *)ctx->scan_out.p, (int)blocks, sc + SC_UPD_HMAX);
   }
   HIP_TRY(ctx, hipGetLastError());
   int32_t st[3];

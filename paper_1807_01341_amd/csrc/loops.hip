@@ -650,6 +650,169 @@ __global__ __launch_bounds__(256) void density_sweep_kernel(LoopArgs g, const in
   }
 }
 
+// Force loop, one wave per active particle (as the density sweep): partner
+// leaves of at most 128 particles and the own leaf as one flat candidate
+// range, larger ones swept in their axis order up to max(H_i, that leaf's max
+// H).  Same predicate (j != i, r < max(H_i, H_j)), pair terms and outputs as
+// the chunk loop; lane sums reduced in a fixed butterfly, v_sig by max.
+struct ForceAcc {
+  float ax, ay, az, visc, adiab, vmax;
+};
+
+__device__ __forceinline__ void force_term(const float4 &vi, const float4 &thi, float invHi, float half_alpha,
+                                           float dx, float dy, float dz, float r2, float Hj, const float4 &vj,
+                                           const float4 &th, ForceAcc &f) {
+  const float rinv = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
+  const float r = r2 * rinv;
+  const float invHj = __builtin_amdgcn_rcpf(Hj);
+  const float vx = vi.x - vj.x, vy = vi.y - vj.y, vz = vi.z - vj.z;
+  const float vr = fmaf(vz, dz, fmaf(vy, dy, vx * dx));
+  const float mj = vj.w;
+  const float wpi = kernel_dw_only(r * invHi);
+  const float wpj = kernel_dw_only(r * invHj);
+  const float ih2 = invHj * invHj;
+  const float Fi = (KNORM32 * invHi * invHi * invHi * invHi) * wpi * rinv;
+  const float Fj = KNORM32 * (ih2 * ih2) * wpj * rinv;
+  const float mu = fminf(vr * rinv, 0.f);
+  const float vsig = thi.z + th.z - 3.f * mu;
+  f.vmax = fmaxf(f.vmax, vsig);
+  const float Pi = -half_alpha * vsig * mu * (thi.w + th.w) * __builtin_amdgcn_rcpf(thi.x + th.x);
+  const float gbar = 0.5f * (Fi + Fj);
+  const float coef = mj * fmaf(thi.y, Fi, fmaf(th.y, Fj, Pi * gbar));
+  f.ax = fmaf(-coef, dx, f.ax);
+  f.ay = fmaf(-coef, dy, f.ay);
+  f.az = fmaf(-coef, dz, f.az);
+  f.visc = fmaf(mj * Pi * vr, gbar, f.visc);
+  f.adiab = fmaf(mj * vr, Fi, f.adiab);
+}
+
+__global__ __launch_bounds__(256) void force_sweep_kernel(LoopArgs g, const int32_t *__restrict__ chunk_of) {
+  __shared__ SweepPair sp[4][64];
+  __shared__ int blk_cnt[4];
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int64_t k = (int64_t)blockIdx.x * 4 + wave;
+  int cnt = 0;
+  if (k < g.n_active) {
+    SweepPair *my = sp[wave];
+    const int i = g.active_idx[k];
+    const float4 pi = g.pos4[i];
+    const float Hi = pi.w, H2i = Hi * Hi, invHi = 1.f / Hi;
+    const float4 vi = g.jvm[i];
+    const float4 thi = g.jth[i];
+    const Chunk ch = g.chunks[chunk_of[k]];
+    const int pbeg = g.pair_off[ch.act_leaf], pend = g.pair_off[ch.act_leaf + 1];
+    ForceAcc f = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    auto visit = [&](int j, float sx, float sy, float sz) {
+      const float4 pj = g.pos4[j];
+      const float dx = pi.x - (pj.x + sx), dy = pi.y - (pj.y + sy), dz = pi.z - (pj.z + sz);
+      const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+      if ((r2 < H2i || r2 < pj.w * pj.w) && j != i) {
+        force_term(vi, thi, invHi, g.half_alpha, dx, dy, dz, r2, pj.w, g.jvm[j], g.jth[j], f);
+        ++cnt;
+      }
+    };
+    for (int p0 = pbeg; p0 < pend; p0 += 64) {
+      const int p = p0 + lane;
+      PairEntry e;
+      e.b = 0;
+      e.sx = e.sy = e.sz = 0.f;
+      int bb = 0, bc = 0;
+      if (p < pend) {
+        e = g.pairs[p];
+        bb = g.leaf_begin[e.b];
+        bc = g.leaf_count[e.b];
+      }
+      const bool big = p < pend && e.b != ch.leaf && bc > 128;
+      const int n_small = (p < pend && !big) ? bc : 0;
+      int incl = n_small;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+      }
+      const int total = __shfl(incl, 63, 64);
+      wave_sync();
+      my[lane].off = incl - n_small;
+      my[lane].bb = bb;
+      my[lane].sx = e.sx;
+      my[lane].sy = e.sy;
+      my[lane].sz = e.sz;
+      wave_sync();
+      for (int t = 0; t < total; t += 64) {
+        const int fi = t + lane;
+        if (fi < total) {
+          int lo = 0, hi = 63;
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (my[mid].off <= fi) lo = mid; else hi = mid - 1;
+          }
+          const SweepPair q = my[lo];
+          visit(q.bb + (fi - q.off), q.sx, q.sy, q.sz);
+        }
+      }
+      uint64_t bigm = __ballot(big);
+      while (bigm) {
+        const int src = __ffsll((unsigned long long)bigm) - 1;
+        bigm &= bigm - 1;
+        const int bbq = __shfl(bb, src, 64), bcq = __shfl(bc, src, 64), Bq = __shfl(e.b, src, 64);
+        const float sx = __shfl(e.sx, src, 64), sy = __shfl(e.sy, src, 64), sz = __shfl(e.sz, src, 64);
+        int axis = 0;
+        float best = -1.f, sgn = 1.f;
+#pragma unroll
+        for (int a = 0; a < 13; ++a) {
+          const float d = fmaf(sz, g.ax.e[a][2], fmaf(sy, g.ax.e[a][1], sx * g.ax.e[a][0]));
+          if (fabsf(d) > best) {
+            best = fabsf(d);
+            axis = a;
+            sgn = d >= 0.f ? 1.f : -1.f;
+          }
+        }
+        const float ex = g.ax.e[axis][0], ey = g.ax.e[axis][1], ez = g.ax.e[axis][2];
+        const float Rb = fmaxf(Hi, g.leaf_hmax[Bq]);
+        const float pp = fmaf(pi.z, ez, fmaf(pi.y, ey, pi.x * ex));
+        const float sproj = fmaf(sz, ez, fmaf(sy, ey, sx * ex));
+        const float margin = 1.0001f * Rb + 1e-6f * (2.f * fabsf(pp) + fabsf(sproj));
+        const float lo_b = pp - margin - sproj, hi_b = pp + margin - sproj;
+        const uint16_t *ord = g.axis_order + (int64_t)axis * g.n + bbq;
+        for (int t = 0; t < bcq; t += 64) {
+          const int kk = t + lane;
+          const bool valid = kk < bcq;
+          const int j = valid ? bbq + (int)ord[sgn > 0.f ? kk : bcq - 1 - kk] : bbq;
+          const float4 pj = valid ? g.pos4[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+          const float key = fmaf(pj.z, ez, fmaf(pj.y, ey, pj.x * ex));
+          const bool beyond = sgn > 0.f ? key > hi_b : key < lo_b;
+          if (__ballot(valid && !beyond) == 0ull) break;
+          if (valid) visit(j, sx, sy, sz);
+        }
+      }
+    }
+    float v[5] = {f.ax, f.ay, f.az, f.visc, f.adiab};
+#pragma unroll
+    for (int q = 0; q < 5; ++q)
+      for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o, 64);
+    float vm = f.vmax;
+    for (int o = 32; o > 0; o >>= 1) vm = fmaxf(vm, __shfl_xor(vm, o, 64));
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+    if (lane == 0) {
+      g.ax_out[i] = v[0];
+      g.ay_out[i] = v[1];
+      g.az_out[i] = v[2];
+      const float rho = thi.x;
+      g.dA_out[i] = 0.5f * g.gm1 * __powf(rho, -g.gm1) * v[3];
+      g.du_out[i] = fmaf(thi.y, v[4], 0.5f * v[3]);
+      g.vsig_out[i] = vm;
+      if (g.nngb_out) g.nngb_out[i] = cnt;
+    }
+  }
+  // interactions of the block, one counter update
+  if (lane == 0) blk_cnt[wave] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int s = blk_cnt[0] + blk_cnt[1] + blk_cnt[2] + blk_cnt[3];
+    if (s) atomicAdd(g.ctr, (unsigned long long)s);
+  }
+}
+
 // ---------------------------------------------------------------- density pass phases
 
 // Checks the arrays, resets the pass counters and, with active particles,
@@ -818,7 +981,7 @@ sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u)
         SPH_TRY(sort_partners(ctx, 0));
         if (pass > 1) {
           HIP_TRY(ctx, hipMemsetAsync(list + na, 0, 4, ctx->stream));
-          PROF(ctx, "density_loop");
+          PROF(ctx, "density_todo");
           unconverged_kernel<<<grid256(na), 256, 0, ctx->stream>>>((const uint8_t *)ctx->conv.p, na, list,
                                                                     list + na);
         }
@@ -888,10 +1051,19 @@ sph_status force_pass_impl(sph_ctx *ctx, sph_particles *p) {
   fill_i32_kernel<<<grid256(ctx->n_chunks), 256, 0, ctx->stream>>>((int32_t *)ctx->chunk_todo.p, ctx->n_chunks, 1);
   HIP_TRY(ctx, hipGetLastError());
   LoopArgs a = force_loop_args(ctx, p);
-  if (ctx->prm.compensated)
+  if (ctx->n_active < ctx->prm.sweep_below) {
+    SPH_TRY(sort_partners(ctx, 1));
+    {
+      PROF(ctx, "force_loop");
+      force_sweep_kernel<<<(unsigned)ceil_div(ctx->n_active, 4), 256, 0, ctx->stream>>>(
+          a, (const int32_t *)ctx->chunk_of.p);
+    }
+    HIP_TRY(ctx, hipGetLastError());
+  } else if (ctx->prm.compensated) {
     SPH_TRY((launch_loop<1, true>(ctx, a)));
-  else
+  } else {
     SPH_TRY((launch_loop<1, false>(ctx, a)));
+  }
   ctx->state = 5;
   return SPH_OK;
 }

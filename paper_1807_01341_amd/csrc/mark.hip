@@ -154,54 +154,82 @@ __global__ __launch_bounds__(MT) void pairs_kernel(int mode, float slack, PairGe
   int written = 0;
   int staged = 0;
   const int base = FILL ? offs[a] : 0;
-  for (int u = 0; u < cnt3[0]; ++u) {
-    const int tx = ((lo[0] + u) % ntop + ntop) % ntop;
-    for (int v = 0; v < cnt3[1]; ++v) {
+  // the top cells of the search box, 64 at a time; their leaves as one flat
+  // range (in cell order, leaves in order), 64 leaves per step
+  __shared__ int cell_off[MT / 64][64], cell_first[MT / 64][64];
+  int *coff = cell_off[threadIdx.x >> 6], *cfirst = cell_first[threadIdx.x >> 6];
+  const int ncell = cnt3[0] * cnt3[1] * cnt3[2];
+  for (int c0 = 0; c0 < ncell; c0 += 64) {
+    const int cc = c0 + lane;
+    int f = 0, nleaf = 0;
+    if (cc < ncell) {
+      const int u = cc / (cnt3[1] * cnt3[2]), v = (cc / cnt3[2]) % cnt3[1], w = cc % cnt3[2];
+      const int tx = ((lo[0] + u) % ntop + ntop) % ntop;
       const int ty = ((lo[1] + v) % ntop + ntop) % ntop;
-      for (int w = 0; w < cnt3[2]; ++w) {
-        const int tz = ((lo[2] + w) % ntop + ntop) % ntop;
-        const int64_t tc = ((int64_t)tx * ntop + ty) * ntop + tz;
-        const int f = top_first[tc], e = top_last[tc];
-        for (int B0 = f; B0 < e; B0 += 64) {
-          const int B = B0 + lane;
-          bool ok = false;
-          int64_t dl[3] = {0, 0, 0};
-          if (B < e) {
-            int64_t cb[3];
-            const int lvB = level[B];
-            leaf_centre_units(g.D, lvB, ix[B], iy[B], iz[B], cb);
-            const int64_t hwb = (int64_t)1 << (g.D - lvB);
-            double d2 = 0.0;
-            for (int d = 0; d < 3; ++d) {
-              int64_t dd = cb[d] - ca[d];
-              if (dd > g.nu / 2) dd -= g.nu;
-              if (dd < -g.nu / 2) dd += g.nu;
-              dl[d] = dd;
-              int64_t gap = (dd < 0 ? -dd : dd) - hwa - hwb;
-              if (gap < 0) gap = 0;
-              const double gd = (double)gap * g.unit;
-              d2 = d2 + gd * gd;
-            }
-            float R = RA;
-            if (mode == 1) R = fmaxf(R, leaf_hmax[B]);
-            R = (R + dxA) + leaf_dx[B];
-            const double Rd = (double)R;
-            ok = d2 < Rd * Rd;
-          }
-          const uint64_t mask = __ballot(ok);
-          if (FILL && ok) {
-            PairEntry pe;
-            pe.b = B;
-            pe.sx = (float)((double)dl[0] * g.unit);
-            pe.sy = (float)((double)dl[1] * g.unit);
-            pe.sz = (float)((double)dl[2] * g.unit);
-            out[base + written + rank_below(mask)] = pe;
-            if (act_cost) staged += leaf_count[B];
-          }
-          written += __popcll(mask);
-        }
-      }
+      const int tz = ((lo[2] + w) % ntop + ntop) % ntop;
+      const int64_t tc = ((int64_t)tx * ntop + ty) * ntop + tz;
+      f = top_first[tc];
+      nleaf = top_last[tc] - f;
     }
+    int incl = nleaf;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += t;
+    }
+    const int total = __shfl(incl, 63, 64);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    coff[lane] = incl - nleaf;
+    cfirst[lane] = f;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int t0 = 0; t0 < total; t0 += 64) {
+      const int fi = t0 + lane;
+      bool ok = false;
+      int64_t dl[3] = {0, 0, 0};
+      int B = 0;
+      if (fi < total) {
+        int lo_ = 0, hi_ = 63;
+        while (lo_ < hi_) {
+          const int mid = (lo_ + hi_ + 1) >> 1;
+          if (coff[mid] <= fi) lo_ = mid; else hi_ = mid - 1;
+        }
+        B = cfirst[lo_] + (fi - coff[lo_]);
+        int64_t cb[3];
+        const int lvB = level[B];
+        leaf_centre_units(g.D, lvB, ix[B], iy[B], iz[B], cb);
+        const int64_t hwb = (int64_t)1 << (g.D - lvB);
+        double d2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+          int64_t dd = cb[d] - ca[d];
+          if (dd > g.nu / 2) dd -= g.nu;
+          if (dd < -g.nu / 2) dd += g.nu;
+          dl[d] = dd;
+          int64_t gap = (dd < 0 ? -dd : dd) - hwa - hwb;
+          if (gap < 0) gap = 0;
+          const double gd = (double)gap * g.unit;
+          d2 = d2 + gd * gd;
+        }
+        float R = RA;
+        if (mode == 1) R = fmaxf(R, leaf_hmax[B]);
+        R = (R + dxA) + leaf_dx[B];
+        const double Rd = (double)R;
+        ok = d2 < Rd * Rd;
+      }
+      const uint64_t mask = __ballot(ok);
+      if (FILL && ok) {
+        PairEntry pe;
+        pe.b = B;
+        pe.sx = (float)((double)dl[0] * g.unit);
+        pe.sy = (float)((double)dl[1] * g.unit);
+        pe.sz = (float)((double)dl[2] * g.unit);
+        out[base + written + rank_below(mask)] = pe;
+        if (act_cost) staged += leaf_count[B];
+      }
+      written += __popcll(mask);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
   if (!FILL && lane == 0) counts[a] = written;
   if (FILL && act_cost) {
