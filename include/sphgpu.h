@@ -74,6 +74,8 @@ typedef struct {
   int sweep_below;     /* density Newton passes with fewer particles to do than this run one
                           wave per particle (sorted sweep of each partner leaf) instead of
                           the chunk loop (2^30: always; batched passes use chunks) */
+  int sweep_waves;     /* waves per particle in those passes: 1, 2 or 4; 0 = from the number
+                          of particles to do (0) */
   float rebuild_frac;  /* sph_build_cells keeps the cells of its last full build while no
                           leaf's particles moved more than this fraction of the leaf's
                           width since that build (0 = rebuild every call) (0.125) */

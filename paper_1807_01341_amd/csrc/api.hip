@@ -112,6 +112,7 @@ sph_status sph_create(const sph_params *p, void *hip_stream, sph_ctx **out) {
       p->top_cap > 8 || p->n_bins < 1 || p->n_bins > 63 || p->h_max_iter < 1 || !(p->eta > 0) ||
       !(p->gamma > 1.0) || p->cand_cap < 64 || p->list_cap < 64 || p->chunk_split < 0 || p->chunk_split > 2 ||
       !(p->rebuild_frac >= 0.f && p->rebuild_frac <= 1.f) || p->sweep_below < 0 ||
+      !(p->sweep_waves == 0 || p->sweep_waves == 1 || p->sweep_waves == 2 || p->sweep_waves == 4) ||
       !(p->waves_per_chunk == 0 || p->waves_per_chunk == 1 || p->waves_per_chunk == 2 || p->waves_per_chunk == 4 ||
         p->waves_per_chunk == 8))
     return SPH_EINVAL;

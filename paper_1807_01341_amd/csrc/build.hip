@@ -347,6 +347,13 @@ __global__ __launch_bounds__(BT) void max2_reduce_kernel(const float2 *__restric
   }
 }
 
+// Half width of each leaf (float of the exact dyadic value).
+__global__ __launch_bounds__(BT) void leaf_half_kernel(const int32_t *__restrict__ level, int64_t nl, double L,
+                                                       float *__restrict__ half) {
+  for (int64_t l = (int64_t)blockIdx.x * BT + threadIdx.x; l < nl; l += (int64_t)gridDim.x * BT)
+    half[l] = (float)ldexp(L, -level[l] - 1);
+}
+
 __global__ __launch_bounds__(BT) void iota_kernel(int64_t *__restrict__ out, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x; i < n; i += (int64_t)gridDim.x * BT) out[i] = i;
 }
@@ -541,6 +548,9 @@ sph_status build_cells_impl(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *
   // positions the cells were built from (for the update criterion); no drift margin yet
   SPH_TRY(sph_ensure(ctx, ctx->x_build, 24 * (size_t)n));
   SPH_TRY(sph_ensure(ctx, ctx->leaf_dx, 4 * (size_t)(nl > 0 ? nl : 1)));
+  SPH_TRY(sph_ensure(ctx, ctx->leaf_half, 4 * (size_t)(nl > 0 ? nl : 1)));
+  leaf_half_kernel<<<grid_for(nl), BT, 0, ctx->stream>>>(lvl, nl, L, (float *)ctx->leaf_half.p);
+  HIP_TRY(ctx, hipGetLastError());
   {
     double *xb = (double *)ctx->x_build.p;
     HIP_TRY(ctx, hipMemcpyAsync(xb, p->x, 8 * n, hipMemcpyDeviceToDevice, ctx->stream));

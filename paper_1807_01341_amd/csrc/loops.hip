@@ -316,6 +316,8 @@ LoopArgs base_args(sph_ctx *ctx) {
   a.leaf_begin = (const int32_t *)ctx->leaf_begin.p;
   a.leaf_count = (const int32_t *)ctx->leaf_count.p;
   a.leaf_hmax = (const float *)ctx->leaf_hmax.p;
+  a.leaf_half = (const float *)ctx->leaf_half.p;
+  a.leaf_dx = (const float *)ctx->leaf_dx.p;
   a.axis_order = (const uint16_t *)ctx->axis_order.p;
   a.n = ctx->n;
   a.ax = host_axes();
@@ -504,6 +506,30 @@ struct SweepPair {
   float sx, sy, sz;
 };
 
+// Whether partner leaf e.b can hold a particle within R of the particle at
+// offset pi: the distance from pi to the leaf's box (in the particle's leaf
+// frame, widened by the leaf's drift margin) against R, with a relative
+// guard for rounding.  The leaf's own cell-pair reach covers the union of
+// its particles; this prunes per particle.
+__device__ __forceinline__ bool leaf_in_reach(const LoopArgs &g, const PairEntry &e, const float4 &pi, float R) {
+  const float hw = g.leaf_half[e.b] + g.leaf_dx[e.b];
+  const float gx = fmaxf(fabsf(pi.x - e.sx) - hw, 0.f);
+  const float gy = fmaxf(fabsf(pi.y - e.sy) - hw, 0.f);
+  const float gz = fmaxf(fabsf(pi.z - e.sz) - hw, 0.f);
+  const float Rg = 1.0001f * R + 1e-6f * (fabsf(pi.x) + fabsf(pi.y) + fabsf(pi.z) + hw);
+  return fmaf(gz, gz, fmaf(gy, gy, gx * gx)) < Rg * Rg;
+}
+
+// Waves per particle of a sweep pass: enough waves in flight to fill the
+// machine several times over when few particles are to do.
+int sweep_waves(const sph_ctx *ctx, int64_t n_todo) {
+  if (ctx->prm.sweep_waves > 0) return ctx->prm.sweep_waves;
+  const int64_t slots = (int64_t)ctx->n_cu * 32;  // waves resident on the machine
+  if (n_todo * 2 <= slots) return 4;
+  if (n_todo <= 4 * slots) return 2;
+  return 1;
+}
+
 __device__ __forceinline__ void density_term(const float4 &pi, const float4 &vi, float invHi, float dx, float dy,
                                              float dz, float r2, const float4 &vj, float (&acc)[8]) {
   const float rinv = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
@@ -527,15 +553,21 @@ __device__ __forceinline__ void density_term(const float4 &pi, const float4 &vi,
   (void)pi;
 }
 
+// NWP waves share one particle: wave s of it takes the flat candidates
+// s*64 + NWP*64*t and every NWP-th large partner; the waves' sums are added
+// in wave order.
+template <int NWP>
 __global__ __launch_bounds__(256) void density_sweep_kernel(LoopArgs g, const int32_t *__restrict__ todo,
                                                             const int32_t *__restrict__ n_todo_dev, int64_t n_todo,
                                                             const int32_t *__restrict__ chunk_of) {
   __shared__ SweepPair sp[4][64];
+  __shared__ float red[4][9];
   const int wave = threadIdx.x >> 6;
-  const int64_t w = (int64_t)blockIdx.x * 4 + wave;
+  const int sub = wave % NWP;
+  const int64_t w = (int64_t)blockIdx.x * (4 / NWP) + wave / NWP;
   if (n_todo_dev) n_todo = *n_todo_dev;
-  if (w >= n_todo) return;
   const int lane = threadIdx.x & 63;
+  if (w < n_todo) {
   SweepPair *my = sp[wave];
   const int k = todo ? todo[w] : (int)w;
   const int i = g.active_idx[k];
@@ -554,14 +586,16 @@ __global__ __launch_bounds__(256) void density_sweep_kernel(LoopArgs g, const in
     e.b = 0;
     e.sx = e.sy = e.sz = 0.f;
     int bb = 0, bc = 0;
+    bool near = false;
     if (p < pend) {
       e = g.pairs[p];
       bb = g.leaf_begin[e.b];
       bc = g.leaf_count[e.b];
+      near = leaf_in_reach(g, e, pi, Hi);
     }
-    const bool big = p < pend && e.b != ch.leaf && bc > 128;
-    // flat range of the small partners: exclusive scan of their counts
-    const int n_small = (p < pend && !big) ? bc : 0;
+    const bool big = near && e.b != ch.leaf && bc > 128;
+    // flat range of the small partners within reach: exclusive scan of their counts
+    const int n_small = (near && !big) ? bc : 0;
     int incl = n_small;
     for (int o = 1; o < 64; o <<= 1) {
       const int t = __shfl_up(incl, o, 64);
@@ -575,7 +609,7 @@ __global__ __launch_bounds__(256) void density_sweep_kernel(LoopArgs g, const in
     my[lane].sy = e.sy;
     my[lane].sz = e.sz;
     wave_sync();
-    for (int t = 0; t < total; t += 64) {
+    for (int t = sub * 64; t < total; t += NWP * 64) {
       const int f = t + lane;
       if (f < total) {
         // last pair whose range starts at or before f
@@ -597,9 +631,11 @@ __global__ __launch_bounds__(256) void density_sweep_kernel(LoopArgs g, const in
     }
     // large partners, one after the other: sorted sweep
     uint64_t bigm = __ballot(big);
+    int nb = 0;
     while (bigm) {
       const int src = __ffsll((unsigned long long)bigm) - 1;
       bigm &= bigm - 1;
+      if ((nb++ % NWP) != sub) continue;
       const int bbq = __shfl(bb, src, 64), bcq = __shfl(bc, src, 64);
       const float sx = __shfl(e.sx, src, 64), sy = __shfl(e.sy, src, 64), sz = __shfl(e.sz, src, 64);
       int axis = 0;
@@ -643,10 +679,37 @@ __global__ __launch_bounds__(256) void density_sweep_kernel(LoopArgs g, const in
     acc[q] = v;
   }
   for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
-  if (lane == 0) {
+  if (NWP == 1) {
+    if (lane == 0) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) g.sums[(int64_t)q * g.n_active + k] = acc[q];
-    g.act_cnt[k] = cnt;
+      for (int q = 0; q < 8; ++q) g.sums[(int64_t)q * g.n_active + k] = acc[q];
+      g.act_cnt[k] = cnt;
+    }
+  } else {
+    if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) red[wave][q] = acc[q];
+      red[wave][8] = __int_as_float(cnt);
+    }
+  }
+  }
+  if (NWP > 1) {
+    __syncthreads();
+    if (sub == 0 && lane == 0 && w < n_todo) {
+      const int k = todo ? todo[w] : (int)w;
+      float s[8];
+      int cs = 0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s[q] = 0.f;
+      for (int u = 0; u < NWP; ++u) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) s[q] += red[wave + u][q];
+        cs += __float_as_int(red[wave + u][8]);
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) g.sums[(int64_t)q * g.n_active + k] = s[q];
+      g.act_cnt[k] = cs;
+    }
   }
 }
 
@@ -686,12 +749,15 @@ __device__ __forceinline__ void force_term(const float4 &vi, const float4 &thi, 
   f.adiab = fmaf(mj * vr, Fi, f.adiab);
 }
 
+template <int NWP>
 __global__ __launch_bounds__(256) void force_sweep_kernel(LoopArgs g, const int32_t *__restrict__ chunk_of) {
   __shared__ SweepPair sp[4][64];
   __shared__ int blk_cnt[4];
+  __shared__ float red[4][7];
   const int wave = threadIdx.x >> 6;
+  const int sub = wave % NWP;
   const int lane = threadIdx.x & 63;
-  const int64_t k = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t k = (int64_t)blockIdx.x * (4 / NWP) + wave / NWP;
   int cnt = 0;
   if (k < g.n_active) {
     SweepPair *my = sp[wave];
@@ -718,13 +784,15 @@ __global__ __launch_bounds__(256) void force_sweep_kernel(LoopArgs g, const int3
       e.b = 0;
       e.sx = e.sy = e.sz = 0.f;
       int bb = 0, bc = 0;
+      bool near = false;
       if (p < pend) {
         e = g.pairs[p];
         bb = g.leaf_begin[e.b];
         bc = g.leaf_count[e.b];
+        near = leaf_in_reach(g, e, pi, fmaxf(Hi, g.leaf_hmax[e.b]));
       }
-      const bool big = p < pend && e.b != ch.leaf && bc > 128;
-      const int n_small = (p < pend && !big) ? bc : 0;
+      const bool big = near && e.b != ch.leaf && bc > 128;
+      const int n_small = (near && !big) ? bc : 0;
       int incl = n_small;
       for (int o = 1; o < 64; o <<= 1) {
         const int t = __shfl_up(incl, o, 64);
@@ -738,7 +806,7 @@ __global__ __launch_bounds__(256) void force_sweep_kernel(LoopArgs g, const int3
       my[lane].sy = e.sy;
       my[lane].sz = e.sz;
       wave_sync();
-      for (int t = 0; t < total; t += 64) {
+      for (int t = sub * 64; t < total; t += NWP * 64) {
         const int fi = t + lane;
         if (fi < total) {
           int lo = 0, hi = 63;
@@ -751,9 +819,11 @@ __global__ __launch_bounds__(256) void force_sweep_kernel(LoopArgs g, const int3
         }
       }
       uint64_t bigm = __ballot(big);
+      int nb = 0;
       while (bigm) {
         const int src = __ffsll((unsigned long long)bigm) - 1;
         bigm &= bigm - 1;
+        if ((nb++ % NWP) != sub) continue;
         const int bbq = __shfl(bb, src, 64), bcq = __shfl(bc, src, 64), Bq = __shfl(e.b, src, 64);
         const float sx = __shfl(e.sx, src, 64), sy = __shfl(e.sy, src, 64), sz = __shfl(e.sz, src, 64);
         int axis = 0;
@@ -793,7 +863,13 @@ __global__ __launch_bounds__(256) void force_sweep_kernel(LoopArgs g, const int3
     float vm = f.vmax;
     for (int o = 32; o > 0; o >>= 1) vm = fmaxf(vm, __shfl_xor(vm, o, 64));
     for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
-    if (lane == 0) {
+    if (NWP > 1 && lane == 0) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) red[wave][q] = v[q];
+      red[wave][5] = vm;
+      red[wave][6] = __int_as_float(cnt);
+    }
+    if (NWP == 1 && lane == 0) {
       g.ax_out[i] = v[0];
       g.ay_out[i] = v[1];
       g.az_out[i] = v[2];
@@ -802,6 +878,30 @@ __global__ __launch_bounds__(256) void force_sweep_kernel(LoopArgs g, const int3
       g.du_out[i] = fmaf(thi.y, v[4], 0.5f * v[3]);
       g.vsig_out[i] = vm;
       if (g.nngb_out) g.nngb_out[i] = cnt;
+    }
+  }
+  if (NWP > 1) {
+    __syncthreads();
+    if (sub == 0 && lane == 0 && k < g.n_active) {
+      const int i = g.active_idx[k];
+      const float4 thi = g.jth[i];
+      float v[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+      float vm = 0.f;
+      int cs = 0;
+      for (int u = 0; u < NWP; ++u) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) v[q] += red[wave + u][q];
+        vm = fmaxf(vm, red[wave + u][5]);
+        cs += __float_as_int(red[wave + u][6]);
+      }
+      g.ax_out[i] = v[0];
+      g.ay_out[i] = v[1];
+      g.az_out[i] = v[2];
+      const float rho = thi.x;
+      g.dA_out[i] = 0.5f * g.gm1 * __powf(rho, -g.gm1) * v[3];
+      g.du_out[i] = fmaf(thi.y, v[4], 0.5f * v[3]);
+      g.vsig_out[i] = vm;
+      if (g.nngb_out) g.nngb_out[i] = cs;
     }
   }
   // interactions of the block, one counter update
@@ -987,9 +1087,15 @@ sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u)
         }
         {
           PROF(ctx, "density_loop");
-          density_sweep_kernel<<<(unsigned)std::max<int64_t>(1, ceil_div(n_todo, 4)), 256, 0, ctx->stream>>>(
-              a, pass > 1 ? list : nullptr, pass > 1 ? list + na : nullptr, n_todo,
-              (const int32_t *)ctx->chunk_of.p);
+          const int nwp = sweep_waves(ctx, n_todo);
+          const unsigned grid = (unsigned)std::max<int64_t>(1, ceil_div(n_todo * nwp, 4));
+          const int32_t *tl = pass > 1 ? list : nullptr, *tn = pass > 1 ? list + na : nullptr;
+          if (nwp == 4)
+            density_sweep_kernel<4><<<grid, 256, 0, ctx->stream>>>(a, tl, tn, n_todo, (const int32_t *)ctx->chunk_of.p);
+          else if (nwp == 2)
+            density_sweep_kernel<2><<<grid, 256, 0, ctx->stream>>>(a, tl, tn, n_todo, (const int32_t *)ctx->chunk_of.p);
+          else
+            density_sweep_kernel<1><<<grid, 256, 0, ctx->stream>>>(a, tl, tn, n_todo, (const int32_t *)ctx->chunk_of.p);
         }
         HIP_TRY(ctx, hipGetLastError());
         // no chunk is left to do for the chunk loop; the ghost marks them again
@@ -1055,8 +1161,14 @@ sph_status force_pass_impl(sph_ctx *ctx, sph_particles *p) {
     SPH_TRY(sort_partners(ctx, 1));
     {
       PROF(ctx, "force_loop");
-      force_sweep_kernel<<<(unsigned)ceil_div(ctx->n_active, 4), 256, 0, ctx->stream>>>(
-          a, (const int32_t *)ctx->chunk_of.p);
+      const int nwp = sweep_waves(ctx, ctx->n_active);
+      const unsigned grid = (unsigned)ceil_div(ctx->n_active * nwp, 4);
+      if (nwp == 4)
+        force_sweep_kernel<4><<<grid, 256, 0, ctx->stream>>>(a, (const int32_t *)ctx->chunk_of.p);
+      else if (nwp == 2)
+        force_sweep_kernel<2><<<grid, 256, 0, ctx->stream>>>(a, (const int32_t *)ctx->chunk_of.p);
+      else
+        force_sweep_kernel<1><<<grid, 256, 0, ctx->stream>>>(a, (const int32_t *)ctx->chunk_of.p);
     }
     HIP_TRY(ctx, hipGetLastError());
   } else if (ctx->prm.compensated) {

@@ -67,6 +67,8 @@ struct LoopArgs {
   const float4 *jth;   // (rho, f P / rho^2, c, B)  force only
   const int32_t *leaf_begin, *leaf_count;
   const float *leaf_hmax;
+  const float *leaf_half;  // half width of each leaf (sweep pruning)
+  const float *leaf_dx;    // drift margin of each leaf
   const int32_t *pair_off;
   const PairEntry *pairs;
   const uint16_t *axis_order;

@@ -65,7 +65,7 @@ struct sph_ctx {
   float hmax_global = 0.f;  // max H over all particles (monotone between builds)
   // cells kept between builds: positions of the last full build, per-leaf and
   // largest displacement since then (the cell-pair search margin)
-  DevBuf x_build, leaf_dx;
+  DevBuf x_build, leaf_dx, leaf_half;
   float dx_max = 0.f;
   int64_t built_n = 0;
   int64_t n_full_builds = 0, n_updates = 0;
