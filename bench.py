@@ -372,6 +372,7 @@ def main():
     ap.add_argument("--h-tol", type=float, default=None)
     ap.add_argument("--nw", type=int, default=None)
     ap.add_argument("--sweep-below", type=int, default=None)
+    ap.add_argument("--sweep-waves", type=int, default=None)
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--load-tune", default=None, help="load a tuning file instead of tuning")
     ap.add_argument("--tune-file", default=os.path.join(ROOT, "gpurun_out", "tuning_clustered.txt"))
@@ -424,6 +425,8 @@ def main():
         kw["waves_per_chunk"] = args.nw
     if args.sweep_below is not None:
         kw["sweep_below"] = args.sweep_below
+    if args.sweep_waves is not None:
+        kw["sweep_waves"] = args.sweep_waves
     ctx = sg.Context(**kw)
     p = sg.Particles.from_initial(ic)
 

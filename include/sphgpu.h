@@ -71,11 +71,11 @@ typedef struct {
   int chunk_split;     /* loop work items: 0 = one per chunk; 1 / 2 = a chunk's cell-pair
                           list split into parts of about 1024 / 4096 staged partner
                           particles (at most 16), when no tuned entry applies (0) */
-  int sweep_below;     /* density Newton passes with fewer particles to do than this run one
-                          wave per particle (sorted sweep of each partner leaf) instead of
-                          the chunk loop (2^30: always; batched passes use chunks) */
-  int sweep_waves;     /* waves per particle in those passes: 1, 2 or 4; 0 = from the number
-                          of particles to do (0) */
+  int sweep_below;     /* density Newton passes with fewer particles to do, and force passes
+                          with fewer active particles, than this run waves per particle
+                          (a sweep of each partner leaf in reach) instead of the chunk
+                          loop (2^30: always; 0: never; batched passes use chunks) */
+  int sweep_waves;     /* waves per particle in those passes: 1, 2 or 4; 0 = one (0) */
   float rebuild_frac;  /* sph_build_cells keeps the cells of its last full build while no
                           leaf's particles moved more than this fraction of the leaf's
                           width since that build (0 = rebuild every call) (0.125) */

@@ -157,6 +157,15 @@ class Particles:
 
     def __setitem__(self, k, v):
         self.arrays[k] = v
+        self.__dict__.pop("_c", None)
+
+    def c_struct(self) -> ParticlesC:
+        """The C view of the arrays, built once (until an array is replaced)."""
+        s = self.__dict__.get("_c")
+        if s is None:
+            s = self.to_c()
+            self.__dict__["_c"] = s
+        return s
 
     @classmethod
     def from_initial(cls, ic: dict, device="cuda", counts=True):
@@ -244,7 +253,7 @@ class Context:
         return code
 
     def _pcs(self, p: Particles):
-        self._pc = p.to_c()   # keep alive while queued work reads the pointers
+        self._pc = p.c_struct()   # kept alive while queued work reads the pointers
         return C.byref(self._pc)
 
     # ---- the path

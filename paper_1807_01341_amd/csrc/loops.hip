@@ -520,14 +520,13 @@ __device__ __forceinline__ bool leaf_in_reach(const LoopArgs &g, const PairEntry
   return fmaf(gz, gz, fmaf(gy, gy, gx * gx)) < Rg * Rg;
 }
 
-// Waves per particle of a sweep pass: enough waves in flight to fill the
-// machine several times over when few particles are to do.
+// Waves per particle of a sweep pass.  One wave per particle measured fastest
+// on the deep-bin steps (the partial sums of several waves cost more in the
+// merge than the extra waves gain in latency), so several are only taken on
+// request.
 int sweep_waves(const sph_ctx *ctx, int64_t n_todo) {
-  if (ctx->prm.sweep_waves > 0) return ctx->prm.sweep_waves;
-  const int64_t slots = (int64_t)ctx->n_cu * 32;  // waves resident on the machine
-  if (n_todo * 2 <= slots) return 4;
-  if (n_todo <= 4 * slots) return 2;
-  return 1;
+  (void)n_todo;
+  return ctx->prm.sweep_waves > 0 ? ctx->prm.sweep_waves : 1;
 }
 
 __device__ __forceinline__ void density_term(const float4 &pi, const float4 &vi, float invHi, float dx, float dy,
