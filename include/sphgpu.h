@@ -79,6 +79,10 @@ typedef struct {
   float rebuild_frac;  /* sph_build_cells keeps the cells of its last full build while no
                           leaf's particles moved more than this fraction of the leaf's
                           width since that build (0 = rebuild every call) (0.125) */
+  float pair_slack;    /* the density cell-pair lists of sph_mark_active reach this factor
+                          times each active leaf's max H, so that smoothing lengths can grow
+                          that much in the h solve before the lists are widened, in [1, 2]
+                          (1.1) */
 } sph_params;
 
 /* The particle state.  Arrays marked (opt) may be NULL.  build_cells reorders
@@ -136,12 +140,15 @@ sph_status sph_build_cells(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *p
 /* Per-cell particle sorts for neighbour pruning (Fig. 5 "sort" task): for
  * each leaf and each of the 13 directions of the half neighbour stencil, the
  * in-leaf order by projection of the FP32 offset (ties by in-leaf index).
- * The sorts are made lazily, like the paper's sort tasks that run only for
- * active cells: this call prepares them (and synchronises once to check the
- * largest leaf, SPH_EINVAL above 4096 particles); each loop pass then sorts
- * the leaves its cell pairs reach that are not sorted yet in this step, except
- * leaves of at most 128 particles, which the loops read whole.
- * sph_copy_axis_order sorts every leaf first. */
+ * The offsets are those of the last full build: cell updates keep the
+ * orders, and the loops widen the point where a sweep stops by twice the
+ * leaf's drift margin (a particle's projection moves at most that far from
+ * its sorted place), as the paper keeps sorts while particles drift less
+ * than a bound.  After a full build this call sorts every leaf of more than
+ * 128 particles in one launch (the loops read smaller leaves whole), after
+ * one synchronisation that checks the largest leaf (SPH_EINVAL above 4096
+ * particles); after a cell update it does nothing.  sph_copy_axis_order
+ * sorts every leaf first. */
 sph_status sph_sort_cells(sph_ctx *ctx);
 
 /* Active set for the current time-bin (Eq. 2, Sec. III-D): particle i is
@@ -277,7 +284,7 @@ sph_status sph_copy_leaves(sph_ctx *ctx, int32_t *level, int32_t *ix, int32_t *i
                            int32_t *count, float *hmax, float *drift);
 /* Sorted Morton keys and FP32 leaf-centre offsets (length n). */
 sph_status sph_copy_particles(sph_ctx *ctx, uint64_t *keys, float *ox, float *oy, float *oz);
-/* 13 x n in-leaf order (axis-major). */
+/* 13 x n in-leaf order (axis-major), by the offsets of the last full build. */
 sph_status sph_copy_axis_order(sph_ctx *ctx, uint16_t *order);
 /* Active flags (n), active leaves and their max active H (n_active_leaves). */
 sph_status sph_copy_active(sph_ctx *ctx, uint8_t *active, int32_t *active_leaves, float *hmax_act);

@@ -35,7 +35,7 @@ class Params(C.Structure):
                 ("n_bins", C.c_int), ("split_count", C.c_int), ("morton_depth", C.c_int), ("top_cap", C.c_int),
                 ("h_max_iter", C.c_int), ("compensated", C.c_int), ("cand_cap", C.c_int), ("list_cap", C.c_int),
                 ("waves_per_chunk", C.c_int), ("chunk_split", C.c_int), ("sweep_below", C.c_int),
-                ("sweep_waves", C.c_int), ("rebuild_frac", C.c_float)]
+                ("sweep_waves", C.c_int), ("rebuild_frac", C.c_float), ("pair_slack", C.c_float)]
 
 
 # field name, dtype, role

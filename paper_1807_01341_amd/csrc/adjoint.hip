@@ -177,8 +177,6 @@ sph_status adjoint_impl(sph_ctx *ctx, sph_particles *p, const float *wx, const f
   // neighbour cell pairs at the converged smoothing lengths
   SPH_TRY(build_pairs(ctx, 0, 1.0f));
   SPH_TRY(build_pairs(ctx, 1, 1.0f));
-  SPH_TRY(sort_partners(ctx, 1));
-  SPH_TRY(sort_partners(ctx, 0));
 
   // 1. reverse of the force loop
   LoopArgs a = base_args(ctx);

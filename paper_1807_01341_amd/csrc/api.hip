@@ -102,6 +102,7 @@ void sph_default_params(sph_params *p) {
   p->cand_cap = 512;
   p->list_cap = 96;
   p->rebuild_frac = 0.125f;
+  p->pair_slack = 1.1f;
   p->sweep_below = 1 << 30;
 }
 
@@ -111,7 +112,8 @@ sph_status sph_create(const sph_params *p, void *hip_stream, sph_ctx **out) {
   if (!(p->box > 0) || p->morton_depth < 2 || p->morton_depth > 21 || p->split_count < 2 || p->top_cap < 2 ||
       p->top_cap > 8 || p->n_bins < 1 || p->n_bins > 63 || p->h_max_iter < 1 || !(p->eta > 0) ||
       !(p->gamma > 1.0) || p->cand_cap < 64 || p->list_cap < 64 || p->chunk_split < 0 || p->chunk_split > 2 ||
-      !(p->rebuild_frac >= 0.f && p->rebuild_frac <= 1.f) || p->sweep_below < 0 ||
+      !(p->rebuild_frac >= 0.f && p->rebuild_frac <= 1.f) || !(p->pair_slack >= 1.f && p->pair_slack <= 2.f) ||
+      p->sweep_below < 0 ||
       !(p->sweep_waves == 0 || p->sweep_waves == 1 || p->sweep_waves == 2 || p->sweep_waves == 4) ||
       !(p->waves_per_chunk == 0 || p->waves_per_chunk == 1 || p->waves_per_chunk == 2 || p->waves_per_chunk == 4 ||
         p->waves_per_chunk == 8))

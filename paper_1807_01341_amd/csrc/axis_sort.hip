@@ -1,7 +1,7 @@
 // Per-cell particle sorts for neighbour pruning (the "sort" task of Fig. 5):
 // for every leaf and each of the 13 directions of the half neighbour stencil,
-// the in-leaf order of the projections d = e . o of the FP32 offsets
-// (ascending, ties by in-leaf index).  One workgroup per leaf, all 13 axes,
+// the in-leaf order of the projections d = e . o of the FP32 offsets at the
+// last full build (ascending, ties by in-leaf index).  One workgroup per leaf, all 13 axes,
 // bitonic sorts of (key, index) in LDS.
 #include <math.h>
 
@@ -89,16 +89,12 @@ template <int P>
 __global__ __launch_bounds__(AS_THREADS) void axis_sort_kernel(const float4 *__restrict__ pos4,
                                                                const int32_t *__restrict__ leaf_begin,
                                                                const int32_t *__restrict__ leaf_count, int64_t nl,
-                                                               const int32_t *__restrict__ list,
-                                                               const int32_t *__restrict__ list_len, int64_t n,
-                                                               AxisSet ax, int min_count,
+                                                               int64_t n, AxisSet ax, int min_count,
                                                                uint16_t *__restrict__ order) {
   __shared__ float ox[P], oy[P], oz[P];
   __shared__ float key[P];
   __shared__ uint16_t idx[P];
-  const int64_t items = list ? (int64_t)*list_len : nl;
-  for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
-    const int l = list ? list[it] : (int)it;
+  for (int64_t l = blockIdx.x; l < nl; l += gridDim.x) {
     const int cnt = leaf_count[l];
     if (cnt < min_count || cnt > P) continue;
     sort_leaf_lds<P>(pos4, leaf_begin[l], cnt, n, ax, order, ox, oy, oz, key, idx);
@@ -193,22 +189,21 @@ __device__ __forceinline__ void sort_leaf_axes(const float4 *__restrict__ pos4, 
   }
 }
 
-// One wave per (leaf of at most 512 particles, axis), grid-stride: every
-// leaf, or the leaves of `list` (its length on the device).
+// One wave per (leaf of min_count..512 particles, axis), grid-stride over
+// every (leaf, axis).
 __global__ __launch_bounds__(256) void axis_sort_wave_kernel(const float4 *__restrict__ pos4,
                                                              const int32_t *__restrict__ leaf_begin,
                                                              const int32_t *__restrict__ leaf_count, int64_t nl,
-                                                             const int32_t *__restrict__ list,
-                                                             const int32_t *__restrict__ list_len, int64_t n,
-                                                             AxisSet ax, uint16_t *__restrict__ order) {
+                                                             int64_t n, AxisSet ax, int min_count,
+                                                             uint16_t *__restrict__ order) {
   const int lane = threadIdx.x & 63;
   // work item = (leaf, axis): the 13 sorts of a leaf run on 13 waves
-  const int64_t items = 13 * (list ? (int64_t)*list_len : nl);
+  const int64_t items = 13 * nl;
   for (int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); it < items; it += (int64_t)gridDim.x * 4) {
-    const int64_t li = it / 13;
-    const int a = (int)(it - 13 * li);
-    const int64_t l = list ? list[li] : li;
+    const int64_t l = it / 13;
+    const int a = (int)(it - 13 * l);
     const int cnt = leaf_count[l], b = leaf_begin[l];
+    if (cnt < min_count) continue;
     if (cnt <= 64)
       sort_leaf_axes<1>(pos4, b, cnt, n, ax, order, lane, a, a + 1);
     else if (cnt <= 128)
@@ -220,110 +215,52 @@ __global__ __launch_bounds__(256) void axis_sort_wave_kernel(const float4 *__res
   }
 }
 
-// Leaves of a cell-pair list not yet sorted: each is claimed once (its flag
-// set) and appended to the sort list of its size class.  Leaves of at most
-// 128 particles need no order: the loops read them whole.
-__global__ __launch_bounds__(256) void claim_partners_kernel(const PairEntry *__restrict__ pairs, int64_t np,
-                                                             const int32_t *__restrict__ leaf_count,
-                                                             int32_t *__restrict__ sorted, int32_t *__restrict__ list,
-                                                             int32_t *__restrict__ list_len,
-                                                             int32_t *__restrict__ big, int32_t *__restrict__ big_len) {
-  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < np; q += (int64_t)gridDim.x * 256) {
-    const int B = pairs[q].b;
-    if (sorted[B]) continue;
-    if (atomicExch(&sorted[B], 1) == 0) {
-      const int cnt = leaf_count[B];
-      if (cnt > 512)
-        big[atomicAdd(big_len, 1)] = B;
-      else if (cnt > 128)  // leaves of up to two 64-particle tiles are read whole, unsorted
-        list[atomicAdd(list_len, 1)] = B;
-    }
-  }
-}
-
-// The sorts are made lazily: sph_sort_cells prepares them, and a loop pass
-// sorts the leaves its cell pairs reach that no earlier pass of the step has
-// sorted (the paper likewise runs sort tasks only for active cells).
-sph_status sort_cells_impl(sph_ctx *ctx) {
+// Sorts the 13 axes of every leaf of at least min_count particles, by the
+// offsets of the full build.  Grids sized to the machine, not to the leaves.
+static sph_status sort_leaves(sph_ctx *ctx, int min_count) {
   const int64_t n = ctx->n, nl = ctx->n_leaves;
-  SPH_TRY(sph_ensure(ctx, ctx->axis_order, sizeof(uint16_t) * 13 * (size_t)n));
-  SPH_TRY(sph_ensure(ctx, ctx->leaf_sorted, sizeof(int32_t) * (size_t)(nl + 1)));
-  SPH_TRY(sph_ensure(ctx, ctx->sort_list, sizeof(int32_t) * (size_t)(nl + 2)));
-  if (!ctx->leaves_checked) {
-    // the leaf sizes of a new full build (kept by cell updates)
-    int32_t st[SC_NBIG - SC_MAXLEAF + 1];
-    SPH_TRY(read_scalars(ctx, SC_MAXLEAF, SC_NBIG - SC_MAXLEAF + 1, st));
-    const int32_t maxc = st[0];
-    if (maxc > 4096)
-      return sph_fail(ctx, SPH_EINVAL, "sort_cells: a leaf holds %d particles (max 4096 for the axis sorts)", maxc);
-    ctx->max_leaf = maxc;
-    ctx->n_big_leaves = st[SC_NBIG - SC_MAXLEAF];
-    ctx->leaves_checked = 1;
-  }
-  HIP_TRY(ctx, hipMemsetAsync(ctx->leaf_sorted.p, 0, sizeof(int32_t) * (size_t)nl, ctx->stream));
-  ctx->sorted_lists = 0;
-  ctx->state = 2;
-  return SPH_OK;
-}
-
-// Leaves of at most 512 particles from `small` (length *small_len on the
-// device, at most small_cap), larger ones from `big` (*big_len, at most
-// n_big_leaves); grids sized to the machine, not to the lists.
-static sph_status sort_leaves(sph_ctx *ctx, const int32_t *small, const int32_t *small_len, int64_t small_cap,
-                              const int32_t *big, const int32_t *big_len) {
-  const int64_t n = ctx->n, nl = ctx->n_leaves;
+  if (nl <= 0 || ctx->max_leaf < min_count) return SPH_OK;
   const AxisSet ax = make_axes();
-  const int64_t cap_small = std::min<int64_t>(small ? small_cap : nl, nl);
-  if (cap_small > 0) {
+  {
     PROF(ctx, "axis_sort");
-    const int64_t blocks = std::min<int64_t>(ceil_div(13 * cap_small, 4), (int64_t)ctx->n_cu * 8);
+    const int64_t blocks = std::min<int64_t>(ceil_div(13 * nl, 4), (int64_t)ctx->n_cu * 8);
     axis_sort_wave_kernel<<<(unsigned)blocks, 256, 0, ctx->stream>>>(
-        (const float4 *)ctx->pos4.p, (const int32_t *)ctx->leaf_begin.p, (const int32_t *)ctx->leaf_count.p, nl,
-        small, small_len, n, ax, (uint16_t *)ctx->axis_order.p);
+        (const float4 *)ctx->pos4_build.p, (const int32_t *)ctx->leaf_begin.p, (const int32_t *)ctx->leaf_count.p,
+        nl, n, ax, min_count, (uint16_t *)ctx->axis_order.p);
   }
   HIP_TRY(ctx, hipGetLastError());
-  const int64_t cap_big = small ? ctx->n_big_leaves : (ctx->max_leaf > 512 ? nl : 0);
-  if (cap_big > 0) {
+  if (ctx->max_leaf > 512) {
     PROF(ctx, "axis_sort");
-    const int64_t blocks = std::min<int64_t>(cap_big, (int64_t)ctx->n_cu * 2);
+    const int64_t blocks = std::min<int64_t>(nl, (int64_t)ctx->n_cu * 2);
     axis_sort_kernel<4096><<<(unsigned)blocks, AS_THREADS, 0, ctx->stream>>>(
-        (const float4 *)ctx->pos4.p, (const int32_t *)ctx->leaf_begin.p, (const int32_t *)ctx->leaf_count.p, nl,
-        small ? big : nullptr, big_len, n, ax, 513, (uint16_t *)ctx->axis_order.p);
+        (const float4 *)ctx->pos4_build.p, (const int32_t *)ctx->leaf_begin.p, (const int32_t *)ctx->leaf_count.p,
+        nl, n, ax, std::max(513, min_count), (uint16_t *)ctx->axis_order.p);
     HIP_TRY(ctx, hipGetLastError());
   }
   return SPH_OK;
 }
 
-// Sorts the partner leaves of cell-pair list `which` (0 density, 1 force)
-// not sorted yet in this step.  No synchronisation: the lists' lengths stay
-// on the device.
-sph_status sort_partners(sph_ctx *ctx, int which) {
-  const int bit = 1 << which;
-  if (ctx->sorted_lists & bit) return SPH_OK;
-  const int64_t np = which == 0 ? ctx->n_dpairs : ctx->n_fpairs;
-  const PairEntry *pairs = (const PairEntry *)(which == 0 ? ctx->dpairs.p : ctx->fpairs.p);
-  ctx->sorted_lists |= bit;
-  if (np <= 0) return SPH_OK;
-  const int64_t nl = ctx->n_leaves;
-  SPH_TRY(sph_ensure(ctx, ctx->sort_big, sizeof(int32_t) * (size_t)(ctx->n_big_leaves + 1)));
-  int32_t *len = (int32_t *)ctx->sort_list.p + nl;  // [small length, big length]
-  HIP_TRY(ctx, hipMemsetAsync(len, 0, 2 * sizeof(int32_t), ctx->stream));
-  {
-    PROF(ctx, "axis_sort");
-    claim_partners_kernel<<<(unsigned)std::min<int64_t>(ceil_div(np, 256), 4096), 256, 0, ctx->stream>>>(
-        pairs, np, (const int32_t *)ctx->leaf_count.p, (int32_t *)ctx->leaf_sorted.p, (int32_t *)ctx->sort_list.p,
-        len, (int32_t *)ctx->sort_big.p, len + 1);
+// After a full build: every leaf of more than two 64-particle tiles is
+// sorted at once (the loops read smaller leaves whole, unsorted).  The keys
+// are the offsets of the full build, so cell updates keep the orders.  Where
+// the paper runs sort tasks only for the active cells of a step, one launch
+// over all leaves here costs less than the per-step launches that finding
+// the newly reached leaves would take.
+sph_status sort_cells_impl(sph_ctx *ctx) {
+  const int64_t n = ctx->n;
+  SPH_TRY(sph_ensure(ctx, ctx->axis_order, sizeof(uint16_t) * 13 * (size_t)n));
+  if (!ctx->leaves_checked) {
+    int32_t maxc;
+    SPH_TRY(read_scalars(ctx, SC_MAXLEAF, 1, &maxc));
+    if (maxc > 4096)
+      return sph_fail(ctx, SPH_EINVAL, "sort_cells: a leaf holds %d particles (max 4096 for the axis sorts)", maxc);
+    ctx->max_leaf = maxc;
+    SPH_TRY(sort_leaves(ctx, 129));
+    ctx->leaves_checked = 1;
   }
-  HIP_TRY(ctx, hipGetLastError());
-  return sort_leaves(ctx, (const int32_t *)ctx->sort_list.p, len, std::min<int64_t>(np, nl),
-                     (const int32_t *)ctx->sort_big.p, len + 1);
-}
-
-// Every leaf (for the introspection copy).
-sph_status sort_all_leaves(sph_ctx *ctx) {
-  SPH_TRY(sort_leaves(ctx, nullptr, nullptr, 0, nullptr, nullptr));
-  if (ctx->n_leaves > 0)
-    HIP_TRY(ctx, hipMemsetAsync(ctx->leaf_sorted.p, 0x01, sizeof(int32_t) * (size_t)ctx->n_leaves, ctx->stream));
-  ctx->sorted_lists = 3;
+  ctx->state = 2;
   return SPH_OK;
 }
+
+// Every leaf, also those the loops read unsorted (for the introspection copy).
+sph_status sort_all_leaves(sph_ctx *ctx) { return sort_leaves(ctx, 1); }

@@ -202,21 +202,15 @@ __global__ __launch_bounds__(BT) void leaf_table_kernel(const int32_t *__restric
 }
 
 __global__ __launch_bounds__(BT) void leaf_count_kernel(const int32_t *__restrict__ begin, int32_t *__restrict__ count,
-                                                        int64_t nl, int64_t n, int32_t *__restrict__ max_count,
-                                                        int32_t *__restrict__ n_big) {
-  int mc = 0, nb = 0;
+                                                        int64_t nl, int64_t n, int32_t *__restrict__ max_count) {
+  int mc = 0;
   for (int64_t l = (int64_t)blockIdx.x * BT + threadIdx.x; l < nl; l += (int64_t)gridDim.x * BT) {
     const int c = (int32_t)(((l + 1 < nl) ? begin[l + 1] : n) - begin[l]);
     count[l] = c;
     mc = max(mc, c);
-    nb += c > 512;
   }
   mc = wave_max_i(mc);
-  nb = wave_sum_i(nb);
-  if ((threadIdx.x & 63) == 0) {
-    atomicMax(max_count, mc);
-    if (nb) atomicAdd(n_big, nb);
-  }
+  if ((threadIdx.x & 63) == 0) atomicMax(max_count, mc);
 }
 
 // FP32 offsets from the leaf centre, H, and the leaf's max H: one wave per
@@ -460,7 +454,6 @@ sph_status build_cells_impl(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *
   int k0 = 2;
   while (k0 < ctx->prm.top_cap && k0 < D && ldexp(L, -(k0 + 1)) >= (double)hmax) ++k0;
   ctx->top_level = k0;
-  ctx->hmax_global = hmax;
 
   const uint64_t *keys = (const uint64_t *)ctx->keys_a.p;
   SPH_TRY(sph_ensure(ctx, ctx->flags, 4 * n));
@@ -524,7 +517,7 @@ sph_status build_cells_impl(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *
   }
   {
     PROF(ctx, "leaf_build");
-    leaf_count_kernel<<<grid_for(nl), BT, 0, ctx->stream>>>(lb, lc, nl, n, sc + SC_MAXLEAF, sc + SC_NBIG);
+    leaf_count_kernel<<<grid_for(nl), BT, 0, ctx->stream>>>(lb, lc, nl, n, sc + SC_MAXLEAF);
   }
   HIP_TRY(ctx, hipGetLastError());
   {
@@ -558,6 +551,9 @@ sph_status build_cells_impl(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *
     HIP_TRY(ctx, hipMemcpyAsync(xb + 2 * n, p->z, 8 * n, hipMemcpyDeviceToDevice, ctx->stream));
     HIP_TRY(ctx, hipMemsetAsync(ctx->leaf_dx.p, 0, 4 * (size_t)nl, ctx->stream));
   }
+  // the axis sorts order these offsets until the next full build
+  SPH_TRY(sph_ensure(ctx, ctx->pos4_build, 16 * (size_t)n));
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->pos4_build.p, ctx->pos4.p, 16 * (size_t)n, hipMemcpyDeviceToDevice, ctx->stream));
   ctx->dx_max = 0.f;
   ctx->built_n = n;
   ctx->n_full_builds++;
@@ -599,7 +595,9 @@ sph_status update_cells(sph_ctx *ctx, sph_particles *p, int64_t *perm_out, int *
     return SPH_OK;
   }
   *rebuild = 0;
-  ctx->hmax_global = hmax;
+  // the running global max H starts from the kept cells' max H
+  HIP_TRY(ctx, hipMemcpyAsync(sc + SC_HMAX_BITS, sc + SC_UPD_HMAX, sizeof(int32_t), hipMemcpyDeviceToDevice,
+                              ctx->stream));
   ctx->dx_max = dxm;
   ctx->n_updates++;
   if (perm_out) {

@@ -277,7 +277,6 @@ namespace {
 
 template <int MODE, bool COMP>
 sph_status launch_loop(sph_ctx *ctx, const LoopArgs &a0) {
-  SPH_TRY(sort_partners(ctx, MODE == 0 ? 0 : 1));
   const LoopConfig cfg = choose_config(ctx, MODE);
   LoopArgs a = a0;
   SPH_TRY(apply_config(ctx, cfg, a));
@@ -554,12 +553,15 @@ __device__ __forceinline__ void density_term(const float4 &pi, const float4 &vi,
 
 // NWP waves share one particle: wave s of it takes the flat candidates
 // s*64 + NWP*64*t and every NWP-th large partner; the waves' sums are added
-// in wave order.
+// in wave order.  The neighbours a wave finds are queued in LDS and their
+// pair terms evaluated 64 at a time, one per lane, so that the terms run on
+// full waves although few of the candidates tested together are neighbours.
 template <int NWP>
 __global__ __launch_bounds__(256) void density_sweep_kernel(LoopArgs g, const int32_t *__restrict__ todo,
                                                             const int32_t *__restrict__ n_todo_dev, int64_t n_todo,
                                                             const int32_t *__restrict__ chunk_of) {
   __shared__ SweepPair sp[4][64];
+  __shared__ float4 hq[4][128];  // per wave: queued neighbours (dx, dy, dz, j)
   __shared__ float red[4][9];
   const int wave = threadIdx.x >> 6;
   const int sub = wave % NWP;
@@ -579,6 +581,35 @@ __global__ __launch_bounds__(256) void density_sweep_kernel(LoopArgs g, const in
 #pragma unroll
   for (int q = 0; q < 8; ++q) acc[q] = 0.f;
   int cnt = 0;
+  float4 *Q = hq[wave];
+  int qn = 0;  // queue length (wave-uniform)
+  auto drain = [&](int m) {
+    if (lane < m) {
+      const float4 e = Q[lane];
+      const int j = __float_as_int(e.w);
+      const float r2 = fmaf(e.z, e.z, fmaf(e.y, e.y, e.x * e.x));
+      density_term(pi, vi, invHi, e.x, e.y, e.z, r2, g.jvm[j], acc);
+      cnt += (j != i);
+    }
+  };
+  // queue the lanes' hits; a full wave of them is evaluated at once
+  auto push = [&](bool hit, float dx, float dy, float dz, int j) {
+    const uint64_t m = __ballot(hit);
+    if (m == 0ull) return;
+    if (hit) Q[qn + rank_below(m)] = make_float4(dx, dy, dz, __int_as_float(j));
+    qn += __popcll(m);
+    if (qn >= 64) {
+      wave_sync();
+      drain(64);
+      const int rest = qn - 64;
+      float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (lane < rest) t = Q[64 + lane];
+      wave_sync();
+      if (lane < rest) Q[lane] = t;
+      wave_sync();
+      qn = rest;
+    }
+  };
   for (int p0 = pbeg; p0 < pend; p0 += 64) {
     const int p = p0 + lane;
     PairEntry e;
@@ -610,6 +641,9 @@ __global__ __launch_bounds__(256) void density_sweep_kernel(LoopArgs g, const in
     wave_sync();
     for (int t = sub * 64; t < total; t += NWP * 64) {
       const int f = t + lane;
+      bool hit = false;
+      float dx = 0.f, dy = 0.f, dz = 0.f;
+      int j = 0;
       if (f < total) {
         // last pair whose range starts at or before f
         int lo = 0, hi = 63;
@@ -618,15 +652,14 @@ __global__ __launch_bounds__(256) void density_sweep_kernel(LoopArgs g, const in
           if (my[mid].off <= f) lo = mid; else hi = mid - 1;
         }
         const SweepPair q = my[lo];
-        const int j = q.bb + (f - q.off);
+        j = q.bb + (f - q.off);
         const float4 pj = g.pos4[j];
-        const float dx = pi.x - (pj.x + q.sx), dy = pi.y - (pj.y + q.sy), dz = pi.z - (pj.z + q.sz);
-        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        if (r2 < H2i) {
-          density_term(pi, vi, invHi, dx, dy, dz, r2, g.jvm[j], acc);
-          cnt += (j != i);
-        }
+        dx = pi.x - (pj.x + q.sx);
+        dy = pi.y - (pj.y + q.sy);
+        dz = pi.z - (pj.z + q.sz);
+        hit = fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < H2i;
       }
+      push(hit, dx, dy, dz, j);
     }
     // large partners, one after the other: sorted sweep
     uint64_t bigm = __ballot(big);
@@ -635,7 +668,7 @@ __global__ __launch_bounds__(256) void density_sweep_kernel(LoopArgs g, const in
       const int src = __ffsll((unsigned long long)bigm) - 1;
       bigm &= bigm - 1;
       if ((nb++ % NWP) != sub) continue;
-      const int bbq = __shfl(bb, src, 64), bcq = __shfl(bc, src, 64);
+      const int bbq = __shfl(bb, src, 64), bcq = __shfl(bc, src, 64), Bq = __shfl(e.b, src, 64);
       const float sx = __shfl(e.sx, src, 64), sy = __shfl(e.sy, src, 64), sz = __shfl(e.sz, src, 64);
       int axis = 0;
       float best = -1.f, sgn = 1.f;
@@ -651,7 +684,8 @@ __global__ __launch_bounds__(256) void density_sweep_kernel(LoopArgs g, const in
       const float ex = g.ax.e[axis][0], ey = g.ax.e[axis][1], ez = g.ax.e[axis][2];
       const float pp = fmaf(pi.z, ez, fmaf(pi.y, ey, pi.x * ex));
       const float sproj = fmaf(sz, ez, fmaf(sy, ey, sx * ex));
-      const float margin = 1.0001f * Hi + 1e-6f * (2.f * fabsf(pp) + fabsf(sproj));
+      // orders are by the offsets of the full build (see the chunk loop)
+      const float margin = 1.0001f * Hi + 2.0001f * g.leaf_dx[Bq] + 1e-6f * (2.f * fabsf(pp) + fabsf(sproj));
       const float lo_b = pp - margin - sproj, hi_b = pp + margin - sproj;
       const uint16_t *ord = g.axis_order + (int64_t)axis * g.n + bbq;
       for (int t = 0; t < bcq; t += 64) {
@@ -664,13 +698,12 @@ __global__ __launch_bounds__(256) void density_sweep_kernel(LoopArgs g, const in
         if (__ballot(valid && !beyond) == 0ull) break;
         const float dx = pi.x - (pj.x + sx), dy = pi.y - (pj.y + sy), dz = pi.z - (pj.z + sz);
         const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        if (valid && r2 < H2i) {
-          density_term(pi, vi, invHi, dx, dy, dz, r2, g.jvm[j], acc);
-          cnt += (j != i);
-        }
+        push(valid && r2 < H2i, dx, dy, dz, j);
       }
     }
   }
+  wave_sync();
+  drain(qn);
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     float v = acc[q];
@@ -716,7 +749,9 @@ __global__ __launch_bounds__(256) void density_sweep_kernel(LoopArgs g, const in
 // leaves of at most 128 particles and the own leaf as one flat candidate
 // range, larger ones swept in their axis order up to max(H_i, that leaf's max
 // H).  Same predicate (j != i, r < max(H_i, H_j)), pair terms and outputs as
-// the chunk loop; lane sums reduced in a fixed butterfly, v_sig by max.
+// the chunk loop; neighbours queued in LDS and evaluated a full wave at a
+// time (as in the density sweep); lane sums reduced in a fixed butterfly,
+// v_sig by max.
 struct ForceAcc {
   float ax, ay, az, visc, adiab, vmax;
 };
@@ -751,6 +786,8 @@ __device__ __forceinline__ void force_term(const float4 &vi, const float4 &thi, 
 template <int NWP>
 __global__ __launch_bounds__(256) void force_sweep_kernel(LoopArgs g, const int32_t *__restrict__ chunk_of) {
   __shared__ SweepPair sp[4][64];
+  __shared__ float4 hq[4][128];  // per wave: queued neighbours (dx, dy, dz, j) and their H
+  __shared__ float hqH[4][128];
   __shared__ int blk_cnt[4];
   __shared__ float red[4][7];
   const int wave = threadIdx.x >> 6;
@@ -768,13 +805,56 @@ __global__ __launch_bounds__(256) void force_sweep_kernel(LoopArgs g, const int3
     const Chunk ch = g.chunks[chunk_of[k]];
     const int pbeg = g.pair_off[ch.act_leaf], pend = g.pair_off[ch.act_leaf + 1];
     ForceAcc f = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    auto visit = [&](int j, float sx, float sy, float sz) {
-      const float4 pj = g.pos4[j];
-      const float dx = pi.x - (pj.x + sx), dy = pi.y - (pj.y + sy), dz = pi.z - (pj.z + sz);
-      const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-      if ((r2 < H2i || r2 < pj.w * pj.w) && j != i) {
-        force_term(vi, thi, invHi, g.half_alpha, dx, dy, dz, r2, pj.w, g.jvm[j], g.jth[j], f);
+    float4 *Q = hq[wave];
+    float *QH = hqH[wave];
+    int qn = 0;  // queue length (wave-uniform)
+    auto drain = [&](int m) {
+      if (lane < m) {
+        const float4 e = Q[lane];
+        const int j = __float_as_int(e.w);
+        const float r2 = fmaf(e.z, e.z, fmaf(e.y, e.y, e.x * e.x));
+        force_term(vi, thi, invHi, g.half_alpha, e.x, e.y, e.z, r2, QH[lane], g.jvm[j], g.jth[j], f);
         ++cnt;
+      }
+    };
+    // tests candidate j (valid lanes) and queues it if it is a neighbour
+    auto visit = [&](bool valid, int j, float sx, float sy, float sz) {
+      bool hit = false;
+      float dx = 0.f, dy = 0.f, dz = 0.f, Hj = 0.f;
+      if (valid) {
+        const float4 pj = g.pos4[j];
+        dx = pi.x - (pj.x + sx);
+        dy = pi.y - (pj.y + sy);
+        dz = pi.z - (pj.z + sz);
+        Hj = pj.w;
+        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        hit = (r2 < H2i || r2 < Hj * Hj) && j != i;
+      }
+      const uint64_t m = __ballot(hit);
+      if (m == 0ull) return;
+      if (hit) {
+        const int s = qn + rank_below(m);
+        Q[s] = make_float4(dx, dy, dz, __int_as_float(j));
+        QH[s] = Hj;
+      }
+      qn += __popcll(m);
+      if (qn >= 64) {
+        wave_sync();
+        drain(64);
+        const int rest = qn - 64;
+        float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
+        float th = 0.f;
+        if (lane < rest) {
+          t = Q[64 + lane];
+          th = QH[64 + lane];
+        }
+        wave_sync();
+        if (lane < rest) {
+          Q[lane] = t;
+          QH[lane] = th;
+        }
+        wave_sync();
+        qn = rest;
       }
     };
     for (int p0 = pbeg; p0 < pend; p0 += 64) {
@@ -807,15 +887,16 @@ __global__ __launch_bounds__(256) void force_sweep_kernel(LoopArgs g, const int3
       wave_sync();
       for (int t = sub * 64; t < total; t += NWP * 64) {
         const int fi = t + lane;
+        SweepPair q = {0, 0, 0.f, 0.f, 0.f};
         if (fi < total) {
           int lo = 0, hi = 63;
           while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (my[mid].off <= fi) lo = mid; else hi = mid - 1;
           }
-          const SweepPair q = my[lo];
-          visit(q.bb + (fi - q.off), q.sx, q.sy, q.sz);
+          q = my[lo];
         }
+        visit(fi < total, q.bb + (fi - q.off), q.sx, q.sy, q.sz);
       }
       uint64_t bigm = __ballot(big);
       int nb = 0;
@@ -840,7 +921,7 @@ __global__ __launch_bounds__(256) void force_sweep_kernel(LoopArgs g, const int3
         const float Rb = fmaxf(Hi, g.leaf_hmax[Bq]);
         const float pp = fmaf(pi.z, ez, fmaf(pi.y, ey, pi.x * ex));
         const float sproj = fmaf(sz, ez, fmaf(sy, ey, sx * ex));
-        const float margin = 1.0001f * Rb + 1e-6f * (2.f * fabsf(pp) + fabsf(sproj));
+        const float margin = 1.0001f * Rb + 2.0001f * g.leaf_dx[Bq] + 1e-6f * (2.f * fabsf(pp) + fabsf(sproj));
         const float lo_b = pp - margin - sproj, hi_b = pp + margin - sproj;
         const uint16_t *ord = g.axis_order + (int64_t)axis * g.n + bbq;
         for (int t = 0; t < bcq; t += 64) {
@@ -851,10 +932,12 @@ __global__ __launch_bounds__(256) void force_sweep_kernel(LoopArgs g, const int3
           const float key = fmaf(pj.z, ez, fmaf(pj.y, ey, pj.x * ex));
           const bool beyond = sgn > 0.f ? key > hi_b : key < lo_b;
           if (__ballot(valid && !beyond) == 0ull) break;
-          if (valid) visit(j, sx, sy, sz);
+          visit(valid, j, sx, sy, sz);
         }
       }
     }
+    wave_sync();
+    drain(qn);
     float v[5] = {f.ax, f.ay, f.az, f.visc, f.adiab};
 #pragma unroll
     for (int q = 0; q < 5; ++q)
@@ -1010,9 +1093,9 @@ GhostArgs density_ghost_args(sph_ctx *ctx, sph_particles *p, int it, int entropy
 // Book-keeping after Newton pass `it` with the ghost's counters st: returns
 // SPH_OK with *done = 1 when the solve is over; widens the pair lists when a
 // smoothing length outgrew them.
-// Passes are grouped like the single-box path's batches (passes 1-2, 3-4,
-// ...): widening happens only at the end of a group.
-static inline bool group_end(int it) { return (it % 2) == 0; }
+// Passes are grouped like the single-box path's batches (passes 1-4, then
+// 5-6, 7-8, ...): widening happens only at the end of a group.
+static inline bool group_end(int it) { return it == 4 || (it > 4 && (it % 2) == 0); }
 
 sph_status density_after_pass(sph_ctx *ctx, int it, const int32_t st[2], int *done) {
   *done = 0;
@@ -1034,7 +1117,7 @@ sph_status density_after_pass(sph_ctx *ctx, int it, const int32_t st[2], int *do
     // then the waiting particles go on
     ctx->widen_pending = 0;
     ctx->pair_rebuilds++;
-    SPH_TRY(refresh_leaf_hmax(ctx, false));
+    SPH_TRY(refresh_leaf_hmax(ctx));
     SPH_TRY(build_pairs(ctx, 0, 1.5f));
     release_waiting_kernel<<<grid256(ctx->n_active), 256, 0, ctx->stream>>>(
         (uint8_t *)ctx->conv.p, (const int32_t *)ctx->chunk_of.p, ctx->n_active, (int32_t *)ctx->chunk_todo.p);
@@ -1045,8 +1128,8 @@ sph_status density_after_pass(sph_ctx *ctx, int it, const int32_t st[2], int *do
 
 // Leaf max H follows the new smoothing lengths, so that any later cell-pair
 // list (the force list, or a later active set without a rebuild) sees them.
-sph_status density_end(sph_ctx *ctx, bool read_global) {
-  SPH_TRY(refresh_leaf_hmax(ctx, read_global));
+sph_status density_end(sph_ctx *ctx) {
+  SPH_TRY(refresh_leaf_hmax(ctx));
   ctx->state = 4;
   if (ctx->n_unconverged > 0)
     return sph_fail(ctx, SPH_ENOCONV, "density_pass: %lld particles not converged after %d iterations",
@@ -1054,10 +1137,10 @@ sph_status density_end(sph_ctx *ctx, bool read_global) {
   return SPH_OK;
 }
 
-// Newton passes are enqueued in pairs without waiting for the host: each
-// pass's loop runs over what the previous ghost left to do, read on the
-// device, and a pass past convergence does nothing.  One synchronisation per
-// pair of passes reads both passes' counters.
+// Newton passes are enqueued in groups without waiting for the host (four,
+// then pairs): each pass's loop runs over what the previous ghost left to
+// do, read on the device, and a pass past convergence does nothing.  One
+// synchronisation per group reads its passes' counters.
 sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u) {
   int any;
   SPH_TRY(density_begin(ctx, p, entropy_from_u, &any));
@@ -1071,13 +1154,12 @@ sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u)
   int64_t n_todo = na;  // upper bound of the particles left to do
   int it = 0, done = 0;
   while (!done) {
-    const int first = it + 1, last = std::min(it + 2, maxit);
+    const int first = it + 1, last = std::min(it == 0 ? 4 : it + 2, maxit);
     HIP_TRY(ctx, hipMemsetAsync(stats + 2 * first, 0, sizeof(int32_t) * 2 * (last - first + 1), ctx->stream));
     for (int pass = first; pass <= last; ++pass) {
       LoopArgs a = density_loop_args(ctx);
       if (n_todo < ctx->prm.sweep_below) {
         // few particles to do: one wave per particle
-        SPH_TRY(sort_partners(ctx, 0));
         if (pass > 1) {
           HIP_TRY(ctx, hipMemsetAsync(list + na, 0, 4, ctx->stream));
           PROF(ctx, "density_todo");
@@ -1123,7 +1205,7 @@ sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u)
     }
     it = last;
   }
-  return density_end(ctx, true);
+  return density_end(ctx);
 }
 
 // Force loop arguments with the outputs of p.
@@ -1157,7 +1239,6 @@ sph_status force_pass_impl(sph_ctx *ctx, sph_particles *p) {
   HIP_TRY(ctx, hipGetLastError());
   LoopArgs a = force_loop_args(ctx, p);
   if (ctx->n_active < ctx->prm.sweep_below) {
-    SPH_TRY(sort_partners(ctx, 1));
     {
       PROF(ctx, "force_loop");
       const int nwp = sweep_waves(ctx, ctx->n_active);
@@ -1574,7 +1655,6 @@ sph_status batch_density_impl(sph_ctx **cs, sph_particles *ps, int nb, int entro
   for (int it = 1; it <= maxit && !iterating.empty(); ++it) {
     // loop over every live box's chunks (finished boxes have no chunk to do)
     for (int q = 0; q < nl; ++q) {
-      BATCH_TRY(live[q], sort_partners(cs[live[q]], 0));
       s.args[q] = density_loop_args(cs[live[q]]);
       batch_split_args(cs[live[q]], target, s.args[q]);
     }
@@ -1613,22 +1693,11 @@ sph_status batch_density_impl(sph_ctx **cs, sph_particles *ps, int nb, int entro
     }
     iterating.swap(next);
   }
-  // leaf max H per box, then one read-back of every box's running global max H
-  std::vector<int32_t> hb(nl);
-  for (int q = 0; q < nl; ++q) {
-    sph_ctx *c = cs[live[q]];
-    BATCH_TRY(live[q], refresh_leaf_hmax(c, false));
-    HIP_TRY(lead, hipMemcpyAsync(&hb[q], (int32_t *)c->scalars.p + SC_HMAX_BITS, 4, hipMemcpyDeviceToHost,
-                                 lead->stream));
-  }
-  HIP_TRY(lead, hipStreamSynchronize(lead->stream));
+  // leaf max H per box (and its running global max, on the device)
   sph_status first = SPH_OK;
   for (int q = 0; q < nl; ++q) {
     sph_ctx *c = cs[live[q]];
-    float hg;
-    memcpy(&hg, &hb[q], 4);
-    c->hmax_global = hg;
-    const sph_status e = density_end(c, false);
+    const sph_status e = density_end(c);
     if (e != SPH_OK && first == SPH_OK) first = batch_fail(lead, live[q], c, e);
   }
   return first;
@@ -1666,7 +1735,6 @@ sph_status batch_force_impl(sph_ctx **cs, sph_particles *ps, int nb) {
   SPH_TRY(batch_work_list(lead, cs, live, s, 1, target, &total));
   SPH_TRY(sph_ensure(lead, lead->batch_args, sizeof(LoopArgs) * (size_t)nl));
   for (int q = 0; q < nl; ++q) {
-    BATCH_TRY(live[q], sort_partners(cs[live[q]], 1));
     s.args[q] = force_loop_args(cs[live[q]], &ps[live[q]]);
     batch_split_args(cs[live[q]], target, s.args[q]);
   }

@@ -491,7 +491,10 @@ __device__ __forceinline__ void chunk_body(const LoopArgs &g, int code, bool cod
     const float pmin = fminf(ex * bminx, ex * bmaxx) + fminf(ey * bminy, ey * bmaxy) + fminf(ez * bminz, ez * bmaxz);
     const float pmax = fmaxf(ex * bminx, ex * bmaxx) + fmaxf(ey * bminy, ey * bmaxy) + fmaxf(ez * bminz, ez * bmaxz);
     const float sproj = fmaf(e.sz, ez, fmaf(e.sy, ey, e.sx * ex));
-    const float margin = 1.0001f * Rb + 1e-6f * (fabsf(pmin) + fabsf(pmax) + fabsf(sproj));
+    // the order is by the offsets of the full build: a projection is at most
+    // the leaf's drift margin from its sorted place, so the stop waits for
+    // keys twice that margin past the reach
+    const float margin = 1.0001f * Rb + 2.0001f * g.leaf_dx[B] + 1e-6f * (fabsf(pmin) + fabsf(pmax) + fabsf(sproj));
     const float lo_b = pmin - margin - sproj, hi_b = pmax + margin - sproj;
     const uint16_t *ord = g.axis_order + (int64_t)axis * g.n + bb;
     for (int t = 0; t < bc; t += 64) {

@@ -118,7 +118,8 @@ __global__ __launch_bounds__(MT) void pairs_kernel(int mode, float slack, PairGe
                                                    const int32_t *__restrict__ iy, const int32_t *__restrict__ iz,
                                                    const float *__restrict__ leaf_hmax,
                                                    const int32_t *__restrict__ top_first,
-                                                   const int32_t *__restrict__ top_last, float hmax_global,
+                                                   const int32_t *__restrict__ top_last,
+                                                   const int32_t *__restrict__ hmax_bits,
                                                    const float *__restrict__ leaf_dx, float dx_max,
                                                    int32_t *__restrict__ counts, const int32_t *__restrict__ offs,
                                                    PairEntry *__restrict__ out, const int32_t *__restrict__ leaf_count,
@@ -135,6 +136,9 @@ __global__ __launch_bounds__(MT) void pairs_kernel(int mode, float slack, PairGe
   // particles may have drifted out of their leaves since the cells were
   // built: leaf_dx widens every test by both leaves' displacement bounds
   const float dxA = leaf_dx[A];
+  // the running max H over all particles (device scalar, raised by every
+  // refresh of the leaf max H)
+  const float hmax_global = __int_as_float(*hmax_bits);
   const float Rreach = (mode == 0 ? RA : fmaxf(RA, hmax_global)) + dxA + dx_max;
   const int ntop = 1 << g.k0;
   const double rr = ceil((double)Rreach / g.wtop);
@@ -305,8 +309,8 @@ sph_status build_pairs_count(sph_ctx *ctx, int which, float slack, int32_t *host
         which, slack, g, na, (const int32_t *)ctx->act_leaves.p, (const float *)ctx->act_hmax.p,
         (const int32_t *)ctx->leaf_level.p, (const int32_t *)ctx->leaf_ix.p, (const int32_t *)ctx->leaf_iy.p,
         (const int32_t *)ctx->leaf_iz.p, (const float *)ctx->leaf_hmax.p, (const int32_t *)ctx->top_first.p,
-        (const int32_t *)ctx->top_last.p, ctx->hmax_global, (const float *)ctx->leaf_dx.p, ctx->dx_max,
-        (int32_t *)ctx->pair_cnt.p, nullptr, nullptr, nullptr, nullptr);
+        (const int32_t *)ctx->top_last.p, (const int32_t *)ctx->scalars.p + SC_HMAX_BITS,
+        (const float *)ctx->leaf_dx.p, ctx->dx_max, (int32_t *)ctx->pair_cnt.p, nullptr, nullptr, nullptr, nullptr);
   }
   HIP_TRY(ctx, hipGetLastError());
   int32_t *o = (int32_t *)off.p;
@@ -320,7 +324,6 @@ sph_status build_pairs_fill(sph_ctx *ctx, int which, float slack, int32_t np) {
   DevBuf &off = which == 0 ? ctx->dpair_off : ctx->fpair_off;
   DevBuf &lst = which == 0 ? ctx->dpairs : ctx->fpairs;
   if (which == 0) ctx->n_dpairs = np; else ctx->n_fpairs = np;
-  ctx->sorted_lists &= ~(1 << which);  // new partners may need their axis sorts
   if (na == 0) return SPH_OK;
   SPH_TRY(sph_ensure(ctx, lst, sizeof(PairEntry) * (size_t)(np > 0 ? np : 1)));
   const PairGeom g = pair_geom(ctx);
@@ -330,7 +333,8 @@ sph_status build_pairs_fill(sph_ctx *ctx, int which, float slack, int32_t np) {
         which, slack, g, na, (const int32_t *)ctx->act_leaves.p, (const float *)ctx->act_hmax.p,
         (const int32_t *)ctx->leaf_level.p, (const int32_t *)ctx->leaf_ix.p, (const int32_t *)ctx->leaf_iy.p,
         (const int32_t *)ctx->leaf_iz.p, (const float *)ctx->leaf_hmax.p, (const int32_t *)ctx->top_first.p,
-        (const int32_t *)ctx->top_last.p, ctx->hmax_global, (const float *)ctx->leaf_dx.p, ctx->dx_max, nullptr,
+        (const int32_t *)ctx->top_last.p, (const int32_t *)ctx->scalars.p + SC_HMAX_BITS,
+        (const float *)ctx->leaf_dx.p, ctx->dx_max, nullptr,
         (int32_t *)off.p, (PairEntry *)lst.p, (const int32_t *)ctx->leaf_count.p,
         which == 0 ? (int32_t *)ctx->act_cost.p : nullptr);
   }
@@ -346,18 +350,12 @@ sph_status build_pairs(sph_ctx *ctx, int which, float slack) {
 }
 
 // Refreshes the max H of every active leaf (all particles, and active ones)
-// from the current smoothing lengths; with read_global the running global
-// max H is read back for the pair-search reach (synchronises).
-sph_status refresh_leaf_hmax(sph_ctx *ctx, bool read_global) {
+// from the current smoothing lengths, and raises the running global max H on
+// the device (the force pair search reads it there).  No synchronisation.
+sph_status refresh_leaf_hmax(sph_ctx *ctx) {
   const int64_t na = ctx->n_active_leaves;
   if (na == 0) return SPH_OK;
   int32_t *sc = (int32_t *)ctx->scalars.p;
-  int32_t hb;
-  {
-    float hg = ctx->hmax_global;
-    memcpy(&hb, &hg, 4);
-  }
-  HIP_TRY(ctx, hipMemcpyAsync(sc + SC_HMAX_BITS, &hb, 4, hipMemcpyHostToDevice, ctx->stream));
   {
     PROF(ctx, "cell_pairs");
     leaf_hmax_refresh_kernel<<<waves_grid(na), MT, 0, ctx->stream>>>(
@@ -366,11 +364,6 @@ sph_status refresh_leaf_hmax(sph_ctx *ctx, bool read_global) {
         (float *)ctx->act_hmax.p, sc + SC_HMAX_BITS);
   }
   HIP_TRY(ctx, hipGetLastError());
-  if (!read_global) return SPH_OK;
-  SPH_TRY(read_scalars(ctx, SC_HMAX_BITS, 1, &hb));
-  float hg;
-  memcpy(&hg, &hb, 4);
-  ctx->hmax_global = hg;
   return SPH_OK;
 }
 
@@ -428,7 +421,7 @@ sph_status mark_active_impl(sph_ctx *ctx, const sph_particles *p, int m, int64_t
   // new chunks: the loop work items are rebuilt at the next launch (they keep
   // the costs of these lists through the pass, also if the lists are widened)
   ctx->work_valid = 0;
-  SPH_TRY(build_pairs(ctx, 0, 1.0f));
+  SPH_TRY(build_pairs(ctx, 0, ctx->prm.pair_slack));
   if (n_active_host) *n_active_host = ctx->n_active;
   ctx->state = 3;
   return SPH_OK;

@@ -62,7 +62,6 @@ struct sph_ctx {
   int32_t unconv_hist[32] = {0};
   int32_t pair_rebuilds = 0;
   float dpair_slack = 1.f;  // reach factor of the current density pair lists
-  float hmax_global = 0.f;  // max H over all particles (monotone between builds)
   // cells kept between builds: positions of the last full build, per-leaf and
   // largest displacement since then (the cell-pair search margin)
   DevBuf x_build, leaf_dx, leaf_half;
@@ -77,13 +76,11 @@ struct sph_ctx {
   DevBuf leaf_level, leaf_ix, leaf_iy, leaf_iz, leaf_begin, leaf_count, leaf_hmax, leaf_of;
   DevBuf top_first, top_last;
   DevBuf pos4;                            // float4 (ox, oy, oz, H) per particle
+  DevBuf pos4_build;                      // pos4 of the last full build (the axis sorts' keys)
   // sort
   DevBuf axis_order;                      // uint16 13 x n
-  DevBuf leaf_sorted, sort_list, sort_big;  // per leaf: axis orders made this step; leaves to sort
   int max_leaf = 0;                       // largest leaf of the build
-  int64_t n_big_leaves = 0;               // leaves of more than 512 particles
-  int leaves_checked = 0;                 // max_leaf / n_big_leaves read for the current build
-  int sorted_lists = 0;                   // bit w: partners of cell-pair list w are sorted
+  int leaves_checked = 0;                 // max_leaf read and the leaves sorted for the current build
   // mark
   DevBuf active, leaf_nact, leaf_act_off, leaf_actleaf, act_leaves, act_hmax, act_leaf_chunk_off;
   DevBuf active_idx, chunk_of, chunks, chunk_todo;
@@ -174,7 +171,6 @@ enum ScalarSlot {
   SC_UPD_HMAX = 13,   // cell update: max H bits, max displacement bits, rebuild flag
   SC_UPD_DX = 14,
   SC_UPD_FLAG = 15,
-  SC_NBIG = 16,       // leaves of more than 512 particles (full build)
   SC_COUNT = 32
 };
 
@@ -194,8 +190,7 @@ sph_status mark_active_impl(sph_ctx *ctx, const sph_particles *p, int m, int64_t
 sph_status build_pairs(sph_ctx *ctx, int which, float slack);
 sph_status build_pairs_count(sph_ctx *ctx, int which, float slack, int32_t *host_total);
 sph_status build_pairs_fill(sph_ctx *ctx, int which, float slack, int32_t np);
-sph_status refresh_leaf_hmax(sph_ctx *ctx, bool read_global);
-sph_status sort_partners(sph_ctx *ctx, int which);
+sph_status refresh_leaf_hmax(sph_ctx *ctx);
 sph_status sort_all_leaves(sph_ctx *ctx);
 sph_status pack_neighbour_data(sph_ctx *ctx, const sph_particles *p);
 sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u);

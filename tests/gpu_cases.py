@@ -28,6 +28,7 @@ def run_gpu_step(sg, ic, m_bin, ctx_kw=None, entropy_from_u=True, setup_all=Fals
     snap["leaves"] = {k: v.cpu().numpy() for k, v in ctx.copy_leaves().items()}
     snap["order"] = ctx.copy_axis_order().cpu().numpy().view(np.uint16)
     snap["info_build"] = ctx.info()
+    snap["pair_slack"] = ctx.params.pair_slack
     snap["H_mark"] = None
     if setup_all:
         ctx.mark_active(p, ctx.params.n_bins - 1)
@@ -52,6 +53,14 @@ def run_gpu_step(sg, ic, m_bin, ctx_kw=None, entropy_from_u=True, setup_all=Fals
 
 def host(p, k):
     return p[k].detach().cpu().numpy()
+
+
+def with_slack(act, slack):
+    """The active set with the reach of the density cell-pair lists: each
+    active leaf's max H times the slack, rounded to FP32 as on the device."""
+    out = dict(act)
+    out["hmax_act"] = (np.asarray(act["hmax_act"], np.float32) * np.float32(slack)).astype(np.float32)
+    return out
 
 
 def pair_set(a, b, s):
@@ -81,7 +90,7 @@ def check_structures(ic, perm, snap, split=400, m_bin=0, D=16):
     assert np.array_equal(snap["active"], act["active"])
     assert np.array_equal(snap["active_leaves"], act["active_leaves"])
     assert np.array_equal(snap["hmax_act"].view(np.uint32), act["hmax_act"].view(np.uint32))
-    ea, eb, es = emu.pairs(cl, act, "density")
+    ea, eb, es = emu.pairs(cl, with_slack(act, snap["pair_slack"]), "density")
     assert pair_set(*snap["dpairs"]) == pair_set(ea, eb, es)
     return cl, act
 

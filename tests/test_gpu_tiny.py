@@ -189,9 +189,10 @@ def test_autotune_keeps_results(gpu_lib, tmp_path):
     assert np.max(np.abs(host(p3, "rho") / ref["rho"] - 1)) < 2e-6
 
 
-def test_lazy_axis_sorts_match_full_sorts(gpu_lib):
-    """A deep-bin step whose loop passes sort only the partner leaves they
-    reach gives the same bits as the step after a sort of every leaf."""
+def test_unsorted_small_leaves_match_full_sorts(gpu_lib):
+    """A deep-bin step on the sorts of the full build (leaves of at most two
+    tiles are not sorted: the loops read them whole) gives the same bits as
+    the step after a sort of every leaf."""
     sg = gpu_lib
     ic = ics.tiny_lattice(16, velocity_sigma=0.1)
     ic["bin"] = np.random.default_rng(7).integers(0, 6, size=ic["x"].shape[0]).astype(np.int8)

@@ -8,7 +8,7 @@ import torch
 import ics
 from oracle import cells as emu
 from oracle import sph
-from tests.gpu_cases import A_TOL, RHO_TOL, host, pair_set
+from tests.gpu_cases import A_TOL, RHO_TOL, host, pair_set, with_slack
 
 pytestmark = pytest.mark.gpu
 
@@ -56,7 +56,7 @@ def test_cell_update_matches_definitions_and_oracle(gpu_lib):
     ctx.mark_active(p, ctx.params.n_bins - 1)
     act = emu.mark_active(up, host(p, "time_bin"), ctx.params.n_bins - 1, H=up["H"])
     a, b, s = ctx.copy_pairs(0)
-    ea, eb, es = emu.pairs(up, act, "density", leaf_dx=up["leaf_dx"])
+    ea, eb, es = emu.pairs(up, with_slack(act, ctx.params.pair_slack), "density", leaf_dx=up["leaf_dx"])
     assert pair_set(a.cpu().numpy(), b.cpu().numpy(), s.cpu().numpy()) == pair_set(ea, eb, es)
     ctx.density_pass(p, True)
     ctx.force_pass(p)
@@ -69,6 +69,9 @@ def test_cell_update_matches_definitions_and_oracle(gpu_lib):
     a, b, s = ctx.copy_pairs(1)
     ea, eb, es = emu.pairs(up, act, "force", leaf_hmax_arr=lh, leaf_dx=up["leaf_dx"])
     assert pair_set(a.cpu().numpy(), b.cpu().numpy(), s.cpu().numpy()) == pair_set(ea, eb, es)
+    # the axis orders are those of the full build's offsets
+    order_ref, _ = emu.axis_sort(cl)
+    assert np.array_equal(ctx.copy_axis_order().cpu().numpy().view(np.uint16), order_ref)
     # physics at the moved positions, in cell order
     xs = np.stack([up["xw"], up["yw"], up["zw"]], 1)
     v = np.stack([host(p, k) for k in ("vx", "vy", "vz")], 1)
@@ -100,3 +103,62 @@ def test_large_move_rebuilds(gpu_lib):
     ctx0.build_cells(p0)
     ctx0.build_cells(p0)
     assert ctx0.info()["full_builds"] == 2
+
+
+def test_kept_axis_orders_on_clustered_update(gpu_lib):
+    """Cells and axis orders kept across an update on a clustered box with
+    leaves past two tiles (their partners are swept in the kept order, with
+    the stop widened by the drift margins): physics against the oracle."""
+    sg = gpu_lib
+    ic = dict(ics.clustered(n_total=20000, n_clumps=3))
+    rng = np.random.default_rng(11)
+    ic["v"] = rng.normal(0.0, 0.3, size=ic["x"].shape)
+    print("case update clustered20k", flush=True)
+    p = sg.Particles.from_initial(ic)
+    ctx = sg.Context()
+    perm = torch.empty(p.n, dtype=torch.int64, device="cuda")
+    ctx.build_cells(p, perm)
+    ctx.sort_cells()
+    ctx.mark_active(p, ctx.params.n_bins - 1)
+    ctx.density_pass(p, True)
+    ctx.force_pass(p)
+    ctx.sync()
+    lv = {k: v.cpu().numpy() for k, v in ctx.copy_leaves().items()}
+    assert lv["count"].max() > 128
+    # every particle moves by up to 5% of its leaf's width
+    width = np.repeat(np.ldexp(1.0, -lv["level"]), lv["count"])
+    xs = np.stack([host(p, k) for k in "xyz"], 1)
+    xs = np.mod(xs + rng.uniform(-0.03, 0.03, size=xs.shape) * width[:, None], 1.0)
+    for d, k in enumerate("xyz"):
+        p[k].copy_(torch.from_numpy(np.ascontiguousarray(xs[:, d])))
+    h_now = host(p, "h").copy()
+    ctx.build_cells(p)
+    inf = ctx.info()
+    assert inf["full_builds"] == 1 and inf["cell_updates"] == 1 and inf["dx_max"] > 0
+    ctx.sort_cells()
+    ctx.mark_active(p, ctx.params.n_bins - 1)
+    ctx.density_pass(p, True)
+    ctx.force_pass(p)
+    ctx.sync()
+    cl = emu.build_cells(ic["x"], ic["h"], split=400, D=16)
+    assert np.array_equal(perm.cpu().numpy(), cl["perm"])
+    order_ref, _ = emu.axis_sort(cl)
+    assert np.array_equal(ctx.copy_axis_order().cpu().numpy().view(np.uint16), order_ref)
+    xs = np.stack([host(p, k) for k in "xyz"], 1)
+    v = np.stack([host(p, k) for k in ("vx", "vy", "vz")], 1)
+    u = host(p, "u").astype(np.float64)
+    out = sph.density_and_ghost(xs, v, host(p, "m"), h_now, 1.0, u=u)
+    fo = sph.force(xs, v, host(p, "m"), out["h"], out["rho"], out["f"], out["P"], out["c"], out["B"], 1.0)
+    H = (np.float32(1.825742) * host(p, "h")).astype(np.float32)
+    up, flag = emu.update(cl, xs, host(p, "h"), np.stack([ic["x"][cl["perm"], d] for d in range(3)], 1))
+    assert not flag
+    idx = np.arange(0, p.n, 5)
+    assert np.array_equal(host(p, "nngb_density")[idx], emu.counts(up, "density", idx, H=H))
+    assert np.array_equal(host(p, "nngb_force")[idx], emu.counts(up, "force", idx, H=H))
+    rho_err = np.max(np.abs(host(p, "rho") / out["rho"].numpy() - 1))
+    a_g = np.stack([host(p, k) for k in ("ax", "ay", "az")], 1).astype(np.float64)
+    a_r = fo["a"].numpy()
+    den = np.maximum(np.linalg.norm(a_r, axis=1), 1e-2 * fo["scale"].numpy())
+    a_err = np.max(np.linalg.norm(a_g - a_r, axis=1) / den)
+    print(f"rho {rho_err:.2e} a {a_err:.2e}", flush=True)
+    assert rho_err < RHO_TOL and a_err < A_TOL
