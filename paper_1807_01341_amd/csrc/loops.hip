@@ -47,25 +47,21 @@ __global__ __launch_bounds__(256) void density_init_kernel(int64_t n_chunks, int
 // unconverged ones again, their chunks to do.
 __global__ __launch_bounds__(256) void release_waiting_kernel(uint8_t *__restrict__ conv,
                                                               const int32_t *__restrict__ chunk_of, int64_t n_act,
-                                                              int32_t *__restrict__ chunk_todo) {
-  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n_act; k += (int64_t)gridDim.x * 256)
-    if (conv[k] == 2) {
+                                                              int32_t *__restrict__ chunk_todo,
+                                                              int32_t *__restrict__ todo, int32_t *__restrict__ todo_n) {
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n_act; k += (int64_t)gridDim.x * 256) {
+    const bool rel = conv[k] == 2;
+    if (rel) {
       conv[k] = 0;
       chunk_todo[chunk_of[k]] = 1;
     }
-}
-
-// Active indices whose smoothing length is not converged yet (waiting ones
-// excluded).
-__global__ __launch_bounds__(256) void unconverged_kernel(const uint8_t *__restrict__ conv, int64_t n_act,
-                                                          int32_t *__restrict__ list, int32_t *__restrict__ len) {
-  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n_act; k += (int64_t)gridDim.x * 256) {
-    const bool todo = conv[k] == 0;
-    const uint64_t m = __ballot(todo);
-    int base = 0;
-    if ((threadIdx.x & 63) == 0 && m) base = atomicAdd(len, __popcll(m));
-    base = __shfl(base, 0, 64);
-    if (todo) list[base + rank_below(m)] = (int32_t)k;
+    if (todo) {
+      const uint64_t m = __ballot(rel);
+      int base = 0;
+      if ((threadIdx.x & 63) == 0 && m) base = atomicAdd(todo_n, __popcll(m));
+      base = __shfl(base, 0, 64);
+      if (rel) todo[base + rank_below(m)] = (int32_t)k;
+    }
   }
 }
 
@@ -377,6 +373,7 @@ struct GhostArgs {
   int32_t *nngb;
   int32_t *n_unconv, *rebuild;
   unsigned long long *ctr;  // cumulative density interactions of finished solves
+  int32_t *todo, *todo_n;   // (opt) appends the particles the next pass evaluates
 };
 
 // Newton step on F(h) = h^3 sum_j W(r_ij, h) - eta^3 for each active particle
@@ -386,10 +383,12 @@ __device__ __forceinline__ void ghost_body(const GhostArgs &g) {
   int finished = 0;
   int unconv = 0;
   for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < g.n_active; k += (int64_t)gridDim.x * 256) {
-    if (g.conv[k] == 1) continue;
+    // whether the next pass evaluates particle k
+    const bool again = [&]() -> bool {
+    if (g.conv[k] == 1) return false;
     if (g.conv[k] == 2) {  // waiting for wider cell-pair lists: not converged
       ++unconv;
-      continue;
+      return false;
     }
     const int i = g.active_idx[k];
     const float S_w = g.sums[k], S_mw = g.sums[g.n_active + k], S_d = g.sums[2 * g.n_active + k],
@@ -456,23 +455,36 @@ __device__ __forceinline__ void ghost_body(const GhostArgs &g) {
       finished += g.act_cnt[k];
       g.conv[k] = 1;
       if (!done) ++unconv;
-    } else {
-      const Chunk ch = g.chunks[g.chunk_of[k]];
-      const float Hn = GK32 * hn;
-      if (Hn > g.act_hmax[ch.act_leaf] * g.reach) {
-        // beyond the reach of the cell-pair lists: the particle waits (no
-        // evaluation) until they are widened, so that every evaluation sees
-        // all its neighbours
-        atomicOr(g.rebuild, 1);
-        g.conv[k] = 2;
-      }
-      if (Hn > g.box_quarter) atomicOr(g.rebuild, 2);
-      g.hlo[k] = lo;
-      g.hhi[k] = hi;
-      g.h[i] = hn;
-      g.pos4[i].w = Hn;
-      g.chunk_todo[g.chunk_of[k]] = 1;
-      ++unconv;
+      return false;
+    }
+    const Chunk ch = g.chunks[g.chunk_of[k]];
+    const float Hn = GK32 * hn;
+    bool wait = false;
+    if (Hn > g.act_hmax[ch.act_leaf] * g.reach) {
+      // beyond the reach of the cell-pair lists: the particle waits (no
+      // evaluation) until they are widened, so that every evaluation sees
+      // all its neighbours
+      atomicOr(g.rebuild, 1);
+      g.conv[k] = 2;
+      wait = true;
+    }
+    if (Hn > g.box_quarter) atomicOr(g.rebuild, 2);
+    g.hlo[k] = lo;
+    g.hhi[k] = hi;
+    g.h[i] = hn;
+    g.pos4[i].w = Hn;
+    g.chunk_todo[g.chunk_of[k]] = 1;
+    ++unconv;
+    return !wait;
+    }();
+    if (g.todo) {
+      // one append per wave (lane 0 holds the wave's lowest k, so it is in
+      // the loop whenever any lane is)
+      const uint64_t m = __ballot(again);
+      int base = 0;
+      if ((threadIdx.x & 63) == 0 && m) base = atomicAdd(g.todo_n, __popcll(m));
+      base = __shfl(base, 0, 64);
+      if (again) g.todo[base + rank_below(m)] = (int32_t)k;
     }
   }
   finished = wave_sum_i(finished);
@@ -504,6 +516,52 @@ struct SweepPair {
   int off, bb;
   float sx, sy, sz;
 };
+
+// The partners of up to 64 cell pairs (one per lane) that a wave reads as one
+// flat candidate range: those with `small` set, compacted into `my` in lane
+// order with their first flat index.  ns entries; steps = ceil(log2(ns)).
+struct FlatRange {
+  int total, ns, steps;
+};
+
+__device__ __forceinline__ FlatRange compact_small(SweepPair *my, bool small, int bc, int bb, const PairEntry &e,
+                                                   int lane) {
+  const int n_small = small ? bc : 0;
+  int incl = n_small;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
+  }
+  FlatRange r;
+  r.total = __shfl(incl, 63, 64);
+  const uint64_t m = __ballot(small);
+  r.ns = __popcll(m);
+  r.steps = 0;
+  while ((1 << r.steps) < r.ns) ++r.steps;
+  wave_sync();  // earlier readers of `my` are done
+  if (small) {
+    SweepPair q;
+    q.off = incl - n_small;
+    q.bb = bb;
+    q.sx = e.sx;
+    q.sy = e.sy;
+    q.sz = e.sz;
+    my[rank_below(m)] = q;
+  }
+  wave_sync();
+  return r;
+}
+
+// The compacted partner whose flat range holds index f (offsets increase
+// strictly: every leaf holds a particle).
+__device__ __forceinline__ SweepPair locate(const SweepPair *my, const FlatRange &r, int f) {
+  int lo = 0;
+  for (int s = r.steps - 1; s >= 0; --s) {
+    const int mid = lo + (1 << s);
+    if (mid < r.ns && my[mid].off <= f) lo = mid;
+  }
+  return my[lo];
+}
 
 // Whether partner leaf e.b can hold a particle within R of the particle at
 // offset pi: the distance from pi to the leaf's box (in the particle's leaf
@@ -559,7 +617,8 @@ __device__ __forceinline__ void density_term(const float4 &pi, const float4 &vi,
 template <int NWP>
 __global__ __launch_bounds__(256) void density_sweep_kernel(LoopArgs g, const int32_t *__restrict__ todo,
                                                             const int32_t *__restrict__ n_todo_dev, int64_t n_todo,
-                                                            const int32_t *__restrict__ chunk_of) {
+                                                            const int32_t *__restrict__ chunk_of,
+                                                            int32_t *__restrict__ next_n) {
   __shared__ SweepPair sp[4][64];
   __shared__ float4 hq[4][128];  // per wave: queued neighbours (dx, dy, dz, j)
   __shared__ float red[4][9];
@@ -567,6 +626,8 @@ __global__ __launch_bounds__(256) void density_sweep_kernel(LoopArgs g, const in
   const int sub = wave % NWP;
   const int64_t w = (int64_t)blockIdx.x * (4 / NWP) + wave / NWP;
   if (n_todo_dev) n_todo = *n_todo_dev;
+  // the next pass's list starts empty (its ghost appends after this launch)
+  if (next_n && blockIdx.x == 0 && threadIdx.x == 0) *next_n = 0;
   const int lane = threadIdx.x & 63;
   if (w < n_todo) {
   SweepPair *my = sp[wave];
@@ -624,42 +685,19 @@ __global__ __launch_bounds__(256) void density_sweep_kernel(LoopArgs g, const in
       near = leaf_in_reach(g, e, pi, Hi);
     }
     const bool big = near && e.b != ch.leaf && bc > 128;
-    // flat range of the small partners within reach: exclusive scan of their counts
-    const int n_small = (near && !big) ? bc : 0;
-    int incl = n_small;
-    for (int o = 1; o < 64; o <<= 1) {
-      const int t = __shfl_up(incl, o, 64);
-      if (lane >= o) incl += t;
-    }
-    const int total = __shfl(incl, 63, 64);
-    wave_sync();
-    my[lane].off = incl - n_small;
-    my[lane].bb = bb;
-    my[lane].sx = e.sx;
-    my[lane].sy = e.sy;
-    my[lane].sz = e.sz;
-    wave_sync();
-    for (int t = sub * 64; t < total; t += NWP * 64) {
-      const int f = t + lane;
-      bool hit = false;
-      float dx = 0.f, dy = 0.f, dz = 0.f;
-      int j = 0;
-      if (f < total) {
-        // last pair whose range starts at or before f
-        int lo = 0, hi = 63;
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (my[mid].off <= f) lo = mid; else hi = mid - 1;
-        }
-        const SweepPair q = my[lo];
-        j = q.bb + (f - q.off);
-        const float4 pj = g.pos4[j];
-        dx = pi.x - (pj.x + q.sx);
-        dy = pi.y - (pj.y + q.sy);
-        dz = pi.z - (pj.z + q.sz);
-        hit = fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < H2i;
-      }
-      push(hit, dx, dy, dz, j);
+    // the small partners within reach as one flat range
+    const FlatRange fr = compact_small(my, near && !big, bc, bb, e, lane);
+    for (int t = sub * 64; t < fr.total; t += 2 * NWP * 64) {
+      // two candidates per lane, their loads in flight together
+      const int f0 = t + lane, f1 = t + NWP * 64 + lane;
+      const bool v0 = f0 < fr.total, v1 = f1 < fr.total;
+      const SweepPair q0 = locate(my, fr, v0 ? f0 : 0), q1 = locate(my, fr, v1 ? f1 : 0);
+      const int j0 = q0.bb + (v0 ? f0 - q0.off : 0), j1 = q1.bb + (v1 ? f1 - q1.off : 0);
+      const float4 pj0 = g.pos4[j0], pj1 = g.pos4[j1];
+      const float dx0 = pi.x - (pj0.x + q0.sx), dy0 = pi.y - (pj0.y + q0.sy), dz0 = pi.z - (pj0.z + q0.sz);
+      const float dx1 = pi.x - (pj1.x + q1.sx), dy1 = pi.y - (pj1.y + q1.sy), dz1 = pi.z - (pj1.z + q1.sz);
+      push(v0 && fmaf(dz0, dz0, fmaf(dy0, dy0, dx0 * dx0)) < H2i, dx0, dy0, dz0, j0);
+      push(v1 && fmaf(dz1, dz1, fmaf(dy1, dy1, dx1 * dx1)) < H2i, dx1, dy1, dz1, j1);
     }
     // large partners, one after the other: sorted sweep
     uint64_t bigm = __ballot(big);
@@ -688,17 +726,22 @@ __global__ __launch_bounds__(256) void density_sweep_kernel(LoopArgs g, const in
       const float margin = 1.0001f * Hi + 2.0001f * g.leaf_dx[Bq] + 1e-6f * (2.f * fabsf(pp) + fabsf(sproj));
       const float lo_b = pp - margin - sproj, hi_b = pp + margin - sproj;
       const uint16_t *ord = g.axis_order + (int64_t)axis * g.n + bbq;
-      for (int t = 0; t < bcq; t += 64) {
-        const int kk = t + lane;
-        const bool valid = kk < bcq;
-        const int j = valid ? bbq + (int)ord[sgn > 0.f ? kk : bcq - 1 - kk] : bbq;
-        const float4 pj = valid ? g.pos4[j] : make_float4(0.f, 0.f, 0.f, 0.f);
-        const float key = fmaf(pj.z, ez, fmaf(pj.y, ey, pj.x * ex));
-        const bool beyond = sgn > 0.f ? key > hi_b : key < lo_b;
-        if (__ballot(valid && !beyond) == 0ull) break;
-        const float dx = pi.x - (pj.x + sx), dy = pi.y - (pj.y + sy), dz = pi.z - (pj.z + sz);
-        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        push(valid && r2 < H2i, dx, dy, dz, j);
+      // two tiles per step, their loads in flight together; the sweep stops
+      // at the first tile wholly past the reach
+      for (int t = 0; t < bcq; t += 128) {
+        const int k0 = t + lane, k1 = t + 64 + lane;
+        const bool v0 = k0 < bcq, v1 = k1 < bcq;
+        const int j0 = bbq + (v0 ? (int)ord[sgn > 0.f ? k0 : bcq - 1 - k0] : 0);
+        const int j1 = bbq + (v1 ? (int)ord[sgn > 0.f ? k1 : bcq - 1 - k1] : 0);
+        const float4 pj0 = g.pos4[j0], pj1 = g.pos4[j1];
+        const float key0 = fmaf(pj0.z, ez, fmaf(pj0.y, ey, pj0.x * ex));
+        if (__ballot(v0 && !(sgn > 0.f ? key0 > hi_b : key0 < lo_b)) == 0ull) break;
+        const float dx0 = pi.x - (pj0.x + sx), dy0 = pi.y - (pj0.y + sy), dz0 = pi.z - (pj0.z + sz);
+        push(v0 && fmaf(dz0, dz0, fmaf(dy0, dy0, dx0 * dx0)) < H2i, dx0, dy0, dz0, j0);
+        const float key1 = fmaf(pj1.z, ez, fmaf(pj1.y, ey, pj1.x * ex));
+        if (__ballot(v1 && !(sgn > 0.f ? key1 > hi_b : key1 < lo_b)) == 0ull) break;
+        const float dx1 = pi.x - (pj1.x + sx), dy1 = pi.y - (pj1.y + sy), dz1 = pi.z - (pj1.z + sz);
+        push(v1 && fmaf(dz1, dz1, fmaf(dy1, dy1, dx1 * dx1)) < H2i, dx1, dy1, dz1, j1);
       }
     }
   }
@@ -817,19 +860,12 @@ __global__ __launch_bounds__(256) void force_sweep_kernel(LoopArgs g, const int3
         ++cnt;
       }
     };
-    // tests candidate j (valid lanes) and queues it if it is a neighbour
-    auto visit = [&](bool valid, int j, float sx, float sy, float sz) {
-      bool hit = false;
-      float dx = 0.f, dy = 0.f, dz = 0.f, Hj = 0.f;
-      if (valid) {
-        const float4 pj = g.pos4[j];
-        dx = pi.x - (pj.x + sx);
-        dy = pi.y - (pj.y + sy);
-        dz = pi.z - (pj.z + sz);
-        Hj = pj.w;
-        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        hit = (r2 < H2i || r2 < Hj * Hj) && j != i;
-      }
+    // tests candidate j at pj (valid lanes) and queues it if it is a neighbour
+    auto visit = [&](bool valid, int j, const float4 &pj, float sx, float sy, float sz) {
+      const float dx = pi.x - (pj.x + sx), dy = pi.y - (pj.y + sy), dz = pi.z - (pj.z + sz);
+      const float Hj = pj.w;
+      const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+      const bool hit = valid && (r2 < H2i || r2 < Hj * Hj) && j != i;
       const uint64_t m = __ballot(hit);
       if (m == 0ull) return;
       if (hit) {
@@ -871,32 +907,16 @@ __global__ __launch_bounds__(256) void force_sweep_kernel(LoopArgs g, const int3
         near = leaf_in_reach(g, e, pi, fmaxf(Hi, g.leaf_hmax[e.b]));
       }
       const bool big = near && e.b != ch.leaf && bc > 128;
-      const int n_small = (near && !big) ? bc : 0;
-      int incl = n_small;
-      for (int o = 1; o < 64; o <<= 1) {
-        const int t = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += t;
-      }
-      const int total = __shfl(incl, 63, 64);
-      wave_sync();
-      my[lane].off = incl - n_small;
-      my[lane].bb = bb;
-      my[lane].sx = e.sx;
-      my[lane].sy = e.sy;
-      my[lane].sz = e.sz;
-      wave_sync();
-      for (int t = sub * 64; t < total; t += NWP * 64) {
-        const int fi = t + lane;
-        SweepPair q = {0, 0, 0.f, 0.f, 0.f};
-        if (fi < total) {
-          int lo = 0, hi = 63;
-          while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (my[mid].off <= fi) lo = mid; else hi = mid - 1;
-          }
-          q = my[lo];
-        }
-        visit(fi < total, q.bb + (fi - q.off), q.sx, q.sy, q.sz);
+      const FlatRange fr = compact_small(my, near && !big, bc, bb, e, lane);
+      for (int t = sub * 64; t < fr.total; t += 2 * NWP * 64) {
+        // two candidates per lane, their loads in flight together
+        const int f0 = t + lane, f1 = t + NWP * 64 + lane;
+        const bool v0 = f0 < fr.total, v1 = f1 < fr.total;
+        const SweepPair q0 = locate(my, fr, v0 ? f0 : 0), q1 = locate(my, fr, v1 ? f1 : 0);
+        const int j0 = q0.bb + (v0 ? f0 - q0.off : 0), j1 = q1.bb + (v1 ? f1 - q1.off : 0);
+        const float4 pj0 = g.pos4[j0], pj1 = g.pos4[j1];
+        visit(v0, j0, pj0, q0.sx, q0.sy, q0.sz);
+        visit(v1, j1, pj1, q1.sx, q1.sy, q1.sz);
       }
       uint64_t bigm = __ballot(big);
       int nb = 0;
@@ -924,15 +944,19 @@ __global__ __launch_bounds__(256) void force_sweep_kernel(LoopArgs g, const int3
         const float margin = 1.0001f * Rb + 2.0001f * g.leaf_dx[Bq] + 1e-6f * (2.f * fabsf(pp) + fabsf(sproj));
         const float lo_b = pp - margin - sproj, hi_b = pp + margin - sproj;
         const uint16_t *ord = g.axis_order + (int64_t)axis * g.n + bbq;
-        for (int t = 0; t < bcq; t += 64) {
-          const int kk = t + lane;
-          const bool valid = kk < bcq;
-          const int j = valid ? bbq + (int)ord[sgn > 0.f ? kk : bcq - 1 - kk] : bbq;
-          const float4 pj = valid ? g.pos4[j] : make_float4(0.f, 0.f, 0.f, 0.f);
-          const float key = fmaf(pj.z, ez, fmaf(pj.y, ey, pj.x * ex));
-          const bool beyond = sgn > 0.f ? key > hi_b : key < lo_b;
-          if (__ballot(valid && !beyond) == 0ull) break;
-          visit(valid, j, sx, sy, sz);
+        // two tiles per step (as in the density sweep)
+        for (int t = 0; t < bcq; t += 128) {
+          const int k0 = t + lane, k1 = t + 64 + lane;
+          const bool v0 = k0 < bcq, v1 = k1 < bcq;
+          const int j0 = bbq + (v0 ? (int)ord[sgn > 0.f ? k0 : bcq - 1 - k0] : 0);
+          const int j1 = bbq + (v1 ? (int)ord[sgn > 0.f ? k1 : bcq - 1 - k1] : 0);
+          const float4 pj0 = g.pos4[j0], pj1 = g.pos4[j1];
+          const float key0 = fmaf(pj0.z, ez, fmaf(pj0.y, ey, pj0.x * ex));
+          if (__ballot(v0 && !(sgn > 0.f ? key0 > hi_b : key0 < lo_b)) == 0ull) break;
+          visit(v0, j0, pj0, sx, sy, sz);
+          const float key1 = fmaf(pj1.z, ez, fmaf(pj1.y, ey, pj1.x * ex));
+          if (__ballot(v1 && !(sgn > 0.f ? key1 > hi_b : key1 < lo_b)) == 0ull) break;
+          visit(v1, j1, pj1, sx, sy, sz);
         }
       }
     }
@@ -1011,6 +1035,7 @@ sph_status density_begin(sph_ctx *ctx, const sph_particles *p, int entropy_from_
   const int64_t na = ctx->n_active;
   ctx->density_from_u = entropy_from_u ? 1 : 0;
   ctx->widen_pending = 0;
+  ctx->todo_collect = 0;
   ctx->density_iterations = 0;
   ctx->n_unconverged = 0;
   ctx->pair_rebuilds = 0;
@@ -1087,6 +1112,8 @@ GhostArgs density_ghost_args(sph_ctx *ctx, sph_particles *p, int it, int entropy
   gh.n_unconv = status;
   gh.rebuild = status + 1;
   gh.ctr = (unsigned long long *)ctx->counters64.p;
+  gh.todo = nullptr;
+  gh.todo_n = nullptr;
   return gh;
 }
 
@@ -1119,8 +1146,12 @@ sph_status density_after_pass(sph_ctx *ctx, int it, const int32_t st[2], int *do
     ctx->pair_rebuilds++;
     SPH_TRY(refresh_leaf_hmax(ctx));
     SPH_TRY(build_pairs(ctx, 0, 1.5f));
+    // (single-box passes: the released particles join the next pass's list)
+    int32_t *todo = ctx->todo_collect ? (int32_t *)ctx->todo_list.p : nullptr;
+    int32_t *todo_n = todo ? todo + ctx->n_active + ((it + 1) & 1) : nullptr;
     release_waiting_kernel<<<grid256(ctx->n_active), 256, 0, ctx->stream>>>(
-        (uint8_t *)ctx->conv.p, (const int32_t *)ctx->chunk_of.p, ctx->n_active, (int32_t *)ctx->chunk_todo.p);
+        (uint8_t *)ctx->conv.p, (const int32_t *)ctx->chunk_of.p, ctx->n_active, (int32_t *)ctx->chunk_todo.p, todo,
+        todo_n);
     HIP_TRY(ctx, hipGetLastError());
   }
   return SPH_OK;
@@ -1148,9 +1179,13 @@ sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u)
   const int64_t na = ctx->n_active;
   const int maxit = ctx->prm.h_max_iter;
   SPH_TRY(sph_ensure(ctx, ctx->pass_stats, sizeof(int32_t) * 2 * (size_t)(maxit + 1)));
-  SPH_TRY(sph_ensure(ctx, ctx->todo_list, 4 * (size_t)(na + 1)));
+  // the particles each pass evaluates: appended by the ghost (and by the
+  // release of waiting particles) before it; two counters, pass p reading
+  // counter p % 2
+  SPH_TRY(sph_ensure(ctx, ctx->todo_list, 4 * (size_t)(na + 2)));
+  ctx->todo_collect = 1;
   int32_t *stats = (int32_t *)ctx->pass_stats.p;
-  int32_t *list = (int32_t *)ctx->todo_list.p;
+  int32_t *list = (int32_t *)ctx->todo_list.p, *list_n = list + na;
   int64_t n_todo = na;  // upper bound of the particles left to do
   int it = 0, done = 0;
   while (!done) {
@@ -1158,37 +1193,33 @@ sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u)
     HIP_TRY(ctx, hipMemsetAsync(stats + 2 * first, 0, sizeof(int32_t) * 2 * (last - first + 1), ctx->stream));
     for (int pass = first; pass <= last; ++pass) {
       LoopArgs a = density_loop_args(ctx);
+      int32_t *next_n = list_n + ((pass + 1) & 1);
       if (n_todo < ctx->prm.sweep_below) {
-        // few particles to do: one wave per particle
-        if (pass > 1) {
-          HIP_TRY(ctx, hipMemsetAsync(list + na, 0, 4, ctx->stream));
-          PROF(ctx, "density_todo");
-          unconverged_kernel<<<grid256(na), 256, 0, ctx->stream>>>((const uint8_t *)ctx->conv.p, na, list,
-                                                                    list + na);
-        }
-        {
-          PROF(ctx, "density_loop");
-          const int nwp = sweep_waves(ctx, n_todo);
-          const unsigned grid = (unsigned)std::max<int64_t>(1, ceil_div(n_todo * nwp, 4));
-          const int32_t *tl = pass > 1 ? list : nullptr, *tn = pass > 1 ? list + na : nullptr;
-          if (nwp == 4)
-            density_sweep_kernel<4><<<grid, 256, 0, ctx->stream>>>(a, tl, tn, n_todo, (const int32_t *)ctx->chunk_of.p);
-          else if (nwp == 2)
-            density_sweep_kernel<2><<<grid, 256, 0, ctx->stream>>>(a, tl, tn, n_todo, (const int32_t *)ctx->chunk_of.p);
-          else
-            density_sweep_kernel<1><<<grid, 256, 0, ctx->stream>>>(a, tl, tn, n_todo, (const int32_t *)ctx->chunk_of.p);
-        }
+        // few particles to do: one wave per particle.  The number to do only
+        // falls from here on, so no later pass of this solve runs the chunk
+        // loop (whose chunk flags the sweep leaves as they are).
+        PROF(ctx, "density_loop");
+        const int nwp = sweep_waves(ctx, n_todo);
+        const unsigned grid = (unsigned)std::max<int64_t>(1, ceil_div(n_todo * nwp, 4));
+        const int32_t *tl = pass > 1 ? list : nullptr, *tn = pass > 1 ? list_n + (pass & 1) : nullptr;
+        const int32_t *co = (const int32_t *)ctx->chunk_of.p;
+        if (nwp == 4)
+          density_sweep_kernel<4><<<grid, 256, 0, ctx->stream>>>(a, tl, tn, n_todo, co, next_n);
+        else if (nwp == 2)
+          density_sweep_kernel<2><<<grid, 256, 0, ctx->stream>>>(a, tl, tn, n_todo, co, next_n);
+        else
+          density_sweep_kernel<1><<<grid, 256, 0, ctx->stream>>>(a, tl, tn, n_todo, co, next_n);
         HIP_TRY(ctx, hipGetLastError());
-        // no chunk is left to do for the chunk loop; the ghost marks them again
-        fill_i32_kernel<<<grid256(ctx->n_chunks), 256, 0, ctx->stream>>>((int32_t *)ctx->chunk_todo.p,
-                                                                          ctx->n_chunks, 0);
-        HIP_TRY(ctx, hipGetLastError());
-      } else if (ctx->prm.compensated) {
-        SPH_TRY((launch_loop<0, true>(ctx, a)));
       } else {
-        SPH_TRY((launch_loop<0, false>(ctx, a)));
+        HIP_TRY(ctx, hipMemsetAsync(next_n, 0, sizeof(int32_t), ctx->stream));
+        if (ctx->prm.compensated)
+          SPH_TRY((launch_loop<0, true>(ctx, a)));
+        else
+          SPH_TRY((launch_loop<0, false>(ctx, a)));
       }
       GhostArgs gh = density_ghost_args(ctx, p, pass, entropy_from_u, stats + 2 * pass);
+      gh.todo = list;
+      gh.todo_n = next_n;
       {
         PROF(ctx, "ghost");
         ghost_kernel<<<grid256(na), 256, 0, ctx->stream>>>(gh);

@@ -89,6 +89,7 @@ struct sph_ctx {
   DevBuf jvm;                             // float4 (vx, vy, vz, m)
   DevBuf jth;                             // float4 (rho, f P / rho^2, c, B)
   DevBuf sums, hlo, hhi, conv, todo_list, pass_stats;
+  int todo_collect = 0;                   // the ghosts of this density pass append to todo_list
   DevBuf counters64;                      // cumulative interaction counts (2 x uint64)
   DevBuf act_cost;                        // staged partner particles per active leaf
   DevBuf work, work_tmp, box_args, box_work;
