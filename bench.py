@@ -98,11 +98,12 @@ def _loops_ms(prof):
     return sum(prof.get(k, (0, 0.0))[1] for k in ("density_loop", "force_loop"))
 
 
-def measure_all_active(sg, ic, reps=3):
+def measure_all_active(sg, ic, reps=3, **kw):
     """All-active density + force on the same clustered particles (a fresh
-    context): the loops at full occupancy, for the ALU roofline."""
+    context with the step's parameters): the loops at full occupancy, for the
+    ALU roofline."""
     import torch
-    ctx = sg.Context()
+    ctx = sg.Context(**kw)
     p = sg.Particles.from_initial(ic)
     ctx.build_cells(p)
     ctx.sort_cells()
@@ -574,7 +575,7 @@ def main():
     if not args.no_extras:
         del p, ctx, src, dst
         torch.cuda.empty_cache()
-        out["all_active"] = measure_all_active(sg, ic)
+        out["all_active"] = measure_all_active(sg, ic, **kw)
         out["batch"] = measure_batch(sg)
         out["adjoint"] = measure_adjoint(sg)
     if not args.no_cpu_baseline:

@@ -74,7 +74,8 @@ typedef struct {
   int sweep_below;     /* density Newton passes with fewer particles to do, and force passes
                           with fewer active particles, than this run waves per particle
                           (a sweep of each partner leaf in reach) instead of the chunk
-                          loop (2^30: always; 0: never; batched passes use chunks) */
+                          loop (0: never; batched passes use chunks) (2^18: the sweep
+                          wins on sparse deep time-bins, the chunk loop on dense ones) */
   int sweep_waves;     /* waves per particle in those passes: 1, 2 or 4; 0 = one (0) */
   float rebuild_frac;  /* sph_build_cells keeps the cells of its last full build while no
                           leaf's particles moved more than this fraction of the leaf's

@@ -103,7 +103,7 @@ void sph_default_params(sph_params *p) {
   p->list_cap = 96;
   p->rebuild_frac = 0.125f;
   p->pair_slack = 1.1f;
-  p->sweep_below = 1 << 30;
+  p->sweep_below = 1 << 18;
 }
 
 sph_status sph_create(const sph_params *p, void *hip_stream, sph_ctx **out) {

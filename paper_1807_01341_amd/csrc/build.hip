@@ -271,10 +271,12 @@ __global__ __launch_bounds__(BT) void update_kernel(double *__restrict__ x, doub
     double d2m = 0.0;  // largest displacement component
     for (int k = lane; k < cnt; k += 64) {
       const int s = b + k;
-      const double xw = wrap_box(x[s], L), yw = wrap_box(y[s], L), zw = wrap_box(z[s], L);
-      x[s] = xw;
-      y[s] = yw;
-      z[s] = zw;
+      const double x0 = x[s], y0 = y[s], z0 = z[s];
+      const double xw = wrap_box(x0, L), yw = wrap_box(y0, L), zw = wrap_box(z0, L);
+      // written back only where the wrap moved a particle
+      if (xw != x0) x[s] = xw;
+      if (yw != y0) y[s] = yw;
+      if (zw != z0) z[s] = zw;
       double ox = xw - cx, oy = yw - cy, oz = zw - cz;
       ox = ox > half ? ox - L : (ox < -half ? ox + L : ox);
       oy = oy > half ? oy - L : (oy < -half ? oy + L : oy);

@@ -1036,6 +1036,7 @@ sph_status density_begin(sph_ctx *ctx, const sph_particles *p, int entropy_from_
   ctx->density_from_u = entropy_from_u ? 1 : 0;
   ctx->widen_pending = 0;
   ctx->todo_collect = 0;
+  ctx->fpairs_counted = -1;
   ctx->density_iterations = 0;
   ctx->n_unconverged = 0;
   ctx->pair_rebuilds = 0;
@@ -1159,8 +1160,8 @@ sph_status density_after_pass(sph_ctx *ctx, int it, const int32_t st[2], int *do
 
 // Leaf max H follows the new smoothing lengths, so that any later cell-pair
 // list (the force list, or a later active set without a rebuild) sees them.
-sph_status density_end(sph_ctx *ctx) {
-  SPH_TRY(refresh_leaf_hmax(ctx));
+sph_status density_end(sph_ctx *ctx, bool refreshed) {
+  if (!refreshed) SPH_TRY(refresh_leaf_hmax(ctx));
   ctx->state = 4;
   if (ctx->n_unconverged > 0)
     return sph_fail(ctx, SPH_ENOCONV, "density_pass: %lld particles not converged after %d iterations",
@@ -1226,6 +1227,12 @@ sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u)
       }
       HIP_TRY(ctx, hipGetLastError());
     }
+    // in case this group ends the solve: the leaf max H from the new
+    // smoothing lengths and the force cell-pair count, read in the same
+    // synchronisation (wasted work when another group follows)
+    SPH_TRY(refresh_leaf_hmax(ctx));
+    int32_t fcount = 0;
+    SPH_TRY(build_pairs_count(ctx, 1, 1.0f, &fcount));
     std::vector<int32_t> st(2 * (size_t)(last - first + 1));
     HIP_TRY(ctx, hipMemcpyAsync(st.data(), stats + 2 * first, sizeof(int32_t) * st.size(), hipMemcpyDeviceToHost,
                                 ctx->stream));
@@ -1234,9 +1241,10 @@ sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u)
       SPH_TRY(density_after_pass(ctx, pass, &st[2 * (pass - first)], &done));
       n_todo = st[2 * (pass - first)];
     }
+    if (done) ctx->fpairs_counted = fcount;
     it = last;
   }
-  return density_end(ctx);
+  return density_end(ctx, true);
 }
 
 // Force loop arguments with the outputs of p.
@@ -1265,9 +1273,13 @@ sph_status force_pass_impl(sph_ctx *ctx, sph_particles *p) {
     return SPH_OK;
   }
   (void)n;
-  SPH_TRY(build_pairs(ctx, 1, 1.0f));
-  fill_i32_kernel<<<grid256(ctx->n_chunks), 256, 0, ctx->stream>>>((int32_t *)ctx->chunk_todo.p, ctx->n_chunks, 1);
-  HIP_TRY(ctx, hipGetLastError());
+  if (ctx->fpairs_counted >= 0) {
+    // counted at the end of the density solve (same smoothing lengths)
+    SPH_TRY(build_pairs_fill(ctx, 1, 1.0f, (int32_t)ctx->fpairs_counted));
+    ctx->fpairs_counted = -1;
+  } else {
+    SPH_TRY(build_pairs(ctx, 1, 1.0f));
+  }
   LoopArgs a = force_loop_args(ctx, p);
   if (ctx->n_active < ctx->prm.sweep_below) {
     {
@@ -1282,10 +1294,14 @@ sph_status force_pass_impl(sph_ctx *ctx, sph_particles *p) {
         force_sweep_kernel<1><<<grid, 256, 0, ctx->stream>>>(a, (const int32_t *)ctx->chunk_of.p);
     }
     HIP_TRY(ctx, hipGetLastError());
-  } else if (ctx->prm.compensated) {
-    SPH_TRY((launch_loop<1, true>(ctx, a)));
   } else {
-    SPH_TRY((launch_loop<1, false>(ctx, a)));
+    fill_i32_kernel<<<grid256(ctx->n_chunks), 256, 0, ctx->stream>>>((int32_t *)ctx->chunk_todo.p, ctx->n_chunks,
+                                                                      1);
+    HIP_TRY(ctx, hipGetLastError());
+    if (ctx->prm.compensated)
+      SPH_TRY((launch_loop<1, true>(ctx, a)));
+    else
+      SPH_TRY((launch_loop<1, false>(ctx, a)));
   }
   ctx->state = 5;
   return SPH_OK;
@@ -1728,7 +1744,7 @@ sph_status batch_density_impl(sph_ctx **cs, sph_particles *ps, int nb, int entro
   sph_status first = SPH_OK;
   for (int q = 0; q < nl; ++q) {
     sph_ctx *c = cs[live[q]];
-    const sph_status e = density_end(c);
+    const sph_status e = density_end(c, false);
     if (e != SPH_OK && first == SPH_OK) first = batch_fail(lead, live[q], c, e);
   }
   return first;

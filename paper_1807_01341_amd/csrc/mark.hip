@@ -293,6 +293,7 @@ static PairGeom pair_geom(const sph_ctx *ctx) {
 sph_status build_pairs_count(sph_ctx *ctx, int which, float slack, int32_t *host_total) {
   const int64_t na = ctx->n_active_leaves;
   if (which == 0) ctx->dpair_slack = slack;
+  if (which == 1) ctx->fpairs_counted = -1;  // a count read back later is no longer the current one
   DevBuf &off = which == 0 ? ctx->dpair_off : ctx->fpair_off;
   SPH_TRY(sph_ensure(ctx, ctx->pair_cnt, 4 * (size_t)(na + 1)));
   SPH_TRY(sph_ensure(ctx, ctx->act_cost, 4 * (size_t)(na + 1)));

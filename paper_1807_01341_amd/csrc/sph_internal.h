@@ -56,6 +56,7 @@ struct sph_ctx {
   int64_t n_leaves = 0;
   int64_t n_active = 0, n_active_leaves = 0, n_chunks = 0;
   int64_t n_dpairs = 0, n_fpairs = 0;
+  int64_t fpairs_counted = -1;  // force pair total counted at the end of the density solve (-1: none)
   int max_active_bin = 0;
   int density_iterations = 0;
   int64_t n_unconverged = 0;
