@@ -560,6 +560,7 @@ sph_status build_cells_impl(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *
   ctx->built_n = n;
   ctx->n_full_builds++;
   ctx->leaves_checked = 0;
+  ctx->blocks_valid = 0;
   SPH_TRY(pack_neighbour_data(ctx, p));
   ctx->state = 1;
   return SPH_OK;

@@ -1,7 +1,9 @@
 // Active set for the current time-bin (Eq. 2, Sec. III-D) and the cell-pair
 // lists of the active cells (Sec. III-A: every pair of cells with at least one
 // member on the active list, paired where the geometry allows an interaction).
+#include <limits.h>
 #include <math.h>
+#include <stdint.h>
 #include <string.h>
 
 #include "sph_internal.h"
@@ -106,10 +108,40 @@ __device__ __forceinline__ void leaf_centre_units(int D, int lvl, int ix, int iy
   c[2] = (2 * (int64_t)iz + 1) << sh;
 }
 
+// Bounding boxes (in half-units) of each run of LEAF_BLOCK consecutive leaves
+// in Morton order, for pruning the pair search before its leaf tests.
+__global__ __launch_bounds__(MT) void leaf_block_box_kernel(int D, const int32_t *__restrict__ level,
+                                                           const int32_t *__restrict__ ix,
+                                                           const int32_t *__restrict__ iy,
+                                                           const int32_t *__restrict__ iz, int64_t nl,
+                                                           int4 *__restrict__ box) {
+  const int64_t q = (int64_t)blockIdx.x * MT + threadIdx.x;
+  const int64_t b0 = q * LEAF_BLOCK;
+  if (b0 >= nl) return;
+  const int64_t b1 = b0 + LEAF_BLOCK < nl ? b0 + LEAF_BLOCK : nl;
+  int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
+  for (int64_t l = b0; l < b1; ++l) {
+    const int sh = D - level[l];
+    const int c[3] = {(2 * ix[l] + 1) << sh, (2 * iy[l] + 1) << sh, (2 * iz[l] + 1) << sh};
+    const int hw = 1 << sh;
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = min(lo[d], c[d] - hw);
+      hi[d] = max(hi[d], c[d] + hw);
+    }
+  }
+  box[2 * q] = make_int4(lo[0], lo[1], lo[2], 0);
+  box[2 * q + 1] = make_int4(hi[0], hi[1], hi[2], 0);
+}
+
 // One wave per active leaf A: walk the top-level cells within reach, test
 // every leaf B there by periodic box distance (exact integer gaps, compared in
 // double) and count (FILL=false) or write (FILL=true) the pairs in a fixed
 // order.  mode 0: R = max active H of A; mode 1: R = max(that, max H of B).
+// Runs of LEAF_BLOCK leaves are tested first by their bounding box with the
+// largest reach any of their leaves can have (global max H, largest drift
+// margin), so the leaves of a run out of reach are never read: the box gap is
+// at most any member's gap and that reach at least any member's, so no pair
+// is lost and the set and its order are those of the leaf tests alone.
 template <bool FILL>
 __global__ __launch_bounds__(MT) void pairs_kernel(int mode, float slack, PairGeom g, int64_t n_act_leaves,
                                                    const int32_t *__restrict__ act_leaves,
@@ -121,6 +153,7 @@ __global__ __launch_bounds__(MT) void pairs_kernel(int mode, float slack, PairGe
                                                    const int32_t *__restrict__ top_last,
                                                    const int32_t *__restrict__ hmax_bits,
                                                    const float *__restrict__ leaf_dx, float dx_max,
+                                                   const int4 *__restrict__ block_box,
                                                    int32_t *__restrict__ counts, const int32_t *__restrict__ offs,
                                                    PairEntry *__restrict__ out, const int32_t *__restrict__ leaf_count,
                                                    int32_t *__restrict__ act_cost) {
@@ -158,10 +191,14 @@ __global__ __launch_bounds__(MT) void pairs_kernel(int mode, float slack, PairGe
   int written = 0;
   int staged = 0;
   const int base = FILL ? offs[a] : 0;
-  // the top cells of the search box, 64 at a time; their leaves as one flat
-  // range (in cell order, leaves in order), 64 leaves per step
-  __shared__ int cell_off[MT / 64][64], cell_first[MT / 64][64];
-  int *coff = cell_off[threadIdx.x >> 6], *cfirst = cell_first[threadIdx.x >> 6];
+  // the top cells of the search box, 64 at a time; their runs of leaves as
+  // one flat range (cells in order, runs in order), 64 runs per step; the
+  // leaves of the runs in reach as a second flat range, 64 leaves per step
+  __shared__ int cell_off[MT / 64][64], cell_first[MT / 64][64], cell_end[MT / 64][64];
+  __shared__ int run_off[MT / 64][64], run_first[MT / 64][64];
+  const int wv = threadIdx.x >> 6;
+  int *coff = cell_off[wv], *cfirst = cell_first[wv], *cend = cell_end[wv];
+  int *roff = run_off[wv], *rfirst = run_first[wv];
   const int ncell = cnt3[0] * cnt3[1] * cnt3[2];
   for (int c0 = 0; c0 < ncell; c0 += 64) {
     const int cc = c0 + lane;
@@ -175,30 +212,80 @@ __global__ __launch_bounds__(MT) void pairs_kernel(int mode, float slack, PairGe
       f = top_first[tc];
       nleaf = top_last[tc] - f;
     }
-    int incl = nleaf;
+    const int nrun = nleaf > 0 ? (f + nleaf - 1) / LEAF_BLOCK - f / LEAF_BLOCK + 1 : 0;
+    int incl = nrun;
     for (int o = 1; o < 64; o <<= 1) {
       const int t = __shfl_up(incl, o, 64);
       if (lane >= o) incl += t;
     }
-    const int total = __shfl(incl, 63, 64);
+    const int total_r = __shfl(incl, 63, 64);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    coff[lane] = incl - nleaf;
+    coff[lane] = incl - nrun;
     cfirst[lane] = f;
+    cend[lane] = f + nleaf;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
+    for (int r0 = 0; r0 < total_r; r0 += 64) {
+      const int ri = r0 + lane;
+      int lf = 0, nl_run = 0;
+      if (ri < total_r) {
+        // last cell whose runs start at or before ri (cells without runs
+        // share the offset of the next one)
+        int lo_ = 0, hi_ = 63;
+        while (lo_ < hi_) {
+          const int mid = (lo_ + hi_ + 1) >> 1;
+          if (coff[mid] <= ri) lo_ = mid; else hi_ = mid - 1;
+        }
+        const int run = cfirst[lo_] / LEAF_BLOCK + (ri - coff[lo_]);
+        lf = max(cfirst[lo_], run * LEAF_BLOCK);
+        const int ll = min(cend[lo_], run * LEAF_BLOCK + LEAF_BLOCK);
+        // the run's box against A's, nearest periodic image per axis
+        const int4 blo = block_box[2 * run], bhi = block_box[2 * run + 1];
+        const int64_t rl[3] = {blo.x, blo.y, blo.z}, rh[3] = {bhi.x, bhi.y, bhi.z};
+        double d2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+          int64_t best = INT64_MAX;
+          for (int k = -1; k <= 1; ++k) {
+            const int64_t s = (int64_t)k * g.nu;
+            int64_t gap = rl[d] + s - (ca[d] + hwa);
+            const int64_t g2 = (ca[d] - hwa) - (rh[d] + s);
+            if (g2 > gap) gap = g2;
+            if (gap < 0) gap = 0;
+            if (gap < best) best = gap;
+          }
+          const double gd = (double)best * g.unit;
+          d2 = d2 + gd * gd;
+        }
+        const double Rd = (double)Rreach;
+        if (d2 < Rd * Rd) nl_run = ll - lf;
+      }
+      int incl2 = nl_run;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(incl2, o, 64);
+        if (lane >= o) incl2 += t;
+      }
+      const int total = __shfl(incl2, 63, 64);
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      roff[lane] = incl2 - nl_run;
+      rfirst[lane] = lf;
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
     for (int t0 = 0; t0 < total; t0 += 64) {
       const int fi = t0 + lane;
       bool ok = false;
       int64_t dl[3] = {0, 0, 0};
       int B = 0;
       if (fi < total) {
+        // last run whose leaves start at or before fi (runs out of reach
+        // share the offset of the next one)
         int lo_ = 0, hi_ = 63;
         while (lo_ < hi_) {
           const int mid = (lo_ + hi_ + 1) >> 1;
-          if (coff[mid] <= fi) lo_ = mid; else hi_ = mid - 1;
+          if (roff[mid] <= fi) lo_ = mid; else hi_ = mid - 1;
         }
-        B = cfirst[lo_] + (fi - coff[lo_]);
+        B = rfirst[lo_] + (fi - roff[lo_]);
         int64_t cb[3];
         const int lvB = level[B];
         leaf_centre_units(g.D, lvB, ix[B], iy[B], iz[B], cb);
@@ -231,6 +318,9 @@ __global__ __launch_bounds__(MT) void pairs_kernel(int mode, float slack, PairGe
         if (act_cost) staged += leaf_count[B];
       }
       written += __popcll(mask);
+    }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -304,6 +394,19 @@ sph_status build_pairs_count(sph_ctx *ctx, int which, float slack, int32_t *host
     return SPH_OK;
   }
   const PairGeom g = pair_geom(ctx);
+  if (!ctx->blocks_valid) {
+    // run boxes of the current full build (cell updates keep the leaves)
+    const int64_t nl = ctx->n_leaves, nrun = ceil_div(nl, LEAF_BLOCK);
+    SPH_TRY(sph_ensure(ctx, ctx->block_box, 2 * sizeof(int4) * (size_t)(nrun > 0 ? nrun : 1)));
+    if (nrun > 0) {
+      PROF(ctx, "cell_pairs");
+      leaf_block_box_kernel<<<(unsigned)ceil_div(nrun, MT), MT, 0, ctx->stream>>>(
+          g.D, (const int32_t *)ctx->leaf_level.p, (const int32_t *)ctx->leaf_ix.p, (const int32_t *)ctx->leaf_iy.p,
+          (const int32_t *)ctx->leaf_iz.p, nl, (int4 *)ctx->block_box.p);
+      HIP_TRY(ctx, hipGetLastError());
+    }
+    ctx->blocks_valid = 1;
+  }
   {
     PROF(ctx, "cell_pairs");
     pairs_kernel<false><<<waves_grid(na), MT, 0, ctx->stream>>>(
@@ -311,7 +414,7 @@ sph_status build_pairs_count(sph_ctx *ctx, int which, float slack, int32_t *host
         (const int32_t *)ctx->leaf_level.p, (const int32_t *)ctx->leaf_ix.p, (const int32_t *)ctx->leaf_iy.p,
         (const int32_t *)ctx->leaf_iz.p, (const float *)ctx->leaf_hmax.p, (const int32_t *)ctx->top_first.p,
         (const int32_t *)ctx->top_last.p, (const int32_t *)ctx->scalars.p + SC_HMAX_BITS,
-        (const float *)ctx->leaf_dx.p, ctx->dx_max, (int32_t *)ctx->pair_cnt.p, nullptr, nullptr, nullptr, nullptr);
+        (const float *)ctx->leaf_dx.p, ctx->dx_max, (const int4 *)ctx->block_box.p, (int32_t *)ctx->pair_cnt.p, nullptr, nullptr, nullptr, nullptr);
   }
   HIP_TRY(ctx, hipGetLastError());
   int32_t *o = (int32_t *)off.p;
@@ -335,7 +438,7 @@ sph_status build_pairs_fill(sph_ctx *ctx, int which, float slack, int32_t np) {
         (const int32_t *)ctx->leaf_level.p, (const int32_t *)ctx->leaf_ix.p, (const int32_t *)ctx->leaf_iy.p,
         (const int32_t *)ctx->leaf_iz.p, (const float *)ctx->leaf_hmax.p, (const int32_t *)ctx->top_first.p,
         (const int32_t *)ctx->top_last.p, (const int32_t *)ctx->scalars.p + SC_HMAX_BITS,
-        (const float *)ctx->leaf_dx.p, ctx->dx_max, nullptr,
+        (const float *)ctx->leaf_dx.p, ctx->dx_max, (const int4 *)ctx->block_box.p, nullptr,
         (int32_t *)off.p, (PairEntry *)lst.p, (const int32_t *)ctx->leaf_count.p,
         which == 0 ? (int32_t *)ctx->act_cost.p : nullptr);
   }

@@ -66,35 +66,48 @@ __device__ __forceinline__ int wave_inclusive_scan(int v) {
 }
 
 // WRITE=false: per-block totals.  WRITE=true: exclusive scan of the tile plus
-// the block offset (or 0), and the grand total from the last block.
+// the block offset (or 0), and the grand total from the last block.  Each
+// thread owns SCAN_ROUNDS consecutive elements: a serial sum in registers,
+// one block-wide scan of the thread sums, then a serial write-out (no
+// barrier per round).  In-place use (in == out) is safe: a thread reads its
+// elements before it writes them.
 template <bool WRITE>
-__global__ __launch_bounds__(SCAN_THREADS) void scan_kernel(const int32_t *__restrict__ in, int32_t *__restrict__ out,
-                                                            int64_t n, int32_t *__restrict__ block_sums,
+__global__ __launch_bounds__(SCAN_THREADS) void scan_kernel(const int32_t *in, int32_t *out, int64_t n,
+                                                            int32_t *__restrict__ block_sums,
                                                             const int32_t *__restrict__ block_offsets,
                                                             int32_t *__restrict__ total) {
   __shared__ int wsum[SCAN_THREADS / 64];
   const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
-  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
-  int carry = (WRITE && block_offsets) ? block_offsets[blockIdx.x] : 0;
-  for (int r = 0; r < SCAN_ROUNDS; ++r) {
-    const int64_t i = base + (int64_t)r * SCAN_THREADS + tid;
-    const int v = i < n ? in[i] : 0;
-    const int inc = wave_inclusive_scan(v);
-    if (lane == 63) wsum[wid] = inc;
-    __syncthreads();
-    int wpre = 0, rtot = 0;
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)tid * SCAN_ROUNDS;
+  int v[SCAN_ROUNDS];
+  int s = 0;
 #pragma unroll
-    for (int w = 0; w < SCAN_THREADS / 64; ++w) {
-      const int s = wsum[w];
-      if (w < wid) wpre += s;
-      rtot += s;
-    }
-    if (WRITE && i < n) out[i] = carry + wpre + inc - v;
-    carry += rtot;
-    __syncthreads();
+  for (int r = 0; r < SCAN_ROUNDS; ++r) {
+    v[r] = base + r < n ? in[base + r] : 0;
+    s += v[r];
   }
-  if (!WRITE && tid == 0) block_sums[blockIdx.x] = carry;
-  if (WRITE && total && blockIdx.x == gridDim.x - 1 && tid == 0) *total = carry;
+  const int inc = wave_inclusive_scan(s);
+  if (lane == 63) wsum[wid] = inc;
+  __syncthreads();
+  int wpre = 0, btot = 0;
+#pragma unroll
+  for (int w = 0; w < SCAN_THREADS / 64; ++w) {
+    const int t = wsum[w];
+    if (w < wid) wpre += t;
+    btot += t;
+  }
+  const int carry = (WRITE && block_offsets) ? block_offsets[blockIdx.x] : 0;
+  if (WRITE) {
+    int run = carry + wpre + inc - s;
+#pragma unroll
+    for (int r = 0; r < SCAN_ROUNDS; ++r) {
+      if (base + r < n) out[base + r] = run;
+      run += v[r];
+    }
+    if (total && blockIdx.x == gridDim.x - 1 && tid == 0) *total = carry + btot;
+  } else if (tid == 0) {
+    block_sums[blockIdx.x] = btot;
+  }
 }
 
 static sph_status scan_rec(sph_ctx *ctx, const int32_t *in, int32_t *out, int64_t n, int32_t *total,

@@ -76,6 +76,8 @@ struct sph_ctx {
   DevBuf flags, scan_out, nodes_a, nodes_b, leaf_lvl_at;
   DevBuf leaf_level, leaf_ix, leaf_iy, leaf_iz, leaf_begin, leaf_count, leaf_hmax, leaf_of;
   DevBuf top_first, top_last;
+  DevBuf block_box;                       // per run of LEAF_BLOCK leaves: int4 lo, int4 hi (half-units)
+  int blocks_valid = 0;                   // block_box made for the current full build
   DevBuf pos4;                            // float4 (ox, oy, oz, H) per particle
   DevBuf pos4_build;                      // pos4 of the last full build (the axis sorts' keys)
   // sort
@@ -193,6 +195,7 @@ sph_status build_pairs(sph_ctx *ctx, int which, float slack);
 sph_status build_pairs_count(sph_ctx *ctx, int which, float slack, int32_t *host_total);
 sph_status build_pairs_fill(sph_ctx *ctx, int which, float slack, int32_t np);
 sph_status refresh_leaf_hmax(sph_ctx *ctx);
+#define LEAF_BLOCK 32
 sph_status sort_all_leaves(sph_ctx *ctx);
 sph_status pack_neighbour_data(sph_ctx *ctx, const sph_particles *p);
 sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u);
