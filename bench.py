@@ -451,11 +451,22 @@ def main():
     # active particle is recomputed before it is read, and the step does not
     # write those of inactive particles)
     names = ["x", "y", "z", "vx", "vy", "vz", "vfx", "vfy", "vfz", "A", "Af", "h", "time_bin"]
-    dst = [p[k] for k in names]
-    src = [t.clone() for t in dst]
+    # they are moved into one device buffer (256-byte aligned slices), so
+    # that the restore is a single copy
+    sizes = [p[k].numel() * p[k].element_size() for k in names]
+    offs, tot = [], 0
+    for sz in sizes:
+        offs.append(tot)
+        tot += (sz + 255) // 256 * 256
+    state = torch.empty(tot, dtype=torch.uint8, device="cuda")
+    for k, o, sz in zip(names, offs, sizes):
+        t = state[o:o + sz].view(p[k].dtype)
+        t.copy_(p[k])
+        p[k] = t
+    snapshot = state.clone()
 
     def restore():
-        torch._foreach_copy_(dst, src)
+        state.copy_(snapshot)
 
     def step(s):
         restore()
@@ -573,7 +584,7 @@ def main():
         "roofline": roof,
     }
     if not args.no_extras:
-        del p, ctx, src, dst
+        del p, ctx, state, snapshot
         torch.cuda.empty_cache()
         out["all_active"] = measure_all_active(sg, ic, **kw)
         out["batch"] = measure_batch(sg)

@@ -257,7 +257,7 @@ __global__ __launch_bounds__(BT) void update_kernel(double *__restrict__ x, doub
                                                     int64_t nl, int D, double L, double unit, float frac,
                                                     float4 *__restrict__ pos4, float *__restrict__ leaf_hmax,
                                                     float *__restrict__ leaf_dx, float2 *__restrict__ block_max,
-                                                    int32_t *__restrict__ sc_flag) {
+                                                    int32_t *__restrict__ sc_flag, PackArgs pk) {
   const int64_t l = (int64_t)blockIdx.x * (BT / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   float hm = 0.f, dm = 0.f;
@@ -289,6 +289,7 @@ __global__ __launch_bounds__(BT) void update_kernel(double *__restrict__ x, doub
       const float H = GK32 * h[s];
       pos4[s] = make_float4((float)ox, (float)oy, (float)oz, H);
       hm = fmaxf(hm, H);
+      if (pk.jvm) pack_one(pk, s);  // the loops' neighbour data, in the same pass
     }
     for (int o = 32; o > 0; o >>= 1) d2m = fmax(d2m, __shfl_xor(d2m, o, 64));
     hm = wave_max_f(hm);
@@ -577,6 +578,13 @@ sph_status update_cells(sph_ctx *ctx, sph_particles *p, int64_t *perm_out, int *
   const double *xb = (const double *)ctx->x_build.p;
   const int64_t blocks = ceil_div(nl, BT / 64);
   SPH_TRY(sph_ensure(ctx, ctx->scan_out, sizeof(float2) * (size_t)blocks));
+  // with every array given, the neighbour data are packed in the update pass
+  // (the kernel writes them whether or not the cells are kept: a full build
+  // packs again after its reorder)
+  PackArgs pk;
+  bool pack_all;
+  SPH_TRY(pack_args(ctx, p, &pk, &pack_all));
+  if (!pack_all) pk.jvm = nullptr;
   {
     PROF(ctx, "cell_update");
     update_kernel<<<(unsigned)blocks, BT, 0, ctx->stream>>>(
@@ -584,7 +592,7 @@ sph_status update_cells(sph_ctx *ctx, sph_particles *p, int64_t *perm_out, int *
         (const int32_t *)ctx->leaf_count.p, (const int32_t *)ctx->leaf_level.p, (const int32_t *)ctx->leaf_ix.p,
         (const int32_t *)ctx->leaf_iy.p, (const int32_t *)ctx->leaf_iz.p, nl, D, L, ldexp(L, -(D + 1)),
         ctx->prm.rebuild_frac, (float4 *)ctx->pos4.p, (float *)ctx->leaf_hmax.p, (float *)ctx->leaf_dx.p,
-        (float2 *)ctx->scan_out.p, sc + SC_UPD_FLAG);
+        (float2 *)ctx->scan_out.p, sc + SC_UPD_FLAG, pk);
     max2_reduce_kernel<<<1, BT, 0, ctx->stream>>>((const float2 *)ctx->scan_out.p, (int)blocks, sc + SC_UPD_HMAX);
   }
   HIP_TRY(ctx, hipGetLastError());
@@ -607,7 +615,7 @@ sph_status update_cells(sph_ctx *ctx, sph_particles *p, int64_t *perm_out, int *
     iota_kernel<<<grid_for(n), BT, 0, ctx->stream>>>(perm_out, n);
     HIP_TRY(ctx, hipGetLastError());
   }
-  SPH_TRY(pack_neighbour_data(ctx, p));
+  if (!pack_all) SPH_TRY(pack_neighbour_data(ctx, p));
   ctx->state = 1;
   return SPH_OK;
 }

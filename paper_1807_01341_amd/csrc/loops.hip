@@ -19,6 +19,10 @@ __global__ __launch_bounds__(256) void pack_jvm_kernel(const double *__restrict_
     out[s] = make_float4((float)vx[s], (float)vy[s], (float)vz[s], m[s]);
 }
 
+__global__ __launch_bounds__(256) void pack_kernel(PackArgs a, int64_t n) {
+  for (int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x; s < n; s += (int64_t)gridDim.x * 256) pack_one(a, s);
+}
+
 __global__ __launch_bounds__(256) void pack_jth_kernel(const float *__restrict__ rho, const float *__restrict__ f,
                                                        const float *__restrict__ P, const float *__restrict__ c,
                                                        const float *__restrict__ B, int64_t n,
@@ -326,10 +330,37 @@ LoopArgs base_args(sph_ctx *ctx) {
 // and mass, and the density-loop state (rho, f P/rho^2, c, B) that inactive
 // neighbours keep from their last active step.  The ghost refreshes the
 // latter for every active particle it finishes.
-sph_status pack_neighbour_data(sph_ctx *ctx, const sph_particles *p) {
+sph_status pack_args(sph_ctx *ctx, const sph_particles *p, PackArgs *a, bool *ok) {
   const int64_t n = ctx->n;
   SPH_TRY(sph_ensure(ctx, ctx->jvm, 16 * (size_t)n));
   SPH_TRY(sph_ensure(ctx, ctx->jth, 16 * (size_t)n));
+  *ok = p->vx && p->vy && p->vz && p->m && p->rho && p->f_gradh && p->P && p->c && p->balsara;
+  a->vx = p->vx;
+  a->vy = p->vy;
+  a->vz = p->vz;
+  a->m = p->m;
+  a->rho = p->rho;
+  a->f = p->f_gradh;
+  a->P = p->P;
+  a->c = p->c;
+  a->B = p->balsara;
+  a->jvm = (float4 *)ctx->jvm.p;
+  a->jth = (float4 *)ctx->jth.p;
+  return SPH_OK;
+}
+
+sph_status pack_neighbour_data(sph_ctx *ctx, const sph_particles *p) {
+  const int64_t n = ctx->n;
+  PackArgs pa;
+  bool all;
+  SPH_TRY(pack_args(ctx, p, &pa, &all));
+  if (all) {
+    {
+      PROF(ctx, "pack");
+      pack_kernel<<<grid256(n), 256, 0, ctx->stream>>>(pa, n);
+    }
+    return sph_hip_check(ctx, hipGetLastError(), "pack_kernel");
+  }
   if (p->vx && p->vy && p->vz && p->m) {
     {
       PROF(ctx, "pack");
@@ -615,7 +646,7 @@ __device__ __forceinline__ void density_term(const float4 &pi, const float4 &vi,
 // pair terms evaluated 64 at a time, one per lane, so that the terms run on
 // full waves although few of the candidates tested together are neighbours.
 template <int NWP>
-__global__ __launch_bounds__(256) void density_sweep_kernel(LoopArgs g, const int32_t *__restrict__ todo,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void density_sweep_kernel(LoopArgs g, const int32_t *__restrict__ todo,
                                                             const int32_t *__restrict__ n_todo_dev, int64_t n_todo,
                                                             const int32_t *__restrict__ chunk_of,
                                                             int32_t *__restrict__ next_n) {

@@ -198,6 +198,10 @@ sph_status refresh_leaf_hmax(sph_ctx *ctx);
 #define LEAF_BLOCK 32
 sph_status sort_all_leaves(sph_ctx *ctx);
 sph_status pack_neighbour_data(sph_ctx *ctx, const sph_particles *p);
+struct PackArgs;
+// The pack arguments when every array is given (else *ok = false: the pack
+// kernels fill what is missing with zeros); sizes jvm and jth.
+sph_status pack_args(sph_ctx *ctx, const sph_particles *p, PackArgs *a, bool *ok);
 sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u);
 sph_status force_pass_impl(sph_ctx *ctx, sph_particles *p);
 sph_status batch_density_impl(sph_ctx **cs, sph_particles *ps, int nb, int entropy_from_u);
@@ -211,6 +215,20 @@ sph_status kick_drift_impl(sph_ctx *ctx, sph_particles *p, int64_t ti, double t_
 // ---------------------------------------------------------------- device helpers
 __device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
 // Number of set bits of `mask` below this lane.
+// The loops' packed neighbour data of particle s: (v, m) and the density
+// state (rho, f P / rho^2, c, B).
+struct PackArgs {
+  const double *vx, *vy, *vz;
+  const float *m, *rho, *f, *P, *c, *B;
+  float4 *jvm, *jth;
+};
+
+__device__ __forceinline__ void pack_one(const PackArgs &a, int64_t s) {
+  a.jvm[s] = make_float4((float)a.vx[s], (float)a.vy[s], (float)a.vz[s], a.m[s]);
+  const float r = a.rho[s];
+  a.jth[s] = make_float4(r, a.f[s] * a.P[s] / (r * r), a.c[s], a.B[s]);
+}
+
 __device__ __forceinline__ int rank_below(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
