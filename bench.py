@@ -312,12 +312,7 @@ def run_large(args):
     for t in range(1, S + 1):
         m = min((t & -t).bit_length() - 1, top)
         ts = time.perf_counter()
-        ctx.build_cells(p)
-        ctx.sort_cells()
-        na = ctx.mark_active(p, m)
-        ctx.density_pass(p, entropy_from_u=False)
-        ctx.force_pass(p)
-        ctx.kick_drift(p, t, t_min, 1, False)
+        na = ctx.step(p, m, t, t_min, 1, False, want_count=True)
         ctx.sync()
         dt = time.perf_counter() - ts
         e = per_m.setdefault(m, [0, 0.0, 0])
@@ -470,12 +465,8 @@ def main():
 
     def step(s):
         restore()
-        ctx.build_cells(p)
-        ctx.sort_cells()
-        ctx.mark_active(p, m, want_count=False)
-        ctx.density_pass(p, entropy_from_u=False)
-        ctx.force_pass(p)
-        ctx.kick_drift(p, 3 << m, t_min, 1 << m, False)
+        # build, sort, mark, density, force, kick_drift: one library call
+        ctx.step(p, m, 3 << m, t_min, 1 << m, False)
 
     tuned = None
     if args.load_tune:

@@ -186,6 +186,18 @@ sph_status sph_force_pass(sph_ctx *ctx, sph_particles *p);
 sph_status sph_kick_drift(sph_ctx *ctx, sph_particles *p, int64_t ti, double t_min, int64_t drift_int,
                           int first_step);
 
+/* One whole step of the method (Sec. II-A, Sec. III-D) in one call:
+ * sph_build_cells(p, n, perm_out), sph_sort_cells, sph_mark_active(
+ * max_active_bin, n_active_host), sph_density_pass(entropy_from_u),
+ * sph_force_pass and sph_kick_drift(ti, t_min, drift_int, first_step), with
+ * the same arguments, results and errors as those calls (the first failing
+ * one ends the step and its status is returned), and no return to the caller
+ * between them, so the device does not wait on the caller at the step's
+ * synchronisation points.  perm_out and n_active_host may be NULL. */
+sph_status sph_step(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *perm_out, int max_active_bin,
+                    int64_t *n_active_host, int entropy_from_u, int64_t ti, double t_min, int64_t drift_int,
+                    int first_step);
+
 /* ---- Batched passes: several contexts (independent periodic boxes, or any
  * set of particle systems), each built, sorted and marked by its own calls
  * and all created on the SAME stream, run each loop pass of the density /

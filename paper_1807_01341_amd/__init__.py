@@ -88,6 +88,7 @@ def lib():
             "sph_density_pass": (i32, [vp, vp, i32]),
             "sph_force_pass": (i32, [vp, vp]),
             "sph_kick_drift": (i32, [vp, vp, i64, C.c_double, i64, i32]),
+            "sph_step": (i32, [vp, vp, i64, vp, i32, vp, i32, i64, C.c_double, i64, i32]),
             "sph_sync": (i32, [vp]),
             "sph_last_error": (C.c_char_p, [vp]),
             "sph_info": (i32, [vp, vp]),
@@ -119,7 +120,7 @@ def exported_symbols():
             "sph_last_error", "sph_info", "sph_copy_leaves", "sph_copy_particles", "sph_copy_axis_order",
             "sph_copy_active", "sph_copy_pairs", "sph_profile", "sph_profile_read", "sph_autotune",
             "sph_load_tuning", "sph_adjoint", "sph_batch_density_pass", "sph_batch_force_pass",
-            "sph_batch_autotune"]
+            "sph_batch_autotune", "sph_step"]
 
 
 def require_device():
@@ -278,6 +279,17 @@ class Context:
     def kick_drift(self, p: Particles, ti: int, t_min: float, drift_int: int, first_step: bool):
         return self._check(lib().sph_kick_drift(self.h, self._pcs(p), int(ti), float(t_min), int(drift_int),
                                                 int(bool(first_step))))
+
+    def step(self, p: Particles, max_active_bin: int, ti: int, t_min: float, drift_int: int, first_step: bool,
+             entropy_from_u: bool = False, perm_out: torch.Tensor | None = None, want_count: bool = False):
+        """build_cells, sort_cells, mark_active, density_pass, force_pass and
+        kick_drift in one library call; returns the number of active
+        particles with want_count (else -1)."""
+        n = C.c_int64(-1)
+        self._check(lib().sph_step(self.h, self._pcs(p), p.n, _ptr(perm_out), int(max_active_bin),
+                                   C.byref(n) if want_count else None, int(bool(entropy_from_u)), int(ti),
+                                   float(t_min), int(drift_int), int(bool(first_step))))
+        return n.value
 
     def adjoint(self, p: Particles, w: torch.Tensor):
         """dL/dx (N,3) float64 and dL/du (N,) float32 of L = sum_i w_i . a_i

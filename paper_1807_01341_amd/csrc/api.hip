@@ -220,6 +220,17 @@ sph_status sph_kick_drift(sph_ctx *ctx, sph_particles *p, int64_t ti, double t_m
   return kick_drift_impl(ctx, p, ti, t_min, drift_int, first_step);
 }
 
+sph_status sph_step(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *perm_out, int max_active_bin,
+                    int64_t *n_active_host, int entropy_from_u, int64_t ti, double t_min, int64_t drift_int,
+                    int first_step) {
+  SPH_TRY(sph_build_cells(ctx, p, n, perm_out));
+  SPH_TRY(sph_sort_cells(ctx));
+  SPH_TRY(sph_mark_active(ctx, p, max_active_bin, n_active_host));
+  SPH_TRY(sph_density_pass(ctx, p, entropy_from_u));
+  SPH_TRY(sph_force_pass(ctx, p));
+  return sph_kick_drift(ctx, p, ti, t_min, drift_int, first_step);
+}
+
 sph_status sph_sync(sph_ctx *ctx) {
   if (!ctx) return SPH_EINVAL;
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));

@@ -216,3 +216,29 @@ def test_unsorted_small_leaves_match_full_sorts(gpu_lib):
         out.append({k: host(p, k).copy() for k in ("h", "rho", "ax", "ay", "az", "vsig", "nngb_density", "nngb_force")})
     for k in out[0]:
         assert np.array_equal(out[0][k].view(np.uint8), out[1][k].view(np.uint8)), k
+
+
+def test_step_call_equals_separate_calls(gpu_lib):
+    """sph_step gives the same bits as its six calls made one by one, over two
+    steps (the second on kept cells)."""
+    sg = gpu_lib
+    ic = ics.tiny_lattice(16, velocity_sigma=0.1)
+    ic["bin"] = np.random.default_rng(3).integers(0, 4, size=ic["x"].shape[0]).astype(np.int8)
+    out = []
+    for fused in (False, True):
+        p = sg.Particles.from_initial(ic)
+        ctx = sg.Context(split_count=64)
+        for t, (m, first) in enumerate(((ctx.params.n_bins - 1, True), (0, False))):
+            if fused:
+                ctx.step(p, m, t, 1e-4, 1, first, entropy_from_u=first)
+            else:
+                ctx.build_cells(p)
+                ctx.sort_cells()
+                ctx.mark_active(p, m)
+                ctx.density_pass(p, first)
+                ctx.force_pass(p)
+                ctx.kick_drift(p, t, 1e-4, 1, first)
+        ctx.sync()
+        out.append({k: host(p, k).copy() for k in ("x", "vx", "h", "rho", "ax", "vsig", "time_bin", "nngb_force")})
+    for k in out[0]:
+        assert np.array_equal(out[0][k].view(np.uint8), out[1][k].view(np.uint8)), k
