@@ -548,6 +548,18 @@ struct SweepPair {
   float sx, sy, sz;
 };
 
+// Logical block of a sweep launch whose grid is a multiple of 8: the blocks
+// the dispatcher sends to one XCD (blockIdx % 8) take one contiguous range of
+// the nblk blocks of work, so particles that share partner leaves read them
+// from the same L2.  Returns -1 for a block beyond the work.
+__device__ __forceinline__ int64_t xcd_block(int64_t nblk) {
+  const int64_t per = (nblk + 7) >> 3;
+  const int64_t lb = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  return lb < nblk ? lb : -1;
+}
+
+static unsigned xcd_grid(int64_t nblk) { return (unsigned)(8 * std::max<int64_t>(1, (nblk + 7) / 8)); }
+
 // The partners of up to 64 cell pairs (one per lane) that a wave reads as one
 // flat candidate range: those with `small` set, compacted into `my` in lane
 // order with their first flat index.  ns entries; steps = ceil(log2(ns)).
@@ -655,10 +667,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void d
   __shared__ float red[4][9];
   const int wave = threadIdx.x >> 6;
   const int sub = wave % NWP;
-  const int64_t w = (int64_t)blockIdx.x * (4 / NWP) + wave / NWP;
   if (n_todo_dev) n_todo = *n_todo_dev;
   // the next pass's list starts empty (its ghost appends after this launch)
   if (next_n && blockIdx.x == 0 && threadIdx.x == 0) *next_n = 0;
+  const int64_t lb = xcd_block(ceil_div(n_todo, 4 / NWP));
+  const int64_t w = lb < 0 ? n_todo : lb * (4 / NWP) + wave / NWP;
   const int lane = threadIdx.x & 63;
   if (w < n_todo) {
   SweepPair *my = sp[wave];
@@ -867,7 +880,8 @@ __global__ __launch_bounds__(256) void force_sweep_kernel(LoopArgs g, const int3
   const int wave = threadIdx.x >> 6;
   const int sub = wave % NWP;
   const int lane = threadIdx.x & 63;
-  const int64_t k = (int64_t)blockIdx.x * (4 / NWP) + wave / NWP;
+  const int64_t lb = xcd_block(ceil_div(g.n_active, 4 / NWP));
+  const int64_t k = lb < 0 ? g.n_active : lb * (4 / NWP) + wave / NWP;
   int cnt = 0;
   if (k < g.n_active) {
     SweepPair *my = sp[wave];
@@ -1232,7 +1246,7 @@ sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u)
         // loop (whose chunk flags the sweep leaves as they are).
         PROF(ctx, "density_loop");
         const int nwp = sweep_waves(ctx, n_todo);
-        const unsigned grid = (unsigned)std::max<int64_t>(1, ceil_div(n_todo * nwp, 4));
+        const unsigned grid = xcd_grid(ceil_div(n_todo * nwp, 4));
         const int32_t *tl = pass > 1 ? list : nullptr, *tn = pass > 1 ? list_n + (pass & 1) : nullptr;
         const int32_t *co = (const int32_t *)ctx->chunk_of.p;
         if (nwp == 4)
@@ -1316,7 +1330,7 @@ sph_status force_pass_impl(sph_ctx *ctx, sph_particles *p) {
     {
       PROF(ctx, "force_loop");
       const int nwp = sweep_waves(ctx, ctx->n_active);
-      const unsigned grid = (unsigned)ceil_div(ctx->n_active * nwp, 4);
+      const unsigned grid = xcd_grid(ceil_div(ctx->n_active * nwp, 4));
       if (nwp == 4)
         force_sweep_kernel<4><<<grid, 256, 0, ctx->stream>>>(a, (const int32_t *)ctx->chunk_of.p);
       else if (nwp == 2)
