@@ -548,6 +548,23 @@ struct SweepPair {
   float sx, sy, sz;
 };
 
+// Sweep axis of a cell pair: the stencil direction closest to the pair
+// offset, and the side (sign) the partner lies on.
+__device__ __forceinline__ void sweep_axis(const AxisTab &ax, float sx, float sy, float sz, int &axis, float &sgn) {
+  axis = 0;
+  sgn = 1.f;
+  float best = -1.f;
+#pragma unroll
+  for (int a = 0; a < 13; ++a) {
+    const float d = fmaf(sz, ax.e[a][2], fmaf(sy, ax.e[a][1], sx * ax.e[a][0]));
+    if (fabsf(d) > best) {
+      best = fabsf(d);
+      axis = a;
+      sgn = d >= 0.f ? 1.f : -1.f;
+    }
+  }
+}
+
 // Logical block of a sweep launch whose grid is a multiple of 8: the blocks
 // the dispatcher sends to one XCD (blockIdx % 8) take one contiguous range of
 // the nblk blocks of work, so particles that share partner leaves read them
@@ -729,6 +746,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void d
       near = leaf_in_reach(g, e, pi, Hi);
     }
     const bool big = near && e.b != ch.leaf && bc > 128;
+    int axl = 0;
+    float sgl = 1.f;
+    if (big) sweep_axis(g.ax, e.sx, e.sy, e.sz, axl, sgl);
     // the small partners within reach as one flat range
     const FlatRange fr = compact_small(my, near && !big, bc, bb, e, lane);
     for (int t = sub * 64; t < fr.total; t += 2 * NWP * 64) {
@@ -752,17 +772,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void d
       if ((nb++ % NWP) != sub) continue;
       const int bbq = __shfl(bb, src, 64), bcq = __shfl(bc, src, 64), Bq = __shfl(e.b, src, 64);
       const float sx = __shfl(e.sx, src, 64), sy = __shfl(e.sy, src, 64), sz = __shfl(e.sz, src, 64);
-      int axis = 0;
-      float best = -1.f, sgn = 1.f;
-#pragma unroll
-      for (int a = 0; a < 13; ++a) {
-        const float d = fmaf(sz, g.ax.e[a][2], fmaf(sy, g.ax.e[a][1], sx * g.ax.e[a][0]));
-        if (fabsf(d) > best) {
-          best = fabsf(d);
-          axis = a;
-          sgn = d >= 0.f ? 1.f : -1.f;
-        }
-      }
+      // the partner's sweep axis, found by its own lane in the pair phase
+      const int axis = __builtin_amdgcn_readfirstlane(__shfl(axl, src, 64));
+      const float sgn = __shfl(sgl, src, 64);
       const float ex = g.ax.e[axis][0], ey = g.ax.e[axis][1], ez = g.ax.e[axis][2];
       const float pp = fmaf(pi.z, ez, fmaf(pi.y, ey, pi.x * ex));
       const float sproj = fmaf(sz, ez, fmaf(sy, ey, sx * ex));
@@ -952,6 +964,9 @@ __global__ __launch_bounds__(256) void force_sweep_kernel(LoopArgs g, const int3
         near = leaf_in_reach(g, e, pi, fmaxf(Hi, g.leaf_hmax[e.b]));
       }
       const bool big = near && e.b != ch.leaf && bc > 128;
+      int axl = 0;
+      float sgl = 1.f;
+      if (big) sweep_axis(g.ax, e.sx, e.sy, e.sz, axl, sgl);
       const FlatRange fr = compact_small(my, near && !big, bc, bb, e, lane);
       for (int t = sub * 64; t < fr.total; t += 2 * NWP * 64) {
         // two candidates per lane, their loads in flight together
@@ -971,17 +986,8 @@ __global__ __launch_bounds__(256) void force_sweep_kernel(LoopArgs g, const int3
         if ((nb++ % NWP) != sub) continue;
         const int bbq = __shfl(bb, src, 64), bcq = __shfl(bc, src, 64), Bq = __shfl(e.b, src, 64);
         const float sx = __shfl(e.sx, src, 64), sy = __shfl(e.sy, src, 64), sz = __shfl(e.sz, src, 64);
-        int axis = 0;
-        float best = -1.f, sgn = 1.f;
-#pragma unroll
-        for (int a = 0; a < 13; ++a) {
-          const float d = fmaf(sz, g.ax.e[a][2], fmaf(sy, g.ax.e[a][1], sx * g.ax.e[a][0]));
-          if (fabsf(d) > best) {
-            best = fabsf(d);
-            axis = a;
-            sgn = d >= 0.f ? 1.f : -1.f;
-          }
-        }
+        const int axis = __builtin_amdgcn_readfirstlane(__shfl(axl, src, 64));
+        const float sgn = __shfl(sgl, src, 64);
         const float ex = g.ax.e[axis][0], ey = g.ax.e[axis][1], ez = g.ax.e[axis][2];
         const float Rb = fmaxf(Hi, g.leaf_hmax[Bq]);
         const float pp = fmaf(pi.z, ez, fmaf(pi.y, ey, pi.x * ex));
