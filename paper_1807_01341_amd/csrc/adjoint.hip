@@ -182,6 +182,7 @@ sph_status adjoint_impl(sph_ctx *ctx, sph_particles *p, const float *wx, const f
   LoopArgs a = base_args(ctx);
   a.pair_off = (const int32_t *)ctx->fpair_off.p;
   a.pairs = (const PairEntry *)ctx->fpairs.p;
+  a.pair_axis = (const uint8_t *)ctx->fpair_axis.p;
   a.jw = (const float4 *)ctx->adj_w.p;
   a.outp = fa;
   SPH_TRY(adjoint_loop<2>(ctx, a, "adjoint_force"));
@@ -216,6 +217,7 @@ sph_status adjoint_impl(sph_ctx *ctx, sph_particles *p, const float *wx, const f
   a = base_args(ctx);
   a.pair_off = (const int32_t *)ctx->dpair_off.p;
   a.pairs = (const PairEntry *)ctx->dpairs.p;
+  a.pair_axis = (const uint8_t *)ctx->dpair_axis.p;
   a.outp = ds;
   SPH_TRY(adjoint_loop<3>(ctx, a, "adjoint_density_h"));
   {
@@ -229,6 +231,7 @@ sph_status adjoint_impl(sph_ctx *ctx, sph_particles *p, const float *wx, const f
   a = base_args(ctx);
   a.pair_off = (const int32_t *)ctx->fpair_off.p;
   a.pairs = (const PairEntry *)ctx->fpairs.p;
+  a.pair_axis = (const uint8_t *)ctx->fpair_axis.p;
   a.jadj1 = (const float4 *)ctx->adj1.p;
   a.jadj2 = (const float4 *)ctx->adj2.p;
   a.outp = da;

@@ -11,33 +11,10 @@
 
 #define AS_THREADS 256
 
-struct AxisSet {
-  float e[13][3];
-};
-
-// Directions (dx, dy, dz) in {-1,0,1}^3 with the first non-zero component
-// positive, in lexicographic order, normalised in double and rounded to float.
-static AxisSet make_axes() {
-  AxisSet a;
-  int k = 0;
-  for (int dx = -1; dx <= 1; ++dx)
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dz = -1; dz <= 1; ++dz) {
-        const int first = dx != 0 ? dx : (dy != 0 ? dy : dz);
-        if (first <= 0) continue;
-        const double nrm = sqrt((double)(dx * dx + dy * dy + dz * dz));
-        a.e[k][0] = (float)(dx / nrm);
-        a.e[k][1] = (float)(dy / nrm);
-        a.e[k][2] = (float)(dz / nrm);
-        ++k;
-      }
-  return a;
-}
-
 // Workgroup LDS bitonic sort for leaves of 513..4096 particles (only at the
 // maximum depth, where coincident particles cannot be split further).
 template <int P>
-__device__ void sort_leaf_lds(const float4 *__restrict__ pos4, int b, int cnt, int64_t n, const AxisSet &ax,
+__device__ void sort_leaf_lds(const float4 *__restrict__ pos4, int b, int cnt, int64_t n, const AxisTab &ax,
                               uint16_t *__restrict__ order, float *ox, float *oy, float *oz, float *key,
                               uint16_t *idx) {
   int size = 2;
@@ -89,7 +66,7 @@ template <int P>
 __global__ __launch_bounds__(AS_THREADS) void axis_sort_kernel(const float4 *__restrict__ pos4,
                                                                const int32_t *__restrict__ leaf_begin,
                                                                const int32_t *__restrict__ leaf_count, int64_t nl,
-                                                               int64_t n, AxisSet ax, int min_count,
+                                                               int64_t n, AxisTab ax, int min_count,
                                                                uint16_t *__restrict__ order) {
   __shared__ float ox[P], oy[P], oz[P];
   __shared__ float key[P];
@@ -157,7 +134,7 @@ __device__ __forceinline__ void wave_bitonic(uint64_t (&w)[E], int lane) {
 
 template <int E>
 __device__ __forceinline__ void sort_leaf_axes(const float4 *__restrict__ pos4, int b, int cnt, int64_t n,
-                                               const AxisSet &ax, uint16_t *__restrict__ order, int lane,
+                                               const AxisTab &ax, uint16_t *__restrict__ order, int lane,
                                                int a_first, int a_end) {
   float ox[E], oy[E], oz[E];
 #pragma unroll
@@ -194,7 +171,7 @@ __device__ __forceinline__ void sort_leaf_axes(const float4 *__restrict__ pos4, 
 __global__ __launch_bounds__(256) void axis_sort_wave_kernel(const float4 *__restrict__ pos4,
                                                              const int32_t *__restrict__ leaf_begin,
                                                              const int32_t *__restrict__ leaf_count, int64_t nl,
-                                                             int64_t n, AxisSet ax, int min_count,
+                                                             int64_t n, AxisTab ax, int min_count,
                                                              uint16_t *__restrict__ order) {
   const int lane = threadIdx.x & 63;
   // work item = (leaf, axis): the 13 sorts of a leaf run on 13 waves
@@ -220,7 +197,7 @@ __global__ __launch_bounds__(256) void axis_sort_wave_kernel(const float4 *__res
 static sph_status sort_leaves(sph_ctx *ctx, int min_count) {
   const int64_t n = ctx->n, nl = ctx->n_leaves;
   if (nl <= 0 || ctx->max_leaf < min_count) return SPH_OK;
-  const AxisSet ax = make_axes();
+  const AxisTab ax = host_axes();
   {
     PROF(ctx, "axis_sort");
     const int64_t blocks = std::min<int64_t>(ceil_div(13 * nl, 4), (int64_t)ctx->n_cu * 8);

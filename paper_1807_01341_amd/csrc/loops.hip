@@ -548,23 +548,6 @@ struct SweepPair {
   float sx, sy, sz;
 };
 
-// Sweep axis of a cell pair: the stencil direction closest to the pair
-// offset, and the side (sign) the partner lies on.
-__device__ __forceinline__ void sweep_axis(const AxisTab &ax, float sx, float sy, float sz, int &axis, float &sgn) {
-  axis = 0;
-  sgn = 1.f;
-  float best = -1.f;
-#pragma unroll
-  for (int a = 0; a < 13; ++a) {
-    const float d = fmaf(sz, ax.e[a][2], fmaf(sy, ax.e[a][1], sx * ax.e[a][0]));
-    if (fabsf(d) > best) {
-      best = fabsf(d);
-      axis = a;
-      sgn = d >= 0.f ? 1.f : -1.f;
-    }
-  }
-}
-
 // Logical block of a sweep launch whose grid is a multiple of 8: the blocks
 // the dispatcher sends to one XCD (blockIdx % 8) take one contiguous range of
 // the nblk blocks of work, so particles that share partner leaves read them
@@ -748,7 +731,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void d
     const bool big = near && e.b != ch.leaf && bc > 128;
     int axl = 0;
     float sgl = 1.f;
-    if (big) sweep_axis(g.ax, e.sx, e.sy, e.sz, axl, sgl);
+    if (big) {
+      const uint8_t code = g.pair_axis[p];
+      axl = code & 0x7f;
+      sgl = (code & 0x80) ? -1.f : 1.f;
+    }
     // the small partners within reach as one flat range
     const FlatRange fr = compact_small(my, near && !big, bc, bb, e, lane);
     for (int t = sub * 64; t < fr.total; t += 2 * NWP * 64) {
@@ -966,7 +953,11 @@ __global__ __launch_bounds__(256) void force_sweep_kernel(LoopArgs g, const int3
       const bool big = near && e.b != ch.leaf && bc > 128;
       int axl = 0;
       float sgl = 1.f;
-      if (big) sweep_axis(g.ax, e.sx, e.sy, e.sz, axl, sgl);
+      if (big) {
+      const uint8_t code = g.pair_axis[p];
+      axl = code & 0x7f;
+      sgl = (code & 0x80) ? -1.f : 1.f;
+    }
       const FlatRange fr = compact_small(my, near && !big, bc, bb, e, lane);
       for (int t = sub * 64; t < fr.total; t += 2 * NWP * 64) {
         // two candidates per lane, their loads in flight together
@@ -1115,6 +1106,7 @@ LoopArgs density_loop_args(sph_ctx *ctx) {
   LoopArgs a = base_args(ctx);
   a.pair_off = (const int32_t *)ctx->dpair_off.p;
   a.pairs = (const PairEntry *)ctx->dpairs.p;
+  a.pair_axis = (const uint8_t *)ctx->dpair_axis.p;
   a.sums = (float *)ctx->sums.p;
   a.act_cnt = (int32_t *)ctx->sums.p + 8 * ctx->n_active;
   return a;
@@ -1303,6 +1295,7 @@ LoopArgs force_loop_args(sph_ctx *ctx, sph_particles *p) {
   LoopArgs a = base_args(ctx);
   a.pair_off = (const int32_t *)ctx->fpair_off.p;
   a.pairs = (const PairEntry *)ctx->fpairs.p;
+  a.pair_axis = (const uint8_t *)ctx->fpair_axis.p;
   a.ax_out = p->ax;
   a.ay_out = p->ay;
   a.az_out = p->az;

@@ -27,26 +27,6 @@
 #include "sph_internal.h"
 
 
-struct AxisTab {
-  float e[13][3];
-};
-
-inline AxisTab host_axes() {
-  AxisTab a;
-  int k = 0;
-  for (int dx = -1; dx <= 1; ++dx)
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dz = -1; dz <= 1; ++dz) {
-        const int first = dx != 0 ? dx : (dy != 0 ? dy : dz);
-        if (first <= 0) continue;
-        const double nrm = sqrt((double)(dx * dx + dy * dy + dz * dz));
-        a.e[k][0] = (float)(dx / nrm);
-        a.e[k][1] = (float)(dy / nrm);
-        a.e[k][2] = (float)(dz / nrm);
-        ++k;
-      }
-  return a;
-}
 
 struct LoopArgs {
   const Chunk *chunks;
@@ -71,6 +51,7 @@ struct LoopArgs {
   const float *leaf_dx;    // drift margin of each leaf
   const int32_t *pair_off;
   const PairEntry *pairs;
+  const uint8_t *pair_axis;  // per pair: sweep axis code
   const uint16_t *axis_order;
   int64_t n;
   AxisTab ax;
@@ -472,19 +453,14 @@ __device__ __forceinline__ void chunk_body(const LoopArgs &g, int code, bool cod
     const int bb = g.leaf_begin[B], bc = g.leaf_count[B];
     const bool selfp = (B == ch.leaf);
     const float Rb = !ModeTraits<MODE>::sym ? Rc : fmaxf(Rc, g.leaf_hmax[B]);
-    // sweep axis: the stencil direction closest to the pair offset
+    // sweep axis: the stencil direction closest to the pair offset (coded
+    // when the pair list was filled)
     int axis = 0;
-    float best = -1.f, sgn = 1.f;
+    float sgn = 1.f;
     if (!selfp) {
-#pragma unroll
-      for (int a = 0; a < 13; ++a) {
-        const float d = fmaf(e.sz, g.ax.e[a][2], fmaf(e.sy, g.ax.e[a][1], e.sx * g.ax.e[a][0]));
-        if (fabsf(d) > best) {
-          best = fabsf(d);
-          axis = a;
-          sgn = d >= 0.f ? 1.f : -1.f;
-        }
-      }
+      const int code = __builtin_amdgcn_readfirstlane((int)g.pair_axis[pp]);
+      axis = code & 0x7f;
+      sgn = (code & 0x80) ? -1.f : 1.f;
     }
     const float ex = g.ax.e[axis][0], ey = g.ax.e[axis][1], ez = g.ax.e[axis][2];
     // reach of the chunk box along the axis, in the partner leaf's frame

@@ -155,7 +155,8 @@ __global__ __launch_bounds__(MT) void pairs_kernel(int mode, float slack, PairGe
                                                    const float *__restrict__ leaf_dx, float dx_max,
                                                    const int4 *__restrict__ block_box,
                                                    int32_t *__restrict__ counts, const int32_t *__restrict__ offs,
-                                                   PairEntry *__restrict__ out, const int32_t *__restrict__ leaf_count,
+                                                   PairEntry *__restrict__ out, uint8_t *__restrict__ out_axis,
+                                                   AxisTab ax, const int32_t *__restrict__ leaf_count,
                                                    int32_t *__restrict__ act_cost) {
   const int64_t a = (int64_t)blockIdx.x * (MT / 64) + (threadIdx.x >> 6);
   if (a >= n_act_leaves) return;
@@ -315,6 +316,7 @@ __global__ __launch_bounds__(MT) void pairs_kernel(int mode, float slack, PairGe
         pe.sy = (float)((double)dl[1] * g.unit);
         pe.sz = (float)((double)dl[2] * g.unit);
         out[base + written + rank_below(mask)] = pe;
+        out_axis[base + written + rank_below(mask)] = sweep_axis_code(ax, pe.sx, pe.sy, pe.sz);
         if (act_cost) staged += leaf_count[B];
       }
       written += __popcll(mask);
@@ -414,7 +416,8 @@ sph_status build_pairs_count(sph_ctx *ctx, int which, float slack, int32_t *host
         (const int32_t *)ctx->leaf_level.p, (const int32_t *)ctx->leaf_ix.p, (const int32_t *)ctx->leaf_iy.p,
         (const int32_t *)ctx->leaf_iz.p, (const float *)ctx->leaf_hmax.p, (const int32_t *)ctx->top_first.p,
         (const int32_t *)ctx->top_last.p, (const int32_t *)ctx->scalars.p + SC_HMAX_BITS,
-        (const float *)ctx->leaf_dx.p, ctx->dx_max, (const int4 *)ctx->block_box.p, (int32_t *)ctx->pair_cnt.p, nullptr, nullptr, nullptr, nullptr);
+        (const float *)ctx->leaf_dx.p, ctx->dx_max, (const int4 *)ctx->block_box.p, (int32_t *)ctx->pair_cnt.p,
+        nullptr, nullptr, nullptr, AxisTab(), nullptr, nullptr);
   }
   HIP_TRY(ctx, hipGetLastError());
   int32_t *o = (int32_t *)off.p;
@@ -427,9 +430,11 @@ sph_status build_pairs_fill(sph_ctx *ctx, int which, float slack, int32_t np) {
   const int64_t na = ctx->n_active_leaves;
   DevBuf &off = which == 0 ? ctx->dpair_off : ctx->fpair_off;
   DevBuf &lst = which == 0 ? ctx->dpairs : ctx->fpairs;
+  DevBuf &axl = which == 0 ? ctx->dpair_axis : ctx->fpair_axis;
   if (which == 0) ctx->n_dpairs = np; else ctx->n_fpairs = np;
   if (na == 0) return SPH_OK;
   SPH_TRY(sph_ensure(ctx, lst, sizeof(PairEntry) * (size_t)(np > 0 ? np : 1)));
+  SPH_TRY(sph_ensure(ctx, axl, (size_t)(np > 0 ? np : 1)));
   const PairGeom g = pair_geom(ctx);
   {
     PROF(ctx, "cell_pairs");
@@ -439,7 +444,7 @@ sph_status build_pairs_fill(sph_ctx *ctx, int which, float slack, int32_t np) {
         (const int32_t *)ctx->leaf_iz.p, (const float *)ctx->leaf_hmax.p, (const int32_t *)ctx->top_first.p,
         (const int32_t *)ctx->top_last.p, (const int32_t *)ctx->scalars.p + SC_HMAX_BITS,
         (const float *)ctx->leaf_dx.p, ctx->dx_max, (const int4 *)ctx->block_box.p, nullptr,
-        (int32_t *)off.p, (PairEntry *)lst.p, (const int32_t *)ctx->leaf_count.p,
+        (int32_t *)off.p, (PairEntry *)lst.p, (uint8_t *)axl.p, host_axes(), (const int32_t *)ctx->leaf_count.p,
         which == 0 ? (int32_t *)ctx->act_cost.p : nullptr);
   }
   HIP_TRY(ctx, hipGetLastError());

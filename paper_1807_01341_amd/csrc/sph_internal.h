@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdint.h>
 
 #include <string>
@@ -36,6 +37,49 @@ struct PairEntry {
   int32_t b;
   float sx, sy, sz;
 };
+
+// The 13 directions (dx, dy, dz) in {-1,0,1}^3 of the half neighbour stencil
+// (first non-zero component positive, lexicographic order), normalised in
+// double and rounded to float: the axes of the per-leaf sorts.
+struct AxisTab {
+  float e[13][3];
+};
+
+inline AxisTab host_axes() {
+  AxisTab a;
+  int k = 0;
+  for (int dx = -1; dx <= 1; ++dx)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dz = -1; dz <= 1; ++dz) {
+        const int first = dx != 0 ? dx : (dy != 0 ? dy : dz);
+        if (first <= 0) continue;
+        const double nrm = sqrt((double)(dx * dx + dy * dy + dz * dz));
+        a.e[k][0] = (float)(dx / nrm);
+        a.e[k][1] = (float)(dy / nrm);
+        a.e[k][2] = (float)(dz / nrm);
+        ++k;
+      }
+  return a;
+}
+
+// Sweep axis of a cell pair with shift (sx, sy, sz): the stencil direction
+// closest to the offset, coded as axis | 0x80 when the partner lies on the
+// negative side.  Made once per pair when the lists are filled.
+__device__ __forceinline__ uint8_t sweep_axis_code(const AxisTab &ax, float sx, float sy, float sz) {
+  int axis = 0;
+  bool neg = false;
+  float best = -1.f;
+#pragma unroll
+  for (int a = 0; a < 13; ++a) {
+    const float d = fmaf(sz, ax.e[a][2], fmaf(sy, ax.e[a][1], sx * ax.e[a][0]));
+    if (fabsf(d) > best) {
+      best = fabsf(d);
+      axis = a;
+      neg = !(d >= 0.f);
+    }
+  }
+  return (uint8_t)(axis | (neg ? 0x80 : 0));
+}
 
 struct Chunk {
   int32_t act_leaf;  // index into the active-leaf list
@@ -88,6 +132,7 @@ struct sph_ctx {
   DevBuf active, leaf_nact, leaf_act_off, leaf_actleaf, act_leaves, act_hmax, act_leaf_chunk_off;
   DevBuf active_idx, chunk_of, chunks, chunk_todo;
   DevBuf dpair_off, dpairs, fpair_off, fpairs, pair_cnt;
+  DevBuf dpair_axis, fpair_axis;          // per pair: sweep axis code (sweep_axis_code)
   // loops
   DevBuf jvm;                             // float4 (vx, vy, vz, m)
   DevBuf jth;                             // float4 (rho, f P / rho^2, c, B)
