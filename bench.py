@@ -34,6 +34,30 @@ FP32_UNPACKED = 78.6e12   # one FMA per lane per clock (256 CU x 4 SIMD x 16 lan
 HBM_PEAK = 8.0e12         # bytes/s
 # algorithmic FLOP per interaction of the two loops (mul/add = 1, fma = 2,
 # rsqrt/rcp = 1, compare/select = 0), counted from the pair formulas
+# HBM traffic of the dominant kernel per launch, from two rocprofv3 --pmc
+# runs (FETCH_SIZE, WRITE_SIZE) scaled by the same counters on a plain
+# 512 MiB copy (profiles/force_sweep_deepbin_pmc.md), valid while the
+# kernel's sources are the ones that were measured (else reported as null)
+MEASURED_TRAFFIC = {
+    "force_loop": {"bytes": 15039254.0,
+                   "sources": ["paper_1807_01341_amd/csrc/loops.hip", "paper_1807_01341_amd/csrc/loops_common.h",
+                               "paper_1807_01341_amd/csrc/sph_internal.h"],
+                   "sha256": "9ba547684024b583028590e37d3eaa1db1bf2927eb93cd038df4c0bf70164249"},
+}
+
+
+def measured_traffic(kernel):
+    import hashlib
+    m = MEASURED_TRAFFIC.get(kernel)
+    if m is None:
+        return None
+    h = hashlib.sha256()
+    for f in m["sources"]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return m["bytes"] if h.hexdigest() == m["sha256"] else None
+
+
 FLOP_DENSITY = 60
 FLOP_FORCE = 72
 
@@ -535,10 +559,10 @@ def main():
         achieved = per_launch / dur
         if bound == "alu":
             roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": FP32_PEAK / 1e12, "unit": "TFLOP/s",
-                    "frac": achieved / FP32_PEAK, "traffic": None, "kernel": dom}
+                    "frac": achieved / FP32_PEAK, "traffic": measured_traffic(dom), "kernel": dom}
         else:
             roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK, "traffic": None, "kernel": dom}
+                    "frac": achieved / HBM_PEAK, "traffic": measured_traffic(dom), "kernel": dom}
     loop_ms = sum(prof.get(k, (0, 0.0))[1] for k in ("density_loop", "force_loop")) / ksteps
     flops_step = (FLOP_DENSITY * I_d + FLOP_FORCE * I_f) / args.steps
     out = {
