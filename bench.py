@@ -280,7 +280,7 @@ def run_large(args):
     print(f"generated {ic['x'].shape[0]} particles in {time.perf_counter() - t_gen:.0f} s", file=sys.stderr,
           flush=True)
     N = ic["x"].shape[0]
-    ctx = sg.Context()
+    ctx = sg.Context(lazy_drift=int(args.lazy_drift))
     p = sg.Particles.from_initial(ic)
     del ic
     top = ctx.params.n_bins - 1
@@ -367,8 +367,10 @@ def run_large(args):
         "config": {"workload": f"grf {N} particles (256^3 lattice + Zel'dovich displacement of a P(k)~k^-2.5 "
                                f"field, rms {args.grf_amplitude} spacings; u log-uniform; 14 bins), "
                                f"{S} sub-steps t=1..{S} with max active bin min(ctz(t),13)",
-                   "n_particles": N},
+                   "n_particles": N, "drift": "lazy (needed leaves)" if args.lazy_drift else "all particles"},
         "interactions": inter,
+        "full_builds_in_sweep": k1["full_builds"] - k0["full_builds"],
+        "cell_updates_in_sweep": k1["cell_updates"] - k0["cell_updates"],
         "fp32_peak_frac_sweep": (FLOP_DENSITY * I_sd + FLOP_FORCE * I_sf) / wall / FP32_PEAK,
         "all_active": all_active,
         "per_bin": [{"max_active_bin": m, "sub_steps": e[0], "mean_active": e[2] / e[0],
@@ -399,6 +401,8 @@ def main():
     ap.add_argument("--workload", choices=("deepbin", "large"), default="deepbin")
     ap.add_argument("--substeps", type=int, default=8192, help="large workload: sub-steps of the sweep")
     ap.add_argument("--grf-amplitude", type=float, default=12.0)
+    ap.add_argument("--lazy-drift", action="store_true",
+                    help="large workload: drift only the particles each sub-step needs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy 5 times (for scaling HBM counters)")
     ap.add_argument("--no-extras", action="store_true",

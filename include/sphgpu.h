@@ -84,6 +84,14 @@ typedef struct {
                           times each active leaf's max H, so that smoothing lengths can grow
                           that much in the h solve before the lists are widened, in [1, 2]
                           (1.1) */
+  int lazy_drift;      /* 1: drift only the particles a step needs (Sec. II-A, Sec. III-D):
+                          sph_kick_drift kicks the active particles and advances the time
+                          line; a leaf's particles are drifted to the current time when its
+                          step needs them (active leaves, partners of the cell pairs), so
+                          the caller's x, v, A, h of other particles lag until
+                          sph_drift_all.  Only the library may change the particle state
+                          between steps; batched passes refuse such contexts.  0: every
+                          particle drifts in sph_kick_drift (0) */
 } sph_params;
 
 /* The particle state.  Arrays marked (opt) may be NULL.  build_cells reorders
@@ -239,6 +247,12 @@ sph_status sph_batch_autotune(sph_ctx **ctxs, sph_particles *ps, int n_boxes, co
  * Synchronises twice (cell-pair list sizes). */
 sph_status sph_adjoint(sph_ctx *ctx, sph_particles *p, const float *wx, const float *wy, const float *wz,
                        double *gx, double *gy, double *gz, float *gu);
+
+/* With lazy_drift: drifts every particle still behind the time line to it
+ * (x, v, A, h and the derived offsets), e.g. before the caller reads the
+ * state of all particles.  Without lazy_drift, or before the first build,
+ * nothing to do.  No synchronisation. */
+sph_status sph_drift_all(sph_ctx *ctx, sph_particles *p);
 
 /* Waits for the context's stream and reports a pending device error. */
 sph_status sph_sync(sph_ctx *ctx);

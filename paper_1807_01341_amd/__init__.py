@@ -35,7 +35,8 @@ class Params(C.Structure):
                 ("n_bins", C.c_int), ("split_count", C.c_int), ("morton_depth", C.c_int), ("top_cap", C.c_int),
                 ("h_max_iter", C.c_int), ("compensated", C.c_int), ("cand_cap", C.c_int), ("list_cap", C.c_int),
                 ("waves_per_chunk", C.c_int), ("chunk_split", C.c_int), ("sweep_below", C.c_int),
-                ("sweep_waves", C.c_int), ("rebuild_frac", C.c_float), ("pair_slack", C.c_float)]
+                ("sweep_waves", C.c_int), ("rebuild_frac", C.c_float), ("pair_slack", C.c_float),
+                ("lazy_drift", C.c_int)]
 
 
 # field name, dtype, role
@@ -89,6 +90,7 @@ def lib():
             "sph_force_pass": (i32, [vp, vp]),
             "sph_kick_drift": (i32, [vp, vp, i64, C.c_double, i64, i32]),
             "sph_step": (i32, [vp, vp, i64, vp, i32, vp, i32, i64, C.c_double, i64, i32]),
+            "sph_drift_all": (i32, [vp, vp]),
             "sph_sync": (i32, [vp]),
             "sph_last_error": (C.c_char_p, [vp]),
             "sph_info": (i32, [vp, vp]),
@@ -120,7 +122,7 @@ def exported_symbols():
             "sph_last_error", "sph_info", "sph_copy_leaves", "sph_copy_particles", "sph_copy_axis_order",
             "sph_copy_active", "sph_copy_pairs", "sph_profile", "sph_profile_read", "sph_autotune",
             "sph_load_tuning", "sph_adjoint", "sph_batch_density_pass", "sph_batch_force_pass",
-            "sph_batch_autotune", "sph_step"]
+            "sph_batch_autotune", "sph_step", "sph_drift_all"]
 
 
 def require_device():
@@ -290,6 +292,10 @@ class Context:
                                    C.byref(n) if want_count else None, int(bool(entropy_from_u)), int(ti),
                                    float(t_min), int(drift_int), int(bool(first_step))))
         return n.value
+
+    def drift_all(self, p: Particles):
+        """With lazy drift: bring every particle to the current time."""
+        return self._check(lib().sph_drift_all(self.h, self._pcs(p)))
 
     def adjoint(self, p: Particles, w: torch.Tensor):
         """dL/dx (N,3) float64 and dL/du (N,) float32 of L = sum_i w_i . a_i

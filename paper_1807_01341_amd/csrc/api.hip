@@ -103,6 +103,7 @@ void sph_default_params(sph_params *p) {
   p->list_cap = 96;
   p->rebuild_frac = 0.125f;
   p->pair_slack = 1.1f;
+  p->lazy_drift = 0;
   p->sweep_below = 1 << 18;
 }
 
@@ -113,6 +114,7 @@ sph_status sph_create(const sph_params *p, void *hip_stream, sph_ctx **out) {
       p->top_cap > 8 || p->n_bins < 1 || p->n_bins > 63 || p->h_max_iter < 1 || !(p->eta > 0) ||
       !(p->gamma > 1.0) || p->cand_cap < 64 || p->list_cap < 64 || p->chunk_split < 0 || p->chunk_split > 2 ||
       !(p->rebuild_frac >= 0.f && p->rebuild_frac <= 1.f) || !(p->pair_slack >= 1.f && p->pair_slack <= 2.f) ||
+      !(p->lazy_drift == 0 || p->lazy_drift == 1) ||
       p->sweep_below < 0 ||
       !(p->sweep_waves == 0 || p->sweep_waves == 1 || p->sweep_waves == 2 || p->sweep_waves == 4) ||
       !(p->waves_per_chunk == 0 || p->waves_per_chunk == 1 || p->waves_per_chunk == 2 || p->waves_per_chunk == 4 ||
@@ -229,6 +231,13 @@ sph_status sph_step(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *perm_out
   SPH_TRY(sph_density_pass(ctx, p, entropy_from_u));
   SPH_TRY(sph_force_pass(ctx, p));
   return sph_kick_drift(ctx, p, ti, t_min, drift_int, first_step);
+}
+
+sph_status sph_drift_all(sph_ctx *ctx, sph_particles *p) {
+  if (!ctx) return SPH_EINVAL;
+  if (!p) return sph_fail(ctx, SPH_EINVAL, "drift_all: null particles");
+  if (!ctx->prm.lazy_drift || ctx->n_leaves == 0 || ctx->built_n != ctx->n) return SPH_OK;
+  return drift_leaves(ctx, p, nullptr, nullptr, 0);
 }
 
 sph_status sph_sync(sph_ctx *ctx) {

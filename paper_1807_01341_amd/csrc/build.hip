@@ -242,6 +242,30 @@ __global__ __launch_bounds__(BT) void offsets_kernel(const double *__restrict__ 
 }
 
 // Cell update without a rebuild (the leaves of the last build kept): wraps
+// The FP32 offset of a wrapped position from its kept leaf's centre
+// (cx, cy, cz), by the minimum image, stored with H in p4; returns the largest
+// component of the displacement from the full build's position (minimum
+// image).
+__device__ __forceinline__ double kept_offset(double cx, double cy, double cz, double L, double xw, double yw,
+                                              double zw, double xb, double yb, double zb, float H, float4 &p4) {
+  const double half = 0.5 * L;
+  double ox = xw - cx, oy = yw - cy, oz = zw - cz;
+  ox = ox > half ? ox - L : (ox < -half ? ox + L : ox);
+  oy = oy > half ? oy - L : (oy < -half ? oy + L : oy);
+  oz = oz > half ? oz - L : (oz < -half ? oz + L : oz);
+  double dx = xw - xb, dy = yw - yb, dz = zw - zb;
+  dx = dx > half ? dx - L : (dx < -half ? dx + L : dx);
+  dy = dy > half ? dy - L : (dy < -half ? dy + L : dy);
+  dz = dz > half ? dz - L : (dz < -half ? dz + L : dz);
+  p4 = make_float4((float)ox, (float)oy, (float)oz, H);
+  return fmax(fabs(dx), fmax(fabs(dy), fabs(dz)));
+}
+
+// |displacement| <= sqrt(3) * (largest component), rounded up to float.
+__device__ __forceinline__ float disp_bound(double d2m) {
+  return d2m > 0.0 ? __int_as_float(__float_as_int((float)(d2m * 1.7320508075688772)) + 1) : 0.f;
+}
+
 // the positions, the FP32 offsets from the leaf centre (minimum image), H,
 // the leaf's max H and a bound on its particles' displacement since the last
 // build (sqrt(3) times the largest component, rounded up to float),
@@ -266,7 +290,6 @@ __global__ __launch_bounds__(BT) void update_kernel(double *__restrict__ x, doub
     const double cx = (double)((2 * (int64_t)ix[l] + 1) << sh) * unit;
     const double cy = (double)((2 * (int64_t)iy[l] + 1) << sh) * unit;
     const double cz = (double)((2 * (int64_t)iz[l] + 1) << sh) * unit;
-    const double half = 0.5 * L;
     const int b = begin[l], cnt = count[l];
     double d2m = 0.0;  // largest displacement component
     for (int k = lane; k < cnt; k += 64) {
@@ -277,24 +300,14 @@ __global__ __launch_bounds__(BT) void update_kernel(double *__restrict__ x, doub
       if (xw != x0) x[s] = xw;
       if (yw != y0) y[s] = yw;
       if (zw != z0) z[s] = zw;
-      double ox = xw - cx, oy = yw - cy, oz = zw - cz;
-      ox = ox > half ? ox - L : (ox < -half ? ox + L : ox);
-      oy = oy > half ? oy - L : (oy < -half ? oy + L : oy);
-      oz = oz > half ? oz - L : (oz < -half ? oz + L : oz);
-      double dx = xw - xb[s], dy = yw - yb[s], dz = zw - zb[s];
-      dx = dx > half ? dx - L : (dx < -half ? dx + L : dx);
-      dy = dy > half ? dy - L : (dy < -half ? dy + L : dy);
-      dz = dz > half ? dz - L : (dz < -half ? dz + L : dz);
-      d2m = fmax(d2m, fmax(fabs(dx), fmax(fabs(dy), fabs(dz))));
       const float H = GK32 * h[s];
-      pos4[s] = make_float4((float)ox, (float)oy, (float)oz, H);
+      d2m = fmax(d2m, kept_offset(cx, cy, cz, L, xw, yw, zw, xb[s], yb[s], zb[s], H, pos4[s]));
       hm = fmaxf(hm, H);
       if (pk.jvm) pack_one(pk, s);  // the loops' neighbour data, in the same pass
     }
     for (int o = 32; o > 0; o >>= 1) d2m = fmax(d2m, __shfl_xor(d2m, o, 64));
     hm = wave_max_f(hm);
-    // |displacement| <= sqrt(3) * (largest component), rounded up to float
-    dm = d2m > 0.0 ? __int_as_float(__float_as_int((float)(d2m * 1.7320508075688772)) + 1) : 0.f;
+    dm = disp_bound(d2m);
     if (lane == 0) {
       leaf_hmax[l] = hm;
       leaf_dx[l] = dm;
@@ -351,6 +364,10 @@ __global__ __launch_bounds__(BT) void leaf_half_kernel(const int32_t *__restrict
     half[l] = (float)ldexp(L, -level[l] - 1);
 }
 
+__global__ __launch_bounds__(BT) void fill_i64_kernel(int64_t *__restrict__ out, int64_t n, int64_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x; i < n; i += (int64_t)gridDim.x * BT) out[i] = v;
+}
+
 __global__ __launch_bounds__(BT) void iota_kernel(int64_t *__restrict__ out, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x; i < n; i += (int64_t)gridDim.x * BT) out[i] = i;
 }
@@ -391,13 +408,27 @@ sph_status build_cells_impl(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *
   if (!p->x || !p->y || !p->z || !p->h) return sph_fail(ctx, SPH_EINVAL, "build_cells: x, y, z and h are required");
   const int D = ctx->prm.morton_depth;
   const double L = ctx->prm.box;
-  if (ctx->prm.rebuild_frac > 0.f && ctx->built_n == n && ctx->n_leaves > 0) {
+  const bool have_cells = ctx->built_n == n && ctx->n_leaves > 0;
+  if (ctx->prm.rebuild_frac > 0.f && have_cells) {
     // keep the cells of the last build while every leaf's particles stay
     // within rebuild_frac of its width of where that build saw them
     int rebuild = 0;
-    SPH_TRY(update_cells(ctx, p, perm_out, &rebuild));
-    if (!rebuild) return SPH_OK;
+    if (ctx->prm.lazy_drift) {
+      SPH_TRY(lazy_keep_cells(ctx, &rebuild));
+      if (!rebuild) {
+        if (perm_out) {
+          iota_kernel<<<grid_for(n), BT, 0, ctx->stream>>>(perm_out, n);
+          HIP_TRY(ctx, hipGetLastError());
+        }
+        return SPH_OK;
+      }
+    } else {
+      SPH_TRY(update_cells(ctx, p, perm_out, &rebuild));
+      if (!rebuild) return SPH_OK;
+    }
   }
+  // a full build sees every particle at the current time
+  if (ctx->prm.lazy_drift && have_cells) SPH_TRY(drift_leaves(ctx, p, nullptr, nullptr, 0));
   ctx->n = n;
   ctx->state = 0;
   SPH_TRY(sph_ensure(ctx, ctx->keys_a, 8 * n));
@@ -563,6 +594,297 @@ sph_status build_cells_impl(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *
   ctx->leaves_checked = 0;
   ctx->blocks_valid = 0;
   SPH_TRY(pack_neighbour_data(ctx, p));
+  if (ctx->prm.lazy_drift) SPH_TRY(lazy_init_leaves(ctx, p));
+  ctx->state = 1;
+  return SPH_OK;
+}
+
+// ---------------------------------------------------------------- lazy drift
+//
+// With lazy_drift, sph_kick_drift only kicks the active particles and
+// advances ctx->ti_now by the drift interval; a leaf's particles are drifted
+// when a step needs them (the active leaves at sph_mark_active, the partner
+// leaves of every new cell-pair list), with the drift-all formulas applied
+// over the whole interval since the leaf's last drift: x += vf dt (wrapped),
+// v += a dt, A += dA/dt dt, h *= exp(clip(-div v dt / 3, +-0.2)).  Between
+// drifts a leaf's displacement bound from the full build grows by its speed
+// bound times the elapsed time; that bound is the leaf's drift margin for
+// the pair search and the sweep stops of the step.
+
+struct DriftArgs {
+  double *x, *y, *z, *vx, *vy, *vz;
+  const double *vfx, *vfy, *vfz;
+  const float *ax, *ay, *az, *dA, *divv, *m;
+  float *A, *h;
+  float4 *jvm;
+  double t_min;
+  int64_t ti_now;
+};
+
+// Per leaf (one thread): this step's drift margin (the displacement bound at
+// the current time), the rebuild flag, and block maxima of the margin and of
+// a bound on the leaf's max H (a leaf behind the time line may grow by the
+// clipped h prediction).
+__global__ __launch_bounds__(BT) void lazy_bound_kernel(const int64_t *__restrict__ leaf_ti,
+                                                        const float *__restrict__ vmax,
+                                                        const float *__restrict__ dx_base,
+                                                        const float *__restrict__ leaf_hmax,
+                                                        const int32_t *__restrict__ level, int64_t nl, double L,
+                                                        float frac, int64_t ti_now, double t_min,
+                                                        float *__restrict__ leaf_dx, float2 *__restrict__ block_max,
+                                                        int32_t *__restrict__ sc_flag) {
+  const int64_t l = (int64_t)blockIdx.x * BT + threadIdx.x;
+  float dm = 0.f, hb = 0.f;
+  if (l < nl) {
+    const int64_t t0 = leaf_ti[l];
+    dm = dx_base[l];
+    hb = leaf_hmax[l];
+    if (t0 != ti_now) {
+      const double bnd = (double)dm + (double)vmax[l] * ((double)(ti_now - t0) * t_min);
+      dm = __int_as_float(__float_as_int((float)bnd) + 1);  // rounded up
+      hb = hb * LAZY_HGROW;
+    }
+    leaf_dx[l] = dm;
+    if ((double)dm > (double)frac * ldexp(L, -level[l])) atomicOr(sc_flag, 1);
+  }
+  dm = wave_max_f(dm);
+  hb = wave_max_f(hb);
+  __shared__ float wh[BT / 64], wd[BT / 64];
+  if ((threadIdx.x & 63) == 0) {
+    wh[threadIdx.x >> 6] = hb;
+    wd[threadIdx.x >> 6] = dm;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float a = wh[0], d = wd[0];
+    for (int w = 1; w < BT / 64; ++w) {
+      a = fmaxf(a, wh[w]);
+      d = fmaxf(d, wd[w]);
+    }
+    block_max[blockIdx.x] = make_float2(a, d);
+  }
+}
+
+// One wave per listed leaf (list_n on the device, or n_items when list_n is
+// null; every leaf when list is null), grid-stride: a leaf behind the time
+// line is drifted to it and its offsets, H, packed velocity, max H and exact
+// displacement bound are renewed.
+__global__ __launch_bounds__(BT) void drift_leaves_kernel(DriftArgs d, const int32_t *__restrict__ list,
+                                                          const int32_t *__restrict__ list_n, int64_t n_items,
+                                                          const double *__restrict__ xb,
+                                                          const double *__restrict__ yb,
+                                                          const double *__restrict__ zb,
+                                                          const int32_t *__restrict__ begin,
+                                                          const int32_t *__restrict__ count,
+                                                          const int32_t *__restrict__ level,
+                                                          const int32_t *__restrict__ ix,
+                                                          const int32_t *__restrict__ iy,
+                                                          const int32_t *__restrict__ iz, int D, double L,
+                                                          double unit, int64_t *__restrict__ leaf_ti,
+                                                          float4 *__restrict__ pos4, float *__restrict__ leaf_hmax,
+                                                          float *__restrict__ dx_base) {
+  const int lane = threadIdx.x & 63;
+  const int64_t items = list_n ? (int64_t)*list_n : n_items;
+  for (int64_t it = (int64_t)blockIdx.x * (BT / 64) + (threadIdx.x >> 6); it < items;
+       it += (int64_t)gridDim.x * (BT / 64)) {
+    const int64_t l = list ? list[it] : it;
+    const int64_t t0 = leaf_ti[l];
+    if (t0 == d.ti_now) continue;
+    const double dt = (double)(d.ti_now - t0) * d.t_min;
+    const int sh = D - level[l];
+    const double cx = (double)((2 * (int64_t)ix[l] + 1) << sh) * unit;
+    const double cy = (double)((2 * (int64_t)iy[l] + 1) << sh) * unit;
+    const double cz = (double)((2 * (int64_t)iz[l] + 1) << sh) * unit;
+    const int b = begin[l], cnt = count[l];
+    double d2m = 0.0;
+    float hm = 0.f;
+    for (int k = lane; k < cnt; k += 64) {
+      const int s = b + k;
+      const double xw = wrap_box(d.x[s] + d.vfx[s] * dt, L);
+      const double yw = wrap_box(d.y[s] + d.vfy[s] * dt, L);
+      const double zw = wrap_box(d.z[s] + d.vfz[s] * dt, L);
+      d.x[s] = xw;
+      d.y[s] = yw;
+      d.z[s] = zw;
+      const double vx = d.vx[s] + (double)d.ax[s] * dt, vy = d.vy[s] + (double)d.ay[s] * dt,
+                   vz = d.vz[s] + (double)d.az[s] * dt;
+      d.vx[s] = vx;
+      d.vy[s] = vy;
+      d.vz[s] = vz;
+      d.A[s] = (float)((double)d.A[s] + (double)d.dA[s] * dt);
+      double e = -(double)d.divv[s] * dt / 3.0;
+      e = fmin(fmax(e, -0.2), 0.2);
+      const float h = (float)((double)d.h[s] * exp(e));
+      d.h[s] = h;
+      const float H = GK32 * h;
+      d2m = fmax(d2m, kept_offset(cx, cy, cz, L, xw, yw, zw, xb[s], yb[s], zb[s], H, pos4[s]));
+      hm = fmaxf(hm, H);
+      d.jvm[s] = make_float4((float)vx, (float)vy, (float)vz, d.m[s]);
+    }
+    for (int o = 32; o > 0; o >>= 1) d2m = fmax(d2m, __shfl_xor(d2m, o, 64));
+    hm = wave_max_f(hm);
+    if (lane == 0) {
+      leaf_hmax[l] = hm;
+      dx_base[l] = disp_bound(d2m);
+      leaf_ti[l] = d.ti_now;
+    }
+  }
+}
+
+// Per leaf: the largest |vf| of its particles, rounded up to float.
+__global__ __launch_bounds__(BT) void leaf_vmax_kernel(const double *__restrict__ vfx, const double *__restrict__ vfy,
+                                                       const double *__restrict__ vfz,
+                                                       const int32_t *__restrict__ begin,
+                                                       const int32_t *__restrict__ count, int64_t nl,
+                                                       float *__restrict__ vmax) {
+  const int64_t l = (int64_t)blockIdx.x * (BT / 64) + (threadIdx.x >> 6);
+  if (l >= nl) return;
+  const int lane = threadIdx.x & 63;
+  const int b = begin[l], cnt = count[l];
+  double v2 = 0.0;
+  for (int k = lane; k < cnt; k += 64) {
+    const int s = b + k;
+    v2 = fmax(v2, vfx[s] * vfx[s] + vfy[s] * vfy[s] + vfz[s] * vfz[s]);
+  }
+  for (int o = 32; o > 0; o >>= 1) v2 = fmax(v2, __shfl_xor(v2, o, 64));
+  if (lane == 0) vmax[l] = v2 > 0.0 ? __int_as_float(__float_as_int((float)sqrt(v2)) + 1) : 0.f;
+}
+
+// Partner leaves of a cell-pair list that are behind the time line, each
+// listed once per stamp.
+__global__ __launch_bounds__(BT) void claim_drift_kernel(const PairEntry *__restrict__ pairs, int64_t np,
+                                                         const int64_t *__restrict__ leaf_ti, int64_t ti_now,
+                                                         int32_t *__restrict__ claim, int32_t stamp,
+                                                         int32_t *__restrict__ list, int32_t *__restrict__ list_n) {
+  for (int64_t q = (int64_t)blockIdx.x * BT + threadIdx.x; q < np; q += (int64_t)gridDim.x * BT) {
+    const int B = pairs[q].b;
+    if (leaf_ti[B] == ti_now) continue;
+    if (atomicExch(&claim[B], stamp) != stamp) list[atomicAdd(list_n, 1)] = B;
+  }
+}
+
+static DriftArgs drift_args(sph_ctx *ctx, const sph_particles *p) {
+  DriftArgs d;
+  d.x = p->x;
+  d.y = p->y;
+  d.z = p->z;
+  d.vx = p->vx;
+  d.vy = p->vy;
+  d.vz = p->vz;
+  d.vfx = p->vfx;
+  d.vfy = p->vfy;
+  d.vfz = p->vfz;
+  d.ax = p->ax;
+  d.ay = p->ay;
+  d.az = p->az;
+  d.dA = p->dA_dt;
+  d.divv = p->divv;
+  d.m = p->m;
+  d.A = p->A;
+  d.h = p->h;
+  d.jvm = (float4 *)ctx->jvm.p;
+  d.t_min = ctx->t_min_line;
+  d.ti_now = ctx->ti_now;
+  return d;
+}
+
+sph_status drift_leaves(sph_ctx *ctx, const sph_particles *p, const int32_t *list, const int32_t *list_n,
+                        int64_t cap) {
+  if (!ctx->prm.lazy_drift || ctx->n_leaves == 0) return SPH_OK;
+  if (!p->vx || !p->vy || !p->vz || !p->vfx || !p->vfy || !p->vfz || !p->ax || !p->ay || !p->az || !p->dA_dt ||
+      !p->divv || !p->m || !p->A || !p->h)
+    return sph_fail(ctx, SPH_EINVAL, "lazy drift: a state array is missing");
+  const int64_t nl = ctx->n_leaves;
+  const int64_t items = list ? std::min<int64_t>(cap, nl) : nl;
+  if (items <= 0) return SPH_OK;
+  const double *xb = (const double *)ctx->x_build.p;
+  const int64_t n = ctx->n;
+  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(items, BT / 64), (int64_t)ctx->n_cu * 16);
+  {
+    PROF(ctx, "drift");
+    drift_leaves_kernel<<<grid, BT, 0, ctx->stream>>>(
+        drift_args(ctx, p), list, list_n, items, xb, xb + n, xb + 2 * n, (const int32_t *)ctx->leaf_begin.p,
+        (const int32_t *)ctx->leaf_count.p, (const int32_t *)ctx->leaf_level.p, (const int32_t *)ctx->leaf_ix.p,
+        (const int32_t *)ctx->leaf_iy.p, (const int32_t *)ctx->leaf_iz.p, ctx->prm.morton_depth, ctx->prm.box,
+        ldexp(ctx->prm.box, -(ctx->prm.morton_depth + 1)), (int64_t *)ctx->leaf_ti.p, (float4 *)ctx->pos4.p,
+        (float *)ctx->leaf_hmax.p, (float *)ctx->leaf_dx_base.p);
+  }
+  return sph_hip_check(ctx, hipGetLastError(), "drift_leaves_kernel");
+}
+
+sph_status drift_partners(sph_ctx *ctx, const sph_particles *p, int which) {
+  if (!ctx->prm.lazy_drift) return SPH_OK;
+  const int64_t np = which == 0 ? ctx->n_dpairs : ctx->n_fpairs;
+  if (np <= 0) return SPH_OK;
+  const int64_t nl = ctx->n_leaves;
+  int32_t *list = (int32_t *)ctx->drift_list.p, *list_n = list + nl;
+  HIP_TRY(ctx, hipMemsetAsync(list_n, 0, sizeof(int32_t), ctx->stream));
+  ++ctx->drift_stamp;
+  {
+    PROF(ctx, "drift");
+    claim_drift_kernel<<<(unsigned)std::min<int64_t>(ceil_div(np, BT), 4096), BT, 0, ctx->stream>>>(
+        (const PairEntry *)(which == 0 ? ctx->dpairs.p : ctx->fpairs.p), np, (const int64_t *)ctx->leaf_ti.p,
+        ctx->ti_now, (int32_t *)ctx->drift_claim.p, ctx->drift_stamp, list, list_n);
+  }
+  HIP_TRY(ctx, hipGetLastError());
+  return drift_leaves(ctx, p, list, list_n, std::min<int64_t>(np, nl));
+}
+
+// After a full build: every leaf at the current time, no displacement, speed
+// bounds from the full-step velocities.
+sph_status lazy_init_leaves(sph_ctx *ctx, const sph_particles *p) {
+  const int64_t nl = ctx->n_leaves;
+  const size_t nl1 = (size_t)(nl > 0 ? nl : 1);
+  SPH_TRY(sph_ensure(ctx, ctx->leaf_ti, sizeof(int64_t) * nl1));
+  SPH_TRY(sph_ensure(ctx, ctx->leaf_vmax, sizeof(float) * nl1));
+  SPH_TRY(sph_ensure(ctx, ctx->leaf_dx_base, sizeof(float) * nl1));
+  SPH_TRY(sph_ensure(ctx, ctx->drift_claim, sizeof(int32_t) * nl1));
+  SPH_TRY(sph_ensure(ctx, ctx->drift_list, sizeof(int32_t) * (nl1 + 1)));
+  if (nl == 0) return SPH_OK;
+  if (!p->vfx || !p->vfy || !p->vfz) return sph_fail(ctx, SPH_EINVAL, "lazy drift: vf is required");
+  fill_i64_kernel<<<(unsigned)ceil_div(nl, BT), BT, 0, ctx->stream>>>((int64_t *)ctx->leaf_ti.p, nl, ctx->ti_now);
+  HIP_TRY(ctx, hipMemsetAsync(ctx->leaf_dx_base.p, 0, sizeof(float) * (size_t)nl, ctx->stream));
+  HIP_TRY(ctx, hipMemsetAsync(ctx->drift_claim.p, 0, sizeof(int32_t) * (size_t)nl, ctx->stream));
+  ctx->drift_stamp = 0;
+  leaf_vmax_kernel<<<(unsigned)ceil_div(nl, BT / 64), BT, 0, ctx->stream>>>(
+      p->vfx, p->vfy, p->vfz, (const int32_t *)ctx->leaf_begin.p, (const int32_t *)ctx->leaf_count.p, nl,
+      (float *)ctx->leaf_vmax.p);
+  return sph_hip_check(ctx, hipGetLastError(), "leaf_vmax_kernel");
+}
+
+// The lazy update path of sph_build_cells: the keep test from the per-leaf
+// bounds only (one synchronisation); *rebuild = 1 when the full build must
+// run (the caller drifts every leaf first).
+sph_status lazy_keep_cells(sph_ctx *ctx, int *rebuild) {
+  const int64_t nl = ctx->n_leaves;
+  const double L = ctx->prm.box;
+  int32_t *sc = (int32_t *)ctx->scalars.p;
+  HIP_TRY(ctx, hipMemsetAsync(sc + SC_UPD_HMAX, 0, 3 * sizeof(int32_t), ctx->stream));
+  const int64_t blocks = ceil_div(nl, BT);
+  SPH_TRY(sph_ensure(ctx, ctx->scan_out, sizeof(float2) * (size_t)blocks));
+  {
+    PROF(ctx, "cell_update");
+    lazy_bound_kernel<<<(unsigned)blocks, BT, 0, ctx->stream>>>(
+        (const int64_t *)ctx->leaf_ti.p, (const float *)ctx->leaf_vmax.p, (const float *)ctx->leaf_dx_base.p,
+        (const float *)ctx->leaf_hmax.p, (const int32_t *)ctx->leaf_level.p, nl, L, ctx->prm.rebuild_frac,
+        ctx->ti_now, ctx->t_min_line, (float *)ctx->leaf_dx.p, (float2 *)ctx->scan_out.p, sc + SC_UPD_FLAG);
+    max2_reduce_kernel<<<1, BT, 0, ctx->stream>>>((const float2 *)ctx->scan_out.p, (int)blocks, sc + SC_UPD_HMAX);
+  }
+  HIP_TRY(ctx, hipGetLastError());
+  int32_t st[3];
+  SPH_TRY(read_scalars(ctx, SC_UPD_HMAX, 3, st));
+  float hmax, dxm;
+  memcpy(&hmax, &st[0], 4);
+  memcpy(&dxm, &st[1], 4);
+  if (st[2] || L * 0.25 < (double)hmax) {
+    *rebuild = 1;
+    return SPH_OK;
+  }
+  *rebuild = 0;
+  HIP_TRY(ctx, hipMemcpyAsync(sc + SC_HMAX_BITS, sc + SC_UPD_HMAX, sizeof(int32_t), hipMemcpyDeviceToDevice,
+                              ctx->stream));
+  ctx->dx_max = dxm;
+  ctx->n_updates++;
   ctx->state = 1;
   return SPH_OK;
 }

@@ -1168,7 +1168,7 @@ GhostArgs density_ghost_args(sph_ctx *ctx, sph_particles *p, int it, int entropy
 // 5-6, 7-8, ...): widening happens only at the end of a group.
 static inline bool group_end(int it) { return it == 4 || (it > 4 && (it % 2) == 0); }
 
-sph_status density_after_pass(sph_ctx *ctx, int it, const int32_t st[2], int *done) {
+sph_status density_after_pass(sph_ctx *ctx, const sph_particles *p, int it, const int32_t st[2], int *done) {
   *done = 0;
   ctx->density_iterations = it;
   if (it <= 32) ctx->unconv_hist[it - 1] = st[0];
@@ -1190,6 +1190,7 @@ sph_status density_after_pass(sph_ctx *ctx, int it, const int32_t st[2], int *do
     ctx->pair_rebuilds++;
     SPH_TRY(refresh_leaf_hmax(ctx));
     SPH_TRY(build_pairs(ctx, 0, 1.5f));
+    SPH_TRY(drift_partners(ctx, p, 0));
     // (single-box passes: the released particles join the next pass's list)
     int32_t *todo = ctx->todo_collect ? (int32_t *)ctx->todo_list.p : nullptr;
     int32_t *todo_n = todo ? todo + ctx->n_active + ((it + 1) & 1) : nullptr;
@@ -1281,7 +1282,7 @@ sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u)
                                 ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     for (int pass = first; pass <= last && !done; ++pass) {
-      SPH_TRY(density_after_pass(ctx, pass, &st[2 * (pass - first)], &done));
+      SPH_TRY(density_after_pass(ctx, p, pass, &st[2 * (pass - first)], &done));
       n_todo = st[2 * (pass - first)];
     }
     if (done) ctx->fpairs_counted = fcount;
@@ -1324,6 +1325,7 @@ sph_status force_pass_impl(sph_ctx *ctx, sph_particles *p) {
   } else {
     SPH_TRY(build_pairs(ctx, 1, 1.0f));
   }
+  SPH_TRY(drift_partners(ctx, p, 1));
   LoopArgs a = force_loop_args(ctx, p);
   if (ctx->n_active < ctx->prm.sweep_below) {
     {
@@ -1709,6 +1711,7 @@ sph_status batch_check(sph_ctx **cs, int nb, int at_least, const char *call) {
                       at_least);
     for (int q = 0; q < b; ++q)
       if (cs[q] == cs[b]) return sph_fail(lead, SPH_EINVAL, "%s: context %d appears twice", call, b);
+    if (cs[b]->prm.lazy_drift) return sph_fail(lead, SPH_EINVAL, "%s: box %d drifts lazily", call, b);
   }
   return SPH_OK;
 }
@@ -1779,7 +1782,7 @@ sph_status batch_density_impl(sph_ctx **cs, sph_particles *ps, int nb, int entro
     for (int q = 0; q < ni; ++q) {
       const int b = iterating[q];
       int done;
-      BATCH_TRY(b, density_after_pass(cs[b], it, &st[2 * q], &done));
+      BATCH_TRY(b, density_after_pass(cs[b], &ps[b], it, &st[2 * q], &done));
       if (!done) next.push_back(b);
     }
     iterating.swap(next);

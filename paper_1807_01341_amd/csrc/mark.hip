@@ -157,7 +157,8 @@ __global__ __launch_bounds__(MT) void pairs_kernel(int mode, float slack, PairGe
                                                    int32_t *__restrict__ counts, const int32_t *__restrict__ offs,
                                                    PairEntry *__restrict__ out, uint8_t *__restrict__ out_axis,
                                                    AxisTab ax, const int32_t *__restrict__ leaf_count,
-                                                   int32_t *__restrict__ act_cost) {
+                                                   int32_t *__restrict__ act_cost,
+                                                   const int64_t *__restrict__ leaf_ti, int64_t ti_now) {
   const int64_t a = (int64_t)blockIdx.x * (MT / 64) + (threadIdx.x >> 6);
   if (a >= n_act_leaves) return;
   const int lane = threadIdx.x & 63;
@@ -303,7 +304,12 @@ __global__ __launch_bounds__(MT) void pairs_kernel(int mode, float slack, PairGe
           d2 = d2 + gd * gd;
         }
         float R = RA;
-        if (mode == 1) R = fmaxf(R, leaf_hmax[B]);
+        if (mode == 1) {
+          // (lazy drift: a leaf behind the time line may grow by its drift)
+          float hB = leaf_hmax[B];
+          if (leaf_ti && leaf_ti[B] != ti_now) hB *= LAZY_HGROW;
+          R = fmaxf(R, hB);
+        }
         R = (R + dxA) + leaf_dx[B];
         const double Rd = (double)R;
         ok = d2 < Rd * Rd;
@@ -396,6 +402,7 @@ sph_status build_pairs_count(sph_ctx *ctx, int which, float slack, int32_t *host
     return SPH_OK;
   }
   const PairGeom g = pair_geom(ctx);
+  const int64_t *lazy_ti = ctx->prm.lazy_drift ? (const int64_t *)ctx->leaf_ti.p : nullptr;
   if (!ctx->blocks_valid) {
     // run boxes of the current full build (cell updates keep the leaves)
     const int64_t nl = ctx->n_leaves, nrun = ceil_div(nl, LEAF_BLOCK);
@@ -417,7 +424,7 @@ sph_status build_pairs_count(sph_ctx *ctx, int which, float slack, int32_t *host
         (const int32_t *)ctx->leaf_iz.p, (const float *)ctx->leaf_hmax.p, (const int32_t *)ctx->top_first.p,
         (const int32_t *)ctx->top_last.p, (const int32_t *)ctx->scalars.p + SC_HMAX_BITS,
         (const float *)ctx->leaf_dx.p, ctx->dx_max, (const int4 *)ctx->block_box.p, (int32_t *)ctx->pair_cnt.p,
-        nullptr, nullptr, nullptr, AxisTab(), nullptr, nullptr);
+        nullptr, nullptr, nullptr, AxisTab(), nullptr, nullptr, lazy_ti, ctx->ti_now);
   }
   HIP_TRY(ctx, hipGetLastError());
   int32_t *o = (int32_t *)off.p;
@@ -436,6 +443,7 @@ sph_status build_pairs_fill(sph_ctx *ctx, int which, float slack, int32_t np) {
   SPH_TRY(sph_ensure(ctx, lst, sizeof(PairEntry) * (size_t)(np > 0 ? np : 1)));
   SPH_TRY(sph_ensure(ctx, axl, (size_t)(np > 0 ? np : 1)));
   const PairGeom g = pair_geom(ctx);
+  const int64_t *lazy_ti = ctx->prm.lazy_drift ? (const int64_t *)ctx->leaf_ti.p : nullptr;
   {
     PROF(ctx, "cell_pairs");
     pairs_kernel<true><<<waves_grid(na), MT, 0, ctx->stream>>>(
@@ -445,7 +453,7 @@ sph_status build_pairs_fill(sph_ctx *ctx, int which, float slack, int32_t np) {
         (const int32_t *)ctx->top_last.p, (const int32_t *)ctx->scalars.p + SC_HMAX_BITS,
         (const float *)ctx->leaf_dx.p, ctx->dx_max, (const int4 *)ctx->block_box.p, nullptr,
         (int32_t *)off.p, (PairEntry *)lst.p, (uint8_t *)axl.p, host_axes(), (const int32_t *)ctx->leaf_count.p,
-        which == 0 ? (int32_t *)ctx->act_cost.p : nullptr);
+        which == 0 ? (int32_t *)ctx->act_cost.p : nullptr, lazy_ti, ctx->ti_now);
   }
   HIP_TRY(ctx, hipGetLastError());
   return SPH_OK;
@@ -530,7 +538,13 @@ sph_status mark_active_impl(sph_ctx *ctx, const sph_particles *p, int m, int64_t
   // new chunks: the loop work items are rebuilt at the next launch (they keep
   // the costs of these lists through the pass, also if the lists are widened)
   ctx->work_valid = 0;
+  if (ctx->prm.lazy_drift && ctx->n_active_leaves > 0) {
+    // the active leaves reach the current time before their max H is taken
+    SPH_TRY(drift_leaves(ctx, p, (const int32_t *)ctx->act_leaves.p, nullptr, ctx->n_active_leaves));
+    SPH_TRY(refresh_leaf_hmax(ctx));
+  }
   SPH_TRY(build_pairs(ctx, 0, ctx->prm.pair_slack));
+  SPH_TRY(drift_partners(ctx, p, 0));
   if (n_active_host) *n_active_host = ctx->n_active;
   ctx->state = 3;
   return SPH_OK;

@@ -110,6 +110,14 @@ struct sph_ctx {
   // cells kept between builds: positions of the last full build, per-leaf and
   // largest displacement since then (the cell-pair search margin)
   DevBuf x_build, leaf_dx, leaf_half;
+  // lazy drift (params.lazy_drift): the internal time line in units of t_min
+  // (advanced by each kick's drift interval), the time each leaf's particles
+  // were drifted to, a bound on their full-step speed, their displacement
+  // bound from the full build at that time, and the leaves a claim collects
+  int64_t ti_now = 0;
+  double t_min_line = 0.0;
+  DevBuf leaf_ti, leaf_vmax, leaf_dx_base, drift_claim, drift_list;
+  int32_t drift_stamp = 0;
   float dx_max = 0.f;
   int64_t built_n = 0;
   int64_t n_full_builds = 0, n_updates = 0;
@@ -234,6 +242,16 @@ sph_status read_scalars(sph_ctx *ctx, int first, int count, int32_t *host);
 // ---------------------------------------------------------------- stages
 sph_status build_cells_impl(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *perm_out);
 sph_status update_cells(sph_ctx *ctx, sph_particles *p, int64_t *perm_out, int *rebuild);
+// Lazy drift: the cell-keep test from the per-leaf bounds (no particle
+// access), the drift of listed leaves (or all: list == nullptr) to the
+// current time, the drift of the partner leaves of cell-pair list `which`,
+// and the per-leaf state of a new full build.
+sph_status lazy_keep_cells(sph_ctx *ctx, int *rebuild);
+sph_status drift_leaves(sph_ctx *ctx, const sph_particles *p, const int32_t *list, const int32_t *list_n,
+                        int64_t cap);
+sph_status drift_partners(sph_ctx *ctx, const sph_particles *p, int which);
+sph_status lazy_init_leaves(sph_ctx *ctx, const sph_particles *p);
+#define LAZY_HGROW 1.2215f  // bound on H's growth in one drift (the h prediction is clipped at e^0.2)
 sph_status sort_cells_impl(sph_ctx *ctx);
 sph_status mark_active_impl(sph_ctx *ctx, const sph_particles *p, int m, int64_t *n_active_host);
 sph_status build_pairs(sph_ctx *ctx, int which, float slack);

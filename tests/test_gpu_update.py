@@ -162,3 +162,57 @@ def test_kept_axis_orders_on_clustered_update(gpu_lib):
     a_err = np.max(np.linalg.norm(a_g - a_r, axis=1) / den)
     print(f"rho {rho_err:.2e} a {a_err:.2e}", flush=True)
     assert rho_err < RHO_TOL and a_err < A_TOL
+
+
+def test_lazy_drift_matches_drift_all(gpu_lib):
+    """Sixteen sub-steps of the bin hierarchy with lazy drift (only the leaves
+    a step needs are drifted) and with every particle drifted each step: the
+    same active sets, and after drifting everything the same state to
+    rounding."""
+    sg = gpu_lib
+    ic = dict(ics.clustered(n_total=20000, n_clumps=3))
+    rng = np.random.default_rng(5)
+    ic["v"] = rng.normal(0.0, 0.3, size=ic["x"].shape)
+    print("case lazy drift clustered20k 16 sub-steps", flush=True)
+    keys = ("x", "y", "z", "vx", "vfx", "A", "h", "rho", "ax", "ay", "az", "vsig", "time_bin")
+    runs = []
+    for lazy in (0, 1):
+        p = sg.Particles.from_initial(ic)
+        ctx = sg.Context(lazy_drift=lazy)
+        top = ctx.params.n_bins - 1
+        ctx.build_cells(p)
+        ctx.sort_cells()
+        ctx.mark_active(p, top)
+        ctx.density_pass(p, True)
+        ctx.force_pass(p)
+        vs = p["vsig"].double()
+        t_min = float((ctx.params.cfl * p["h"].double() / vs).min())
+        ctx.kick_drift(p, 0, t_min, 0, True)
+        counts = []
+        for t in range(1, 17):
+            m = min((t & -t).bit_length() - 1, top)
+            counts.append(ctx.step(p, m, t, t_min, 1, False, want_count=True))
+        ctx.drift_all(p)
+        ctx.sync()
+        inf = ctx.info()
+        runs.append((counts, {k: host(p, k).copy() for k in keys}, inf))
+    (c0, s0, i0), (c1, s1, i1) = runs
+    print("active per sub-step", c0, "builds", i0["full_builds"], i1["full_builds"], flush=True)
+    # the two runs differ by rounding only: the lazy drift adds each
+    # particle's motion over several sub-steps at once, so its h prediction
+    # and positions round differently, and the accelerations (FP32) that
+    # feed the kicks follow; a missed or repeated drift would move a particle
+    # by |vf| t_min (about 1e-6 here)
+    dx = max(np.max(np.minimum(np.abs(s0[k] - s1[k]), 1.0 - np.abs(s0[k] - s1[k]))) for k in ("x", "y", "z"))
+    dv = np.max(np.abs(s0["vx"] - s1["vx"])) / np.max(np.abs(s0["vx"]))
+    dvf = np.max(np.abs(s0["vfx"] - s1["vfx"])) / np.max(np.abs(s0["vfx"]))
+    rel = {k: float(np.max(np.abs(s1[k] / s0[k] - 1))) for k in ("A", "h", "rho", "vsig")}
+    print(f"t_min {t_min:.3e} max |dx| {dx:.2e} dv {dv:.2e} dvf {dvf:.2e} {rel}", flush=True)
+    assert c0 == c1 and sum(c0) > 0
+    assert np.array_equal(s0["time_bin"], s1["time_bin"])
+    assert dx < 1e-9 and dv < 1e-6 and dvf < 1e-6
+    for k in ("A", "h", "rho", "vsig"):
+        assert rel[k] < 1e-5, k
+    a0 = np.stack([s0[k] for k in ("ax", "ay", "az")], 1).astype(np.float64)
+    a1 = np.stack([s1[k] for k in ("ax", "ay", "az")], 1).astype(np.float64)
+    assert np.linalg.norm(a1 - a0) < 1e-5 * np.linalg.norm(a0)
