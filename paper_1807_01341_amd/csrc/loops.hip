@@ -670,9 +670,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void d
   if (n_todo_dev) n_todo = *n_todo_dev;
   // the next pass's list starts empty (its ghost appends after this launch)
   if (next_n && blockIdx.x == 0 && threadIdx.x == 0) *next_n = 0;
-  const int64_t lb = xcd_block(ceil_div(n_todo, 4 / NWP));
-  const int64_t w = lb < 0 ? n_todo : lb * (4 / NWP) + wave / NWP;
   const int lane = threadIdx.x & 63;
+  // grid-stride over the logical blocks of the particles to do (known on the
+  // device only, so the grid is sized to the machine): the blocks the
+  // dispatcher sends to one XCD (blockIdx % 8, the grid being a multiple of
+  // 8) take one contiguous range, so particles sharing partner leaves read
+  // them from the same L2
+  const int64_t nblk = ceil_div(n_todo, 4 / NWP);
+  const int64_t per = (nblk + 7) >> 3;
+  for (int64_t bi = blockIdx.x; bi < 8 * per; bi += gridDim.x) {
+  const int64_t lb = (bi & 7) * per + (bi >> 3);
+  const int64_t w = lb < nblk ? lb * (4 / NWP) + wave / NWP : n_todo;
   if (w < n_todo) {
   SweepPair *my = sp[wave];
   const int k = todo ? todo[w] : (int)w;
@@ -828,6 +836,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void d
       for (int q = 0; q < 8; ++q) g.sums[(int64_t)q * g.n_active + k] = s[q];
       g.act_cnt[k] = cs;
     }
+    __syncthreads();  // red is reused by the next logical block
+  }
   }
 }
 
@@ -1245,7 +1255,7 @@ sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u)
         // loop (whose chunk flags the sweep leaves as they are).
         PROF(ctx, "density_loop");
         const int nwp = sweep_waves(ctx, n_todo);
-        const unsigned grid = xcd_grid(ceil_div(n_todo * nwp, 4));
+        const unsigned grid = xcd_grid(std::min<int64_t>(ceil_div(n_todo * nwp, 4), (int64_t)ctx->n_cu * 16));
         const int32_t *tl = pass > 1 ? list : nullptr, *tn = pass > 1 ? list_n + (pass & 1) : nullptr;
         const int32_t *co = (const int32_t *)ctx->chunk_of.p;
         if (nwp == 4)
