@@ -135,6 +135,11 @@ sph_status sph_create(const sph_params *p, void *hip_stream, sph_ctx **out) {
     delete ctx;
     return SPH_ENOMEM;
   }
+  if (hipHostMalloc((void **)&ctx->pin.p, sizeof(int32_t) * PIN_COUNT, hipHostMallocDefault) != hipSuccess) {
+    ctx->pin.p = nullptr;
+    delete ctx;
+    return SPH_ENOMEM;
+  }
   if (sph_ensure(ctx, ctx->counters64, 2 * sizeof(uint64_t)) != SPH_OK) {
     delete ctx;
     return SPH_ENOMEM;

@@ -248,10 +248,10 @@ sph_status items_fill(sph_ctx *ctx, int target, int32_t total) {
 
 sph_status ensure_items(sph_ctx *ctx, int target) {
   if (ctx->work_valid && ctx->items_target == target) return SPH_OK;
-  int32_t total = 0;
-  SPH_TRY(items_count(ctx, target, &total));
+  int32_t *total = ctx->pin.p + PIN_ITEMS;
+  SPH_TRY(items_count(ctx, target, total));
   if (ctx->n_chunks > 0 && target > 0) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-  return items_fill(ctx, target, total);
+  return items_fill(ctx, target, *total);
 }
 
 // The loop arguments' work list for a configuration (items built if needed).
@@ -1285,17 +1285,23 @@ sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u)
     // smoothing lengths and the force cell-pair count, read in the same
     // synchronisation (wasted work when another group follows)
     SPH_TRY(refresh_leaf_hmax(ctx));
-    int32_t fcount = 0;
-    SPH_TRY(build_pairs_count(ctx, 1, 1.0f, &fcount));
-    std::vector<int32_t> st(2 * (size_t)(last - first + 1));
-    HIP_TRY(ctx, hipMemcpyAsync(st.data(), stats + 2 * first, sizeof(int32_t) * st.size(), hipMemcpyDeviceToHost,
-                                ctx->stream));
+    // both reads queued into page-locked slots, one synchronisation
+    int32_t *fcount = ctx->pin.p + PIN_FCOUNT;
+    SPH_TRY(build_pairs_count(ctx, 1, 1.0f, fcount));
+    const size_t nst = 2 * (size_t)(last - first + 1);
+    if (nst > PIN_COUNT - PIN_STATS) return sph_fail(ctx, SPH_EINVAL, "density pass: group of passes too long");
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->pin.p + PIN_STATS, stats + 2 * first, sizeof(int32_t) * nst,
+                                hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    // density_after_pass may issue reads of its own: the counters leave the slots first
+    int32_t st[PIN_COUNT - PIN_STATS];
+    memcpy(st, ctx->pin.p + PIN_STATS, sizeof(int32_t) * nst);
+    const int32_t fc = *fcount;
     for (int pass = first; pass <= last && !done; ++pass) {
       SPH_TRY(density_after_pass(ctx, p, pass, &st[2 * (pass - first)], &done));
       n_todo = st[2 * (pass - first)];
     }
-    if (done) ctx->fpairs_counted = fcount;
+    if (done) ctx->fpairs_counted = fc;
     it = last;
   }
   return density_end(ctx, true);

@@ -460,10 +460,10 @@ sph_status build_pairs_fill(sph_ctx *ctx, int which, float slack, int32_t np) {
 }
 
 sph_status build_pairs(sph_ctx *ctx, int which, float slack) {
-  int32_t np = 0;
-  SPH_TRY(build_pairs_count(ctx, which, slack, &np));
+  int32_t *np = ctx->pin.p + PIN_NPAIRS;
+  SPH_TRY(build_pairs_count(ctx, which, slack, np));
   if (ctx->n_active_leaves > 0) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-  return build_pairs_fill(ctx, which, slack, np);
+  return build_pairs_fill(ctx, which, slack, *np);
 }
 
 // Refreshes the max H of every active leaf (all particles, and active ones)
@@ -510,10 +510,11 @@ sph_status mark_active_impl(sph_ctx *ctx, const sph_particles *p, int m, int64_t
   // one scan over [nact | isact | nchunk]: the second and third segments come
   // out shifted by the totals before them, read back by the fill kernel
   SPH_TRY(scan_exclusive_i32(ctx, nact, aoff, 3 * nl, aoff + 3 * nl));
-  int32_t tot3[4];
-  HIP_TRY(ctx, hipMemcpyAsync(tot3, aoff + nl, 4, hipMemcpyDeviceToHost, ctx->stream));
-  HIP_TRY(ctx, hipMemcpyAsync(tot3 + 1, aoff + 2 * nl, 4, hipMemcpyDeviceToHost, ctx->stream));
-  HIP_TRY(ctx, hipMemcpyAsync(tot3 + 2, aoff + 3 * nl, 4, hipMemcpyDeviceToHost, ctx->stream));
+  // the three totals, queued into page-locked slots, one synchronisation
+  const int32_t *tot3 = ctx->pin.p + PIN_MARK;
+  for (int q = 0; q < 3; ++q)
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->pin.p + PIN_MARK + q, aoff + (q + 1) * nl, 4, hipMemcpyDeviceToHost,
+                                ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   int32_t tot[3] = {tot3[0], tot3[1] - tot3[0], tot3[2] - tot3[1]};
   ctx->n_active = tot[0];

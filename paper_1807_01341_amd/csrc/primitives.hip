@@ -2,6 +2,7 @@
 // sort of (uint64 key, int32 value) pairs with 8-bit digits.
 #include <stdarg.h>
 #include <stdio.h>
+#include <string.h>
 
 #include "sph_internal.h"
 
@@ -43,9 +44,13 @@ sph_status sph_ensure(sph_ctx *ctx, DevBuf &b, size_t bytes) {
 }
 
 sph_status read_scalars(sph_ctx *ctx, int first, int count, int32_t *host) {
-  HIP_TRY(ctx, hipMemcpyAsync(host, (int32_t *)ctx->scalars.p + first, sizeof(int32_t) * count,
+  if (count < 1 || count > PIN_MARK - PIN_SCALARS || first < 0 || first + count > SC_COUNT)
+    return sph_fail(ctx, SPH_EINVAL, "read_scalars: slots [%d, %d) out of range", first, first + count);
+  int32_t *pin = ctx->pin.p + PIN_SCALARS;
+  HIP_TRY(ctx, hipMemcpyAsync(pin, (int32_t *)ctx->scalars.p + first, sizeof(int32_t) * count,
                               hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  memcpy(host, pin, sizeof(int32_t) * count);
   return SPH_OK;
 }
 

@@ -31,6 +31,19 @@ struct DevBuf {
   }
 };
 
+// Page-locked host memory for the small device-to-host reads of a step: a
+// copy into it is queued like a kernel, so several reads share one stream
+// synchronisation (a copy into pageable memory waits for the stream itself).
+struct HostPin {
+  int32_t *p = nullptr;
+  HostPin() = default;
+  HostPin(const HostPin &) = delete;
+  HostPin &operator=(const HostPin &) = delete;
+  ~HostPin() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+
 // Pair-list entry: partner leaf index (as int bits) and the FP32 shift of the
 // partner's offsets into the owner leaf's frame.
 struct PairEntry {
@@ -125,6 +138,7 @@ struct sph_ctx {
   // build
   DevBuf keys_a, keys_b, vals_a, vals_b, radix_counts, scan_tmp, gather_tmp;
   DevBuf scalars;                         // small device counters
+  HostPin pin;                            // host side of the reads (PinSlot)
   DevBuf flags, scan_out, nodes_a, nodes_b, leaf_lvl_at;
   DevBuf leaf_level, leaf_ix, leaf_iy, leaf_iz, leaf_begin, leaf_count, leaf_hmax, leaf_of;
   DevBuf top_first, top_last;
@@ -229,6 +243,18 @@ enum ScalarSlot {
   SC_UPD_DX = 14,
   SC_UPD_FLAG = 15,
   SC_COUNT = 32
+};
+
+// Slots of ctx->pin (int32).  Each read is queued, followed by one stream
+// synchronisation, then taken from its slot; slots in flight together differ.
+enum PinSlot {
+  PIN_SCALARS = 0,    // read_scalars (at most 16 values)
+  PIN_MARK = 16,      // mark: active particles, active leaves, chunks (scan totals)
+  PIN_NPAIRS = 20,    // cell-pair total of build_pairs
+  PIN_FCOUNT = 21,    // force cell-pair total counted during the density solve
+  PIN_ITEMS = 22,     // loop work items
+  PIN_STATS = 32,     // density solve: per-pass counters of one group of passes
+  PIN_COUNT = 64
 };
 
 // ---------------------------------------------------------------- primitives (primitives.hip)
