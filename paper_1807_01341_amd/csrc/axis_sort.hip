@@ -1,8 +1,11 @@
 // Per-cell particle sorts for neighbour pruning (the "sort" task of Fig. 5):
 // for every leaf and each of the 13 directions of the half neighbour stencil,
 // the in-leaf order of the projections d = e . o of the FP32 offsets at the
-// last full build (ascending, ties by in-leaf index).  One workgroup per leaf, all 13 axes,
-// bitonic sorts of (key, index) in LDS.
+// last full build (ascending, ties by in-leaf index).  A 14th order
+// (HORD_ROW) lists the particles by H at the full build, largest first: the
+// force loop reads only its head where a partner leaf is beyond H_i and only
+// particles of large H_j can reach (the symmetric cutoff of Eq. 12/13).
+// Bitonic sorts of (key, index), in LDS or in registers.
 #include <math.h>
 
 #include <algorithm>
@@ -14,7 +17,8 @@
 // Workgroup LDS bitonic sort for leaves of 513..4096 particles (only at the
 // maximum depth, where coincident particles cannot be split further).
 template <int P>
-__device__ void sort_leaf_lds(const float4 *__restrict__ pos4, int b, int cnt, int64_t n, const AxisTab &ax,
+__device__ void sort_leaf_lds(const float4 *__restrict__ pos4, const float *__restrict__ hb, int b, int cnt, int64_t n,
+                              const AxisTab &ax,
                               uint16_t *__restrict__ order, float *ox, float *oy, float *oz, float *key,
                               uint16_t *idx) {
   int size = 2;
@@ -26,11 +30,12 @@ __device__ void sort_leaf_lds(const float4 *__restrict__ pos4, int b, int cnt, i
     oz[k] = q.z;
   }
   __syncthreads();
-  for (int a = 0; a < 13; ++a) {
-    const float ex = ax.e[a][0], ey = ax.e[a][1], ez = ax.e[a][2];
+  for (int a = 0; a <= HORD_ROW; ++a) {
+    const bool hrow = a == HORD_ROW;
+    const float ex = hrow ? 0.f : ax.e[a][0], ey = hrow ? 0.f : ax.e[a][1], ez = hrow ? 0.f : ax.e[a][2];
     for (int k = threadIdx.x; k < size; k += AS_THREADS) {
       if (k < cnt) {
-        key[k] = fmaf(oz[k], ez, fmaf(oy[k], ey, ox[k] * ex));
+        key[k] = hrow ? -hb[b + k] + 0.0f : fmaf(oz[k], ez, fmaf(oy[k], ey, ox[k] * ex));
         idx[k] = (uint16_t)k;
       } else {
         key[k] = INFINITY;
@@ -64,6 +69,7 @@ __device__ void sort_leaf_lds(const float4 *__restrict__ pos4, int b, int cnt, i
 
 template <int P>
 __global__ __launch_bounds__(AS_THREADS) void axis_sort_kernel(const float4 *__restrict__ pos4,
+                                                               const float *__restrict__ hb,
                                                                const int32_t *__restrict__ leaf_begin,
                                                                const int32_t *__restrict__ leaf_count, int64_t nl,
                                                                int64_t n, AxisTab ax, int min_count,
@@ -74,7 +80,7 @@ __global__ __launch_bounds__(AS_THREADS) void axis_sort_kernel(const float4 *__r
   for (int64_t l = blockIdx.x; l < nl; l += gridDim.x) {
     const int cnt = leaf_count[l];
     if (cnt < min_count || cnt > P) continue;
-    sort_leaf_lds<P>(pos4, leaf_begin[l], cnt, n, ax, order, ox, oy, oz, key, idx);
+    sort_leaf_lds<P>(pos4, hb, leaf_begin[l], cnt, n, ax, order, ox, oy, oz, key, idx);
   }
 }
 
@@ -133,10 +139,11 @@ __device__ __forceinline__ void wave_bitonic(uint64_t (&w)[E], int lane) {
 }
 
 template <int E>
-__device__ __forceinline__ void sort_leaf_axes(const float4 *__restrict__ pos4, int b, int cnt, int64_t n,
+__device__ __forceinline__ void sort_leaf_axes(const float4 *__restrict__ pos4, const float *__restrict__ hb, int b,
+                                               int cnt, int64_t n,
                                                const AxisTab &ax, uint16_t *__restrict__ order, int lane,
                                                int a_first, int a_end) {
-  float ox[E], oy[E], oz[E];
+  float ox[E], oy[E], oz[E], ow[E];
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int e = lane * E + r;
@@ -145,17 +152,21 @@ __device__ __forceinline__ void sort_leaf_axes(const float4 *__restrict__ pos4, 
       ox[r] = q.x;
       oy[r] = q.y;
       oz[r] = q.z;
+      ow[r] = hb[b + e];
     } else {
-      ox[r] = oy[r] = oz[r] = 0.f;
+      ox[r] = oy[r] = oz[r] = ow[r] = 0.f;
     }
   }
   for (int a = a_first; a < a_end; ++a) {
-    const float ex = ax.e[a][0], ey = ax.e[a][1], ez = ax.e[a][2];
+    // the H order: -H ascending
+    const bool hrow = a == HORD_ROW;
+    const float ex = hrow ? 0.f : ax.e[a][0], ey = hrow ? 0.f : ax.e[a][1], ez = hrow ? 0.f : ax.e[a][2];
     uint64_t w[E];
 #pragma unroll
     for (int r = 0; r < E; ++r) {
       const int e = lane * E + r;
-      w[r] = e < cnt ? sort_word(fmaf(oz[r], ez, fmaf(oy[r], ey, ox[r] * ex)), e) : ~0ull;
+      const float key = hrow ? -ow[r] : fmaf(oz[r], ez, fmaf(oy[r], ey, ox[r] * ex));
+      w[r] = e < cnt ? sort_word(key, e) : ~0ull;
     }
     wave_bitonic<E>(w, lane);
 #pragma unroll
@@ -166,43 +177,130 @@ __device__ __forceinline__ void sort_leaf_axes(const float4 *__restrict__ pos4, 
   }
 }
 
-// One wave per (leaf of min_count..512 particles, axis), grid-stride over
-// every (leaf, axis).
+// One wave per (leaf of at most 512 particles, order), grid-stride over
+// every (leaf, order): the axis orders of leaves of min_count particles or
+// more, the H order of every leaf.
 __global__ __launch_bounds__(256) void axis_sort_wave_kernel(const float4 *__restrict__ pos4,
+                                                             const float *__restrict__ hb,
                                                              const int32_t *__restrict__ leaf_begin,
                                                              const int32_t *__restrict__ leaf_count, int64_t nl,
                                                              int64_t n, AxisTab ax, int min_count,
                                                              uint16_t *__restrict__ order) {
   const int lane = threadIdx.x & 63;
-  // work item = (leaf, axis): the 13 sorts of a leaf run on 13 waves
-  const int64_t items = 13 * nl;
+  // work item = (leaf, order): the 14 sorts of a leaf run on 14 waves
+  constexpr int NR = HORD_ROW + 1;
+  const int64_t items = NR * nl;
   for (int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); it < items; it += (int64_t)gridDim.x * 4) {
-    const int64_t l = it / 13;
-    const int a = (int)(it - 13 * l);
+    const int64_t l = it / NR;
+    const int a = (int)(it - NR * l);
     const int cnt = leaf_count[l], b = leaf_begin[l];
-    if (cnt < min_count) continue;
+    if (a != HORD_ROW && cnt < min_count) continue;
     if (cnt <= 64)
-      sort_leaf_axes<1>(pos4, b, cnt, n, ax, order, lane, a, a + 1);
+      sort_leaf_axes<1>(pos4, hb, b, cnt, n, ax, order, lane, a, a + 1);
     else if (cnt <= 128)
-      sort_leaf_axes<2>(pos4, b, cnt, n, ax, order, lane, a, a + 1);
+      sort_leaf_axes<2>(pos4, hb, b, cnt, n, ax, order, lane, a, a + 1);
     else if (cnt <= 256)
-      sort_leaf_axes<4>(pos4, b, cnt, n, ax, order, lane, a, a + 1);
+      sort_leaf_axes<4>(pos4, hb, b, cnt, n, ax, order, lane, a, a + 1);
     else if (cnt <= 512)
-      sort_leaf_axes<8>(pos4, b, cnt, n, ax, order, lane, a, a + 1);
+      sort_leaf_axes<8>(pos4, hb, b, cnt, n, ax, order, lane, a, a + 1);
+  }
+}
+
+// The largest H at the build at ranks hq_rank(q) of each leaf's H order, one
+// thread per (leaf, q); 0 where the rank is past the leaf's count.
+__global__ __launch_bounds__(256) void leaf_hq_kernel(const float *__restrict__ hb,
+                                                      const int32_t *__restrict__ leaf_begin,
+                                                      const int32_t *__restrict__ leaf_count, int64_t nl, int64_t n,
+                                                      const uint16_t *__restrict__ order, float *__restrict__ hq) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= HQ_N * nl) return;
+  const int64_t l = t / HQ_N;
+  const int q = (int)(t - HQ_N * l);
+  const int r = hq_rank(q), b = leaf_begin[l];
+  hq[t] = r < leaf_count[l] ? hb[b + order[(int64_t)HORD_ROW * n + b + r]] : 0.f;
+}
+
+// The float whose sort_word key is the high half of w.
+__device__ __forceinline__ float sort_word_key(uint64_t w) {
+  const uint32_t u = (uint32_t)(w >> 32);
+  return __uint_as_float((u >> 31) ? (u ^ 0x80000000u) : ~u);
+}
+
+// A leaf whose H grew past `limit` times the keys of its H order since they
+// were taken: the keys become the current H (pos4.w), the order and its
+// samples are renewed, and the growth bound is 1.  Leaves of more than 512
+// particles keep their order (their bound stays valid).
+template <int E>
+__device__ __forceinline__ void rekey_leaf(const float4 *__restrict__ pos4, int64_t l, int b, int cnt, int64_t n,
+                                           float *__restrict__ hb, uint16_t *__restrict__ order,
+                                           float *__restrict__ hq, float *__restrict__ hgrow, int lane) {
+  uint64_t w[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int e = lane * E + r;
+    if (e < cnt) {
+      const float H = pos4[b + e].w;
+      hb[b + e] = H;
+      w[r] = sort_word(-H, e);
+    } else {
+      w[r] = ~0ull;
+    }
+  }
+  wave_bitonic<E>(w, lane);
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int e = lane * E + r;
+    if (e < cnt) order[(int64_t)HORD_ROW * n + b + e] = (uint16_t)(w[r] & 0xffffu);
+  }
+#pragma unroll
+  for (int q = 0; q < HQ_N; ++q) {
+    const int pos = hq_rank(q);
+    if (pos < cnt) {
+      if (lane == pos / E) hq[HQ_N * l + q] = -sort_word_key(w[pos % E]);
+    } else if (lane == 0) {
+      hq[HQ_N * l + q] = 0.f;
+    }
+  }
+  if (lane == 0) hgrow[l] = 1.f;
+}
+
+__global__ __launch_bounds__(256) void hrow_rekey_kernel(const float4 *__restrict__ pos4,
+                                                         const int32_t *__restrict__ leaf_begin,
+                                                         const int32_t *__restrict__ leaf_count, int64_t nl,
+                                                         int64_t n, float limit, float *__restrict__ hb,
+                                                         uint16_t *__restrict__ order, float *__restrict__ hq,
+                                                         float *__restrict__ hgrow) {
+  const int lane = threadIdx.x & 63;
+  // each wave checks 64 leaves at once, one per lane, then keys those flagged
+  for (int64_t l0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64; l0 < nl; l0 += (int64_t)gridDim.x * 256) {
+    const bool flag = l0 + lane < nl && hgrow[l0 + lane] > limit;
+    for (uint64_t m = __ballot(flag); m; m &= m - 1) {
+    const int64_t l = l0 + __ffsll((unsigned long long)m) - 1;
+    const int cnt = leaf_count[l], b = leaf_begin[l];
+    if (cnt <= 64)
+      rekey_leaf<1>(pos4, l, b, cnt, n, hb, order, hq, hgrow, lane);
+    else if (cnt <= 128)
+      rekey_leaf<2>(pos4, l, b, cnt, n, hb, order, hq, hgrow, lane);
+    else if (cnt <= 256)
+      rekey_leaf<4>(pos4, l, b, cnt, n, hb, order, hq, hgrow, lane);
+    else if (cnt <= 512)
+      rekey_leaf<8>(pos4, l, b, cnt, n, hb, order, hq, hgrow, lane);
+    }
   }
 }
 
 // Sorts the 13 axes of every leaf of at least min_count particles, by the
-// offsets of the full build.  Grids sized to the machine, not to the leaves.
+// offsets of the full build, and the H order of every leaf with its samples.
+// Grids sized to the machine, not to the leaves.
 static sph_status sort_leaves(sph_ctx *ctx, int min_count) {
   const int64_t n = ctx->n, nl = ctx->n_leaves;
-  if (nl <= 0 || ctx->max_leaf < min_count) return SPH_OK;
+  if (nl <= 0) return SPH_OK;
   const AxisTab ax = host_axes();
   {
     PROF(ctx, "axis_sort");
-    const int64_t blocks = std::min<int64_t>(ceil_div(13 * nl, 4), (int64_t)ctx->n_cu * 8);
+    const int64_t blocks = std::min<int64_t>(ceil_div((HORD_ROW + 1) * nl, 4), (int64_t)ctx->n_cu * 8);
     axis_sort_wave_kernel<<<(unsigned)blocks, 256, 0, ctx->stream>>>(
-        (const float4 *)ctx->pos4_build.p, (const int32_t *)ctx->leaf_begin.p, (const int32_t *)ctx->leaf_count.p,
+        (const float4 *)ctx->pos4_build.p, (const float *)ctx->h_build.p, (const int32_t *)ctx->leaf_begin.p, (const int32_t *)ctx->leaf_count.p,
         nl, n, ax, min_count, (uint16_t *)ctx->axis_order.p);
   }
   HIP_TRY(ctx, hipGetLastError());
@@ -210,22 +308,30 @@ static sph_status sort_leaves(sph_ctx *ctx, int min_count) {
     PROF(ctx, "axis_sort");
     const int64_t blocks = std::min<int64_t>(nl, (int64_t)ctx->n_cu * 2);
     axis_sort_kernel<4096><<<(unsigned)blocks, AS_THREADS, 0, ctx->stream>>>(
-        (const float4 *)ctx->pos4_build.p, (const int32_t *)ctx->leaf_begin.p, (const int32_t *)ctx->leaf_count.p,
+        (const float4 *)ctx->pos4_build.p, (const float *)ctx->h_build.p, (const int32_t *)ctx->leaf_begin.p, (const int32_t *)ctx->leaf_count.p,
         nl, n, ax, std::max(513, min_count), (uint16_t *)ctx->axis_order.p);
     HIP_TRY(ctx, hipGetLastError());
   }
+  {
+    PROF(ctx, "axis_sort");
+    leaf_hq_kernel<<<(unsigned)ceil_div(HQ_N * nl, 256), 256, 0, ctx->stream>>>(
+        (const float *)ctx->h_build.p, (const int32_t *)ctx->leaf_begin.p, (const int32_t *)ctx->leaf_count.p,
+        nl, n, (const uint16_t *)ctx->axis_order.p, (float *)ctx->leaf_hq.p);
+  }
+  HIP_TRY(ctx, hipGetLastError());
   return SPH_OK;
 }
 
-// After a full build: every leaf of more than two 64-particle tiles is
-// sorted at once (the loops read smaller leaves whole, unsorted).  The keys
-// are the offsets of the full build, so cell updates keep the orders.  Where
+// After a full build: the axis orders of every leaf of more than two
+// 64-particle tiles (the loops read smaller leaves whole, unsorted) and the H
+// order of every leaf, at once.  The keys are the offsets and H of the full
+// build, so cell updates keep the orders.  Where
 // the paper runs sort tasks only for the active cells of a step, one launch
 // over all leaves here costs less than the per-step launches that finding
 // the newly reached leaves would take.
 sph_status sort_cells_impl(sph_ctx *ctx) {
   const int64_t n = ctx->n;
-  SPH_TRY(sph_ensure(ctx, ctx->axis_order, sizeof(uint16_t) * 13 * (size_t)n));
+  SPH_TRY(sph_ensure(ctx, ctx->axis_order, sizeof(uint16_t) * (HORD_ROW + 1) * (size_t)n));
   if (!ctx->leaves_checked) {
     int32_t maxc;
     SPH_TRY(read_scalars(ctx, SC_MAXLEAF, 1, &maxc));
@@ -234,6 +340,16 @@ sph_status sort_cells_impl(sph_ctx *ctx) {
     ctx->max_leaf = maxc;
     SPH_TRY(sort_leaves(ctx, 129));
     ctx->leaves_checked = 1;
+  } else if (ctx->n_leaves > 0) {
+    // kept cells: leaves whose H outgrew the keys of their H order by more
+    // than 2% are keyed again from the current H
+    const int64_t nl = ctx->n_leaves;
+    PROF(ctx, "axis_sort");
+    hrow_rekey_kernel<<<(unsigned)std::min<int64_t>(ceil_div(nl, 256), (int64_t)ctx->n_cu * 8), 256, 0, ctx->stream>>>(
+        (const float4 *)ctx->pos4.p, (const int32_t *)ctx->leaf_begin.p, (const int32_t *)ctx->leaf_count.p, nl, n,
+        1.02f, (float *)ctx->h_build.p, (uint16_t *)ctx->axis_order.p, (float *)ctx->leaf_hq.p,
+        (float *)ctx->leaf_hgrow.p);
+    HIP_TRY(ctx, hipGetLastError());
   }
   ctx->state = 2;
   return SPH_OK;

@@ -221,7 +221,8 @@ __global__ __launch_bounds__(BT) void offsets_kernel(const double *__restrict__ 
                                                      const int32_t *__restrict__ level, const int32_t *__restrict__ ix,
                                                      const int32_t *__restrict__ iy, const int32_t *__restrict__ iz,
                                                      int64_t nl, int D, double unit, float4 *__restrict__ pos4,
-                                                     float *__restrict__ leaf_hmax) {
+                                                     float *__restrict__ leaf_hmax, float *__restrict__ hb,
+                                                     float *__restrict__ hgrow) {
   const int64_t l = (int64_t)blockIdx.x * (BT / 64) + (threadIdx.x >> 6);
   if (l >= nl) return;
   const int lane = threadIdx.x & 63;
@@ -235,10 +236,14 @@ __global__ __launch_bounds__(BT) void offsets_kernel(const double *__restrict__ 
     const int s = b + k;
     const float H = GK32 * h[s];
     pos4[s] = make_float4((float)(x[s] - cx), (float)(y[s] - cy), (float)(z[s] - cz), H);
+    hb[s] = H;
     hm = fmaxf(hm, H);
   }
   hm = wave_max_f(hm);
-  if (lane == 0) leaf_hmax[l] = hm;
+  if (lane == 0) {
+    leaf_hmax[l] = hm;
+    hgrow[l] = 1.f;
+  }
 }
 
 // Cell update without a rebuild (the leaves of the last build kept): wraps
@@ -281,7 +286,8 @@ __global__ __launch_bounds__(BT) void update_kernel(double *__restrict__ x, doub
                                                     int64_t nl, int D, double L, double unit, float frac,
                                                     float4 *__restrict__ pos4, float *__restrict__ leaf_hmax,
                                                     float *__restrict__ leaf_dx, float2 *__restrict__ block_max,
-                                                    int32_t *__restrict__ sc_flag, PackArgs pk) {
+                                                    int32_t *__restrict__ sc_flag, const float *__restrict__ hb,
+                                                    float *__restrict__ hgrow, PackArgs pk) {
   const int64_t l = (int64_t)blockIdx.x * (BT / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   float hm = 0.f, dm = 0.f;
@@ -292,6 +298,7 @@ __global__ __launch_bounds__(BT) void update_kernel(double *__restrict__ x, doub
     const double cz = (double)((2 * (int64_t)iz[l] + 1) << sh) * unit;
     const int b = begin[l], cnt = count[l];
     double d2m = 0.0;  // largest displacement component
+    float gr = 0.f;    // largest H / H at the build
     for (int k = lane; k < cnt; k += 64) {
       const int s = b + k;
       const double x0 = x[s], y0 = y[s], z0 = z[s];
@@ -303,13 +310,16 @@ __global__ __launch_bounds__(BT) void update_kernel(double *__restrict__ x, doub
       const float H = GK32 * h[s];
       d2m = fmax(d2m, kept_offset(cx, cy, cz, L, xw, yw, zw, xb[s], yb[s], zb[s], H, pos4[s]));
       hm = fmaxf(hm, H);
+      gr = fmaxf(gr, H / hb[s]);
       if (pk.jvm) pack_one(pk, s);  // the loops' neighbour data, in the same pass
     }
     for (int o = 32; o > 0; o >>= 1) d2m = fmax(d2m, __shfl_xor(d2m, o, 64));
     hm = wave_max_f(hm);
+    gr = wave_max_f(gr);
     dm = disp_bound(d2m);
     if (lane == 0) {
       leaf_hmax[l] = hm;
+      hgrow[l] = gr;
       leaf_dx[l] = dm;
       if ((double)dm > (double)frac * ldexp(L, -level[l])) atomicOr(sc_flag, 1);
     }
@@ -541,6 +551,9 @@ sph_status build_cells_impl(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *
   SPH_TRY(sph_ensure(ctx, ctx->leaf_hmax, 4 * (size_t)nl));
   SPH_TRY(sph_ensure(ctx, ctx->leaf_of, 4 * n));
   SPH_TRY(sph_ensure(ctx, ctx->pos4, 16 * n));
+  SPH_TRY(sph_ensure(ctx, ctx->h_build, 4 * n));
+  SPH_TRY(sph_ensure(ctx, ctx->leaf_hgrow, 4 * (size_t)nl));
+  SPH_TRY(sph_ensure(ctx, ctx->leaf_hq, sizeof(float) * HQ_N * (size_t)nl));
   int32_t *lvl = (int32_t *)ctx->leaf_level.p, *lix = (int32_t *)ctx->leaf_ix.p, *liy = (int32_t *)ctx->leaf_iy.p,
           *liz = (int32_t *)ctx->leaf_iz.p, *lb = (int32_t *)ctx->leaf_begin.p, *lc = (int32_t *)ctx->leaf_count.p,
           *lof = (int32_t *)ctx->leaf_of.p;
@@ -558,7 +571,7 @@ sph_status build_cells_impl(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *
     PROF(ctx, "offsets");
     offsets_kernel<<<(unsigned)ceil_div(nl, BT / 64), BT, 0, ctx->stream>>>(
         p->x, p->y, p->z, p->h, lb, lc, lvl, lix, liy, liz, nl, D, ldexp(L, -(D + 1)), (float4 *)ctx->pos4.p,
-        (float *)ctx->leaf_hmax.p);
+        (float *)ctx->leaf_hmax.p, (float *)ctx->h_build.p, (float *)ctx->leaf_hgrow.p);
   }
   HIP_TRY(ctx, hipGetLastError());
   const int64_t ntop3 = (int64_t)1 << (3 * k0);
@@ -682,7 +695,8 @@ __global__ __launch_bounds__(BT) void drift_leaves_kernel(DriftArgs d, const int
                                                           const int32_t *__restrict__ iz, int D, double L,
                                                           double unit, int64_t *__restrict__ leaf_ti,
                                                           float4 *__restrict__ pos4, float *__restrict__ leaf_hmax,
-                                                          float *__restrict__ dx_base) {
+                                                          float *__restrict__ dx_base, const float *__restrict__ hb,
+                                                          float *__restrict__ hgrow) {
   const int lane = threadIdx.x & 63;
   const int64_t items = list_n ? (int64_t)*list_n : n_items;
   for (int64_t it = (int64_t)blockIdx.x * (BT / 64) + (threadIdx.x >> 6); it < items;
@@ -697,7 +711,7 @@ __global__ __launch_bounds__(BT) void drift_leaves_kernel(DriftArgs d, const int
     const double cz = (double)((2 * (int64_t)iz[l] + 1) << sh) * unit;
     const int b = begin[l], cnt = count[l];
     double d2m = 0.0;
-    float hm = 0.f;
+    float hm = 0.f, gr = 0.f;
     for (int k = lane; k < cnt; k += 64) {
       const int s = b + k;
       const double xw = wrap_box(d.x[s] + d.vfx[s] * dt, L);
@@ -719,12 +733,15 @@ __global__ __launch_bounds__(BT) void drift_leaves_kernel(DriftArgs d, const int
       const float H = GK32 * h;
       d2m = fmax(d2m, kept_offset(cx, cy, cz, L, xw, yw, zw, xb[s], yb[s], zb[s], H, pos4[s]));
       hm = fmaxf(hm, H);
+      gr = fmaxf(gr, H / hb[s]);
       d.jvm[s] = make_float4((float)vx, (float)vy, (float)vz, d.m[s]);
     }
     for (int o = 32; o > 0; o >>= 1) d2m = fmax(d2m, __shfl_xor(d2m, o, 64));
     hm = wave_max_f(hm);
+    gr = wave_max_f(gr);
     if (lane == 0) {
       leaf_hmax[l] = hm;
+      hgrow[l] = gr;
       dx_base[l] = disp_bound(d2m);
       leaf_ti[l] = d.ti_now;
     }
@@ -807,7 +824,8 @@ sph_status drift_leaves(sph_ctx *ctx, const sph_particles *p, const int32_t *lis
         (const int32_t *)ctx->leaf_count.p, (const int32_t *)ctx->leaf_level.p, (const int32_t *)ctx->leaf_ix.p,
         (const int32_t *)ctx->leaf_iy.p, (const int32_t *)ctx->leaf_iz.p, ctx->prm.morton_depth, ctx->prm.box,
         ldexp(ctx->prm.box, -(ctx->prm.morton_depth + 1)), (int64_t *)ctx->leaf_ti.p, (float4 *)ctx->pos4.p,
-        (float *)ctx->leaf_hmax.p, (float *)ctx->leaf_dx_base.p);
+        (float *)ctx->leaf_hmax.p, (float *)ctx->leaf_dx_base.p, (const float *)ctx->h_build.p,
+        (float *)ctx->leaf_hgrow.p);
   }
   return sph_hip_check(ctx, hipGetLastError(), "drift_leaves_kernel");
 }
@@ -914,7 +932,7 @@ sph_status update_cells(sph_ctx *ctx, sph_particles *p, int64_t *perm_out, int *
         (const int32_t *)ctx->leaf_count.p, (const int32_t *)ctx->leaf_level.p, (const int32_t *)ctx->leaf_ix.p,
         (const int32_t *)ctx->leaf_iy.p, (const int32_t *)ctx->leaf_iz.p, nl, D, L, ldexp(L, -(D + 1)),
         ctx->prm.rebuild_frac, (float4 *)ctx->pos4.p, (float *)ctx->leaf_hmax.p, (float *)ctx->leaf_dx.p,
-        (float2 *)ctx->scan_out.p, sc + SC_UPD_FLAG, pk);
+        (float2 *)ctx->scan_out.p, sc + SC_UPD_FLAG, (const float *)ctx->h_build.p, (float *)ctx->leaf_hgrow.p, pk);
     max2_reduce_kernel<<<1, BT, 0, ctx->stream>>>((const float2 *)ctx->scan_out.p, (int)blocks, sc + SC_UPD_HMAX);
   }
   HIP_TRY(ctx, hipGetLastError());

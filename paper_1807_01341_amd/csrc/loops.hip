@@ -318,6 +318,8 @@ LoopArgs base_args(sph_ctx *ctx) {
   a.leaf_half = (const float *)ctx->leaf_half.p;
   a.leaf_dx = (const float *)ctx->leaf_dx.p;
   a.axis_order = (const uint16_t *)ctx->axis_order.p;
+  a.leaf_hgrow = (const float *)ctx->leaf_hgrow.p;
+  a.leaf_hq = (const float4 *)ctx->leaf_hq.p;
   a.n = ctx->n;
   a.ax = host_axes();
   a.n_active = ctx->n_active;
@@ -546,6 +548,7 @@ __global__ __launch_bounds__(256) void ghost_multi_kernel(const GhostArgs *__res
 struct SweepPair {
   int off, bb;
   float sx, sy, sz;
+  int hord;  // nonzero: the range is the head of the leaf's H order, not the leaf itself
 };
 
 // Logical block of a sweep launch whose grid is a multiple of 8: the blocks
@@ -568,7 +571,7 @@ struct FlatRange {
 };
 
 __device__ __forceinline__ FlatRange compact_small(SweepPair *my, bool small, int bc, int bb, const PairEntry &e,
-                                                   int lane) {
+                                                   int lane, bool hord = false) {
   const int n_small = small ? bc : 0;
   int incl = n_small;
   for (int o = 1; o < 64; o <<= 1) {
@@ -589,6 +592,7 @@ __device__ __forceinline__ FlatRange compact_small(SweepPair *my, bool small, in
     q.sx = e.sx;
     q.sy = e.sy;
     q.sz = e.sz;
+    q.hord = hord ? 1 : 0;
     my[rank_below(m)] = q;
   }
   wave_sync();
@@ -952,29 +956,63 @@ __global__ __launch_bounds__(256) void force_sweep_kernel(LoopArgs g, const int3
       PairEntry e;
       e.b = 0;
       e.sx = e.sy = e.sz = 0.f;
-      int bb = 0, bc = 0;
-      bool near = false;
+      int bb = 0, bc = 0, nflat = 0;
+      bool near = false, head = false;
       if (p < pend) {
         e = g.pairs[p];
         bb = g.leaf_begin[e.b];
         bc = g.leaf_count[e.b];
-        near = leaf_in_reach(g, e, pi, fmaxf(Hi, g.leaf_hmax[e.b]));
+        nflat = bc;
+        // distance from pi to the leaf's box (widened by its drift margin),
+        // with the relative rounding guard of leaf_in_reach
+        const float hw = g.leaf_half[e.b] + g.leaf_dx[e.b];
+        const float gx = fmaxf(fabsf(pi.x - e.sx) - hw, 0.f);
+        const float gy = fmaxf(fabsf(pi.y - e.sy) - hw, 0.f);
+        const float gz = fmaxf(fabsf(pi.z - e.sz) - hw, 0.f);
+        const float g2 = fmaf(gz, gz, fmaf(gy, gy, gx * gx));
+        const float c = 1e-6f * (fabsf(pi.x) + fabsf(pi.y) + fabsf(pi.z) + hw);
+        const float Rm = 1.0001f * fmaxf(Hi, g.leaf_hmax[e.b]) + c, Ri = 1.0001f * Hi + c;
+        near = g2 < Rm * Rm;
+        if (near && !(g2 < Ri * Ri)) {
+          // beyond H_i from the whole leaf: only particles whose own H
+          // exceeds T (the gap less the guard) can be neighbours, and every
+          // one past rank hq_rank(q) of the leaf's H order has H at most
+          // sample q times the leaf's growth bound
+          const float T = (sqrtf(g2) - c) * (0.99999f / 1.0001f);
+          const float gr = g.leaf_hgrow[e.b] * 1.00001f;
+          const float4 *hq = g.leaf_hq + 4 * (int64_t)e.b;
+          int above = 0;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const float4 s = hq[u];
+            above += (s.x * gr > T) + (s.y * gr > T) + (s.z * gr > T) + (s.w * gr > T);
+          }
+          const int need = above < HQ_N ? min(hq_rank(above), bc) : bc;
+          if (need < bc) {
+            head = true;
+            nflat = need;
+          }
+        }
       }
-      const bool big = near && e.b != ch.leaf && bc > 128;
+      const bool big = near && !head && e.b != ch.leaf && bc > 128;
       int axl = 0;
       float sgl = 1.f;
       if (big) {
-      const uint8_t code = g.pair_axis[p];
-      axl = code & 0x7f;
-      sgl = (code & 0x80) ? -1.f : 1.f;
-    }
-      const FlatRange fr = compact_small(my, near && !big, bc, bb, e, lane);
+        const uint8_t code = g.pair_axis[p];
+        axl = code & 0x7f;
+        sgl = (code & 0x80) ? -1.f : 1.f;
+      }
+      // the own leaf, small partners and the heads of H orders as one flat range
+      const FlatRange fr = compact_small(my, near && !big, nflat, bb, e, lane, head);
+      const uint16_t *hrow = g.axis_order + (int64_t)HORD_ROW * g.n;
       for (int t = sub * 64; t < fr.total; t += 2 * NWP * 64) {
         // two candidates per lane, their loads in flight together
         const int f0 = t + lane, f1 = t + NWP * 64 + lane;
         const bool v0 = f0 < fr.total, v1 = f1 < fr.total;
         const SweepPair q0 = locate(my, fr, v0 ? f0 : 0), q1 = locate(my, fr, v1 ? f1 : 0);
-        const int j0 = q0.bb + (v0 ? f0 - q0.off : 0), j1 = q1.bb + (v1 ? f1 - q1.off : 0);
+        const int l0 = v0 ? f0 - q0.off : 0, l1 = v1 ? f1 - q1.off : 0;
+        const int j0 = q0.bb + (q0.hord ? (int)hrow[q0.bb + l0] : l0);
+        const int j1 = q1.bb + (q1.hord ? (int)hrow[q1.bb + l1] : l1);
         const float4 pj0 = g.pos4[j0], pj1 = g.pos4[j1];
         visit(v0, j0, pj0, q0.sx, q0.sy, q0.sz);
         visit(v1, j1, pj1, q1.sx, q1.sy, q1.sz);

@@ -52,7 +52,9 @@ struct LoopArgs {
   const int32_t *pair_off;
   const PairEntry *pairs;
   const uint8_t *pair_axis;  // per pair: sweep axis code
-  const uint16_t *axis_order;
+  const uint16_t *axis_order;  // 13 axis orders, then the H order (HORD_ROW)
+  const float *leaf_hgrow;     // per leaf: bound on H now / H at the full build
+  const float4 *leaf_hq;       // per leaf: H at the build at ranks hq_rank(0..15) of its H order
   int64_t n;
   AxisTab ax;
   // density outputs: per active index

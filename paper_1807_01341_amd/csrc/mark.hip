@@ -349,22 +349,27 @@ __global__ __launch_bounds__(MT) void leaf_hmax_refresh_kernel(const float4 *__r
                                                                const int32_t *__restrict__ act_leaves,
                                                                int64_t n_act_leaves, float *__restrict__ leaf_hmax,
                                                                float *__restrict__ act_hmax,
-                                                               int *__restrict__ hmax_bits) {
+                                                               int *__restrict__ hmax_bits,
+                                                               const float *__restrict__ hb,
+                                                               float *__restrict__ hgrow) {
   const int64_t a = (int64_t)blockIdx.x * (MT / 64) + (threadIdx.x >> 6);
   if (a >= n_act_leaves) return;
   const int lane = threadIdx.x & 63;
   const int A = act_leaves[a];
   const int b = leaf_begin[A], c = leaf_count[A];
-  float hm = 0.f, ha = 0.f;
+  float hm = 0.f, ha = 0.f, gr = 0.f;
   for (int k = lane; k < c; k += 64) {
     const float H = pos4[b + k].w;
     hm = fmaxf(hm, H);
+    gr = fmaxf(gr, H / hb[b + k]);
     if (active[b + k]) ha = fmaxf(ha, H);
   }
   hm = wave_max_f(hm);
   ha = wave_max_f(ha);
+  gr = wave_max_f(gr);
   if (lane == 0) {
     leaf_hmax[A] = hm;
+    hgrow[A] = gr;
     act_hmax[a] = ha;
     atomicMax(hmax_bits, __float_as_int(hm));
   }
@@ -478,7 +483,7 @@ sph_status refresh_leaf_hmax(sph_ctx *ctx) {
     leaf_hmax_refresh_kernel<<<waves_grid(na), MT, 0, ctx->stream>>>(
         (const float4 *)ctx->pos4.p, (const uint8_t *)ctx->active.p, (const int32_t *)ctx->leaf_begin.p,
         (const int32_t *)ctx->leaf_count.p, (const int32_t *)ctx->act_leaves.p, na, (float *)ctx->leaf_hmax.p,
-        (float *)ctx->act_hmax.p, sc + SC_HMAX_BITS);
+        (float *)ctx->act_hmax.p, sc + SC_HMAX_BITS, (const float *)ctx->h_build.p, (float *)ctx->leaf_hgrow.p);
   }
   HIP_TRY(ctx, hipGetLastError());
   return SPH_OK;

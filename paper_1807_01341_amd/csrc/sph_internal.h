@@ -58,6 +58,16 @@ struct AxisTab {
   float e[13][3];
 };
 
+// Row of axis_order that lists each leaf's particles by H at the full build,
+// largest first (ties by in-leaf index), and the ranks of that order at which
+// leaf_hq samples H: every particle at rank >= hq_rank(q) has H at the build
+// <= sample q.
+constexpr int HORD_ROW = 13;
+constexpr int HQ_N = 16;
+__host__ __device__ __forceinline__ int hq_rank(int q) {
+  return q < 6 ? 4 * (q + 1) : (q < 9 ? 32 + 8 * (q - 6) : (q < 12 ? 64 + 16 * (q - 9) : (q < 13 ? 128 : 64 * (q - 10))));
+}
+
 inline AxisTab host_axes() {
   AxisTab a;
   int k = 0;
@@ -147,7 +157,11 @@ struct sph_ctx {
   DevBuf pos4;                            // float4 (ox, oy, oz, H) per particle
   DevBuf pos4_build;                      // pos4 of the last full build (the axis sorts' keys)
   // sort
-  DevBuf axis_order;                      // uint16 13 x n
+  DevBuf axis_order;                      // uint16 14 x n: the 13 axes, then the H order (HORD_ROW)
+  // force-loop pruning by H: each particle's H at the full build, per leaf a
+  // bound on H now / H at the build over its particles, and H at the build at
+  // the ranks hq_rank(0..15) of the leaf's H order (0 past its count)
+  DevBuf h_build, leaf_hgrow, leaf_hq;
   int max_leaf = 0;                       // largest leaf of the build
   int leaves_checked = 0;                 // max_leaf read and the leaves sorted for the current build
   // mark
