@@ -56,16 +56,19 @@ __global__ __launch_bounds__(BT) void morton_kernel(double *__restrict__ x, doub
   }
 }
 
-__global__ __launch_bounds__(BT) void max_reduce_kernel(const float *__restrict__ part, int n, int *__restrict__ out_bits) {
+__global__ __launch_bounds__(1024) void max_reduce_kernel(const float *__restrict__ part, int n, int *__restrict__ out_bits) {
   float m = 0.f;
-  for (int k = threadIdx.x; k < n; k += BT) m = fmaxf(m, part[k]);
-  __shared__ float wmax[BT / 64];
+  int k = threadIdx.x;
+  for (; k + 3 * 1024 < n; k += 4 * 1024)
+    m = fmaxf(fmaxf(m, part[k]), fmaxf(part[k + 1024], fmaxf(part[k + 2048], part[k + 3072])));
+  for (; k < n; k += 1024) m = fmaxf(m, part[k]);
+  __shared__ float wmax[16];
   m = wave_max_f(m);
   if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
   __syncthreads();
   if (threadIdx.x == 0) {
     float b = wmax[0];
-    for (int w = 1; w < BT / 64; ++w) b = fmaxf(b, wmax[w]);
+    for (int w = 1; w < 16; ++w) b = fmaxf(b, wmax[w]);
     *out_bits = __float_as_int(b);
   }
 }
@@ -340,14 +343,23 @@ __global__ __launch_bounds__(BT) void update_kernel(double *__restrict__ x, doub
   }
 }
 
-__global__ __launch_bounds__(BT) void max2_reduce_kernel(const float2 *__restrict__ part, int n,
+// One block of RT threads: every thread takes a strided quarter of the
+// partials four at a time, so that its loads are in flight together.
+#define RT 1024
+__global__ __launch_bounds__(RT) void max2_reduce_kernel(const float2 *__restrict__ part, int n,
                                                          int32_t *__restrict__ out_bits) {
   float a = 0.f, d = 0.f;
-  for (int k = threadIdx.x; k < n; k += BT) {
+  int k = threadIdx.x;
+  for (; k + 3 * RT < n; k += 4 * RT) {
+    const float2 p0 = part[k], p1 = part[k + RT], p2 = part[k + 2 * RT], p3 = part[k + 3 * RT];
+    a = fmaxf(fmaxf(a, p0.x), fmaxf(p1.x, fmaxf(p2.x, p3.x)));
+    d = fmaxf(fmaxf(d, p0.y), fmaxf(p1.y, fmaxf(p2.y, p3.y)));
+  }
+  for (; k < n; k += RT) {
     a = fmaxf(a, part[k].x);
     d = fmaxf(d, part[k].y);
   }
-  __shared__ float wa[BT / 64], wd[BT / 64];
+  __shared__ float wa[RT / 64], wd[RT / 64];
   a = wave_max_f(a);
   d = wave_max_f(d);
   if ((threadIdx.x & 63) == 0) {
@@ -356,12 +368,10 @@ __global__ __launch_bounds__(BT) void max2_reduce_kernel(const float2 *__restric
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int w = 1; w < BT / 64; ++w) {
+    for (int w = 0; w < RT / 64; ++w) {
       a = fmaxf(a, wa[w]);
       d = fmaxf(d, wd[w]);
     }
-    a = fmaxf(a, wa[0]);
-    d = fmaxf(d, wd[0]);
     out_bits[0] = __float_as_int(a);
     out_bits[1] = __float_as_int(d);
   }
@@ -457,7 +467,7 @@ sph_status build_cells_impl(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *
     morton_kernel<<<mgrid, BT, 0, ctx->stream>>>(p->x, p->y, p->z, p->h, n, L, scale, kmax,
                                                 (uint64_t *)ctx->keys_a.p, (int32_t *)ctx->vals_a.p,
                                                 (float *)ctx->scan_out.p);
-    max_reduce_kernel<<<1, BT, 0, ctx->stream>>>((const float *)ctx->scan_out.p, (int)mgrid, sc + SC_HMAX_BITS);
+    max_reduce_kernel<<<1, 1024, 0, ctx->stream>>>((const float *)ctx->scan_out.p, (int)mgrid, sc + SC_HMAX_BITS);
   }
   HIP_TRY(ctx, hipGetLastError());
   SPH_TRY(radix_sort_pairs(ctx, n, 3 * D));
@@ -886,7 +896,7 @@ sph_status lazy_keep_cells(sph_ctx *ctx, int *rebuild) {
         (const int64_t *)ctx->leaf_ti.p, (const float *)ctx->leaf_vmax.p, (const float *)ctx->leaf_dx_base.p,
         (const float *)ctx->leaf_hmax.p, (const int32_t *)ctx->leaf_level.p, nl, L, ctx->prm.rebuild_frac,
         ctx->ti_now, ctx->t_min_line, (float *)ctx->leaf_dx.p, (float2 *)ctx->scan_out.p, sc + SC_UPD_FLAG);
-    max2_reduce_kernel<<<1, BT, 0, ctx->stream>>>((const float2 *)ctx->scan_out.p, (int)blocks, sc + SC_UPD_HMAX);
+    max2_reduce_kernel<<<1, RT, 0, ctx->stream>>>((const float2 *)ctx->scan_out.p, (int)blocks, sc + SC_UPD_HMAX);
   }
   HIP_TRY(ctx, hipGetLastError());
   int32_t st[3];
@@ -933,7 +943,7 @@ sph_status update_cells(sph_ctx *ctx, sph_particles *p, int64_t *perm_out, int *
         (const int32_t *)ctx->leaf_iy.p, (const int32_t *)ctx->leaf_iz.p, nl, D, L, ldexp(L, -(D + 1)),
         ctx->prm.rebuild_frac, (float4 *)ctx->pos4.p, (float *)ctx->leaf_hmax.p, (float *)ctx->leaf_dx.p,
         (float2 *)ctx->scan_out.p, sc + SC_UPD_FLAG, (const float *)ctx->h_build.p, (float *)ctx->leaf_hgrow.p, pk);
-    max2_reduce_kernel<<<1, BT, 0, ctx->stream>>>((const float2 *)ctx->scan_out.p, (int)blocks, sc + SC_UPD_HMAX);
+    max2_reduce_kernel<<<1, RT, 0, ctx->stream>>>((const float2 *)ctx->scan_out.p, (int)blocks, sc + SC_UPD_HMAX);
   }
   HIP_TRY(ctx, hipGetLastError());
   int32_t st[3];

@@ -371,7 +371,8 @@ __global__ __launch_bounds__(MT) void leaf_hmax_refresh_kernel(const float4 *__r
     leaf_hmax[A] = hm;
     hgrow[A] = gr;
     act_hmax[a] = ha;
-    atomicMax(hmax_bits, __float_as_int(hm));
+    // the running max rarely rises: most waves skip the contended atomic
+    if (hm > __int_as_float(__atomic_load_n(hmax_bits, __ATOMIC_RELAXED))) atomicMax(hmax_bits, __float_as_int(hm));
   }
 }
 
