@@ -216,3 +216,44 @@ def test_lazy_drift_matches_drift_all(gpu_lib):
     a0 = np.stack([s0[k] for k in ("ax", "ay", "az")], 1).astype(np.float64)
     a1 = np.stack([s1[k] for k in ("ax", "ay", "az")], 1).astype(np.float64)
     assert np.linalg.norm(a1 - a0) < 1e-5 * np.linalg.norm(a0)
+
+
+@pytest.mark.parametrize("growth", [1.015, 1.3])
+def test_force_counts_after_h_growth_on_kept_cells(gpu_lib, growth):
+    """The force loop reads a partner leaf beyond H_i only up to the rank of
+    its H order past which no particle's H can reach the gap.  After the
+    smoothing lengths on kept cells grow by up to `growth` (below the re-key
+    margin the growth bound scales the keys, above it the orders are keyed
+    again from the current H), the counts of a deep time-bin are still those
+    of the all-pairs definition."""
+    sg = gpu_lib
+    ic = ics.clustered(n_total=20000, n_clumps=3)
+    m = ics.deep_bin_for_fraction(ic["bin"], 0.05)
+    print(f"case clustered20k h growth {growth} m={m}", flush=True)
+    p = sg.Particles.from_initial(ic)
+    ctx = sg.Context()
+    perm = torch.empty(p.n, dtype=torch.int64, device="cuda")
+    ctx.build_cells(p, perm)
+    ctx.sort_cells()
+    ctx.mark_active(p, ctx.params.n_bins - 1)
+    ctx.density_pass(p, True)
+    ctx.force_pass(p)
+    ctx.sync()
+    rng = np.random.default_rng(11)
+    fac = torch.as_tensor(rng.uniform(1.0, growth, p.n).astype(np.float32), device="cuda")
+    p["h"].mul_(fac)
+    ctx.build_cells(p)
+    assert ctx.info()["cell_updates"] == 1
+    ctx.sort_cells()
+    ctx.mark_active(p, m)
+    ctx.density_pass(p, False)
+    ctx.force_pass(p)
+    ctx.sync()
+    cl = emu.build_cells(ic["x"], ic["h"], split=400, D=16)
+    assert np.array_equal(perm.cpu().numpy(), cl["perm"])
+    H = (np.float32(1.825742) * host(p, "h")).astype(np.float32)
+    act = emu.mark_active(cl, ic["bin"][cl["perm"]], m, H=H)
+    idx = np.nonzero(act["active"])[0]
+    assert 0 < idx.size < p.n
+    assert np.array_equal(host(p, "nngb_density")[idx], emu.counts(cl, "density", idx, H=H))
+    assert np.array_equal(host(p, "nngb_force")[idx], emu.counts(cl, "force", idx, H=H))
