@@ -32,17 +32,20 @@ sys.path.insert(0, ROOT)
 FP32_PEAK = 157.3e12      # MI355X FP32 vector, FLOP/s
 FP32_UNPACKED = 78.6e12   # one FMA per lane per clock (256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz)
 HBM_PEAK = 8.0e12         # bytes/s
-# algorithmic FLOP per interaction of the two loops (mul/add = 1, fma = 2,
-# rsqrt/rcp = 1, compare/select = 0), counted from the pair formulas
-# HBM traffic of the dominant kernel per launch, from two rocprofv3 --pmc
-# runs (FETCH_SIZE, WRITE_SIZE) scaled by the same counters on a plain
-# 512 MiB copy (profiles/force_sweep_deepbin_pmc.md), valid while the
-# kernel's sources are the ones that were measured (else reported as null)
+# HBM traffic of the loop kernels per launch, from two rocprofv3 --pmc runs
+# (FETCH_SIZE, WRITE_SIZE) scaled by the same counters on a plain 512 MiB
+# copy (profiles/force_sweep_deepbin_pmc.md, profiles/density_sweep_deepbin_pmc.md),
+# valid while the kernels' sources are the ones that were measured (else
+# reported as null)
 MEASURED_TRAFFIC = {
     "force_loop": {"bytes": 15270806.0,
                    "sources": ["paper_1807_01341_amd/csrc/loops.hip", "paper_1807_01341_amd/csrc/loops_common.h",
                                "paper_1807_01341_amd/csrc/sph_internal.h"],
                    "sha256": "46466b9c276de732df9c9b130e4235eefc19969f76b4eacae133731b339cac29"},
+    "density_loop": {"bytes": 33483828.0,
+                     "sources": ["paper_1807_01341_amd/csrc/loops.hip", "paper_1807_01341_amd/csrc/loops_common.h",
+                                 "paper_1807_01341_amd/csrc/sph_internal.h"],
+                     "sha256": "46466b9c276de732df9c9b130e4235eefc19969f76b4eacae133731b339cac29"},
 }
 
 
@@ -58,6 +61,8 @@ def measured_traffic(kernel):
     return m["bytes"] if h.hexdigest() == m["sha256"] else None
 
 
+# algorithmic FLOP per interaction of the two loops (mul/add = 1, fma = 2,
+# rsqrt/rcp = 1, compare/select = 0), counted from the pair formulas
 FLOP_DENSITY = 60
 FLOP_FORCE = 72
 
