@@ -245,7 +245,8 @@ class Context:
         self._pc = None
 
     def __del__(self):
-        if getattr(self, "h", None):
+        # at interpreter exit the module's globals may already be gone
+        if getattr(self, "h", None) and callable(lib):
             lib().sph_destroy(self.h)
             self.h = None
 

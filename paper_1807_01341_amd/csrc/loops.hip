@@ -133,11 +133,36 @@ __global__ void cost_bucket_scan_kernel(int32_t *hist) {
   }
 }
 
+// Slot of a lane's item in its bucket (valid lanes): the lanes of a wave
+// with the same bucket take consecutive slots through one atomic per
+// distinct bucket (per-lane atomics on the few bucket cursors serialise).
+// Every lane of the wave calls it.
+__device__ __forceinline__ int bucket_slot(int32_t *__restrict__ cursor, int bucket, bool valid) {
+  const int lane = threadIdx.x & 63;
+  int slot = -1;
+  for (uint64_t todo = __ballot(valid); todo;) {
+    const int leader = __ffsll((unsigned long long)todo) - 1;
+    const int b = __shfl(bucket, leader, 64);
+    const uint64_t m = __ballot(valid && bucket == b);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&cursor[b], __popcll(m));
+    base = __shfl(base, leader, 64);
+    if (valid && bucket == b) slot = base + rank_below(m);
+    todo &= ~m;
+  }
+  return slot;
+}
+
 __global__ __launch_bounds__(256) void item_scatter_kernel(const int32_t *__restrict__ items,
                                                            const int32_t *__restrict__ bucket_of, int64_t n,
                                                            int32_t *__restrict__ cursor, int32_t *__restrict__ out) {
-  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256)
-    out[atomicAdd(&cursor[bucket_of[q]], 1)] = items[q];
+  const int lane = threadIdx.x & 63;
+  for (int64_t q0 = (int64_t)blockIdx.x * 256 + (threadIdx.x & ~63); q0 < n; q0 += (int64_t)gridDim.x * 256) {
+    const int64_t q = q0 + lane;
+    const bool valid = q < n;
+    const int s = bucket_slot(cursor, valid ? bucket_of[q] : 0, valid);
+    if (valid) out[s] = items[q];
+  }
 }
 
 // Workgroups of a persistent launch: every CU filled to the occupancy its
@@ -1600,8 +1625,14 @@ __global__ __launch_bounds__(256) void batch_scatter_kernel(const BatchItems *__
                                                             const int32_t *__restrict__ bucket_of,
                                                             int32_t *__restrict__ cursor, int2 *__restrict__ work) {
   const BatchItems b = boxes[blockIdx.y];
-  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < b.n_items; q += (int64_t)gridDim.x * 256)
-    work[atomicAdd(&cursor[bucket_of[b.off + q]], 1)] = make_int2(b.box, b.items[q]);
+  const int lane = threadIdx.x & 63;
+  for (int64_t q0 = (int64_t)blockIdx.x * 256 + (threadIdx.x & ~63); q0 < b.n_items;
+       q0 += (int64_t)gridDim.x * 256) {
+    const int64_t q = q0 + lane;
+    const bool valid = q < b.n_items;
+    const int s = bucket_slot(cursor, valid ? bucket_of[b.off + q] : 0, valid);
+    if (valid) work[s] = make_int2(b.box, b.items[q]);
+  }
 }
 
 __global__ __launch_bounds__(256) void batch_todo_kernel(const BatchItems *__restrict__ boxes) {
@@ -1684,19 +1715,19 @@ sph_status batch_fail(sph_ctx *lead, int b, sph_ctx *box, sph_status st) {
 sph_status batch_work_list(sph_ctx *lead, sph_ctx **cs, const std::vector<int> &live, Staging &s, int set_todo,
                            int target, int64_t *total_out) {
   const int nl = (int)live.size();
-  std::vector<int32_t> totals(nl, 0);
+  // each box's item total into its page-locked slot, one synchronisation
   bool any = false;
   for (int q = 0; q < nl; ++q) {
     sph_ctx *c = cs[live[q]];
     if (c->work_valid && c->items_target == target) continue;
-    SPH_TRY(items_count(c, target, &totals[q]));
+    SPH_TRY(items_count(c, target, c->pin.p + PIN_ITEMS));
     any = true;
   }
   if (any && target > 0) HIP_TRY(lead, hipStreamSynchronize(lead->stream));
   for (int q = 0; q < nl; ++q) {
     sph_ctx *c = cs[live[q]];
     if (c->work_valid && c->items_target == target) continue;
-    SPH_TRY(items_fill(c, target, totals[q]));
+    SPH_TRY(items_fill(c, target, c->pin.p[PIN_ITEMS]));
   }
   int64_t total = 0, maxc = 0;
   for (int q = 0; q < nl; ++q) {
@@ -1841,11 +1872,12 @@ sph_status batch_density_impl(sph_ctx **cs, sph_particles *ps, int nb, int entro
     }
     iterating.swap(next);
   }
-  // leaf max H per box (and its running global max, on the device)
+  // leaf max H per box (and its running global max, on the device), one launch
+  SPH_TRY(refresh_leaf_hmax_boxes(lead, cs, live.data(), nl));
   sph_status first = SPH_OK;
   for (int q = 0; q < nl; ++q) {
     sph_ctx *c = cs[live[q]];
-    const sph_status e = density_end(c, false);
+    const sph_status e = density_end(c, true);
     if (e != SPH_OK && first == SPH_OK) first = batch_fail(lead, live[q], c, e);
   }
   return first;
@@ -1870,10 +1902,12 @@ sph_status batch_force_impl(sph_ctx **cs, sph_particles *ps, int nb) {
   if (live.empty()) return SPH_OK;
   const int nl = (int)live.size();
   // force cell pairs of every box with one synchronisation
-  std::vector<int32_t> np(nl);
-  for (int q = 0; q < nl; ++q) BATCH_TRY(live[q], build_pairs_count(cs[live[q]], 1, 1.0f, &np[q]));
+  // (each count into its box's page-locked slot, so that none waits by itself)
+  for (int q = 0; q < nl; ++q)
+    BATCH_TRY(live[q], build_pairs_count(cs[live[q]], 1, 1.0f, cs[live[q]]->pin.p + PIN_NPAIRS));
   HIP_TRY(lead, hipStreamSynchronize(lead->stream));
-  for (int q = 0; q < nl; ++q) BATCH_TRY(live[q], build_pairs_fill(cs[live[q]], 1, 1.0f, np[q]));
+  for (int q = 0; q < nl; ++q)
+    BATCH_TRY(live[q], build_pairs_fill(cs[live[q]], 1, 1.0f, cs[live[q]]->pin.p[PIN_NPAIRS]));
   Staging s = staging(lead, nl);
   int64_t nchunks = 0;
   for (int b : live) nchunks += cs[b]->n_chunks;

@@ -340,40 +340,68 @@ __global__ __launch_bounds__(MT) void pairs_kernel(int mode, float slack, PairGe
   }
 }
 
-// Max H over each active leaf's particles (all of them) and the running
-// global max, after the density loop changed active smoothing lengths.
-__global__ __launch_bounds__(MT) void leaf_hmax_refresh_kernel(const float4 *__restrict__ pos4,
-                                                               const uint8_t *__restrict__ active,
-                                                               const int32_t *__restrict__ leaf_begin,
-                                                               const int32_t *__restrict__ leaf_count,
-                                                               const int32_t *__restrict__ act_leaves,
-                                                               int64_t n_act_leaves, float *__restrict__ leaf_hmax,
-                                                               float *__restrict__ act_hmax,
-                                                               int *__restrict__ hmax_bits,
-                                                               const float *__restrict__ hb,
-                                                               float *__restrict__ hgrow) {
-  const int64_t a = (int64_t)blockIdx.x * (MT / 64) + (threadIdx.x >> 6);
-  if (a >= n_act_leaves) return;
+// Max H over each active leaf's particles (all of them), the max over its
+// active ones, the H growth bound of its H order, and the running global max,
+// after the density loop changed active smoothing lengths.  One wave per
+// active leaf; `boxes` holds one set of arguments per box (blockIdx.y).
+struct RefreshArgs {
+  const float4 *pos4;
+  const uint8_t *active;
+  const int32_t *leaf_begin, *leaf_count, *act_leaves;
+  int64_t n_act_leaves;
+  float *leaf_hmax, *act_hmax;
+  int *hmax_bits;
+  const float *hb;
+  float *hgrow;
+};
+
+__device__ __forceinline__ void refresh_body(const RefreshArgs &r) {
   const int lane = threadIdx.x & 63;
-  const int A = act_leaves[a];
-  const int b = leaf_begin[A], c = leaf_count[A];
-  float hm = 0.f, ha = 0.f, gr = 0.f;
-  for (int k = lane; k < c; k += 64) {
-    const float H = pos4[b + k].w;
-    hm = fmaxf(hm, H);
-    gr = fmaxf(gr, H / hb[b + k]);
-    if (active[b + k]) ha = fmaxf(ha, H);
+  for (int64_t a = (int64_t)blockIdx.x * (MT / 64) + (threadIdx.x >> 6); a < r.n_act_leaves;
+       a += (int64_t)gridDim.x * (MT / 64)) {
+    const int A = r.act_leaves[a];
+    const int b = r.leaf_begin[A], c = r.leaf_count[A];
+    float hm = 0.f, ha = 0.f, gr = 0.f;
+    for (int k = lane; k < c; k += 64) {
+      const float H = r.pos4[b + k].w;
+      hm = fmaxf(hm, H);
+      gr = fmaxf(gr, H / r.hb[b + k]);
+      if (r.active[b + k]) ha = fmaxf(ha, H);
+    }
+    hm = wave_max_f(hm);
+    ha = wave_max_f(ha);
+    gr = wave_max_f(gr);
+    if (lane == 0) {
+      r.leaf_hmax[A] = hm;
+      r.hgrow[A] = gr;
+      r.act_hmax[a] = ha;
+      // the running max rarely rises: most waves skip the contended atomic
+      if (hm > __int_as_float(__atomic_load_n(r.hmax_bits, __ATOMIC_RELAXED)))
+        atomicMax(r.hmax_bits, __float_as_int(hm));
+    }
   }
-  hm = wave_max_f(hm);
-  ha = wave_max_f(ha);
-  gr = wave_max_f(gr);
-  if (lane == 0) {
-    leaf_hmax[A] = hm;
-    hgrow[A] = gr;
-    act_hmax[a] = ha;
-    // the running max rarely rises: most waves skip the contended atomic
-    if (hm > __int_as_float(__atomic_load_n(hmax_bits, __ATOMIC_RELAXED))) atomicMax(hmax_bits, __float_as_int(hm));
-  }
+}
+
+__global__ __launch_bounds__(MT) void leaf_hmax_refresh_kernel(RefreshArgs r) { refresh_body(r); }
+
+__global__ __launch_bounds__(MT) void leaf_hmax_refresh_multi_kernel(const RefreshArgs *__restrict__ boxes) {
+  refresh_body(boxes[blockIdx.y]);
+}
+
+static RefreshArgs refresh_args(sph_ctx *ctx) {
+  RefreshArgs r;
+  r.pos4 = (const float4 *)ctx->pos4.p;
+  r.active = (const uint8_t *)ctx->active.p;
+  r.leaf_begin = (const int32_t *)ctx->leaf_begin.p;
+  r.leaf_count = (const int32_t *)ctx->leaf_count.p;
+  r.act_leaves = (const int32_t *)ctx->act_leaves.p;
+  r.n_act_leaves = ctx->n_active_leaves;
+  r.leaf_hmax = (float *)ctx->leaf_hmax.p;
+  r.act_hmax = (float *)ctx->act_hmax.p;
+  r.hmax_bits = (int32_t *)ctx->scalars.p + SC_HMAX_BITS;
+  r.hb = (const float *)ctx->h_build.p;
+  r.hgrow = (float *)ctx->leaf_hgrow.p;
+  return r;
 }
 
 static unsigned waves_grid(int64_t n_items) { return (unsigned)(ceil_div(n_items, MT / 64) > 0 ? ceil_div(n_items, MT / 64) : 1); }
@@ -478,16 +506,38 @@ sph_status build_pairs(sph_ctx *ctx, int which, float slack) {
 sph_status refresh_leaf_hmax(sph_ctx *ctx) {
   const int64_t na = ctx->n_active_leaves;
   if (na == 0) return SPH_OK;
-  int32_t *sc = (int32_t *)ctx->scalars.p;
   {
     PROF(ctx, "cell_pairs");
-    leaf_hmax_refresh_kernel<<<waves_grid(na), MT, 0, ctx->stream>>>(
-        (const float4 *)ctx->pos4.p, (const uint8_t *)ctx->active.p, (const int32_t *)ctx->leaf_begin.p,
-        (const int32_t *)ctx->leaf_count.p, (const int32_t *)ctx->act_leaves.p, na, (float *)ctx->leaf_hmax.p,
-        (float *)ctx->act_hmax.p, sc + SC_HMAX_BITS, (const float *)ctx->h_build.p, (float *)ctx->leaf_hgrow.p);
+    leaf_hmax_refresh_kernel<<<waves_grid(na), MT, 0, ctx->stream>>>(refresh_args(ctx));
   }
   HIP_TRY(ctx, hipGetLastError());
   return SPH_OK;
+}
+
+// The refresh of several boxes (one stream) in one launch.  The host copy of
+// the arguments lives in the lead context and is rewritten only by the next
+// batched pass, which starts by draining the stream.
+sph_status refresh_leaf_hmax_boxes(sph_ctx *lead, sph_ctx **cs, const int *boxes, int nbox) {
+  lead->refresh_host.resize(sizeof(RefreshArgs) * (size_t)nbox);
+  RefreshArgs *rs = reinterpret_cast<RefreshArgs *>(lead->refresh_host.data());
+  int nr = 0;
+  int64_t maxa = 0;
+  for (int q = 0; q < nbox; ++q) {
+    sph_ctx *c = cs[boxes[q]];
+    if (c->n_active_leaves == 0) continue;
+    rs[nr++] = refresh_args(c);
+    maxa = std::max<int64_t>(maxa, c->n_active_leaves);
+  }
+  if (nr == 0) return SPH_OK;
+  SPH_TRY(sph_ensure(lead, lead->refresh_args, sizeof(RefreshArgs) * (size_t)nr));
+  {
+    PROF(lead, "cell_pairs");
+    HIP_TRY(lead, hipMemcpyAsync(lead->refresh_args.p, rs, sizeof(RefreshArgs) * (size_t)nr, hipMemcpyHostToDevice,
+                                 lead->stream));
+    leaf_hmax_refresh_multi_kernel<<<dim3(std::min<unsigned>(waves_grid(maxa), 1024u), (unsigned)nr), MT, 0,
+                                     lead->stream>>>((const RefreshArgs *)lead->refresh_args.p);
+  }
+  return sph_hip_check(lead, hipGetLastError(), "leaf max H refresh");
 }
 
 sph_status mark_active_impl(sph_ctx *ctx, const sph_particles *p, int m, int64_t *n_active_host) {

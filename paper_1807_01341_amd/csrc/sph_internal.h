@@ -162,6 +162,8 @@ struct sph_ctx {
   // bound on H now / H at the build over its particles, and H at the build at
   // the ranks hq_rank(0..15) of the leaf's H order (0 past its count)
   DevBuf h_build, leaf_hgrow, leaf_hq;
+  DevBuf refresh_args;                    // batched leaf max-H refresh: device copy of the per-box arguments
+  std::vector<char> refresh_host;         // and its host staging
   int max_leaf = 0;                       // largest leaf of the build
   int leaves_checked = 0;                 // max_leaf read and the leaves sorted for the current build
   // mark
@@ -298,6 +300,8 @@ sph_status build_pairs(sph_ctx *ctx, int which, float slack);
 sph_status build_pairs_count(sph_ctx *ctx, int which, float slack, int32_t *host_total);
 sph_status build_pairs_fill(sph_ctx *ctx, int which, float slack, int32_t np);
 sph_status refresh_leaf_hmax(sph_ctx *ctx);
+// The same for the boxes cs[boxes[0..nbox)] (one stream), in one launch.
+sph_status refresh_leaf_hmax_boxes(sph_ctx *lead, sph_ctx **cs, const int *boxes, int nbox);
 #define LEAF_BLOCK 32
 sph_status sort_all_leaves(sph_ctx *ctx);
 sph_status pack_neighbour_data(sph_ctx *ctx, const sph_particles *p);
