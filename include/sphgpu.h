@@ -156,8 +156,12 @@ sph_status sph_build_cells(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *p
  * than a bound.  After a full build this call sorts every leaf of more than
  * 128 particles in one launch (the loops read smaller leaves whole), after
  * one synchronisation that checks the largest leaf (SPH_EINVAL above 4096
- * particles); after a cell update it does nothing.  sph_copy_axis_order
- * sorts every leaf first. */
+ * particles).  It also orders every leaf's particles by H, largest first,
+ * for the force loop: with the symmetric cutoff r < max(H_i, H_j), a partner
+ * leaf beyond H_i is read only as far as some H_j can reach it.  After a
+ * cell update it orders again by the current H the leaves whose H grew more
+ * than 2 % past the H they were ordered by (no synchronisation).
+ * sph_copy_axis_order sorts every leaf first and copies the 13 axis orders. */
 sph_status sph_sort_cells(sph_ctx *ctx);
 
 /* Active set for the current time-bin (Eq. 2, Sec. III-D): particle i is

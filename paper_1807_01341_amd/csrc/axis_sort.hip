@@ -2,9 +2,10 @@
 // for every leaf and each of the 13 directions of the half neighbour stencil,
 // the in-leaf order of the projections d = e . o of the FP32 offsets at the
 // last full build (ascending, ties by in-leaf index).  A 14th order
-// (HORD_ROW) lists the particles by H at the full build, largest first: the
-// force loop reads only its head where a partner leaf is beyond H_i and only
-// particles of large H_j can reach (the symmetric cutoff of Eq. 12/13).
+// (HORD_ROW) lists the particles by H, largest first, keyed by h_build (H at
+// the full build, or at a later re-key of the leaf): the force loop reads
+// only its head where a partner leaf lies beyond H_i, since with the
+// symmetric cutoff r < max(H_i, H_j) only particles of large H_j reach there.
 // Bitonic sorts of (key, index), in LDS or in registers.
 #include <math.h>
 
@@ -206,8 +207,8 @@ __global__ __launch_bounds__(256) void axis_sort_wave_kernel(const float4 *__res
   }
 }
 
-// The largest H at the build at ranks hq_rank(q) of each leaf's H order, one
-// thread per (leaf, q); 0 where the rank is past the leaf's count.
+// The key (h_build) at rank hq_rank(q) of each leaf's H order, one thread
+// per (leaf, q); 0 where the rank is past the leaf's count.
 __global__ __launch_bounds__(256) void leaf_hq_kernel(const float *__restrict__ hb,
                                                       const int32_t *__restrict__ leaf_begin,
                                                       const int32_t *__restrict__ leaf_count, int64_t nl, int64_t n,

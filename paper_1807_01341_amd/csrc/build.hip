@@ -217,7 +217,8 @@ __global__ __launch_bounds__(BT) void leaf_count_kernel(const int32_t *__restric
 }
 
 // FP32 offsets from the leaf centre, H, and the leaf's max H: one wave per
-// leaf.
+// leaf.  H is also each particle's key of its leaf's H order (hb), so the
+// leaf's H growth bound starts at 1.
 __global__ __launch_bounds__(BT) void offsets_kernel(const double *__restrict__ x, const double *__restrict__ y,
                                                      const double *__restrict__ z, const float *__restrict__ h,
                                                      const int32_t *__restrict__ begin, const int32_t *__restrict__ count,
@@ -275,8 +276,8 @@ __device__ __forceinline__ float disp_bound(double d2m) {
 }
 
 // the positions, the FP32 offsets from the leaf centre (minimum image), H,
-// the leaf's max H and a bound on its particles' displacement since the last
-// build (sqrt(3) times the largest component, rounded up to float),
+// the leaf's max H, the bound on H / (its H-order key) and a bound on its
+// particles' displacement since the last build (sqrt(3) times the largest component, rounded up to float),
 // and flags a rebuild when a leaf's particles moved more than frac of its
 // width.  One wave per leaf; block maxima of H and of the displacement.
 __global__ __launch_bounds__(BT) void update_kernel(double *__restrict__ x, double *__restrict__ y,
@@ -301,7 +302,7 @@ __global__ __launch_bounds__(BT) void update_kernel(double *__restrict__ x, doub
     const double cz = (double)((2 * (int64_t)iz[l] + 1) << sh) * unit;
     const int b = begin[l], cnt = count[l];
     double d2m = 0.0;  // largest displacement component
-    float gr = 0.f;    // largest H / H at the build
+    float gr = 0.f;    // largest H / its H-order key
     for (int k = lane; k < cnt; k += 64) {
       const int s = b + k;
       const double x0 = x[s], y0 = y[s], z0 = z[s];
@@ -690,8 +691,8 @@ __global__ __launch_bounds__(BT) void lazy_bound_kernel(const int64_t *__restric
 
 // One wave per listed leaf (list_n on the device, or n_items when list_n is
 // null; every leaf when list is null), grid-stride: a leaf behind the time
-// line is drifted to it and its offsets, H, packed velocity, max H and exact
-// displacement bound are renewed.
+// line is drifted to it and its offsets, H, packed velocity, max H, H growth
+// bound and exact displacement bound are renewed.
 __global__ __launch_bounds__(BT) void drift_leaves_kernel(DriftArgs d, const int32_t *__restrict__ list,
                                                           const int32_t *__restrict__ list_n, int64_t n_items,
                                                           const double *__restrict__ xb,
