@@ -441,24 +441,33 @@ __device__ __forceinline__ void ghost_body(const GhostArgs &g) {
   int finished = 0;
   int unconv = 0;
   for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < g.n_active; k += (int64_t)gridDim.x * 256) {
+    // every load that does not depend on another is issued first (the
+    // kernel is a chain of dependent loads; valid indices for every k)
+    const uint8_t cv = g.conv[k];
+    const int i = g.active_idx[k];
+    const int co = g.chunk_of[k];
+    const float lo0 = g.hlo[k], hi0 = g.hhi[k];
+    const int64_t na = g.n_active;
+    const float S_w = g.sums[k], S_mw = g.sums[na + k], S_d = g.sums[2 * na + k], S_md = g.sums[3 * na + k];
+    const float S_dv = g.sums[4 * na + k], S_cx = g.sums[5 * na + k], S_cy = g.sums[6 * na + k],
+                S_cz = g.sums[7 * na + k];
+    const int cnt_k = g.act_cnt[k];
+    const float h = g.h[i];
+    const Chunk ch = g.chunks[co];
     // whether the next pass evaluates particle k
     const bool again = [&]() -> bool {
-    if (g.conv[k] == 1) return false;
-    if (g.conv[k] == 2) {  // waiting for wider cell-pair lists: not converged
+    if (cv == 1) return false;
+    if (cv == 2) {  // waiting for wider cell-pair lists: not converged
       ++unconv;
       return false;
     }
-    const int i = g.active_idx[k];
-    const float S_w = g.sums[k], S_mw = g.sums[g.n_active + k], S_d = g.sums[2 * g.n_active + k],
-                S_md = g.sums[3 * g.n_active + k];
-    const float h = g.h[i];
     // Newton in ln h on G = ln(h^3 n / eta^3), with h^3 n = (8/pi)/GK^3 sum w
     // and dG/dln h = (3 sum w - sum (3w + q w')) / sum w: the same root as
     // h^3 n = eta^3, reached in one step where the density is locally uniform.
     const float hn3 = g.kc * S_w;
     const float G = __logf(hn3 / g.eta3);
     const float Gp = (3.f * S_w - S_d) / S_w;
-    float lo = g.hlo[k], hi = g.hhi[k];
+    float lo = lo0, hi = hi0;
     if (G < 0.f) lo = fmaxf(lo, h);
     if (G > 0.f) hi = fminf(hi, h);
     float hn = h * __expf(fminf(fmaxf(-G / Gp, -0.6931472f), 0.6931472f));
@@ -491,10 +500,10 @@ __device__ __forceinline__ void ghost_body(const GhostArgs &g) {
       }
       const float cs = sqrtf(g.gamma * P / rho);
       const float C4 = C3 * iH;
-      const float dv = -C4 * g.sums[4 * g.n_active + k] / rho;
-      const float cx = C4 * g.sums[5 * g.n_active + k] / rho;
-      const float cy = C4 * g.sums[6 * g.n_active + k] / rho;
-      const float cz = C4 * g.sums[7 * g.n_active + k] / rho;
+      const float dv = -C4 * S_dv / rho;
+      const float cx = C4 * S_cx / rho;
+      const float cy = C4 * S_cy / rho;
+      const float cz = C4 * S_cz / rho;
       const float adv = fabsf(dv);
       const float acu = sqrtf(fmaf(cz, cz, fmaf(cy, cy, cx * cx)));
       const float Bs = adv > 0.f ? adv / (adv + acu + g.eps * cs / h) : 0.f;
@@ -508,14 +517,13 @@ __device__ __forceinline__ void ghost_body(const GhostArgs &g) {
       g.P[i] = P;
       g.c[i] = cs;
       g.B[i] = Bs;
-      if (g.nngb) g.nngb[i] = g.act_cnt[k];
+      if (g.nngb) g.nngb[i] = cnt_k;
       g.jth[i] = make_float4(rho, fg * P / (rho * rho), cs, Bs);
-      finished += g.act_cnt[k];
+      finished += cnt_k;
       g.conv[k] = 1;
       if (!done) ++unconv;
       return false;
     }
-    const Chunk ch = g.chunks[g.chunk_of[k]];
     const float Hn = GK32 * hn;
     bool wait = false;
     if (Hn > g.act_hmax[ch.act_leaf] * g.reach) {
@@ -531,7 +539,7 @@ __device__ __forceinline__ void ghost_body(const GhostArgs &g) {
     g.hhi[k] = hi;
     g.h[i] = hn;
     g.pos4[i].w = Hn;
-    g.chunk_todo[g.chunk_of[k]] = 1;
+    g.chunk_todo[co] = 1;
     ++unconv;
     return !wait;
     }();
@@ -909,7 +917,7 @@ __device__ __forceinline__ void force_term(const float4 &vi, const float4 &thi, 
 }
 
 template <int NWP>
-__global__ __launch_bounds__(256) void force_sweep_kernel(LoopArgs g, const int32_t *__restrict__ chunk_of) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void force_sweep_kernel(LoopArgs g, const int32_t *__restrict__ chunk_of) {
   __shared__ SweepPair sp[4][64];
   __shared__ float4 hq[4][128];  // per wave: queued neighbours (dx, dy, dz, j) and their H
   __shared__ float hqH[4][128];
