@@ -345,10 +345,15 @@ __global__ __launch_bounds__(BT) void update_kernel(double *__restrict__ x, doub
 }
 
 // One block of RT threads: every thread takes a strided quarter of the
-// partials four at a time, so that its loads are in flight together.
+// partials four at a time, so that its loads are in flight together.  Writes
+// the max H and max displacement bits to out[0], out[1] and to hmax_bits (the
+// running max H of the kept cells: the host reads out[] only to decide on a
+// rebuild, which recomputes it), and moves the raised rebuild flag *flag to
+// out[2], clearing it.
 #define RT 1024
 __global__ __launch_bounds__(RT) void max2_reduce_kernel(const float2 *__restrict__ part, int n,
-                                                         int32_t *__restrict__ out_bits) {
+                                                         int32_t *__restrict__ out_bits, int32_t *__restrict__ flag,
+                                                         int32_t *__restrict__ hmax_bits) {
   float a = 0.f, d = 0.f;
   int k = threadIdx.x;
   for (; k + 3 * RT < n; k += 4 * RT) {
@@ -375,6 +380,9 @@ __global__ __launch_bounds__(RT) void max2_reduce_kernel(const float2 *__restric
     }
     out_bits[0] = __float_as_int(a);
     out_bits[1] = __float_as_int(d);
+    out_bits[2] = *flag;
+    *flag = 0;
+    *hmax_bits = __float_as_int(a);
   }
 }
 
@@ -888,7 +896,6 @@ sph_status lazy_keep_cells(sph_ctx *ctx, int *rebuild) {
   const int64_t nl = ctx->n_leaves;
   const double L = ctx->prm.box;
   int32_t *sc = (int32_t *)ctx->scalars.p;
-  HIP_TRY(ctx, hipMemsetAsync(sc + SC_UPD_HMAX, 0, 3 * sizeof(int32_t), ctx->stream));
   const int64_t blocks = ceil_div(nl, BT);
   SPH_TRY(sph_ensure(ctx, ctx->scan_out, sizeof(float2) * (size_t)blocks));
   {
@@ -896,8 +903,9 @@ sph_status lazy_keep_cells(sph_ctx *ctx, int *rebuild) {
     lazy_bound_kernel<<<(unsigned)blocks, BT, 0, ctx->stream>>>(
         (const int64_t *)ctx->leaf_ti.p, (const float *)ctx->leaf_vmax.p, (const float *)ctx->leaf_dx_base.p,
         (const float *)ctx->leaf_hmax.p, (const int32_t *)ctx->leaf_level.p, nl, L, ctx->prm.rebuild_frac,
-        ctx->ti_now, ctx->t_min_line, (float *)ctx->leaf_dx.p, (float2 *)ctx->scan_out.p, sc + SC_UPD_FLAG);
-    max2_reduce_kernel<<<1, RT, 0, ctx->stream>>>((const float2 *)ctx->scan_out.p, (int)blocks, sc + SC_UPD_HMAX);
+        ctx->ti_now, ctx->t_min_line, (float *)ctx->leaf_dx.p, (float2 *)ctx->scan_out.p, sc + SC_UPD_FLAG_ACC);
+    max2_reduce_kernel<<<1, RT, 0, ctx->stream>>>((const float2 *)ctx->scan_out.p, (int)blocks, sc + SC_UPD_HMAX,
+                                                  sc + SC_UPD_FLAG_ACC, sc + SC_HMAX_BITS);
   }
   HIP_TRY(ctx, hipGetLastError());
   int32_t st[3];
@@ -910,8 +918,7 @@ sph_status lazy_keep_cells(sph_ctx *ctx, int *rebuild) {
     return SPH_OK;
   }
   *rebuild = 0;
-  HIP_TRY(ctx, hipMemcpyAsync(sc + SC_HMAX_BITS, sc + SC_UPD_HMAX, sizeof(int32_t), hipMemcpyDeviceToDevice,
-                              ctx->stream));
+  // (the reduction also set the running global max H to the kept cells' max H)
   ctx->dx_max = dxm;
   ctx->n_updates++;
   ctx->state = 1;
@@ -925,7 +932,6 @@ sph_status update_cells(sph_ctx *ctx, sph_particles *p, int64_t *perm_out, int *
   const int D = ctx->prm.morton_depth;
   const double L = ctx->prm.box;
   int32_t *sc = (int32_t *)ctx->scalars.p;
-  HIP_TRY(ctx, hipMemsetAsync(sc + SC_UPD_HMAX, 0, 3 * sizeof(int32_t), ctx->stream));
   const double *xb = (const double *)ctx->x_build.p;
   const int64_t blocks = ceil_div(nl, BT / 64);
   SPH_TRY(sph_ensure(ctx, ctx->scan_out, sizeof(float2) * (size_t)blocks));
@@ -943,8 +949,9 @@ sph_status update_cells(sph_ctx *ctx, sph_particles *p, int64_t *perm_out, int *
         (const int32_t *)ctx->leaf_count.p, (const int32_t *)ctx->leaf_level.p, (const int32_t *)ctx->leaf_ix.p,
         (const int32_t *)ctx->leaf_iy.p, (const int32_t *)ctx->leaf_iz.p, nl, D, L, ldexp(L, -(D + 1)),
         ctx->prm.rebuild_frac, (float4 *)ctx->pos4.p, (float *)ctx->leaf_hmax.p, (float *)ctx->leaf_dx.p,
-        (float2 *)ctx->scan_out.p, sc + SC_UPD_FLAG, (const float *)ctx->h_build.p, (float *)ctx->leaf_hgrow.p, pk);
-    max2_reduce_kernel<<<1, RT, 0, ctx->stream>>>((const float2 *)ctx->scan_out.p, (int)blocks, sc + SC_UPD_HMAX);
+        (float2 *)ctx->scan_out.p, sc + SC_UPD_FLAG_ACC, (const float *)ctx->h_build.p, (float *)ctx->leaf_hgrow.p, pk);
+    max2_reduce_kernel<<<1, RT, 0, ctx->stream>>>((const float2 *)ctx->scan_out.p, (int)blocks, sc + SC_UPD_HMAX,
+                                                  sc + SC_UPD_FLAG_ACC, sc + SC_HMAX_BITS);
   }
   HIP_TRY(ctx, hipGetLastError());
   int32_t st[3];
@@ -957,9 +964,7 @@ sph_status update_cells(sph_ctx *ctx, sph_particles *p, int64_t *perm_out, int *
     return SPH_OK;
   }
   *rebuild = 0;
-  // the running global max H starts from the kept cells' max H
-  HIP_TRY(ctx, hipMemcpyAsync(sc + SC_HMAX_BITS, sc + SC_UPD_HMAX, sizeof(int32_t), hipMemcpyDeviceToDevice,
-                              ctx->stream));
+  // (the reduction also set the running global max H to the kept cells' max H)
   ctx->dx_max = dxm;
   ctx->n_updates++;
   if (perm_out) {

@@ -35,8 +35,11 @@ __global__ __launch_bounds__(256) void pack_jth_kernel(const float *__restrict__
 
 __global__ __launch_bounds__(256) void density_init_kernel(int64_t n_chunks, int32_t *__restrict__ todo,
                                                            int64_t n_act, float *__restrict__ lo,
-                                                           float *__restrict__ hi, uint8_t *__restrict__ conv) {
+                                                           float *__restrict__ hi, uint8_t *__restrict__ conv,
+                                                           int32_t *__restrict__ stats, int n_stats) {
   const int64_t m = n_chunks > n_act ? n_chunks : n_act;
+  if (blockIdx.x == 0)
+    for (int q = threadIdx.x; q < n_stats; q += 256) stats[q] = 0;
   for (int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x; s < m; s += (int64_t)gridDim.x * 256) {
     if (s < n_chunks) todo[s] = 1;
     if (s < n_act) {
@@ -1172,11 +1175,14 @@ sph_status density_begin(sph_ctx *ctx, const sph_particles *p, int entropy_from_
   SPH_TRY(sph_ensure(ctx, ctx->hlo, 4 * (size_t)na));
   SPH_TRY(sph_ensure(ctx, ctx->hhi, 4 * (size_t)na));
   SPH_TRY(sph_ensure(ctx, ctx->conv, (size_t)na));
+  // the per-pass counters (unconverged, rebuild flags) start at zero
+  const int n_stats = 2 * (ctx->prm.h_max_iter + 1);
+  SPH_TRY(sph_ensure(ctx, ctx->pass_stats, sizeof(int32_t) * (size_t)n_stats));
   {
     PROF(ctx, "ghost");
     density_init_kernel<<<grid256(na > ctx->n_chunks ? na : ctx->n_chunks), 256, 0, ctx->stream>>>(
         ctx->n_chunks, (int32_t *)ctx->chunk_todo.p, na, (float *)ctx->hlo.p, (float *)ctx->hhi.p,
-        (uint8_t *)ctx->conv.p);
+        (uint8_t *)ctx->conv.p, (int32_t *)ctx->pass_stats.p, n_stats);
   }
   HIP_TRY(ctx, hipGetLastError());
   *any = 1;
@@ -1316,7 +1322,6 @@ sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u)
   int it = 0, done = 0;
   while (!done) {
     const int first = it + 1, last = std::min(it == 0 ? 4 : it + 2, maxit);
-    HIP_TRY(ctx, hipMemsetAsync(stats + 2 * first, 0, sizeof(int32_t) * 2 * (last - first + 1), ctx->stream));
     for (int pass = first; pass <= last; ++pass) {
       LoopArgs a = density_loop_args(ctx);
       int32_t *next_n = list_n + ((pass + 1) & 1);

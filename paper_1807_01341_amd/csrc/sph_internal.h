@@ -258,6 +258,8 @@ enum ScalarSlot {
   SC_UPD_HMAX = 13,   // cell update: max H bits, max displacement bits, rebuild flag
   SC_UPD_DX = 14,
   SC_UPD_FLAG = 15,
+  SC_UPD_FLAG_ACC = 16,  // the rebuild flag as the update kernel raises it (moved to SC_UPD_FLAG and
+                         // cleared by the reduction, so that it starts at zero for the next update)
   SC_COUNT = 32
 };
 
