@@ -22,6 +22,7 @@ import json
 import math
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -402,7 +403,7 @@ def main():
     ap.add_argument("--sweep-waves", type=int, default=None)
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--load-tune", default=None, help="load a tuning file instead of tuning")
-    ap.add_argument("--tune-file", default=os.path.join(ROOT, "gpurun_out", "tuning_clustered.txt"))
+    ap.add_argument("--tune-file", default=os.path.join(tempfile.gettempdir(), "sph_tuning_clustered.txt"))
     ap.add_argument("--workload", choices=("deepbin", "large"), default="deepbin")
     ap.add_argument("--substeps", type=int, default=8192, help="large workload: sub-steps of the sweep")
     ap.add_argument("--grf-amplitude", type=float, default=12.0)
