@@ -698,7 +698,7 @@ __device__ __forceinline__ void density_term(const float4 &pi, const float4 &vi,
 // pair terms evaluated 64 at a time, one per lane, so that the terms run on
 // full waves although few of the candidates tested together are neighbours.
 template <int NWP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void density_sweep_kernel(LoopArgs g, const int32_t *__restrict__ todo,
+__global__ __launch_bounds__(256) void density_sweep_kernel(LoopArgs g, const int32_t *__restrict__ todo,
                                                             const int32_t *__restrict__ n_todo_dev, int64_t n_todo,
                                                             const int32_t *__restrict__ chunk_of,
                                                             int32_t *__restrict__ next_n) {
@@ -920,7 +920,7 @@ __device__ __forceinline__ void force_term(const float4 &vi, const float4 &thi, 
 }
 
 template <int NWP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void force_sweep_kernel(LoopArgs g, const int32_t *__restrict__ chunk_of) {
+__global__ __launch_bounds__(256) void force_sweep_kernel(LoopArgs g, const int32_t *__restrict__ chunk_of) {
   __shared__ SweepPair sp[4][64];
   __shared__ float4 hq[4][128];  // per wave: queued neighbours (dx, dy, dz, j) and their H
   __shared__ float hqH[4][128];
