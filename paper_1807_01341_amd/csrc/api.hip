@@ -135,10 +135,17 @@ sph_status sph_create(const sph_params *p, void *hip_stream, sph_ctx **out) {
     delete ctx;
     return SPH_ENOMEM;
   }
-  if (hipHostMalloc((void **)&ctx->pin.p, sizeof(int32_t) * PIN_COUNT, hipHostMallocDefault) != hipSuccess) {
+  // page-locked, mapped and coherent: copies land in it without a staging
+  // wait, and small kernels write their results into it directly
+  if (hipHostMalloc((void **)&ctx->pin.p, sizeof(int32_t) * PIN_COUNT,
+                    hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
     ctx->pin.p = nullptr;
     delete ctx;
     return SPH_ENOMEM;
+  }
+  if (hipHostGetDevicePointer((void **)&ctx->pin_dev, ctx->pin.p, 0) != hipSuccess || !ctx->pin_dev) {
+    delete ctx;
+    return SPH_EDEVICE;
   }
   if (sph_ensure(ctx, ctx->counters64, 2 * sizeof(uint64_t)) != SPH_OK) {
     delete ctx;

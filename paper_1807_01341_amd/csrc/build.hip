@@ -349,11 +349,12 @@ __global__ __launch_bounds__(BT) void update_kernel(double *__restrict__ x, doub
 // the max H and max displacement bits to out[0], out[1] and to hmax_bits (the
 // running max H of the kept cells: the host reads out[] only to decide on a
 // rebuild, which recomputes it), and moves the raised rebuild flag *flag to
-// out[2], clearing it.
+// out[2], clearing it.  The three values also go to host_out (page-locked
+// host memory) for the host to read after one synchronisation.
 #define RT 1024
 __global__ __launch_bounds__(RT) void max2_reduce_kernel(const float2 *__restrict__ part, int n,
                                                          int32_t *__restrict__ out_bits, int32_t *__restrict__ flag,
-                                                         int32_t *__restrict__ hmax_bits) {
+                                                         int32_t *__restrict__ hmax_bits, int32_t *host_out) {
   float a = 0.f, d = 0.f;
   int k = threadIdx.x;
   for (; k + 3 * RT < n; k += 4 * RT) {
@@ -378,11 +379,15 @@ __global__ __launch_bounds__(RT) void max2_reduce_kernel(const float2 *__restric
       a = fmaxf(a, wa[w]);
       d = fmaxf(d, wd[w]);
     }
+    const int32_t fl = *flag;
     out_bits[0] = __float_as_int(a);
     out_bits[1] = __float_as_int(d);
-    out_bits[2] = *flag;
+    out_bits[2] = fl;
     *flag = 0;
     *hmax_bits = __float_as_int(a);
+    host_out[0] = __float_as_int(a);
+    host_out[1] = __float_as_int(d);
+    host_out[2] = fl;
   }
 }
 
@@ -905,11 +910,12 @@ sph_status lazy_keep_cells(sph_ctx *ctx, int *rebuild) {
         (const float *)ctx->leaf_hmax.p, (const int32_t *)ctx->leaf_level.p, nl, L, ctx->prm.rebuild_frac,
         ctx->ti_now, ctx->t_min_line, (float *)ctx->leaf_dx.p, (float2 *)ctx->scan_out.p, sc + SC_UPD_FLAG_ACC);
     max2_reduce_kernel<<<1, RT, 0, ctx->stream>>>((const float2 *)ctx->scan_out.p, (int)blocks, sc + SC_UPD_HMAX,
-                                                  sc + SC_UPD_FLAG_ACC, sc + SC_HMAX_BITS);
+                                                  sc + SC_UPD_FLAG_ACC, sc + SC_HMAX_BITS, ctx->pin_dev + PIN_UPD);
   }
   HIP_TRY(ctx, hipGetLastError());
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   int32_t st[3];
-  SPH_TRY(read_scalars(ctx, SC_UPD_HMAX, 3, st));
+  memcpy(st, ctx->pin.p + PIN_UPD, sizeof st);
   float hmax, dxm;
   memcpy(&hmax, &st[0], 4);
   memcpy(&dxm, &st[1], 4);
@@ -951,11 +957,12 @@ sph_status update_cells(sph_ctx *ctx, sph_particles *p, int64_t *perm_out, int *
         ctx->prm.rebuild_frac, (float4 *)ctx->pos4.p, (float *)ctx->leaf_hmax.p, (float *)ctx->leaf_dx.p,
         (float2 *)ctx->scan_out.p, sc + SC_UPD_FLAG_ACC, (const float *)ctx->h_build.p, (float *)ctx->leaf_hgrow.p, pk);
     max2_reduce_kernel<<<1, RT, 0, ctx->stream>>>((const float2 *)ctx->scan_out.p, (int)blocks, sc + SC_UPD_HMAX,
-                                                  sc + SC_UPD_FLAG_ACC, sc + SC_HMAX_BITS);
+                                                  sc + SC_UPD_FLAG_ACC, sc + SC_HMAX_BITS, ctx->pin_dev + PIN_UPD);
   }
   HIP_TRY(ctx, hipGetLastError());
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   int32_t st[3];
-  SPH_TRY(read_scalars(ctx, SC_UPD_HMAX, 3, st));
+  memcpy(st, ctx->pin.p + PIN_UPD, sizeof st);
   float hmax, dxm;
   memcpy(&hmax, &st[0], 4);
   memcpy(&dxm, &st[1], 4);

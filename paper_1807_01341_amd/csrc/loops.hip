@@ -1253,6 +1253,14 @@ GhostArgs density_ghost_args(sph_ctx *ctx, sph_particles *p, int it, int entropy
 // smoothing length outgrew them.
 // Passes are grouped like the single-box path's batches (passes 1-4, then
 // 5-6, 7-8, ...): widening happens only at the end of a group.
+// The force cell-pair total and a group's per-pass counters into page-locked
+// host slots.
+__global__ void group_read_kernel(const int32_t *__restrict__ ftotal, const int32_t *__restrict__ stats, int nst,
+                                  int32_t *host_fc, int32_t *host_st) {
+  if (threadIdx.x == 0) host_fc[0] = *ftotal;
+  for (int q = threadIdx.x; q < nst; q += blockDim.x) host_st[q] = stats[q];
+}
+
 static inline bool group_end(int it) { return it == 4 || (it > 4 && (it % 2) == 0); }
 
 sph_status density_after_pass(sph_ctx *ctx, const sph_particles *p, int it, const int32_t st[2], int *done) {
@@ -1361,13 +1369,16 @@ sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u)
     // smoothing lengths and the force cell-pair count, read in the same
     // synchronisation (wasted work when another group follows)
     SPH_TRY(refresh_leaf_hmax(ctx));
-    // both reads queued into page-locked slots, one synchronisation
+    // both read through page-locked slots that one small kernel writes, one
+    // synchronisation
     int32_t *fcount = ctx->pin.p + PIN_FCOUNT;
-    SPH_TRY(build_pairs_count(ctx, 1, 1.0f, fcount));
+    SPH_TRY(build_pairs_count(ctx, 1, 1.0f, nullptr));
     const size_t nst = 2 * (size_t)(last - first + 1);
     if (nst > PIN_COUNT - PIN_STATS) return sph_fail(ctx, SPH_EINVAL, "density pass: group of passes too long");
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->pin.p + PIN_STATS, stats + 2 * first, sizeof(int32_t) * nst,
-                                hipMemcpyDeviceToHost, ctx->stream));
+    group_read_kernel<<<1, 64, 0, ctx->stream>>>((const int32_t *)ctx->fpair_off.p + ctx->n_active_leaves,
+                                                 stats + 2 * first, (int)nst, ctx->pin_dev + PIN_FCOUNT,
+                                                 ctx->pin_dev + PIN_STATS);
+    HIP_TRY(ctx, hipGetLastError());
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     // density_after_pass may issue reads of its own: the counters leave the slots first
     int32_t st[PIN_COUNT - PIN_STATS];

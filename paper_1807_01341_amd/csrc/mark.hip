@@ -404,6 +404,12 @@ static RefreshArgs refresh_args(sph_ctx *ctx) {
   return r;
 }
 
+// The three totals of the active-set scan (active particles, active leaves,
+// chunks: the scan output at nl, 2 nl and 3 nl) into page-locked host slots.
+__global__ void mark_totals_kernel(const int32_t *__restrict__ aoff, int64_t nl, int32_t *host) {
+  if (threadIdx.x < 3) host[threadIdx.x] = aoff[(threadIdx.x + 1) * nl];
+}
+
 static unsigned waves_grid(int64_t n_items) { return (unsigned)(ceil_div(n_items, MT / 64) > 0 ? ceil_div(n_items, MT / 64) : 1); }
 
 static PairGeom pair_geom(const sph_ctx *ctx) {
@@ -430,7 +436,7 @@ sph_status build_pairs_count(sph_ctx *ctx, int which, float slack, int32_t *host
   SPH_TRY(sph_ensure(ctx, ctx->pair_cnt, 4 * (size_t)(na + 1)));
   SPH_TRY(sph_ensure(ctx, ctx->act_cost, 4 * (size_t)(na + 1)));
   SPH_TRY(sph_ensure(ctx, off, 4 * (size_t)(na + 1)));
-  *host_total = 0;
+  if (host_total) *host_total = 0;
   if (na == 0) {
     HIP_TRY(ctx, hipMemsetAsync(off.p, 0, 4, ctx->stream));
     return SPH_OK;
@@ -463,7 +469,8 @@ sph_status build_pairs_count(sph_ctx *ctx, int which, float slack, int32_t *host
   HIP_TRY(ctx, hipGetLastError());
   int32_t *o = (int32_t *)off.p;
   SPH_TRY(scan_exclusive_i32(ctx, (const int32_t *)ctx->pair_cnt.p, o, na, o + na));
-  HIP_TRY(ctx, hipMemcpyAsync(host_total, o + na, 4, hipMemcpyDeviceToHost, ctx->stream));
+  // (a null host_total: the caller reads the total at offsets[n_active_leaves])
+  if (host_total) HIP_TRY(ctx, hipMemcpyAsync(host_total, o + na, 4, hipMemcpyDeviceToHost, ctx->stream));
   return SPH_OK;
 }
 
@@ -566,11 +573,11 @@ sph_status mark_active_impl(sph_ctx *ctx, const sph_particles *p, int m, int64_t
   // one scan over [nact | isact | nchunk]: the second and third segments come
   // out shifted by the totals before them, read back by the fill kernel
   SPH_TRY(scan_exclusive_i32(ctx, nact, aoff, 3 * nl, aoff + 3 * nl));
-  // the three totals, queued into page-locked slots, one synchronisation
+  // the three totals written into page-locked slots by one small kernel, one
+  // synchronisation
   const int32_t *tot3 = ctx->pin.p + PIN_MARK;
-  for (int q = 0; q < 3; ++q)
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->pin.p + PIN_MARK + q, aoff + (q + 1) * nl, 4, hipMemcpyDeviceToHost,
-                                ctx->stream));
+  mark_totals_kernel<<<1, 64, 0, ctx->stream>>>(aoff, nl, ctx->pin_dev + PIN_MARK);
+  HIP_TRY(ctx, hipGetLastError());
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   int32_t tot[3] = {tot3[0], tot3[1] - tot3[0], tot3[2] - tot3[1]};
   ctx->n_active = tot[0];

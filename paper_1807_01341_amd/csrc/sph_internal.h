@@ -149,6 +149,7 @@ struct sph_ctx {
   DevBuf keys_a, keys_b, vals_a, vals_b, radix_counts, scan_tmp, gather_tmp;
   DevBuf scalars;                         // small device counters
   HostPin pin;                            // host side of the reads (PinSlot)
+  int32_t *pin_dev = nullptr;             // the same slots as kernels address them (mapped)
   DevBuf flags, scan_out, nodes_a, nodes_b, leaf_lvl_at;
   DevBuf leaf_level, leaf_ix, leaf_iy, leaf_iz, leaf_begin, leaf_count, leaf_hmax, leaf_of;
   DevBuf top_first, top_last;
@@ -271,6 +272,7 @@ enum PinSlot {
   PIN_NPAIRS = 20,    // cell-pair total of build_pairs
   PIN_FCOUNT = 21,    // force cell-pair total counted during the density solve
   PIN_ITEMS = 22,     // loop work items
+  PIN_UPD = 24,       // cell update: max H bits, max displacement bits, rebuild flag (written by the reduction)
   PIN_STATS = 32,     // density solve: per-pass counters of one group of passes
   PIN_COUNT = 64
 };
