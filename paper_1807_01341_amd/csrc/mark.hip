@@ -404,6 +404,11 @@ static RefreshArgs refresh_args(sph_ctx *ctx) {
   return r;
 }
 
+// One int32 into a page-locked host slot.
+__global__ void copy_total_kernel(const int32_t *__restrict__ src, int32_t *host) {
+  if (threadIdx.x == 0) host[0] = *src;
+}
+
 // The three totals of the active-set scan (active particles, active leaves,
 // chunks: the scan output at nl, 2 nl and 3 nl) into page-locked host slots.
 __global__ void mark_totals_kernel(const int32_t *__restrict__ aoff, int64_t nl, int32_t *host) {
@@ -501,10 +506,15 @@ sph_status build_pairs_fill(sph_ctx *ctx, int which, float slack, int32_t np) {
 }
 
 sph_status build_pairs(sph_ctx *ctx, int which, float slack) {
-  int32_t *np = ctx->pin.p + PIN_NPAIRS;
-  SPH_TRY(build_pairs_count(ctx, which, slack, np));
-  if (ctx->n_active_leaves > 0) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-  return build_pairs_fill(ctx, which, slack, *np);
+  const int64_t na = ctx->n_active_leaves;
+  SPH_TRY(build_pairs_count(ctx, which, slack, nullptr));
+  if (na == 0) return build_pairs_fill(ctx, which, slack, 0);
+  // the total (offsets[na]) written into its page-locked slot by one thread
+  const DevBuf &off = which == 0 ? ctx->dpair_off : ctx->fpair_off;
+  copy_total_kernel<<<1, 64, 0, ctx->stream>>>((const int32_t *)off.p + na, ctx->pin_dev + PIN_NPAIRS);
+  HIP_TRY(ctx, hipGetLastError());
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return build_pairs_fill(ctx, which, slack, ctx->pin.p[PIN_NPAIRS]);
 }
 
 // Refreshes the max H of every active leaf (all particles, and active ones)
