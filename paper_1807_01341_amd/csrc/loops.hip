@@ -1261,6 +1261,11 @@ __global__ void group_read_kernel(const int32_t *__restrict__ ftotal, const int3
   for (int q = threadIdx.x; q < nst; q += blockDim.x) host_st[q] = stats[q];
 }
 
+// The int32 at src[q] into host slot q (page-locked), q < n.
+__global__ void gather_totals_kernel(const int32_t *const *__restrict__ src, int n, int32_t *host) {
+  for (int q = threadIdx.x; q < n; q += blockDim.x) host[q] = *src[q];
+}
+
 static inline bool group_end(int it) { return it == 4 || (it > 4 && (it % 2) == 0); }
 
 sph_status density_after_pass(sph_ctx *ctx, const sph_particles *p, int it, const int32_t st[2], int *done) {
@@ -1926,12 +1931,27 @@ sph_status batch_force_impl(sph_ctx **cs, sph_particles *ps, int nb) {
   if (live.empty()) return SPH_OK;
   const int nl = (int)live.size();
   // force cell pairs of every box with one synchronisation
-  // (each count into its box's page-locked slot, so that none waits by itself)
-  for (int q = 0; q < nl; ++q)
-    BATCH_TRY(live[q], build_pairs_count(cs[live[q]], 1, 1.0f, cs[live[q]]->pin.p + PIN_NPAIRS));
-  HIP_TRY(lead, hipStreamSynchronize(lead->stream));
-  for (int q = 0; q < nl; ++q)
-    BATCH_TRY(live[q], build_pairs_fill(cs[live[q]], 1, 1.0f, cs[live[q]]->pin.p[PIN_NPAIRS]));
+  // (the totals gathered into the lead's page-locked slots by one kernel per
+  // PIN_COUNT boxes)
+  for (int q = 0; q < nl; ++q) BATCH_TRY(live[q], build_pairs_count(cs[live[q]], 1, 1.0f, nullptr));
+  std::vector<int32_t> np(nl);
+  SPH_TRY(sph_ensure(lead, lead->gather_src, sizeof(const int32_t *) * PIN_COUNT));
+  lead->gather_host.resize(sizeof(const int32_t *) * PIN_COUNT);
+  const int32_t **src = reinterpret_cast<const int32_t **>(lead->gather_host.data());
+  for (int g0 = 0; g0 < nl; g0 += PIN_COUNT) {
+    const int ng = std::min(nl - g0, (int)PIN_COUNT);
+    for (int q = 0; q < ng; ++q) {
+      sph_ctx *c = cs[live[g0 + q]];
+      src[q] = (const int32_t *)c->fpair_off.p + c->n_active_leaves;
+    }
+    HIP_TRY(lead, hipMemcpyAsync(lead->gather_src.p, src, sizeof(const int32_t *) * (size_t)ng,
+                                 hipMemcpyHostToDevice, lead->stream));
+    gather_totals_kernel<<<1, 64, 0, lead->stream>>>((const int32_t *const *)lead->gather_src.p, ng, lead->pin_dev);
+    HIP_TRY(lead, hipGetLastError());
+    HIP_TRY(lead, hipStreamSynchronize(lead->stream));
+    for (int q = 0; q < ng; ++q) np[g0 + q] = lead->pin.p[q];
+  }
+  for (int q = 0; q < nl; ++q) BATCH_TRY(live[q], build_pairs_fill(cs[live[q]], 1, 1.0f, np[q]));
   Staging s = staging(lead, nl);
   int64_t nchunks = 0;
   for (int b : live) nchunks += cs[b]->n_chunks;

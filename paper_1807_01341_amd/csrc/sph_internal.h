@@ -165,6 +165,8 @@ struct sph_ctx {
   DevBuf h_build, leaf_hgrow, leaf_hq;
   DevBuf refresh_args;                    // batched leaf max-H refresh: device copy of the per-box arguments
   std::vector<char> refresh_host;         // and its host staging
+  DevBuf gather_src;                      // batched force pass: where each box's pair total is
+  std::vector<char> gather_host;          // and its host staging
   int max_leaf = 0;                       // largest leaf of the build
   int leaves_checked = 0;                 // max_leaf read and the leaves sorted for the current build
   // mark
