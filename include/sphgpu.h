@@ -168,9 +168,9 @@ sph_status sph_sort_cells(sph_ctx *ctx);
  * active iff time_bin[i] <= max_active_bin; a leaf is active if it holds an
  * active particle; every active leaf A is paired with each leaf B (A
  * included) whose periodic box distance is below max H over A's active
- * particles.  If n_active_host is non-NULL the call synchronises and writes
- * the number of active particles there.  SPH_EINVAL if max_active_bin is
- * outside [0, n_bins-1]. */
+ * particles.  Synchronises twice (the active-set totals, the cell-pair
+ * count); writes the number of active particles to n_active_host if it is
+ * non-NULL.  SPH_EINVAL if max_active_bin is outside [0, n_bins-1]. */
 sph_status sph_mark_active(sph_ctx *ctx, const sph_particles *p, int max_active_bin, int64_t *n_active_host);
 
 /* Density loop over the active cell pairs with the ghost's smoothing-length
@@ -180,7 +180,9 @@ sph_status sph_mark_active(sph_ctx *ctx, const sph_particles *p, int max_active_
  * div v, curl v, the grad-h factor, pressure, sound speed, Balsara switch and
  * the entropic function.  entropy_from_u=1 takes u as the thermal input
  * (A = (gamma-1) u rho^(1-gamma)); 0 takes A (and writes u).  Synchronises
- * once per Newton pass.  SPH_ENOCONV / SPH_EREBUILD as described above. */
+ * once per group of Newton passes (passes 1-4, then two at a time; a pass
+ * reads on the device which particles the previous one left unconverged).
+ * SPH_ENOCONV / SPH_EREBUILD as described above. */
 sph_status sph_density_pass(sph_ctx *ctx, sph_particles *p, int entropy_from_u);
 
 /* Force loop over the active cell pairs (Fig. 5): for active i and j != i
