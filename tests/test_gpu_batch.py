@@ -172,3 +172,30 @@ def test_h_solve_converges_where_a_clamped_step_cycled(gpu_lib):
     c.density_pass(p, True)
     inf = c.info()
     assert inf["n_unconverged"] == 0 and inf["density_iterations"] <= 12
+
+
+def test_batch_of_more_boxes_than_host_slots(gpu_lib):
+    """70 small all-active boxes: the batched force pass reads the boxes' cell
+    pair totals in groups of 64; results equal the boxes' own passes bitwise."""
+    sg = gpu_lib
+    boxes = ics.batch_of_boxes(n_boxes=70, n_range=(2_000, 4_000), frac_range=(1.0, 1.0))
+    for b in boxes:
+        b["bin"] = np.zeros_like(b["bin"])
+    ms = [0] * len(boxes)
+    print(f"case batch70 N={sum(b['x'].shape[0] for b in boxes)}", flush=True)
+    cs, ps, _ = prepare(sg, boxes, ms, TILING)
+    for c, p in zip(cs, ps):
+        c.density_pass(p, False)
+        c.force_pass(p)
+    torch.cuda.synchronize()
+    ref = snapshot(ps)
+    del cs, ps
+    cs, ps, _ = prepare(sg, boxes, ms, TILING)
+    batch = sg.Batch(cs, ps)
+    batch.density_pass(False)
+    batch.force_pass()
+    torch.cuda.synchronize()
+    got = snapshot(ps)
+    for b in range(len(boxes)):
+        for k in OUTPUTS:
+            assert np.array_equal(got[b][k].view(np.uint8), ref[b][k].view(np.uint8)), (b, k)
