@@ -11,8 +11,11 @@
 #define MT 256
 #define CHUNK 64
 
-// One wave per leaf: active flags, the number of active particles, their
-// max H, and the number of 64-particle chunks.
+// One wave per MARK_LEAVES consecutive leaves: active flags, the number of
+// active particles, their max H, and the number of 64-particle chunks.  The
+// leaves' first 64 particles are read together (most leaves hold fewer), so
+// their loads are in flight at once; longer leaves continue one by one.
+#define MARK_LEAVES 4
 __global__ __launch_bounds__(MT) void mark_count_kernel(const int8_t *__restrict__ bin, int m,
                                                         const float4 *__restrict__ pos4,
                                                         const int32_t *__restrict__ leaf_begin,
@@ -20,25 +23,46 @@ __global__ __launch_bounds__(MT) void mark_count_kernel(const int8_t *__restrict
                                                         uint8_t *__restrict__ active, int32_t *__restrict__ nact,
                                                         int32_t *__restrict__ isact, int32_t *__restrict__ nchunk,
                                                         float *__restrict__ hmax_act_leaf) {
-  const int64_t l = (int64_t)blockIdx.x * (MT / 64) + (threadIdx.x >> 6);
-  if (l >= nl) return;
+  const int64_t l0 = ((int64_t)blockIdx.x * (MT / 64) + (threadIdx.x >> 6)) * MARK_LEAVES;
+  if (l0 >= nl) return;
   const int lane = threadIdx.x & 63;
-  const int b = leaf_begin[l], c = leaf_count[l];
-  int na = 0;
-  float hm = 0.f;
-  for (int t = 0; t < c; t += 64) {
-    const int k = t + lane;
-    const bool a = k < c && bin[b + k] <= m;
-    if (k < c) active[b + k] = a;
-    if (a) hm = fmaxf(hm, pos4[b + k].w);
-    na += __popcll(__ballot(a));
+  int b[MARK_LEAVES], c[MARK_LEAVES], na[MARK_LEAVES];
+  float hm[MARK_LEAVES];
+  int8_t bn[MARK_LEAVES];
+#pragma unroll
+  for (int u = 0; u < MARK_LEAVES; ++u) {
+    const int64_t l = l0 + u;
+    b[u] = l < nl ? leaf_begin[l] : 0;
+    c[u] = l < nl ? leaf_count[l] : 0;
+    na[u] = 0;
+    hm[u] = 0.f;
   }
-  hm = wave_max_f(hm);
-  if (lane == 0) {
-    nact[l] = na;
-    isact[l] = na > 0;
-    nchunk[l] = (na + CHUNK - 1) / CHUNK;
-    hmax_act_leaf[l] = hm;
+#pragma unroll
+  for (int u = 0; u < MARK_LEAVES; ++u) bn[u] = lane < c[u] ? bin[b[u] + lane] : (int8_t)127;
+#pragma unroll
+  for (int u = 0; u < MARK_LEAVES; ++u) {
+    const bool a = lane < c[u] && bn[u] <= m;
+    if (lane < c[u]) active[b[u] + lane] = a;
+    if (a) hm[u] = pos4[b[u] + lane].w;
+    na[u] = __popcll(__ballot(a));
+  }
+#pragma unroll
+  for (int u = 0; u < MARK_LEAVES; ++u) {
+    for (int t = 64; t < c[u]; t += 64) {
+      const int k = t + lane;
+      const bool a = k < c[u] && bin[b[u] + k] <= m;
+      if (k < c[u]) active[b[u] + k] = a;
+      if (a) hm[u] = fmaxf(hm[u], pos4[b[u] + k].w);
+      na[u] += __popcll(__ballot(a));
+    }
+    const float h = wave_max_f(hm[u]);
+    const int64_t l = l0 + u;
+    if (lane == 0 && l < nl) {
+      nact[l] = na[u];
+      isact[l] = na[u] > 0;
+      nchunk[l] = (na[u] + CHUNK - 1) / CHUNK;
+      hmax_act_leaf[l] = h;
+    }
   }
 }
 
@@ -573,7 +597,7 @@ sph_status mark_active_impl(sph_ctx *ctx, const sph_particles *p, int m, int64_t
   int32_t *sc = (int32_t *)ctx->scalars.p;
   {
     PROF(ctx, "mark");
-    mark_count_kernel<<<waves_grid(nl), MT, 0, ctx->stream>>>(p->time_bin, m, (const float4 *)ctx->pos4.p,
+    mark_count_kernel<<<waves_grid(ceil_div(nl, MARK_LEAVES)), MT, 0, ctx->stream>>>(p->time_bin, m, (const float4 *)ctx->pos4.p,
                                                               (const int32_t *)ctx->leaf_begin.p,
                                                               (const int32_t *)ctx->leaf_count.p, nl,
                                                               (uint8_t *)ctx->active.p, nact, isact, nchunk,
