@@ -405,7 +405,8 @@ def kick_drift(x, vf, vp, Af, Ap, a, dA_dt, h, vsig, bins, active, ti, t_min, dr
     copied to vp, Ap; a new bin from Eq. 1 and Eq. 2, limited to bins whose
     period divides ti; then the opening half-kick of the new step.  Then every
     particle drifts by drift_int units of t_min: x += vf dt, vp += a dt,
-    Ap += dA/dt dt, and x is wrapped into the box.  FP64 throughout."""
+    Ap += dA/dt dt, and x is wrapped into the box; with `divv` given, h is
+    predicted along the flow (continuity).  FP64 throughout."""
     x = np.array(x, np.float64, copy=True)
     vf = np.array(vf, np.float64, copy=True)
     vp = np.array(vp, np.float64, copy=True)
@@ -433,11 +434,14 @@ def kick_drift(x, vf, vp, Af, Ap, a, dA_dt, h, vsig, bins, active, ti, t_min, dr
     x += vf * dt
     vp += a * dt
     Ap += dA * dt
-    # smoothing length carried along the flow, dh/dt = -(h/3) div v, limited
-    # to a factor e^0.2 per drift (only the starting point of the next solve)
+    # smoothing length carried along the flow.  Continuity, d rho/dt =
+    # -rho div v, with h proportional to rho^(-1/3) gives dh/dt = +(h/3) div v;
+    # over the drift interval h is multiplied by exp(div v dt / 3), the
+    # exponent limited to +-0.2 (a reading: the paper does not state how h of
+    # particles between their active steps evolves).
     hn = None
     if divv is not None:
-        xx = np.clip(-np.asarray(divv, np.float64) * dt / 3.0, -0.2, 0.2)
+        xx = np.clip(np.asarray(divv, np.float64) * dt / 3.0, -0.2, 0.2)
         hn = np.asarray(h, np.float64) * np.exp(xx)
     x = np.mod(x, L)
     x[x >= L] -= L

@@ -243,6 +243,9 @@ class Context:
                     ctx=None)
         self.h = h
         self._pc = None
+        # counts the calls that change the context's derived structures or
+        # step state; a saved forward evaluation checks it before its backward
+        self.generation = 0
 
     def __del__(self):
         # at interpreter exit the module's globals may already be gone
@@ -256,8 +259,10 @@ class Context:
             raise SPHError(code, msg)
         return code
 
-    def _pcs(self, p: Particles):
+    def _pcs(self, p: Particles, changes=True):
         self._pc = p.c_struct()   # kept alive while queued work reads the pointers
+        if changes:
+            self.generation += 1
         return C.byref(self._pc)
 
     # ---- the path
@@ -265,6 +270,7 @@ class Context:
         return self._check(lib().sph_build_cells(self.h, self._pcs(p), p.n, _ptr(perm_out)))
 
     def sort_cells(self):
+        self.generation += 1
         return self._check(lib().sph_sort_cells(self.h))
 
     def mark_active(self, p: Particles, max_active_bin: int, want_count=True):
@@ -307,7 +313,7 @@ class Context:
         dev = w.device
         gx, gy, gz = (torch.empty(n, dtype=torch.float64, device=dev) for _ in range(3))
         gu = torch.empty(n, dtype=torch.float32, device=dev)
-        self._check(lib().sph_adjoint(self.h, self._pcs(p), _ptr(wx), _ptr(wy), _ptr(wz), _ptr(gx), _ptr(gy),
+        self._check(lib().sph_adjoint(self.h, self._pcs(p, changes=False), _ptr(wx), _ptr(wy), _ptr(wz), _ptr(gx), _ptr(gy),
                                       _ptr(gz), _ptr(gu)))
         self._keep = (wx, wy, wz)
         return torch.stack([gx, gy, gz], 1), gu
@@ -438,13 +444,17 @@ class SPHForce(torch.autograd.Function):
         c.force_pass(p)
         a = torch.empty(n, 3, dtype=torch.float32, device=x.device)
         a[perm] = torch.stack([p["ax"], p["ay"], p["az"]], 1)
-        fctx.sph = (c, p, perm)
+        fctx.sph = (c, p, perm, c.generation)
         fctx.x_dtype, fctx.u_dtype = x.dtype, u.dtype
         return a
 
     @staticmethod
     def backward(fctx, ga):
-        c, p, perm = fctx.sph
+        c, p, perm, gen = fctx.sph
+        if c.generation != gen:
+            # the adjoint reads the context's current cells and pair lists
+            raise RuntimeError("SPHForce backward: the context was used by another call after this forward "
+                               "evaluation; give each evaluation its own context or run backward first")
         gx_s, gu_s = c.adjoint(p, ga[perm])
         gx = torch.empty(p.n, 3, dtype=torch.float64, device=ga.device)
         gu = torch.empty(p.n, dtype=torch.float32, device=ga.device)

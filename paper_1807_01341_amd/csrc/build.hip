@@ -643,7 +643,7 @@ sph_status build_cells_impl(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *
 // when a step needs them (the active leaves at sph_mark_active, the partner
 // leaves of every new cell-pair list), with the drift-all formulas applied
 // over the whole interval since the leaf's last drift: x += vf dt (wrapped),
-// v += a dt, A += dA/dt dt, h *= exp(clip(-div v dt / 3, +-0.2)).  Between
+// v += a dt, A += dA/dt dt, h *= exp(clip(div v dt / 3, +-0.2)).  Between
 // drifts a leaf's displacement bound from the full build grows by its speed
 // bound times the elapsed time; that bound is the leaf's drift margin for
 // the pair search and the sweep stops of the step.
@@ -750,7 +750,7 @@ __global__ __launch_bounds__(BT) void drift_leaves_kernel(DriftArgs d, const int
       d.vy[s] = vy;
       d.vz[s] = vz;
       d.A[s] = (float)((double)d.A[s] + (double)d.dA[s] * dt);
-      double e = -(double)d.divv[s] * dt / 3.0;
+      double e = (double)d.divv[s] * dt / 3.0;
       e = fmin(fmax(e, -0.2), 0.2);
       const float h = (float)((double)d.h[s] * exp(e));
       d.h[s] = h;

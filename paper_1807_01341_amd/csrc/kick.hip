@@ -72,10 +72,11 @@ __global__ __launch_bounds__(256) void kick_drift_kernel(KickArgs g) {
     g.vy[s] = v1 + a1 * dt;
     g.vz[s] = v2 + a2 * dt;
     g.A[s] = (float)(A + da * dt);
-    // smoothing length predicted along the flow, dh/dt = -(h/3) div v (a
-    // starting point for the next solve), at most a factor e^0.2 per drift
+    // smoothing length carried along the flow: continuity with h ~ rho^(-1/3)
+    // gives dh/dt = +(h/3) div v; at most a factor e^0.2 per drift.  An
+    // inactive particle's h is the H_j its neighbours' force loops read.
     if (g.divv) {
-      double x = -(double)g.divv[s] * dt / 3.0;
+      double x = (double)g.divv[s] * dt / 3.0;
       x = fmin(fmax(x, -0.2), 0.2);
       g.h[s] = (float)((double)g.h[s] * exp(x));
     }

@@ -669,6 +669,29 @@ int sweep_waves(const sph_ctx *ctx, int64_t n_todo) {
   return ctx->prm.sweep_waves > 0 ? ctx->prm.sweep_waves : 1;
 }
 
+// Compensated sums of the sweep kernels: a lane sums its own terms (a few
+// per particle: a particle's neighbours are spread over the 64 lanes) in
+// plain FP32, and the 64 lane partials are added in a butterfly whose every
+// level is a TwoSum, the rounding errors carried in c; the waves sharing a
+// particle are then added with Neumaier's update.  TwoSum's error term is
+// exact, so both lanes of a butterfly level compute the same pair and every
+// lane ends with the same total s + c.
+__device__ __forceinline__ void neu_add(float &s, float &c, float b) {
+  const float t = s + b;
+  c += fabsf(s) >= fabsf(b) ? (s - t) + b : (b - t) + s;
+  s = t;
+}
+__device__ __forceinline__ void two_sum_butterfly(float &s, float &c) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const float s2 = __shfl_xor(s, o, 64), c2 = __shfl_xor(c, o, 64);
+    const float t = s + s2;
+    const float bp = t - s;
+    const float e = (s - (t - bp)) + (s2 - bp);
+    s = t;
+    c = (c + c2) + e;
+  }
+}
+
 __device__ __forceinline__ void density_term(const float4 &pi, const float4 &vi, float invHi, float dx, float dy,
                                              float dz, float r2, const float4 &vj, float (&acc)[8]) {
   const float rinv = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
@@ -697,7 +720,7 @@ __device__ __forceinline__ void density_term(const float4 &pi, const float4 &vi,
 // in wave order.  The neighbours a wave finds are queued in LDS and their
 // pair terms evaluated 64 at a time, one per lane, so that the terms run on
 // full waves although few of the candidates tested together are neighbours.
-template <int NWP>
+template <int NWP, bool COMP>
 __global__ __launch_bounds__(256) void density_sweep_kernel(LoopArgs g, const int32_t *__restrict__ todo,
                                                             const int32_t *__restrict__ n_todo_dev, int64_t n_todo,
                                                             const int32_t *__restrict__ chunk_of,
@@ -840,9 +863,15 @@ __global__ __launch_bounds__(256) void density_sweep_kernel(LoopArgs g, const in
   drain(qn);
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
-    float v = acc[q];
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    acc[q] = v;
+    if (COMP) {
+      float c = 0.f;
+      two_sum_butterfly(acc[q], c);
+      acc[q] += c;
+    } else {
+      float v = acc[q];
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      acc[q] = v;
+    }
   }
   for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
   if (NWP == 1) {
@@ -863,15 +892,22 @@ __global__ __launch_bounds__(256) void density_sweep_kernel(LoopArgs g, const in
     __syncthreads();
     if (sub == 0 && lane == 0 && w < n_todo) {
       const int k = todo ? todo[w] : (int)w;
-      float s[8];
+      float s[8], c[8];
       int cs = 0;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) s[q] = 0.f;
+      for (int q = 0; q < 8; ++q) s[q] = c[q] = 0.f;
       for (int u = 0; u < NWP; ++u) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) s[q] += red[wave + u][q];
+        for (int q = 0; q < 8; ++q) {
+          if (COMP)
+            neu_add(s[q], c[q], red[wave + u][q]);
+          else
+            s[q] += red[wave + u][q];
+        }
         cs += __float_as_int(red[wave + u][8]);
       }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s[q] += c[q];
 #pragma unroll
       for (int q = 0; q < 8; ++q) g.sums[(int64_t)q * g.n_active + k] = s[q];
       g.act_cnt[k] = cs;
@@ -919,7 +955,7 @@ __device__ __forceinline__ void force_term(const float4 &vi, const float4 &thi, 
   f.adiab = fmaf(mj * vr, Fi, f.adiab);
 }
 
-template <int NWP>
+template <int NWP, bool COMP>
 __global__ __launch_bounds__(256) void force_sweep_kernel(LoopArgs g, const int32_t *__restrict__ chunk_of) {
   __shared__ SweepPair sp[4][64];
   __shared__ float4 hq[4][128];  // per wave: queued neighbours (dx, dy, dz, j) and their H
@@ -1090,8 +1126,15 @@ __global__ __launch_bounds__(256) void force_sweep_kernel(LoopArgs g, const int3
     drain(qn);
     float v[5] = {f.ax, f.ay, f.az, f.visc, f.adiab};
 #pragma unroll
-    for (int q = 0; q < 5; ++q)
-      for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o, 64);
+    for (int q = 0; q < 5; ++q) {
+      if (COMP) {
+        float c = 0.f;
+        two_sum_butterfly(v[q], c);
+        v[q] += c;
+      } else {
+        for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o, 64);
+      }
+    }
     float vm = f.vmax;
     for (int o = 32; o > 0; o >>= 1) vm = fmaxf(vm, __shfl_xor(vm, o, 64));
     for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
@@ -1117,15 +1160,22 @@ __global__ __launch_bounds__(256) void force_sweep_kernel(LoopArgs g, const int3
     if (sub == 0 && lane == 0 && k < g.n_active) {
       const int i = g.active_idx[k];
       const float4 thi = g.jth[i];
-      float v[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+      float v[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, c[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
       float vm = 0.f;
       int cs = 0;
       for (int u = 0; u < NWP; ++u) {
 #pragma unroll
-        for (int q = 0; q < 5; ++q) v[q] += red[wave + u][q];
+        for (int q = 0; q < 5; ++q) {
+          if (COMP)
+            neu_add(v[q], c[q], red[wave + u][q]);
+          else
+            v[q] += red[wave + u][q];
+        }
         vm = fmaxf(vm, red[wave + u][5]);
         cs += __float_as_int(red[wave + u][6]);
       }
+#pragma unroll
+      for (int q = 0; q < 5; ++q) v[q] += c[q];
       g.ax_out[i] = v[0];
       g.ay_out[i] = v[1];
       g.az_out[i] = v[2];
@@ -1347,12 +1397,15 @@ sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u)
         const unsigned grid = xcd_grid(std::min<int64_t>(ceil_div(n_todo * nwp, 4), (int64_t)ctx->n_cu * 16));
         const int32_t *tl = pass > 1 ? list : nullptr, *tn = pass > 1 ? list_n + (pass & 1) : nullptr;
         const int32_t *co = (const int32_t *)ctx->chunk_of.p;
+        const bool comp = ctx->prm.compensated != 0;
+#define SPH_DSWEEP(NWP_, C_) density_sweep_kernel<NWP_, C_><<<grid, 256, 0, ctx->stream>>>(a, tl, tn, n_todo, co, next_n)
         if (nwp == 4)
-          density_sweep_kernel<4><<<grid, 256, 0, ctx->stream>>>(a, tl, tn, n_todo, co, next_n);
+          { if (comp) SPH_DSWEEP(4, true); else SPH_DSWEEP(4, false); }
         else if (nwp == 2)
-          density_sweep_kernel<2><<<grid, 256, 0, ctx->stream>>>(a, tl, tn, n_todo, co, next_n);
+          { if (comp) SPH_DSWEEP(2, true); else SPH_DSWEEP(2, false); }
         else
-          density_sweep_kernel<1><<<grid, 256, 0, ctx->stream>>>(a, tl, tn, n_todo, co, next_n);
+          { if (comp) SPH_DSWEEP(1, true); else SPH_DSWEEP(1, false); }
+#undef SPH_DSWEEP
         HIP_TRY(ctx, hipGetLastError());
       } else {
         HIP_TRY(ctx, hipMemsetAsync(next_n, 0, sizeof(int32_t), ctx->stream));
@@ -1440,12 +1493,16 @@ sph_status force_pass_impl(sph_ctx *ctx, sph_particles *p) {
       PROF(ctx, "force_loop");
       const int nwp = sweep_waves(ctx, ctx->n_active);
       const unsigned grid = xcd_grid(ceil_div(ctx->n_active * nwp, 4));
+      const bool comp = ctx->prm.compensated != 0;
+      const int32_t *co = (const int32_t *)ctx->chunk_of.p;
+#define SPH_FSWEEP(NWP_, C_) force_sweep_kernel<NWP_, C_><<<grid, 256, 0, ctx->stream>>>(a, co)
       if (nwp == 4)
-        force_sweep_kernel<4><<<grid, 256, 0, ctx->stream>>>(a, (const int32_t *)ctx->chunk_of.p);
+        { if (comp) SPH_FSWEEP(4, true); else SPH_FSWEEP(4, false); }
       else if (nwp == 2)
-        force_sweep_kernel<2><<<grid, 256, 0, ctx->stream>>>(a, (const int32_t *)ctx->chunk_of.p);
+        { if (comp) SPH_FSWEEP(2, true); else SPH_FSWEEP(2, false); }
       else
-        force_sweep_kernel<1><<<grid, 256, 0, ctx->stream>>>(a, (const int32_t *)ctx->chunk_of.p);
+        { if (comp) SPH_FSWEEP(1, true); else SPH_FSWEEP(1, false); }
+#undef SPH_FSWEEP
     }
     HIP_TRY(ctx, hipGetLastError());
   } else {
