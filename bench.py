@@ -1,19 +1,24 @@
 """Benchmark of the SPH hot path on one MI355X.
 
-One step = build_cells -> sort_cells -> mark_active(m) -> density_pass ->
-force_pass -> kick_drift on the clustered workload (2,097,152 particles: 90 %
-uniform background, 10 % in 20 Plummer spheres, u log-uniform, 14 model
-time-bins), at the deep bin m whose active set {bin <= m} is closest to 1 %
-of the particles.  The step's input is the state one deep-bin drift after an
-all-active density + force pass (positions moved, h predicted); every timed
-step starts from that input (a fused device copy of the arrays a step
-changes, inside the timed region) and runs the whole path on it, so all
-steps do the same work.
+Default workload: the large single-GPU share, 16,777,216 particles (a 256^3
+lattice displaced by the Zel'dovich field of a Gaussian random field with
+P(k) ~ k^-2.5, u log-uniform in [1e-2, 1e2], 14 power-of-two time-bins of
+Eq. 2).  One benchmark step is one top-level step of the bin hierarchy: the
+2^13 sub-steps t, each running the whole path -- build_cells (cell update,
+or a full build when particles moved too far), sort_cells, mark_active(m)
+with m = min(ctz(t), 13), density_pass, force_pass, kick_drift -- with only
+the particles a sub-step needs drifted (Sec. II-A, Sec. III-D).  The
+simulation continues from step to step.
 
-Prints one JSON line: interactions/s (density + force, in-support pairs only,
-counted by the kernels) over the whole step, the fraction of FP32 vector peak,
-the roofline of the dominant kernel, and the FP64 oracle's rate on a bounded
-sample of the same step on the host cores.
+Prints one JSON line: active particle-neighbour interactions/s (density +
+force, in-support pairs only, counted by the kernels) over the timed
+top-level steps, the roofline of the dominant kernel group (HIP events on
+the library's stream in a profiled top-level step after the timed ones),
+the per-bin time against the number of active particles (the single-GPU
+analogue of the paper's Fig. 7), and the FP64 oracle's rate on a bounded
+sample of the same particles on the host cores.  `--workload clustered`
+runs the 2,097,152-particle deep-bin step instead (also reported as an
+extra key of the default line).
 """
 from __future__ import annotations
 
@@ -62,18 +67,19 @@ def measured_traffic(kernel):
     return m["bytes"] if h.hexdigest() == m["sha256"] else None
 
 
-# algorithmic FLOP per interaction of the two loops (mul/add = 1, fma = 2,
-# rsqrt/rcp = 1, compare/select = 0), counted from the pair formulas
-FLOP_DENSITY = 60
-FLOP_FORCE = 72
+# algorithmic FLOP per in-support interaction of the two loops, from the
+# operation list of the pair formulas (mul/add = 1, fma = 2, rsqrt/rcp = 1,
+# compare/select = 0): density 54, force 67
+FLOP_DENSITY = 54
+FLOP_FORCE = 67
 
 
 def kernel_model(name, n, n_active, n_leaves, n_dens, n_force, launches):
     """Algorithmic bytes (hbm) or flops (alu) of ONE launch of a kernel group,
     for the roofline of the dominant kernel."""
-    if name == "density_loop":
+    if name in ("density_loop", "density_sweep"):
         return "alu", FLOP_DENSITY * n_dens / launches
-    if name == "force_loop":
+    if name in ("force_loop", "force_sweep"):
         return "alu", FLOP_FORCE * n_force / launches
     if name == "radix_scatter":
         return "hbm", 24.0 * n             # read key+value, write key+value
@@ -92,40 +98,81 @@ def kernel_model(name, n, n_active, n_leaves, n_dens, n_force, launches):
     return "hbm", None
 
 
-def run_cpu_baseline(ic, active_orig, n_sample, seed=5):
-    """The FP64 oracle, unchanged, on a sample of the step's active particles:
-    density solve for the sample and every particle within reach of it, force
-    loop for the sample.  Rate = the sample's in-support interactions / time."""
+def cpu_info():
+    """The host's CPU model and core counts (for the baseline's record)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "host_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
+def oracle_on_cube(ic, centre, half, label):
+    """The FP64 oracle, unchanged, on the particles of a cube of half-side
+    `half` around `centre` (periodic): the density loop with the h solve for
+    every particle at least 1.6 max(H) inside the cube (their neighbours all
+    lie in the cube), the ghost, and the force loop for every particle at
+    least 2.7 max(H) inside (its neighbours are all solved).  Credits every
+    in-support interaction it evaluated at the converged h."""
     import torch
 
     from oracle import sph
-    rng = np.random.default_rng(seed)
-    sample = np.sort(rng.choice(active_orig, size=min(n_sample, active_orig.size), replace=False))
+    x = ic["x"]
+    d = x - centre
+    d -= np.round(d)
+    cheb = np.max(np.abs(d), 1)
+    sub = np.nonzero(cheb < half)[0]
+    Hmax = sph.GAMMA_K * float(ic["h"][sub].max())
+    dens = np.searchsorted(sub, sub[cheb[sub] < half - 1.6 * Hmax])
+    forc = np.searchsorted(sub, sub[cheb[sub] < half - 2.7 * Hmax])
+    if dens.size == 0 or forc.size == 0:
+        return None
+    xs, vs, ms, us, hs = ic["x"][sub], ic["v"][sub], ic["m"][sub], ic["u"][sub], ic["h"][sub]
     t0 = time.perf_counter()
-    from scipy.spatial import cKDTree
-    tree = cKDTree(ic["x"], boxsize=1.0)
-    reach = 2.0 * sph.GAMMA_K * float(ic["h"].max()) * 1.5
-    near = np.unique(np.concatenate(tree.query_ball_point(ic["x"][sample], reach)))
-    dens = sph.density_and_ghost(ic["x"], ic["v"], ic["m"], ic["h"], 1.0, u=ic["u"], centres=near)
-    N = ic["x"].shape[0]
+    out = sph.density_and_ghost(xs, vs, ms, hs, 1.0, u=us, centres=dens)
     full = {}
     for k in ("h", "rho", "f", "P", "c", "B"):
-        a = torch.full((N,), float("nan"), dtype=torch.float64)
-        a[torch.as_tensor(near)] = dens[k]
+        a = torch.full((sub.size,), float("nan"), dtype=torch.float64)
+        a[torch.as_tensor(dens)] = out[k]
         full[k] = a
-    fo = sph.force(ic["x"], ic["v"], ic["m"], full["h"], full["rho"], full["f"], full["P"], full["c"], full["B"],
-                   1.0, centres=sample)
+    fo = sph.force(xs, vs, ms, full["h"], full["rho"], full["f"], full["P"], full["c"], full["B"], 1.0,
+                   centres=forc)
     t = time.perf_counter() - t0
-    pos = np.searchsorted(near, sample)
-    inter = int(dens["count"].numpy()[pos].sum() + fo["count"].numpy().sum())
+    inter = int(out["count"].sum() + fo["count"].sum())
     return dict(value=inter / t, unit="interactions/s", cores=torch.get_num_threads(), kind="oracle",
-                sample=f"{sample.size} active particles of the step (density solve for the {near.size} particles "
-                       f"within reach, force for the sample), {inter} interactions in {t:.1f} s",
-                seconds=t)
+                sample=f"{label}: the {sub.size} particles of a cube of half-side {half:.3f} around a seeded "
+                       f"particle; density loop with the h solve for the {dens.size} at least 1.6 max H inside, "
+                       f"force loop for the {forc.size} at least 2.7 max H inside; every in-support interaction "
+                       f"evaluated at the converged h credited: {inter} in {t:.1f} s",
+                seconds=t, interactions=inter, **cpu_info())
 
 
-def _loops_ms(prof):
-    return sum(prof.get(k, (0, 0.0))[1] for k in ("density_loop", "force_loop"))
+def run_cpu_baseline(ic, label, seed=5, target_centres=30000, max_half=0.3):
+    """The oracle on a bounded sample: a cube around a seeded particle, grown
+    until its density region holds about `target_centres` particles."""
+    from oracle import sph
+    rng = np.random.default_rng(seed)
+    centre = ic["x"][int(rng.integers(ic["x"].shape[0]))]
+    d = ic["x"] - centre
+    d -= np.round(d)
+    cheb = np.max(np.abs(d), 1)
+    half = 0.02
+    while half < max_half:
+        sub = cheb < half
+        Hmax = sph.GAMMA_K * float(ic["h"][sub].max()) if sub.any() else 0.0
+        if np.count_nonzero(cheb < half - 1.6 * Hmax) >= target_centres and np.any(cheb < half - 2.7 * Hmax):
+            break
+        half *= 1.15
+    return oracle_on_cube(ic, centre, min(half, max_half), label)
 
 
 def measure_all_active(sg, ic, reps=3, **kw):
@@ -270,41 +317,59 @@ def measure_adjoint(sg, reps=5):
 
 
 
-def run_large(args):
-    """Large single-GPU share: 256^3 lattice displaced by a Zel'dovich
-    Gaussian random field (P(k) ~ k^-2.5), u log-uniform, 14 model bins.
-    (i) all-active steps; (ii) one top-level step of `substeps` sub-steps
-    t = 1.. with max active bin min(ctz(t), 13), each a full step (build,
-    sort, mark, density, force, kick_drift by t_min)."""
-    import torch
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
 
-    import ics
-    import paper_1807_01341_amd as sg
-    sg.require_device()
-    t_gen = time.perf_counter()
-    ic = ics.grf_zeldovich(amplitude=args.grf_amplitude)
-    print(f"generated {ic['x'].shape[0]} particles in {time.perf_counter() - t_gen:.0f} s", file=sys.stderr,
-          flush=True)
-    N = ic["x"].shape[0]
-    ctx = sg.Context(lazy_drift=int(args.lazy_drift))
+
+def ctz(t):
+    return (t & -t).bit_length() - 1
+
+
+def loop_kwargs(args):
+    kw = {}
+    for a, k in (("split", "split_count"), ("cand_cap", "cand_cap"), ("list_cap", "list_cap"), ("h_tol", "h_tol"),
+                 ("nw", "waves_per_chunk"), ("sweep_below", "sweep_below"), ("sweep_waves", "sweep_waves")):
+        v = getattr(args, a, None)
+        if v is not None and v is not False:
+            kw[k] = v
+    return kw
+
+
+def grf_setup(sg, ic, lazy, kw, tune_file=None, n_bins=None):
+    """Context and particles of the large share, after an all-active density
+    + force pass (u the thermal input), the loop tuning on those chunks, the
+    t_min of Eq. 1 (the smallest time-step of the converged state, so every
+    particle's bin satisfies its own Courant condition) and the first kick
+    with the drift to t = 1."""
+    import torch
+    kw = dict(kw)
+    if n_bins is not None:
+        kw["n_bins"] = n_bins
+    ctx = sg.Context(lazy_drift=int(lazy), **kw)
     p = sg.Particles.from_initial(ic)
-    del ic
     top = ctx.params.n_bins - 1
     ctx.build_cells(p)
     ctx.sort_cells()
     ctx.mark_active(p, top)
     ctx.density_pass(p, entropy_from_u=True)
     ctx.force_pass(p)
-    ctx.autotune(p, None)
-    # t_min = the smallest Eq. 1 time-step of the converged state, so that
-    # every particle's bin satisfies its own Courant condition
+    if tune_file is not False:
+        if tune_file and os.path.exists(tune_file):
+            os.remove(tune_file)
+        ctx.autotune(p, tune_file or None)
     vs = p["vsig"].double()
     dt = torch.where(vs > 0, ctx.params.cfl * p["h"].double() / vs, torch.full_like(vs, float("inf")))
     t_min = float(dt.min())
-    ctx.kick_drift(p, 0, t_min, 0, True)
+    ctx.kick_drift(p, 0, t_min, 1, True)
     ctx.sync()
-    # (i) all-active steps (no time advance: the kick_drift of the sweep does that)
-    reps = 3
+    return ctx, p, t_min
+
+
+def all_active_steps(ctx, p, reps=3):
+    """Whole steps with every particle active (no time advance): build, sort,
+    mark, density (all Newton passes), force; the loops at full occupancy."""
+    import torch
+    top = ctx.params.n_bins - 1
     i0 = ctx.info()
     ctx.profile(True)
     t0 = time.perf_counter()
@@ -315,123 +380,257 @@ def run_large(args):
         ctx.density_pass(p, entropy_from_u=False)
         ctx.force_pass(p)
     torch.cuda.synchronize()
-    wall_all = (time.perf_counter() - t0) / reps
+    wall = (time.perf_counter() - t0) / reps
     prof = ctx.profile_read()
     ctx.profile(False)
     i1 = ctx.info()
     I_d = (i1["interactions_density"] - i0["interactions_density"]) / reps
     I_f = (i1["interactions_force"] - i0["interactions_force"]) / reps
-    d_cnt, d_ms = prof["density_loop"]
-    f_cnt, f_ms = prof["force_loop"]
-    all_active = {
-        "interactions_per_step": I_d + I_f, "ms_per_step": wall_all * 1e3,
-        "interactions_per_s": (I_d + I_f) / wall_all,
-        "fp32_peak_frac_step": (FLOP_DENSITY * I_d + FLOP_FORCE * I_f) / wall_all / FP32_PEAK,
-        "density_loop_tflops": FLOP_DENSITY * I_d * reps / (d_ms / 1e3) / 1e12,
-        "force_loop_tflops": FLOP_FORCE * I_f * reps / (f_ms / 1e3) / 1e12,
-        "newton_passes": i1["density_iterations"],
-        "kernels_ms_per_step": {k: round(ms / reps, 3) for k, (cnt, ms) in sorted(prof.items(), key=lambda kv: -kv[1][1])},
-    }
-    print(f"all-active: {wall_all * 1e3:.1f} ms/step, {(I_d + I_f) / wall_all:.3g} interactions/s", file=sys.stderr,
-          flush=True)
-    # (ii) the sub-step sweep
+    out = {"interactions_per_step": I_d + I_f, "ms_per_step": wall * 1e3, "interactions_per_s": (I_d + I_f) / wall,
+           "fp32_peak_frac_step": (FLOP_DENSITY * I_d + FLOP_FORCE * I_f) / wall / FP32_PEAK,
+           "newton_passes": i1["density_iterations"],
+           "kernels_ms_per_step": {k: round(ms / reps, 3)
+                                   for k, (cnt, ms) in sorted(prof.items(), key=lambda kv: -kv[1][1])}}
+    for name, flop, I in (("density_loop", FLOP_DENSITY, I_d), ("force_loop", FLOP_FORCE, I_f)):
+        if name in prof:
+            cnt, ms = prof[name]
+            out[name + "_tflops"] = flop * I * reps / (ms / 1e3) / 1e12
+    return out
+
+
+def run_grf(args):
+    """The default line: top-level steps of the 2^13 sub-step hierarchy on the
+    16,777,216-particle share."""
+    import torch
+
+    import ics
+    import paper_1807_01341_amd as sg
+    sg.require_device()
+    tg = time.perf_counter()
+    ic = ics.grf_zeldovich(amplitude=args.grf_amplitude)
+    N = ic["x"].shape[0]
+    log(f"generated {N} particles in {time.perf_counter() - tg:.0f} s")
+    lazy = not args.drift_all
+    ctx, p, t_min = grf_setup(sg, ic, lazy, loop_kwargs(args),
+                              tune_file=False if args.no_tune else args.tune_file)
+    top = ctx.params.n_bins - 1
     S = args.substeps
+    sweep_below = ctx.params.sweep_below
+    log(f"setup done: t_min {t_min:.4e}")
+    clock = {"t": 0}
+
+    def top_step(per_sub=None):
+        for _ in range(S):
+            clock["t"] += 1
+            t = clock["t"]
+            m = min(ctz(t), top)
+            if per_sub is None:
+                ctx.step(p, m, t, t_min, 1, False)
+            else:
+                ts = time.perf_counter()
+                na = ctx.step(p, m, t, t_min, 1, False, want_count=True)
+                ctx.sync()
+                per_sub(m, na, time.perf_counter() - ts)
+
+    for w in range(args.warmup):
+        tw = time.perf_counter()
+        top_step()
+        torch.cuda.synchronize()
+        log(f"warm-up step {w + 1}/{args.warmup}: {time.perf_counter() - tw:.2f} s")
+    torch.cuda.synchronize()
+    i0 = ctx.info()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        top_step()
+        torch.cuda.synchronize()
+        log(f"timed step {k + 1}/{args.steps}: {time.perf_counter() - t0:.2f} s so far")
+    t1 = time.perf_counter()
+    i1 = ctx.info()
+    wall = t1 - t0
+    I_d = i1["interactions_density"] - i0["interactions_density"]
+    I_f = i1["interactions_force"] - i0["interactions_force"]
+    value = (I_d + I_f) / wall
+
+    # one more top-level step with HIP events around every launch group and a
+    # synchronisation after each sub-step (per-bin times, interactions per
+    # loop form)
     per_m = {}
-    k0 = ctx.info()
-    t_sweep = time.perf_counter()
-    for t in range(1, S + 1):
-        m = min((t & -t).bit_length() - 1, top)
-        ts = time.perf_counter()
-        na = ctx.step(p, m, t, t_min, 1, False, want_count=True)
-        ctx.sync()
-        dt = time.perf_counter() - ts
-        e = per_m.setdefault(m, [0, 0.0, 0])
+    I_grp = {"density_loop": 0, "density_sweep": 0, "force_loop": 0, "force_sweep": 0}
+    last = {"i": ctx.info()}
+
+    def per_sub(m, na, dt):
+        inf = ctx.info()
+        dd = inf["interactions_density"] - last["i"]["interactions_density"]
+        df = inf["interactions_force"] - last["i"]["interactions_force"]
+        last["i"] = inf
+        form = "loop" if na >= sweep_below else "sweep"
+        I_grp["density_" + form] += dd
+        I_grp["force_" + form] += df
+        e = per_m.setdefault(m, [0, 0.0, 0, 0])
         e[0] += 1
         e[1] += dt
         e[2] += na
-        if t % 256 == 0:
-            print(f"sub-step {t}/{S}: {(time.perf_counter() - t_sweep):.1f} s", file=sys.stderr, flush=True)
-    wall = time.perf_counter() - t_sweep
-    k1 = ctx.info()
-    I_sd = k1["interactions_density"] - k0["interactions_density"]
-    I_sf = k1["interactions_force"] - k0["interactions_force"]
-    inter = I_sd + I_sf
+        e[3] += dd + df
+
+    ctx.profile(True)
+    tp = time.perf_counter()
+    top_step(per_sub)
+    torch.cuda.synchronize()
+    prof_wall = time.perf_counter() - tp
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    log(f"profiled step: {prof_wall:.2f} s")
+    kernels = {k: {"launches": c, "ms_total": round(ms, 3), "ms_per_step": round(ms, 3)}
+               for k, (c, ms) in sorted(prof.items(), key=lambda kv: -kv[1][1])}
+    groups = {}
+    for name, flop in (("density_loop", FLOP_DENSITY), ("density_sweep", FLOP_DENSITY),
+                       ("force_loop", FLOP_FORCE), ("force_sweep", FLOP_FORCE)):
+        if name in prof:
+            c, ms = prof[name]
+            groups[name] = {"launches": c, "ms": ms, "interactions": I_grp[name],
+                            "tflops": flop * I_grp[name] / (ms / 1e3) / 1e12 if ms > 0 else None}
+    dom = max(prof.items(), key=lambda kv: kv[1][1])[0]
+    cnt, ms = prof[dom]
+    roof = None
+    if dom in groups:
+        flop = FLOP_DENSITY if dom.startswith("density") else FLOP_FORCE
+        per_launch = flop * I_grp[dom] / cnt
+        dur = ms / 1e3 / cnt
+        achieved = per_launch / dur
+        roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": FP32_PEAK / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / FP32_PEAK, "traffic": measured_traffic(dom), "kernel": dom,
+                "launches": cnt, "avg_launch_ms": ms / cnt, "flop_per_launch": per_launch}
+    else:
+        bound, per_launch = kernel_model(dom, N, 0, 0, 0, 0, cnt)
+        if per_launch is not None:
+            achieved = per_launch / (ms / 1e3 / cnt)
+            roof = {"bound": bound, "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK, "traffic": None, "kernel": dom}
     out = {
         "metric": "active particle-neighbour interactions/s (density+force), % FP32 peak, vs plain",
-        "value": inter / wall,
+        "value": value,
         "unit": "interactions/s",
         "n_gpus": 1,
-        "steps": S,
-        "warmup": 0,
-        "ms_per_step": wall / S * 1e3,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 pair arithmetic, f64 positions/integration",
+        "dtype": "f32",
+        "dtype_note": "FP32 pair arithmetic on cell-relative offsets with compensated per-particle sums; FP64 "
+                      "positions, velocities and time integration",
         "data": "synthetic",
+        "config": {"workload": f"large single-GPU share: {N} particles (256^3 lattice displaced by the Zel'dovich "
+                               f"field of a Gaussian random field, P(k)~k^-2.5, rms {args.grf_amplitude} spacings; "
+                               f"u log-uniform 1e-2..1e2; 14 time-bins); one step = one top-level step of "
+                               f"{S} sub-steps t with max active bin min(ctz(t),13)",
+                   "n_particles": N, "substeps_per_step": S,
+                   "drift": "lazy (only the particles a sub-step needs)" if lazy else "every particle each sub-step"},
+        "interactions": I_d + I_f,
+        "interactions_density": I_d,
+        "interactions_force": I_f,
+        "fp32_peak_frac_step": (FLOP_DENSITY * I_d + FLOP_FORCE * I_f) / wall / FP32_PEAK,
+        "full_builds_timed": i1["full_builds"] - i0["full_builds"],
+        "cell_updates_timed": i1["cell_updates"] - i0["cell_updates"],
         "t_min": t_min,
-        "config": {"workload": f"grf {N} particles (256^3 lattice + Zel'dovich displacement of a P(k)~k^-2.5 "
-                               f"field, rms {args.grf_amplitude} spacings; u log-uniform; 14 bins), "
-                               f"{S} sub-steps t=1..{S} with max active bin min(ctz(t),13)",
-                   "n_particles": N, "drift": "lazy (needed leaves)" if args.lazy_drift else "all particles"},
-        "interactions": inter,
-        "full_builds_in_sweep": k1["full_builds"] - k0["full_builds"],
-        "cell_updates_in_sweep": k1["cell_updates"] - k0["cell_updates"],
-        "fp32_peak_frac_sweep": (FLOP_DENSITY * I_sd + FLOP_FORCE * I_sf) / wall / FP32_PEAK,
-        "all_active": all_active,
-        "per_bin": [{"max_active_bin": m, "sub_steps": e[0], "mean_active": e[2] / e[0],
-                     "mean_ms": e[1] / e[0] * 1e3} for m, e in sorted(per_m.items())],
+        "roofline": roof,
+        "loop_groups": groups,
+        "profiled_step_s": prof_wall,
+        "kernels": kernels,
+        "per_bin": [{"max_active_bin": m, "sub_steps": e[0], "mean_active": e[2] / e[0], "mean_ms": e[1] / e[0] * 1e3,
+                     "interactions_per_s": e[3] / e[1] if e[1] > 0 else None}
+                    for m, e in sorted(per_m.items())],
     }
+    out["all_active"] = all_active_steps(ctx, p)
+    log("all-active steps done")
+    del ctx, p
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        out["clustered_deepbin"] = run_clustered(args, with_baseline=False)
+        log("clustered deep-bin line done")
+        out["batch"] = measure_batch(sg)
+        out["adjoint"] = measure_adjoint(sg)
+        log("batch and adjoint done")
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = run_cpu_baseline(ic, "all-active state of the large share (u the thermal input)")
+        log("cpu baseline done")
     print(json.dumps(out))
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--active-fraction", type=float, default=0.01)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=24)
-    ap.add_argument("--split", type=int, default=None)
-    ap.add_argument("--cand-cap", type=int, default=None)
-    ap.add_argument("--list-cap", type=int, default=None)
-    ap.add_argument("--profile-steps", type=int, default=None)
-    ap.add_argument("--h-tol", type=float, default=None)
-    ap.add_argument("--nw", type=int, default=None)
-    ap.add_argument("--sweep-below", type=int, default=None)
-    ap.add_argument("--sweep-waves", type=int, default=None)
-    ap.add_argument("--no-tune", action="store_true")
-    ap.add_argument("--load-tune", default=None, help="load a tuning file instead of tuning")
-    ap.add_argument("--tune-file", default=os.path.join(tempfile.gettempdir(), "sph_tuning_clustered.txt"))
-    ap.add_argument("--workload", choices=("deepbin", "large"), default="deepbin")
-    ap.add_argument("--substeps", type=int, default=8192, help="large workload: sub-steps of the sweep")
-    ap.add_argument("--grf-amplitude", type=float, default=12.0)
-    ap.add_argument("--lazy-drift", action="store_true",
-                    help="large workload: drift only the particles each sub-step needs")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run a plain 512 MiB device copy 5 times (for scaling HBM counters)")
-    ap.add_argument("--no-extras", action="store_true",
-                    help="skip the all-active, 64-box batch and adjoint companion measurements")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the multi-GPU decomposition "
-                                   "is design-only)"}))
-        sys.exit(2)
-    if args.workload == "large":
-        run_large(args)
-        return
-    if args.copy_calibration:
-        import torch
-        n = 512 << 20
-        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(5):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 5}))
-        return
+def run_all_active(args):
+    """The large share's all-active step alone (the loops at full occupancy):
+    setup as in the default line, then `--steps` whole steps with every
+    particle active; the command the loop kernels are profiled with."""
+    import ics
+    import paper_1807_01341_amd as sg
+    sg.require_device()
+    ic = ics.grf_zeldovich(amplitude=args.grf_amplitude)
+    log(f"generated {ic['x'].shape[0]} particles")
+    ctx, p, t_min = grf_setup(sg, ic, not args.drift_all, loop_kwargs(args),
+                              tune_file=False if args.no_tune else args.tune_file)
+    out = all_active_steps(ctx, p, reps=max(1, args.steps))
+    out["workload"] = f"large share {ic['x'].shape[0]} particles, all active"
+    print(json.dumps(out))
 
+
+def run_strategies(args):
+    """The strategy comparison of the paper's Fig. 2 on the large share: one
+    top-level step with every particle drifted each sub-step, one with only
+    the needed particles drifted, and the global step (every particle active
+    every sub-step at t_min: n_bins = 1), the last extrapolated from a few
+    sub-steps to the same 2^13."""
+    import torch
+
+    import ics
+    import paper_1807_01341_amd as sg
+    sg.require_device()
+    ic = ics.grf_zeldovich(amplitude=args.grf_amplitude)
+    N = ic["x"].shape[0]
+    S = args.substeps
+    res = {}
+    for name, lazy in (("relevant_only_drift", True), ("drift_all_kick_active", False)):
+        ctx, p, t_min = grf_setup(sg, ic, lazy, loop_kwargs(args), tune_file=None)
+        top = ctx.params.n_bins - 1
+        i0 = ctx.info()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for t in range(1, S + 1):
+            ctx.step(p, min(ctz(t), top), t, t_min, 1, False)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        i1 = ctx.info()
+        I = i1["interactions_density"] + i1["interactions_force"] - i0["interactions_density"] - i0["interactions_force"]
+        res[name] = {"seconds": wall, "interactions": I, "interactions_per_s": I / wall, "t_min": t_min}
+        log(f"{name}: {wall:.2f} s")
+        del ctx, p
+        torch.cuda.empty_cache()
+    G = args.global_substeps
+    ctx, p, t_min = grf_setup(sg, ic, False, loop_kwargs(args), tune_file=None, n_bins=1)
+    i0 = ctx.info()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(1, G + 1):
+        ctx.step(p, 0, t, t_min, 1, False)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    i1 = ctx.info()
+    I = i1["interactions_density"] + i1["interactions_force"] - i0["interactions_density"] - i0["interactions_force"]
+    res["global_step"] = {"seconds_measured": wall, "substeps_measured": G, "seconds": wall * S / G,
+                          "extrapolated": True, "interactions_per_s": I / wall, "t_min": t_min,
+                          "note": f"every particle active at every sub-step of t_min; {G} sub-steps timed, "
+                                  f"scaled to {S}"}
+    base = res["global_step"]["seconds"]
+    for k in res:
+        res[k]["speedup_vs_global_step"] = base / res[k]["seconds"]
+    print(json.dumps({"workload": f"large share {N} particles, {S} sub-steps", "strategies": res}))
+
+
+def run_clustered(args, with_baseline=True, steps=20, warmup=3):
+    """The 2,097,152-particle clustered box at the deep bin with about 1 % of
+    the particles active: every timed step starts from the same input state
+    (a fused device copy of the arrays a step changes, inside the timed
+    region) and runs the whole path on it."""
     import torch
 
     import ics
@@ -442,21 +641,7 @@ def main():
     N = ic["x"].shape[0]
     m = ics.deep_bin_for_fraction(ic["bin"], args.active_fraction)
     t_min = ic["t_min_model"]
-    kw = {}
-    if args.split:
-        kw["split_count"] = args.split
-    if args.cand_cap:
-        kw["cand_cap"] = args.cand_cap
-    if args.list_cap:
-        kw["list_cap"] = args.list_cap
-    if args.h_tol:
-        kw["h_tol"] = args.h_tol
-    if args.nw:
-        kw["waves_per_chunk"] = args.nw
-    if args.sweep_below is not None:
-        kw["sweep_below"] = args.sweep_below
-    if args.sweep_waves is not None:
-        kw["sweep_waves"] = args.sweep_waves
+    kw = loop_kwargs(args)
     ctx = sg.Context(**kw)
     p = sg.Particles.from_initial(ic)
 
@@ -514,11 +699,11 @@ def main():
         ctx.mark_active(p, m, want_count=False)
         ctx.density_pass(p, entropy_from_u=False)
         ctx.force_pass(p)
-        os.makedirs(os.path.dirname(args.tune_file), exist_ok=True)
-        if os.path.exists(args.tune_file):
-            os.remove(args.tune_file)
-        ctx.autotune(p, args.tune_file)
-        tuned = [l.split() for l in open(args.tune_file) if l.startswith("best")]
+        os.makedirs(os.path.dirname(args.tune_file_clustered), exist_ok=True)
+        if os.path.exists(args.tune_file_clustered):
+            os.remove(args.tune_file_clustered)
+        ctx.autotune(p, args.tune_file_clustered)
+        tuned = [l.split() for l in open(args.tune_file_clustered) if l.startswith("best")]
 
     # cost of the input restore alone (it is inside every timed step)
     torch.cuda.synchronize()
@@ -528,12 +713,12 @@ def main():
     torch.cuda.synchronize()
     restore_ms = (time.perf_counter() - tr) / 10 * 1e3
 
-    for s in range(args.warmup):
+    for s in range(warmup):
         step(s)
     torch.cuda.synchronize()
     inf0 = ctx.info()
     t0 = time.perf_counter()
-    for s in range(args.warmup, args.warmup + args.steps):
+    for s in range(warmup, warmup + steps):
         step(s)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -545,10 +730,10 @@ def main():
     value = inter / wall
 
     # the same steps again with HIP events around every launch of the library
-    ksteps = args.profile_steps or args.steps
+    ksteps = args.profile_steps or steps
     ctx.profile(True)
     t2 = time.perf_counter()
-    for s in range(args.warmup + args.steps, args.warmup + args.steps + ksteps):
+    for s in range(warmup + steps, warmup + steps + ksteps):
         step(s)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
@@ -573,29 +758,30 @@ def main():
         else:
             roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK, "traffic": measured_traffic(dom), "kernel": dom}
-    loop_ms = sum(prof.get(k, (0, 0.0))[1] for k in ("density_loop", "force_loop")) / ksteps
-    flops_step = (FLOP_DENSITY * I_d + FLOP_FORCE * I_f) / args.steps
+    loop_ms = sum(prof.get(k, (0, 0.0))[1]
+                  for k in ("density_loop", "force_loop", "density_sweep", "force_sweep")) / ksteps
+    flops_step = (FLOP_DENSITY * I_d + FLOP_FORCE * I_f) / steps
     out = {
         "metric": "active particle-neighbour interactions/s (density+force), % FP32 peak, vs plain",
         "value": value,
         "unit": "interactions/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": wall / steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 pair arithmetic, f64 positions/integration",
+        "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"clustered {N} particles (90% uniform + 10% in 20 Plummer spheres, "
                                f"a in [0.002,0.02], u log-uniform 1e-2..1e2, 14 bins), deep-bin step m={m}",
                    "n_particles": N, "max_active_bin": m, "n_active": inf1["n_active"],
                    "active_fraction": inf1["n_active"] / N, "n_leaves": inf1["n_leaves"],
                    "split_count": ctx.params.split_count},
-        "interactions_per_step": inter / args.steps,
+        "interactions_per_step": inter / steps,
         "input_restore_ms_per_step": restore_ms,
-        "fp32_peak_frac_step": flops_step / (wall / args.steps) / FP32_PEAK,
+        "fp32_peak_frac_step": flops_step / (wall / steps) / FP32_PEAK,
         "fp32_peak_frac_loops": (flops_step / (loop_ms / 1e3) / FP32_PEAK) if loop_ms > 0 else None,
         "loops_rate_interactions_per_s": ((I_d2 + I_f2) / ksteps) / (loop_ms / 1e3) if loop_ms > 0 else None,
         "profiled_ms_per_step": (t3 - t2) / ksteps * 1e3,
@@ -608,16 +794,71 @@ def main():
                         for t in (tuned or [])],
         "roofline": roof,
     }
-    if not args.no_extras:
-        del p, ctx, state, snapshot
-        torch.cuda.empty_cache()
-        out["all_active"] = measure_all_active(sg, ic, **kw)
-        out["batch"] = measure_batch(sg)
-        out["adjoint"] = measure_adjoint(sg)
-    if not args.no_cpu_baseline:
-        act = ic["bin"] <= m
-        out["cpu_baseline"] = run_cpu_baseline(ic, np.nonzero(act)[0], args.cpu_sample)
-    print(json.dumps(out))
+    del p, ctx, state, snapshot
+    torch.cuda.empty_cache()
+    out["all_active"] = measure_all_active(sg, ic, **kw)
+    if with_baseline and not args.no_cpu_baseline:
+        out["cpu_baseline"] = run_cpu_baseline(ic, "clustered workload, initial state (u the thermal input)")
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2, help="timed steps (large share: top-level steps)")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=("grf", "clustered", "strategies", "allactive"), default="grf")
+    ap.add_argument("--substeps", type=int, default=8192, help="sub-steps of one top-level step (2^13)")
+    ap.add_argument("--global-substeps", type=int, default=16,
+                    help="strategies: sub-steps timed for the global-step arm")
+    ap.add_argument("--grf-amplitude", type=float, default=12.0)
+    ap.add_argument("--drift-all", action="store_true", help="large share: drift every particle each sub-step")
+    ap.add_argument("--active-fraction", type=float, default=0.01)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--split", type=int, default=None)
+    ap.add_argument("--cand-cap", type=int, default=None)
+    ap.add_argument("--list-cap", type=int, default=None)
+    ap.add_argument("--profile-steps", type=int, default=None)
+    ap.add_argument("--h-tol", type=float, default=None)
+    ap.add_argument("--nw", type=int, default=None)
+    ap.add_argument("--sweep-below", type=int, default=None)
+    ap.add_argument("--sweep-waves", type=int, default=None)
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--load-tune", default=None, help="clustered: load a tuning file instead of tuning")
+    ap.add_argument("--tune-file", default=os.path.join(tempfile.gettempdir(), "sph_tuning_grf.txt"))
+    ap.add_argument("--tune-file-clustered", default=os.path.join(tempfile.gettempdir(), "sph_tuning_clustered.txt"))
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 512 MiB device copy 5 times (for scaling HBM counters)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the clustered deep-bin, 64-box batch and adjoint companion measurements")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the multi-GPU decomposition "
+                                   "is design-only)"}))
+        sys.exit(2)
+    if args.copy_calibration:
+        import torch
+        n = 512 << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 5}))
+        return
+    if args.workload == "grf":
+        run_grf(args)
+    elif args.workload == "strategies":
+        run_strategies(args)
+    elif args.workload == "allactive":
+        run_all_active(args)
+    else:
+        out = run_clustered(args, steps=max(args.steps, 20), warmup=max(args.warmup, 3))
+        if not args.no_extras:
+            import paper_1807_01341_amd as sg
+            out["batch"] = measure_batch(sg)
+            out["adjoint"] = measure_adjoint(sg)
+        print(json.dumps(out))
 
 
 if __name__ == "__main__":

@@ -16,8 +16,10 @@
  *  - Every call enqueues work on the stream given to sph_create and returns
  *    without waiting, except where a host output is requested (stated below).
  *  - Everything the library derives (cells, sorts, active lists, cell-pair
- *    lists, scratch) belongs to the context and is allocated with hipMalloc;
- *    it is freed by sph_destroy.
+ *    lists, scratch) belongs to the context.  Its device memory comes from
+ *    the allocator callbacks given to sph_create (the Python binding passes
+ *    PyTorch's caching allocator), or from hipMalloc / hipFree when none are
+ *    given; it is freed by sph_destroy.
  *  - No exception crosses this boundary.  Calls return sph_status; on an
  *    error the context keeps a message readable with sph_last_error.  A
  *    device fault surfaces as SPH_EDEVICE at the next call that synchronises.
@@ -118,10 +120,28 @@ typedef struct {
 /* Fills p with the defaults listed in sph_params. */
 void sph_default_params(sph_params *p);
 
+/* Device memory of a context.  alloc returns `bytes` of device memory (256-byte
+ * aligned) usable by work queued on `hip_stream` from now on, or NULL when it
+ * has none; free returns a block alloc gave.  Both are stream-ordered: a
+ * freed block may be handed out again for work queued later on the same
+ * stream, so the library frees a buffer it outgrows without waiting for the
+ * work still queued on it (PyTorch's caching allocator has exactly these
+ * semantics).  `user` is passed through unchanged. */
+typedef void *(*sph_alloc_fn)(size_t bytes, void *hip_stream, void *user);
+typedef void (*sph_free_fn)(void *ptr, void *hip_stream, void *user);
+
 /* Creates a context that enqueues on `hip_stream` (a hipStream_t, NULL for the
- * default stream) of the current device.  Returns SPH_EINVAL for invalid
- * parameters (morton_depth outside 2..21, split_count < 2, ...). */
-sph_status sph_create(const sph_params *p, void *hip_stream, sph_ctx **out);
+ * default stream) of the current device.  Every device buffer the context
+ * ever holds is taken from alloc and returned through free (both non-NULL),
+ * so no call of the context allocates or frees device memory itself or
+ * waits to grow a buffer.  With alloc and free both NULL the context uses
+ * hipMalloc and hipFree, and growing a buffer waits for the stream first.
+ * The page-locked host slots of the small device-to-host reads (64 int32) are
+ * allocated here with hipHostMalloc.  Returns SPH_EINVAL for invalid
+ * parameters (morton_depth outside 2..21, split_count < 2, ...) or only one
+ * of alloc / free; SPH_ENOMEM when an allocation fails. */
+sph_status sph_create(const sph_params *p, void *hip_stream, sph_alloc_fn alloc, sph_free_fn free, void *user,
+                      sph_ctx **out);
 void sph_destroy(sph_ctx *ctx);
 
 /* Adaptive cells (Sec. III-A: a fixed top-level grid refined while a cell has
@@ -212,7 +232,41 @@ sph_status sph_step(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *perm_out
                     int64_t *n_active_host, int entropy_from_u, int64_t ti, double t_min, int64_t drift_int,
                     int first_step);
 
-/* ---- Batched passes: several contexts (independent periodic boxes, or any
+/* ---- Batches of independent periodic boxes in ONE context (the batching
+ * workload: many boxes whose uneven active cell-pair lists run as one launch
+ * per loop pass).
+ *
+ * sph_batch_create turns a context that has not been used yet (no build)
+ * into a batch of n_boxes boxes: box b owns particles [box_offsets_host[b],
+ * box_offsets_host[b+1]) of every particle array and has side box_L_host[b]
+ * (host arrays of n_boxes + 1 and n_boxes entries, copied; offsets start at 0
+ * and increase strictly).  Each box gets its own cells, sorts, active set and
+ * cell-pair lists (a child context with the batch's parameters, stream and
+ * allocator).  On a batch context:
+ *  - sph_build_cells(n = last offset) builds every box's cells, reordering
+ *    each box's slice of the arrays within the slice; perm_out[i] is the
+ *    original (global) index of position i;
+ *  - sph_sort_cells, sph_kick_drift and sph_step apply to every box;
+ *  - sph_mark_active uses one max_active_bin for every box,
+ *    sph_batch_mark_active one per box (host array of n_boxes);
+ *  - sph_density_pass and sph_force_pass run each loop pass as ONE launch over
+ *    the active chunks of all boxes (work items in decreasing order of
+ *    staged partner particles, tiled by the batch autotuner's table), with the
+ *    per-box results of each box's own passes under the same tiling;
+ *    sph_batch_density_force is the two in one call;
+ *  - sph_autotune tunes the batched loops; sph_info sums over the boxes;
+ *    sph_adjoint and the sph_copy_* calls return SPH_EINVAL (use
+ *    sph_batch_box for a box's structures).
+ * Errors name the failing box.  Batches need lazy_drift = 0 (SPH_EINVAL). */
+sph_status sph_batch_create(sph_ctx *ctx, int n_boxes, const int64_t *box_offsets_host, const double *box_L_host);
+sph_status sph_batch_mark_active(sph_ctx *ctx, const sph_particles *p, const int *max_active_bin_host,
+                                 int64_t *n_active_host);
+sph_status sph_batch_density_force(sph_ctx *ctx, sph_particles *p, int entropy_from_u);
+/* The context of box b of a batch (owned by the batch; NULL if b is out of
+ * range or ctx is not a batch), for sph_info and the sph_copy_* calls. */
+sph_ctx *sph_batch_box(sph_ctx *ctx, int b);
+
+/* ---- Batched passes over several contexts (independent periodic boxes, or any
  * set of particle systems), each built, sorted and marked by its own calls
  * and all created on the SAME stream, run each loop pass of the density /
  * force pass as ONE launch over the concatenation of their active chunks
@@ -307,6 +361,8 @@ typedef struct {
   int64_t full_builds;       /* cumulative: sph_build_cells calls that rebuilt the cells */
   int64_t cell_updates;      /* cumulative: calls that kept them (offsets, H_max, drift margins) */
   float dx_max;              /* largest displacement since the last full build */
+  int64_t device_bytes;      /* device memory the context holds now (all of it from its
+                                allocator) */
 } sph_info_t;
 sph_status sph_info(sph_ctx *ctx, sph_info_t *out); /* synchronises */
 

@@ -403,3 +403,138 @@ int emu_update(int64_t n, double *x, double *y, double *z, const float *h, const
   }
   return flag;
 }
+
+/* ---------------- neighbour counts through a grid ----------------
+ *
+ * The counts of emu_counts, with each sample's candidates j taken from a
+ * uniform grid over the wrapped FP64 positions (x, y, z; sorted order): only
+ * particles within R_i = 1.001 max(H_i, Hcut) + 1e-6 L of the sample
+ * (minimum image, FP64) are tested with the FP32 predicate, Hcut = 0 for the
+ * density loop and the largest H for the force loop.  The FP32 offsets and
+ * shifts differ from the exact separation by well under 1e-6 L, so every
+ * pair the predicate accepts lies within R_i and the counts are those of
+ * emu_counts (a test compares the two on the same inputs). */
+int emu_counts_grid(int mode, double L, int D, int64_t n, const double *x, const double *y, const double *z,
+                    const float *ox, const float *oy, const float *oz, const float *H_s, const int64_t *leaf_of,
+                    const int32_t *leaf_level, const int64_t *leaf_ix, const int64_t *leaf_iy,
+                    const int64_t *leaf_iz, int64_t n_samples, const int64_t *samples, int64_t *counts) {
+  int64_t nu = (int64_t)1 << (D + 1);
+  double unit = ldexp(L, -(D + 1));
+  float Hcut = 0.0f;
+  if (mode == 1)
+    for (int64_t j = 0; j < n; ++j)
+      if (H_s[j] > Hcut) Hcut = H_s[j];
+  double rmax = 0.0;
+  for (int64_t t = 0; t < n_samples; ++t) {
+    double Hi = (double)H_s[samples[t]];
+    double R = 1.001 * (Hi > (double)Hcut ? Hi : (double)Hcut) + 1e-6 * L;
+    if (R > rmax) rmax = R;
+  }
+  int64_t ng = rmax > 0.0 ? (int64_t)floor(L / rmax) : 1;
+  if (ng < 1) ng = 1;
+  if (ng > 256) ng = 256;
+  double cell = L / (double)ng;
+  int64_t ncell = ng * ng * ng;
+  int64_t *head = (int64_t *)calloc((size_t)ncell + 1, sizeof(int64_t));
+  int64_t *item = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+  int64_t *cof = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+  if (!head || !item || !cof) {
+    free(head);
+    free(item);
+    free(cof);
+    return -1;
+  }
+  for (int64_t j = 0; j < n; ++j) {
+    int64_t c[3];
+    const double p[3] = {x[j], y[j], z[j]};
+    for (int a = 0; a < 3; ++a) {
+      int64_t k = (int64_t)floor(p[a] / cell);
+      if (k < 0) k = 0;
+      if (k >= ng) k = ng - 1;
+      c[a] = k;
+    }
+    cof[j] = (c[0] * ng + c[1]) * ng + c[2];
+    head[cof[j] + 1]++;
+  }
+  for (int64_t c = 0; c < ncell; ++c) head[c + 1] += head[c];
+  {
+    int64_t *fill = (int64_t *)malloc((size_t)ncell * sizeof(int64_t));
+    if (!fill) {
+      free(head);
+      free(item);
+      free(cof);
+      return -1;
+    }
+    memcpy(fill, head, (size_t)ncell * sizeof(int64_t));
+    for (int64_t j = 0; j < n; ++j) item[fill[cof[j]]++] = j;
+    free(fill);
+  }
+  const double half = 0.5 * L;
+  for (int64_t t = 0; t < n_samples; ++t) {
+    int64_t i = samples[t];
+    int64_t A = leaf_of[i];
+    int64_t ca[3];
+    leaf_centre_units(D, leaf_level[A], leaf_ix[A], leaf_iy[A], leaf_iz[A], ca);
+    float Hi = H_s[i];
+    float Hi2 = Hi * Hi;
+    double Hd = (double)Hi > (double)Hcut ? (double)Hi : (double)Hcut;
+    double R = 1.001 * Hd + 1e-6 * L;
+    const double pi[3] = {x[i], y[i], z[i]};
+    int64_t lo[3], span[3];
+    for (int a = 0; a < 3; ++a) {
+      int64_t k = (int64_t)floor(pi[a] / cell);
+      if (k < 0) k = 0;
+      if (k >= ng) k = ng - 1;
+      int64_t r = (int64_t)ceil(R / cell);
+      if (2 * r + 1 >= ng) {
+        lo[a] = 0;
+        span[a] = ng;
+      } else {
+        lo[a] = k - r;
+        span[a] = 2 * r + 1;
+      }
+    }
+    int64_t cnt = 0;
+    for (int64_t u = 0; u < span[0]; ++u)
+      for (int64_t v = 0; v < span[1]; ++v)
+        for (int64_t w = 0; w < span[2]; ++w) {
+          int64_t gx = ((lo[0] + u) % ng + ng) % ng, gy = ((lo[1] + v) % ng + ng) % ng,
+                  gz = ((lo[2] + w) % ng + ng) % ng;
+          int64_t c = (gx * ng + gy) * ng + gz;
+          for (int64_t q = head[c]; q < head[c + 1]; ++q) {
+            int64_t j = item[q];
+            if (j == i) continue;
+            double d2 = 0.0;
+            const double pj[3] = {x[j], y[j], z[j]};
+            for (int a = 0; a < 3; ++a) {
+              double d = pj[a] - pi[a];
+              if (d > half) d -= L;
+              if (d < -half) d += L;
+              d2 += d * d;
+            }
+            if (d2 >= R * R) continue;
+            int64_t B = leaf_of[j];
+            int64_t cb[3], dl[3];
+            leaf_centre_units(D, leaf_level[B], leaf_ix[B], leaf_iy[B], leaf_iz[B], cb);
+            nearest_image(nu, ca, cb, dl);
+            float s0 = (float)((double)dl[0] * unit);
+            float s1 = (float)((double)dl[1] * unit);
+            float s2 = (float)((double)dl[2] * unit);
+            float jx = ox[j] + s0, jy = oy[j] + s1, jz = oz[j] + s2;
+            float dx = ox[i] - jx, dy = oy[i] - jy, dz = oz[i] - jz;
+            float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+            int in = r2 < Hi2;
+            if (mode == 1 && !in) {
+              float Hj = H_s[j];
+              in = r2 < Hj * Hj;
+            }
+            cnt += in;
+          }
+        }
+    counts[t] = cnt;
+  }
+  free(head);
+  free(item);
+  free(cof);
+  return 0;
+}

@@ -153,6 +153,26 @@ def counts(cells, mode, samples, H=None):
     return out
 
 
+def counts_grid(cells, mode, samples, H=None):
+    """The counts of `counts`, with candidates from a grid over the wrapped
+    positions (fast for large inputs; equal to `counts` by construction and
+    by test)."""
+    md = {"density": 0, "force": 1}[mode]
+    H = cells["H"] if H is None else np.ascontiguousarray(H, np.float32)
+    samples = np.ascontiguousarray(samples, np.int64)
+    out = np.empty(samples.size, np.int64)
+    xw, yw, zw = (np.ascontiguousarray(cells[k], np.float64) for k in ("xw", "yw", "zw"))
+    f = lib().emu_counts_grid
+    f.restype = C.c_int
+    rc = f(C.c_int(md), C.c_double(cells["L"]), C.c_int(cells["D"]), C.c_int64(cells["ox"].size), _p(xw), _p(yw),
+           _p(zw), _p(cells["ox"]), _p(cells["oy"]), _p(cells["oz"]), _p(H), _p(cells["leaf_of"]),
+           _p(cells["leaf_level"]), _p(cells["leaf_ix"]), _p(cells["leaf_iy"]), _p(cells["leaf_iz"]),
+           C.c_int64(samples.size), _p(samples), _p(out))
+    if rc != 0:
+        raise MemoryError("emu_counts_grid: allocation failed")
+    return out
+
+
 def update(cells, x_sorted, h_sorted, x_build, frac=0.125):
     """The cells of `cells` kept for new positions (sorted order): wrapped
     positions, offsets by the minimum image, H, leaf max H, leaf drift

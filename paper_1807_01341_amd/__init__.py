@@ -9,8 +9,10 @@ Names follow the C functions without their `sph_` prefix.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -65,10 +67,41 @@ class Info(C.Structure):
                 ("n_force_pairs", C.c_int64), ("density_iterations", C.c_int32), ("n_unconverged", C.c_int64),
                 ("interactions_density", C.c_int64), ("interactions_force", C.c_int64),
                 ("unconverged_after_pass", C.c_int32 * 32), ("pair_rebuilds", C.c_int32),
-                ("full_builds", C.c_int64), ("cell_updates", C.c_int64), ("dx_max", C.c_float)]
+                ("full_builds", C.c_int64), ("cell_updates", C.c_int64), ("dx_max", C.c_float),
+                ("device_bytes", C.c_int64)]
 
 
 _lib = None
+
+# device memory of the contexts: the allocator callbacks of sph_create
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+def _torch_alloc(nbytes, stream, user):
+    """PyTorch's caching allocator, stream-ordered on the context's stream;
+    NULL (the library reports SPH_ENOMEM) when it has no memory."""
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+    except Exception:  # noqa: BLE001 -- no exception may cross the C boundary
+        return None
+
+
+def _torch_free(ptr, stream, user):
+    torch.cuda.caching_allocator_delete(int(ptr))
+
+
+TORCH_ALLOC = ALLOC_FN(_torch_alloc)
+TORCH_FREE = FREE_FN(_torch_free)
+
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _destroy_live_contexts():
+    # destroy contexts while torch (their allocator) is still alive
+    for c in list(_live):
+        c.close()
 
 
 def lib():
@@ -81,7 +114,11 @@ def lib():
         vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int
         sigs = {
             "sph_default_params": (None, [vp]),
-            "sph_create": (i32, [vp, vp, vp]),
+            "sph_create": (i32, [vp, vp, ALLOC_FN, FREE_FN, vp, vp]),
+            "sph_batch_create": (i32, [vp, i32, vp, vp]),
+            "sph_batch_mark_active": (i32, [vp, vp, vp, vp]),
+            "sph_batch_density_force": (i32, [vp, vp, i32]),
+            "sph_batch_box": (vp, [vp, i32]),
             "sph_destroy": (None, [vp]),
             "sph_build_cells": (i32, [vp, vp, i64, vp]),
             "sph_sort_cells": (i32, [vp]),
@@ -122,7 +159,8 @@ def exported_symbols():
             "sph_last_error", "sph_info", "sph_copy_leaves", "sph_copy_particles", "sph_copy_axis_order",
             "sph_copy_active", "sph_copy_pairs", "sph_profile", "sph_profile_read", "sph_autotune",
             "sph_load_tuning", "sph_adjoint", "sph_batch_density_pass", "sph_batch_force_pass",
-            "sph_batch_autotune", "sph_step", "sph_drift_all"]
+            "sph_batch_autotune", "sph_step", "sph_drift_all", "sph_batch_create", "sph_batch_mark_active",
+            "sph_batch_density_force", "sph_batch_box"]
 
 
 def require_device():
@@ -232,26 +270,42 @@ class Particles:
 
 
 class Context:
-    """One sph_ctx bound to a torch stream (the current one by default)."""
+    """One sph_ctx bound to a torch stream (the current one by default).
 
-    def __init__(self, params: Params | None = None, stream=None, **overrides):
+    allocator: "torch" (default) takes every device buffer of the context
+    from PyTorch's caching allocator on the context's stream; None lets the
+    library use hipMalloc / hipFree; or a pair (alloc, free) of ALLOC_FN /
+    FREE_FN callbacks."""
+
+    def __init__(self, params: Params | None = None, stream=None, allocator="torch", **overrides):
         require_device()
         self.params = params if params is not None else default_params(**overrides)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
+        if allocator == "torch":
+            self._alloc = (TORCH_ALLOC, TORCH_FREE)
+        elif allocator is None:
+            self._alloc = (ALLOC_FN(), FREE_FN())
+        else:
+            self._alloc = tuple(allocator)
         h = C.c_void_p()
-        self._check(lib().sph_create(C.byref(self.params), C.c_void_p(self.stream.cuda_stream), C.byref(h)),
-                    ctx=None)
+        self._check(lib().sph_create(C.byref(self.params), C.c_void_p(self.stream.cuda_stream), self._alloc[0],
+                                     self._alloc[1], None, C.byref(h)), ctx=None)
         self.h = h
+        self._owns = True
         self._pc = None
         # counts the calls that change the context's derived structures or
         # step state; a saved forward evaluation checks it before its backward
         self.generation = 0
+        _live.add(self)
+
+    def close(self):
+        if getattr(self, "h", None) and getattr(self, "_owns", False) and callable(lib):
+            lib().sph_destroy(self.h)
+        self.h = None
 
     def __del__(self):
         # at interpreter exit the module's globals may already be gone
-        if getattr(self, "h", None) and callable(lib):
-            lib().sph_destroy(self.h)
-            self.h = None
+        self.close()
 
     def _check(self, code, ctx="self"):
         if code != 0:
@@ -320,6 +374,38 @@ class Context:
 
     def sync(self):
         return self._check(lib().sph_sync(self.h))
+
+    # ---- batches of boxes in this context
+    def batch_create(self, box_sizes, box_L=None):
+        """Turns this (unused) context into a batch of len(box_sizes) boxes
+        whose particles are consecutive slices of the particle arrays."""
+        nb = len(box_sizes)
+        off = (C.c_int64 * (nb + 1))(*np.concatenate([[0], np.cumsum(np.asarray(box_sizes, np.int64))]).tolist())
+        L = (C.c_double * nb)(*([1.0] * nb if box_L is None else [float(v) for v in box_L]))
+        self.generation += 1
+        self._check(lib().sph_batch_create(self.h, nb, off, L))
+        self.n_boxes = nb
+        return self
+
+    def batch_mark_active(self, p: Particles, max_active_bins):
+        m = (C.c_int * len(max_active_bins))(*[int(v) for v in max_active_bins])
+        n = C.c_int64(-1)
+        self._check(lib().sph_batch_mark_active(self.h, self._pcs(p), m, C.byref(n)))
+        return n.value
+
+    def batch_density_force(self, p: Particles, entropy_from_u: bool):
+        return self._check(lib().sph_batch_density_force(self.h, self._pcs(p), int(bool(entropy_from_u))))
+
+    def batch_box(self, b: int) -> "Context":
+        """A view of box b's context (owned by this batch) for introspection."""
+        k = lib().sph_batch_box(self.h, int(b))
+        if not k:
+            raise IndexError(b)
+        v = Context.__new__(Context)
+        v.params, v.stream, v._alloc = self.params, self.stream, self._alloc
+        v.h, v._owns, v._pc, v.generation = C.c_void_p(k), False, None, 0
+        v._parent = self
+        return v
 
     def info(self) -> dict:
         inf = Info()

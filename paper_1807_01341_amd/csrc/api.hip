@@ -2,7 +2,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
+#include <vector>
 
 #include "sph_internal.h"
 
@@ -56,10 +58,26 @@ static void resolve_profile(sph_ctx *ctx) {
   ctx->pending.clear();
 }
 
+// ---------------------------------------------------------------- batch contexts
+
+
+// A failing box's status, with its message copied to the batch context.
+static sph_status box_fail(sph_ctx *ctx, size_t b, sph_status s) {
+  if (s == SPH_OK) return s;
+  return sph_fail(ctx, s, "box %zu: %s", b, ctx->kids[b]->err.c_str());
+}
+
+__global__ void add_offset_kernel(int64_t *p, int64_t n, int64_t off) {
+  for (int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x; s < n; s += (int64_t)gridDim.x * 256) p[s] += off;
+}
+
+static bool is_batch(const sph_ctx *ctx) { return ctx && !ctx->kids.empty(); }
+
 extern "C" {
 
 sph_status sph_profile(sph_ctx *ctx, int enable) {
   if (!ctx) return SPH_EINVAL;
+  for (sph_ctx *k : ctx->kids) SPH_TRY(sph_profile(k, enable));
   resolve_profile(ctx);
   ctx->acc.clear();
   ctx->prof = enable;
@@ -69,9 +87,24 @@ sph_status sph_profile(sph_ctx *ctx, int enable) {
 int64_t sph_profile_read(sph_ctx *ctx, char *buf, int64_t cap) {
   if (!ctx) return -1;
   resolve_profile(ctx);
+  // a batch context reports its boxes' launches (batched ones are recorded by the first box)
+  std::vector<sph_ctx::Acc> acc = ctx->acc;
+  for (sph_ctx *k : ctx->kids) {
+    resolve_profile(k);
+    for (auto &a : k->acc) {
+      bool found = false;
+      for (auto &b : acc)
+        if (b.name == a.name) {
+          b.count += a.count;
+          b.ms += a.ms;
+          found = true;
+        }
+      if (!found) acc.push_back(a);
+    }
+  }
   std::string s;
   char line[256];
-  for (auto &a : ctx->acc) {
+  for (auto &a : acc) {
     snprintf(line, sizeof line, "%s %ld %.6f\n", a.name.c_str(), a.count, a.ms);
     s += line;
   }
@@ -107,9 +140,11 @@ void sph_default_params(sph_params *p) {
   p->sweep_below = 1 << 18;
 }
 
-sph_status sph_create(const sph_params *p, void *hip_stream, sph_ctx **out) {
+sph_status sph_create(const sph_params *p, void *hip_stream, sph_alloc_fn alloc, sph_free_fn free_fn, void *user,
+                      sph_ctx **out) {
   if (!p || !out) return SPH_EINVAL;
   *out = nullptr;
+  if ((alloc == nullptr) != (free_fn == nullptr)) return SPH_EINVAL;
   if (!(p->box > 0) || p->morton_depth < 2 || p->morton_depth > 21 || p->split_count < 2 || p->top_cap < 2 ||
       p->top_cap > 8 || p->n_bins < 1 || p->n_bins > 63 || p->h_max_iter < 1 || !(p->eta > 0) ||
       !(p->gamma > 1.0) || p->cand_cap < 64 || p->list_cap < 64 || p->chunk_split < 0 || p->chunk_split > 2 ||
@@ -124,6 +159,10 @@ sph_status sph_create(const sph_params *p, void *hip_stream, sph_ctx **out) {
   if (!ctx) return SPH_ENOMEM;
   ctx->prm = *p;
   ctx->stream = (hipStream_t)hip_stream;
+  ctx->mem.alloc = alloc;
+  ctx->mem.free = free_fn;
+  ctx->mem.user = user;
+  ctx->mem.stream = ctx->stream;
   if (hipGetDevice(&ctx->device) != hipSuccess) {
     delete ctx;
     return SPH_EDEVICE;
@@ -165,6 +204,8 @@ sph_status sph_create(const sph_params *p, void *hip_stream, sph_ctx **out) {
 
 void sph_destroy(sph_ctx *ctx) {
   if (!ctx) return;
+  for (sph_ctx *k : ctx->kids) sph_destroy(k);
+  ctx->kids.clear();
   (void)hipStreamSynchronize(ctx->stream);
   resolve_profile(ctx);
   for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
@@ -174,35 +215,131 @@ void sph_destroy(sph_ctx *ctx) {
 
 static sph_status need_state(sph_ctx *ctx, int at_least, const char *call) {
   if (!ctx) return SPH_EINVAL;
+  if (is_batch(ctx)) return sph_fail(ctx, SPH_EINVAL, "%s: not for batch contexts (see sph_batch_box)", call);
   if (ctx->state < at_least) return sph_fail(ctx, SPH_ESTATE, "%s called out of order (state %d)", call, ctx->state);
   return SPH_OK;
 }
 
+sph_status sph_batch_create(sph_ctx *ctx, int n_boxes, const int64_t *box_offsets_host, const double *box_L_host) {
+  if (!ctx) return SPH_EINVAL;
+  if (is_batch(ctx)) return sph_fail(ctx, SPH_ESTATE, "batch_create: already a batch context");
+  if (ctx->n_full_builds != 0 || ctx->state != 0)
+    return sph_fail(ctx, SPH_ESTATE, "batch_create: the context has been used");
+  if (n_boxes < 1 || !box_offsets_host || !box_L_host)
+    return sph_fail(ctx, SPH_EINVAL, "batch_create: need n_boxes >= 1, offsets and box sides");
+  if (ctx->prm.lazy_drift) return sph_fail(ctx, SPH_EINVAL, "batch_create: batched passes need lazy_drift = 0");
+  if (box_offsets_host[0] != 0) return sph_fail(ctx, SPH_EINVAL, "batch_create: box_offsets[0] must be 0");
+  for (int b = 0; b < n_boxes; ++b) {
+    if (box_offsets_host[b + 1] <= box_offsets_host[b])
+      return sph_fail(ctx, SPH_EINVAL, "batch_create: box %d is empty or the offsets decrease", b);
+    if (!(box_L_host[b] > 0.0)) return sph_fail(ctx, SPH_EINVAL, "batch_create: box %d has side <= 0", b);
+  }
+  std::vector<sph_ctx *> kids;
+  for (int b = 0; b < n_boxes; ++b) {
+    sph_params q = ctx->prm;
+    q.box = box_L_host[b];
+    sph_ctx *k = nullptr;
+    const sph_status st = sph_create(&q, (void *)ctx->stream, ctx->mem.alloc, ctx->mem.free, ctx->mem.user, &k);
+    if (st != SPH_OK) {
+      for (sph_ctx *c : kids) sph_destroy(c);
+      return sph_fail(ctx, st, "batch_create: box %d: context not created", b);
+    }
+    kids.push_back(k);
+  }
+  ctx->kids = kids;
+  ctx->box_off.assign(box_offsets_host, box_offsets_host + n_boxes + 1);
+  return SPH_OK;
+}
+
+sph_ctx *sph_batch_box(sph_ctx *ctx, int b) {
+  if (!is_batch(ctx) || b < 0 || b >= (int)ctx->kids.size()) return nullptr;
+  return ctx->kids[b];
+}
+
 sph_status sph_build_cells(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *perm_out) {
   if (!ctx) return SPH_EINVAL;
+  if (is_batch(ctx)) {
+    if (!p) return sph_fail(ctx, SPH_EINVAL, "build_cells: null particles");
+    if (n != ctx->box_off.back())
+      return sph_fail(ctx, SPH_EINVAL, "build_cells: n = %lld, the boxes hold %lld", (long long)n,
+                      (long long)ctx->box_off.back());
+    const std::vector<sph_particles> sl = box_slices(ctx, p);
+    for (size_t b = 0; b < ctx->kids.size(); ++b) {
+      const int64_t off = ctx->box_off[b], nb = ctx->box_off[b + 1] - off;
+      sph_particles q = sl[b];
+      SPH_TRY(box_fail(ctx, b, build_cells_impl(ctx->kids[b], &q, nb, perm_out ? perm_out + off : nullptr)));
+      if (perm_out && off > 0) {
+        add_offset_kernel<<<(unsigned)std::min<int64_t>(ceil_div(nb, 256), 4096), 256, 0, ctx->stream>>>(
+            perm_out + off, nb, off);
+        HIP_TRY(ctx, hipGetLastError());
+      }
+    }
+    return SPH_OK;
+  }
   return build_cells_impl(ctx, p, n, perm_out);
 }
 
 sph_status sph_sort_cells(sph_ctx *ctx) {
+  if (is_batch(ctx)) {
+    for (size_t b = 0; b < ctx->kids.size(); ++b) SPH_TRY(box_fail(ctx, b, sph_sort_cells(ctx->kids[b])));
+    return SPH_OK;
+  }
   SPH_TRY(need_state(ctx, 1, "sort_cells"));
   return sort_cells_impl(ctx);
 }
 
+sph_status sph_batch_mark_active(sph_ctx *ctx, const sph_particles *p, const int *max_active_bin_host,
+                                 int64_t *n_active_host) {
+  if (!is_batch(ctx)) return ctx ? sph_fail(ctx, SPH_EINVAL, "batch_mark_active: not a batch context") : SPH_EINVAL;
+  if (!p || !max_active_bin_host) return sph_fail(ctx, SPH_EINVAL, "batch_mark_active: null argument");
+  const std::vector<sph_particles> sl = box_slices(ctx, p);
+  int64_t tot = 0;
+  for (size_t b = 0; b < ctx->kids.size(); ++b) {
+    int64_t na = 0;
+    SPH_TRY(box_fail(ctx, b, sph_mark_active(ctx->kids[b], &sl[b], max_active_bin_host[b], &na)));
+    tot += na;
+  }
+  if (n_active_host) *n_active_host = tot;
+  return SPH_OK;
+}
+
 sph_status sph_mark_active(sph_ctx *ctx, const sph_particles *p, int max_active_bin, int64_t *n_active_host) {
+  if (is_batch(ctx)) {
+    std::vector<int> m(ctx->kids.size(), max_active_bin);
+    return sph_batch_mark_active(ctx, p, m.data(), n_active_host);
+  }
   SPH_TRY(need_state(ctx, 2, "mark_active"));
   return mark_active_impl(ctx, p, max_active_bin, n_active_host);
 }
 
 sph_status sph_density_pass(sph_ctx *ctx, sph_particles *p, int entropy_from_u) {
+  if (is_batch(ctx)) {
+    if (!p) return sph_fail(ctx, SPH_EINVAL, "density_pass: null particles");
+    std::vector<sph_particles> sl = box_slices(ctx, p);
+    const sph_status st = batch_density_impl(ctx->kids.data(), sl.data(), (int)sl.size(), entropy_from_u);
+    return st == SPH_OK ? st : sph_fail(ctx, st, "%s", ctx->kids[0]->err.c_str());
+  }
   SPH_TRY(need_state(ctx, 3, "density_pass"));
   if (!p) return sph_fail(ctx, SPH_EINVAL, "density_pass: null particles");
   return density_pass_impl(ctx, p, entropy_from_u);
 }
 
 sph_status sph_force_pass(sph_ctx *ctx, sph_particles *p) {
+  if (is_batch(ctx)) {
+    if (!p) return sph_fail(ctx, SPH_EINVAL, "force_pass: null particles");
+    std::vector<sph_particles> sl = box_slices(ctx, p);
+    const sph_status st = batch_force_impl(ctx->kids.data(), sl.data(), (int)sl.size());
+    return st == SPH_OK ? st : sph_fail(ctx, st, "%s", ctx->kids[0]->err.c_str());
+  }
   SPH_TRY(need_state(ctx, 4, "force_pass"));
   if (!p) return sph_fail(ctx, SPH_EINVAL, "force_pass: null particles");
   return force_pass_impl(ctx, p);
+}
+
+sph_status sph_batch_density_force(sph_ctx *ctx, sph_particles *p, int entropy_from_u) {
+  if (!is_batch(ctx)) return ctx ? sph_fail(ctx, SPH_EINVAL, "batch_density_force: not a batch context") : SPH_EINVAL;
+  SPH_TRY(sph_density_pass(ctx, p, entropy_from_u));
+  return sph_force_pass(ctx, p);
 }
 
 sph_status sph_batch_density_pass(sph_ctx **ctxs, sph_particles *ps, int n_boxes, int entropy_from_u) {
@@ -222,6 +359,7 @@ sph_status sph_batch_autotune(sph_ctx **ctxs, sph_particles *ps, int n_boxes, co
 
 sph_status sph_adjoint(sph_ctx *ctx, sph_particles *p, const float *wx, const float *wy, const float *wz, double *gx,
                        double *gy, double *gz, float *gu) {
+  if (is_batch(ctx)) return sph_fail(ctx, SPH_EINVAL, "adjoint: not for batch contexts");
   SPH_TRY(need_state(ctx, 5, "adjoint"));
   if (!p) return sph_fail(ctx, SPH_EINVAL, "adjoint: null particles");
   return adjoint_impl(ctx, p, wx, wy, wz, gx, gy, gz, gu);
@@ -229,6 +367,13 @@ sph_status sph_adjoint(sph_ctx *ctx, sph_particles *p, const float *wx, const fl
 
 sph_status sph_kick_drift(sph_ctx *ctx, sph_particles *p, int64_t ti, double t_min, int64_t drift_int,
                           int first_step) {
+  if (is_batch(ctx)) {
+    if (!p) return sph_fail(ctx, SPH_EINVAL, "kick_drift: null particles");
+    std::vector<sph_particles> sl = box_slices(ctx, p);
+    for (size_t b = 0; b < ctx->kids.size(); ++b)
+      SPH_TRY(box_fail(ctx, b, sph_kick_drift(ctx->kids[b], &sl[b], ti, t_min, drift_int, first_step)));
+    return SPH_OK;
+  }
   SPH_TRY(need_state(ctx, 5, "kick_drift"));
   if (!p) return sph_fail(ctx, SPH_EINVAL, "kick_drift: null particles");
   return kick_drift_impl(ctx, p, ti, t_min, drift_int, first_step);
@@ -247,6 +392,7 @@ sph_status sph_step(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *perm_out
 
 sph_status sph_drift_all(sph_ctx *ctx, sph_particles *p) {
   if (!ctx) return SPH_EINVAL;
+  if (is_batch(ctx)) return SPH_OK;  // batch contexts drift every particle in kick_drift
   if (!p) return sph_fail(ctx, SPH_EINVAL, "drift_all: null particles");
   if (!ctx->prm.lazy_drift || ctx->n_leaves == 0 || ctx->built_n != ctx->n) return SPH_OK;
   return drift_leaves(ctx, p, nullptr, nullptr, 0);
@@ -263,6 +409,33 @@ const char *sph_last_error(const sph_ctx *ctx) { return ctx ? ctx->err.c_str() :
 
 sph_status sph_info(sph_ctx *ctx, sph_info_t *out) {
   if (!ctx || !out) return SPH_EINVAL;
+  if (is_batch(ctx)) {
+    // sums over the boxes (density_iterations, top_level: the largest; dx_max: the largest)
+    memset(out, 0, sizeof *out);
+    for (size_t b = 0; b < ctx->kids.size(); ++b) {
+      sph_info_t k;
+      SPH_TRY(box_fail(ctx, b, sph_info(ctx->kids[b], &k)));
+      out->n += k.n;
+      out->n_leaves += k.n_leaves;
+      out->top_level = std::max(out->top_level, k.top_level);
+      out->n_active += k.n_active;
+      out->n_active_leaves += k.n_active_leaves;
+      out->n_density_pairs += k.n_density_pairs;
+      out->n_force_pairs += k.n_force_pairs;
+      out->density_iterations = std::max(out->density_iterations, k.density_iterations);
+      out->n_unconverged += k.n_unconverged;
+      out->interactions_density += k.interactions_density;
+      out->interactions_force += k.interactions_force;
+      for (int q = 0; q < 32; ++q) out->unconverged_after_pass[q] += k.unconverged_after_pass[q];
+      out->pair_rebuilds += k.pair_rebuilds;
+      out->full_builds += k.full_builds;
+      out->cell_updates += k.cell_updates;
+      out->dx_max = std::max(out->dx_max, k.dx_max);
+      out->device_bytes += k.device_bytes;
+    }
+    out->device_bytes += ctx->mem.live_bytes;
+    return SPH_OK;
+  }
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   out->n = ctx->n;
   out->n_leaves = ctx->n_leaves;
@@ -282,6 +455,7 @@ sph_status sph_info(sph_ctx *ctx, sph_info_t *out) {
   out->full_builds = ctx->n_full_builds;
   out->cell_updates = ctx->n_updates;
   out->dx_max = ctx->dx_max;
+  out->device_bytes = ctx->mem.live_bytes;
   return SPH_OK;
 }
 

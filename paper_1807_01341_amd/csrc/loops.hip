@@ -1392,7 +1392,7 @@ sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u)
         // few particles to do: one wave per particle.  The number to do only
         // falls from here on, so no later pass of this solve runs the chunk
         // loop (whose chunk flags the sweep leaves as they are).
-        PROF(ctx, "density_loop");
+        PROF(ctx, "density_sweep");
         const int nwp = sweep_waves(ctx, n_todo);
         const unsigned grid = xcd_grid(std::min<int64_t>(ceil_div(n_todo * nwp, 4), (int64_t)ctx->n_cu * 16));
         const int32_t *tl = pass > 1 ? list : nullptr, *tn = pass > 1 ? list_n + (pass & 1) : nullptr;
@@ -1490,7 +1490,7 @@ sph_status force_pass_impl(sph_ctx *ctx, sph_particles *p) {
   LoopArgs a = force_loop_args(ctx, p);
   if (ctx->n_active < ctx->prm.sweep_below) {
     {
-      PROF(ctx, "force_loop");
+      PROF(ctx, "force_sweep");
       const int nwp = sweep_waves(ctx, ctx->n_active);
       const unsigned grid = xcd_grid(ceil_div(ctx->n_active * nwp, 4));
       const bool comp = ctx->prm.compensated != 0;
@@ -1567,6 +1567,13 @@ sph_status time_config(sph_ctx *ctx, const LoopArgs &a0, const LoopConfig &cfg, 
 }  // namespace
 
 extern "C" sph_status sph_autotune(sph_ctx *ctx, sph_particles *p, const char *path) {
+  if (ctx && !ctx->kids.empty()) {
+    // a batch context tunes its batched loops
+    if (!p) return sph_fail(ctx, SPH_EINVAL, "autotune: null particles");
+    std::vector<sph_particles> sl = box_slices(ctx, p);
+    const sph_status st = batch_autotune_impl(ctx->kids.data(), sl.data(), (int)sl.size(), path);
+    return st == SPH_OK ? st : sph_fail(ctx, st, "%s", ctx->kids[0]->err.c_str());
+  }
   if (!ctx || !p) return SPH_EINVAL;
   if (ctx->state < 5) return sph_fail(ctx, SPH_ESTATE, "autotune: run a force pass first");
   if (ctx->n_chunks == 0) return SPH_OK;

@@ -140,14 +140,20 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// Bytes of LDS one wave of the loop kernel uses.
+// Bytes of LDS one wave of the loop kernel uses: per staged candidate its
+// shifted offset and index, its velocity and mass, for the force loops its
+// density-loop state and H; then the per-lane neighbour lists.
 template <int MODE, int CAP, int LCAP>
 struct WaveLds {
+  static constexpr bool th = MODE == 1 || MODE == 2;
   static constexpr int cand = CAP * 16;
+  static constexpr int candV = CAP * 16;
+  static constexpr int candT = th ? CAP * 16 : 0;
   static constexpr int candH = ModeTraits<MODE>::sym ? CAP * 4 : 0;
   static constexpr int lists = LCAP * 64 * 2;
-  static constexpr int bytes = cand + candH + lists;
+  static constexpr int bytes = cand + candV + candT + candH + lists;
   static_assert(bytes >= 10 * 64 * 4, "room for the cross-wave reduction");
+  static_assert(CAP % 4 == 0, "16-byte alignment of the arrays after candH");
 };
 
 // One chunk of up to 64 active particles of one leaf.  MODE 0: density loop;
@@ -168,8 +174,10 @@ __device__ __forceinline__ void chunk_body(const LoopArgs &g, int code, bool cod
   const int wave = threadIdx.x >> 6;
   char *mine = lds + wave * W::bytes;
   float4 *cand = reinterpret_cast<float4 *>(mine);
-  float *candH = reinterpret_cast<float *>(mine + W::cand);
-  uint16_t *lists = reinterpret_cast<uint16_t *>(mine + W::cand + W::candH);
+  float4 *candV = reinterpret_cast<float4 *>(mine + W::cand);
+  float4 *candT = reinterpret_cast<float4 *>(mine + W::cand + W::candV);
+  float *candH = reinterpret_cast<float *>(mine + W::cand + W::candV + W::candT);
+  uint16_t *lists = reinterpret_cast<uint16_t *>(mine + W::cand + W::candV + W::candT + W::candH);
   const Chunk ch = g.chunks[cid];
   const bool live = lane < ch.count;
   const int k = ch.begin + lane;
@@ -209,14 +217,17 @@ __device__ __forceinline__ void chunk_body(const LoopArgs &g, int code, bool cod
 
   auto interact = [&]() {
     const int maxlen = wave_max_i(len);
+    // the next list entry is read one step ahead
+    int cnext = len > 0 ? lists[lane] : 0;
     for (int t = 0; t < maxlen; ++t) {
+      const int c = cnext;
+      if (t + 1 < len) cnext = lists[(t + 1) * 64 + lane];
       if (t < len) {
-        const int c = lists[t * 64 + lane];
         const float4 cj = cand[c];
         const int j = __float_as_int(cj.w);
         const float dx = pi.x - cj.x, dy = pi.y - cj.y, dz = pi.z - cj.z;
         const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        const float4 vj = g.jvm[j];
+        const float4 vj = candV[c];
         const float rinv = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
         const float r = r2 * rinv;
         const float vx = vi.x - vj.x, vy = vi.y - vj.y, vz = vi.z - vj.z;
@@ -241,7 +252,7 @@ __device__ __forceinline__ void chunk_body(const LoopArgs &g, int code, bool cod
           // force adjoint: both orders (i,j) and (j,i) of the pair
           const float Hj = candH[c];
           const float invHj = __builtin_amdgcn_rcpf(Hj);
-          const float4 th = g.jth[j];
+          const float4 th = candT[c];
           const float4 wj = g.jw[j];
           const float qi = r * invHi, qj = r * invHj;
           float wpi, wppi, wpj, wppj;
@@ -338,7 +349,7 @@ __device__ __forceinline__ void chunk_body(const LoopArgs &g, int code, bool cod
         } else {
           const float Hj = candH[c];
           const float invHj = __builtin_amdgcn_rcpf(Hj);
-          const float4 th = g.jth[j];
+          const float4 th = candT[c];
           const float wpi = kernel_dw_only(r * invHi);
           const float wpj = kernel_dw_only(r * invHj);
           const float ih2 = invHj * invHj;
@@ -482,6 +493,11 @@ __device__ __forceinline__ void chunk_body(const LoopArgs &g, int code, bool cod
       // a partner of at most two tiles is read in cell order (its axis order is not made)
       if (valid) j = (selfp || bc <= 128) ? bb + kk : bb + (int)ord[sgn > 0.f ? kk : bc - 1 - kk];
       const float4 pj = valid ? g.pos4[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+      // the candidate's neighbour data, loaded with its position (a kept
+      // candidate's pair terms then read LDS only)
+      const float4 vjs = valid ? g.jvm[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+      float4 ths = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (W::th && valid) ths = g.jth[j];
       if (!selfp && bc > 128) {
         // sorted partner: stop at the first tile wholly past the reach
         const float key = fmaf(pj.z, ez, fmaf(pj.y, ey, pj.x * ex));
@@ -502,6 +518,8 @@ __device__ __forceinline__ void chunk_body(const LoopArgs &g, int code, bool cod
       if (keep) {
         const int slot = ncand + rank_below(mask);
         cand[slot] = make_float4(xj, yj, zj, __int_as_float(j));
+        candV[slot] = vjs;
+        if (W::th) candT[slot] = ths;
         if (ModeTraits<MODE>::sym) candH[slot] = pj.w;
       }
       ncand += __popcll(mask);
@@ -683,7 +701,8 @@ __global__ __launch_bounds__(64 * NW) void loop_multi_kernel(const LoopArgs *__r
 
 // Loop tiling: waves per chunk, tile class (candidate slots / list slots per
 // lane), work order and launch style.  Tile classes: 0 = 128/32, 1 = 256/64,
-// 2 = 512/96, 3 = 1024/128, 4 = 2048/192.
+// 2 = 512/96, 3 = 1024/128, 4 = 2048/192 (the classes that fit the 160 KB of
+// LDS per CU with the waves of one chunk).
 struct LoopConfig {
   int nw = 1;
   int tile = 2;
@@ -701,7 +720,7 @@ inline bool loop_config_valid(const LoopConfig &c) {
     case 1: return c.tile >= 0 && c.tile <= 4;
     case 2: return c.tile >= 0 && c.tile <= 2;
     case 4: return c.tile >= 0 && c.tile <= 1;
-    case 8: return c.tile >= 0 && c.tile <= 1;
+    case 8: return c.tile == 0;
     default: return false;
   }
 }
@@ -755,7 +774,6 @@ hipError_t launch_loop_any(hipStream_t st, const LoopArgs &a, const LoopConfig &
     case 40: SPH_LAUNCH(128, 32, 4);
     case 41: SPH_LAUNCH(256, 64, 4);
     case 80: SPH_LAUNCH(128, 32, 8);
-    case 81: SPH_LAUNCH(256, 64, 8);
     default: return hipErrorInvalidValue;
   }
 #undef SPH_LAUNCH

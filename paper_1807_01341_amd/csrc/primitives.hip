@@ -26,20 +26,33 @@ sph_status sph_hip_check(sph_ctx *ctx, hipError_t e, const char *what) {
 
 sph_status sph_ensure(sph_ctx *ctx, DevBuf &b, size_t bytes) {
   if (bytes <= b.cap && b.p) return SPH_OK;
+  const DevAlloc &mem = ctx->mem;
   if (b.p) {
-    // the old buffer may still be read by queued work
-    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    HIP_TRY(ctx, hipFree(b.p));
-    b.p = nullptr;
-    b.cap = 0;
+    if (b.from && b.from->free) {
+      // stream-ordered: the allocator reuses the block only for work queued
+      // after what is already on the stream
+      b.release();
+    } else {
+      // the old buffer may still be read by queued work
+      HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+      b.release();
+    }
   }
   size_t cap = bytes < 256 ? 256 : bytes + bytes / 8;
-  hipError_t e = hipMalloc(&b.p, cap);
-  if (e != hipSuccess) {
-    b.p = nullptr;
-    return sph_fail(ctx, SPH_ENOMEM, "hipMalloc(%zu bytes) failed: %s", cap, hipGetErrorString(e));
+  cap = (cap + 255) & ~(size_t)255;
+  if (mem.alloc) {
+    b.p = mem.alloc(cap, (void *)mem.stream, mem.user);
+    if (!b.p) return sph_fail(ctx, SPH_ENOMEM, "allocator callback returned no memory for %zu bytes", cap);
+  } else {
+    hipError_t e = hipMalloc(&b.p, cap);
+    if (e != hipSuccess) {
+      b.p = nullptr;
+      return sph_fail(ctx, SPH_ENOMEM, "hipMalloc(%zu bytes) failed: %s", cap, hipGetErrorString(e));
+    }
   }
+  b.from = &ctx->mem;
   b.cap = cap;
+  ctx->mem.live_bytes += (int64_t)cap;
   return SPH_OK;
 }
 

@@ -18,17 +18,38 @@
 
 #define WAVE 64
 
+// Where a context's device memory comes from: the caller's allocator
+// callbacks (stream-ordered, e.g. PyTorch's caching allocator), or hipMalloc
+// and hipFree when the caller gives none.
+struct DevAlloc {
+  sph_alloc_fn alloc = nullptr;
+  sph_free_fn free = nullptr;
+  void *user = nullptr;
+  hipStream_t stream = nullptr;
+  mutable int64_t live_bytes = 0;         // held by the context's buffers now
+};
+
 // Device allocation owned by the context: grown by sph_ensure, freed with the
-// context.
+// context, both through the allocator it was taken from.
 struct DevBuf {
   void *p = nullptr;
   size_t cap = 0;
+  const DevAlloc *from = nullptr;
   DevBuf() = default;
   DevBuf(const DevBuf &) = delete;
   DevBuf &operator=(const DevBuf &) = delete;
-  ~DevBuf() {
-    if (p) (void)hipFree(p);
+  void release() {
+    if (p) {
+      if (from && from->free)
+        from->free(p, (void *)from->stream, from->user);
+      else
+        (void)hipFree(p);
+      if (from) from->live_bytes -= (int64_t)cap;
+    }
+    p = nullptr;
+    cap = 0;
   }
+  ~DevBuf() { release(); }
 };
 
 // Page-locked host memory for the small device-to-host reads of a step: a
@@ -114,6 +135,11 @@ struct Chunk {
 struct sph_ctx {
   sph_params prm;
   hipStream_t stream = nullptr;
+  DevAlloc mem;                           // declared before every DevBuf: outlives them
+  // a batch context (sph_batch_create): one child context per box, each over
+  // the slice [box_off[b], box_off[b+1]) of the particle arrays
+  std::vector<sph_ctx *> kids;
+  std::vector<int64_t> box_off;
   int device = 0;
   int n_cu = 256;
   std::string err;
@@ -220,6 +246,29 @@ struct sph_ctx {
   };
   std::vector<Acc> acc;
 };
+
+// The particle arrays of box b: every non-NULL pointer advanced to the box's
+// first particle.
+inline sph_particles slice_particles(const sph_particles &p, int64_t off) {
+  sph_particles q = p;
+  double **d[] = {&q.x, &q.y, &q.z, &q.vx, &q.vy, &q.vz, &q.vfx, &q.vfy, &q.vfz};
+  for (double **a : d)
+    if (*a) *a += off;
+  float **f[] = {&q.m, &q.u, &q.A, &q.Af, &q.h, &q.rho, &q.drho_dh, &q.f_gradh, &q.divv, &q.curlx, &q.curly,
+                 &q.curlz, &q.P, &q.c, &q.balsara, &q.ax, &q.ay, &q.az, &q.dA_dt, &q.du_dt, &q.vsig};
+  for (float **a : f)
+    if (*a) *a += off;
+  if (q.time_bin) q.time_bin += off;
+  if (q.nngb_density) q.nngb_density += off;
+  if (q.nngb_force) q.nngb_force += off;
+  return q;
+}
+
+inline std::vector<sph_particles> box_slices(const sph_ctx *ctx, const sph_particles *p) {
+  std::vector<sph_particles> v;
+  for (size_t b = 0; b < ctx->kids.size(); ++b) v.push_back(slice_particles(*p, ctx->box_off[b]));
+  return v;
+}
 
 // Records events around the enclosed launches when profiling is on.
 struct ProfScope {

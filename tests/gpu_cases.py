@@ -158,3 +158,179 @@ def float_errors(p, perm, out, fo, idx_sorted=None, fo_aligned=False):
     dA_r = fo["dA_dt"].numpy() if fo_aligned else fo["dA_dt"].numpy()[orig]
     e["dA_dt"] = np.max(np.abs(host(p, "dA_dt")[idx_sorted] - dA_r)) / max(np.max(np.abs(dA_r)), 1e-300)
     return e
+
+
+# ---------------------------------------------------------------- one step of a running simulation
+
+STATE_KEYS = ("x", "y", "z", "vx", "vy", "vz", "m", "A", "h", "time_bin", "rho", "f_gradh", "P", "c", "balsara",
+              "divv", "ax", "ay", "az", "dA_dt", "vsig", "nngb_density", "nngb_force")
+
+
+def step_state(p):
+    """Host copy (cell order) of the particle state after a step's force
+    pass: the step's inputs (positions, predicted velocities and entropies,
+    bins, and the density-loop state inactive particles keep) and outputs."""
+    return {k: host(p, k).copy() for k in STATE_KEYS}
+
+
+class CellTracker:
+    """The C definitions' cells for a running GPU context: a full build is
+    emulated from the positions the GPU built from (recovered from its
+    permutation), a kept build by the update definitions at the positions
+    the step's loops read."""
+
+    def __init__(self, D=16, split=400):
+        self.D, self.split = D, split
+        self.cl_build = None
+
+    def after_build(self, ctx, p, perm_dev, full_before):
+        """Call right after ctx.build_cells(p, perm_dev); full_before is
+        ctx.info()['full_builds'] before that call.  Returns True if it was a
+        full build."""
+        inf = ctx.info()
+        if inf["full_builds"] == full_before:
+            return False
+        perm = perm_dev.cpu().numpy()
+        inv = np.empty_like(perm)
+        inv[perm] = np.arange(perm.size)
+        x_in = np.stack([host(p, k) for k in "xyz"], 1)[inv]
+        h_in = host(p, "h")[inv]
+        cl = emu.build_cells(x_in, h_in, split=self.split, D=self.D)
+        assert np.array_equal(perm, cl["perm"]), "full build: permutation differs from the C definitions"
+        self.cl_build = cl
+        return True
+
+    def now(self, st):
+        """The cells at the positions of state st (cell order)."""
+        xs = np.stack([st["x"], st["y"], st["z"]], 1)
+        xb = np.stack([self.cl_build["xw"], self.cl_build["yw"], self.cl_build["zw"]], 1)
+        up, _ = emu.update(self.cl_build, xs, st["h"], xb)
+        return up
+
+
+def reach_set(x, H, samples, L=1.0):
+    """Indices j (any order) with r_ij < 1.01 max(H_i, H_j) for some sample
+    i (minimum image, FP64): every force neighbour of the samples."""
+    from scipy.spatial import cKDTree
+    tree = cKDTree(x, boxsize=L)
+    Hmax = float(H.max())
+    out = [np.asarray(samples)]
+    for i in samples:
+        c = np.asarray(tree.query_ball_point(x[i], 1.01 * max(float(H[i]), Hmax)), np.int64)
+        d = x[c] - x[i]
+        d -= L * np.round(d / L)
+        r = np.sqrt((d * d).sum(1))
+        out.append(c[r < 1.01 * np.maximum(H[i], H[c])])
+    return np.unique(np.concatenate(out))
+
+
+def local_subset(cl, x, H, samples, L=1.0):
+    """Sorted indices of every particle within 2.6 max(H) of a sample
+    (minimum image): a superset of the samples' force neighbours and of
+    those neighbours' density neighbours at up to 1.5 times their H, so that
+    the oracle's sums over the subset equal its sums over all particles.
+    Leaves (bounding boxes of their particles' positions) are tested first."""
+    R = 2.6 * float(H.max()) + 1e-9
+    b = np.asarray(cl["leaf_begin"], np.int64)
+    c = np.asarray(cl["leaf_count"], np.int64)
+    lo = np.stack([np.minimum.reduceat(x[:, a], b) for a in range(3)], 1)
+    hi = np.stack([np.maximum.reduceat(x[:, a], b) for a in range(3)], 1)
+    keep = np.zeros(b.size, bool)
+    for i in samples:
+        d2 = np.zeros(b.size)
+        for a in range(3):
+            best = None
+            for sh in (-L, 0.0, L):
+                p = x[i, a] + sh
+                g = np.maximum(np.maximum(lo[:, a] - p, p - hi[:, a]), 0.0)
+                best = g if best is None else np.minimum(best, g)
+            d2 += best * best
+        keep |= d2 < R * R
+    idx = [np.arange(bb, bb + cc) for bb, cc in zip(b[keep], c[keep])]
+    return np.concatenate(idx) if idx else np.asarray(samples)
+
+
+def check_step_vs_oracle(st, active, m_bin, samples, cl_now, count_samples=None, entropy_from_u=False,
+                         u=None, label=""):
+    """One step of the path against the oracle at the step's own inputs.
+
+    st: step_state after the force pass; active: the GPU's active flags
+    (cell order).  Checks: the active set is {bin <= m}; neighbour counts of
+    every active particle (or count_samples) bit-exact against the FP32
+    definitions at the GPU's final h; for `samples`, h, rho, f, P, c within
+    1e-5 and a within A_TOL of the FP64 oracle, which solves the density
+    loop for every active particle within force reach of a sample and takes
+    the stored state of inactive neighbours (their last active step's h,
+    rho, f, P, c, B) as the step does.  Returns the error dict."""
+    assert np.array_equal(active, st["time_bin"] <= m_bin), f"{label}: active set"
+    H = (np.float32(1.825742) * st["h"]).astype(np.float32)
+    idx = np.nonzero(active)[0] if count_samples is None else np.asarray(count_samples)
+    cd = emu.counts_grid(cl_now, "density", idx, H=H)
+    cf = emu.counts_grid(cl_now, "force", idx, H=H)
+    nd, nf = st["nngb_density"][idx], st["nngb_force"][idx]
+    assert np.array_equal(nd, cd), f"{label}: density counts differ at {int((nd != cd).sum())} of {idx.size}"
+    assert np.array_equal(nf, cf), f"{label}: force counts differ at {int((nf != cf).sum())} of {idx.size}"
+    samples = np.asarray(samples, np.int64)
+    x_all = np.stack([st["x"], st["y"], st["z"]], 1)
+    # the oracle runs on a local subset that holds every particle its sums reach
+    sub = local_subset(cl_now, x_all, H.astype(np.float64), samples)
+    loc = np.searchsorted(sub, samples)
+    assert np.array_equal(sub[loc], samples)
+    x = x_all[sub]
+    v = np.stack([st["vx"], st["vy"], st["vz"]], 1)[sub]
+    ms = st["m"][sub]
+    act_s = active[sub]
+    J = reach_set(x, H[sub].astype(np.float64), loc)
+    Ja = J[act_s[J]]
+    out = sph.solve_density(x, v, ms, st["h"][sub], 1.0, centres=Ja)
+    th = u[sub][Ja].astype(np.float64) if entropy_from_u else None
+    tA = None if entropy_from_u else torch.as_tensor(st["A"][sub][Ja].astype(np.float64))
+    gh = sph.ghost(out["h"], out["rho"], out["drho_dh"], out["div_raw"], out["curl_raw"],
+                   u=None if th is None else torch.as_tensor(th), A=tA)
+    full = {}
+    for k, gk in (("h", "h"), ("rho", "rho"), ("f", "f_gradh"), ("P", "P"), ("c", "c"), ("B", "balsara")):
+        a = torch.as_tensor(st[gk][sub].astype(np.float64))
+        a[torch.as_tensor(Ja)] = out[k] if k in out else gh[k]
+        full[k] = a
+    fo = sph.force(x, v, ms, full["h"], full["rho"], full["f"], full["P"], full["c"], full["B"], 1.0,
+                   centres=loc)
+    pos = np.searchsorted(Ja, loc)
+
+    def rel(g, r):
+        return float(np.max(np.abs(g.astype(np.float64) - r) / np.abs(r)))
+
+    e = {"h": rel(st["h"][samples], out["h"].numpy()[pos]),
+         "rho": rel(st["rho"][samples], out["rho"].numpy()[pos]),
+         "f": rel(st["f_gradh"][samples], gh["f"].numpy()[pos]),
+         "P": rel(st["P"][samples], gh["P"].numpy()[pos]),
+         "c": rel(st["c"][samples], gh["c"].numpy()[pos]),
+         "vsig": rel(st["vsig"][samples], fo["vsig"].numpy())}
+    a_g = np.stack([st[k][samples] for k in ("ax", "ay", "az")], 1).astype(np.float64)
+    a_r = fo["a"].numpy()
+    den = np.maximum(np.linalg.norm(a_r, axis=1), 1e-2 * fo["scale"].numpy())
+    e["a"] = float(np.max(np.linalg.norm(a_g - a_r, axis=1) / den))
+    e["a_normwise"] = float(np.linalg.norm(a_g - a_r) / np.linalg.norm(a_r))
+    dA_r = fo["dA_dt"].numpy()
+    e["dA_dt"] = float(np.max(np.abs(st["dA_dt"][samples] - dA_r)) / max(np.max(np.abs(dA_r)), 1e-300))
+    print(f"{label}: {idx.size} counts exact; oracle on {len(samples)} samples ({Ja.size} density solves, "
+          f"subset {sub.size}): "
+          + " ".join(f"{k} {v:.2e}" for k, v in e.items()), flush=True)
+    assert e["rho"] < RHO_TOL and e["h"] < 1e-5, label
+    assert e["f"] < 1e-5 and e["P"] < 1e-5 and e["c"] < 1e-5 and e["vsig"] < 1e-5, label
+    assert e["a"] < A_TOL, label
+    return e
+
+
+def spread_sample(active, h, k, rng, centres=None, x=None, per_centre=0):
+    """k active particles spread over the density range (even ranks of h),
+    plus `per_centre` nearest active particles to each of `centres`."""
+    act = np.nonzero(active)[0]
+    order = act[np.argsort(h[act], kind="stable")]
+    pick = [order[np.linspace(0, order.size - 1, min(k, order.size)).astype(np.int64)]]
+    if centres is not None and per_centre > 0:
+        from scipy.spatial import cKDTree
+        t = cKDTree(x[act], boxsize=1.0)
+        for c in centres:
+            _, nn = t.query(c, k=min(per_centre, act.size))
+            pick.append(act[np.atleast_1d(nn)])
+    return np.unique(np.concatenate(pick))

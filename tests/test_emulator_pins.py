@@ -219,3 +219,17 @@ def test_gradient_matches_finite_differences():
     fx, fu = grad.finite_difference(c["x"], c["v"], c["m"], c["u"], c["h"], 1.0, w, ps, 1e-6 / 6)
     assert np.abs(gx[ps] - fx).max() <= 1e-6 * np.abs(fx).max()
     assert np.abs(gu[ps] - fu).max() <= 1e-6 * np.abs(fu).max()
+
+
+@pytest.mark.parametrize("mode", ["density", "force"])
+def test_grid_counts_equal_all_pairs_counts(mode):
+    """The grid-pruned counts used on the large workloads equal the
+    all-pairs FP32 counts, on a clustered box with grown smoothing lengths
+    (leaves of every size class, neighbours across leaf and box faces)."""
+    ic = ics.clustered(n_total=12000, n_clumps=3)
+    cl = cells.build_cells(ic["x"], ic["h"], split=400, D=16)
+    idx = np.arange(0, 12000, 5)
+    H = (cl["H"] * np.float32(1.03)).astype(np.float32)
+    a = cells.counts(cl, mode, idx, H=H)
+    b = cells.counts_grid(cl, mode, idx, H=H)
+    assert a.sum() > 0 and np.array_equal(a, b)

@@ -22,6 +22,21 @@ def test_header_declares_the_path():
         assert f in names
 
 
+def test_header_declares_the_boundary_calls():
+    """The calls of the boundary: the path, the allocator callbacks of
+    sph_create, the one-context batch and the adjoint."""
+    text = open(os.path.join(ROOT, "include", "sphgpu.h")).read()
+    flat = re.sub(r"\s+", " ", re.sub(r"/\*.*?\*/", "", text, flags=re.S))
+    assert "typedef void *(*sph_alloc_fn)(size_t bytes, void *hip_stream, void *user);" in flat
+    assert "typedef void (*sph_free_fn)(void *ptr, void *hip_stream, void *user);" in flat
+    assert ("sph_status sph_create(const sph_params *p, void *hip_stream, sph_alloc_fn alloc, sph_free_fn free, "
+            "void *user, sph_ctx **out);") in flat
+    names = declared_functions()
+    for f in ("sph_batch_create", "sph_batch_density_force", "sph_batch_mark_active", "sph_batch_box",
+              "sph_adjoint", "sph_step", "sph_sync", "sph_last_error"):
+        assert f in names, f
+
+
 def test_library_exports_every_declared_symbol():
     import paper_1807_01341_amd as sg
     if not os.path.exists(sg.LIB_PATH):
