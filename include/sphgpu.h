@@ -152,8 +152,9 @@ void sph_destroy(sph_ctx *ctx);
  * particle from its leaf centre.  perm_out (opt, device, n) receives the
  * original index of each sorted position.  Synchronises once (the top-level
  * size depends on the largest H).  SPH_EINVAL if max H > L/4.
- * Rebuild criterion (the paper rebuilds its cells only when particles have
- * moved too far, Sec. V): when the context's last full build had the same n
+ * Rebuild criterion (the paper's Fig. 7, Sec. IV, sets apart the steps that
+ * rebuild the cells but does not state when a rebuild happens; this rule is
+ * the library's reading): when the context's last full build had the same n
  * and rebuild_frac > 0, the call first tries to keep those cells.  It wraps
  * the positions and recomputes the offsets from the same leaves (minimum
  * image), H, each leaf's max H and each leaf's largest displacement since the
@@ -172,8 +173,9 @@ sph_status sph_build_cells(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *p
  * The offsets are those of the last full build: cell updates keep the
  * orders, and the loops widen the point where a sweep stops by twice the
  * leaf's drift margin (a particle's projection moves at most that far from
- * its sorted place), as the paper keeps sorts while particles drift less
- * than a bound.  After a full build this call sorts every leaf of more than
+ * its sorted place).  Keeping the orders between full builds is the
+ * library's own rule; the paper does not state when sorts are redone.
+ * After a full build this call sorts every leaf of more than
  * 128 particles in one launch (the loops read smaller leaves whole), after
  * one synchronisation that checks the largest leaf (SPH_EINVAL above 4096
  * particles).  It also orders every leaf's particles by H, largest first,
@@ -199,7 +201,8 @@ sph_status sph_mark_active(sph_ctx *ctx, const sph_particles *p, int max_active_
  * re-running the loop for particles not yet converged; then rho, drho/dh,
  * div v, curl v, the grad-h factor, pressure, sound speed, Balsara switch and
  * the entropic function.  entropy_from_u=1 takes u as the thermal input
- * (A = (gamma-1) u rho^(1-gamma)); 0 takes A (and writes u).  Synchronises
+ * (A = (gamma-1) u rho^(1-gamma), written to A and to the kicked copy Af, the
+ * state a first kick starts from); 0 takes A (and writes u).  Synchronises
  * once per group of Newton passes (passes 1-4, then two at a time; a pass
  * reads on the device which particles the previous one left unconverged).
  * SPH_ENOCONV / SPH_EREBUILD as described above. */

@@ -58,6 +58,65 @@ static void resolve_profile(sph_ctx *ctx) {
   ctx->pending.clear();
 }
 
+// ---------------------------------------------------------------- context set-up
+
+static bool params_valid(const sph_params *p) {
+  return p->box > 0 && p->morton_depth >= 2 && p->morton_depth <= 21 && p->split_count >= 2 && p->top_cap >= 2 &&
+         p->top_cap <= 8 && p->n_bins >= 1 && p->n_bins <= 63 && p->h_max_iter >= 1 && p->eta > 0 &&
+         p->gamma > 1.0 && p->cand_cap >= 64 && p->list_cap >= 64 && p->chunk_split >= 0 && p->chunk_split <= 2 &&
+         p->rebuild_frac >= 0.f && p->rebuild_frac <= 1.f && p->pair_slack >= 1.f && p->pair_slack <= 2.f &&
+         (p->lazy_drift == 0 || p->lazy_drift == 1) && p->sweep_below >= 0 &&
+         (p->sweep_waves == 0 || p->sweep_waves == 1 || p->sweep_waves == 2 || p->sweep_waves == 4) &&
+         (p->waves_per_chunk == 0 || p->waves_per_chunk == 1 || p->waves_per_chunk == 2 || p->waves_per_chunk == 4 ||
+          p->waves_per_chunk == 8);
+}
+
+__global__ void zero_i32_kernel(int32_t *p, int64_t n) {
+  for (int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x; s < n; s += (int64_t)gridDim.x * 256) p[s] = 0;
+}
+
+sph_status ctx_init(sph_ctx *ctx, const sph_params *p, void *hip_stream, sph_alloc_fn alloc, sph_free_fn free_fn,
+                    void *user, bool mapped) {
+  if ((alloc == nullptr) != (free_fn == nullptr) || !params_valid(p)) return SPH_EINVAL;
+  ctx->prm = *p;
+  ctx->stream = (hipStream_t)hip_stream;
+  ctx->mem.alloc = alloc;
+  ctx->mem.free = free_fn;
+  ctx->mem.user = user;
+  ctx->mem.stream = ctx->stream;
+  if (hipGetDevice(&ctx->device) != hipSuccess) return SPH_EDEVICE;
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device) == hipSuccess && ncu > 0)
+    ctx->n_cu = ncu;
+  SPH_TRY(sph_ensure(ctx, ctx->scalars, sizeof(int32_t) * SC_COUNT));
+  SPH_TRY(sph_ensure(ctx, ctx->counters64, 2 * sizeof(uint64_t)));
+  if (mapped) {
+    // page-locked, mapped and coherent: copies land in it without a staging
+    // wait, and small kernels write their results into it directly
+    if (hipHostMalloc((void **)&ctx->pin.p, sizeof(int32_t) * PIN_COUNT,
+                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+      ctx->pin.p = nullptr;
+      return SPH_ENOMEM;
+    }
+    if (hipHostGetDevicePointer((void **)&ctx->pin_dev, ctx->pin.p, 0) != hipSuccess || !ctx->pin_dev)
+      return SPH_EDEVICE;
+    ctx->pin_h = ctx->pin.p;
+    ctx->pin_mapped = 1;
+  } else {
+    SPH_TRY(sph_ensure(ctx, ctx->pin_devbuf, sizeof(int32_t) * PIN_COUNT));
+    ctx->pin_dev = (int32_t *)ctx->pin_devbuf.p;
+    ctx->pin_h = ctx->pin_local;
+    ctx->pin_mapped = 0;
+  }
+  // the counters start at zero (a kernel, not a memset node: the set-up may
+  // run inside a caller's stream capture)
+  zero_i32_kernel<<<1, 256, 0, ctx->stream>>>((int32_t *)ctx->scalars.p, SC_COUNT);
+  zero_i32_kernel<<<1, 256, 0, ctx->stream>>>((int32_t *)ctx->counters64.p, 4);
+  if (!mapped) zero_i32_kernel<<<1, 256, 0, ctx->stream>>>(ctx->pin_dev, PIN_COUNT);
+  if (hipGetLastError() != hipSuccess) return SPH_EDEVICE;
+  return SPH_OK;
+}
+
 // ---------------------------------------------------------------- batch contexts
 
 
@@ -144,59 +203,12 @@ sph_status sph_create(const sph_params *p, void *hip_stream, sph_alloc_fn alloc,
                       sph_ctx **out) {
   if (!p || !out) return SPH_EINVAL;
   *out = nullptr;
-  if ((alloc == nullptr) != (free_fn == nullptr)) return SPH_EINVAL;
-  if (!(p->box > 0) || p->morton_depth < 2 || p->morton_depth > 21 || p->split_count < 2 || p->top_cap < 2 ||
-      p->top_cap > 8 || p->n_bins < 1 || p->n_bins > 63 || p->h_max_iter < 1 || !(p->eta > 0) ||
-      !(p->gamma > 1.0) || p->cand_cap < 64 || p->list_cap < 64 || p->chunk_split < 0 || p->chunk_split > 2 ||
-      !(p->rebuild_frac >= 0.f && p->rebuild_frac <= 1.f) || !(p->pair_slack >= 1.f && p->pair_slack <= 2.f) ||
-      !(p->lazy_drift == 0 || p->lazy_drift == 1) ||
-      p->sweep_below < 0 ||
-      !(p->sweep_waves == 0 || p->sweep_waves == 1 || p->sweep_waves == 2 || p->sweep_waves == 4) ||
-      !(p->waves_per_chunk == 0 || p->waves_per_chunk == 1 || p->waves_per_chunk == 2 || p->waves_per_chunk == 4 ||
-        p->waves_per_chunk == 8))
-    return SPH_EINVAL;
   sph_ctx *ctx = new (std::nothrow) sph_ctx();
   if (!ctx) return SPH_ENOMEM;
-  ctx->prm = *p;
-  ctx->stream = (hipStream_t)hip_stream;
-  ctx->mem.alloc = alloc;
-  ctx->mem.free = free_fn;
-  ctx->mem.user = user;
-  ctx->mem.stream = ctx->stream;
-  if (hipGetDevice(&ctx->device) != hipSuccess) {
+  const sph_status st = ctx_init(ctx, p, hip_stream, alloc, free_fn, user, true);
+  if (st != SPH_OK) {
     delete ctx;
-    return SPH_EDEVICE;
-  }
-  int ncu = 0;
-  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device) == hipSuccess && ncu > 0)
-    ctx->n_cu = ncu;
-  if (sph_ensure(ctx, ctx->scalars, sizeof(int32_t) * SC_COUNT) != SPH_OK) {
-    delete ctx;
-    return SPH_ENOMEM;
-  }
-  // page-locked, mapped and coherent: copies land in it without a staging
-  // wait, and small kernels write their results into it directly
-  if (hipHostMalloc((void **)&ctx->pin.p, sizeof(int32_t) * PIN_COUNT,
-                    hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
-    ctx->pin.p = nullptr;
-    delete ctx;
-    return SPH_ENOMEM;
-  }
-  if (hipHostGetDevicePointer((void **)&ctx->pin_dev, ctx->pin.p, 0) != hipSuccess || !ctx->pin_dev) {
-    delete ctx;
-    return SPH_EDEVICE;
-  }
-  if (sph_ensure(ctx, ctx->counters64, 2 * sizeof(uint64_t)) != SPH_OK) {
-    delete ctx;
-    return SPH_ENOMEM;
-  }
-  if (hipMemsetAsync(ctx->counters64.p, 0, 2 * sizeof(uint64_t), ctx->stream) != hipSuccess) {
-    delete ctx;
-    return SPH_EDEVICE;
-  }
-  if (hipMemsetAsync(ctx->scalars.p, 0, sizeof(int32_t) * SC_COUNT, ctx->stream) != hipSuccess) {
-    delete ctx;
-    return SPH_EDEVICE;
+    return st;
   }
   *out = ctx;
   return SPH_OK;

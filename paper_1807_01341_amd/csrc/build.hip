@@ -914,8 +914,9 @@ sph_status lazy_keep_cells(sph_ctx *ctx, int *rebuild) {
   }
   HIP_TRY(ctx, hipGetLastError());
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  SPH_TRY(pin_fetch(ctx, PIN_UPD, 3));
   int32_t st[3];
-  memcpy(st, ctx->pin.p + PIN_UPD, sizeof st);
+  memcpy(st, ctx->pin_h + PIN_UPD, sizeof st);
   float hmax, dxm;
   memcpy(&hmax, &st[0], 4);
   memcpy(&dxm, &st[1], 4);
@@ -961,8 +962,9 @@ sph_status update_cells(sph_ctx *ctx, sph_particles *p, int64_t *perm_out, int *
   }
   HIP_TRY(ctx, hipGetLastError());
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  SPH_TRY(pin_fetch(ctx, PIN_UPD, 3));
   int32_t st[3];
-  memcpy(st, ctx->pin.p + PIN_UPD, sizeof st);
+  memcpy(st, ctx->pin_h + PIN_UPD, sizeof st);
   float hmax, dxm;
   memcpy(&hmax, &st[0], 4);
   memcpy(&dxm, &st[1], 4);

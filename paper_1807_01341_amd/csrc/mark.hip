@@ -538,7 +538,8 @@ sph_status build_pairs(sph_ctx *ctx, int which, float slack) {
   copy_total_kernel<<<1, 64, 0, ctx->stream>>>((const int32_t *)off.p + na, ctx->pin_dev + PIN_NPAIRS);
   HIP_TRY(ctx, hipGetLastError());
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-  return build_pairs_fill(ctx, which, slack, ctx->pin.p[PIN_NPAIRS]);
+  SPH_TRY(pin_fetch(ctx, PIN_NPAIRS, 1));
+  return build_pairs_fill(ctx, which, slack, ctx->pin_h[PIN_NPAIRS]);
 }
 
 // Refreshes the max H of every active leaf (all particles, and active ones)
@@ -609,10 +610,11 @@ sph_status mark_active_impl(sph_ctx *ctx, const sph_particles *p, int m, int64_t
   SPH_TRY(scan_exclusive_i32(ctx, nact, aoff, 3 * nl, aoff + 3 * nl));
   // the three totals written into page-locked slots by one small kernel, one
   // synchronisation
-  const int32_t *tot3 = ctx->pin.p + PIN_MARK;
+  const int32_t *tot3 = ctx->pin_h + PIN_MARK;
   mark_totals_kernel<<<1, 64, 0, ctx->stream>>>(aoff, nl, ctx->pin_dev + PIN_MARK);
   HIP_TRY(ctx, hipGetLastError());
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  SPH_TRY(pin_fetch(ctx, PIN_MARK, 3));
   int32_t tot[3] = {tot3[0], tot3[1] - tot3[0], tot3[2] - tot3[1]};
   ctx->n_active = tot[0];
   ctx->n_active_leaves = tot[1];

@@ -56,10 +56,19 @@ sph_status sph_ensure(sph_ctx *ctx, DevBuf &b, size_t bytes) {
   return SPH_OK;
 }
 
+sph_status pin_fetch(sph_ctx *ctx, int first, int count) {
+  if (ctx->pin_mapped || count <= 0) return SPH_OK;
+  if (first < 0 || first + count > PIN_COUNT) return sph_fail(ctx, SPH_EINVAL, "pin_fetch: slots out of range");
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->pin_h + first, ctx->pin_dev + first, sizeof(int32_t) * count,
+                              hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return SPH_OK;
+}
+
 sph_status read_scalars(sph_ctx *ctx, int first, int count, int32_t *host) {
   if (count < 1 || count > PIN_MARK - PIN_SCALARS || first < 0 || first + count > SC_COUNT)
     return sph_fail(ctx, SPH_EINVAL, "read_scalars: slots [%d, %d) out of range", first, first + count);
-  int32_t *pin = ctx->pin.p + PIN_SCALARS;
+  int32_t *pin = ctx->pin_h + PIN_SCALARS;
   HIP_TRY(ctx, hipMemcpyAsync(pin, (int32_t *)ctx->scalars.p + first, sizeof(int32_t) * count,
                               hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));

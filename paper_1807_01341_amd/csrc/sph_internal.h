@@ -174,8 +174,14 @@ struct sph_ctx {
   // build
   DevBuf keys_a, keys_b, vals_a, vals_b, radix_counts, scan_tmp, gather_tmp;
   DevBuf scalars;                         // small device counters
-  HostPin pin;                            // host side of the reads (PinSlot)
-  int32_t *pin_dev = nullptr;             // the same slots as kernels address them (mapped)
+  HostPin pin;                            // page-locked host slots of the reads (PinSlot)
+  int32_t *pin_dev = nullptr;             // the slots as kernels address them
+  int32_t *pin_h = nullptr;               // the slots as the host reads them
+  int pin_mapped = 1;                     // 1: pin_h and pin_dev are one mapped page-locked
+                                          // block; 0: pin_dev is device memory, copied to
+                                          // pin_local by pin_fetch
+  int32_t pin_local[64] = {0};
+  DevBuf pin_devbuf;                      // device side of the slots when not mapped
   DevBuf flags, scan_out, nodes_a, nodes_b, leaf_lvl_at;
   DevBuf leaf_level, leaf_ix, leaf_iy, leaf_iz, leaf_begin, leaf_count, leaf_hmax, leaf_of;
   DevBuf top_first, top_last;
@@ -284,6 +290,12 @@ struct ProfScope {
 
 // ---------------------------------------------------------------- host helpers
 sph_status sph_fail(sph_ctx *ctx, sph_status code, const char *fmt, ...);
+// Initialises a context made with new: parameters, stream, allocator, the
+// small counters (zeroed) and the read slots -- page-locked and mapped
+// (hipHostMalloc) when `mapped`, else taken from the allocator and read back
+// by pin_fetch.
+sph_status ctx_init(sph_ctx *ctx, const sph_params *p, void *hip_stream, sph_alloc_fn alloc, sph_free_fn free_fn,
+                    void *user, bool mapped);
 sph_status sph_hip_check(sph_ctx *ctx, hipError_t e, const char *what);
 sph_status sph_ensure(sph_ctx *ctx, DevBuf &b, size_t bytes);
 
@@ -327,6 +339,7 @@ enum PinSlot {
   PIN_STATS = 32,     // density solve: per-pass counters of one group of passes
   PIN_COUNT = 64
 };
+static_assert(PIN_COUNT == sizeof(((sph_ctx *)nullptr)->pin_local) / sizeof(int32_t), "pin_local holds every slot");
 
 // ---------------------------------------------------------------- primitives (primitives.hip)
 // Exclusive prefix sum of n int32 values; the total lands in *total_dev.
@@ -335,6 +348,10 @@ sph_status scan_exclusive_i32(sph_ctx *ctx, const int32_t *in, int32_t *out, int
 // The sorted result is left in ctx->keys_a / ctx->vals_a.
 sph_status radix_sort_pairs(sph_ctx *ctx, int64_t n, int bits);
 sph_status read_scalars(sph_ctx *ctx, int first, int count, int32_t *host);
+// After a stream synchronisation: the host view of the pin slots [first,
+// first + count) that kernels wrote (a copy from the device side when the
+// slots are not mapped page-locked memory).
+sph_status pin_fetch(sph_ctx *ctx, int first, int count);
 
 // ---------------------------------------------------------------- stages
 sph_status build_cells_impl(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *perm_out);

@@ -100,7 +100,7 @@ def test_one_context_batch_equals_multi_context_batch(gpu_lib):
     ms = [ics.deep_bin_for_fraction(b["bin"], b["target_active_fraction"]) for b in boxes]
     sizes = [b["x"].shape[0] for b in boxes]
     print(f"case batch64 one context vs 64 contexts, N={sum(sizes)}", flush=True)
-    # 64 contexts, batched passes
+    # 64 contexts, batched passes (the all-active set-up pass batched too)
     cs, ps, perms = [], [], []
     for b, m in zip(boxes, ms):
         p = sg.Particles.from_initial(b)
@@ -109,12 +109,13 @@ def test_one_context_batch_equals_multi_context_batch(gpu_lib):
         c.build_cells(p, perm)
         c.sort_cells()
         c.mark_active(p, c.params.n_bins - 1)
-        c.density_pass(p, True)
-        c.mark_active(p, m)
         cs.append(c)
         ps.append(p)
         perms.append(perm)
     batch = sg.Batch(cs, ps)
+    batch.density_pass(True)
+    for c, p, m in zip(cs, ps, ms):
+        c.mark_active(p, m)
     batch.density_pass(False)
     batch.force_pass()
     torch.cuda.synchronize()
