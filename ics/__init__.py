@@ -209,17 +209,67 @@ def batch_of_boxes(n_boxes: int = 64, n_range=(1_000, 200_000), index: int = 3,
     return boxes
 
 
+def _smooth_gaussian_field(n: int, length: float, rng):
+    """A unit-variance Gaussian random field on the n^3 grid, white noise
+    smoothed with a Gaussian of `length` grid spacings (periodic)."""
+    k1 = np.fft.fftfreq(n) * 2.0 * math.pi
+    kz1 = np.fft.rfftfreq(n) * 2.0 * math.pi
+    KX, KY, KZ = np.meshgrid(k1, k1, kz1, indexing="ij")
+    filt = np.exp(-0.5 * (KX * KX + KY * KY + KZ * KZ) * length * length)
+    del KX, KY, KZ
+    g = np.fft.irfftn(np.fft.rfftn(rng.normal(size=(n, n, n))) * filt, s=(n, n, n), axes=(0, 1, 2))
+    return g / g.std()
+
+
+def _cic_density(x, n):
+    """Cloud-in-cell count of the particles on the n^3 grid (mean 1 per cell),
+    and the same field read back at each particle."""
+    d = 1.0 / n
+    gi = x / d - 0.5
+    i0 = np.floor(gi).astype(np.int64)
+    f = gi - i0
+    rho = np.zeros((n, n, n))
+    corners = []
+    for dx in (0, 1):
+        wx = f[:, 0] if dx else 1 - f[:, 0]
+        for dy in (0, 1):
+            wy = f[:, 1] if dy else 1 - f[:, 1]
+            for dz in (0, 1):
+                wz = f[:, 2] if dz else 1 - f[:, 2]
+                idx = ((i0[:, 0] + dx) % n, (i0[:, 1] + dy) % n, (i0[:, 2] + dz) % n)
+                w = wx * wy * wz
+                np.add.at(rho, idx, w)
+                corners.append((idx, w))
+    rho *= n ** 3 / x.shape[0]
+    rho_p = np.zeros(x.shape[0])
+    for idx, w in corners:
+        rho_p += w * rho[idx]
+    return rho, rho_p
+
+
 def grf_zeldovich(nside: int = 256, spectral_index: float = -2.5, amplitude: float = 12.0,
-                  index: int = 5, u_range=(1e-2, 1e2)):
-    """Workload 5: nside^3 lattice displaced by the Zel'dovich field of a
-    Gaussian random density field with P(k) ~ k^spectral_index.  The
-    displacement is psi_k = i k delta_k / k^2 scaled so that its rms equals
-    `amplitude` lattice spacings (12 gives the largest density contrast of
-    this spectrum at 256^3, about 2e2 between the densest particles and the
-    median; larger amplitudes smear the caustics out); u is log-uniform.  The model density for the
-    initial h guess and the model bins is a cloud-in-cell count of the
-    displaced particles on the nside^3 grid."""
-    r_field, r_u = _streams(index, 2)
+                  index: int = 5, n_clumps: int = 16, clump_fraction: float = 0.02,
+                  clump_a=(0.002, 0.01), u_scatter: float = 0.5, scatter_length: float = 8.0,
+                  thermal: str = "adiabatic", u_range=(1e-2, 1e2)):
+    """Workload 5: nside^3 particles.  A lattice displaced by the Zel'dovich
+    field of a Gaussian random density field with P(k) ~ k^spectral_index
+    (psi_k = i k delta_k / k^2, scaled to an rms displacement of `amplitude`
+    lattice spacings; 12 gives this spectrum's largest contrast at 256^3,
+    about 2e2 between the densest particles and the median), with
+    clump_fraction of the particles (drawn at random) moved into n_clumps
+    Plummer spheres (scale radii log-uniform in clump_a) centred on the
+    densest cells of the displaced lattice, which carries the density
+    contrast to about 1e4.
+
+    Thermal state (thermal="adiabatic"): u = (rho / rho_median)^(gamma-1)
+    times exp(u_scatter * g), g a unit Gaussian field smoothed over
+    scatter_length spacings: hotter where denser, smooth in space, so that
+    the time-steps of Eq. 1 form a hierarchy with geometrically fewer
+    particles on the shorter steps.  thermal="loguniform" draws u
+    independently per particle, log-uniform in u_range.  v = 0.  The model
+    density for the initial h and the model bins is the cloud-in-cell
+    density of the displaced lattice plus each clump's Plummer profile."""
+    r_field, r_u, r_cl, r_g = _streams(index, 4)
     n = nside
     d = 1.0 / n
     k1 = np.fft.fftfreq(n, d=d) * 2.0 * math.pi
@@ -234,7 +284,7 @@ def grf_zeldovich(nside: int = 256, spectral_index: float = -2.5, amplitude: flo
     del noise, amp
     psi = []
     for K in (KX, KY, KZ):
-        psi.append(np.fft.irfftn(1j * K * dk / k2, s=(n, n, n)).ravel())
+        psi.append(np.fft.irfftn(1j * K * dk / k2, s=(n, n, n), axes=(0, 1, 2)).ravel())
     del dk, KX, KY, KZ, k2
     psi = np.stack(psi, axis=1)
     rms = math.sqrt(float(np.mean(np.sum(psi * psi, axis=1))))
@@ -244,33 +294,46 @@ def grf_zeldovich(nside: int = 256, spectral_index: float = -2.5, amplitude: flo
     x = _wrap(x)
     N = x.shape[0]
     m = 1.0 / N
-    # cloud-in-cell density on the lattice grid, read back at each particle
-    gi = x / d - 0.5
-    i0 = np.floor(gi).astype(np.int64)
-    f = gi - i0
-    rho = np.zeros((n, n, n))
-    for dx in (0, 1):
-        wx = f[:, 0] if dx else 1 - f[:, 0]
-        for dy in (0, 1):
-            wy = f[:, 1] if dy else 1 - f[:, 1]
-            for dz in (0, 1):
-                wz = f[:, 2] if dz else 1 - f[:, 2]
-                np.add.at(rho, ((i0[:, 0] + dx) % n, (i0[:, 1] + dy) % n, (i0[:, 2] + dz) % n),
-                          wx * wy * wz)
-    rho_p = np.zeros(N)
-    for dx in (0, 1):
-        wx = f[:, 0] if dx else 1 - f[:, 0]
-        for dy in (0, 1):
-            wy = f[:, 1] if dy else 1 - f[:, 1]
-            for dz in (0, 1):
-                wz = f[:, 2] if dz else 1 - f[:, 2]
-                rho_p += wx * wy * wz * rho[(i0[:, 0] + dx) % n, (i0[:, 1] + dy) % n, (i0[:, 2] + dz) % n]
+    rho_grid, rho_p = _cic_density(x, n)
     rho_p = np.maximum(rho_p, 0.05)  # mean is 1 in particle units
-    u = np.exp(r_u.uniform(math.log(u_range[0]), math.log(u_range[1]), size=N)).astype(np.float32)
+    n_cl_tot = int(round(clump_fraction * N)) if n_clumps > 0 else 0
+    if n_cl_tot > 0:
+        # clump centres: the densest cells, each at least 0.1 from the ones before
+        order = np.argsort(rho_grid.ravel())[::-1]
+        centres = []
+        for c in order[: 64 * n_clumps]:
+            cc = (np.array(np.unravel_index(c, rho_grid.shape)) + 0.5) * d
+            if all(np.max(np.abs((cc - q + 0.5) % 1.0 - 0.5)) >= 0.1 for q in centres):
+                centres.append(cc)
+            if len(centres) == n_clumps:
+                break
+        centres = np.array(centres)
+        moved = np.sort(r_cl.choice(N, size=n_cl_tot, replace=False))
+        a_s = np.exp(r_cl.uniform(math.log(clump_a[0]), math.log(clump_a[1]), size=len(centres)))
+        base, rem = divmod(n_cl_tot, len(centres))
+        start = 0
+        for k in range(len(centres)):
+            nk = base + (1 if k < rem else 0)
+            sel = moved[start:start + nk]
+            off = plummer_offsets(nk, a_s[k], r_cl)
+            x[sel] = _wrap(centres[k] + off)
+            rho_p[sel] = plummer_density(np.linalg.norm(off, axis=1), a_s[k], nk * m) + 1.0
+            start += nk
+    else:
+        centres = np.zeros((0, 3))
+        a_s = np.zeros(0)
     h = (ETA * d * np.cbrt(1.0 / rho_p)).astype(np.float32)
+    if thermal == "adiabatic":
+        g = _smooth_gaussian_field(n, scatter_length, r_g)
+        gi = np.minimum((x / d).astype(np.int64), n - 1)
+        gp = g[gi[:, 0], gi[:, 1], gi[:, 2]]
+        del g
+        u = ((rho_p / np.median(rho_p)) ** (GAMMA - 1.0) * np.exp(u_scatter * gp)).astype(np.float32)
+    else:
+        u = np.exp(r_u.uniform(math.log(u_range[0]), math.log(u_range[1]), size=N)).astype(np.float32)
     bins, tmin = _model_bins(h, u)
     return dict(x=x, v=np.zeros((N, 3)), m=np.full(N, m, np.float32), u=u, h=h, bin=bins,
-                t_min_model=tmin, L=1.0, name=f"grf{nside}^3")
+                t_min_model=tmin, L=1.0, clump_centres=centres, clump_a=a_s, name=f"grf{nside}^3")
 
 
 def deep_bin_for_fraction(bins, target_fraction: float, n_bins: int = N_BINS):

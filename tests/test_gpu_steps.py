@@ -232,6 +232,9 @@ def test_individual_steps_kick_drift_vs_oracle(gpu_lib, lazy):
     assert np.array_equal(host(p, "time_bin").astype(np.int64), o["bins"])
     assert len(set(o["bins"].tolist())) > 1
     # positions and velocities: FP64 on both sides, the lazy drift adding a
-    # lag of several sub-steps at once; entropies and h: FP32 storage
+    # lag of several sub-steps at once; entropies and h: stored in FP32 by the
+    # path, one rounding (at most 2^-24 relative) per sub-step that updates
+    # them, against the oracle's FP64: 17 sub-steps x 2^-23
     assert err["x"] < 1e-12 and err["v"] < 1e-12 and err["vf"] < 1e-12
-    assert err["A"] < 1e-6 and err["Af"] < 1e-6 and err["h"] < 1e-6
+    tol32 = 17 * 2.0 ** -23
+    assert err["A"] < tol32 and err["Af"] < tol32 and err["h"] < tol32
