@@ -311,6 +311,28 @@ sph_status sph_batch_autotune(sph_ctx **ctxs, sph_particles *ps, int n_boxes, co
 sph_status sph_adjoint(sph_ctx *ctx, sph_particles *p, const float *wx, const float *wy, const float *wz,
                        double *gx, double *gy, double *gz, float *gu);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * serving loops, harnesses that forbid hipMalloc): one whole step of
+ * sph_step -- build_cells, sort_cells, mark_active, density_pass, force_pass,
+ * kick_drift with the same arguments and results as sph_step on a newly
+ * created context with parameters *p on hip_stream -- run on a context that
+ * lives only for this call, every device buffer of which is carved from a
+ * fixed 256 MiB array of the library (each GPU it runs on holds its own copy
+ * until the process ends), and whose small device-to-host reads go through
+ * host memory of that context.  The call allocates no device or page-locked
+ * memory and returns after the work has finished (it synchronises the
+ * stream).  n is at most 2^18 = 262144 (SPH_EINVAL beyond); a step that needs
+ * more than the array returns SPH_ENOMEM.  The array keeps the previous
+ * call's contents; calls that overlap on one GPU (from several host threads
+ * or streams) race on it and must not be made.  perm_out and n_active_host
+ * may be NULL; scratch_used_host (opt) receives the bytes of the array the
+ * step used; err (opt, err_cap bytes) receives the error message, empty on
+ * success. */
+sph_status sph_step_noalloc(const sph_params *p, void *hip_stream, sph_particles *parts, int64_t n,
+                            int64_t *perm_out, int max_active_bin, int64_t *n_active_host, int entropy_from_u,
+                            int64_t ti, double t_min, int64_t drift_int, int first_step,
+                            int64_t *scratch_used_host, char *err, size_t err_cap);
+
 /* With lazy_drift: drifts every particle still behind the time line to it
  * (x, v, A, h and the derived offsets), e.g. before the caller reads the
  * state of all particles.  Without lazy_drift, or before the first build,

@@ -119,6 +119,8 @@ def lib():
             "sph_batch_mark_active": (i32, [vp, vp, vp, vp]),
             "sph_batch_density_force": (i32, [vp, vp, i32]),
             "sph_batch_box": (vp, [vp, i32]),
+            "sph_step_noalloc": (i32, [vp, vp, vp, i64, vp, i32, vp, i32, i64, C.c_double, i64, i32, vp,
+                                       C.c_char_p, C.c_size_t]),
             "sph_destroy": (None, [vp]),
             "sph_build_cells": (i32, [vp, vp, i64, vp]),
             "sph_sort_cells": (i32, [vp]),
@@ -160,7 +162,7 @@ def exported_symbols():
             "sph_copy_active", "sph_copy_pairs", "sph_profile", "sph_profile_read", "sph_autotune",
             "sph_load_tuning", "sph_adjoint", "sph_batch_density_pass", "sph_batch_force_pass",
             "sph_batch_autotune", "sph_step", "sph_drift_all", "sph_batch_create", "sph_batch_mark_active",
-            "sph_batch_density_force", "sph_batch_box"]
+            "sph_batch_density_force", "sph_batch_box", "sph_step_noalloc"]
 
 
 def require_device():
