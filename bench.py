@@ -347,6 +347,8 @@ def grf_setup(sg, ic, lazy, kw, tune_file=None, n_bins=None):
         kw["n_bins"] = n_bins
     ctx = sg.Context(lazy_drift=int(lazy), **kw)
     p = sg.Particles.from_initial(ic)
+    if n_bins is not None:
+        p["time_bin"].clamp_(max=n_bins - 1)   # every particle in a bin the context has
     top = ctx.params.n_bins - 1
     ctx.build_cells(p)
     ctx.sort_cells()
@@ -458,12 +460,19 @@ def run_grf(args):
     I_grp = {"density_loop": 0, "density_sweep": 0, "force_loop": 0, "force_sweep": 0}
     last = {"i": ctx.info()}
 
+    newton = []
+
     def per_sub(m, na, dt):
         inf = ctx.info()
         dd = inf["interactions_density"] - last["i"]["interactions_density"]
         df = inf["interactions_force"] - last["i"]["interactions_force"]
         last["i"] = inf
         form = "loop" if na >= sweep_below else "sweep"
+        if form == "loop":
+            newton.append({"max_active_bin": m, "active": na, "ms": round(dt * 1e3, 3),
+                           "unconverged_after_pass": inf["unconverged_after_pass"],
+                           "full_build": inf["full_builds"] != last.setdefault("fb", inf["full_builds"])})
+        last["fb"] = inf["full_builds"]
         I_grp["density_" + form] += dd
         I_grp["force_" + form] += df
         e = per_m.setdefault(m, [0, 0.0, 0, 0])
@@ -541,6 +550,7 @@ def run_grf(args):
         "per_bin": [{"max_active_bin": m, "sub_steps": e[0], "mean_active": e[2] / e[0], "mean_ms": e[1] / e[0] * 1e3,
                      "interactions_per_s": e[3] / e[1] if e[1] > 0 else None}
                     for m, e in sorted(per_m.items())],
+        "dense_substeps": newton[:24],
     }
     out["all_active"] = all_active_steps(ctx, p)
     log("all-active steps done")
