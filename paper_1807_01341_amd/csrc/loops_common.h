@@ -103,11 +103,12 @@ __device__ __forceinline__ void kernel_d1_d2(float q, float &wp, float &wpp) {
   wpp = in ? fmaf(36.f, q, -12.f) : (sup ? 12.f * t : 0.f);
 }
 
+// w' alone, zero (signed) from q = 1 on; one select, no branch.
 __device__ __forceinline__ float kernel_dw_only(float q) {
   const float wpi = q * fmaf(18.f, q, -12.f);
-  const float t = 1.f - q;
-  const float wpo = -6.f * t * t;
-  return q < 0.5f ? wpi : (q < 1.f ? wpo : 0.f);
+  const float t = fmaxf(1.f - q, 0.f);
+  const float wpo = -6.f * (t * t);
+  return q < 0.5f ? wpi : wpo;
 }
 
 struct Neu {  // compensated running sum
@@ -142,14 +143,15 @@ __device__ __forceinline__ void wave_sync() {
 
 // Bytes of LDS one wave of the loop kernel uses: per staged candidate its
 // shifted offset and index, its velocity and mass, for the force loops its
-// density-loop state and H; then the per-lane neighbour lists.
+// density-loop state, and H (the force loop keeps H^2 and 1/H); then the
+// per-lane neighbour lists.
 template <int MODE, int CAP, int LCAP>
 struct WaveLds {
   static constexpr bool th = MODE == 1 || MODE == 2;
   static constexpr int cand = CAP * 16;
   static constexpr int candV = CAP * 16;
   static constexpr int candT = th ? CAP * 16 : 0;
-  static constexpr int candH = ModeTraits<MODE>::sym ? CAP * 4 : 0;
+  static constexpr int candH = MODE == 1 ? CAP * 8 : (ModeTraits<MODE>::sym ? CAP * 4 : 0);
   static constexpr int lists = LCAP * 64 * 2;
   static constexpr int bytes = cand + candV + candT + candH + lists;
   static_assert(bytes >= 10 * 64 * 4, "room for the cross-wave reduction");
@@ -177,6 +179,7 @@ __device__ __forceinline__ void chunk_body(const LoopArgs &g, int code, bool cod
   float4 *candV = reinterpret_cast<float4 *>(mine + W::cand);
   float4 *candT = reinterpret_cast<float4 *>(mine + W::cand + W::candV);
   float *candH = reinterpret_cast<float *>(mine + W::cand + W::candV + W::candT);
+  float2 *candH2 = reinterpret_cast<float2 *>(candH);  // force loop: (H^2, 1/H)
   uint16_t *lists = reinterpret_cast<uint16_t *>(mine + W::cand + W::candV + W::candT + W::candH);
   const Chunk ch = g.chunks[cid];
   const bool live = lane < ch.count;
@@ -198,10 +201,10 @@ __device__ __forceinline__ void chunk_body(const LoopArgs &g, int code, bool cod
   const float hi_ = Hi * (1.f / GK32);
 
   // chunk bounding box and reach
-  const float bminx = wave_min_f(live ? pi.x : INFINITY), bmaxx = wave_max_f(live ? pi.x : -INFINITY);
-  const float bminy = wave_min_f(live ? pi.y : INFINITY), bmaxy = wave_max_f(live ? pi.y : -INFINITY);
-  const float bminz = wave_min_f(live ? pi.z : INFINITY), bmaxz = wave_max_f(live ? pi.z : -INFINITY);
-  const float Rc = wave_max_f(live ? Hi : 0.f);
+  const float bminx = wave_min_f_dpp(live ? pi.x : INFINITY), bmaxx = wave_max_f_dpp(live ? pi.x : -INFINITY);
+  const float bminy = wave_min_f_dpp(live ? pi.y : INFINITY), bmaxy = wave_max_f_dpp(live ? pi.y : -INFINITY);
+  const float bminz = wave_min_f_dpp(live ? pi.z : INFINITY), bmaxz = wave_max_f_dpp(live ? pi.z : -INFINITY);
+  const float Rc = wave_max_f_dpp(live ? Hi : 0.f);
   const float R2c = Rc * Rc;
 
   // accumulators: density (w, m w, 3w+qw', m(3w+qw'), div, curl x3); force (a x3, visc, adiab)
@@ -209,14 +212,13 @@ __device__ __forceinline__ void chunk_body(const LoopArgs &g, int code, bool cod
   Neu tot[9];
 #pragma unroll
   for (int q = 0; q < 9; ++q) acc[q] = 0.f;
-  Kahan ka[3];
   float vmax = 0.f;
   int cnt = 0;
   int len = 0;
   int ncand = 0;
 
   auto interact = [&]() {
-    const int maxlen = wave_max_i(len);
+    const int maxlen = wave_max_i_dpp(len);
     // the next list entry is read one step ahead
     int cnext = len > 0 ? lists[lane] : 0;
     for (int t = 0; t < maxlen; ++t) {
@@ -347,8 +349,7 @@ __device__ __forceinline__ void chunk_body(const LoopArgs &g, int code, bool cod
           acc[2] = fmaf(se, dz, fmaf(sv, vz, gzv + acc[2]));
           ++cnt;
         } else {
-          const float Hj = candH[c];
-          const float invHj = __builtin_amdgcn_rcpf(Hj);
+          const float invHj = candH2[c].y;
           const float4 th = candT[c];
           const float wpi = kernel_dw_only(r * invHi);
           const float wpj = kernel_dw_only(r * invHj);
@@ -361,15 +362,9 @@ __device__ __forceinline__ void chunk_body(const LoopArgs &g, int code, bool cod
           const float Pi = -g.half_alpha * vsig * mu * (thi.w + th.w) * __builtin_amdgcn_rcpf(thi.x + th.x);
           const float gbar = 0.5f * (Fi + Fj);
           const float coef = mj * fmaf(thi.y, Fi, fmaf(th.y, Fj, Pi * gbar));
-          if (COMP) {
-            ka[0].add(-coef * dx);
-            ka[1].add(-coef * dy);
-            ka[2].add(-coef * dz);
-          } else {
-            acc[0] = fmaf(-coef, dx, acc[0]);
-            acc[1] = fmaf(-coef, dy, acc[1]);
-            acc[2] = fmaf(-coef, dz, acc[2]);
-          }
+          acc[0] = fmaf(-coef, dx, acc[0]);
+          acc[1] = fmaf(-coef, dy, acc[1]);
+          acc[2] = fmaf(-coef, dz, acc[2]);
           acc[3] = fmaf(mj * Pi * vr, gbar, acc[3]);
           acc[4] = fmaf(mj * vr, Fi, acc[4]);
           ++cnt;
@@ -401,11 +396,13 @@ __device__ __forceinline__ void chunk_body(const LoopArgs &g, int code, bool cod
     wave_sync();
     if (nlive < FB) {
       for (int b0 = 0; b0 < ncand; b0 += FB) {
-        if (wave_max_i(len) > LCAP - FB) interact();
+        if (__ballot(len > LCAP - FB)) interact();
         const int c = b0 + lane;
         const bool cv = lane < FB && c < ncand;
         const float4 cj = cv ? cand[c] : make_float4(0.f, 0.f, 0.f, 0.f);
-        const float Hj = (ModeTraits<MODE>::sym && cv) ? candH[c] : 0.f;
+        float H2j = 0.f;
+        if (MODE == 1 && cv) H2j = candH2[c].x;
+        if (MODE != 1 && ModeTraits<MODE>::sym && cv) H2j = candH[c] * candH[c];
         const int jj = __float_as_int(cj.w);
         for (int ii = 0; ii < nlive; ++ii) {
           const float xi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pxb), ii));
@@ -418,7 +415,7 @@ __device__ __forceinline__ void chunk_body(const LoopArgs &g, int code, bool cod
           if (!ModeTraits<MODE>::sym)
             hit = cv && r2 < H2;
           else
-            hit = cv && (r2 < H2 || r2 < Hj * Hj) && jj != __builtin_amdgcn_readlane(i, ii);
+            hit = cv && (r2 < H2 || r2 < H2j) && jj != __builtin_amdgcn_readlane(i, ii);
           const uint64_t hm = __ballot(hit);
           if (hm) {
             const int base = __builtin_amdgcn_readlane(len, ii);
@@ -432,23 +429,43 @@ __device__ __forceinline__ void chunk_body(const LoopArgs &g, int code, bool cod
       wave_sync();
       return;
     }
-    for (int b0 = 0; b0 < ncand; b0 += FB) {
-      if (wave_max_i(len) > LCAP - FB) interact();
-      const int bend = min(ncand, b0 + FB);
-      for (int c = b0; c < bend; ++c) {
-        const float4 cj = cand[c];
-        const float dx = pi.x - cj.x, dy = pi.y - cj.y, dz = pi.z - cj.z;
-        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        bool hit;
-        if (!ModeTraits<MODE>::sym) {
-          hit = r2 < H2i;
-        } else {
-          const float Hj = candH[c];
-          hit = live && (r2 < H2i || r2 < Hj * Hj) && __float_as_int(cj.w) != i;
+    const int nc = __builtin_amdgcn_readfirstlane(ncand);
+    for (int b0 = 0; b0 < nc; b0 += FB) {
+      if (__ballot(len > LCAP - FB)) interact();
+      const int bend = min(nc, b0 + FB);
+      for (int c0 = b0; c0 < bend; c0 += 4) {
+        // four candidates per round: their LDS reads are issued together
+        float4 cq[4];
+        float h2q[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int cc = min(c0 + u, bend - 1);
+          cq[u] = cand[cc];
+          h2q[u] = 0.f;
+          if (MODE == 1) h2q[u] = candH2[cc].x;
+          if (MODE != 1 && ModeTraits<MODE>::sym) h2q[u] = candH[cc];
         }
-        if (hit) {
-          lists[len * 64 + lane] = (uint16_t)c;
-          ++len;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int c = c0 + u;
+          if (c < bend) {
+            const float4 cj = cq[u];
+            const float dx = pi.x - cj.x, dy = pi.y - cj.y, dz = pi.z - cj.z;
+            const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+            bool hit;
+            if (!ModeTraits<MODE>::sym) {
+              hit = r2 < H2i;
+            } else if (MODE == 1) {
+              hit = live && r2 < fmaxf(H2i, h2q[u]) && __float_as_int(cj.w) != i;
+            } else {
+              hit = live && (r2 < H2i || r2 < h2q[u] * h2q[u]) && __float_as_int(cj.w) != i;
+            }
+            // branch-free append: the slot past the end is written and kept
+            // only on a hit (len <= LCAP - 1 here: at most LCAP - FB at the
+            // start of the block, at most FB - 1 appends since)
+            lists[len * 64 + lane] = (uint16_t)c;
+            len += hit ? 1 : 0;
+          }
         }
       }
     }
@@ -520,7 +537,10 @@ __device__ __forceinline__ void chunk_body(const LoopArgs &g, int code, bool cod
         cand[slot] = make_float4(xj, yj, zj, __int_as_float(j));
         candV[slot] = vjs;
         if (W::th) candT[slot] = ths;
-        if (ModeTraits<MODE>::sym) candH[slot] = pj.w;
+        if (MODE == 1)
+          candH2[slot] = make_float2(pj.w * pj.w, __builtin_amdgcn_rcpf(pj.w));
+        else if (ModeTraits<MODE>::sym)
+          candH[slot] = pj.w;
       }
       ncand += __popcll(mask);
       if (ncand > CAP - 64) flush();
@@ -534,15 +554,9 @@ __device__ __forceinline__ void chunk_body(const LoopArgs &g, int code, bool cod
 #pragma unroll
     for (int q = 0; q < 9; ++q) res[q] = tot[q].value();
   } else {
-    if (COMP) {
-      res[0] = ka[0].s - ka[0].c + tot[0].value();
-      res[1] = ka[1].s - ka[1].c + tot[1].value();
-      res[2] = ka[2].s - ka[2].c + tot[2].value();
-    } else {
-      res[0] = tot[0].value();
-      res[1] = tot[1].value();
-      res[2] = tot[2].value();
-    }
+    res[0] = tot[0].value();
+    res[1] = tot[1].value();
+    res[2] = tot[2].value();
     res[3] = tot[3].value();
     res[4] = tot[4].value();
     res[5] = vmax;
@@ -639,7 +653,7 @@ __device__ __forceinline__ void chunk_body(const LoopArgs &g, int code, bool cod
     }
   }
   if (MODE == 1) {
-    const int tot_cnt = wave_sum_i(live ? cnt : 0);
+    const int tot_cnt = wave_sum_i_dpp(live ? cnt : 0);
     if (lane == 0) atomicAdd(g.ctr, (unsigned long long)tot_cnt);
   }
 }

@@ -2,6 +2,8 @@
 // shared device helpers and the host launchers of every kernel file.
 #pragma once
 
+#include <limits.h>
+
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -410,6 +412,45 @@ __device__ __forceinline__ void pack_one(const PackArgs &a, int64_t s) {
 
 __device__ __forceinline__ int rank_below(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Wave-wide scans and reductions on the DPP lane network (VALU only, no
+// LDS round trips): Hillis-Steele shifts by 1, 2, 4, 8 lanes inside each row
+// of 16, then lane 15 of rows 0 and 2 into rows 1 and 3, then lane 31 into
+// rows 2 and 3.  Lanes without a source take the identity `id`.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_from(int id, int v) {
+  return __builtin_amdgcn_update_dpp(id, v, CTRL, ROWS, 0xf, false);
+}
+template <class F>
+__device__ __forceinline__ int wave_scan_bits(int v, int id, F op) {
+  v = op(v, dpp_from<0x111, 0xf>(id, v));  // row_shr:1
+  v = op(v, dpp_from<0x112, 0xf>(id, v));  // row_shr:2
+  v = op(v, dpp_from<0x114, 0xf>(id, v));  // row_shr:4
+  v = op(v, dpp_from<0x118, 0xf>(id, v));  // row_shr:8
+  v = op(v, dpp_from<0x142, 0xa>(id, v));  // row_bcast:15 into rows 1, 3
+  v = op(v, dpp_from<0x143, 0xc>(id, v));  // row_bcast:31 into rows 2, 3
+  return v;
+}
+// Inclusive prefix sum over the lanes.
+__device__ __forceinline__ int wave_incl_scan_dpp(int v) {
+  return wave_scan_bits(v, 0, [](int a, int b) { return a + b; });
+}
+__device__ __forceinline__ int wave_last(int v) { return __builtin_amdgcn_readlane(v, 63); }
+// Reductions to every lane; the DPP forms need all 64 lanes active.
+__device__ __forceinline__ float wave_max_f_dpp(float v) {
+  const int s = wave_scan_bits(__float_as_int(v), __float_as_int(-INFINITY),
+                               [](int a, int b) { return __float_as_int(fmaxf(__int_as_float(a), __int_as_float(b))); });
+  return __int_as_float(wave_last(s));
+}
+__device__ __forceinline__ float wave_min_f_dpp(float v) {
+  const int s = wave_scan_bits(__float_as_int(v), __float_as_int(INFINITY),
+                               [](int a, int b) { return __float_as_int(fminf(__int_as_float(a), __int_as_float(b))); });
+  return __int_as_float(wave_last(s));
+}
+__device__ __forceinline__ int wave_sum_i_dpp(int v) { return wave_last(wave_incl_scan_dpp(v)); }
+__device__ __forceinline__ int wave_max_i_dpp(int v) {
+  return wave_last(wave_scan_bits(v, INT_MIN, [](int a, int b) { return max(a, b); }));
 }
 
 __device__ __forceinline__ float wave_max_f(float v) {
