@@ -335,7 +335,19 @@ def loop_kwargs(args):
     return kw
 
 
-def grf_setup(sg, ic, lazy, kw, tune_file=None, n_bins=None):
+def fixed_tiling_file(tiling):
+    """A tuning table that gives every pass of both loops the tiling
+    "NW,TILE" (waves per chunk, tile class), Morton order, grid launch."""
+    nw, tile = (int(v) for v in tiling.split(","))
+    path = os.path.join(tempfile.gettempdir(), f"sph_tiling_{nw}_{tile}.txt")
+    with open(path, "w") as f:
+        for loop in (0, 1):
+            for cls in range(32):
+                f.write(f"best {loop} {cls} {nw} {tile} 0 0 0 0 0\n")
+    return path
+
+
+def grf_setup(sg, ic, lazy, kw, tune_file=None, n_bins=None, tiling=None):
     """Context and particles of the large share, after an all-active density
     + force pass (u the thermal input), the loop tuning on those chunks, the
     t_min of Eq. 1 (the smallest time-step of the converged state, so every
@@ -355,7 +367,9 @@ def grf_setup(sg, ic, lazy, kw, tune_file=None, n_bins=None):
     ctx.mark_active(p, top)
     ctx.density_pass(p, entropy_from_u=True)
     ctx.force_pass(p)
-    if tune_file is not False:
+    if tiling:
+        ctx.load_tuning(fixed_tiling_file(tiling))
+    elif tune_file is not False:
         if tune_file and os.path.exists(tune_file):
             os.remove(tune_file)
         ctx.autotune(p, tune_file or None)
@@ -365,6 +379,38 @@ def grf_setup(sg, ic, lazy, kw, tune_file=None, n_bins=None):
     ctx.kick_drift(p, 0, t_min, 1, True)
     ctx.sync()
     return ctx, p, t_min
+
+
+class TimeLine:
+    """The individual-time-step time line of one context after grf_setup
+    (whose kick_drift at t = 0 moved the line to 1): advance(n) moves the line
+    on by n units of t_min, taking a step at each time some particle is
+    active (Sec. II-A) and none at the times in between -- the step at tn runs
+    with no drift, then sph_drift moves the line on to the next active time."""
+
+    def __init__(self, ctx, p, t_min):
+        self.ctx, self.p, self.t_min = ctx, p, t_min
+        self.top = ctx.params.n_bins - 1
+        self.t, self.line, self.end, self.stepped = 0, 1, 0, 0
+
+    def advance(self, n, per_sub=None):
+        self.end += n
+        while True:
+            tn = self.ctx.next_active_time(self.p, self.t)
+            if tn > self.end:
+                return
+            if tn > self.line:
+                self.ctx.drift(self.p, self.t_min, tn - self.line)
+            m = min(ctz(tn), self.top)
+            self.t = self.line = tn
+            self.stepped += 1
+            if per_sub is None:
+                self.ctx.step(self.p, m, tn, self.t_min, 0, False)
+            else:
+                ts = time.perf_counter()
+                na = self.ctx.step(self.p, m, tn, self.t_min, 0, False, want_count=True)
+                self.ctx.sync()
+                per_sub(m, na, time.perf_counter() - ts)
 
 
 def all_active_steps(ctx, p, reps=3):
@@ -401,8 +447,10 @@ def all_active_steps(ctx, p, reps=3):
 
 
 def run_grf(args):
-    """The default line: top-level steps of the 2^13 sub-step hierarchy on the
-    16,777,216-particle share."""
+    """The default line: the 2^13-sub-step hierarchy on the 16,777,216-particle
+    share, one benchmark step = `--substeps` consecutive sub-steps (2048: 20
+    timed steps are exactly five top-level periods), then one whole period
+    with a synchronisation after every sub-step for the per-bin table."""
     import torch
 
     import ics
@@ -414,25 +462,15 @@ def run_grf(args):
     log(f"generated {N} particles in {time.perf_counter() - tg:.0f} s")
     lazy = not args.drift_all
     ctx, p, t_min = grf_setup(sg, ic, lazy, loop_kwargs(args),
-                              tune_file=False if args.no_tune else args.tune_file)
+                              tune_file=False if args.no_tune else args.tune_file, tiling=args.tiling)
     top = ctx.params.n_bins - 1
     S = args.substeps
     sweep_below = ctx.params.sweep_below
     log(f"setup done: t_min {t_min:.4e}")
-    clock = {"t": 0}
+    line = TimeLine(ctx, p, t_min)
 
-    def top_step(per_sub=None):
-        for _ in range(S):
-            clock["t"] += 1
-            t = clock["t"]
-            m = min(ctz(t), top)
-            if per_sub is None:
-                ctx.step(p, m, t, t_min, 1, False)
-            else:
-                ts = time.perf_counter()
-                na = ctx.step(p, m, t, t_min, 1, False, want_count=True)
-                ctx.sync()
-                per_sub(m, na, time.perf_counter() - ts)
+    def top_step(per_sub=None, n_sub=S):
+        line.advance(n_sub, per_sub)
 
     for w in range(args.warmup):
         tw = time.perf_counter()
@@ -441,6 +479,7 @@ def run_grf(args):
         log(f"warm-up step {w + 1}/{args.warmup}: {time.perf_counter() - tw:.2f} s")
     torch.cuda.synchronize()
     i0 = ctx.info()
+    stepped0 = line.stepped
     t0 = time.perf_counter()
     for k in range(args.steps):
         top_step()
@@ -448,13 +487,14 @@ def run_grf(args):
         log(f"timed step {k + 1}/{args.steps}: {time.perf_counter() - t0:.2f} s so far")
     t1 = time.perf_counter()
     i1 = ctx.info()
+    stepped_timed = line.stepped - stepped0
     wall = t1 - t0
     I_d = i1["interactions_density"] - i0["interactions_density"]
     I_f = i1["interactions_force"] - i0["interactions_force"]
     value = (I_d + I_f) / wall
 
-    # one more top-level step with HIP events around every launch group and a
-    # synchronisation after each sub-step (per-bin times, interactions per
+    # one more top-level period with HIP events around every launch group and
+    # a synchronisation after each sub-step (per-bin times, interactions per
     # loop form)
     per_m = {}
     I_grp = {"density_loop": 0, "density_sweep": 0, "force_loop": 0, "force_sweep": 0}
@@ -481,15 +521,22 @@ def run_grf(args):
         e[2] += na
         e[3] += dd + df
 
+    # one whole period (bins 0..13 each at its own rate), from a period boundary
+    period = 1 << top
+    top_step(None, (-line.end) % period)
+    stepped_p = line.stepped
+    torch.cuda.synchronize()
+    last["i"] = ctx.info()
+    last["fb"] = last["i"]["full_builds"]
     ctx.profile(True)
     tp = time.perf_counter()
-    top_step(per_sub)
+    top_step(per_sub, period)
     torch.cuda.synchronize()
     prof_wall = time.perf_counter() - tp
     prof = ctx.profile_read()
     ctx.profile(False)
-    log(f"profiled step: {prof_wall:.2f} s")
-    kernels = {k: {"launches": c, "ms_total": round(ms, 3), "ms_per_step": round(ms, 3)}
+    log(f"profiled period: {prof_wall:.2f} s")
+    kernels = {k: {"launches": c, "ms_per_period": round(ms, 3)}
                for k, (c, ms) in sorted(prof.items(), key=lambda kv: -kv[1][1])}
     groups = {}
     for name, flop in (("density_loop", FLOP_DENSITY), ("density_sweep", FLOP_DENSITY),
@@ -532,22 +579,26 @@ def run_grf(args):
         "data": "synthetic",
         "config": {"workload": f"large single-GPU share: {N} particles (256^3 lattice displaced by the Zel'dovich "
                                f"field of a Gaussian random field, P(k)~k^-2.5, rms {args.grf_amplitude} spacings; "
-                               f"u log-uniform 1e-2..1e2; 14 time-bins); one step = one top-level step of "
-                               f"{S} sub-steps t with max active bin min(ctz(t),13)",
+                               f"u adiabatic with log-normal scatter, 2% of the particles in 16 Plummer clumps; 14 time-bins); one step "
+                               f"= {S} units t_min of the time line (a quarter of the 2^13 period), stepped at "
+                               f"each time t some bin is active (max active bin min(ctz(t),13))",
                    "n_particles": N, "substeps_per_step": S,
                    "drift": "lazy (only the particles a sub-step needs)" if lazy else "every particle each sub-step"},
         "interactions": I_d + I_f,
         "interactions_density": I_d,
         "interactions_force": I_f,
         "fp32_peak_frac_step": (FLOP_DENSITY * I_d + FLOP_FORCE * I_f) / wall / FP32_PEAK,
+        "times_stepped_timed": stepped_timed,
+        "times_on_line_timed": args.steps * S,
         "full_builds_timed": i1["full_builds"] - i0["full_builds"],
         "cell_updates_timed": i1["cell_updates"] - i0["cell_updates"],
         "t_min": t_min,
         "roofline": roof,
         "loop_groups": groups,
-        "profiled_step_s": prof_wall,
+        "profiled_period_s": prof_wall,
+        "profiled_period_times_stepped": line.stepped - stepped_p,
         "kernels": kernels,
-        "per_bin": [{"max_active_bin": m, "sub_steps": e[0], "mean_active": e[2] / e[0], "mean_ms": e[1] / e[0] * 1e3,
+        "per_bin": [{"max_active_bin": m, "steps_taken": e[0], "mean_active": e[2] / e[0], "mean_ms": e[1] / e[0] * 1e3,
                      "interactions_per_s": e[3] / e[1] if e[1] > 0 else None}
                     for m, e in sorted(per_m.items())],
         "dense_substeps": newton[:24],
@@ -578,7 +629,7 @@ def run_all_active(args):
     ic = ics.grf_zeldovich(amplitude=args.grf_amplitude)
     log(f"generated {ic['x'].shape[0]} particles")
     ctx, p, t_min = grf_setup(sg, ic, not args.drift_all, loop_kwargs(args),
-                              tune_file=False if args.no_tune else args.tune_file)
+                              tune_file=False if args.no_tune else args.tune_file, tiling=args.tiling)
     out = all_active_steps(ctx, p, reps=max(1, args.steps))
     out["workload"] = f"large share {ic['x'].shape[0]} particles, all active"
     print(json.dumps(out))
@@ -586,10 +637,11 @@ def run_all_active(args):
 
 def run_strategies(args):
     """The strategy comparison of the paper's Fig. 2 on the large share: one
-    top-level step with every particle drifted each sub-step, one with only
-    the needed particles drifted, and the global step (every particle active
-    every sub-step at t_min: n_bins = 1), the last extrapolated from a few
-    sub-steps to the same 2^13."""
+    2^13 period of the time line with every particle drifted at each step,
+    one with only the needed particles drifted (both stepping only at times
+    some bin is active), and the global step (every particle active at every
+    time t_min: n_bins = 1), the last extrapolated from a few steps to the
+    same 2^13."""
     import torch
 
     import ics
@@ -597,21 +649,22 @@ def run_strategies(args):
     sg.require_device()
     ic = ics.grf_zeldovich(amplitude=args.grf_amplitude)
     N = ic["x"].shape[0]
-    S = args.substeps
     res = {}
+    S = None
     for name, lazy in (("relevant_only_drift", True), ("drift_all_kick_active", False)):
         ctx, p, t_min = grf_setup(sg, ic, lazy, loop_kwargs(args), tune_file=None)
-        top = ctx.params.n_bins - 1
+        S = 1 << (ctx.params.n_bins - 1)
+        line = TimeLine(ctx, p, t_min)
         i0 = ctx.info()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for t in range(1, S + 1):
-            ctx.step(p, min(ctz(t), top), t, t_min, 1, False)
+        line.advance(S)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         i1 = ctx.info()
         I = i1["interactions_density"] + i1["interactions_force"] - i0["interactions_density"] - i0["interactions_force"]
-        res[name] = {"seconds": wall, "interactions": I, "interactions_per_s": I / wall, "t_min": t_min}
+        res[name] = {"seconds": wall, "interactions": I, "interactions_per_s": I / wall, "t_min": t_min,
+                     "times_stepped": line.stepped}
         log(f"{name}: {wall:.2f} s")
         del ctx, p
         torch.cuda.empty_cache()
@@ -818,7 +871,9 @@ def main():
     ap.add_argument("--steps", type=int, default=2, help="timed steps (large share: top-level steps)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", choices=("grf", "clustered", "strategies", "allactive"), default="grf")
-    ap.add_argument("--substeps", type=int, default=8192, help="sub-steps of one top-level step (2^13)")
+    ap.add_argument("--substeps", type=int, default=2048,
+                    help="sub-steps per benchmark step (a divisor of the 2^13-sub-step period: K steps with K a "
+                         "multiple of 8192/substeps cover whole periods, every bin in its exact proportion)")
     ap.add_argument("--global-substeps", type=int, default=16,
                     help="strategies: sub-steps timed for the global-step arm")
     ap.add_argument("--grf-amplitude", type=float, default=12.0)
@@ -834,6 +889,8 @@ def main():
     ap.add_argument("--sweep-below", type=int, default=None)
     ap.add_argument("--sweep-waves", type=int, default=None)
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--tiling", default=None,
+                    help="large share: 'NW,TILE' for every loop pass instead of the autotuner's choice")
     ap.add_argument("--load-tune", default=None, help="clustered: load a tuning file instead of tuning")
     ap.add_argument("--tune-file", default=os.path.join(tempfile.gettempdir(), "sph_tuning_grf.txt"))
     ap.add_argument("--tune-file-clustered", default=os.path.join(tempfile.gettempdir(), "sph_tuning_clustered.txt"))

@@ -333,6 +333,30 @@ sph_status sph_step_noalloc(const sph_params *p, void *hip_stream, sph_particles
                             int64_t ti, double t_min, int64_t drift_int, int first_step,
                             int64_t *scratch_used_host, char *err, size_t err_cap);
 
+/* Moves the time line on by drift_int units of t_min with no kick: the
+ * times passed over are ones at which no particle is active (Sec. II-A), so
+ * the step there would only drift.  With lazy_drift only the line moves
+ * (the particles follow when a step needs them); without it every particle
+ * drifts as in sph_kick_drift (x by the kicked velocity, v, A and h
+ * predicted).  Allowed after a build and the step's sph_kick_drift (before
+ * the next build_cells); SPH_ESTATE otherwise, SPH_EINVAL for t_min <= 0,
+ * drift_int < 0 or a missing array.  No synchronisation. */
+sph_status sph_drift(sph_ctx *ctx, sph_particles *p, double t_min, int64_t drift_int);
+
+/* The first time after ti, in units of t_min, at which some particle is
+ * active (Sec. II-A: a particle in time-bin b is active at the multiples of
+ * 2^b, so this is the next multiple of 2^b_min, b_min the smallest bin of
+ * p->time_bin over the context's particles; for a batch context, the
+ * earliest over the boxes).  A caller that advances the time line from step
+ * to step takes no step at the times in between, where nothing is active,
+ * and moves the time line there (drift_int = *ti_next - ti, in the step's
+ * kick_drift or with sph_drift).  Reads
+ * p->time_bin (device, int8, length n of the last build_cells, cell order);
+ * changes nothing.  SPH_EINVAL for a null argument or ti < 0, SPH_ESTATE
+ * before the first build_cells or if a bin is outside [0, n_bins).
+ * Synchronises the stream once. */
+sph_status sph_next_active_time(sph_ctx *ctx, const sph_particles *p, int64_t ti, int64_t *ti_next);
+
 /* With lazy_drift: drifts every particle still behind the time line to it
  * (x, v, A, h and the derived offsets), e.g. before the caller reads the
  * state of all particles.  Without lazy_drift, or before the first build,

@@ -378,6 +378,22 @@ def max_active_bin(t_int: int, n_bins=14):
     return min((t & -t).bit_length() - 1, n_bins - 1)
 
 
+def next_active_time(bins, t_int: int, n_bins=14):
+    """The first integer time after t_int (units of t_min) at which some
+    particle is active (Sec. II-A): the times are visited one by one from
+    t_int + 1 and the first with bin_i <= max_active_bin(t) for some i is
+    returned.  The times passed over have no active particle, so a step
+    there would change nothing."""
+    b = np.asarray(bins, np.int64)
+    if b.size == 0:
+        raise ValueError("next_active_time: no particles")
+    bmin = int(b.min())
+    t = int(t_int) + 1
+    while max_active_bin(t, n_bins) < bmin:
+        t += 1
+    return t
+
+
 # --------------------------------------------------------------------------
 # One full plain step (all the loops of Fig. 5 for the active set)
 # --------------------------------------------------------------------------

@@ -130,6 +130,8 @@ def lib():
             "sph_kick_drift": (i32, [vp, vp, i64, C.c_double, i64, i32]),
             "sph_step": (i32, [vp, vp, i64, vp, i32, vp, i32, i64, C.c_double, i64, i32]),
             "sph_drift_all": (i32, [vp, vp]),
+            "sph_next_active_time": (i32, [vp, vp, i64, vp]),
+            "sph_drift": (i32, [vp, vp, C.c_double, i64]),
             "sph_sync": (i32, [vp]),
             "sph_last_error": (C.c_char_p, [vp]),
             "sph_info": (i32, [vp, vp]),
@@ -162,7 +164,7 @@ def exported_symbols():
             "sph_copy_active", "sph_copy_pairs", "sph_profile", "sph_profile_read", "sph_autotune",
             "sph_load_tuning", "sph_adjoint", "sph_batch_density_pass", "sph_batch_force_pass",
             "sph_batch_autotune", "sph_step", "sph_drift_all", "sph_batch_create", "sph_batch_mark_active",
-            "sph_batch_density_force", "sph_batch_box", "sph_step_noalloc"]
+            "sph_batch_density_force", "sph_batch_box", "sph_step_noalloc", "sph_next_active_time", "sph_drift"]
 
 
 def require_device():
@@ -355,6 +357,17 @@ class Context:
                                    C.byref(n) if want_count else None, int(bool(entropy_from_u)), int(ti),
                                    float(t_min), int(drift_int), int(bool(first_step))))
         return n.value
+
+    def next_active_time(self, p: Particles, ti: int) -> int:
+        """First time after ti (units of t_min) at which some particle is
+        active: the next multiple of 2^(smallest time-bin)."""
+        out = C.c_int64(-1)
+        self._check(lib().sph_next_active_time(self.h, self._pcs(p, changes=False), int(ti), C.byref(out)))
+        return out.value
+
+    def drift(self, p: Particles, t_min: float, drift_int: int):
+        """Move the time line on by drift_int units of t_min with no kick."""
+        return self._check(lib().sph_drift(self.h, self._pcs(p), float(t_min), int(drift_int)))
 
     def drift_all(self, p: Particles):
         """With lazy drift: bring every particle to the current time."""

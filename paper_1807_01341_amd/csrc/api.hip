@@ -402,6 +402,38 @@ sph_status sph_step(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *perm_out
   return sph_kick_drift(ctx, p, ti, t_min, drift_int, first_step);
 }
 
+sph_status sph_drift(sph_ctx *ctx, sph_particles *p, double t_min, int64_t drift_int) {
+  if (!ctx) return SPH_EINVAL;
+  if (!p) return sph_fail(ctx, SPH_EINVAL, "drift: null particles");
+  if (is_batch(ctx)) {
+    std::vector<sph_particles> sl = box_slices(ctx, p);
+    for (size_t b = 0; b < ctx->kids.size(); ++b)
+      SPH_TRY(box_fail(ctx, b, sph_drift(ctx->kids[b], &sl[b], t_min, drift_int)));
+    return SPH_OK;
+  }
+  if (ctx->n_full_builds == 0 || ctx->state != 0)
+    return sph_fail(ctx, SPH_ESTATE, "drift: only after a build and the step's kick_drift (state %d)", ctx->state);
+  return drift_impl(ctx, p, t_min, drift_int);
+}
+
+sph_status sph_next_active_time(sph_ctx *ctx, const sph_particles *p, int64_t ti, int64_t *ti_next) {
+  if (!ctx) return SPH_EINVAL;
+  if (!p || !p->time_bin || !ti_next || ti < 0)
+    return sph_fail(ctx, SPH_EINVAL, "next_active_time: null argument or ti < 0");
+  if (is_batch(ctx)) {
+    std::vector<sph_particles> sl = box_slices(ctx, p);
+    int64_t best = INT64_MAX;
+    for (size_t b = 0; b < ctx->kids.size(); ++b) {
+      int64_t t = 0;
+      SPH_TRY(box_fail(ctx, b, next_active_impl(ctx->kids[b], sl[b].time_bin, ctx->kids[b]->n, ti, &t)));
+      best = std::min(best, t);
+    }
+    *ti_next = best;
+    return SPH_OK;
+  }
+  return next_active_impl(ctx, p->time_bin, ctx->n, ti, ti_next);
+}
+
 sph_status sph_drift_all(sph_ctx *ctx, sph_particles *p) {
   if (!ctx) return SPH_EINVAL;
   if (is_batch(ctx)) return SPH_OK;  // batch contexts drift every particle in kick_drift

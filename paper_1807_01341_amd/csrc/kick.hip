@@ -1,5 +1,6 @@
 // Kick-drift-kick with individual power-of-two time-steps (Sec. II-A, Eq. 1,
 // Eq. 2).  FP64 for positions and velocities.
+#include <limits.h>
 #include <math.h>
 
 #include <algorithm>
@@ -16,6 +17,7 @@ struct KickArgs {
   int64_t ti, drift_int;
   double t_min, L, cfl;
   int n_bins, first, ctz_ti;
+  int kick;  // 0: drift only (no particle is active)
 };
 
 __device__ __forceinline__ double wrap_box_k(double x, double L) {
@@ -33,7 +35,7 @@ __global__ __launch_bounds__(256) void kick_drift_kernel(KickArgs g) {
     double vf0 = g.vfx[s], vf1 = g.vfy[s], vf2 = g.vfz[s];
     double v0 = g.vx[s], v1 = g.vy[s], v2 = g.vz[s];
     double Af = g.Af[s], A = g.A[s];
-    if (g.active[s]) {
+    if (g.kick && g.active[s]) {
       if (!g.first) {
         // closing half-kick of the step that ends now
         const double h0 = 0.5 * ldexp(g.t_min, (int)g.bin[s]);
@@ -127,12 +129,13 @@ __global__ __launch_bounds__(256) void kick_active_kernel(KickArgs g, const int3
   }
 }
 
-sph_status kick_drift_impl(sph_ctx *ctx, sph_particles *p, int64_t ti, double t_min, int64_t drift_int,
-                           int first_step) {
-  if (!p->x || !p->y || !p->z || !p->vx || !p->vy || !p->vz || !p->vfx || !p->vfy || !p->vfz || !p->A || !p->Af ||
-      !p->ax || !p->ay || !p->az || !p->dA_dt || !p->h || !p->vsig || !p->time_bin)
-    return sph_fail(ctx, SPH_EINVAL, "kick_drift: a state array is missing");
-  if (!(t_min > 0.0) || drift_int < 0 || ti < 0) return sph_fail(ctx, SPH_EINVAL, "kick_drift: bad time arguments");
+static bool kick_arrays_present(const sph_particles *p) {
+  return p->x && p->y && p->z && p->vx && p->vy && p->vz && p->vfx && p->vfy && p->vfz && p->A && p->Af && p->ax &&
+         p->ay && p->az && p->dA_dt && p->h && p->vsig && p->time_bin;
+}
+
+static KickArgs kick_args(sph_ctx *ctx, sph_particles *p, int64_t ti, double t_min, int64_t drift_int,
+                          int first_step) {
   KickArgs g;
   g.n = ctx->n;
   g.x = p->x; g.y = p->y; g.z = p->z;
@@ -151,6 +154,15 @@ sph_status kick_drift_impl(sph_ctx *ctx, sph_particles *p, int64_t ti, double t_
   g.n_bins = ctx->prm.n_bins;
   g.first = first_step;
   g.ctz_ti = ti != 0 ? __builtin_ctzll((unsigned long long)ti) : 0;
+  g.kick = 1;
+  return g;
+}
+
+sph_status kick_drift_impl(sph_ctx *ctx, sph_particles *p, int64_t ti, double t_min, int64_t drift_int,
+                           int first_step) {
+  if (!kick_arrays_present(p)) return sph_fail(ctx, SPH_EINVAL, "kick_drift: a state array is missing");
+  if (!(t_min > 0.0) || drift_int < 0 || ti < 0) return sph_fail(ctx, SPH_EINVAL, "kick_drift: bad time arguments");
+  KickArgs g = kick_args(ctx, p, ti, t_min, drift_int, first_step);
   if (ctx->prm.lazy_drift) {
     // the time line advances; drifts happen when steps need them
     if (ctx->t_min_line != 0.0 && t_min != ctx->t_min_line)
@@ -175,5 +187,68 @@ sph_status kick_drift_impl(sph_ctx *ctx, sph_particles *p, int64_t ti, double t_
   }
   HIP_TRY(ctx, hipGetLastError());
   ctx->state = 0;
+  return SPH_OK;
+}
+
+// Drift with no kick: the time line moves on by drift_int units of t_min
+// over times at which no particle is active.  With lazy drift only the line
+// moves (drifts happen when steps need them); else every particle drifts.
+sph_status drift_impl(sph_ctx *ctx, sph_particles *p, double t_min, int64_t drift_int) {
+  if (!kick_arrays_present(p)) return sph_fail(ctx, SPH_EINVAL, "drift: a state array is missing");
+  if (!(t_min > 0.0) || drift_int < 0) return sph_fail(ctx, SPH_EINVAL, "drift: bad time arguments");
+  if (ctx->prm.lazy_drift) {
+    if (ctx->t_min_line != 0.0 && t_min != ctx->t_min_line)
+      return sph_fail(ctx, SPH_EINVAL, "drift: lazy drift needs one t_min for the whole time line");
+    ctx->t_min_line = t_min;
+    ctx->ti_now += drift_int;
+    return SPH_OK;
+  }
+  if (drift_int == 0) return SPH_OK;
+  KickArgs g = kick_args(ctx, p, 0, t_min, drift_int, 0);
+  g.kick = 0;
+  g.active = nullptr;
+  int64_t grid = ceil_div(g.n, 256);
+  if (grid > 8192) grid = 8192;
+  {
+    PROF(ctx, "drift");
+    kick_drift_kernel<<<(unsigned)grid, 256, 0, ctx->stream>>>(g);
+  }
+  HIP_TRY(ctx, hipGetLastError());
+  return SPH_OK;
+}
+
+// ---------------------------------------------------------------- next active time
+//
+// A particle in bin b is active at the multiples of 2^b (Sec. II-A), so the
+// first time after ti at which anything is active is the next multiple of
+// 2^b_min, b_min the smallest bin any particle holds; the times in between
+// have no active particle and take no step.
+
+__global__ __launch_bounds__(64) void set_i32_kernel(int32_t *__restrict__ p, int32_t v) {
+  if (threadIdx.x == 0) p[0] = v;
+}
+
+__global__ __launch_bounds__(256) void min_bin_kernel(const int8_t *__restrict__ bin, int64_t n,
+                                                      int32_t *__restrict__ out) {
+  int m = INT_MAX;
+  for (int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x; s < n; s += (int64_t)gridDim.x * 256)
+    m = min(m, (int)bin[s]);
+  for (int o = 32; o > 0; o >>= 1) m = min(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) atomicMin(out, m);
+}
+
+sph_status next_active_impl(sph_ctx *ctx, const int8_t *bin, int64_t n, int64_t ti, int64_t *ti_next) {
+  if (n <= 0) return sph_fail(ctx, SPH_ESTATE, "next_active_time: no particles (build_cells first)");
+  int32_t *slot = (int32_t *)ctx->scalars.p + SC_MINBIN;
+  set_i32_kernel<<<1, 64, 0, ctx->stream>>>(slot, INT_MAX);
+  const int64_t grid = std::min<int64_t>(ceil_div(n, 256), 2048);
+  min_bin_kernel<<<(unsigned)grid, 256, 0, ctx->stream>>>(bin, n, slot);
+  HIP_TRY(ctx, hipGetLastError());
+  int32_t b = 0;
+  SPH_TRY(read_scalars(ctx, SC_MINBIN, 1, &b));
+  if (b < 0 || b >= ctx->prm.n_bins)
+    return sph_fail(ctx, SPH_ESTATE, "next_active_time: a time-bin outside [0, %d)", ctx->prm.n_bins);
+  const int64_t period = (int64_t)1 << b;
+  *ti_next = (ti / period + 1) * period;
   return SPH_OK;
 }

@@ -190,9 +190,17 @@ unsigned grid_for_items(int64_t n) {
 // one exists, else a rule that keeps enough waves in flight.
 LoopConfig choose_config(sph_ctx *ctx, int mode) {
   const int cls = tune_class(ctx->n_chunks);
-  const auto &t = ctx->tune[mode][cls];
+  // the pass's own chunk-count class, else the nearest tuned class within a
+  // factor of four in chunks (a time-stepping run tunes on one pass; its
+  // partly active dense steps fall in the classes next to it)
+  int tc = -1;
+  for (int d = 0; d <= 2 && tc < 0; ++d) {
+    if (cls + d < 32 && ctx->tune[mode][cls + d].valid) tc = cls + d;
+    else if (cls - d >= 0 && ctx->tune[mode][cls - d].valid) tc = cls - d;
+  }
   LoopConfig c;
-  if (t.valid) {
+  if (tc >= 0) {
+    const auto &t = ctx->tune[mode][tc];
     c.nw = t.nw;
     c.tile = t.tile;
     c.ordered = t.ordered;
@@ -218,7 +226,9 @@ LoopConfig choose_config(sph_ctx *ctx, int mode) {
   } else if (nc < 32768) {
     c.nw = 2, c.tile = 2;
   } else {
-    c.nw = 1, c.tile = 2;
+    // dense passes: the loop is bound by instruction issue, and the smallest
+    // tile keeps the most waves resident
+    c.nw = 1, c.tile = 0;
   }
   return c;
 }

@@ -326,6 +326,7 @@ enum ScalarSlot {
   SC_UPD_FLAG = 15,
   SC_UPD_FLAG_ACC = 16,  // the rebuild flag as the update kernel raises it (moved to SC_UPD_FLAG and
                          // cleared by the reduction, so that it starts at zero for the next update)
+  SC_MINBIN = 17,     // next_active_time: smallest time-bin held
   SC_COUNT = 32
 };
 
@@ -392,6 +393,9 @@ sph_status adjoint_impl(sph_ctx *ctx, sph_particles *p, const float *wx, const f
                         double *gx, double *gy, double *gz, float *gu);
 sph_status kick_drift_impl(sph_ctx *ctx, sph_particles *p, int64_t ti, double t_min, int64_t drift_int,
                            int first_step);
+sph_status drift_impl(sph_ctx *ctx, sph_particles *p, double t_min, int64_t drift_int);
+// First time after ti at which some particle of bin[0..n) is active.
+sph_status next_active_impl(sph_ctx *ctx, const int8_t *bin, int64_t n, int64_t ti, int64_t *ti_next);
 
 // ---------------------------------------------------------------- device helpers
 __device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }

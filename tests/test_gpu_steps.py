@@ -238,3 +238,70 @@ def test_individual_steps_kick_drift_vs_oracle(gpu_lib, lazy):
     assert err["x"] < 1e-12 and err["v"] < 1e-12 and err["vf"] < 1e-12
     tol32 = 17 * 2.0 ** -23
     assert err["A"] < tol32 and err["Af"] < tol32 and err["h"] < tol32
+
+
+@pytest.mark.parametrize("lazy", [0, 1])
+def test_drift_over_inactive_times_equals_drift_in_the_step(gpu_lib, lazy):
+    """Steps taken only at the times some particle is active (Sec. II-A):
+    each step's kick_drift moving the time line on to the next active time
+    equals, bit for bit, the step with no drift followed by sph_drift over
+    the times in between (nothing but the drift happens there).  The first
+    run takes the times from sph_next_active_time; the second replays them."""
+    sg = gpu_lib
+    ic = dict(ics.clustered(n_total=20000, n_clumps=3))
+    rng = np.random.default_rng(8)
+    ic["v"] = rng.normal(0.0, 0.3, size=ic["x"].shape)
+    print(f"case drift over inactive times clustered20k lazy={lazy}", flush=True)
+    runs, times = [], []
+    for split in (True, False):
+        p = sg.Particles.from_initial(ic)
+        ctx = sg.Context(lazy_drift=lazy)
+        top = ctx.params.n_bins - 1
+        ctx.build_cells(p)
+        ctx.sort_cells()
+        ctx.mark_active(p, top)
+        ctx.density_pass(p, True)
+        ctx.force_pass(p)
+        ctx.sync()
+        t_min = float((ctx.params.cfl * p["h"].double() / p["vsig"].double()).min()) / 4
+        if split:
+            ctx.kick_drift(p, 0, t_min, 0, True)
+            t = 0
+            for _ in range(4):
+                tn = ctx.next_active_time(p, t)
+                assert tn > t
+                times.append(tn)
+                ctx.drift(p, t_min, tn - t)
+                ctx.step(p, min((tn & -tn).bit_length() - 1, top), tn, t_min, 0, False)
+                t = tn
+        else:
+            ctx.kick_drift(p, 0, t_min, times[0], True)
+            for q, tn in enumerate(times):
+                nxt = times[q + 1] - tn if q + 1 < len(times) else 0
+                ctx.step(p, min((tn & -tn).bit_length() - 1, top), tn, t_min, nxt, False)
+        ctx.drift_all(p)
+        ctx.sync()
+        runs.append({k: host(p, k).copy() for k in ("x", "y", "z", "vx", "vy", "vz", "vfx", "vfy", "vfz", "A", "Af",
+                                                    "h", "time_bin", "ax", "rho")})
+    print("active times", times, flush=True)
+    # t_min a quarter of the smallest step: every particle sits in bin >= 2,
+    # so the line passes over times with nothing active
+    assert times[0] > 1
+    if lazy:
+        for k in runs[0]:
+            assert np.array_equal(runs[0][k].view(np.uint8), runs[1][k].view(np.uint8)), k
+        return
+    # drifting every particle, the step with no drift stores the entropy it
+    # kicked in FP32 before the drift adds dA/dt dt (one more rounding, at
+    # most 2^-24 relative): the same times and bins, the state within that
+    assert np.array_equal(runs[0]["time_bin"], runs[1]["time_bin"])
+    rel = {k: float(np.max(np.abs(runs[0][k].astype(np.float64) - runs[1][k]) /
+                           np.abs(runs[1][k].astype(np.float64))))
+           for k in ("A", "Af", "h", "rho")}
+    rel.update({k: float(np.max(np.abs(runs[0][k].astype(np.float64) - runs[1][k])) /
+                         np.max(np.abs(runs[1][k].astype(np.float64))))
+                for k in ("vx", "vy", "vz", "ax")})
+    dx = max(float(np.max(np.abs(runs[0][k] - runs[1][k]))) for k in "xyz")
+    print("drift-all differences", dx, rel, flush=True)
+    assert dx < 1e-9
+    assert max(rel.values()) < 1e-4

@@ -242,3 +242,36 @@ def test_step_call_equals_separate_calls(gpu_lib):
         out.append({k: host(p, k).copy() for k in ("x", "vx", "h", "rho", "ax", "vsig", "time_bin", "nngb_force")})
     for k in out[0]:
         assert np.array_equal(out[0][k].view(np.uint8), out[1][k].view(np.uint8)), k
+
+
+def test_next_active_time_matches_oracle(gpu_lib):
+    """sph_next_active_time against the oracle's scan of Sec. II-A's
+    activity rule, on one context and on a batch context of three boxes
+    (the earliest over the boxes)."""
+    sg = gpu_lib
+    ic = ics.tiny_lattice(12)
+    n = ic["x"].shape[0]
+    print("case next_active_time tiny12 and a batch of 3", flush=True)
+    rng = np.random.default_rng(4)
+    p = sg.Particles.from_initial(ic)
+    ctx = sg.Context()
+    ctx.build_cells(p)
+    for trial in range(12):
+        lo = int(rng.integers(0, 14))
+        bins = rng.integers(lo, 14, size=n)
+        p["time_bin"].copy_(torch.from_numpy(bins.astype(np.int8)))
+        for t0 in (0, int(rng.integers(1, 1 << 13)), (1 << 13) - 1):
+            assert ctx.next_active_time(p, t0) == sph.next_active_time(bins, t0), (trial, t0)
+    boxes = [ics.tiny_lattice(10), ics.tiny_lattice(12), ics.tiny_lattice(11)]
+    sizes = [b["x"].shape[0] for b in boxes]
+    cat = {k: np.concatenate([b[k] for b in boxes]) for k in ("x", "v", "m", "u", "h", "bin")}
+    P = sg.Particles.from_initial(cat)
+    bctx = sg.Context().batch_create(sizes)
+    bctx.build_cells(P)
+    for trial in range(6):
+        bins = rng.integers(int(rng.integers(0, 14)), 14, size=sum(sizes))
+        P["time_bin"].copy_(torch.from_numpy(bins.astype(np.int8)))
+        t0 = int(rng.integers(0, 1 << 13))
+        assert bctx.next_active_time(P, t0) == sph.next_active_time(bins, t0), trial
+    with pytest.raises(sg.SPHError):
+        ctx.next_active_time(p, -1)

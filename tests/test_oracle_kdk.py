@@ -282,3 +282,26 @@ def test_h_prediction_follows_the_resolved_h_of_an_expanding_lattice():
     exact = alpha * dt
     assert np.all(pred > 0)
     assert np.max(np.abs(pred / exact - 1)) < 0.06
+
+
+def test_next_active_time_is_the_first_time_a_bin_is_active():
+    """Sec. II-A: a particle of bin b is active at the integer times that 2^b
+    divides.  The oracle's next_active_time checked against that definition
+    particle by particle (nothing active strictly between, something active
+    at the result) and against the closed form (t // 2^b_min + 1) 2^b_min."""
+    rng = np.random.default_rng(11)
+    for trial in range(300):
+        n = int(rng.integers(1, 40))
+        lo = int(rng.integers(0, 14))
+        bins = rng.integers(lo, 14, size=n)
+        t0 = int(rng.integers(0, 1 << 14))
+        t1 = sph.next_active_time(bins, t0)
+        assert t1 > t0
+        for t in range(t0 + 1, t1):
+            assert not np.any(t % (1 << bins) == 0), (trial, t)
+        assert np.any(t1 % (1 << bins) == 0)
+        bm = int(bins.min())
+        assert t1 == (t0 // (1 << bm) + 1) * (1 << bm)
+    # every particle in the top bin: one step per period
+    assert sph.next_active_time(np.full(5, 13), 0) == 1 << 13
+    assert sph.next_active_time(np.array([0, 13]), 7) == 8
