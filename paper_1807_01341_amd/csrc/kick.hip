@@ -231,8 +231,22 @@ __global__ __launch_bounds__(64) void set_i32_kernel(int32_t *__restrict__ p, in
 __global__ __launch_bounds__(256) void min_bin_kernel(const int8_t *__restrict__ bin, int64_t n,
                                                       int32_t *__restrict__ out) {
   int m = INT_MAX;
-  for (int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x; s < n; s += (int64_t)gridDim.x * 256)
-    m = min(m, (int)bin[s]);
+  // 16 bins per load where the array is 16-byte aligned, single bins for the rest
+  const int64_t head = (int64_t)((16 - ((uintptr_t)bin & 15)) & 15);
+  const int64_t h = head < n ? head : n;
+  const int64_t nv = (n - h) >> 4;
+  const int4 *v = reinterpret_cast<const int4 *>(bin + h);
+  const int64_t tid = (int64_t)blockIdx.x * 256 + threadIdx.x, stride = (int64_t)gridDim.x * 256;
+  for (int64_t s = tid; s < nv; s += stride) {
+    const int4 w = v[s];
+    const int32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) m = min(m, (int)(int8_t)(ws[q] >> (8 * b)));
+  }
+  for (int64_t s = tid; s < h; s += stride) m = min(m, (int)bin[s]);
+  for (int64_t s = h + (nv << 4) + tid; s < n; s += stride) m = min(m, (int)bin[s]);
   for (int o = 32; o > 0; o >>= 1) m = min(m, __shfl_xor(m, o, 64));
   if ((threadIdx.x & 63) == 0) atomicMin(out, m);
 }
@@ -241,7 +255,7 @@ sph_status next_active_impl(sph_ctx *ctx, const int8_t *bin, int64_t n, int64_t 
   if (n <= 0) return sph_fail(ctx, SPH_ESTATE, "next_active_time: no particles (build_cells first)");
   int32_t *slot = (int32_t *)ctx->scalars.p + SC_MINBIN;
   set_i32_kernel<<<1, 64, 0, ctx->stream>>>(slot, INT_MAX);
-  const int64_t grid = std::min<int64_t>(ceil_div(n, 256), 2048);
+  const int64_t grid = std::min<int64_t>(ceil_div(n, 256 * 16), 2048) + 1;
   min_bin_kernel<<<(unsigned)grid, 256, 0, ctx->stream>>>(bin, n, slot);
   HIP_TRY(ctx, hipGetLastError());
   int32_t b = 0;

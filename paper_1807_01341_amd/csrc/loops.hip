@@ -218,17 +218,18 @@ LoopConfig choose_config(sph_ctx *ctx, int mode) {
     if (c.nw == 8) c.tile = 0;  // the one tile class whose eight waves fit the LDS
     return c;
   }
+  // The loop is bound by instruction issue, and the smallest tile keeps the
+  // most waves resident; with few chunks, more waves share one chunk.
   const int64_t nc = ctx->n_chunks;
+  c.tile = 0;
   if (nc < 2048) {
-    c.nw = 8, c.tile = 0, c.ordered = 1;
+    c.nw = 8, c.ordered = 1;
   } else if (nc < 8192) {
-    c.nw = 4, c.tile = 1, c.ordered = 1;
+    c.nw = 4, c.ordered = 1;
   } else if (nc < 32768) {
-    c.nw = 2, c.tile = 2;
+    c.nw = 2;
   } else {
-    // dense passes: the loop is bound by instruction issue, and the smallest
-    // tile keeps the most waves resident
-    c.nw = 1, c.tile = 0;
+    c.nw = 1;
   }
   return c;
 }
