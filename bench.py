@@ -156,7 +156,7 @@ def oracle_on_cube(ic, centre, half, label):
                 seconds=t, interactions=inter, **cpu_info())
 
 
-def run_cpu_baseline(ic, label, seed=5, target_centres=30000, max_half=0.3):
+def run_cpu_baseline(ic, label, seed=5, target_centres=90000, max_half=0.3):
     """The oracle on a bounded sample: a cube around a seeded particle, grown
     until its density region holds about `target_centres` particles."""
     from oracle import sph
