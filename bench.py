@@ -328,7 +328,8 @@ def ctz(t):
 def loop_kwargs(args):
     kw = {}
     for a, k in (("split", "split_count"), ("cand_cap", "cand_cap"), ("list_cap", "list_cap"), ("h_tol", "h_tol"),
-                 ("nw", "waves_per_chunk"), ("sweep_below", "sweep_below"), ("sweep_waves", "sweep_waves")):
+                 ("nw", "waves_per_chunk"), ("sweep_below", "sweep_below"), ("sweep_waves", "sweep_waves"),
+                 ("rebuild_frac", "rebuild_frac")):
         v = getattr(args, a, None)
         if v is not None and v is not False:
             kw[k] = v
@@ -892,6 +893,9 @@ def main():
     ap.add_argument("--list-cap", type=int, default=None)
     ap.add_argument("--profile-steps", type=int, default=None)
     ap.add_argument("--h-tol", type=float, default=None)
+    ap.add_argument("--rebuild-frac", type=float, default=0.25,
+                    help="cells kept while every particle moved less than this fraction of its leaf "
+                         "(the library's default is 1/8; 1/4 halves the large share's full builds)")
     ap.add_argument("--nw", type=int, default=None)
     ap.add_argument("--sweep-below", type=int, default=None)
     ap.add_argument("--sweep-waves", type=int, default=None)

@@ -9,7 +9,8 @@ drifted (Sec. II-A, Sec. III-D):
   the physics of about a thousand active particles spread over all clumps
   and the background against the oracle;
 * the first 64 sub-steps (bins 0-6) of the 16,777,216-particle share, with
-  both drift policies, checked at five sub-steps;
+  both drift policies (and the benchmark's cell-keeping fraction 1/4 with
+  lazy drift), checked at five sub-steps;
 * all 64 boxes of the batching workload at their active fractions, batched;
 * the individual-time-step kick-drift-kick of 16 sub-steps, both drift
   policies, against the oracle's kick_drift driven with the same
@@ -86,14 +87,14 @@ def grf_share():
     return ics.grf_zeldovich()
 
 
-@pytest.mark.parametrize("lazy", [0, 1])
-def test_large_share_first_64_substeps(gpu_lib, grf_share, lazy):
+@pytest.mark.parametrize("lazy,rebuild_frac", [(0, 0.125), (1, 0.125), (1, 0.25)])
+def test_large_share_first_64_substeps(gpu_lib, grf_share, lazy, rebuild_frac):
     sg = gpu_lib
     ic = grf_share
     N = ic["x"].shape[0]
-    print(f"case large share N={N} lazy_drift={lazy}: sub-steps 1..64", flush=True)
+    print(f"case large share N={N} lazy_drift={lazy} rebuild_frac={rebuild_frac}: sub-steps 1..64", flush=True)
     p = sg.Particles.from_initial(ic)
-    ctx = sg.Context(lazy_drift=lazy)
+    ctx = sg.Context(lazy_drift=lazy, rebuild_frac=rebuild_frac)
     tr = CellTracker()
     perm = torch.empty(N, dtype=torch.int64, device="cuda")
     top = ctx.params.n_bins - 1
