@@ -219,6 +219,34 @@ __global__ __launch_bounds__(BT) void leaf_count_kernel(const int32_t *__restric
 // FP32 offsets from the leaf centre, H, and the leaf's max H: one wave per
 // leaf.  H is also each particle's key of its leaf's H order (hb), so the
 // leaf's H growth bound starts at 1.
+// Bounding boxes of the groups of 8 consecutive particles of every leaf, from
+// the offsets of the full build (the sweeps prune partner leaves group by
+// group, each box widened by its leaf's drift bound).  Group g of leaf l sits
+// at slot (begin_l >> 3) + l + g: disjoint ranges, (n >> 3) + nl slots in all.
+__global__ __launch_bounds__(BT) void group_box_kernel(const float4 *__restrict__ pos4,
+                                                       const int32_t *__restrict__ begin,
+                                                       const int32_t *__restrict__ count, int64_t nl,
+                                                       float4 *__restrict__ glo, float4 *__restrict__ ghi) {
+  const int64_t l = (int64_t)blockIdx.x * (BT / 64) + (threadIdx.x >> 6);
+  if (l >= nl) return;
+  const int lane = threadIdx.x & 63;
+  const int b = begin[l], c = count[l];
+  const int ng = (c + 7) >> 3;
+  const int64_t slot0 = (int64_t)(b >> 3) + l;
+  for (int g = lane; g < ng; g += 64) {
+    float4 lo = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
+    float4 hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.f);
+    const int k1 = min(c, 8 * g + 8);
+    for (int k = 8 * g; k < k1; ++k) {
+      const float4 q = pos4[b + k];
+      lo.x = fminf(lo.x, q.x), lo.y = fminf(lo.y, q.y), lo.z = fminf(lo.z, q.z);
+      hi.x = fmaxf(hi.x, q.x), hi.y = fmaxf(hi.y, q.y), hi.z = fmaxf(hi.z, q.z);
+    }
+    glo[slot0 + g] = lo;
+    ghi[slot0 + g] = hi;
+  }
+}
+
 __global__ __launch_bounds__(BT) void offsets_kernel(const double *__restrict__ x, const double *__restrict__ y,
                                                      const double *__restrict__ z, const float *__restrict__ h,
                                                      const int32_t *__restrict__ begin, const int32_t *__restrict__ count,
@@ -625,6 +653,15 @@ sph_status build_cells_impl(sph_ctx *ctx, sph_particles *p, int64_t n, int64_t *
   // the axis sorts order these offsets until the next full build
   SPH_TRY(sph_ensure(ctx, ctx->pos4_build, 16 * (size_t)n));
   HIP_TRY(ctx, hipMemcpyAsync(ctx->pos4_build.p, ctx->pos4.p, 16 * (size_t)n, hipMemcpyDeviceToDevice, ctx->stream));
+  {
+    const size_t ngs = (size_t)(n >> 3) + (size_t)nl + 1;
+    SPH_TRY(sph_ensure(ctx, ctx->gbox_lo, 16 * ngs));
+    SPH_TRY(sph_ensure(ctx, ctx->gbox_hi, 16 * ngs));
+    PROF(ctx, "leaf_build");
+    group_box_kernel<<<(unsigned)ceil_div(nl, BT / 64), BT, 0, ctx->stream>>>(
+        (const float4 *)ctx->pos4.p, lb, lc, nl, (float4 *)ctx->gbox_lo.p, (float4 *)ctx->gbox_hi.p);
+  }
+  HIP_TRY(ctx, hipGetLastError());
   ctx->dx_max = 0.f;
   ctx->built_n = n;
   ctx->n_full_builds++;

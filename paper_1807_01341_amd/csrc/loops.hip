@@ -358,6 +358,8 @@ LoopArgs base_args(sph_ctx *ctx) {
   a.leaf_count = (const int32_t *)ctx->leaf_count.p;
   a.leaf_hmax = (const float *)ctx->leaf_hmax.p;
   a.leaf_half = (const float *)ctx->leaf_half.p;
+  a.gbox_lo = (const float4 *)ctx->gbox_lo.p;
+  a.gbox_hi = (const float4 *)ctx->gbox_hi.p;
   a.leaf_dx = (const float *)ctx->leaf_dx.p;
   a.axis_order = (const uint16_t *)ctx->axis_order.p;
   a.leaf_hgrow = (const float *)ctx->leaf_hgrow.p;
@@ -434,7 +436,7 @@ struct GhostArgs {
   int32_t *chunk_todo;
   const float *sums;
   const int32_t *act_cnt;
-  const float *act_hmax;
+  const float *act_reach;  // per active leaf: the radius its density cell-pair list is complete for
   float *hlo, *hhi;
   uint8_t *conv;
   float4 *pos4;
@@ -442,7 +444,7 @@ struct GhostArgs {
   float *h;
   int last;
   int from_u;
-  float eta3, kc, tol, gamma, eps, box_quarter, reach;
+  float eta3, kc, tol, gamma, eps, box_quarter;
   // outputs
   float *rho, *drho_dh, *f, *divv, *curlx, *curly, *curlz, *P, *c, *B, *A, *u;
   float *Af;  // (opt) the kicked copy of A, set with A when u is the thermal input
@@ -451,6 +453,39 @@ struct GhostArgs {
   unsigned long long *ctr;  // cumulative density interactions of finished solves
   int32_t *todo, *todo_n;   // (opt) appends the particles the next pass evaluates
 };
+
+// One Newton step of the h solve from the sums at h: sum_j w(q_ij) (S_w) and
+// sum_j (3 w + q w') (S_d), with the bracket [lo, hi] of the root.  Newton in
+// ln h on G = ln(h^3 n / eta^3), with h^3 n = (8/pi)/GK^3 sum w and
+// dG/dln h = (3 sum w - sum (3w + q w')) / sum w: the same root as
+// h^3 n = eta^3, reached in one step where the density is locally uniform.
+// The ghost and the sweep's own steps share it, so that both take bitwise
+// the same step from the same sums.
+struct HStep {
+  float hn, lo, hi;
+  bool done;  // |hn - h| < tol h: h is the solution
+};
+__device__ __forceinline__ HStep h_newton_step(float S_w, float S_d, float h, float lo, float hi, float kc,
+                                               float eta3, float tol) {
+  const float hn3 = kc * S_w;
+  const float G = __logf(hn3 / eta3);
+  const float Gp = (3.f * S_w - S_d) / S_w;
+  if (G < 0.f) lo = fmaxf(lo, h);
+  if (G > 0.f) hi = fminf(hi, h);
+  float hn = h * __expf(fminf(fmaxf(-G / Gp, -0.6931472f), 0.6931472f));
+  // a step that lands on (or beyond) an end of the bracket falls back to
+  // bisection: a clamped step of exactly x2 / x0.5 between two earlier
+  // iterates would otherwise cycle
+  const bool small = Gp > 0.f && fabsf(hn - h) < tol * h;
+  if (!small && (!(hn > lo && hn < hi) || !(Gp > 0.f))) hn = (hi < INFINITY) ? 0.5f * (lo + hi) : 2.f * h;
+  if (G == 0.f) hn = h;
+  HStep r;
+  r.hn = hn;
+  r.lo = lo;
+  r.hi = hi;
+  r.done = fabsf(hn - h) < tol * h;
+  return r;
+}
 
 // Newton step on F(h) = h^3 sum_j W(r_ij, h) - eta^3 for each active particle
 // not yet converged; converged (or last-pass) particles get their ghost
@@ -479,23 +514,9 @@ __device__ __forceinline__ void ghost_body(const GhostArgs &g) {
       ++unconv;
       return false;
     }
-    // Newton in ln h on G = ln(h^3 n / eta^3), with h^3 n = (8/pi)/GK^3 sum w
-    // and dG/dln h = (3 sum w - sum (3w + q w')) / sum w: the same root as
-    // h^3 n = eta^3, reached in one step where the density is locally uniform.
-    const float hn3 = g.kc * S_w;
-    const float G = __logf(hn3 / g.eta3);
-    const float Gp = (3.f * S_w - S_d) / S_w;
-    float lo = lo0, hi = hi0;
-    if (G < 0.f) lo = fmaxf(lo, h);
-    if (G > 0.f) hi = fminf(hi, h);
-    float hn = h * __expf(fminf(fmaxf(-G / Gp, -0.6931472f), 0.6931472f));
-    // a step that lands on (or beyond) an end of the bracket falls back to
-    // bisection: a clamped step of exactly x2 / x0.5 between two earlier
-    // iterates would otherwise cycle
-    const bool small = Gp > 0.f && fabsf(hn - h) < g.tol * h;
-    if (!small && (!(hn > lo && hn < hi) || !(Gp > 0.f))) hn = (hi < INFINITY) ? 0.5f * (lo + hi) : 2.f * h;
-    if (G == 0.f) hn = h;
-    const bool done = fabsf(hn - h) < g.tol * h;
+    const HStep st = h_newton_step(S_w, S_d, h, lo0, hi0, g.kc, g.eta3, g.tol);
+    const float hn = st.hn, lo = st.lo, hi = st.hi;
+    const bool done = st.done;
     if (done || g.last) {
       const float H = GK32 * h;
       const float iH = 1.f / H;
@@ -545,7 +566,7 @@ __device__ __forceinline__ void ghost_body(const GhostArgs &g) {
     }
     const float Hn = GK32 * hn;
     bool wait = false;
-    if (Hn > g.act_hmax[ch.act_leaf] * g.reach) {
+    if (Hn > g.act_reach[ch.act_leaf]) {
       // beyond the reach of the cell-pair lists: the particle waits (no
       // evaluation) until they are widened, so that every evaluation sees
       // all its neighbours
@@ -662,6 +683,38 @@ __device__ __forceinline__ SweepPair locate(const SweepPair *my, const FlatRange
   return my[lo];
 }
 
+// A value every lane of the wave holds alike, moved to a scalar register.
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float wave_uniform(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ float4 wave_uniform(float4 v) {
+  return make_float4(wave_uniform(v.x), wave_uniform(v.y), wave_uniform(v.z), wave_uniform(v.w));
+}
+
+// A partner leaf of the flat range, for the group-by-group test.
+struct GroupPart {
+  int goff, bb, bc, b;
+  float sx, sy, sz, m;  // shift into the particle's frame; drift margin
+};
+
+// Whether the 8-particle group `slot` of a partner leaf (box of the full
+// build, widened by the leaf's drift margin m, shifted into the particle's
+// frame) can hold a particle within R of the particle at offset pi; the
+// relative guard covers the FP32 rounding of the predicate as in
+// leaf_in_reach.
+__device__ __forceinline__ bool group_in_reach(const LoopArgs &g, int64_t slot, const GroupPart &q, const float4 &pi,
+                                               float R) {
+  const float4 lo = g.gbox_lo[slot], hi = g.gbox_hi[slot];
+  const float gx = fmaxf(fmaxf((lo.x + q.sx - q.m) - pi.x, pi.x - (hi.x + q.sx + q.m)), 0.f);
+  const float gy = fmaxf(fmaxf((lo.y + q.sy - q.m) - pi.y, pi.y - (hi.y + q.sy + q.m)), 0.f);
+  const float gz = fmaxf(fmaxf((lo.z + q.sz - q.m) - pi.z, pi.z - (hi.z + q.sz + q.m)), 0.f);
+  const float Rg = 1.0001f * R + 1e-6f * (fabsf(pi.x) + fabsf(pi.y) + fabsf(pi.z) + fabsf(q.sx) + fabsf(q.sy) +
+                                         fabsf(q.sz) + fmaxf(fabsf(lo.x), fabsf(hi.x)) + fmaxf(fabsf(lo.y), fabsf(hi.y)) +
+                                         fmaxf(fabsf(lo.z), fabsf(hi.z)) + q.m);
+  return fmaf(gz, gz, fmaf(gy, gy, gx * gx)) < Rg * Rg;
+}
+
 // Whether partner leaf e.b can hold a particle within R of the particle at
 // offset pi: the distance from pi to the leaf's box (in the particle's leaf
 // frame, widened by the leaf's drift margin) against R, with a relative
@@ -731,18 +784,44 @@ __device__ __forceinline__ void density_term(const float4 &pi, const float4 &vi,
   (void)pi;
 }
 
+// The sweep's own steps of the h solve (one wave per particle).  The walk
+// keeps every candidate within a cache radius Rc >= H (at most cache_f H, and
+// within the radius the particle's cell-pair list is complete for) in LDS;
+// the kernel then evaluates the sums at h from that cache, takes the Newton
+// step while the new H stays within Rc, and evaluates again.  The step that
+// ends the solve, or would leave the cache, is left to the ghost: the kernel
+// writes the sums at the last h it evaluated and the solver state (h, its
+// bracket) that step starts from, and the ghost takes it bitwise as the
+// kernel would (the same function from the same sums).  A pass p takes at
+// most h_max_iter - p steps of its own.
+struct SweepSolve {
+  int steps;  // Newton steps the kernel may take itself (0: none)
+  float cache_f, kc, eta3, tol, box_quarter;
+  const float *act_reach;  // per active leaf: radius the density cell-pair list is complete for
+  float *h, *hlo, *hhi;
+  float4 *pos4;  // H (w) follows h
+  int32_t *chunk_todo;
+};
+
+// Entries of a wave's neighbour queue: with the cache at most SWEEP_QCAP - 64
+// (more neighbours within Rc than that and the particle goes on without it).
+#define SWEEP_QCAP 256
+
 // NWP waves share one particle: wave s of it takes the flat candidates
 // s*64 + NWP*64*t and every NWP-th large partner; the waves' sums are added
 // in wave order.  The neighbours a wave finds are queued in LDS and their
 // pair terms evaluated 64 at a time, one per lane, so that the terms run on
-// full waves although few of the candidates tested together are neighbours.
+// full waves although few of the candidates tested together are neighbours
+// (with one wave per particle and the solver's steps on, all of them are
+// evaluated from the cache after the walk).
 template <int NWP, bool COMP>
 __global__ __launch_bounds__(256) void density_sweep_kernel(LoopArgs g, const int32_t *__restrict__ todo,
                                                             const int32_t *__restrict__ n_todo_dev, int64_t n_todo,
                                                             const int32_t *__restrict__ chunk_of,
-                                                            int32_t *__restrict__ next_n) {
+                                                            int32_t *__restrict__ next_n, SweepSolve sv) {
   __shared__ SweepPair sp[4][64];
-  __shared__ float4 hq[4][128];  // per wave: queued neighbours (dx, dy, dz, j)
+  __shared__ GroupPart gpart[4][64];  // per wave: the small partners of the current 64 pairs
+  __shared__ float4 hq[4][SWEEP_QCAP];  // per wave: queued neighbours (dx, dy, dz, j)
   __shared__ float red[4][9];
   const int wave = threadIdx.x >> 6;
   const int sub = wave % NWP;
@@ -762,37 +841,61 @@ __global__ __launch_bounds__(256) void density_sweep_kernel(LoopArgs g, const in
   const int64_t w = lb < nblk ? lb * (4 / NWP) + wave / NWP : n_todo;
   if (w < n_todo) {
   SweepPair *my = sp[wave];
-  const int k = todo ? todo[w] : (int)w;
-  const int i = g.active_idx[k];
-  const float4 pi = g.pos4[i];
-  const float Hi = pi.w, H2i = Hi * Hi, invHi = 1.f / Hi;
-  const float4 vi = g.jvm[i];
-  const Chunk ch = g.chunks[chunk_of[k]];
-  const int pbeg = g.pair_off[ch.act_leaf], pend = g.pair_off[ch.act_leaf + 1];
+  // the particle's values are the same on every lane: scalar registers
+  const int k = wave_uniform(todo ? todo[w] : (int)w);
+  const int i = wave_uniform(g.active_idx[k]);
+  const float4 pi = wave_uniform(g.pos4[i]);
+  const float Hi = pi.w, H2i = wave_uniform(Hi * Hi), invHi = wave_uniform(1.f / Hi);
+  const float4 vi = wave_uniform(g.jvm[i]);
+  const int co = wave_uniform(chunk_of[k]);
+  const Chunk ch = g.chunks[co];
+  const int pbeg = wave_uniform(g.pair_off[ch.act_leaf]), pend = wave_uniform(g.pair_off[ch.act_leaf + 1]);
+  // the solver's own steps: cache radius and the state the steps start from
+  const bool cache_on = NWP == 1 && sv.steps > 0;
+  bool caching = cache_on;
+  // radius of the walk: the cache radius Rc while caching, else H
+  float Rw = wave_uniform(cache_on ? fmaxf(Hi, fminf(sv.cache_f * Hi, sv.act_reach[ch.act_leaf])) : Hi);
+  float Rw2 = wave_uniform(Rw * Rw);
   float acc[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) acc[q] = 0.f;
   int cnt = 0;
   float4 *Q = hq[wave];
   int qn = 0;  // queue length (wave-uniform)
-  auto drain = [&](int m) {
+  // pair terms of queue entries base + lane (lane < m) within H
+  auto drain = [&](int base, int m) {
     if (lane < m) {
-      const float4 e = Q[lane];
+      const float4 e = Q[base + lane];
       const int j = __float_as_int(e.w);
       const float r2 = fmaf(e.z, e.z, fmaf(e.y, e.y, e.x * e.x));
-      density_term(pi, vi, invHi, e.x, e.y, e.z, r2, g.jvm[j], acc);
-      cnt += (j != i);
+      if (r2 < H2i) {
+        density_term(pi, vi, invHi, e.x, e.y, e.z, r2, g.jvm[j], acc);
+        cnt += (j != i);
+      }
     }
   };
-  // queue the lanes' hits; a full wave of them is evaluated at once
+  // queue the lanes' hits; without the cache a full wave of them is
+  // evaluated at once
   auto push = [&](bool hit, float dx, float dy, float dz, int j) {
     const uint64_t m = __ballot(hit);
     if (m == 0ull) return;
     if (hit) Q[qn + rank_below(m)] = make_float4(dx, dy, dz, __int_as_float(j));
     qn += __popcll(m);
-    if (qn >= 64) {
+    if (caching) {
+      if (qn > SWEEP_QCAP - 64) {
+        // more candidates within Rc than the cache holds: those within H
+        // are evaluated and the walk goes on at H, without the cache
+        wave_sync();
+        for (int b = 0; b < qn; b += 64) drain(b, min(64, qn - b));
+        wave_sync();
+        qn = 0;
+        caching = false;
+        Rw = Hi;
+        Rw2 = H2i;
+      }
+    } else if (qn >= 64) {
       wave_sync();
-      drain(64);
+      drain(0, 64);
       const int rest = qn - 64;
       float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
       if (lane < rest) t = Q[64 + lane];
@@ -813,7 +916,7 @@ __global__ __launch_bounds__(256) void density_sweep_kernel(LoopArgs g, const in
       e = g.pairs[p];
       bb = g.leaf_begin[e.b];
       bc = g.leaf_count[e.b];
-      near = leaf_in_reach(g, e, pi, Hi);
+      near = leaf_in_reach(g, e, pi, Rw);
     }
     const bool big = near && e.b != ch.leaf && bc > 128;
     int axl = 0;
@@ -823,19 +926,66 @@ __global__ __launch_bounds__(256) void density_sweep_kernel(LoopArgs g, const in
       axl = code & 0x7f;
       sgl = (code & 0x80) ? -1.f : 1.f;
     }
-    // the small partners within reach as one flat range
-    const FlatRange fr = compact_small(my, near && !big, bc, bb, e, lane);
-    for (int t = sub * 64; t < fr.total; t += 2 * NWP * 64) {
-      // two candidates per lane, their loads in flight together
-      const int f0 = t + lane, f1 = t + NWP * 64 + lane;
-      const bool v0 = f0 < fr.total, v1 = f1 < fr.total;
-      const SweepPair q0 = locate(my, fr, v0 ? f0 : 0), q1 = locate(my, fr, v1 ? f1 : 0);
-      const int j0 = q0.bb + (v0 ? f0 - q0.off : 0), j1 = q1.bb + (v1 ? f1 - q1.off : 0);
-      const float4 pj0 = g.pos4[j0], pj1 = g.pos4[j1];
-      const float dx0 = pi.x - (pj0.x + q0.sx), dy0 = pi.y - (pj0.y + q0.sy), dz0 = pi.z - (pj0.z + q0.sz);
-      const float dx1 = pi.x - (pj1.x + q1.sx), dy1 = pi.y - (pj1.y + q1.sy), dz1 = pi.z - (pj1.z + q1.sz);
-      push(v0 && fmaf(dz0, dz0, fmaf(dy0, dy0, dx0 * dx0)) < H2i, dx0, dy0, dz0, j0);
-      push(v1 && fmaf(dz1, dz1, fmaf(dy1, dy1, dx1 * dx1)) < H2i, dx1, dy1, dz1, j1);
+    // The small partners within reach, tested group by group: 64 groups of 8
+    // particles per round (one per lane) against the particle's sphere, the
+    // groups within reach then read as one flat candidate range.
+    const bool sm = near && !big;
+    const int ng = sm ? (bc + 7) >> 3 : 0;
+    int ginc = ng;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int v = __shfl_up(ginc, o, 64);
+      if (lane >= o) ginc += v;
+    }
+    const int tg = __shfl(ginc, 63, 64);
+    const uint64_t smask = __ballot(sm);
+    const int nsm = __popcll(smask);
+    int gsteps = 0;
+    while ((1 << gsteps) < nsm) ++gsteps;
+    GroupPart *gp = gpart[wave];
+    wave_sync();  // the previous batch's readers of gp are done
+    if (sm) {
+      GroupPart q;
+      q.goff = ginc - ng;
+      q.bb = bb;
+      q.bc = bc;
+      q.b = e.b;
+      q.sx = e.sx;
+      q.sy = e.sy;
+      q.sz = e.sz;
+      q.m = g.leaf_dx[e.b];
+      gp[rank_below(smask)] = q;
+    }
+    wave_sync();
+    for (int gb = 0; gb < tg; gb += 64) {
+      const int fg = gb + lane;
+      const bool gv = fg < tg;
+      int k = 0;
+      for (int st = gsteps - 1; st >= 0; --st) {
+        const int mid = k + (1 << st);
+        if (mid < nsm && gp[mid].goff <= fg) k = mid;
+      }
+      const GroupPart q = gp[k];
+      const int gi = fg - q.goff;
+      bool keep = false;
+      if (gv) keep = group_in_reach(g, (int64_t)(q.bb >> 3) + q.b + gi, q, pi, Rw);
+      PairEntry ge;
+      ge.b = q.b;
+      ge.sx = q.sx;
+      ge.sy = q.sy;
+      ge.sz = q.sz;
+      const FlatRange fr = compact_small(my, keep, keep ? min(8, q.bc - 8 * gi) : 0, q.bb + 8 * gi, ge, lane);
+      for (int t = sub * 64; t < fr.total; t += 2 * NWP * 64) {
+        // two candidates per lane, their loads in flight together
+        const int f0 = t + lane, f1 = t + NWP * 64 + lane;
+        const bool v0 = f0 < fr.total, v1 = f1 < fr.total;
+        const SweepPair q0 = locate(my, fr, v0 ? f0 : 0), q1 = locate(my, fr, v1 ? f1 : 0);
+        const int j0 = q0.bb + (v0 ? f0 - q0.off : 0), j1 = q1.bb + (v1 ? f1 - q1.off : 0);
+        const float4 pj0 = g.pos4[j0], pj1 = g.pos4[j1];
+        const float dx0 = pi.x - (pj0.x + q0.sx), dy0 = pi.y - (pj0.y + q0.sy), dz0 = pi.z - (pj0.z + q0.sz);
+        const float dx1 = pi.x - (pj1.x + q1.sx), dy1 = pi.y - (pj1.y + q1.sy), dz1 = pi.z - (pj1.z + q1.sz);
+        push(v0 && fmaf(dz0, dz0, fmaf(dy0, dy0, dx0 * dx0)) < Rw2, dx0, dy0, dz0, j0);
+        push(v1 && fmaf(dz1, dz1, fmaf(dy1, dy1, dx1 * dx1)) < Rw2, dx1, dy1, dz1, j1);
+      }
     }
     // large partners, one after the other: sorted sweep
     uint64_t bigm = __ballot(big);
@@ -853,7 +1003,7 @@ __global__ __launch_bounds__(256) void density_sweep_kernel(LoopArgs g, const in
       const float pp = fmaf(pi.z, ez, fmaf(pi.y, ey, pi.x * ex));
       const float sproj = fmaf(sz, ez, fmaf(sy, ey, sx * ex));
       // orders are by the offsets of the full build (see the chunk loop)
-      const float margin = 1.0001f * Hi + 2.0001f * g.leaf_dx[Bq] + 1e-6f * (2.f * fabsf(pp) + fabsf(sproj));
+      const float margin = 1.0001f * Rw + 2.0001f * g.leaf_dx[Bq] + 1e-6f * (2.f * fabsf(pp) + fabsf(sproj));
       const float lo_b = pp - margin - sproj, hi_b = pp + margin - sproj;
       const uint16_t *ord = g.axis_order + (int64_t)axis * g.n + bbq;
       // two tiles per step, their loads in flight together; the sweep stops
@@ -867,16 +1017,80 @@ __global__ __launch_bounds__(256) void density_sweep_kernel(LoopArgs g, const in
         const float key0 = fmaf(pj0.z, ez, fmaf(pj0.y, ey, pj0.x * ex));
         if (__ballot(v0 && !(sgn > 0.f ? key0 > hi_b : key0 < lo_b)) == 0ull) break;
         const float dx0 = pi.x - (pj0.x + sx), dy0 = pi.y - (pj0.y + sy), dz0 = pi.z - (pj0.z + sz);
-        push(v0 && fmaf(dz0, dz0, fmaf(dy0, dy0, dx0 * dx0)) < H2i, dx0, dy0, dz0, j0);
+        push(v0 && fmaf(dz0, dz0, fmaf(dy0, dy0, dx0 * dx0)) < Rw2, dx0, dy0, dz0, j0);
         const float key1 = fmaf(pj1.z, ez, fmaf(pj1.y, ey, pj1.x * ex));
         if (__ballot(v1 && !(sgn > 0.f ? key1 > hi_b : key1 < lo_b)) == 0ull) break;
         const float dx1 = pi.x - (pj1.x + sx), dy1 = pi.y - (pj1.y + sy), dz1 = pi.z - (pj1.z + sz);
-        push(v1 && fmaf(dz1, dz1, fmaf(dy1, dy1, dx1 * dx1)) < H2i, dx1, dy1, dz1, j1);
+        push(v1 && fmaf(dz1, dz1, fmaf(dy1, dy1, dx1 * dx1)) < Rw2, dx1, dy1, dz1, j1);
       }
     }
   }
   wave_sync();
-  drain(qn);
+  bool moved = false;
+  float h_s = 0.f, lo_s = 0.f, hi_s = 0.f;
+  if (caching) {
+    const float Rc = Rw;
+    h_s = sv.h[i];
+    lo_s = sv.hlo[k];
+    hi_s = sv.hhi[k];
+    // the cache, entries lane + 64 u in registers (qn <= SWEEP_QCAP - 64)
+    constexpr int NU = (SWEEP_QCAP - 64) / 64;
+    float4 ce[NU], cv[NU];
+    uint32_t notself = 0;
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int idx = lane + 64 * u;
+      ce[u] = make_float4(0.f, 0.f, 0.f, INFINITY);
+      cv[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (idx < qn) {
+        const float4 e = Q[idx];
+        const int j = __float_as_int(e.w);
+        ce[u] = make_float4(e.x, e.y, e.z, fmaf(e.z, e.z, fmaf(e.y, e.y, e.x * e.x)));
+        cv[u] = g.jvm[j];
+        notself |= (j != i) ? (1u << u) : 0u;
+      }
+    }
+    float H = Hi, H2 = H2i, iH = invHi;
+    for (int left = sv.steps;; --left) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc[q] = 0.f;
+      cnt = 0;
+#pragma unroll
+      for (int u = 0; u < NU; ++u)
+        if (ce[u].w < H2) {
+          density_term(pi, vi, iH, ce[u].x, ce[u].y, ce[u].z, ce[u].w, cv[u], acc);
+          cnt += (notself >> u) & 1u;
+        }
+      if (left == 0) break;
+      // the two sums the step reads, totalled as below
+      float Sw = acc[0], Sd = acc[2];
+      if (COMP) {
+        float c0 = 0.f, c2 = 0.f;
+        two_sum_butterfly(Sw, c0);
+        two_sum_butterfly(Sd, c2);
+        Sw += c0;
+        Sd += c2;
+      } else {
+        for (int o = 32; o > 0; o >>= 1) {
+          Sw += __shfl_xor(Sw, o, 64);
+          Sd += __shfl_xor(Sd, o, 64);
+        }
+      }
+      const HStep st = h_newton_step(Sw, Sd, h_s, lo_s, hi_s, sv.kc, sv.eta3, sv.tol);
+      if (st.done) break;
+      const float Hn = GK32 * st.hn;
+      if (!(Hn <= Rc) || Hn > sv.box_quarter) break;  // the ghost takes this step
+      h_s = st.hn;
+      lo_s = st.lo;
+      hi_s = st.hi;
+      moved = true;
+      H = Hn;
+      H2 = H * H;
+      iH = 1.f / H;
+    }
+  } else {
+    for (int b = 0; b < qn; b += 64) drain(b, min(64, qn - b));
+  }
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     if (COMP) {
@@ -895,6 +1109,14 @@ __global__ __launch_bounds__(256) void density_sweep_kernel(LoopArgs g, const in
 #pragma unroll
       for (int q = 0; q < 8; ++q) g.sums[(int64_t)q * g.n_active + k] = acc[q];
       g.act_cnt[k] = cnt;
+      if (moved) {
+        // the state the ghost's step starts from
+        sv.h[i] = h_s;
+        sv.pos4[i].w = GK32 * h_s;
+        sv.hlo[k] = lo_s;
+        sv.hhi[k] = hi_s;
+        sv.chunk_todo[co] = 1;
+      }
     }
   } else {
     if (lane == 0) {
@@ -1277,7 +1499,7 @@ GhostArgs density_ghost_args(sph_ctx *ctx, sph_particles *p, int it, int entropy
   gh.chunk_todo = (int32_t *)ctx->chunk_todo.p;
   gh.sums = (const float *)ctx->sums.p;
   gh.act_cnt = (const int32_t *)ctx->sums.p + 8 * na;
-  gh.act_hmax = (const float *)ctx->act_hmax.p;
+  gh.act_reach = (const float *)ctx->act_reach.p;
   gh.hlo = (float *)ctx->hlo.p;
   gh.hhi = (float *)ctx->hhi.p;
   gh.conv = (uint8_t *)ctx->conv.p;
@@ -1292,7 +1514,6 @@ GhostArgs density_ghost_args(sph_ctx *ctx, sph_particles *p, int it, int entropy
   gh.gamma = (float)ctx->prm.gamma;
   gh.eps = ctx->prm.balsara_eps;
   gh.box_quarter = (float)(0.25 * ctx->prm.box);
-  gh.reach = ctx->dpair_slack;
   gh.rho = p->rho;
   gh.drho_dh = p->drho_dh;
   gh.f = p->f_gradh;
@@ -1315,6 +1536,25 @@ GhostArgs density_ghost_args(sph_ctx *ctx, sph_particles *p, int it, int entropy
   return gh;
 }
 
+// The sweep's own solver steps in Newton pass `pass`: as the ghost's, at
+// most h_max_iter - pass of them, within 1.1 H.
+SweepSolve sweep_solve_args(sph_ctx *ctx, sph_particles *p, int pass) {
+  SweepSolve sv;
+  sv.steps = std::max(0, ctx->prm.h_max_iter - pass);
+  sv.cache_f = 1.1f;
+  sv.kc = (float)((8.0 / M_PI) / ((double)GK32 * GK32 * GK32));
+  sv.eta3 = ctx->prm.eta * ctx->prm.eta * ctx->prm.eta;
+  sv.tol = ctx->prm.h_tol;
+  sv.box_quarter = (float)(0.25 * ctx->prm.box);
+  sv.act_reach = (const float *)ctx->act_reach.p;
+  sv.h = p->h;
+  sv.hlo = (float *)ctx->hlo.p;
+  sv.hhi = (float *)ctx->hhi.p;
+  sv.pos4 = (float4 *)ctx->pos4.p;
+  sv.chunk_todo = (int32_t *)ctx->chunk_todo.p;
+  return sv;
+}
+
 // Book-keeping after Newton pass `it` with the ghost's counters st: returns
 // SPH_OK with *done = 1 when the solve is over; widens the pair lists when a
 // smoothing length outgrew them.
@@ -1335,7 +1575,8 @@ __global__ void gather_totals_kernel(const int32_t *const *__restrict__ src, int
 
 static inline bool group_end(int it) { return it == 4 || (it > 4 && (it % 2) == 0); }
 
-sph_status density_after_pass(sph_ctx *ctx, const sph_particles *p, int it, const int32_t st[2], int *done) {
+sph_status density_after_pass(sph_ctx *ctx, const sph_particles *p, int it, const int32_t st[2], bool group_last,
+                              int *done) {
   *done = 0;
   ctx->density_iterations = it;
   if (it <= 32) ctx->unconv_hist[it - 1] = st[0];
@@ -1350,7 +1591,7 @@ sph_status density_after_pass(sph_ctx *ctx, const sph_particles *p, int it, cons
     return SPH_OK;
   }
   if (st[1] & 1) ctx->widen_pending = 1;
-  if (ctx->widen_pending && group_end(it)) {
+  if (ctx->widen_pending && group_last) {
     // a smoothing length outgrew its cell's pair reach: widen the pair lists,
     // then the waiting particles go on
     ctx->widen_pending = 0;
@@ -1381,9 +1622,10 @@ sph_status density_end(sph_ctx *ctx, bool refreshed) {
 }
 
 // Newton passes are enqueued in groups without waiting for the host (four,
-// then pairs): each pass's loop runs over what the previous ghost left to
-// do, read on the device, and a pass past convergence does nothing.  One
-// synchronisation per group reads its passes' counters.
+// then pairs; pairs from the start when the first pass is a sweep, whose own
+// steps leave few particles to a second): each pass's loop runs over what the
+// previous ghost left to do, read on the device, and a pass past convergence
+// does nothing.  One synchronisation per group reads its passes' counters.
 sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u) {
   int any;
   SPH_TRY(density_begin(ctx, p, entropy_from_u, &any));
@@ -1401,7 +1643,7 @@ sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u)
   int64_t n_todo = na;  // upper bound of the particles left to do
   int it = 0, done = 0;
   while (!done) {
-    const int first = it + 1, last = std::min(it == 0 ? 4 : it + 2, maxit);
+    const int first = it + 1, last = std::min(it == 0 && n_todo >= ctx->prm.sweep_below ? 4 : it + 2, maxit);
     for (int pass = first; pass <= last; ++pass) {
       LoopArgs a = density_loop_args(ctx);
       int32_t *next_n = list_n + ((pass + 1) & 1);
@@ -1415,7 +1657,9 @@ sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u)
         const int32_t *tl = pass > 1 ? list : nullptr, *tn = pass > 1 ? list_n + (pass & 1) : nullptr;
         const int32_t *co = (const int32_t *)ctx->chunk_of.p;
         const bool comp = ctx->prm.compensated != 0;
-#define SPH_DSWEEP(NWP_, C_) density_sweep_kernel<NWP_, C_><<<grid, 256, 0, ctx->stream>>>(a, tl, tn, n_todo, co, next_n)
+        const SweepSolve sv = sweep_solve_args(ctx, p, pass);
+#define SPH_DSWEEP(NWP_, C_) \
+  density_sweep_kernel<NWP_, C_><<<grid, 256, 0, ctx->stream>>>(a, tl, tn, n_todo, co, next_n, sv)
         if (nwp == 4)
           { if (comp) SPH_DSWEEP(4, true); else SPH_DSWEEP(4, false); }
         else if (nwp == 2)
@@ -1462,7 +1706,7 @@ sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u)
     memcpy(st, ctx->pin_h + PIN_STATS, sizeof(int32_t) * nst);
     const int32_t fc = *fcount;
     for (int pass = first; pass <= last && !done; ++pass) {
-      SPH_TRY(density_after_pass(ctx, p, pass, &st[2 * (pass - first)], &done));
+      SPH_TRY(density_after_pass(ctx, p, pass, &st[2 * (pass - first)], pass == last, &done));
       n_todo = st[2 * (pass - first)];
     }
     if (done) ctx->fpairs_counted = fc;
@@ -2011,7 +2255,7 @@ sph_status batch_density_impl(sph_ctx **cs, sph_particles *ps, int nb, int entro
     for (int q = 0; q < ni; ++q) {
       const int b = iterating[q];
       int done;
-      BATCH_TRY(b, density_after_pass(cs[b], &ps[b], it, &st[2 * q], &done));
+      BATCH_TRY(b, density_after_pass(cs[b], &ps[b], it, &st[2 * q], group_end(it), &done));
       if (!done) next.push_back(b);
     }
     iterating.swap(next);

@@ -48,6 +48,7 @@ struct LoopArgs {
   const int32_t *leaf_begin, *leaf_count;
   const float *leaf_hmax;
   const float *leaf_half;  // half width of each leaf (sweep pruning)
+  const float4 *gbox_lo, *gbox_hi;  // 8-particle group boxes (group g of leaf l at (begin >> 3) + l + g)
   const float *leaf_dx;    // drift margin of each leaf
   const int32_t *pair_off;
   const PairEntry *pairs;

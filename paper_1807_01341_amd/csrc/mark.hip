@@ -181,7 +181,7 @@ __global__ __launch_bounds__(MT) void pairs_kernel(int mode, float slack, PairGe
                                                    int32_t *__restrict__ counts, const int32_t *__restrict__ offs,
                                                    PairEntry *__restrict__ out, uint8_t *__restrict__ out_axis,
                                                    AxisTab ax, const int32_t *__restrict__ leaf_count,
-                                                   int32_t *__restrict__ act_cost,
+                                                   int32_t *__restrict__ act_cost, float *__restrict__ reach_out,
                                                    const int64_t *__restrict__ leaf_ti, int64_t ti_now) {
   const int64_t a = (int64_t)blockIdx.x * (MT / 64) + (threadIdx.x >> 6);
   if (a >= n_act_leaves) return;
@@ -362,6 +362,8 @@ __global__ __launch_bounds__(MT) void pairs_kernel(int mode, float slack, PairGe
     staged = wave_sum_i(staged);
     if (lane == 0) act_cost[a] = staged;
   }
+  // the radius the list is complete for (the h solve's steps stay within it)
+  if (FILL && reach_out && lane == 0) reach_out[a] = RA;
 }
 
 // Max H over each active leaf's particles (all of them), the max over its
@@ -459,11 +461,11 @@ static PairGeom pair_geom(const sph_ctx *ctx) {
 // fill phase writes the lists.
 sph_status build_pairs_count(sph_ctx *ctx, int which, float slack, int32_t *host_total) {
   const int64_t na = ctx->n_active_leaves;
-  if (which == 0) ctx->dpair_slack = slack;
   if (which == 1) ctx->fpairs_counted = -1;  // a count read back later is no longer the current one
   DevBuf &off = which == 0 ? ctx->dpair_off : ctx->fpair_off;
   SPH_TRY(sph_ensure(ctx, ctx->pair_cnt, 4 * (size_t)(na + 1)));
   SPH_TRY(sph_ensure(ctx, ctx->act_cost, 4 * (size_t)(na + 1)));
+  SPH_TRY(sph_ensure(ctx, ctx->act_reach, 4 * (size_t)(na + 1)));
   SPH_TRY(sph_ensure(ctx, off, 4 * (size_t)(na + 1)));
   if (host_total) *host_total = 0;
   if (na == 0) {
@@ -493,7 +495,7 @@ sph_status build_pairs_count(sph_ctx *ctx, int which, float slack, int32_t *host
         (const int32_t *)ctx->leaf_iz.p, (const float *)ctx->leaf_hmax.p, (const int32_t *)ctx->top_first.p,
         (const int32_t *)ctx->top_last.p, (const int32_t *)ctx->scalars.p + SC_HMAX_BITS,
         (const float *)ctx->leaf_dx.p, ctx->dx_max, (const int4 *)ctx->block_box.p, (int32_t *)ctx->pair_cnt.p,
-        nullptr, nullptr, nullptr, AxisTab(), nullptr, nullptr, lazy_ti, ctx->ti_now);
+        nullptr, nullptr, nullptr, AxisTab(), nullptr, nullptr, nullptr, lazy_ti, ctx->ti_now);
   }
   HIP_TRY(ctx, hipGetLastError());
   int32_t *o = (int32_t *)off.p;
@@ -523,7 +525,8 @@ sph_status build_pairs_fill(sph_ctx *ctx, int which, float slack, int32_t np) {
         (const int32_t *)ctx->top_last.p, (const int32_t *)ctx->scalars.p + SC_HMAX_BITS,
         (const float *)ctx->leaf_dx.p, ctx->dx_max, (const int4 *)ctx->block_box.p, nullptr,
         (int32_t *)off.p, (PairEntry *)lst.p, (uint8_t *)axl.p, host_axes(), (const int32_t *)ctx->leaf_count.p,
-        which == 0 ? (int32_t *)ctx->act_cost.p : nullptr, lazy_ti, ctx->ti_now);
+        which == 0 ? (int32_t *)ctx->act_cost.p : nullptr, which == 0 ? (float *)ctx->act_reach.p : nullptr,
+        lazy_ti, ctx->ti_now);
   }
   HIP_TRY(ctx, hipGetLastError());
   return SPH_OK;

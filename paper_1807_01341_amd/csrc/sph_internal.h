@@ -157,7 +157,6 @@ struct sph_ctx {
   int64_t n_unconverged = 0;
   int32_t unconv_hist[32] = {0};
   int32_t pair_rebuilds = 0;
-  float dpair_slack = 1.f;  // reach factor of the current density pair lists
   // cells kept between builds: positions of the last full build, per-leaf and
   // largest displacement since then (the cell-pair search margin)
   DevBuf x_build, leaf_dx, leaf_half;
@@ -191,6 +190,7 @@ struct sph_ctx {
   int blocks_valid = 0;                   // block_box made for the current full build
   DevBuf pos4;                            // float4 (ox, oy, oz, H) per particle
   DevBuf pos4_build;                      // pos4 of the last full build (the axis sorts' keys)
+  DevBuf gbox_lo, gbox_hi;                // boxes of 8-particle groups of each leaf at the full build
   // sort
   DevBuf axis_order;                      // uint16 14 x n: the 13 axes, then the H order (HORD_ROW)
   // force-loop pruning by H: each particle's H at the full build, per leaf a
@@ -215,6 +215,7 @@ struct sph_ctx {
   int todo_collect = 0;                   // the ghosts of this density pass append to todo_list
   DevBuf counters64;                      // cumulative interaction counts (2 x uint64)
   DevBuf act_cost;                        // staged partner particles per active leaf
+  DevBuf act_reach;                       // per active leaf: the radius its density pair list is complete for
   DevBuf work, work_tmp, box_args, box_work;
   int work_valid = 0;                     // the work items match the current chunks and costs
   // loop work items (codes chunk * 16 + part): chunk order and cost order,

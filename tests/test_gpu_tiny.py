@@ -162,6 +162,44 @@ def test_waves_per_chunk_variants_agree(gpu_lib, nw, split, sweep):
     assert np.max(np.linalg.norm(a0 - a1, axis=1)) < 1e-5 * np.max(np.linalg.norm(a0, axis=1))
 
 
+@pytest.mark.parametrize("eta,h_scale", [(None, 1.0), (None, 1.25), (None, 0.8), (1.9, 1.0)])
+def test_sweep_solver_steps_match_chunk_loop(gpu_lib, eta, h_scale):
+    """The density sweep (one wave per particle) takes the h solve's Newton
+    steps on the neighbours it keeps within 1.1 H and leaves the last one to
+    the ghost.  Starting h off the root (x1.25, x0.8), and with eta 1.9
+    (about 200 neighbours: more within 1.1 H than the sweep keeps, and a
+    first step that leaves the reach of the cell-pair lists, which are then
+    widened), it gives the converged h, the neighbour counts and the sums of
+    the chunk loop (one step per pass) and of the sweep with two waves per
+    particle (no steps of its own), in no more passes."""
+    ic = ics.tiny_lattice(24, velocity_sigma=0.1)
+    ic["h"] = (ic["h"] * h_scale).astype(np.float32)
+    kw = {} if eta is None else {"eta": eta}
+    print(f"case tiny24 eta={eta} h_scale={h_scale}", flush=True)
+    runs = []
+    for extra in (dict(sweep_below=0), dict(), dict(sweep_waves=2)):
+        _, p, perm, snap = run_gpu_step(gpu_lib, ic, 0, ctx_kw={**kw, **extra})
+        runs.append((p, perm, snap["info"]))
+    (p0, perm0, i0), (p1, perm1, i1), (p2, perm2, i2) = runs
+    assert np.array_equal(perm0, perm1) and np.array_equal(perm0, perm2)
+    print("passes", i0["density_iterations"], i1["density_iterations"], i2["density_iterations"],
+          "rebuilds", i0["pair_rebuilds"], i1["pair_rebuilds"], i2["pair_rebuilds"])
+    for info in (i0, i1, i2):
+        assert info["n_unconverged"] == 0
+    assert i1["density_iterations"] <= i0["density_iterations"]
+    if eta is not None:
+        # at least 150 within H, so above 192 within 1.1 H
+        assert min(host(p0, "nngb_density")) > 150
+    for pq in (p1, p2):
+        for k in ("nngb_density", "nngb_force"):
+            assert np.array_equal(host(p0, k), host(pq, k)), k
+        for k in ("h", "rho", "vsig"):
+            assert np.max(np.abs(host(p0, k) / host(pq, k) - 1)) < 2e-6, k
+        a0 = np.stack([host(p0, k) for k in ("ax", "ay", "az")], 1)
+        a1 = np.stack([host(pq, k) for k in ("ax", "ay", "az")], 1)
+        assert np.max(np.linalg.norm(a0 - a1, axis=1)) < 1e-5 * np.max(np.linalg.norm(a0, axis=1))
+
+
 def test_autotune_keeps_results(gpu_lib, tmp_path):
     """Tuning picks a loop configuration per pass; passes run with it give
     the same counts and the same sums to rounding."""
