@@ -92,40 +92,61 @@ __global__ __launch_bounds__(256) void kick_drift_kernel(KickArgs g) {
 __global__ __launch_bounds__(256) void kick_active_kernel(KickArgs g, const int32_t *__restrict__ active_idx,
                                                           int64_t n_act, const int32_t *__restrict__ leaf_of,
                                                           float *__restrict__ leaf_vmax) {
-  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n_act; k += (int64_t)gridDim.x * 256) {
-    const int s = active_idx[k];
-    const double a0 = g.ax[s], a1 = g.ay[s], a2 = g.az[s], da = g.dA[s];
-    double vf0 = g.vfx[s], vf1 = g.vfy[s], vf2 = g.vfz[s];
-    double Af = g.Af[s];
-    if (!g.first) {
-      const double h0 = 0.5 * ldexp(g.t_min, (int)g.bin[s]);
-      vf0 = vf0 + a0 * h0;
-      vf1 = vf1 + a1 * h0;
-      vf2 = vf2 + a2 * h0;
-      Af = Af + da * h0;
+  const int lane = threadIdx.x & 63;
+  // whole waves per iteration (lanes past the end idle), so that the lanes
+  // of a leaf can combine their speed bounds
+  for (int64_t k0 = (int64_t)blockIdx.x * 256 + (threadIdx.x & ~63); k0 < n_act; k0 += (int64_t)gridDim.x * 256) {
+    const int64_t k = k0 + lane;
+    int key = -1, bits = 0;
+    if (k < n_act) {
+      const int s = active_idx[k];
+      const double a0 = g.ax[s], a1 = g.ay[s], a2 = g.az[s], da = g.dA[s];
+      double vf0 = g.vfx[s], vf1 = g.vfy[s], vf2 = g.vfz[s];
+      double Af = g.Af[s];
+      if (!g.first) {
+        const double h0 = 0.5 * ldexp(g.t_min, (int)g.bin[s]);
+        vf0 = vf0 + a0 * h0;
+        vf1 = vf1 + a1 * h0;
+        vf2 = vf2 + a2 * h0;
+        Af = Af + da * h0;
+      }
+      g.vx[s] = vf0;
+      g.vy[s] = vf1;
+      g.vz[s] = vf2;
+      g.A[s] = (float)Af;
+      const double vs = g.vsig[s];
+      const double dtn = vs > 0.0 ? g.cfl * (double)g.h[s] / vs : INFINITY;
+      int nb = 0;
+      for (int b = 1; b < g.n_bins; ++b)
+        if (dtn >= ldexp(g.t_min, b)) nb = b;
+      if (g.ti != 0 && nb > g.ctz_ti) nb = g.ctz_ti;
+      g.bin[s] = (int8_t)nb;
+      const double h1 = 0.5 * ldexp(g.t_min, nb);
+      vf0 = vf0 + a0 * h1;
+      vf1 = vf1 + a1 * h1;
+      vf2 = vf2 + a2 * h1;
+      Af = Af + da * h1;
+      g.vfx[s] = vf0;
+      g.vfy[s] = vf1;
+      g.vfz[s] = vf2;
+      g.Af[s] = (float)Af;
+      const double v = sqrt(vf0 * vf0 + vf1 * vf1 + vf2 * vf2);
+      if (v > 0.0) {
+        key = leaf_of[s];
+        bits = __float_as_int((float)v) + 1;  // (positive floats order as their bits)
+      }
     }
-    g.vx[s] = vf0;
-    g.vy[s] = vf1;
-    g.vz[s] = vf2;
-    g.A[s] = (float)Af;
-    const double vs = g.vsig[s];
-    const double dtn = vs > 0.0 ? g.cfl * (double)g.h[s] / vs : INFINITY;
-    int nb = 0;
-    for (int b = 1; b < g.n_bins; ++b)
-      if (dtn >= ldexp(g.t_min, b)) nb = b;
-    if (g.ti != 0 && nb > g.ctz_ti) nb = g.ctz_ti;
-    g.bin[s] = (int8_t)nb;
-    const double h1 = 0.5 * ldexp(g.t_min, nb);
-    vf0 = vf0 + a0 * h1;
-    vf1 = vf1 + a1 * h1;
-    vf2 = vf2 + a2 * h1;
-    Af = Af + da * h1;
-    g.vfx[s] = vf0;
-    g.vfy[s] = vf1;
-    g.vfz[s] = vf2;
-    g.Af[s] = (float)Af;
-    const double v = sqrt(vf0 * vf0 + vf1 * vf1 + vf2 * vf2);
-    if (v > 0.0) atomicMax((int *)&leaf_vmax[leaf_of[s]], __float_as_int((float)v) + 1);
+    // one atomic per leaf of the wave (active particles are in cell order:
+    // a wave spans few leaves), with the largest bound of its lanes
+    bool pend = bits > 0;
+    for (uint64_t m = __ballot(pend); m != 0ull; m = __ballot(pend)) {
+      const int src = __ffsll((unsigned long long)m) - 1;
+      const int L = __shfl(key, src, 64);
+      const bool mine = pend && key == L;
+      const int top = wave_max_i(mine ? bits : 0);
+      if (lane == src) atomicMax((int *)&leaf_vmax[L], top);
+      pend = pend && !mine;
+    }
   }
 }
 
@@ -248,14 +269,18 @@ __global__ __launch_bounds__(256) void min_bin_kernel(const int8_t *__restrict__
   for (int64_t s = tid; s < h; s += stride) m = min(m, (int)bin[s]);
   for (int64_t s = h + (nv << 4) + tid; s < n; s += stride) m = min(m, (int)bin[s]);
   for (int o = 32; o > 0; o >>= 1) m = min(m, __shfl_xor(m, o, 64));
-  if ((threadIdx.x & 63) == 0) atomicMin(out, m);
+  // one atomic per block (a single address: contended atomics serialise)
+  __shared__ int wm[4];
+  if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMin(out, min(min(wm[0], wm[1]), min(wm[2], wm[3])));
 }
 
 sph_status next_active_impl(sph_ctx *ctx, const int8_t *bin, int64_t n, int64_t ti, int64_t *ti_next) {
   if (n <= 0) return sph_fail(ctx, SPH_ESTATE, "next_active_time: no particles (build_cells first)");
   int32_t *slot = (int32_t *)ctx->scalars.p + SC_MINBIN;
   set_i32_kernel<<<1, 64, 0, ctx->stream>>>(slot, INT_MAX);
-  const int64_t grid = std::min<int64_t>(ceil_div(n, 256 * 16), 2048) + 1;
+  const int64_t grid = std::min<int64_t>(ceil_div(n, 256 * 16 * 4), 512) + 1;
   min_bin_kernel<<<(unsigned)grid, 256, 0, ctx->stream>>>(bin, n, slot);
   HIP_TRY(ctx, hipGetLastError());
   int32_t b = 0;

@@ -494,9 +494,17 @@ __device__ __forceinline__ void ghost_body(const GhostArgs &g) {
   int finished = 0;
   int unconv = 0;
   for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < g.n_active; k += (int64_t)gridDim.x * 256) {
-    // every load that does not depend on another is issued first (the
-    // kernel is a chain of dependent loads; valid indices for every k)
+    // finished and waiting particles read nothing more (after the first
+    // pass most are finished); for the others every load that does not
+    // depend on another is issued first (a chain of dependent loads)
     const uint8_t cv = g.conv[k];
+    // whether the next pass evaluates particle k
+    const bool again = [&]() -> bool {
+    if (cv == 1) return false;
+    if (cv == 2) {  // waiting for wider cell-pair lists: not converged
+      ++unconv;
+      return false;
+    }
     const int i = g.active_idx[k];
     const int co = g.chunk_of[k];
     const float lo0 = g.hlo[k], hi0 = g.hhi[k];
@@ -507,13 +515,6 @@ __device__ __forceinline__ void ghost_body(const GhostArgs &g) {
     const int cnt_k = g.act_cnt[k];
     const float h = g.h[i];
     const Chunk ch = g.chunks[co];
-    // whether the next pass evaluates particle k
-    const bool again = [&]() -> bool {
-    if (cv == 1) return false;
-    if (cv == 2) {  // waiting for wider cell-pair lists: not converged
-      ++unconv;
-      return false;
-    }
     const HStep st = h_newton_step(S_w, S_d, h, lo0, hi0, g.kc, g.eta3, g.tol);
     const float hn = st.hn, lo = st.lo, hi = st.hi;
     const bool done = st.done;
@@ -593,11 +594,19 @@ __device__ __forceinline__ void ghost_body(const GhostArgs &g) {
       if (again) g.todo[base + rank_below(m)] = (int32_t)k;
     }
   }
+  // one pair of counter updates per block (every block reaches this point)
   finished = wave_sum_i(finished);
   unconv = wave_sum_i(unconv);
+  __shared__ int bf[4], bu[4];
   if ((threadIdx.x & 63) == 0) {
-    if (finished) atomicAdd(g.ctr, (unsigned long long)finished);
-    if (unconv) atomicAdd(g.n_unconv, unconv);
+    bf[threadIdx.x >> 6] = finished;
+    bu[threadIdx.x >> 6] = unconv;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int f = bf[0] + bf[1] + bf[2] + bf[3], u = bu[0] + bu[1] + bu[2] + bu[3];
+    if (f) atomicAdd(g.ctr, (unsigned long long)f);
+    if (u) atomicAdd(g.n_unconv, u);
   }
 }
 
@@ -1208,13 +1217,14 @@ __global__ __launch_bounds__(256) void force_sweep_kernel(LoopArgs g, const int3
   int cnt = 0;
   if (k < g.n_active) {
     SweepPair *my = sp[wave];
-    const int i = g.active_idx[k];
-    const float4 pi = g.pos4[i];
-    const float Hi = pi.w, H2i = Hi * Hi, invHi = 1.f / Hi;
-    const float4 vi = g.jvm[i];
-    const float4 thi = g.jth[i];
-    const Chunk ch = g.chunks[chunk_of[k]];
-    const int pbeg = g.pair_off[ch.act_leaf], pend = g.pair_off[ch.act_leaf + 1];
+    // the particle's values are the same on every lane: scalar registers
+    const int i = wave_uniform(g.active_idx[k]);
+    const float4 pi = wave_uniform(g.pos4[i]);
+    const float Hi = pi.w, H2i = wave_uniform(Hi * Hi), invHi = wave_uniform(1.f / Hi);
+    const float4 vi = wave_uniform(g.jvm[i]);
+    const float4 thi = wave_uniform(g.jth[i]);
+    const Chunk ch = g.chunks[wave_uniform(chunk_of[k])];
+    const int pbeg = wave_uniform(g.pair_off[ch.act_leaf]), pend = wave_uniform(g.pair_off[ch.act_leaf + 1]);
     ForceAcc f = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     float4 *Q = hq[wave];
     float *QH = hqH[wave];
@@ -1644,10 +1654,11 @@ sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u)
   int it = 0, done = 0;
   while (!done) {
     const int first = it + 1, last = std::min(it == 0 && n_todo >= ctx->prm.sweep_below ? 4 : it + 2, maxit);
+    const bool sweep_group = n_todo < ctx->prm.sweep_below;
     for (int pass = first; pass <= last; ++pass) {
       LoopArgs a = density_loop_args(ctx);
       int32_t *next_n = list_n + ((pass + 1) & 1);
-      if (n_todo < ctx->prm.sweep_below) {
+      if (sweep_group) {
         // few particles to do: one wave per particle.  The number to do only
         // falls from here on, so no later pass of this solve runs the chunk
         // loop (whose chunk flags the sweep leaves as they are).
@@ -1676,8 +1687,13 @@ sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u)
           SPH_TRY((launch_loop<0, false>(ctx, a)));
       }
       GhostArgs gh = density_ghost_args(ctx, p, pass, entropy_from_u, stats + 2 * pass);
-      gh.todo = list;
-      gh.todo_n = next_n;
+      // the list of the next pass: read by a sweep (the passes of a group
+      // are all sweeps or all chunk loops), or by the next group's first
+      // pass; a chunk-loop pass inside a group reads its chunk flags
+      if (sweep_group || pass == last) {
+        gh.todo = list;
+        gh.todo_n = next_n;
+      }
       {
         PROF(ctx, "ghost");
         ghost_kernel<<<grid256(na), 256, 0, ctx->stream>>>(gh);
