@@ -823,11 +823,20 @@ struct SweepSolve {
 // full waves although few of the candidates tested together are neighbours
 // (with one wave per particle and the solver's steps on, all of them are
 // evaluated from the cache after the walk).
-template <int NWP, bool COMP>
+//
+// Work: the particles todo[0 .. n_todo) (all active ones with todo null),
+// or, with SCAN, the active particles k whose scan_conv[k] is 0, a wave
+// taking 64 consecutive k (n_todo = ceil(n_active / 64)) and the particles
+// among them one after the other.  With gate, the launch does nothing unless
+// *gate < gate_min.
+template <int NWP, bool COMP, bool SCAN = false>
 __global__ __launch_bounds__(256) void density_sweep_kernel(LoopArgs g, const int32_t *__restrict__ todo,
                                                             const int32_t *__restrict__ n_todo_dev, int64_t n_todo,
                                                             const int32_t *__restrict__ chunk_of,
-                                                            int32_t *__restrict__ next_n, SweepSolve sv) {
+                                                            int32_t *__restrict__ next_n, SweepSolve sv,
+                                                            const uint8_t *__restrict__ scan_conv,
+                                                            const int32_t *__restrict__ gate, int32_t gate_min) {
+  if (gate && *gate >= gate_min) return;
   __shared__ SweepPair sp[4][64];
   __shared__ GroupPart gpart[4][64];  // per wave: the small partners of the current 64 pairs
   __shared__ float4 hq[4][SWEEP_QCAP];  // per wave: queued neighbours (dx, dy, dz, j)
@@ -849,9 +858,18 @@ __global__ __launch_bounds__(256) void density_sweep_kernel(LoopArgs g, const in
   const int64_t lb = (bi & 7) * per + (bi >> 3);
   const int64_t w = lb < nblk ? lb * (4 / NWP) + wave / NWP : n_todo;
   if (w < n_todo) {
+  // one particle, or with scan_conv those of the wave's 64 still to do
+  uint64_t pend = 1ull;
+  if (SCAN) {
+    const int64_t kk = w * 64 + lane;
+    pend = __ballot(kk < g.n_active && scan_conv[kk] == 0);
+  }
+  while (pend) {
+  const int bit = __ffsll((unsigned long long)pend) - 1;
+  pend = SCAN ? pend & (pend - 1) : 0ull;
   SweepPair *my = sp[wave];
   // the particle's values are the same on every lane: scalar registers
-  const int k = wave_uniform(todo ? todo[w] : (int)w);
+  const int k = wave_uniform(SCAN ? (int)(w * 64) + bit : (todo ? todo[w] : (int)w));
   const int i = wave_uniform(g.active_idx[k]);
   const float4 pi = wave_uniform(g.pos4[i]);
   const float Hi = pi.w, H2i = wave_uniform(Hi * Hi), invHi = wave_uniform(1.f / Hi);
@@ -1133,6 +1151,8 @@ __global__ __launch_bounds__(256) void density_sweep_kernel(LoopArgs g, const in
       for (int q = 0; q < 8; ++q) red[wave][q] = acc[q];
       red[wave][8] = __int_as_float(cnt);
     }
+  }
+  wave_sync();  // the next particle of the wave reuses its LDS
   }
   }
   if (NWP > 1) {
@@ -1669,8 +1689,9 @@ sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u)
         const int32_t *co = (const int32_t *)ctx->chunk_of.p;
         const bool comp = ctx->prm.compensated != 0;
         const SweepSolve sv = sweep_solve_args(ctx, p, pass);
-#define SPH_DSWEEP(NWP_, C_) \
-  density_sweep_kernel<NWP_, C_><<<grid, 256, 0, ctx->stream>>>(a, tl, tn, n_todo, co, next_n, sv)
+#define SPH_DSWEEP(NWP_, C_)                                                                          \
+  density_sweep_kernel<NWP_, C_><<<grid, 256, 0, ctx->stream>>>(a, tl, tn, n_todo, co, next_n, sv, nullptr, \
+                                                                nullptr, 0)
         if (nwp == 4)
           { if (comp) SPH_DSWEEP(4, true); else SPH_DSWEEP(4, false); }
         else if (nwp == 2)
@@ -1681,10 +1702,37 @@ sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u)
         HIP_TRY(ctx, hipGetLastError());
       } else {
         HIP_TRY(ctx, hipMemsetAsync(next_n, 0, sizeof(int32_t), ctx->stream));
+        // after the group's first pass the number left to do is known on the
+        // device only (the previous ghost's count): the chunk loop works
+        // while it is at least sweep_below, else a sweep over the particles
+        // still to do (their conv flag 0) takes the pass
+        const bool gated = pass > first && sweep_waves(ctx, na) == 1;
+        const int32_t *gate = stats + 2 * (pass - 1);
+        const int32_t gate_min = (int32_t)std::min<int64_t>(ctx->prm.sweep_below, INT32_MAX);
+        LoopArgs ac = a;
+        if (gated) {
+          ac.gate = gate;
+          ac.gate_min = gate_min;
+        }
         if (ctx->prm.compensated)
-          SPH_TRY((launch_loop<0, true>(ctx, a)));
+          SPH_TRY((launch_loop<0, true>(ctx, ac)));
         else
-          SPH_TRY((launch_loop<0, false>(ctx, a)));
+          SPH_TRY((launch_loop<0, false>(ctx, ac)));
+        if (gated) {
+          PROF(ctx, "density_sweep");
+          const int64_t ngroups = ceil_div(na, 64);
+          const unsigned grid = xcd_grid(std::min<int64_t>(ceil_div(ngroups, 4), (int64_t)ctx->n_cu * 16));
+          const int32_t *co = (const int32_t *)ctx->chunk_of.p;
+          const uint8_t *conv = (const uint8_t *)ctx->conv.p;
+          const SweepSolve sv = sweep_solve_args(ctx, p, pass);
+          if (ctx->prm.compensated)
+            density_sweep_kernel<1, true, true><<<grid, 256, 0, ctx->stream>>>(a, nullptr, nullptr, ngroups, co,
+                                                                               nullptr, sv, conv, gate, gate_min);
+          else
+            density_sweep_kernel<1, false, true><<<grid, 256, 0, ctx->stream>>>(a, nullptr, nullptr, ngroups, co,
+                                                                                nullptr, sv, conv, gate, gate_min);
+          HIP_TRY(ctx, hipGetLastError());
+        }
       }
       GhostArgs gh = density_ghost_args(ctx, p, pass, entropy_from_u, stats + 2 * pass);
       // the list of the next pass: read by a sweep (the passes of a group

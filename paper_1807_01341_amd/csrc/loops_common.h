@@ -72,6 +72,10 @@ struct LoopArgs {
   const float4 *jadj1;  // (rho_bar, drho_dh_bar, D_bar, lambda) per particle
   const float4 *jadj2;  // (C_bar x, y, z, 0) per particle
   float *outp;          // per-particle outputs, [q * n + i]
+  // (opt) the pass does its work only while the device count *gate is at
+  // least gate_min (every work item returns at once otherwise)
+  const int32_t *gate;
+  int32_t gate_min;
 };
 
 // Modes of the chunk body: 0 density loop, 1 force loop, 2 force adjoint,
@@ -172,6 +176,7 @@ __device__ __forceinline__ void chunk_body(const LoopArgs &g, int code, bool cod
   const int cid = coded ? code >> 4 : code;
   const int part = coded ? code & 15 : 0;
   const int nparts = g.chunk_item0 ? g.chunk_item0[cid + 1] - g.chunk_item0[cid] : 1;
+  if (g.gate && *g.gate < g.gate_min) return;
   if (!g.chunk_todo[cid]) return;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;

@@ -171,26 +171,29 @@ def test_sweep_solver_steps_match_chunk_loop(gpu_lib, eta, h_scale):
     first step that leaves the reach of the cell-pair lists, which are then
     widened), it gives the converged h, the neighbour counts and the sums of
     the chunk loop (one step per pass) and of the sweep with two waves per
-    particle (no steps of its own), in no more passes."""
+    particle (no steps of its own), in no more passes.  With sweep_below 2000
+    the chunk loop takes the first passes and, once fewer particles are left
+    (a count known only on the device), the sweep over the particles whose
+    flag says they are not done takes the rest: the same results again."""
     ic = ics.tiny_lattice(24, velocity_sigma=0.1)
     ic["h"] = (ic["h"] * h_scale).astype(np.float32)
     kw = {} if eta is None else {"eta": eta}
     print(f"case tiny24 eta={eta} h_scale={h_scale}", flush=True)
     runs = []
-    for extra in (dict(sweep_below=0), dict(), dict(sweep_waves=2)):
+    for extra in (dict(sweep_below=0), dict(), dict(sweep_waves=2), dict(sweep_below=2000)):
         _, p, perm, snap = run_gpu_step(gpu_lib, ic, 0, ctx_kw={**kw, **extra})
         runs.append((p, perm, snap["info"]))
-    (p0, perm0, i0), (p1, perm1, i1), (p2, perm2, i2) = runs
-    assert np.array_equal(perm0, perm1) and np.array_equal(perm0, perm2)
-    print("passes", i0["density_iterations"], i1["density_iterations"], i2["density_iterations"],
-          "rebuilds", i0["pair_rebuilds"], i1["pair_rebuilds"], i2["pair_rebuilds"])
-    for info in (i0, i1, i2):
+    (p0, perm0, i0), (p1, perm1, i1), (p2, perm2, i2), (p3, perm3, i3) = runs
+    assert np.array_equal(perm0, perm1) and np.array_equal(perm0, perm2) and np.array_equal(perm0, perm3)
+    print("passes", [r[2]["density_iterations"] for r in runs], "rebuilds", [r[2]["pair_rebuilds"] for r in runs],
+          "unconverged after pass", i3["unconverged_after_pass"])
+    for info in (i0, i1, i2, i3):
         assert info["n_unconverged"] == 0
     assert i1["density_iterations"] <= i0["density_iterations"]
     if eta is not None:
         # at least 150 within H, so above 192 within 1.1 H
         assert min(host(p0, "nngb_density")) > 150
-    for pq in (p1, p2):
+    for pq in (p1, p2, p3):
         for k in ("nngb_density", "nngb_force"):
             assert np.array_equal(host(p0, k), host(pq, k)), k
         for k in ("h", "rho", "vsig"):
