@@ -40,18 +40,19 @@ FP32_UNPACKED = 78.6e12   # one FMA per lane per clock (256 CU x 4 SIMD x 16 lan
 HBM_PEAK = 8.0e12         # bytes/s
 # HBM traffic of the loop kernels per launch, from two rocprofv3 --pmc runs
 # (FETCH_SIZE, WRITE_SIZE) scaled by the same counters on a plain 512 MiB
-# copy (profiles/force_sweep_deepbin_pmc.md, profiles/density_sweep_deepbin_pmc.md),
+# copy (FETCH x 2.000, WRITE x 1.000), each on the workload whose roofline
+# kernel it is: the density chunk loop over one 2^13 period of the large
+# share's time line (profiles/c5_density_loop_traffic_pmc.md), the force sweep
+# of the clustered deep-bin step (profiles/clustered_deepbin_sweeps_pmc.md);
 # valid while the kernels' sources are the ones that were measured (else
 # reported as null)
+_LOOP_SOURCES = ["paper_1807_01341_amd/csrc/loops.hip", "paper_1807_01341_amd/csrc/loops_common.h",
+                 "paper_1807_01341_amd/csrc/sph_internal.h"]
+_LOOP_SHA = "82b9559abf042210ba0a02928758e9f8b201cb3789373090fa625eeab16a63ca"
 MEASURED_TRAFFIC = {
-    "force_loop": {"bytes": 15783444.0,
-                   "sources": ["paper_1807_01341_amd/csrc/loops.hip", "paper_1807_01341_amd/csrc/loops_common.h",
-                               "paper_1807_01341_amd/csrc/sph_internal.h"],
-                   "sha256": "ed72f7189f6ec3482c3075fe0b2d365e4dba243ddbb5eb553b5bebed380fb013"},
-    "density_loop": {"bytes": 10457098.0,
-                     "sources": ["paper_1807_01341_amd/csrc/loops.hip", "paper_1807_01341_amd/csrc/loops_common.h",
-                                 "paper_1807_01341_amd/csrc/sph_internal.h"],
-                     "sha256": "ed72f7189f6ec3482c3075fe0b2d365e4dba243ddbb5eb553b5bebed380fb013"},
+    "density_loop": {"bytes": 7.08897e8, "sources": _LOOP_SOURCES, "sha256": _LOOP_SHA},
+    "force_loop": {"bytes": 2.01347e9, "sources": _LOOP_SOURCES, "sha256": _LOOP_SHA},
+    "force_sweep": {"bytes": 1.78494e7, "sources": _LOOP_SOURCES, "sha256": _LOOP_SHA},
 }
 
 
