@@ -64,7 +64,8 @@ typedef struct {
   int split_count;     /* a cell with at least this many particles is split (400, Sec. III-A) */
   int morton_depth;    /* bits per axis of the Morton keys, D <= 21 (16) */
   int top_cap;         /* top-level grid has at most 2^top_cap cells per side (7) */
-  int h_max_iter;      /* Newton iterations of the h solve (30) */
+  int h_max_iter;      /* Newton passes of the h solve (30); a one-wave-per-particle density
+                          pass p also takes up to h_max_iter - p steps of its own */
   int compensated;     /* 1: compensated FP32 sums in the loops (1) */
   int cand_cap;        /* loop tiling: candidate slots per wave (512) */
   int list_cap;        /* loop tiling: neighbour-list slots per lane (96) */
@@ -77,7 +78,8 @@ typedef struct {
                           with fewer active particles, than this run waves per particle
                           (a sweep of each partner leaf in reach) instead of the chunk
                           loop (0: never; batched passes use chunks) (2^18: the sweep
-                          wins on sparse deep time-bins, the chunk loop on dense ones) */
+                          wins on sparse deep time-bins, the chunk loop on dense ones);
+                          after the first pass of a group the count is read on the device */
   int sweep_waves;     /* waves per particle in those passes: 1, 2 or 4; 0 = one (0) */
   float rebuild_frac;  /* sph_build_cells keeps the cells of its last full build while no
                           leaf's particles moved more than this fraction of the leaf's
@@ -202,9 +204,13 @@ sph_status sph_mark_active(sph_ctx *ctx, const sph_particles *p, int max_active_
  * div v, curl v, the grad-h factor, pressure, sound speed, Balsara switch and
  * the entropic function.  entropy_from_u=1 takes u as the thermal input
  * (A = (gamma-1) u rho^(1-gamma), written to A and to the kicked copy Af, the
- * state a first kick starts from); 0 takes A (and writes u).  Synchronises
- * once per group of Newton passes (passes 1-4, then two at a time; a pass
- * reads on the device which particles the previous one left unconverged).
+ * state a first kick starts from); 0 takes A (and writes u).  A pass that
+ * runs one wave per particle also takes Newton steps on the neighbours it
+ * keeps within 1.1 H while the new H stays inside, leaving the last step to
+ * the ghost (the same iterates, fewer passes).  Synchronises once per group
+ * of Newton passes (passes 1-4, then two at a time, or two at a time from the
+ * start when the first pass runs one wave per particle; a pass reads on the
+ * device which particles the previous one left unconverged).
  * SPH_ENOCONV / SPH_EREBUILD as described above. */
 sph_status sph_density_pass(sph_ctx *ctx, sph_particles *p, int entropy_from_u);
 
