@@ -48,7 +48,7 @@ HBM_PEAK = 8.0e12         # bytes/s
 # reported as null)
 _LOOP_SOURCES = ["paper_1807_01341_amd/csrc/loops.hip", "paper_1807_01341_amd/csrc/loops_common.h",
                  "paper_1807_01341_amd/csrc/sph_internal.h"]
-_LOOP_SHA = "82b9559abf042210ba0a02928758e9f8b201cb3789373090fa625eeab16a63ca"
+_LOOP_SHA = "440a7d9d03be16db30f53c9311e036a21897bd5bd362fb06b84d85593ca5827f"
 MEASURED_TRAFFIC = {
     "density_loop": {"bytes": 7.08897e8, "sources": _LOOP_SOURCES, "sha256": _LOOP_SHA},
     "force_loop": {"bytes": 2.01347e9, "sources": _LOOP_SOURCES, "sha256": _LOOP_SHA},

@@ -1704,8 +1704,11 @@ sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u)
         HIP_TRY(ctx, hipMemsetAsync(next_n, 0, sizeof(int32_t), ctx->stream));
         // after the group's first pass the number left to do is known on the
         // device only (the previous ghost's count): the chunk loop works
-        // while it is at least sweep_below, else a sweep over the particles
-        // still to do (their conv flag 0) takes the pass
+        // while it is at least sweep_below, else a sweep takes the pass: over
+        // the list the previous ghost appended to (passes after the second of
+        // the group), or over the particles whose conv flag is 0 (the second:
+        // the first pass's ghost appends nothing, nearly every particle being
+        // left to do)
         const bool gated = pass > first && sweep_waves(ctx, na) == 1;
         const int32_t *gate = stats + 2 * (pass - 1);
         const int32_t gate_min = (int32_t)std::min<int64_t>(ctx->prm.sweep_below, INT32_MAX);
@@ -1718,7 +1721,20 @@ sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u)
           SPH_TRY((launch_loop<0, true>(ctx, ac)));
         else
           SPH_TRY((launch_loop<0, false>(ctx, ac)));
-        if (gated) {
+        if (gated && pass > first + 1) {
+          PROF(ctx, "density_sweep");
+          const unsigned grid = xcd_grid(std::min<int64_t>(ceil_div(na, 4), (int64_t)ctx->n_cu * 16));
+          const int32_t *co = (const int32_t *)ctx->chunk_of.p;
+          const int32_t *tn = list_n + (pass & 1);
+          const SweepSolve sv = sweep_solve_args(ctx, p, pass);
+          if (ctx->prm.compensated)
+            density_sweep_kernel<1, true><<<grid, 256, 0, ctx->stream>>>(a, list, tn, na, co, nullptr, sv, nullptr,
+                                                                          gate, gate_min);
+          else
+            density_sweep_kernel<1, false><<<grid, 256, 0, ctx->stream>>>(a, list, tn, na, co, nullptr, sv, nullptr,
+                                                                           gate, gate_min);
+          HIP_TRY(ctx, hipGetLastError());
+        } else if (gated) {
           PROF(ctx, "density_sweep");
           const int64_t ngroups = ceil_div(na, 64);
           const unsigned grid = xcd_grid(std::min<int64_t>(ceil_div(ngroups, 4), (int64_t)ctx->n_cu * 16));
@@ -1735,10 +1751,12 @@ sph_status density_pass_impl(sph_ctx *ctx, sph_particles *p, int entropy_from_u)
         }
       }
       GhostArgs gh = density_ghost_args(ctx, p, pass, entropy_from_u, stats + 2 * pass);
-      // the list of the next pass: read by a sweep (the passes of a group
-      // are all sweeps or all chunk loops), or by the next group's first
-      // pass; a chunk-loop pass inside a group reads its chunk flags
-      if (sweep_group || pass == last) {
+      // the list of the next pass: read by a sweep, the next group's first
+      // pass, or a later pass of a chunk-loop group that the device hands to
+      // the sweep.  Only the ghost of a chunk-loop group's first pass appends
+      // nothing: nearly every particle is left after it, and the chunk loop
+      // reads its chunk flags
+      if (sweep_group || pass > first || pass == last) {
         gh.todo = list;
         gh.todo_n = next_n;
       }
